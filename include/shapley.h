@@ -1,0 +1,225 @@
+/*
+ * libshapley -- C ABI of an MI355X (gfx950) solver for the Shapley equation
+ *
+ *     v(x) = max_{a in A(x)} min_{b in B(x,a)} ( sum_y mu p(y|x,a,b) v(y) + r(x,a,b) )
+ *
+ * of a two-player zero-sum discounted stochastic game with finite state space
+ * (Akian & Detournay, "Multigrid methods for two player zero-sum stochastic
+ * games", arXiv:1107.1653, Sec. 2, eq. (eq1)), by policy iteration with an
+ * algebraic-multigrid inner solve (AMGpi, Sec. 5.1) and by full multilevel
+ * policy iteration (FAMGpi, Sec. 5.2, Algorithm algo-FAMGPI).
+ *
+ * Conventions shared by every entry point
+ *   - Return value: SHAPLEY_OK (0) or one of the error codes below; the
+ *     message of the last error of the calling thread is returned by
+ *     shapley_last_error().  On error no output argument is modified unless
+ *     stated otherwise.
+ *   - Pointers are host pointers unless a flag says otherwise.  The library
+ *     copies every input array; the caller keeps ownership of its arrays.
+ *   - A game handle may be used by one thread at a time.  Different handles
+ *     may be used concurrently.  shapley_server_submit is thread-safe.
+ *   - All computation runs on the HIP device that is current when the handle
+ *     is created; work is ordered on the handle's stream.
+ */
+#ifndef SHAPLEY_H
+#define SHAPLEY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- errors */
+#define SHAPLEY_OK 0
+#define SHAPLEY_EINVAL 1   /* bad sizes, w < 0, row sum > 1 + 1e-12, mu not in (0,1],
+                              NaN/Inf, empty action set, bad options */
+#define SHAPLEY_ENOMEM 2   /* device allocation failed or budget exceeded */
+#define SHAPLEY_ENOCONV 3  /* iteration limits or stagnation; partial results readable */
+#define SHAPLEY_EDEVICE 4  /* HIP runtime error or device-side check failure */
+#define SHAPLEY_EAGAIN 5   /* result not ready (server) */
+
+/* Message of the last error raised on the calling thread ("" if none). */
+const char* shapley_last_error(void);
+
+/* ---------------------------------------------------------------- types */
+typedef struct shapley_game_s* shapley_game_t;
+typedef struct shapley_server_s* shapley_server_t;
+
+/* Optional geometric description of a game obtained by discretising a PDE on
+ * the unit cube (Sec. 3.3): s interior points per side, h = 1/(s+1), states
+ * numbered x = (i1-1) + s (i2-1) [+ s^2 (i3-1)].  Needed by FAMGpi for the
+ * transfers I (values) and U (strategies) of Sec. 5.2. */
+typedef struct shapley_grid {
+  int32_t dim;          /* 1, 2 or 3 */
+  int32_t s;            /* interior points per side; n must equal s^dim */
+  const double* bvals;  /* optional: (s+2)^dim Dirichlet values on the grid
+                           extended by its boundary nodes, x1 fastest (only
+                           boundary nodes are read); NULL means zero */
+} shapley_grid;
+
+enum { SHAPLEY_FP64 = 0, SHAPLEY_MIXED = 1 };
+enum { SHAPLEY_AMGPI = 0, SHAPLEY_FAMGPI = 1 };
+
+/* Solve options.  Fill with shapley_default_opts() first. */
+typedef struct shapley_solve_opts {
+  double eps;            /* stop when ||F(v) - v||_inf <= eps after a value step
+                            (Sec. 5.1); eps = 0 stops when no policy improves
+                            (Algorithms algo-MDP / PIalgo). Default 0. */
+  int32_t precision;     /* SHAPLEY_FP64: V-cycles in FP64; SHAPLEY_MIXED: FP32
+                            V-cycles under FP64 iterative refinement. */
+  int32_t method;        /* SHAPLEY_AMGPI, or SHAPLEY_FAMGPI for hierarchies */
+  double c_fmg;          /* FAMGpi coarse-level stop eps_l = c_fmg h_l^2 (Sec. 5.2) */
+  const int32_t* alpha0; /* optional warm start (host, n entries): MAX policy */
+  const int32_t* beta0;  /* optional warm start (host, n entries): MIN policy at alpha0 */
+  const double* v0;      /* optional warm start (host, n entries): initial value */
+  int32_t max_outer;     /* limit on MAX policy iterations (k) */
+  int32_t max_inner;     /* limit on MIN policy iterations per k (n_k) */
+  int32_t max_cycles;    /* limit on refinement cycles per linear system */
+  double lin_rtol;       /* linear stop ||b - A v||_inf <= lin_rtol max(||b||, ||v||) */
+  double lin_atol;       /* ... or <= lin_atol (absolute) */
+  double tie_rtol;       /* an incumbent action is kept unless beaten by more than
+                            tie_rtol * (|r| + mu sum |w||v|) of the compared rows */
+  double theta;          /* strength threshold; <= 0 picks 0.25 (dim <= 2) / 0.5 */
+  int32_t nu1, nu2;      /* pre/post Jacobi sweeps of the V(nu1,nu2) cycle */
+  double omega;          /* Jacobi weight */
+  int32_t coarse_max;    /* dense direct solve at or below this many unknowns */
+  int32_t max_levels;
+  int32_t verbose;       /* 1: one line per outer iteration on stderr */
+  void* stream;          /* hipStream_t to order work on; NULL = handle's stream */
+} shapley_solve_opts;
+
+/* Per-solve statistics (the paper's table columns, Sec. 6, plus timings). */
+typedef struct shapley_stats {
+  int32_t outer;             /* k: MAX policy iterations */
+  int32_t inner_total;       /* linear systems solved (sum of n_k) */
+  int32_t cycles_total;      /* V-cycles over all linear systems */
+  int32_t levels;            /* AMG levels of the last hierarchy */
+  int32_t converged;         /* 1 if stopped on eps or policy stability */
+  int32_t fmg_levels;        /* grids visited (FAMGpi) */
+  double residual;           /* final ||F(v) - v||_inf */
+  double residual_l2;        /* final discrete L2 norm sqrt(mean((F(v)-v)^2)) */
+  double seconds;            /* wall time of the solve (device-resident data) */
+  double setup_seconds;      /* AMG setups */
+  double cycle_seconds;      /* refinement + V-cycles */
+  double improve_seconds;    /* assembly + improvement sweeps */
+  double op_complexity;      /* sum nnz(A_l) / nnz(A_0) of the last hierarchy */
+  double grid_complexity;    /* sum n_l / n_0 */
+  int32_t inner_per_outer[64]; /* n_k for k = 1..64 */
+} shapley_stats;
+
+/* Fills *o with the defaults: eps 0, FP64, AMGpi, c_fmg 1e-2, no warm start,
+ * max_outer 100000, max_inner 100000, max_cycles 200, lin_rtol 1e-14,
+ * lin_atol 0, tie_rtol 1e-12, theta auto, nu1 = nu2 = 2, omega 0.8,
+ * coarse_max 100, max_levels 25, verbose 0, stream NULL. */
+void shapley_default_opts(shapley_solve_opts* o);
+
+/* ---------------------------------------------------------------- games */
+
+/* Flags of shapley_game_create. */
+#define SHAPLEY_HOST_PTRS 0u
+
+/*
+ * Creates a game handle from its transition stencils (Sec. 2): states
+ * X = {0..n-1}, m1 actions for MAX and m2 for MIN at every state (invalid
+ * pairs are masked by `valid`).  Row (x, a, b) = (x*m1 + a)*m2 + b holds the
+ * sparse row y -> w = p(y|x,a,b) in CSR form and the reward r(x,a,b).
+ *   row_ptr  [n*m1*m2 + 1] int64, row_ptr[0] = 0, non-decreasing
+ *   col      [row_ptr[end]] int32 in [0, n)
+ *   w        [row_ptr[end]] double >= 0, sum of each row <= 1 + 1e-12
+ *   r        [n*m1*m2] double, finite
+ *   mu       discount in (0, 1]; the systems I - mu W must be non-singular
+ *            (mu = 1 with substochastic W, as for the discretised PDEs of
+ *            Sec. 3.3, is allowed)
+ *   valid    optional [n*m1*m2] uint8 (1 = pair allowed); every state needs a
+ *            valid a and every valid a a valid b.  NULL = all valid.
+ *   grid     optional geometric description (for FAMGpi), or NULL
+ *   flags    SHAPLEY_HOST_PTRS (all arrays are host arrays, copied)
+ *   stream   hipStream_t for the copies and later work; NULL = a new stream
+ *            owned by the handle
+ * Errors: SHAPLEY_EINVAL on any violated condition, SHAPLEY_ENOMEM.
+ */
+int shapley_game_create(shapley_game_t* out, int64_t n, int32_t m1, int32_t m2,
+                        const int64_t* row_ptr, const int32_t* col, const double* w,
+                        const double* r, double mu, const uint8_t* valid,
+                        const shapley_grid* grid, uint32_t flags, void* stream);
+
+/*
+ * Builds a hierarchy handle for FAMGpi (Algorithm algo-FAMGPI, Sec. 5.2) from
+ * nlev games ordered coarse -> fine, each created with a grid description of
+ * the same dimension; step h_l of level l halves (or, for non-nested grids,
+ * roughly halves) from one level to the next.  The hierarchy takes ownership
+ * of the level handles (do not destroy them separately).  Solving the
+ * hierarchy with method SHAPLEY_FAMGPI runs AMGpi on every level with
+ * eps_l = c_fmg h_l^2 and transfers (v, alpha, beta) upwards by I and U;
+ * results are read from the finest level through the hierarchy handle.
+ */
+int shapley_game_create_hierarchy(shapley_game_t* out, int32_t nlev, shapley_game_t* levels);
+
+/* Solves the game (or hierarchy).  o may be NULL (defaults); st may be NULL.
+ * Returns SHAPLEY_ENOCONV (with results and stats filled) if a limit was hit. */
+int shapley_solve(shapley_game_t g, const shapley_solve_opts* o, shapley_stats* st);
+
+/* Copies the current value (n doubles) to v (host, or device if on_device != 0). */
+int shapley_get_value(shapley_game_t g, double* v, int32_t on_device);
+
+/* Copies the current policies: alpha[n] (MAX), beta[n] (MIN at alpha(x));
+ * beta_all (optional, n*m1) receives MIN's lowest-index argmin at every a for
+ * the current value.  Host arrays; any may be NULL. */
+int shapley_get_policy(shapley_game_t g, int32_t* alpha, int32_t* beta, int32_t* beta_all);
+
+/* Evaluates F(v) (Sec. 2, eq. (eq1)) of the current value: F[n] (host) and
+ * the greedy policies at v (any output may be NULL). */
+int shapley_apply_operator(shapley_game_t g, const double* v, double* F, int32_t* alpha,
+                           int32_t* beta);
+
+/* n, m1, m2 of a handle (the finest level for hierarchies). */
+int shapley_game_info(shapley_game_t g, int64_t* n, int32_t* m1, int32_t* m2);
+
+/* Device bytes held by the handle. */
+int shapley_game_bytes(shapley_game_t g, size_t* bytes);
+
+void shapley_game_destroy(shapley_game_t g);
+
+/* ---------------------------------------------------------------- batch */
+
+/*
+ * Solves `count` independent games in lock-step: every V-cycle level of all
+ * games is processed by one launch per kernel (block-diagonal merged levels),
+ * games that converge leave the active set.  Results of each game equal those
+ * of solving it alone within the linear-solve tolerance.  stats (optional)
+ * receives count entries.  FAMGpi hierarchies are not accepted here.
+ */
+int shapley_solve_batch(shapley_game_t* games, int32_t count, const shapley_solve_opts* o,
+                        shapley_stats* stats);
+
+/* ---------------------------------------------------------------- server */
+
+/*
+ * A request loop with continuous batching: submitted games (or hierarchies)
+ * are admitted while their estimated device footprint fits the budget,
+ * advanced together one policy-iteration step at a time (one merged launch
+ * per kernel), and leave as they converge, freeing their budget.
+ *   hbm_budget  bytes of device memory the server may hold for requests
+ */
+int shapley_server_create(shapley_server_t* out, size_t hbm_budget, void* stream);
+/* Queues g (ownership stays with the caller; do not use or destroy g until
+ * its ticket completes).  Thread-safe. */
+int shapley_server_submit(shapley_server_t srv, shapley_game_t g, const shapley_solve_opts* o,
+                          uint64_t* ticket);
+/* Runs scheduling steps until the ticket completes or `max_steps` steps pass
+ * (max_steps <= 0: until complete).  Returns SHAPLEY_EAGAIN if not complete. */
+int shapley_server_wait(shapley_server_t srv, uint64_t ticket, int32_t max_steps,
+                        shapley_stats* st);
+/* Non-blocking: SHAPLEY_OK if the ticket completed (stats filled), else EAGAIN. */
+int shapley_server_poll(shapley_server_t srv, uint64_t ticket, shapley_stats* st);
+/* Runs one scheduling step (admission + one PI step of all active requests).
+ * *active receives the number of requests still on the device. */
+int shapley_server_step(shapley_server_t srv, int32_t* active);
+void shapley_server_destroy(shapley_server_t srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SHAPLEY_H */

@@ -1,0 +1,899 @@
+// AMG kernels (Sec. 4.3): setup -- strength of connection, PMIS C/F split,
+// extended+i interpolation, R = P^T, Galerkin A_{l+1} = R A_l P, dense
+// inverse of the coarsest blocks -- and the cycle -- weighted Jacobi
+// relaxation u <- u + omega D^{-1}(f - A u), residual, restriction,
+// prolongation + correction, dense coarse solve, FP64 residual of the
+// iterative refinement.  Every row kernel takes a tile list (row ranges of
+// one game each) so one launch covers all games of a merged level.
+#include "amg_kernels.hpp"
+
+#include <climits>
+
+namespace shp {
+
+// ---------------------------------------------------------------------------
+// setup: Dirichlet rows (no non-zero off-diagonal) and strength
+// ---------------------------------------------------------------------------
+__global__ void k_dirichlet(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                            const int* __restrict__ ci, const double* __restrict__ a,
+                            uint8_t* __restrict__ dir) {
+  Tile t = tiles[blockIdx.x];
+  int i = t.r0 + threadIdx.x;
+  if (i >= t.r1) return;
+  bool any = false;
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (ci[e] != i && a[e] != 0.0) any = true;
+  dir[i] = any ? 0 : 1;
+}
+
+__global__ void k_dir_scale(const Tile* __restrict__ tiles, const uint8_t* __restrict__ dir, double f,
+                            double* __restrict__ d64, float* __restrict__ d32) {
+  Tile t = tiles[blockIdx.x];
+  int i = t.r0 + threadIdx.x;
+  if (i >= t.r1 || !dir[i]) return;
+  d64[i] *= f;
+  if (d32) d32[i] = (float)d64[i];
+}
+
+// j strongly influences i when -a_ij >= theta max_{k != i} (-a_ik) (classical
+// strength for M-matrix rows); Dirichlet columns are never strong.
+// lam[j] counts the rows that depend strongly on j.
+__global__ void k_strength(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                           const int* __restrict__ ci, const double* __restrict__ a,
+                           const uint8_t* __restrict__ dir, double theta,
+                           uint8_t* __restrict__ strong, int* __restrict__ lam) {
+  Tile t = tiles[blockIdx.x];
+  int i = t.r0 + threadIdx.x;
+  if (i >= t.r1) return;
+  int e0 = rp[i], e1 = rp[i + 1];
+  double m = 0.0;
+  if (!dir[i])
+    for (int e = e0; e < e1; ++e) {
+      int j = ci[e];
+      if (j != i && !dir[j]) m = fmax(m, -a[e]);
+    }
+  for (int e = e0; e < e1; ++e) {
+    int j = ci[e];
+    bool s = !dir[i] && j != i && !dir[j] && m > 0.0 && -a[e] >= theta * m;
+    strong[e] = s ? 1 : 0;
+    if (s) atomicAdd(&lam[j], 1);
+  }
+}
+
+// transpose of the strength pattern: st_ci[st_rp[j] + slot] = i for strong (i, j)
+__global__ void k_strength_t(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                             const int* __restrict__ ci, const uint8_t* __restrict__ strong,
+                             const int* __restrict__ st_rp, int* __restrict__ cursor,
+                             int* __restrict__ st_ci) {
+  Tile t = tiles[blockIdx.x];
+  int i = t.r0 + threadIdx.x;
+  if (i >= t.r1) return;
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (strong[e]) {
+      int j = ci[e];
+      int pos = atomicAdd(&cursor[j], 1);
+      st_ci[st_rp[j] + pos] = i;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// PMIS (parallel maximal independent set) C/F splitting
+// ---------------------------------------------------------------------------
+constexpr int8_t CF_U = 0, CF_C = 1, CF_F = -1;  // -2: rows of games that end on this level
+
+__global__ void k_pmis_init(const Tile* __restrict__ tiles, const int* __restrict__ goff,
+                            const uint8_t* __restrict__ dir, const int* __restrict__ lam,
+                            uint32_t salt, int8_t* __restrict__ cf, uint64_t* __restrict__ key) {
+  Tile t = tiles[blockIdx.x];
+  int i = t.r0 + threadIdx.x;
+  if (i >= t.r1) return;
+  int local = i - goff[t.game];
+  key[i] = ((uint64_t)(uint32_t)lam[i] << 32) | mix32((uint32_t)local ^ salt);
+  cf[i] = (dir[i] || lam[i] == 0) ? CF_F : CF_U;
+}
+
+// A point joins C when its weight beats every undecided strong neighbour
+// (both directions of the strength graph).
+__global__ void k_pmis_select(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                              const int* __restrict__ ci, const uint8_t* __restrict__ strong,
+                              const int* __restrict__ st_rp, const int* __restrict__ st_ci,
+                              const int8_t* __restrict__ cf, const uint64_t* __restrict__ key,
+                              int* __restrict__ newc) {
+  Tile t = tiles[blockIdx.x];
+  int i = t.r0 + threadIdx.x;
+  if (i >= t.r1) return;
+  int sel = 0;
+  if (cf[i] == CF_U) {
+    uint64_t ki = key[i];
+    bool best = true;
+    for (int e = rp[i]; e < rp[i + 1] && best; ++e)
+      if (strong[e]) {
+        int j = ci[e];
+        if (cf[j] == CF_U && key[j] >= ki) best = false;
+      }
+    for (int e = st_rp[i]; e < st_rp[i + 1] && best; ++e) {
+      int j = st_ci[e];
+      if (cf[j] == CF_U && key[j] >= ki) best = false;
+    }
+    sel = best ? 1 : 0;
+  }
+  newc[i] = sel;
+}
+
+// New C points are fixed; undecided points depending strongly on a C point
+// become F.  `left` counts the points still undecided.
+__global__ void k_pmis_update(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                              const int* __restrict__ ci, const uint8_t* __restrict__ strong,
+                              int8_t* __restrict__ cf, const int* __restrict__ newc,
+                              int* __restrict__ left) {
+  Tile t = tiles[blockIdx.x];
+  int i = t.r0 + threadIdx.x;
+  int und = 0;
+  if (i < t.r1) {
+    if (newc[i]) {
+      cf[i] = CF_C;
+    } else if (cf[i] == CF_U) {
+      bool f = false;
+      for (int e = rp[i]; e < rp[i + 1]; ++e)
+        if (strong[e]) {
+          int j = ci[e];
+          if (cf[j] == CF_C || newc[j]) { f = true; break; }
+        }
+      if (f) cf[i] = CF_F; else und = 1;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) und += __shfl_xor(und, o);
+  if ((threadIdx.x & 63) == 0 && und) atomicAdd(left, und);
+}
+
+__global__ void k_fill_cf(const Tile* __restrict__ tiles, int8_t* __restrict__ cf, int8_t val) {
+  Tile t = tiles[blockIdx.x];
+  int i = t.r0 + threadIdx.x;
+  if (i < t.r1) cf[i] = val;
+}
+
+__global__ void k_is_c(const int8_t* __restrict__ cf, int* __restrict__ out, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = cf[i] == CF_C ? 1 : 0;
+}
+
+__global__ void k_gather_int(const int* __restrict__ src, const int* __restrict__ idx, int m,
+                             int* __restrict__ dst) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) dst[i] = src[idx[i]];
+}
+
+// ---------------------------------------------------------------------------
+// extended+i interpolation, truncated to PW entries per row (sum preserving)
+// ---------------------------------------------------------------------------
+__device__ inline int find_in(const int* lst, int n, int v) {
+  for (int p = 0; p < n; ++p)
+    if (lst[p] == v) return p;
+  return -1;
+}
+
+__global__ __launch_bounds__(256) void k_interp(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                                                const int* __restrict__ ci, const double* __restrict__ a,
+                                                const double* __restrict__ dinv,
+                                                const uint8_t* __restrict__ strong,
+                                                const int8_t* __restrict__ cf, const int* __restrict__ cidx,
+                                                const uint8_t* __restrict__ dir, int* __restrict__ pc,
+                                                double* __restrict__ pv, int* __restrict__ overflow) {
+  Tile t = tiles[blockIdx.x];
+  int i = t.r0 + threadIdx.x;
+  if (i >= t.r1) return;
+  int* pci = pc + (size_t)i * PW;
+  double* pvi = pv + (size_t)i * PW;
+  for (int q = 0; q < PW; ++q) { pci[q] = -1; pvi[q] = 0.0; }
+  if (cf[i] == CF_C) { pci[0] = cidx[i]; pvi[0] = 1.0; return; }
+  if (dir[i]) return;
+  int hc[kMaxChat];
+  double hw[kMaxChat];
+  int nh = 0;
+  bool ovf = false;
+  const int e0 = rp[i], e1 = rp[i + 1];
+  double aii = 0.0;
+  for (int e = e0; e < e1; ++e) {
+    int j = ci[e];
+    if (j == i) { aii = a[e]; continue; }
+    if (strong[e] && cf[j] == CF_C && find_in(hc, nh, j) < 0) {
+      if (nh < kMaxChat) hc[nh++] = j; else ovf = true;
+    }
+  }
+  for (int e = e0; e < e1; ++e) {
+    int k = ci[e];
+    if (k == i || !strong[e] || cf[k] != CF_F) continue;
+    for (int e2 = rp[k]; e2 < rp[k + 1]; ++e2) {
+      int l = ci[e2];
+      if (strong[e2] && cf[l] == CF_C && find_in(hc, nh, l) < 0) {
+        if (nh < kMaxChat) hc[nh++] = l; else ovf = true;
+      }
+    }
+  }
+  if (ovf) atomicAdd(overflow, 1);
+  if (nh == 0) return;
+  for (int p = 0; p < nh; ++p) hw[p] = 0.0;
+  double dd = aii;
+  for (int e = e0; e < e1; ++e) {
+    int j = ci[e];
+    if (j == i) continue;
+    double aij = a[e];
+    if (aij == 0.0) continue;
+    int p = find_in(hc, nh, j);
+    if (p >= 0) { hw[p] += aij; continue; }
+    if (strong[e] && cf[j] == CF_F) {
+      // distribute a_ij over the interpolatory set through row k = j
+      const int k = j;
+      const bool kpos = dinv[k] >= 0.0;
+      double den = 0.0;
+      for (int e2 = rp[k]; e2 < rp[k + 1]; ++e2) {
+        int l = ci[e2];
+        if (l == k) continue;
+        double akl = a[e2];
+        double abar = kpos ? (akl < 0.0 ? akl : 0.0) : (akl > 0.0 ? akl : 0.0);
+        if (abar != 0.0 && (l == i || find_in(hc, nh, l) >= 0)) den += abar;
+      }
+      if (den == 0.0) { dd += aij; continue; }
+      for (int e2 = rp[k]; e2 < rp[k + 1]; ++e2) {
+        int l = ci[e2];
+        if (l == k) continue;
+        double akl = a[e2];
+        double abar = kpos ? (akl < 0.0 ? akl : 0.0) : (akl > 0.0 ? akl : 0.0);
+        if (abar == 0.0) continue;
+        if (l == i) { dd += aij * abar / den; continue; }
+        int p2 = find_in(hc, nh, l);
+        if (p2 >= 0) hw[p2] += aij * abar / den;
+      }
+      continue;
+    }
+    if (dir[j]) continue;  // Dirichlet neighbour: its error is zero after relaxation
+    dd += aij;             // weak connection: lumped into the diagonal
+  }
+  if (dd == 0.0) return;
+  double total = 0.0;
+  for (int p = 0; p < nh; ++p) { hw[p] = -hw[p] / dd; total += hw[p]; }
+  // keep the PW largest |w| (lowest position first on ties)
+  int keep[PW];
+  int nk = 0;
+  for (int q = 0; q < PW && q < nh; ++q) {
+    int best = -1;
+    double bw = -1.0;
+    for (int p = 0; p < nh; ++p) {
+      bool used = false;
+      for (int u = 0; u < nk; ++u) used |= (keep[u] == p);
+      if (!used && fabs(hw[p]) > bw) { bw = fabs(hw[p]); best = p; }
+    }
+    if (best < 0 || bw == 0.0) break;
+    keep[nk++] = best;
+  }
+  double kept = 0.0;
+  for (int u = 0; u < nk; ++u) kept += hw[keep[u]];
+  double sc = (kept != 0.0) ? total / kept : 1.0;
+  // write sorted by coarse column
+  for (int u = 0; u < nk; ++u) {
+    int bu = u;
+    for (int u2 = u + 1; u2 < nk; ++u2)
+      if (cidx[hc[keep[u2]]] < cidx[hc[keep[bu]]]) bu = u2;
+    int tmp = keep[u]; keep[u] = keep[bu]; keep[bu] = tmp;
+    pci[u] = cidx[hc[keep[u]]];
+    pvi[u] = hw[keep[u]] * sc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// R = P^T as CSR over coarse rows (entries sorted by fine row)
+// ---------------------------------------------------------------------------
+__global__ void k_pt_count(const Tile* __restrict__ tiles, const int* __restrict__ pc,
+                           int* __restrict__ cnt) {
+  Tile t = tiles[blockIdx.x];
+  int i = t.r0 + threadIdx.x;
+  if (i >= t.r1) return;
+  for (int q = 0; q < PW; ++q) {
+    int c = pc[(size_t)i * PW + q];
+    if (c >= 0) atomicAdd(&cnt[c], 1);
+  }
+}
+
+__global__ void k_pt_fill(const Tile* __restrict__ tiles, const int* __restrict__ pc,
+                          const double* __restrict__ pv, const int* __restrict__ rrp,
+                          int* __restrict__ cursor, int* __restrict__ rci, double* __restrict__ rv) {
+  Tile t = tiles[blockIdx.x];
+  int i = t.r0 + threadIdx.x;
+  if (i >= t.r1) return;
+  for (int q = 0; q < PW; ++q) {
+    int c = pc[(size_t)i * PW + q];
+    if (c >= 0) {
+      int pos = rrp[c] + atomicAdd(&cursor[c], 1);
+      rci[pos] = i;
+      rv[pos] = pv[(size_t)i * PW + q];
+    }
+  }
+}
+
+__global__ void k_sort_rows(const int* __restrict__ rp, int* __restrict__ ci, double* __restrict__ v,
+                            int n) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= n) return;
+  int e0 = rp[I], e1 = rp[I + 1];
+  for (int e = e0 + 1; e < e1; ++e) {
+    int c = ci[e];
+    double x = v[e];
+    int f = e - 1;
+    while (f >= e0 && ci[f] > c) { ci[f + 1] = ci[f]; v[f + 1] = v[f]; --f; }
+    ci[f + 1] = c;
+    v[f + 1] = x;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Galerkin product A_c = R A P, one workgroup of kRapThreads per coarse row.
+// The row's (R entry, A entry) pairs are flattened over the lanes so that
+// their loads issue in parallel.  Phase 1 collects the distinct coarse
+// columns in an LDS hash set (sized to the row) and sorts them.  Phase 2
+// (numeric) writes the products of a chunk of pairs to LDS at fixed slots of
+// the enumeration order (R entry, A entry, P slot); the lane owning an output
+// column (column index mod kRapThreads) adds its products slot by slot, so
+// the sums are bit-reproducible whatever the batch and the launch shape.
+// err bits: 1 hash full, 2 R row too long, 4 too many distinct columns.
+// ---------------------------------------------------------------------------
+constexpr int kRapThreads = 128;
+constexpr int kRapRCap = 256;      // max entries of one R row
+constexpr int kRapHash = 2048;     // hash slots (>= 2 x products when possible)
+constexpr int kRapND = 1024;       // max distinct columns of one coarse row
+constexpr int kRapChunk = 256;     // (R, A) pairs per product chunk
+
+__device__ inline int rap_locate(const int* rO, int P, int f) {
+  int lo = 0, hi = P - 1;  // largest p with rO[p] <= f
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (rO[mid] <= f) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kRapThreads) void k_rap(int nc, const int* __restrict__ rrp,
+                                                     const int* __restrict__ rci,
+                                                     const double* __restrict__ rv,
+                                                     const int* __restrict__ rp, const int* __restrict__ ci,
+                                                     const double* __restrict__ a, const int* __restrict__ pc,
+                                                     const double* __restrict__ pv,
+                                                     const int* __restrict__ crp, int* __restrict__ ccnt,
+                                                     int* __restrict__ cci, double* __restrict__ cval,
+                                                     int* __restrict__ err) {
+  __shared__ int rS[kRapRCap];
+  __shared__ int rO[kRapRCap + 1];
+  __shared__ double rV[kRapRCap];
+  __shared__ double ubuf[kRapHash / 2];  // hash table, later the product values
+  __shared__ int lst[kRapND];
+  __shared__ double acc[kRapND];
+  __shared__ short ppos[kRapChunk * PW];
+  __shared__ int nd_sh;
+  int* tab = reinterpret_cast<int*>(ubuf);
+  double* pval = ubuf;
+  const int I = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (I >= nc) return;
+  const int p0 = rrp[I], P = rrp[I + 1] - p0;
+  if (P > kRapRCap) {
+    if (tid == 0) {
+      atomicOr(err, 2);
+      if (ccnt) ccnt[I] = 0;
+    }
+    return;
+  }
+  for (int t = tid; t < P; t += kRapThreads) {
+    int i = rci[p0 + t];
+    int b = rp[i];
+    rS[t] = b;
+    rO[t + 1] = rp[i + 1] - b;
+    rV[t] = rv[p0 + t];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    rO[0] = 0;
+    for (int t = 0; t < P; ++t) rO[t + 1] += rO[t];
+    nd_sh = 0;
+  }
+  __syncthreads();
+  const int E = rO[P];
+  int hs = 64;
+  while (hs < 2 * PW * E && hs < kRapHash) hs <<= 1;
+  for (int h = tid; h < hs; h += kRapThreads) tab[h] = -1;
+  __syncthreads();
+  bool full = false;
+  for (int f = tid; f < E; f += kRapThreads) {
+    const int p = rap_locate(rO, P, f);
+    const int k = ci[rS[p] + (f - rO[p])];
+    for (int q = 0; q < PW; ++q) {
+      int J = pc[(size_t)k * PW + q];
+      if (J < 0) continue;
+      unsigned h = mix32((uint32_t)J) & (hs - 1);
+      int probes = 0;
+      while (true) {
+        int old = atomicCAS(&tab[h], -1, J);
+        if (old == -1 || old == J) break;
+        h = (h + 1) & (hs - 1);
+        if (++probes >= hs) { full = true; break; }
+      }
+    }
+  }
+  if (full) atomicOr(err, 1);
+  __syncthreads();
+  bool over = false;
+  for (int h = tid; h < hs; h += kRapThreads) {
+    int J = tab[h];
+    if (J >= 0) {
+      int pos = atomicAdd(&nd_sh, 1);
+      if (pos < kRapND) lst[pos] = J; else over = true;
+    }
+  }
+  if (over) atomicOr(err, 4);
+  __syncthreads();
+  const int nd = nd_sh < kRapND ? nd_sh : kRapND;
+  if (ccnt) {  // symbolic pass
+    if (tid == 0) ccnt[I] = nd;
+    return;
+  }
+  int P2 = 1;
+  while (P2 < nd) P2 <<= 1;
+  for (int h = nd + tid; h < P2; h += kRapThreads) lst[h] = INT_MAX;
+  __syncthreads();
+  for (int k2 = 2; k2 <= P2; k2 <<= 1) {
+    for (int j = k2 >> 1; j > 0; j >>= 1) {
+      for (int idx = tid; idx < P2; idx += kRapThreads) {
+        int ixj = idx ^ j;
+        if (ixj > idx) {
+          int x = lst[idx], y = lst[ixj];
+          bool up = (idx & k2) == 0;
+          if ((x > y) == up) { lst[idx] = y; lst[ixj] = x; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const int base = crp[I];
+  for (int h = tid; h < nd; h += kRapThreads) {
+    cci[base + h] = lst[h];
+    acc[h] = 0.0;
+  }
+  __syncthreads();
+  for (int f0 = 0; f0 < E; f0 += kRapChunk) {
+    const int fe = (E < f0 + kRapChunk) ? E : f0 + kRapChunk;
+    for (int f = f0 + tid; f < fe; f += kRapThreads) {
+      const int p = rap_locate(rO, P, f);
+      const int e = rS[p] + (f - rO[p]);
+      const int k = ci[e];
+      const double ra = rV[p] * a[e];
+      for (int q = 0; q < PW; ++q) {
+        const int slot = (f - f0) * PW + q;
+        int J = pc[(size_t)k * PW + q];
+        short pos = -1;
+        if (J >= 0) {
+          int lo = 0, hi = nd - 1;
+          while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (lst[mid] < J) lo = mid + 1; else hi = mid;
+          }
+          if (lst[lo] == J) {
+            pos = (short)lo;
+            pval[slot] = ra * pv[(size_t)k * PW + q];
+          }
+        }
+        ppos[slot] = pos;
+      }
+    }
+    __syncthreads();
+    const int ns = (fe - f0) * PW;
+    for (int t = 0; t < ns; ++t) {
+      const int pos = ppos[t];
+      if (pos >= 0 && (pos % kRapThreads) == tid) acc[pos] += pval[t];
+    }
+    __syncthreads();
+  }
+  for (int h = tid; h < nd; h += kRapThreads) cval[base + h] = acc[h];
+}
+
+// ---------------------------------------------------------------------------
+// level helpers
+// ---------------------------------------------------------------------------
+__global__ void k_diag_inv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                           const double* __restrict__ a, double* __restrict__ d64,
+                           float* __restrict__ d32) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double d = 0.0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (ci[e] == i) d += a[e];
+  double di = d != 0.0 ? 1.0 / d : 0.0;
+  d64[i] = di;
+  if (d32) d32[i] = (float)di;
+}
+
+__global__ void k_cast(const double* __restrict__ in, float* __restrict__ out, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
+
+// ---------------------------------------------------------------------------
+// dense inverse of the coarsest blocks: Gauss-Jordan with partial pivoting on
+// [A | I], one workgroup per block.  blk = (row0, size, dense offset, slot).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_dense_inv(const int* __restrict__ blk, const int* __restrict__ rp,
+                                                   const int* __restrict__ ci, const double* __restrict__ a,
+                                                   double* __restrict__ work, double* __restrict__ inv64,
+                                                   float* __restrict__ inv32, int* __restrict__ err) {
+  __shared__ double fac[kDenseMax];
+  __shared__ double redv[256];
+  __shared__ int redi[256];
+  const int row0 = blk[4 * blockIdx.x], nb = blk[4 * blockIdx.x + 1];
+  const size_t doff = (size_t)blk[4 * blockIdx.x + 2];
+  double* M = work + 2 * doff;  // nb x 2nb, row-major
+  const int W = 2 * nb;
+  const int tid = threadIdx.x;
+  for (size_t idx = tid; idx < (size_t)nb * W; idx += blockDim.x) M[idx] = 0.0;
+  __syncthreads();
+  for (int i = tid; i < nb; i += blockDim.x) {
+    int r = row0 + i;
+    for (int e = rp[r]; e < rp[r + 1]; ++e) {
+      int c = ci[e] - row0;
+      if (c >= 0 && c < nb) M[(size_t)i * W + c] += a[e];
+    }
+    M[(size_t)i * W + nb + i] = 1.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    double bv = -1.0;
+    int bi = k;
+    for (int i = k + tid; i < nb; i += blockDim.x) {
+      double v = fabs(M[(size_t)i * W + k]);
+      if (v > bv) { bv = v; bi = i; }
+    }
+    redv[tid] = bv;
+    redi[tid] = bi;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+      if (tid < o) {
+        double v2 = redv[tid + o];
+        int i2 = redi[tid + o];
+        if (v2 > redv[tid] || (v2 == redv[tid] && i2 < redi[tid])) { redv[tid] = v2; redi[tid] = i2; }
+      }
+      __syncthreads();
+    }
+    const int p = redi[0];
+    const double pmag = redv[0];
+    __syncthreads();
+    if (!(pmag > 0.0)) {
+      if (tid == 0) atomicOr(err, 4);
+      return;
+    }
+    if (p != k)
+      for (int j = tid; j < W; j += blockDim.x) {
+        double t0 = M[(size_t)k * W + j];
+        M[(size_t)k * W + j] = M[(size_t)p * W + j];
+        M[(size_t)p * W + j] = t0;
+      }
+    __syncthreads();
+    const double piv = M[(size_t)k * W + k];
+    __syncthreads();
+    for (int j = tid; j < W; j += blockDim.x) M[(size_t)k * W + j] /= piv;
+    for (int i = tid; i < nb; i += blockDim.x) fac[i] = M[(size_t)i * W + k];
+    __syncthreads();
+    for (int j = tid; j < W; j += blockDim.x) {
+      const double mkj = M[(size_t)k * W + j];
+      if (mkj == 0.0) continue;
+      for (int i = 0; i < nb; ++i)
+        if (i != k) M[(size_t)i * W + j] -= fac[i] * mkj;
+    }
+    __syncthreads();
+  }
+  for (size_t idx = tid; idx < (size_t)nb * nb; idx += blockDim.x) {
+    int j = (int)(idx / nb), i = (int)(idx % nb);  // column-major output
+    double v = M[(size_t)i * W + nb + j];
+    inv64[doff + idx] = v;
+    if (inv32) inv32[doff + idx] = (float)v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// cycle kernels (T = float for mixed precision, double for FP64 cycles)
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void k_smooth(const Tile* __restrict__ tiles, const int* __restrict__ act,
+                                                const int* __restrict__ rp, const int* __restrict__ ci,
+                                                const T* __restrict__ a, const T* __restrict__ dinv,
+                                                const T* __restrict__ b, const T* __restrict__ xin,
+                                                T* __restrict__ xout, T omega, int first) {
+  Tile t = tiles[blockIdx.x];
+  if (!act[t.game]) return;
+  int i = t.r0 + threadIdx.x;
+  if (i >= t.r1) return;
+  if (first) {
+    xout[i] = omega * dinv[i] * b[i];
+    return;
+  }
+  T s = b[i];
+  for (int e = rp[i]; e < rp[i + 1]; ++e) s -= a[e] * xin[ci[e]];
+  xout[i] = xin[i] + omega * dinv[i] * s;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_resid(const Tile* __restrict__ tiles, const int* __restrict__ act,
+                                               const int* __restrict__ rp, const int* __restrict__ ci,
+                                               const T* __restrict__ a, const T* __restrict__ b,
+                                               const T* __restrict__ x, T* __restrict__ r) {
+  Tile t = tiles[blockIdx.x];
+  if (!act[t.game]) return;
+  int i = t.r0 + threadIdx.x;
+  if (i >= t.r1) return;
+  T s = b[i];
+  for (int e = rp[i]; e < rp[i + 1]; ++e) s -= a[e] * x[ci[e]];
+  r[i] = s;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_restrict(const Tile* __restrict__ tiles, const int* __restrict__ act,
+                                                  const int* __restrict__ rrp, const int* __restrict__ rci,
+                                                  const T* __restrict__ rv, const T* __restrict__ rf,
+                                                  T* __restrict__ bc) {
+  Tile t = tiles[blockIdx.x];
+  if (!act[t.game]) return;
+  int I = t.r0 + threadIdx.x;
+  if (I >= t.r1) return;
+  T s = 0;
+  for (int e = rrp[I]; e < rrp[I + 1]; ++e) s += rv[e] * rf[rci[e]];
+  bc[I] = s;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_prolong(const Tile* __restrict__ tiles, const int* __restrict__ act,
+                                                 const int* __restrict__ pc, const T* __restrict__ pv,
+                                                 const T* __restrict__ xc, T* __restrict__ x) {
+  Tile t = tiles[blockIdx.x];
+  if (!act[t.game]) return;
+  int i = t.r0 + threadIdx.x;
+  if (i >= t.r1) return;
+  T s = x[i];
+  for (int q = 0; q < PW; ++q) {
+    int c = pc[(size_t)i * PW + q];
+    if (c >= 0) s += pv[(size_t)i * PW + q] * xc[c];
+  }
+  x[i] = s;
+}
+
+// x_blk = inv_blk b_blk, one workgroup per block; inv is column-major
+template <class T>
+__global__ __launch_bounds__(256) void k_dense_solve(const int* __restrict__ blk, const int* __restrict__ act,
+                                                     const T* __restrict__ inv, const T* __restrict__ b,
+                                                     T* __restrict__ x) {
+  __shared__ T bs[kDenseMax];
+  const int row0 = blk[4 * blockIdx.x], nb = blk[4 * blockIdx.x + 1];
+  const size_t doff = (size_t)blk[4 * blockIdx.x + 2];
+  const int slot = blk[4 * blockIdx.x + 3];
+  if (!act[slot]) return;
+  for (int j = threadIdx.x; j < nb; j += blockDim.x) bs[j] = b[row0 + j];
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    T s = 0;
+    for (int j = 0; j < nb; ++j) s += inv[doff + (size_t)j * nb + i] * bs[j];
+    x[row0 + i] = s;
+  }
+}
+
+// FP64 residual of the refinement: r = b - A x, its copy in the cycle type,
+// and per-game max |r|, max |x|.
+template <class T>
+__global__ __launch_bounds__(256) void k_resid64(const Tile* __restrict__ tiles, const int* __restrict__ act,
+                                                 const int* __restrict__ rp, const int* __restrict__ ci,
+                                                 const double* __restrict__ a, const double* __restrict__ b,
+                                                 const double* __restrict__ x, T* __restrict__ rc,
+                                                 double* __restrict__ norm) {
+  Tile t = tiles[blockIdx.x];
+  if (!act[t.game]) return;
+  int i = t.r0 + threadIdx.x;
+  double rm = 0.0, xm = 0.0;
+  if (i < t.r1) {
+    double s = b[i];
+    for (int e = rp[i]; e < rp[i + 1]; ++e) s -= a[e] * x[ci[e]];
+    rc[i] = (T)s;
+    rm = fabs(s);
+    xm = fabs(x[i]);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    rm = fmax(rm, __shfl_xor(rm, o));
+    xm = fmax(xm, __shfl_xor(xm, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomic_max_nonneg(&norm[4 * t.game], rm);
+    atomic_max_nonneg(&norm[4 * t.game + 1], xm);
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_update64(const Tile* __restrict__ tiles, const int* __restrict__ act,
+                                                  const T* __restrict__ e, double* __restrict__ x) {
+  Tile t = tiles[blockIdx.x];
+  if (!act[t.game]) return;
+  int i = t.r0 + threadIdx.x;
+  if (i < t.r1) x[i] += (double)e[i];
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+void amg_dirichlet(const Tile* t, int nt, const int* rp, const int* ci, const double* a, uint8_t* dir,
+                   hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_dirichlet, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, a, dir);
+  SHP_LAUNCH_CHECK();
+}
+void amg_dir_scale(const Tile* t, int nt, const uint8_t* dir, double f, double* d64, float* d32,
+                   hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_dir_scale, dim3(nt), dim3(kTileRows), 0, s, t, dir, f, d64, d32);
+  SHP_LAUNCH_CHECK();
+}
+void amg_strength(const Tile* t, int nt, const int* rp, const int* ci, const double* a,
+                  const uint8_t* dir, double theta, uint8_t* strong, int* lam, hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_strength, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, a, dir, theta, strong, lam);
+  SHP_LAUNCH_CHECK();
+}
+void amg_strength_t(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
+                    const int* st_rp, int* cursor, int* st_ci, hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_strength_t, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, strong, st_rp, cursor,
+                     st_ci);
+  SHP_LAUNCH_CHECK();
+}
+void amg_pmis_init(const Tile* t, int nt, const int* goff, const uint8_t* dir, const int* lam,
+                   uint32_t salt, int8_t* cf, uint64_t* key, hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_pmis_init, dim3(nt), dim3(kTileRows), 0, s, t, goff, dir, lam, salt, cf, key);
+  SHP_LAUNCH_CHECK();
+}
+void amg_pmis_select(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
+                     const int* st_rp, const int* st_ci, const int8_t* cf, const uint64_t* key,
+                     int* newc, hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_pmis_select, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, strong, st_rp, st_ci,
+                     cf, key, newc);
+  SHP_LAUNCH_CHECK();
+}
+void amg_pmis_update(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
+                     int8_t* cf, const int* newc, int* left, hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_pmis_update, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, strong, cf, newc, left);
+  SHP_LAUNCH_CHECK();
+}
+void amg_fill_cf(const Tile* t, int nt, int8_t* cf, int8_t val, hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_fill_cf, dim3(nt), dim3(kTileRows), 0, s, t, cf, val);
+  SHP_LAUNCH_CHECK();
+}
+void amg_is_c(const int8_t* cf, int* out, int n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_is_c, dim3(grid_for(n)), dim3(kBlock), 0, s, cf, out, n);
+  SHP_LAUNCH_CHECK();
+}
+void amg_gather_int(const int* src, const int* idx, int m, int* dst, hipStream_t s) {
+  if (!m) return;
+  hipLaunchKernelGGL(k_gather_int, dim3(grid_for(m)), dim3(kBlock), 0, s, src, idx, m, dst);
+  SHP_LAUNCH_CHECK();
+}
+void amg_interp(const Tile* t, int nt, const int* rp, const int* ci, const double* a, const double* dinv,
+                const uint8_t* strong, const int8_t* cf, const int* cidx, const uint8_t* dir, int* pc,
+                double* pv, int* overflow, hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_interp, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, a, dinv, strong, cf, cidx, dir,
+                     pc, pv, overflow);
+  SHP_LAUNCH_CHECK();
+}
+void amg_pt_count(const Tile* t, int nt, const int* pc, int* cnt, hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_pt_count, dim3(nt), dim3(kTileRows), 0, s, t, pc, cnt);
+  SHP_LAUNCH_CHECK();
+}
+void amg_pt_fill(const Tile* t, int nt, const int* pc, const double* pv, const int* rrp, int* cursor,
+                 int* rci, double* rv, hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_pt_fill, dim3(nt), dim3(kTileRows), 0, s, t, pc, pv, rrp, cursor, rci, rv);
+  SHP_LAUNCH_CHECK();
+}
+void amg_sort_rows(const int* rp, int* ci, double* v, int n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(n)), dim3(kBlock), 0, s, rp, ci, v, n);
+  SHP_LAUNCH_CHECK();
+}
+void amg_rap(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,
+             const double* a, const int* pc, const double* pv, const int* crp, int* ccnt, int* cci,
+             double* cval, int* err, hipStream_t s) {
+  if (!nc) return;
+  hipLaunchKernelGGL(k_rap, dim3(nc), dim3(kRapThreads), 0, s, nc, rrp, rci, rv, rp, ci, a, pc, pv, crp, ccnt,
+                     cci, cval, err);
+  SHP_LAUNCH_CHECK();
+}
+void amg_diag_inv(int n, const int* rp, const int* ci, const double* a, double* d64, float* d32,
+                  hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_diag_inv, dim3(grid_for(n)), dim3(kBlock), 0, s, n, rp, ci, a, d64, d32);
+  SHP_LAUNCH_CHECK();
+}
+void amg_cast(const double* in, float* out, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_cast, dim3(grid_for((int64_t)n)), dim3(kBlock), 0, s, in, out, n);
+  SHP_LAUNCH_CHECK();
+}
+void amg_dense_inv(const int* blk, int nblk, const int* rp, const int* ci, const double* a, double* work,
+                   double* inv64, float* inv32, int* err, hipStream_t s) {
+  if (!nblk) return;
+  hipLaunchKernelGGL(k_dense_inv, dim3(nblk), dim3(256), 0, s, blk, rp, ci, a, work, inv64, inv32, err);
+  SHP_LAUNCH_CHECK();
+}
+
+template <class T>
+void cyc_smooth(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const T* a,
+                const T* dinv, const T* b, const T* xin, T* xout, T omega, int first, hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_smooth<T>, dim3(nt), dim3(kTileRows), 0, s, t, act, rp, ci, a, dinv, b, xin, xout,
+                     omega, first);
+  SHP_LAUNCH_CHECK();
+}
+template <class T>
+void cyc_resid(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const T* a, const T* b,
+               const T* x, T* r, hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_resid<T>, dim3(nt), dim3(kTileRows), 0, s, t, act, rp, ci, a, b, x, r);
+  SHP_LAUNCH_CHECK();
+}
+template <class T>
+void cyc_restrict(const Tile* t, int nt, const int* act, const int* rrp, const int* rci, const T* rv,
+                  const T* rf, T* bc, hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_restrict<T>, dim3(nt), dim3(kTileRows), 0, s, t, act, rrp, rci, rv, rf, bc);
+  SHP_LAUNCH_CHECK();
+}
+template <class T>
+void cyc_prolong(const Tile* t, int nt, const int* act, const int* pc, const T* pv, const T* xc, T* x,
+                 hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_prolong<T>, dim3(nt), dim3(kTileRows), 0, s, t, act, pc, pv, xc, x);
+  SHP_LAUNCH_CHECK();
+}
+template <class T>
+void cyc_dense(const int* blk, int nblk, const int* act, const T* inv, const T* b, T* x, hipStream_t s) {
+  if (!nblk) return;
+  hipLaunchKernelGGL(k_dense_solve<T>, dim3(nblk), dim3(256), 0, s, blk, act, inv, b, x);
+  SHP_LAUNCH_CHECK();
+}
+template <class T>
+void cyc_resid64(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const double* a,
+                 const double* b, const double* x, T* rc, double* norm, hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_resid64<T>, dim3(nt), dim3(kTileRows), 0, s, t, act, rp, ci, a, b, x, rc, norm);
+  SHP_LAUNCH_CHECK();
+}
+template <class T>
+void cyc_update64(const Tile* t, int nt, const int* act, const T* e, double* x, hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_update64<T>, dim3(nt), dim3(kTileRows), 0, s, t, act, e, x);
+  SHP_LAUNCH_CHECK();
+}
+
+#define SHP_INST(T)                                                                                  \
+  template void cyc_smooth<T>(const Tile*, int, const int*, const int*, const int*, const T*, const T*, \
+                              const T*, const T*, T*, T, int, hipStream_t);                          \
+  template void cyc_resid<T>(const Tile*, int, const int*, const int*, const int*, const T*, const T*,  \
+                             const T*, T*, hipStream_t);                                             \
+  template void cyc_restrict<T>(const Tile*, int, const int*, const int*, const int*, const T*,        \
+                                const T*, T*, hipStream_t);                                          \
+  template void cyc_prolong<T>(const Tile*, int, const int*, const int*, const T*, const T*, T*,       \
+                               hipStream_t);                                                         \
+  template void cyc_dense<T>(const int*, int, const int*, const T*, const T*, T*, hipStream_t);        \
+  template void cyc_resid64<T>(const Tile*, int, const int*, const int*, const int*, const double*,    \
+                               const double*, const double*, T*, double*, hipStream_t);              \
+  template void cyc_update64<T>(const Tile*, int, const int*, const T*, double*, hipStream_t);
+SHP_INST(float)
+SHP_INST(double)
+#undef SHP_INST
+
+}  // namespace shp

@@ -1,0 +1,62 @@
+// Launchers of the AMG setup and cycle kernels.
+#pragma once
+
+#include "internal.hpp"
+
+namespace shp {
+
+void amg_dirichlet(const Tile* t, int nt, const int* rp, const int* ci, const double* a, uint8_t* dir,
+                   hipStream_t s);
+void amg_dir_scale(const Tile* t, int nt, const uint8_t* dir, double f, double* d64, float* d32,
+                   hipStream_t s);
+void amg_strength(const Tile* t, int nt, const int* rp, const int* ci, const double* a,
+                  const uint8_t* dir, double theta, uint8_t* strong, int* lam, hipStream_t s);
+void amg_strength_t(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
+                    const int* st_rp, int* cursor, int* st_ci, hipStream_t s);
+void amg_pmis_init(const Tile* t, int nt, const int* goff, const uint8_t* dir, const int* lam,
+                   uint32_t salt, int8_t* cf, uint64_t* key, hipStream_t s);
+void amg_pmis_select(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
+                     const int* st_rp, const int* st_ci, const int8_t* cf, const uint64_t* key,
+                     int* newc, hipStream_t s);
+void amg_pmis_update(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
+                     int8_t* cf, const int* newc, int* left, hipStream_t s);
+void amg_fill_cf(const Tile* t, int nt, int8_t* cf, int8_t val, hipStream_t s);
+void amg_is_c(const int8_t* cf, int* out, int n, hipStream_t s);
+void amg_gather_int(const int* src, const int* idx, int m, int* dst, hipStream_t s);
+void amg_interp(const Tile* t, int nt, const int* rp, const int* ci, const double* a, const double* dinv,
+                const uint8_t* strong, const int8_t* cf, const int* cidx, const uint8_t* dir, int* pc,
+                double* pv, int* overflow, hipStream_t s);
+void amg_pt_count(const Tile* t, int nt, const int* pc, int* cnt, hipStream_t s);
+void amg_pt_fill(const Tile* t, int nt, const int* pc, const double* pv, const int* rrp, int* cursor,
+                 int* rci, double* rv, hipStream_t s);
+void amg_sort_rows(const int* rp, int* ci, double* v, int n, hipStream_t s);
+void amg_rap(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,
+             const double* a, const int* pc, const double* pv, const int* crp, int* ccnt, int* cci,
+             double* cval, int* err, hipStream_t s);
+void amg_diag_inv(int n, const int* rp, const int* ci, const double* a, double* d64, float* d32,
+                  hipStream_t s);
+void amg_cast(const double* in, float* out, size_t n, hipStream_t s);
+void amg_dense_inv(const int* blk, int nblk, const int* rp, const int* ci, const double* a, double* work,
+                   double* inv64, float* inv32, int* err, hipStream_t s);
+
+template <class T>
+void cyc_smooth(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const T* a,
+                const T* dinv, const T* b, const T* xin, T* xout, T omega, int first, hipStream_t s);
+template <class T>
+void cyc_resid(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const T* a, const T* b,
+               const T* x, T* r, hipStream_t s);
+template <class T>
+void cyc_restrict(const Tile* t, int nt, const int* act, const int* rrp, const int* rci, const T* rv,
+                  const T* rf, T* bc, hipStream_t s);
+template <class T>
+void cyc_prolong(const Tile* t, int nt, const int* act, const int* pc, const T* pv, const T* xc, T* x,
+                 hipStream_t s);
+template <class T>
+void cyc_dense(const int* blk, int nblk, const int* act, const T* inv, const T* b, T* x, hipStream_t s);
+template <class T>
+void cyc_resid64(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const double* a,
+                 const double* b, const double* x, T* rc, double* norm, hipStream_t s);
+template <class T>
+void cyc_update64(const Tile* t, int nt, const int* act, const T* e, double* x, hipStream_t s);
+
+}  // namespace shp

@@ -1,0 +1,502 @@
+// C ABI of libshapley: argument checking, game creation, solve drivers
+// (AMGpi, FAMGpi, batch), result getters.
+#include "internal.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+
+struct shapley_game_s {
+  shp::Game* g;
+};
+
+namespace shp {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+Game::~Game() {
+  for (Game* l : levels) delete l;
+  levels.clear();
+  if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+size_t Game::device_bytes() const {
+  size_t b = rp.bytes() + ci.bytes() + w.bytes() + r.bytes() + valid.bytes() + urp.bytes() + uci.bytes() +
+             v.bytes() + F.bytes() + alpha.bytes() + beta.bytes() + beta_in.bytes() + alpha_c.bytes() +
+             beta_c.bytes() + bvals.bytes();
+  for (const Game* l : levels) b += l->device_bytes();
+  return b;
+}
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+#define SHP_REQUIRE(cond, msg) \
+  do {                         \
+    if (!(cond)) throw Error(SHAPLEY_EINVAL, msg); \
+  } while (0)
+
+static Game* create_game(int64_t n64, int m1, int m2, const int64_t* row_ptr, const int32_t* col,
+                         const double* w, const double* r, double mu, const uint8_t* valid,
+                         const shapley_grid* grid, uint32_t flags, void* stream) {
+  SHP_REQUIRE(flags == SHAPLEY_HOST_PTRS, "unsupported flags");
+  SHP_REQUIRE(n64 >= 1 && m1 >= 1 && m2 >= 1, "n, m1 and m2 must be positive");
+  SHP_REQUIRE((int64_t)m1 * m2 <= 256, "m1 * m2 must not exceed 256");
+  const int64_t nrows64 = n64 * m1 * m2;
+  SHP_REQUIRE(nrows64 < INT32_MAX, "n * m1 * m2 must be below 2^31");
+  SHP_REQUIRE(row_ptr && r && (row_ptr[nrows64] == 0 || (col && w)), "null input array");
+  SHP_REQUIRE(std::isfinite(mu) && mu > 0.0 && mu <= 1.0, "mu must lie in (0, 1]");
+  SHP_REQUIRE(row_ptr[0] == 0, "row_ptr[0] must be 0");
+  const int n = (int)n64, nrows = (int)nrows64;
+  const int64_t nnz = row_ptr[nrows];
+  SHP_REQUIRE(nnz >= 0 && nnz < INT32_MAX, "number of transitions must be below 2^31");
+  std::vector<int> rp32(nrows + 1);
+  std::vector<int> ci_sorted;
+  std::vector<double> w_sorted;
+  bool need_sort = false;
+  for (int i = 0; i < nrows; ++i) {
+    SHP_REQUIRE(row_ptr[i + 1] >= row_ptr[i], "row_ptr must be non-decreasing");
+    rp32[i] = (int)row_ptr[i];
+    double sum = 0.0;
+    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      SHP_REQUIRE(col[e] >= 0 && col[e] < n, "column index out of range");
+      SHP_REQUIRE(std::isfinite(w[e]) && w[e] >= 0.0, "transition weights must be finite and >= 0");
+      if (e > row_ptr[i] && col[e] < col[e - 1]) need_sort = true;
+      sum += w[e];
+    }
+    SHP_REQUIRE(sum <= 1.0 + 1e-12, "row sum of transition weights exceeds 1");
+    SHP_REQUIRE(std::isfinite(r[i]), "rewards must be finite");
+  }
+  rp32[nrows] = (int)nnz;
+  if (valid) {
+    for (int x = 0; x < n; ++x) {
+      bool any = false;
+      for (int q = 0; q < m1 * m2; ++q) any |= valid[(int64_t)x * m1 * m2 + q] != 0;
+      SHP_REQUIRE(any, "empty action set at a state");
+    }
+  }
+  const int32_t* colp = col;
+  const double* wp = w;
+  if (need_sort) {
+    ci_sorted.assign(col, col + nnz);
+    w_sorted.assign(w, w + nnz);
+    std::vector<int> idx;
+    for (int i = 0; i < nrows; ++i) {
+      int e0 = rp32[i], e1 = rp32[i + 1];
+      idx.resize(e1 - e0);
+      std::iota(idx.begin(), idx.end(), e0);
+      std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return col[a] < col[b]; });
+      for (int k = 0; k < e1 - e0; ++k) { ci_sorted[e0 + k] = col[idx[k]]; w_sorted[e0 + k] = w[idx[k]]; }
+    }
+    colp = ci_sorted.data();
+    wp = w_sorted.data();
+  }
+  if (grid) {
+    SHP_REQUIRE(grid->dim >= 1 && grid->dim <= 3 && grid->s >= 1, "grid: dim in 1..3 and s >= 1");
+    int64_t p = 1;
+    for (int k = 0; k < grid->dim; ++k) p *= grid->s;
+    SHP_REQUIRE(p == n64, "grid: s^dim must equal n");
+  }
+  std::unique_ptr<Game> g(new Game());
+  g->n = n; g->m1 = m1; g->m2 = m2; g->nrows = nrows; g->nnz = nnz; g->mu = mu;
+  if (stream) {
+    g->stream = (hipStream_t)stream;
+  } else {
+    SHP_HIP(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+    g->own_stream = true;
+  }
+  hipStream_t s = g->stream;
+  g->rp.alloc(nrows + 1);
+  g->ci.alloc(std::max<int64_t>(nnz, 1));
+  g->w.alloc(std::max<int64_t>(nnz, 1));
+  g->r.alloc(nrows);
+  h2d(g->rp.p, rp32.data(), nrows + 1, s);
+  h2d(g->ci.p, colp, nnz, s);
+  h2d(g->w.p, wp, nnz, s);
+  h2d(g->r.p, r, nrows, s);
+  if (valid) {
+    g->valid.alloc(nrows);
+    h2d(g->valid.p, valid, nrows, s);
+  }
+  // level-0 pattern: union of the columns of a state's rows plus the diagonal
+  g->urp.alloc(n + 1);
+  DBuf<int> cnt(n + 1), scr;
+  SHP_HIP(hipMemsetAsync(cnt.p + n, 0, sizeof(int), s));
+  launch_union_count(g->rp.p, g->ci.p, n, m1, m2, cnt.p, nullptr, s);
+  scan_exclusive(cnt.p, g->urp.p, n + 1, s, scr);
+  int unnz = 0;
+  d2h(&unnz, g->urp.p + n, 1, s);
+  SHP_HIP(hipStreamSynchronize(s));
+  g->unnz = unnz;
+  g->uci.alloc(std::max(unnz, 1));
+  launch_union_fill(g->rp.p, g->ci.p, n, m1, m2, g->urp.p, g->uci.p, s);
+  g->v.alloc(n); g->F.alloc(n);
+  g->alpha.alloc(n); g->beta.alloc(n); g->beta_in.alloc(n); g->alpha_c.alloc(n); g->beta_c.alloc(n);
+  SHP_HIP(hipMemsetAsync(g->v.p, 0, sizeof(double) * n, s));
+  SHP_HIP(hipMemsetAsync(g->alpha.p, 0, sizeof(int) * n, s));
+  SHP_HIP(hipMemsetAsync(g->beta.p, 0, sizeof(int) * n, s));
+  if (grid) {
+    g->dim = grid->dim;
+    g->s = grid->s;
+    if (grid->bvals) {
+      int64_t ne = 1;
+      for (int k = 0; k < grid->dim; ++k) ne *= (grid->s + 2);
+      g->bvals.alloc(ne);
+      h2d(g->bvals.p, grid->bvals, ne, s);
+      g->has_bvals = true;
+    }
+  }
+  SHP_HIP(hipStreamSynchronize(s));
+  return g.release();
+}
+
+static void check_opts(const shapley_solve_opts& o) {
+  SHP_REQUIRE(std::isfinite(o.eps) && o.eps >= 0.0, "eps must be >= 0");
+  SHP_REQUIRE(o.precision == SHAPLEY_FP64 || o.precision == SHAPLEY_MIXED, "bad precision");
+  SHP_REQUIRE(o.method == SHAPLEY_AMGPI || o.method == SHAPLEY_FAMGPI, "bad method");
+  SHP_REQUIRE(o.max_outer >= 1 && o.max_inner >= 1 && o.max_cycles >= 1, "iteration limits must be >= 1");
+  SHP_REQUIRE(o.nu1 >= 1 && o.nu2 >= 0, "nu1 >= 1 and nu2 >= 0 required");
+  SHP_REQUIRE(o.omega > 0.0 && o.omega < 2.0, "omega must lie in (0, 2)");
+  SHP_REQUIRE(o.coarse_max >= 1 && o.coarse_max <= kDenseMax, "coarse_max must lie in [1, 1024]");
+  SHP_REQUIRE(o.max_levels >= 1 && o.max_levels <= 64, "max_levels must lie in [1, 64]");
+  SHP_REQUIRE(o.lin_rtol >= 0.0 && o.lin_atol >= 0.0 && o.tie_rtol >= 0.0, "tolerances must be >= 0");
+  SHP_REQUIRE(o.c_fmg > 0.0, "c_fmg must be > 0");
+}
+
+static void load_warm_start(Game* g, const shapley_solve_opts& o, SlotState& S, hipStream_t s) {
+  const int n = g->n;
+  if (o.v0) h2d(g->v.p, o.v0, n, s);
+  else SHP_HIP(hipMemsetAsync(g->v.p, 0, sizeof(double) * n, s));
+  if (o.alpha0) {
+    for (int x = 0; x < n; ++x)
+      SHP_REQUIRE(o.alpha0[x] >= 0 && o.alpha0[x] < g->m1, "alpha0 out of range");
+    h2d(g->alpha.p, o.alpha0, n, s);
+    S.init_alpha = true;
+  } else {
+    SHP_HIP(hipMemsetAsync(g->alpha.p, 0xFF, sizeof(int) * n, s));
+  }
+  if (o.alpha0 && o.beta0) {
+    for (int x = 0; x < n; ++x) SHP_REQUIRE(o.beta0[x] >= 0 && o.beta0[x] < g->m2, "beta0 out of range");
+    h2d(g->beta.p, o.beta0, n, s);
+    S.init_beta = true;
+  } else {
+    SHP_HIP(hipMemsetAsync(g->beta.p, 0xFF, sizeof(int) * n, s));
+  }
+  SHP_HIP(hipStreamSynchronize(s));
+}
+
+static void fill_stats(const SlotState& S, shapley_stats* st, double seconds) {
+  if (!st) return;
+  std::memset(st, 0, sizeof(*st));
+  st->outer = S.k;
+  st->inner_total = S.inner_total;
+  st->cycles_total = S.cycles_total;
+  st->levels = S.levels;
+  st->converged = S.converged ? 1 : 0;
+  st->fmg_levels = 1;
+  st->residual = S.res;
+  st->residual_l2 = S.res_l2;
+  st->seconds = seconds;
+  st->setup_seconds = S.setup_s;
+  st->cycle_seconds = S.cycle_s;
+  st->improve_seconds = S.improve_s;
+  st->op_complexity = S.opc;
+  st->grid_complexity = S.gc;
+  std::memcpy(st->inner_per_outer, S.inner_per_outer, sizeof(st->inner_per_outer));
+}
+
+// AMGpi on one game (the value step and improvement of every iteration run
+// in the engine); returns the slot's status.
+static int run_amgpi(Game* g, const shapley_solve_opts& o, double eps, bool warm_from_opts,
+                     hipStream_t s, SlotState& S) {
+  S = SlotState();
+  S.g = g;
+  S.opt = engine_opts_from(o, g->dim);
+  S.opt.eps = eps;
+  if (warm_from_opts) {
+    load_warm_start(g, o, S, s);
+  } else {
+    S.init_alpha = S.init_beta = true;  // v, alpha, beta already on the device
+  }
+  Engine eng(s);
+  eng.slots.push_back(&S);
+  while (eng.step() > 0) {
+  }
+  g->solved = true;
+  return S.status;
+}
+
+}  // namespace shp
+
+using namespace shp;
+
+template <class F>
+static int guarded(F&& f) {
+  try {
+    f();
+    return SHAPLEY_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return SHAPLEY_ENOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return SHAPLEY_EDEVICE;
+  }
+}
+
+extern "C" {
+
+const char* shapley_last_error(void) { return g_last_error.c_str(); }
+
+void shapley_default_opts(shapley_solve_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->eps = 0.0;
+  o->precision = SHAPLEY_FP64;
+  o->method = SHAPLEY_AMGPI;
+  o->c_fmg = 1e-2;
+  o->max_outer = 100000;
+  o->max_inner = 100000;
+  o->max_cycles = 200;
+  o->lin_rtol = 1e-14;
+  o->lin_atol = 0.0;
+  o->tie_rtol = 1e-12;
+  o->theta = -1.0;
+  o->nu1 = 2;
+  o->nu2 = 2;
+  o->omega = 0.8;
+  o->coarse_max = 100;
+  o->max_levels = 25;
+  o->verbose = 0;
+  o->stream = nullptr;
+}
+
+int shapley_game_create(shapley_game_t* out, int64_t n, int32_t m1, int32_t m2, const int64_t* row_ptr,
+                        const int32_t* col, const double* w, const double* r, double mu,
+                        const uint8_t* valid, const shapley_grid* grid, uint32_t flags, void* stream) {
+  return guarded([&] {
+    SHP_REQUIRE(out != nullptr, "out must not be null");
+    Game* g = create_game(n, m1, m2, row_ptr, col, w, r, mu, valid, grid, flags, stream);
+    *out = new shapley_game_s{g};
+  });
+}
+
+int shapley_game_create_hierarchy(shapley_game_t* out, int32_t nlev, shapley_game_t* levels) {
+  return guarded([&] {
+    SHP_REQUIRE(out && levels && nlev >= 1, "bad hierarchy arguments");
+    int dim = -1;
+    for (int l = 0; l < nlev; ++l) {
+      SHP_REQUIRE(levels[l] && levels[l]->g, "null level handle");
+      Game* g = levels[l]->g;
+      SHP_REQUIRE(!g->is_hierarchy(), "levels must be plain games");
+      SHP_REQUIRE(g->dim >= 1, "every level needs a grid description");
+      if (dim < 0) dim = g->dim;
+      SHP_REQUIRE(g->dim == dim, "levels must share the grid dimension");
+      if (l > 0) SHP_REQUIRE(g->s > levels[l - 1]->g->s, "levels must be ordered coarse -> fine");
+    }
+    Game* h = new Game();
+    for (int l = 0; l < nlev; ++l) {
+      h->levels.push_back(levels[l]->g);
+      delete levels[l];
+      levels[l] = nullptr;
+    }
+    Game* f = h->levels.back();
+    h->n = f->n; h->m1 = f->m1; h->m2 = f->m2; h->dim = f->dim; h->s = f->s;
+    h->stream = f->stream;
+    *out = new shapley_game_s{h};
+  });
+}
+
+int shapley_solve(shapley_game_t gh, const shapley_solve_opts* op, shapley_stats* st) {
+  int status = SHAPLEY_OK;
+  int rc = guarded([&] {
+    SHP_REQUIRE(gh && gh->g, "null game");
+    shapley_solve_opts o;
+    if (op) o = *op; else shapley_default_opts(&o);
+    check_opts(o);
+    Game* g = gh->g;
+    hipStream_t s = o.stream ? (hipStream_t)o.stream : g->finest()->stream;
+    double t0 = now_s();
+    SlotState S;
+    if (g->is_hierarchy() && o.method == SHAPLEY_FAMGPI) {
+      // FAMGpi (Algorithm algo-FAMGPI): coarse -> fine with eps_l = c h_l^2,
+      // transfers of (v, alpha, beta) by I and U between consecutive levels.
+      const int L = (int)g->levels.size();
+      int outer = 0, inner = 0, cycles = 0;
+      double su = 0, cy = 0, im = 0;
+      for (int l = 0; l < L; ++l) {
+        Game* lg = g->levels[l];
+        bool last = l == L - 1;
+        double h = 1.0 / (lg->s + 1);
+        double eps = last ? o.eps : o.c_fmg * h * h;
+        if (l > 0) {
+          fmg_transfer(g->levels[l - 1], lg, s);
+          SHP_HIP(hipStreamSynchronize(s));
+        }
+        int stt = run_amgpi(lg, o, eps, l == 0, s, S);
+        outer += S.k; inner += S.inner_total; cycles += S.cycles_total;
+        su += S.setup_s; cy += S.cycle_s; im += S.improve_s;
+        if (stt != SHAPLEY_OK && stt != SHAPLEY_ENOCONV) { status = stt; break; }
+        if (last) status = stt;
+      }
+      double t1 = now_s();
+      fill_stats(S, st, t1 - t0);
+      if (st) {
+        st->fmg_levels = L;
+        st->outer = outer; st->inner_total = inner; st->cycles_total = cycles;
+        st->setup_seconds = su; st->cycle_seconds = cy; st->improve_seconds = im;
+      }
+    } else {
+      status = run_amgpi(g->finest(), o, o.eps, true, s, S);
+      fill_stats(S, st, now_s() - t0);
+    }
+    if (status == SHAPLEY_ENOCONV) set_last_error("policy iteration hit an iteration limit");
+    if (status == SHAPLEY_EDEVICE) set_last_error("non-finite values during the solve");
+  });
+  return rc != SHAPLEY_OK ? rc : status;
+}
+
+int shapley_solve_batch(shapley_game_t* games, int32_t count, const shapley_solve_opts* op,
+                        shapley_stats* stats) {
+  int status = SHAPLEY_OK;
+  int rc = guarded([&] {
+    SHP_REQUIRE(games && count >= 1, "bad batch arguments");
+    shapley_solve_opts o;
+    if (op) o = *op; else shapley_default_opts(&o);
+    check_opts(o);
+    SHP_REQUIRE(o.alpha0 == nullptr && o.beta0 == nullptr && o.v0 == nullptr,
+                "warm starts are not accepted in batch mode");
+    std::vector<SlotState> S(count);
+    for (int i = 0; i < count; ++i) {
+      SHP_REQUIRE(games[i] && games[i]->g && !games[i]->g->is_hierarchy(), "batch members must be games");
+    }
+    hipStream_t s = o.stream ? (hipStream_t)o.stream : games[0]->g->stream;
+    double t0 = now_s();
+    Engine eng(s);
+    for (int i = 0; i < count; ++i) {
+      Game* g = games[i]->g;
+      S[i].g = g;
+      S[i].opt = engine_opts_from(o, g->dim);
+      load_warm_start(g, o, S[i], s);
+      eng.slots.push_back(&S[i]);
+    }
+    while (eng.step() > 0) {
+    }
+    double t1 = now_s();
+    for (int i = 0; i < count; ++i) {
+      games[i]->g->solved = true;
+      if (stats) fill_stats(S[i], &stats[i], t1 - t0);
+      if (S[i].status != SHAPLEY_OK && status == SHAPLEY_OK) status = S[i].status;
+    }
+  });
+  return rc != SHAPLEY_OK ? rc : status;
+}
+
+int shapley_get_value(shapley_game_t gh, double* v, int32_t on_device) {
+  return guarded([&] {
+    SHP_REQUIRE(gh && gh->g && v, "null argument");
+    Game* g = gh->g->finest();
+    SHP_HIP(hipMemcpyAsync(v, g->v.p, sizeof(double) * g->n,
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, g->stream));
+    SHP_HIP(hipStreamSynchronize(g->stream));
+  });
+}
+
+int shapley_get_policy(shapley_game_t gh, int32_t* alpha, int32_t* beta, int32_t* beta_all) {
+  return guarded([&] {
+    SHP_REQUIRE(gh && gh->g, "null game");
+    Game* g = gh->g->finest();
+    hipStream_t s = g->stream;
+    if (alpha) d2h(alpha, g->alpha.p, g->n, s);
+    if (beta) d2h(beta, g->beta.p, g->n, s);
+    SHP_HIP(hipStreamSynchronize(s));
+    if (beta_all) {
+      // MIN's lowest-index argmin at every a: run the improvement sweep with
+      // alpha = a fixed and no incumbent, for each a
+      std::vector<int> keep_a(g->n), keep_b(g->n);
+      d2h(keep_a.data(), g->alpha.p, g->n, s);
+      d2h(keep_b.data(), g->beta.p, g->n, s);
+      SHP_HIP(hipStreamSynchronize(s));
+      SlotState S;
+      S.g = g;
+      Engine eng(s);
+      eng.slots.push_back(&S);
+      std::vector<int> col(g->n);
+      for (int a = 0; a < g->m1; ++a) {
+        std::vector<int> av(g->n, a);
+        h2d(g->alpha.p, av.data(), g->n, s);
+        SHP_HIP(hipMemsetAsync(g->beta.p, 0xFF, sizeof(int) * g->n, s));
+        eng.improve_only();
+        d2h(col.data(), g->beta_in.p, g->n, s);
+        SHP_HIP(hipStreamSynchronize(s));
+        for (int x = 0; x < g->n; ++x) beta_all[(int64_t)x * g->m1 + a] = col[x];
+      }
+      h2d(g->alpha.p, keep_a.data(), g->n, s);
+      h2d(g->beta.p, keep_b.data(), g->n, s);
+      SHP_HIP(hipStreamSynchronize(s));
+    }
+  });
+}
+
+int shapley_apply_operator(shapley_game_t gh, const double* v, double* F, int32_t* alpha, int32_t* beta) {
+  return guarded([&] {
+    SHP_REQUIRE(gh && gh->g && v, "null argument");
+    Game* g = gh->g->finest();
+    hipStream_t s = g->stream;
+    const int n = g->n;
+    std::vector<double> keep_v(n);
+    std::vector<int> keep_a(n), keep_b(n);
+    d2h(keep_v.data(), g->v.p, n, s);
+    d2h(keep_a.data(), g->alpha.p, n, s);
+    d2h(keep_b.data(), g->beta.p, n, s);
+    SHP_HIP(hipStreamSynchronize(s));
+    h2d(g->v.p, v, n, s);
+    SHP_HIP(hipMemsetAsync(g->alpha.p, 0xFF, sizeof(int) * n, s));
+    SHP_HIP(hipMemsetAsync(g->beta.p, 0xFF, sizeof(int) * n, s));
+    SlotState S;
+    S.g = g;
+    Engine eng(s);
+    eng.slots.push_back(&S);
+    eng.improve_only();
+    if (F) d2h(F, g->F.p, n, s);
+    if (alpha) d2h(alpha, g->alpha_c.p, n, s);
+    if (beta) d2h(beta, g->beta_c.p, n, s);
+    SHP_HIP(hipStreamSynchronize(s));
+    h2d(g->v.p, keep_v.data(), n, s);
+    h2d(g->alpha.p, keep_a.data(), n, s);
+    h2d(g->beta.p, keep_b.data(), n, s);
+    SHP_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int shapley_game_info(shapley_game_t gh, int64_t* n, int32_t* m1, int32_t* m2) {
+  return guarded([&] {
+    SHP_REQUIRE(gh && gh->g, "null game");
+    Game* g = gh->g->finest();
+    if (n) *n = g->n;
+    if (m1) *m1 = g->m1;
+    if (m2) *m2 = g->m2;
+  });
+}
+
+int shapley_game_bytes(shapley_game_t gh, size_t* bytes) {
+  return guarded([&] {
+    SHP_REQUIRE(gh && gh->g && bytes, "null argument");
+    *bytes = gh->g->device_bytes();
+  });
+}
+
+void shapley_game_destroy(shapley_game_t gh) {
+  if (!gh) return;
+  delete gh->g;
+  delete gh;
+}
+
+}  // extern "C"

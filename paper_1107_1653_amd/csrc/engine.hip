@@ -1,0 +1,706 @@
+// Lock-step policy-iteration engine (AMGpi, Sec. 5.1) over one or many games.
+//
+// Every step performs, for each running game: the value step -- assemble the
+// policy system (LSPI) and solve it by AMG (setup + FP64 iterative
+// refinement around FP32 or FP64 V-cycles, Algorithm MGcycle) -- then one
+// improvement sweep giving MIN's improvement (algo-MDP step 2), MAX's
+// improvement (PIalgo step 2) and the residual ||F(v) - v||_inf, after which
+// each game decides on its own whether it continues the inner loop, moves to
+// the next outer iteration or stops.  Games are merged block-diagonally into
+// every AMG level so that one launch per kernel serves all of them.
+#include "amg_kernels.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+namespace shp {
+
+namespace {
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+template <class T>
+struct LV;
+template <>
+struct LV<float> {
+  static float* a(Level& L) { return L.a32.p; }
+  static float* d(Level& L) { return L.dinv32.p; }
+  static float* pv(Level& L) { return L.pv32.p; }
+  static float* rv(Level& L) { return L.rv32.p; }
+  static float* dm(Level& L) { return L.dmat32.p; }
+  static float* x(Level& L) { return L.x32.p; }
+  static float* y(Level& L) { return L.y32.p; }
+  static float* b(Level& L) { return L.b32.p; }
+  static float* r(Level& L) { return L.r32.p; }
+};
+template <>
+struct LV<double> {
+  static double* a(Level& L) { return L.a64.p; }
+  static double* d(Level& L) { return L.dinv64.p; }
+  static double* pv(Level& L) { return L.pv64.p; }
+  static double* rv(Level& L) { return L.rv64.p; }
+  static double* dm(Level& L) { return L.dmat64.p; }
+  static double* x(Level& L) { return L.x64.p; }
+  static double* y(Level& L) { return L.y64.p; }
+  static double* b(Level& L) { return L.b64.p; }
+  static double* r(Level& L) { return L.r64.p; }
+};
+}  // namespace
+
+std::vector<Tile> make_tiles(const std::vector<int>& off, const std::vector<char>& keep, int rows) {
+  std::vector<Tile> t;
+  int G = (int)off.size() - 1;
+  for (int g = 0; g < G; ++g) {
+    if (!keep[g]) continue;
+    for (int r = off[g]; r < off[g + 1]; r += rows) t.push_back({r, std::min(r + rows, off[g + 1]), g});
+  }
+  return t;
+}
+
+// Optional phase profile (environment SHAPLEY_PROFILE=1): wall time per
+// setup/solve phase with a stream synchronisation at each phase boundary,
+// printed to stderr when the engine is destroyed.
+static bool profiling() {
+  static int on = -1;
+  if (on < 0) {
+    const char* e = getenv("SHAPLEY_PROFILE");
+    on = (e && e[0] == '1') ? 1 : 0;
+  }
+  return on == 1;
+}
+
+struct PhaseTimer {
+  Engine* eng;
+  std::vector<std::pair<std::string, double>>& acc;
+  double t;
+  PhaseTimer(Engine* e, std::vector<std::pair<std::string, double>>& a) : eng(e), acc(a), t(0) {
+    if (profiling()) { SHP_HIP(hipStreamSynchronize(e->stream)); t = now_s(); }
+  }
+  void mark(const char* name) {
+    if (!profiling()) return;
+    SHP_HIP(hipStreamSynchronize(eng->stream));
+    double t1 = now_s();
+    for (auto& p : acc)
+      if (p.first == name) { p.second += t1 - t; t = t1; return; }
+    acc.emplace_back(name, t1 - t);
+    t = t1;
+  }
+};
+
+Engine::Engine(hipStream_t s) : stream(s) {}
+Engine::~Engine() {
+  if (profiling() && !prof.empty()) {
+    fprintf(stderr, "[shapley profile]");
+    for (auto& p : prof) fprintf(stderr, " %s=%.2fms", p.first.c_str(), 1e3 * p.second);
+    fprintf(stderr, "\n");
+  }
+}
+
+std::vector<int> Engine::running_slots() const {
+  std::vector<int> r;
+  for (int g = 0; g < (int)slots.size(); ++g)
+    if (!slots[g]->done) r.push_back(g);
+  return r;
+}
+
+void Engine::build_layout() {
+  G = (int)slots.size();
+  x_off.assign(G + 1, 0);
+  a_off.assign(G + 1, 0);
+  for (int g = 0; g < G; ++g) {
+    Game* gm = slots[g]->g;
+    x_off[g + 1] = x_off[g] + gm->n;
+    int64_t an = (int64_t)a_off[g] + gm->unnz;
+    if (an > INT32_MAX) throw Error(SHAPLEY_EINVAL, "merged level-0 pattern exceeds 2^31 entries");
+    a_off[g + 1] = (int)an;
+  }
+  N0 = x_off[G];
+  NNZ0 = a_off[G];
+  hdesc.resize(G);
+  h_gtiles_all.clear();
+  h_gtiles_imp.clear();
+  for (int g = 0; g < G; ++g) {
+    Game* gm = slots[g]->g;
+    GameDesc d{};
+    d.rp = gm->rp.p; d.ci = gm->ci.p; d.w = gm->w.p; d.r = gm->r.p; d.valid = gm->valid.p;
+    d.urp = gm->urp.p; d.uci = gm->uci.p;
+    d.v = gm->v.p; d.alpha = gm->alpha.p; d.beta = gm->beta.p;
+    d.beta_in = gm->beta_in.p; d.alpha_c = gm->alpha_c.p; d.beta_c = gm->beta_c.p; d.F = gm->F.p;
+    d.bvals = gm->has_bvals ? gm->bvals.p : nullptr;
+    d.n = gm->n; d.m1 = gm->m1; d.m2 = gm->m2; d.slot = g; d.mu = gm->mu;
+    d.x_off = x_off[g]; d.a_off = a_off[g];
+    hdesc[g] = d;
+    for (int x = 0; x < gm->n; x += kBlock) h_gtiles_all.push_back({g, x, std::min(x + kBlock, gm->n)});
+    int K = gm->m1 * gm->m2;
+    int spb = std::max(1, kBlock / K);
+    for (int x = 0; x < gm->n; x += spb) h_gtiles_imp.push_back({g, x, std::min(x + spb, gm->n)});
+  }
+  ddesc.ensure(std::max(G, 1));
+  h2d(ddesc.p, hdesc.data(), G, stream);
+  gtiles_all.ensure(std::max<size_t>(h_gtiles_all.size(), 1));
+  h2d(gtiles_all.p, h_gtiles_all.data(), h_gtiles_all.size(), stream);
+  gtiles_imp.ensure(std::max<size_t>(h_gtiles_imp.size(), 1));
+  h2d(gtiles_imp.p, h_gtiles_imp.data(), h_gtiles_imp.size(), stream);
+
+  int maxlev = 2;
+  for (auto* s : slots) maxlev = std::max(maxlev, s->opt.max_levels + 1);
+  if ((int)lv.size() < maxlev) lv.resize(maxlev);
+  Level& L0 = lv[0];
+  L0.n = N0;
+  L0.nnz = NNZ0;
+  L0.rp.ensure(N0 + 1);
+  L0.ci.ensure(std::max(NNZ0, 1));
+  launch_layout(ddesc.p, gtiles_all.p, (int)h_gtiles_all.size(), L0.rp.p, L0.ci.p, N0, NNZ0, stream);
+  L0.goff = x_off;
+
+  d_active.ensure(std::max(G, 1));
+  d_lin_active.ensure(std::max(G, 1));
+  d_cnt.ensure(2 * std::max(G, 1));
+  d_norm.ensure(4 * std::max(G, 1));
+  d_shap.ensure(2 * std::max(G, 1));
+  d_decision.ensure(std::max(G, 1));
+  h_active.assign(G, 0);
+  h_lin_active.assign(G, 0);
+  layout_dirty = false;
+}
+
+void Engine::build_tiles(Level& L, const std::vector<char>& keep, bool cont_only) {
+  std::vector<Tile> t = make_tiles(L.goff, keep, kTileRows);
+  if (cont_only) {
+    L.nctiles = (int)t.size();
+    L.ctiles.ensure(std::max<size_t>(t.size(), 1));
+    h2d(L.ctiles.p, t.data(), t.size(), stream);
+  } else {
+    L.ntiles = (int)t.size();
+    L.tiles.ensure(std::max<size_t>(t.size(), 1));
+    h2d(L.tiles.p, t.data(), t.size(), stream);
+  }
+  // pageable copies are staged before the call returns; keep the stream ordered
+  SHP_HIP(hipStreamSynchronize(stream));
+}
+
+void Engine::assemble(const std::vector<int>& run, bool mixed) {
+  Level& L0 = lv[0];
+  L0.a64.ensure(std::max(NNZ0, 1));
+  L0.dinv64.ensure(std::max(N0, 1));
+  if (mixed) {
+    L0.a32.ensure(std::max(NNZ0, 1));
+    L0.dinv32.ensure(std::max(N0, 1));
+  }
+  L0.b64.ensure(std::max(N0, 1));   // cycle vectors (FP64 mode) and refinement storage below
+  L0.r64.ensure(std::max(N0, 1));
+  L0.x64.ensure(std::max(N0, 1));
+  L0.y64.ensure(std::max(N0, 1));
+  d_norm.ensure(4 * std::max(G, 1));
+  SHP_HIP(hipMemsetAsync(d_norm.p, 0, sizeof(double) * 4 * G, stream));
+  // refinement storage: solution in sol (L0.tmp is int; use dedicated buffers)
+  launch_gather_v(ddesc.p, gtiles_all.p, (int)h_gtiles_all.size(), d_active.p, sol.p, stream);
+  launch_assemble(ddesc.p, gtiles_all.p, (int)h_gtiles_all.size(), d_active.p, L0.rp.p, L0.a64.p,
+                  mixed ? L0.a32.p : nullptr, rhs.p, L0.dinv64.p, mixed ? L0.dinv32.p : nullptr,
+                  d_bnorm.p, stream);
+  (void)run;
+}
+
+void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
+  const bool mixed = o.precision == SHAPLEY_MIXED;
+  std::vector<char> present(G, 0);
+  for (int g : run) present[g] = 1;
+  double theta = o.theta;
+  if (theta <= 0) {
+    int dim = 0;
+    for (int g : run) dim = std::max(dim, slots[g]->g->dim);
+    theta = dim >= 3 ? 0.5 : 0.25;
+  }
+  s_err.ensure(4);
+  s_left.ensure(1);
+  PhaseTimer pt(this, prof);
+  nlev = 0;
+  int l = 0;
+  lv[0].goff = x_off;
+  lv[0].present = present;
+  while (true) {
+    Level& L = lv[l];
+    const int n = L.n;
+    L.cont.assign(G, 0);
+    bool any_cont = false;
+    for (int g = 0; g < G; ++g) {
+      if (!L.present[g]) continue;
+      int ng = L.goff[g + 1] - L.goff[g];
+      if (ng > o.coarse_max && l + 1 < (int)lv.size() && l + 1 < o.max_levels) {
+        L.cont[g] = 1;
+        any_cont = true;
+      }
+    }
+    if (l > 0) {
+      L.dinv64.ensure(std::max(n, 1));
+      if (mixed) L.dinv32.ensure(std::max(n, 1));
+      amg_diag_inv(n, L.rp.p, L.ci.p, L.a64.p, L.dinv64.p, mixed ? L.dinv32.p : nullptr, stream);
+      if (mixed) {
+        L.a32.ensure(std::max(L.nnz, 1));
+        amg_cast(L.a64.p, L.a32.p, L.nnz, stream);
+      }
+    }
+    build_tiles(L, L.present, false);
+    pt.mark("diag+tiles");
+    if (any_cont) {
+      build_tiles(L, L.cont, true);
+      // ---- strength of connection
+      L.dir.ensure(std::max(n, 1));
+      L.strong.ensure(std::max(L.nnz, 1));
+      L.lam.ensure(n + 1);
+      L.cf.ensure(std::max(n, 1));
+      L.key.ensure(std::max(n, 1));
+      L.cidx.ensure(n + 1);
+      L.tmp.ensure(n + 1);
+      SHP_HIP(hipMemsetAsync(L.lam.p, 0, sizeof(int) * (n + 1), stream));
+      SHP_HIP(hipMemsetAsync(L.cf.p, 0xFE, n, stream));  // CF_X for rows of terminal games
+      SHP_HIP(hipMemsetAsync(L.strong.p, 0, L.nnz, stream));
+      SHP_HIP(hipMemsetAsync(L.dir.p, 1, n, stream));
+      amg_dirichlet(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, L.dir.p, stream);
+      amg_strength(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, L.dir.p, theta, L.strong.p, L.lam.p,
+                   stream);
+      // Dirichlet rows are relaxed exactly (unit weight)
+      amg_dir_scale(L.ctiles.p, L.nctiles, L.dir.p, 1.0 / o.omega, L.dinv64.p, mixed ? L.dinv32.p : nullptr,
+                    stream);
+      // transpose of the strength pattern
+      L.st_rp.ensure(n + 1);
+      scan_exclusive(L.lam.p, L.st_rp.p, n + 1, stream, s_scan);
+      int st_nnz = 0;
+      d2h(&st_nnz, L.st_rp.p + n, 1, stream);
+      SHP_HIP(hipStreamSynchronize(stream));
+      L.st_ci.ensure(std::max(st_nnz, 1));
+      s_cursor.ensure(n + 1);
+      SHP_HIP(hipMemsetAsync(s_cursor.p, 0, sizeof(int) * (n + 1), stream));
+      amg_strength_t(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.strong.p, L.st_rp.p, s_cursor.p, L.st_ci.p,
+                     stream);
+      pt.mark("strength");
+      // ---- PMIS
+      s_goff.ensure(G + 1);
+      h2d(s_goff.p, L.goff.data(), G + 1, stream);
+      uint32_t salt = mix32(0x9E3779B9u * (uint32_t)(l + 1) + 12345u);
+      amg_pmis_init(L.ctiles.p, L.nctiles, s_goff.p, L.dir.p, L.lam.p, salt, L.cf.p, L.key.p, stream);
+      s_newc.ensure(std::max(n, 1));
+      for (int round = 0; round < 1000; ++round) {
+        amg_pmis_select(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.strong.p, L.st_rp.p, L.st_ci.p, L.cf.p,
+                        L.key.p, s_newc.p, stream);
+        SHP_HIP(hipMemsetAsync(s_left.p, 0, sizeof(int), stream));
+        amg_pmis_update(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.strong.p, L.cf.p, s_newc.p, s_left.p,
+                        stream);
+        int left = 0;
+        d2h(&left, s_left.p, 1, stream);
+        SHP_HIP(hipStreamSynchronize(stream));
+        if (left == 0) break;
+        if (round == 999) throw Error(SHAPLEY_EDEVICE, "PMIS did not terminate");
+      }
+      pt.mark("pmis");
+      // ---- coarse numbering and per-game coarse sizes
+      auto number = [&](std::vector<int>& ncg) {
+        amg_is_c(L.cf.p, L.tmp.p, n, stream);
+        SHP_HIP(hipMemsetAsync(L.tmp.p + n, 0, sizeof(int), stream));
+        scan_exclusive(L.tmp.p, L.cidx.p, n + 1, stream, s_scan);
+        s_gidx.ensure(G + 1);
+        s_gout.ensure(G + 1);
+        h2d(s_gidx.p, L.goff.data(), G + 1, stream);
+        amg_gather_int(L.cidx.p, s_gidx.p, G + 1, s_gout.p, stream);
+        std::vector<int> cpre(G + 1);
+        d2h(cpre.data(), s_gout.p, G + 1, stream);
+        SHP_HIP(hipStreamSynchronize(stream));
+        ncg.assign(G, 0);
+        for (int g = 0; g < G; ++g) ncg[g] = cpre[g + 1] - cpre[g];
+        return cpre;
+      };
+      std::vector<int> ncg;
+      std::vector<int> cpre = number(ncg);
+      bool changed = false;
+      for (int g = 0; g < G; ++g) {
+        if (!L.cont[g]) continue;
+        int ng = L.goff[g + 1] - L.goff[g];
+        // coarsening stalled: small blocks end here with a dense solve.
+        // A block without any coarse point (only Dirichlet or weakly coupled
+        // rows, e.g. the identity of "stop everywhere") stays on this level
+        // and is handled by the smoother alone, which solves such rows.
+        if (ncg[g] > 0 && ncg[g] > 0.9 * ng && ng <= kDenseMax) {
+          L.cont[g] = 0;
+          changed = true;
+        }
+      }
+      if (changed) {
+        std::vector<char> term(G, 0);
+        for (int g = 0; g < G; ++g) term[g] = L.present[g] && !L.cont[g];
+        std::vector<Tile> tt = make_tiles(L.goff, term, kTileRows);
+        s_tiles.ensure(std::max<size_t>(tt.size(), 1));
+        h2d(s_tiles.p, tt.data(), tt.size(), stream);
+        amg_fill_cf(s_tiles.p, (int)tt.size(), L.cf.p, (int8_t)-2, stream);
+        SHP_HIP(hipStreamSynchronize(stream));
+        any_cont = false;
+        for (int g = 0; g < G; ++g) any_cont |= (bool)L.cont[g];
+        build_tiles(L, L.cont, true);
+        cpre = number(ncg);
+      }
+      if (any_cont) {
+        const int nc = cpre[G];
+        L.nc = nc;
+        // ---- interpolation
+        L.pc.ensure((size_t)std::max(n, 1) * PW);
+        L.pv64.ensure((size_t)std::max(n, 1) * PW);
+        SHP_HIP(hipMemsetAsync(L.pc.p, 0xFF, sizeof(int) * (size_t)n * PW, stream));
+        SHP_HIP(hipMemsetAsync(s_err.p, 0, sizeof(int) * 4, stream));
+        // s_err[0]: interpolatory sets truncated, [1]: Galerkin hash overflow, [2]: singular block
+        amg_interp(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, L.dinv64.p, L.strong.p, L.cf.p,
+                   L.cidx.p, L.dir.p, L.pc.p, L.pv64.p, s_err.p, stream);
+        pt.mark("interp");
+        // ---- next level rows
+        Level& Ln = lv[l + 1];
+        Ln.n = nc;
+        Ln.goff.assign(G + 1, 0);
+        Ln.present.assign(G, 0);
+        for (int g = 0; g <= G; ++g) Ln.goff[g] = cpre[g];
+        for (int g = 0; g < G; ++g) Ln.present[g] = L.cont[g] && ncg[g] > 0;
+        // ---- R = P^T
+        s_cnt.ensure(nc + 1);
+        SHP_HIP(hipMemsetAsync(s_cnt.p, 0, sizeof(int) * (nc + 1), stream));
+        amg_pt_count(L.ctiles.p, L.nctiles, L.pc.p, s_cnt.p, stream);
+        L.rrp.ensure(nc + 1);
+        scan_exclusive(s_cnt.p, L.rrp.p, nc + 1, stream, s_scan);
+        int rnnz = 0;
+        d2h(&rnnz, L.rrp.p + nc, 1, stream);
+        SHP_HIP(hipStreamSynchronize(stream));
+        L.rci.ensure(std::max(rnnz, 1));
+        L.rv64.ensure(std::max(rnnz, 1));
+        s_cursor.ensure(nc + 1);
+        SHP_HIP(hipMemsetAsync(s_cursor.p, 0, sizeof(int) * (nc + 1), stream));
+        amg_pt_fill(L.ctiles.p, L.nctiles, L.pc.p, L.pv64.p, L.rrp.p, s_cursor.p, L.rci.p, L.rv64.p, stream);
+        amg_sort_rows(L.rrp.p, L.rci.p, L.rv64.p, nc, stream);
+        pt.mark("transpose");
+        // ---- Galerkin product
+        Ln.rp.ensure(nc + 1);
+        s_cnt.ensure(nc + 1);
+        SHP_HIP(hipMemsetAsync(s_cnt.p + nc, 0, sizeof(int), stream));
+        amg_rap(nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, nullptr, s_cnt.p,
+                nullptr, nullptr, s_err.p + 1, stream);
+        scan_exclusive(s_cnt.p, Ln.rp.p, nc + 1, stream, s_scan);
+        int cnnz = 0;
+        d2h(&cnnz, Ln.rp.p + nc, 1, stream);
+        SHP_HIP(hipStreamSynchronize(stream));
+        Ln.nnz = cnnz;
+        Ln.ci.ensure(std::max(cnnz, 1));
+        Ln.a64.ensure(std::max(cnnz, 1));
+        amg_rap(nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, Ln.rp.p, nullptr,
+                Ln.ci.p, Ln.a64.p, s_err.p + 1, stream);
+        if (mixed) {
+          L.pv32.ensure((size_t)std::max(n, 1) * PW);
+          amg_cast(L.pv64.p, L.pv32.p, (size_t)n * PW, stream);
+          L.rv32.ensure(std::max(rnnz, 1));
+          amg_cast(L.rv64.p, L.rv32.p, rnnz, stream);
+        }
+        int herr[4] = {0, 0, 0, 0};
+        d2h(herr, s_err.p, 4, stream);
+        SHP_HIP(hipStreamSynchronize(stream));
+        pt.mark("rap");
+        if (herr[1] != 0)
+          throw Error(SHAPLEY_EDEVICE, "Galerkin product: coarse row too long (code " + std::to_string(herr[1]) + ")");
+      }
+    }
+    // ---- dense inverses of the games that end at this level
+    std::vector<int> hblk;
+    size_t doff = 0;
+    L.max_blk = 0;
+    for (int g = 0; g < G; ++g) {
+      if (!L.present[g] || L.cont[g]) continue;
+      int nb = L.goff[g + 1] - L.goff[g];
+      if (nb == 0) continue;
+      if (nb > kDenseMax) throw Error(SHAPLEY_ENOCONV, "coarsest block exceeds the dense-solve limit");
+      hblk.insert(hblk.end(), {L.goff[g], nb, (int)doff, g});
+      doff += (size_t)nb * nb;
+      L.max_blk = std::max(L.max_blk, nb);
+    }
+    L.nblk = (int)hblk.size() / 4;
+    if (L.nblk) {
+      L.blk.ensure(hblk.size());
+      h2d(L.blk.p, hblk.data(), hblk.size(), stream);
+      L.dmat64.ensure(doff);
+      if (mixed) L.dmat32.ensure(doff);
+      s_dense.ensure(2 * doff);
+      SHP_HIP(hipMemsetAsync(s_err.p, 0, sizeof(int) * 4, stream));
+      amg_dense_inv(L.blk.p, L.nblk, L.rp.p, L.ci.p, L.a64.p, s_dense.p, L.dmat64.p,
+                    mixed ? L.dmat32.p : nullptr, s_err.p + 2, stream);
+      int herr[4] = {0, 0, 0, 0};
+      d2h(herr, s_err.p, 4, stream);
+      SHP_HIP(hipStreamSynchronize(stream));
+      if (herr[2] != 0) throw Error(SHAPLEY_EDEVICE, "singular coarsest block");
+      pt.mark("dense");
+    }
+    // cycle vectors
+    if (mixed) {
+      L.x32.ensure(std::max(n, 1)); L.y32.ensure(std::max(n, 1));
+      L.b32.ensure(std::max(n, 1)); L.r32.ensure(std::max(n, 1));
+    } else {
+      L.x64.ensure(std::max(n, 1)); L.y64.ensure(std::max(n, 1));
+      L.b64.ensure(std::max(n, 1)); L.r64.ensure(std::max(n, 1));
+    }
+    pt.mark("vectors");
+    if (o.verbose >= 2) {
+      int ncont = 0, nterm = 0;
+      for (int g = 0; g < G; ++g) { ncont += L.cont[g]; nterm += L.present[g] && !L.cont[g]; }
+      fprintf(stderr, "[shapley amg] level %d n %d nnz %d nc %d cont %d term %d blocks %d max_blk %d\n", l, n,
+              L.nnz, any_cont ? L.nc : 0, ncont, nterm, L.nblk, L.max_blk);
+    }
+    if (!any_cont) {
+      L.nctiles = 0;
+      nlev = l + 1;
+      break;
+    }
+    ++l;
+  }
+  // statistics
+  double nnz_sum = 0, n_sum = 0;
+  for (int k = 0; k < nlev; ++k) { nnz_sum += lv[k].nnz; n_sum += lv[k].n; }
+  for (int g : run) {
+    slots[g]->levels = nlev;
+    slots[g]->opc = lv[0].nnz ? nnz_sum / lv[0].nnz : 1.0;
+    slots[g]->gc = lv[0].n ? n_sum / lv[0].n : 1.0;
+  }
+}
+
+template <class T>
+static T* vcycle_impl(Engine* e, std::vector<Level>& lv, int l, const EngineOpts& o, const int* act,
+                      hipStream_t s) {
+  Level& L = lv[l];
+  T* cur = LV<T>::x(L);
+  T* nxt = LV<T>::y(L);
+  T* b = LV<T>::b(L);
+  const T om = (T)o.omega;
+  if (L.nctiles) {
+    const T* A = LV<T>::a(L);
+    const T* D = LV<T>::d(L);
+    cyc_smooth<T>(L.ctiles.p, L.nctiles, act, L.rp.p, L.ci.p, A, D, b, nullptr, cur, om, 1, s);
+    for (int k = 1; k < o.nu1; ++k) {
+      cyc_smooth<T>(L.ctiles.p, L.nctiles, act, L.rp.p, L.ci.p, A, D, b, cur, nxt, om, 0, s);
+      std::swap(cur, nxt);
+    }
+    T* r = LV<T>::r(L);
+    cyc_resid<T>(L.ctiles.p, L.nctiles, act, L.rp.p, L.ci.p, A, b, cur, r, s);
+    Level& Ln = lv[l + 1];
+    cyc_restrict<T>(Ln.tiles.p, Ln.ntiles, act, L.rrp.p, L.rci.p, LV<T>::rv(L), r, LV<T>::b(Ln), s);
+    T* xc = vcycle_impl<T>(e, lv, l + 1, o, act, s);
+    cyc_prolong<T>(L.ctiles.p, L.nctiles, act, L.pc.p, LV<T>::pv(L), xc, cur, s);
+    for (int k = 0; k < o.nu2; ++k) {
+      cyc_smooth<T>(L.ctiles.p, L.nctiles, act, L.rp.p, L.ci.p, A, D, b, cur, nxt, om, 0, s);
+      std::swap(cur, nxt);
+    }
+  }
+  if (L.nblk) cyc_dense<T>(L.blk.p, L.nblk, act, LV<T>::dm(L), b, cur, s);
+  return cur;
+}
+
+void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
+  const bool mixed = o.precision == SHAPLEY_MIXED;
+  Level& L0 = lv[0];
+  h_lin_active.assign(G, 0);
+  for (int g : run) h_lin_active[g] = 1;
+  std::vector<int> cyc(G, 0);
+  std::vector<std::vector<double>> hist(G);
+  std::vector<double> hn(4 * G), hb(G);
+  d2h(hb.data(), d_bnorm.p, G, stream);
+  SHP_HIP(hipStreamSynchronize(stream));
+  while (true) {
+    h2d(d_lin_active.p, h_lin_active.data(), G, stream);
+    SHP_HIP(hipMemsetAsync(d_norm.p, 0, sizeof(double) * 4 * G, stream));
+    if (mixed)
+      cyc_resid64<float>(L0.tiles.p, L0.ntiles, d_lin_active.p, L0.rp.p, L0.ci.p, L0.a64.p, rhs.p, sol.p,
+                         L0.b32.p, d_norm.p, stream);
+    else
+      cyc_resid64<double>(L0.tiles.p, L0.ntiles, d_lin_active.p, L0.rp.p, L0.ci.p, L0.a64.p, rhs.p, sol.p,
+                          L0.b64.p, d_norm.p, stream);
+    d2h(hn.data(), d_norm.p, 4 * G, stream);
+    SHP_HIP(hipStreamSynchronize(stream));
+    bool any = false;
+    for (int g : run) {
+      if (!h_lin_active[g]) continue;
+      SlotState* S = slots[g];
+      double rn = hn[4 * g], xn = hn[4 * g + 1];
+      double tol = std::max(o.lin_rtol * std::max(hb[g], xn), o.lin_atol);
+      auto& h = hist[g];
+      h.push_back(rn);
+      bool stop = false;
+      if (!std::isfinite(rn)) {
+        stop = true;
+        S->status = SHAPLEY_EDEVICE;
+      } else if (rn <= tol) {
+        stop = true;
+      } else if (cyc[g] >= o.max_cycles) {
+        stop = true;
+      } else if (h.size() >= 5 && rn > 0.5 * h[h.size() - 4]) {
+        stop = true;  // stagnation: no halving over three cycles
+      }
+      if (stop) h_lin_active[g] = 0; else any = true;
+    }
+    if (!any) break;
+    h2d(d_lin_active.p, h_lin_active.data(), G, stream);
+    if (mixed) {
+      float* e = vcycle_impl<float>(this, lv, 0, o, d_lin_active.p, stream);
+      cyc_update64<float>(L0.tiles.p, L0.ntiles, d_lin_active.p, e, sol.p, stream);
+    } else {
+      double* e = vcycle_impl<double>(this, lv, 0, o, d_lin_active.p, stream);
+      cyc_update64<double>(L0.tiles.p, L0.ntiles, d_lin_active.p, e, sol.p, stream);
+    }
+    for (int g : run)
+      if (h_lin_active[g]) { ++cyc[g]; ++slots[g]->cycles_total; }
+  }
+}
+
+void Engine::improve(const std::vector<int>& run, double tie_rtol) {
+  (void)run;
+  SHP_HIP(hipMemsetAsync(d_shap.p, 0, sizeof(double) * 2 * G, stream));
+  SHP_HIP(hipMemsetAsync(d_cnt.p, 0, sizeof(int) * 2 * G, stream));
+  launch_improve(ddesc.p, gtiles_imp.p, (int)h_gtiles_imp.size(), d_active.p, tie_rtol, d_shap.p, d_cnt.p,
+                 stream);
+}
+
+void Engine::apply_decisions(const std::vector<int>& code) {
+  h2d(d_decision.p, code.data(), G, stream);
+  launch_apply(ddesc.p, gtiles_all.p, (int)h_gtiles_all.size(), d_decision.p, stream);
+  SHP_HIP(hipStreamSynchronize(stream));
+}
+
+void Engine::run_init(const std::vector<int>& run) {
+  std::vector<int> fresh;
+  for (int g : run)
+    if (slots[g]->need_init) fresh.push_back(g);
+  if (fresh.empty()) return;
+  std::vector<int> act(G, 0);
+  for (int g : fresh) act[g] = 1;
+  h2d(d_active.p, act.data(), G, stream);
+  improve(fresh, slots[fresh[0]]->opt.tie_rtol);
+  std::vector<int> code(G, 0);
+  for (int g : fresh) {
+    SlotState* S = slots[g];
+    code[g] = !S->init_alpha ? 2 : (!S->init_beta ? 1 : 0);
+    S->need_init = false;
+  }
+  apply_decisions(code);
+}
+
+void Engine::improve_only() {
+  if (layout_dirty) build_layout();
+  std::vector<int> all;
+  for (int g = 0; g < G; ++g) all.push_back(g);
+  std::vector<int> act(G, 1);
+  h2d(d_active.p, act.data(), G, stream);
+  improve(all, slots.empty() ? 1e-12 : slots[0]->opt.tie_rtol);
+  SHP_HIP(hipStreamSynchronize(stream));
+}
+
+int Engine::step() {
+  if (layout_dirty) build_layout();
+  std::vector<int> run = running_slots();
+  if (run.empty()) return 0;
+  run_init(run);
+  const EngineOpts& o = slots[run[0]]->opt;
+  const bool mixed = o.precision == SHAPLEY_MIXED;
+  sol.ensure(std::max(N0, 1));
+  rhs.ensure(std::max(N0, 1));
+  d_bnorm.ensure(std::max(G, 1));
+  h_active.assign(G, 0);
+  for (int g : run) h_active[g] = 1;
+  h2d(d_active.p, h_active.data(), G, stream);
+  SHP_HIP(hipMemsetAsync(d_bnorm.p, 0, sizeof(double) * G, stream));
+
+  double t0 = now_s();
+  PhaseTimer pt(this, prof);
+  assemble(run, mixed);
+  pt.mark("assemble");
+  setup(run, o);
+  pt.mark("setup");
+  SHP_HIP(hipStreamSynchronize(stream));
+  double t1 = now_s();
+  solve_linear(run, o);
+  pt.mark("solve");
+  launch_scatter_v(ddesc.p, gtiles_all.p, (int)h_gtiles_all.size(), d_active.p, sol.p, stream);
+  SHP_HIP(hipStreamSynchronize(stream));
+  double t2 = now_s();
+  improve(run, o.tie_rtol);
+  std::vector<double> hs(2 * G);
+  std::vector<int> hc(2 * G);
+  d2h(hs.data(), d_shap.p, 2 * G, stream);
+  d2h(hc.data(), d_cnt.p, 2 * G, stream);
+  SHP_HIP(hipStreamSynchronize(stream));
+  double t3 = now_s();
+  pt.mark("improve");
+
+  std::vector<int> code(G, 0);
+  int still = 0;
+  for (int g : run) {
+    SlotState* S = slots[g];
+    S->setup_s += t1 - t0;
+    S->cycle_s += t2 - t1;
+    S->improve_s += t3 - t2;
+    const Game* gm = S->g;
+    S->res = hs[2 * g];
+    S->res_l2 = gm->n ? std::sqrt(hs[2 * g + 1] / gm->n) : 0.0;
+    int nin = hc[2 * g], nout = hc[2 * g + 1];
+    S->nk += 1;
+    S->inner_total += 1;
+    if (S->status != SHAPLEY_OK) {
+      S->done = true;
+      continue;
+    }
+    if (!std::isfinite(S->res)) {
+      S->status = SHAPLEY_EDEVICE;
+      S->done = true;
+      continue;
+    }
+    if (S->opt.verbose)
+      fprintf(stderr, "[shapley] slot %d k %d nk %d res %.3e in %d out %d levels %d cycles %d\n", g, S->k,
+              S->nk, S->res, nin, nout, S->levels, S->cycles_total);
+    if (S->res <= S->opt.eps) {
+      if (S->k <= 64) S->inner_per_outer[S->k - 1] = S->nk;
+      code[g] = 2;
+      S->converged = true;
+      S->done = true;
+    } else if (nin > 0 && S->nk < S->opt.max_inner) {
+      code[g] = 1;
+    } else {
+      if (S->k <= 64) S->inner_per_outer[S->k - 1] = S->nk;
+      if (nout == 0) {
+        S->converged = true;
+        S->done = true;
+      } else if (S->k >= S->opt.max_outer) {
+        S->status = SHAPLEY_ENOCONV;
+        S->done = true;
+      } else {
+        code[g] = 2;
+        S->k += 1;
+        S->nk = 0;
+      }
+    }
+    if (!S->done) ++still;
+  }
+  apply_decisions(code);
+  return still;
+}
+
+EngineOpts engine_opts_from(const shapley_solve_opts& o, int dim) {
+  (void)dim;
+  EngineOpts e;
+  e.eps = o.eps;
+  e.precision = o.precision;
+  e.max_outer = o.max_outer;
+  e.max_inner = o.max_inner;
+  e.max_cycles = o.max_cycles;
+  e.lin_rtol = o.lin_rtol;
+  e.lin_atol = o.lin_atol;
+  e.tie_rtol = o.tie_rtol;
+  e.theta = o.theta;
+  e.nu1 = o.nu1;
+  e.nu2 = o.nu2;
+  e.omega = o.omega;
+  e.coarse_max = o.coarse_max;
+  e.max_levels = o.max_levels;
+  e.verbose = o.verbose;
+  return e;
+}
+
+}  // namespace shp

@@ -1,0 +1,451 @@
+// Game-level kernels: level-0 pattern, policy-system assembly, policy
+// improvement with the Shapley residual, policy updates and FAMGpi transfers.
+// All of them walk a work-list of (game, state range) tiles so that one launch
+// serves every game of a batch.
+#include "internal.hpp"
+
+#include <climits>
+
+namespace shp {
+
+// ---------------------------------------------------------------------------
+// level-0 pattern of a game: per state the union of the columns of its
+// m1*m2 rows plus the diagonal, sorted.  The rows of state x are contiguous,
+// so the union is found by repeated selection of the next larger column.
+// ---------------------------------------------------------------------------
+__global__ void k_union(const int* __restrict__ rp, const int* __restrict__ ci, int n, int K,
+                        const int* __restrict__ urp, int* __restrict__ uci, int* __restrict__ cnt) {
+  int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  int e0 = rp[(int64_t)x * K], e1 = rp[(int64_t)(x + 1) * K];
+  int last = -1, c = 0;
+  int base = uci ? urp[x] : 0;
+  while (true) {
+    int nxt = INT_MAX;
+    if (x > last) nxt = x;
+    for (int e = e0; e < e1; ++e) {
+      int col = ci[e];
+      if (col > last && col < nxt) nxt = col;
+    }
+    if (nxt == INT_MAX) break;
+    if (uci) uci[base + c] = nxt;
+    ++c;
+    last = nxt;
+  }
+  if (!uci) cnt[x] = c;
+}
+
+void launch_union_count(const int* rp, const int* ci, int n, int m1, int m2, int* cnt, int* err,
+                        hipStream_t s) {
+  (void)err;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_union, dim3(grid_for(n)), dim3(kBlock), 0, s, rp, ci, n, m1 * m2,
+                     (const int*)nullptr, (int*)nullptr, cnt);
+  SHP_LAUNCH_CHECK();
+}
+
+void launch_union_fill(const int* rp, const int* ci, int n, int m1, int m2, const int* urp, int* uci,
+                       hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_union, dim3(grid_for(n)), dim3(kBlock), 0, s, rp, ci, n, m1 * m2, urp, uci,
+                     (int*)nullptr);
+  SHP_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// merged level-0 layout: row pointer and columns of the block-diagonal matrix
+// ---------------------------------------------------------------------------
+__global__ void k_layout(const GameDesc* __restrict__ gd, const GTile* __restrict__ tiles,
+                         int* __restrict__ rp0, int* __restrict__ ci0, int N0, int NNZ0) {
+  GTile t = tiles[blockIdx.x];
+  const GameDesc d = gd[t.game];
+  for (int x = t.s0 + threadIdx.x; x < t.s1; x += blockDim.x) {
+    int u0 = d.urp[x], u1 = d.urp[x + 1];
+    rp0[d.x_off + x] = d.a_off + u0;
+    for (int j = u0; j < u1; ++j) ci0[d.a_off + j] = d.x_off + d.uci[j];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) rp0[N0] = NNZ0;
+}
+
+void launch_layout(const GameDesc* d, const GTile* t, int nt, int* rp0, int* ci0, int N0, int NNZ0,
+                   hipStream_t s) {
+  if (nt == 0) return;
+  hipLaunchKernelGGL(k_layout, dim3(nt), dim3(kBlock), 0, s, d, t, rp0, ci0, N0, NNZ0);
+  SHP_LAUNCH_CHECK();
+}
+
+__global__ void k_gather_v(const GameDesc* __restrict__ gd, const GTile* __restrict__ tiles,
+                           const int* __restrict__ active, double* __restrict__ x0) {
+  GTile t = tiles[blockIdx.x];
+  if (active && !active[t.game]) return;
+  const GameDesc d = gd[t.game];
+  for (int x = t.s0 + threadIdx.x; x < t.s1; x += blockDim.x) x0[d.x_off + x] = d.v[x];
+}
+
+__global__ void k_scatter_v(const GameDesc* __restrict__ gd, const GTile* __restrict__ tiles,
+                            const int* __restrict__ active, const double* __restrict__ x0) {
+  GTile t = tiles[blockIdx.x];
+  if (active && !active[t.game]) return;
+  const GameDesc d = gd[t.game];
+  for (int x = t.s0 + threadIdx.x; x < t.s1; x += blockDim.x) d.v[x] = x0[d.x_off + x];
+}
+
+void launch_gather_v(const GameDesc* d, const GTile* t, int nt, const int* active, double* x0,
+                     hipStream_t s) {
+  if (nt == 0) return;
+  hipLaunchKernelGGL(k_gather_v, dim3(nt), dim3(kBlock), 0, s, d, t, active, x0);
+  SHP_LAUNCH_CHECK();
+}
+
+void launch_scatter_v(const GameDesc* d, const GTile* t, int nt, const int* active, const double* x0,
+                      hipStream_t s) {
+  if (nt == 0) return;
+  hipLaunchKernelGGL(k_scatter_v, dim3(nt), dim3(kBlock), 0, s, d, t, active, x0);
+  SHP_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// K1: policy-system assembly.  Row x of A = I - mu M^{alpha beta} and
+// b = r^{alpha beta} (Sec. 4.2, eq. (LSPI)), written into the fixed level-0
+// pattern of the game (explicit zeros where the chosen row has no entry).
+// ---------------------------------------------------------------------------
+__device__ inline double warp_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ inline double warp_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ inline int warp_sum_i(int v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_assemble(const GameDesc* __restrict__ gd,
+                                                  const GTile* __restrict__ tiles,
+                                                  const int* __restrict__ active,
+                                                  double* __restrict__ a64, float* __restrict__ a32,
+                                                  double* __restrict__ b0, double* __restrict__ dinv64,
+                                                  float* __restrict__ dinv32, double* __restrict__ bnorm) {
+  GTile t = tiles[blockIdx.x];
+  if (!active[t.game]) return;
+  const GameDesc d = gd[t.game];
+  double bmax = 0.0;
+  int x = t.s0 + threadIdx.x;
+  if (x < t.s1) {
+    int s = (x * d.m1 + d.alpha[x]) * d.m2 + d.beta[x];
+    int e = d.rp[s], e1 = d.rp[s + 1];
+    double diag = 0.0;
+    for (int j = d.urp[x], j1 = d.urp[x + 1]; j < j1; ++j) {
+      int c = d.uci[j];
+      double val = (c == x) ? 1.0 : 0.0;
+      while (e < e1 && d.ci[e] < c) ++e;
+      while (e < e1 && d.ci[e] == c) { val -= d.mu * d.w[e]; ++e; }
+      a64[d.a_off + j] = val;
+      if (a32) a32[d.a_off + j] = (float)val;
+      if (c == x) diag = val;
+    }
+    int X = d.x_off + x;
+    double rb = d.r[s];
+    b0[X] = rb;
+    double di = diag != 0.0 ? 1.0 / diag : 0.0;
+    dinv64[X] = di;
+    if (dinv32) dinv32[X] = (float)di;
+    bmax = fabs(rb);
+  }
+  bmax = warp_max(bmax);
+  if ((threadIdx.x & 63) == 0) atomic_max_nonneg(&bnorm[t.game], bmax);
+}
+
+void launch_assemble(const GameDesc* d, const GTile* t, int nt, const int* active, const int* rp0,
+                     double* a64, float* a32, double* b0, double* dinv64, float* dinv32,
+                     double* bnorm, hipStream_t s) {
+  (void)rp0;
+  if (nt == 0) return;
+  hipLaunchKernelGGL(k_assemble, dim3(nt), dim3(kBlock), 0, s, d, t, active, a64, a32, b0, dinv64,
+                     dinv32, bnorm);
+  SHP_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// K14 + K15: policy improvement and Shapley residual in one sweep.
+//   Q(x,a,b) = r(x,a,b) + mu sum_y w(y|x,a,b) v(y)   (the bracket of eq. (eq1))
+//   beta_in(x)  : MIN's improvement at alpha(x)       (Algorithm algo-MDP, step 2)
+//   F(x)        : max_a min_b Q                        (eq. (eq1))
+//   alpha_c(x)  : MAX's improvement                    (Algorithm PIalgo, step 2)
+//   beta_c(x)   : MIN's answer at alpha_c(x)
+// Ties: the incumbent is kept unless another action is better by more than
+// tie_rtol times the rounding scale |r| + mu sum |w v| of the compared rows;
+// otherwise the lowest index attaining the extremum is taken.
+// One thread per row computes Q into LDS; one thread per state reduces.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd,
+                                                 const GTile* __restrict__ tiles,
+                                                 const int* __restrict__ active, double tie_rtol,
+                                                 double* __restrict__ shap, int* __restrict__ cnt) {
+  __shared__ double sq[256];
+  __shared__ double ss[256];
+  __shared__ unsigned char sv[256];
+  GTile t = tiles[blockIdx.x];
+  if (active && !active[t.game]) return;
+  const GameDesc d = gd[t.game];
+  const int K = d.m1 * d.m2;
+  const int ns = t.s1 - t.s0;
+  const int tid = threadIdx.x;
+  if (tid < ns * K) {
+    int x = t.s0 + tid / K;
+    int row = x * K + tid % K;
+    bool ok = d.valid ? (d.valid[row] != 0) : true;
+    double acc = 0.0, sacc = 0.0;
+    for (int e = d.rp[row], e1 = d.rp[row + 1]; e < e1; ++e) {
+      double p = d.w[e] * d.v[d.ci[e]];
+      acc += p;
+      sacc += fabs(p);
+    }
+    double rr = d.r[row];
+    sq[tid] = rr + d.mu * acc;
+    ss[tid] = fabs(rr) + d.mu * sacc;
+    sv[tid] = ok ? 1 : 0;
+  }
+  __syncthreads();
+  double res = 0.0, res2 = 0.0;
+  int chg_in = 0, chg_out = 0;
+  if (tid < ns) {
+    const int x = t.s0 + tid;
+    const int base = tid * K;
+    const int al = d.alpha[x];
+    const int be = d.beta[x];
+    // MIN at the incumbent alpha
+    int bin = -1;
+    if (al >= 0) {
+      double mn = INFINITY, sc = 0.0;
+      int low = -1;
+      for (int b = 0; b < d.m2; ++b) {
+        int q = base + al * d.m2 + b;
+        if (!sv[q]) continue;
+        if (sq[q] < mn) { mn = sq[q]; low = b; }
+        sc = fmax(sc, ss[q]);
+      }
+      bin = low;
+      if (be >= 0 && be < d.m2 && sv[base + al * d.m2 + be] &&
+          sq[base + al * d.m2 + be] <= mn + tie_rtol * sc)
+        bin = be;
+    }
+    // MAX over a of min over b
+    double F = -INFINITY, scall = 0.0;
+    int lowa = -1;
+    double inner_al = -INFINITY;
+    for (int a = 0; a < d.m1; ++a) {
+      double mn = INFINITY;
+      for (int b = 0; b < d.m2; ++b) {
+        int q = base + a * d.m2 + b;
+        if (!sv[q]) continue;
+        mn = fmin(mn, sq[q]);
+        scall = fmax(scall, ss[q]);
+      }
+      if (mn == INFINITY) continue;  // no valid b: action a not available
+      if (a == al) inner_al = mn;
+      if (mn > F) { F = mn; lowa = a; }
+    }
+    int ac = lowa;
+    if (al >= 0 && inner_al >= F - tie_rtol * scall) ac = al;
+    // MIN's answer at the new alpha (keep the incumbent if alpha is unchanged)
+    int bc = -1;
+    {
+      double mn = INFINITY, sc = 0.0;
+      int low = -1;
+      for (int b = 0; b < d.m2; ++b) {
+        int q = base + ac * d.m2 + b;
+        if (!sv[q]) continue;
+        if (sq[q] < mn) { mn = sq[q]; low = b; }
+        sc = fmax(sc, ss[q]);
+      }
+      bc = low;
+      if (ac == al && be >= 0 && be < d.m2 && sv[base + ac * d.m2 + be] &&
+          sq[base + ac * d.m2 + be] <= mn + tie_rtol * sc)
+        bc = be;
+    }
+    d.beta_in[x] = bin;
+    d.alpha_c[x] = ac;
+    d.beta_c[x] = bc;
+    d.F[x] = F;
+    double dv = F - d.v[x];
+    res = fabs(dv);
+    res2 = dv * dv;
+    chg_in = (bin != be) ? 1 : 0;
+    chg_out = (ac != al) ? 1 : 0;
+  }
+  // block reduction: one atomic per wavefront
+  res = warp_max(res);
+  res2 = warp_sum(res2);
+  chg_in = warp_sum_i(chg_in);
+  chg_out = warp_sum_i(chg_out);
+  if ((tid & 63) == 0 && tid < ns + 63) {
+    atomic_max_nonneg(&shap[2 * t.game], res);
+    atomicAdd(&shap[2 * t.game + 1], res2);
+    if (chg_in) atomicAdd(&cnt[2 * t.game], chg_in);
+    if (chg_out) atomicAdd(&cnt[2 * t.game + 1], chg_out);
+  }
+}
+
+void launch_improve(const GameDesc* d, const GTile* t, int nt, const int* active, double tie_rtol,
+                    double* shap, int* cnt, hipStream_t s) {
+  if (nt == 0) return;
+  hipLaunchKernelGGL(k_improve, dim3(nt), dim3(kBlock), 0, s, d, t, active, tie_rtol, shap, cnt);
+  SHP_LAUNCH_CHECK();
+}
+
+// decision codes: 1 = take beta_in (inner step), 2 = take (alpha_c, beta_c) (outer step)
+__global__ void k_apply(const GameDesc* __restrict__ gd, const GTile* __restrict__ tiles,
+                        const int* __restrict__ decision) {
+  GTile t = tiles[blockIdx.x];
+  int code = decision[t.game];
+  if (code == 0) return;
+  const GameDesc d = gd[t.game];
+  for (int x = t.s0 + threadIdx.x; x < t.s1; x += blockDim.x) {
+    if (code == 1) {
+      d.beta[x] = d.beta_in[x];
+    } else {
+      d.alpha[x] = d.alpha_c[x];
+      d.beta[x] = d.beta_c[x];
+    }
+  }
+}
+
+void launch_apply(const GameDesc* d, const GTile* t, int nt, const int* decision, hipStream_t s) {
+  if (nt == 0) return;
+  hipLaunchKernelGGL(k_apply, dim3(nt), dim3(kBlock), 0, s, d, t, decision);
+  SHP_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// K16: FAMGpi transfers (Sec. 5.2).  Value interpolation I: multilinear on the
+// coarse grid extended by its Dirichlet nodes (on nested dyadic grids this is
+// the paper's average of the coarse neighbours within distance h_l).
+// Strategy interpolation U: copy the coarse node at floor(i (s_c+1)/(s_f+1))
+// clamped to [1, s_c] on every axis.
+// ---------------------------------------------------------------------------
+__global__ void k_fmg(int dim, int sc, int sf, const double* __restrict__ vc,
+                      const int* __restrict__ ac, const int* __restrict__ bc,
+                      const double* __restrict__ bvals, double* __restrict__ vf,
+                      int* __restrict__ af, int* __restrict__ bf, int nf) {
+  int xf = blockIdx.x * blockDim.x + threadIdx.x;
+  if (xf >= nf) return;
+  int kk[3] = {0, 0, 0};
+  double tt[3] = {0.0, 0.0, 0.0};
+  int rem = xf;
+  const int64_t den = sf + 1;
+  for (int ax = 0; ax < dim; ++ax) {
+    int i = rem % sf + 1;
+    rem /= sf;
+    int64_t num = (int64_t)i * (sc + 1);
+    int64_t k = num / den;
+    kk[ax] = (int)k;
+    tt[ax] = (double)(num - k * den) / (double)den;
+  }
+  const int se = sc + 2;
+  double acc = 0.0;
+  for (int corner = 0; corner < (1 << dim); ++corner) {
+    double wgt = 1.0;
+    int ext = 0, lin = 0, stride_e = 1, stride_i = 1;
+    bool inner = true;
+    for (int ax = 0; ax < dim; ++ax) {
+      int hi = (corner >> ax) & 1;
+      int c = kk[ax] + hi;
+      if (c > sc + 1) c = sc + 1;
+      wgt *= hi ? tt[ax] : (1.0 - tt[ax]);
+      ext += c * stride_e;
+      stride_e *= se;
+      if (c < 1 || c > sc) inner = false;
+      lin += (c - 1) * stride_i;
+      stride_i *= sc;
+    }
+    if (wgt == 0.0) continue;
+    double val = inner ? vc[lin] : (bvals ? bvals[ext] : 0.0);
+    acc += wgt * val;
+  }
+  vf[xf] = acc;
+  int lin = 0, stride = 1;
+  for (int ax = 0; ax < dim; ++ax) {
+    int c = kk[ax];
+    if (c < 1) c = 1;
+    if (c > sc) c = sc;
+    lin += (c - 1) * stride;
+    stride *= sc;
+  }
+  af[xf] = ac[lin];
+  bf[xf] = bc[lin];
+}
+
+void launch_fmg(const Game* c, const Game* f, hipStream_t s) {
+  if (f->n == 0) return;
+  hipLaunchKernelGGL(k_fmg, dim3(grid_for(f->n)), dim3(kBlock), 0, s, c->dim, c->s, f->s, c->v.p,
+                     c->alpha.p, c->beta.p, c->has_bvals ? c->bvals.p : (const double*)nullptr,
+                     f->v.p, f->alpha.p, f->beta.p, f->n);
+  SHP_LAUNCH_CHECK();
+}
+
+void fmg_transfer(Game* coarse, Game* fine, hipStream_t s) { launch_fmg(coarse, fine, s); }
+
+// ---------------------------------------------------------------------------
+// exclusive scan of int32 (block scan + recursive scan of block sums)
+// ---------------------------------------------------------------------------
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__global__ __launch_bounds__(256) void k_scan_block(const int* __restrict__ in, int* __restrict__ out,
+                                                    int* __restrict__ sums, int n) {
+  __shared__ int sh[kBlock];
+  int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int tot = 0;
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : 0;
+    tot += v[i];
+  }
+  sh[threadIdx.x] = tot;
+  __syncthreads();
+  for (int o = 1; o < kBlock; o <<= 1) {
+    int add = (threadIdx.x >= o) ? sh[threadIdx.x - o] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int run = sh[threadIdx.x] - tot;  // exclusive prefix of this thread
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) out[base + i] = run;
+    run += v[i];
+  }
+  if (threadIdx.x == kBlock - 1) sums[blockIdx.x] = sh[kBlock - 1];
+}
+
+__global__ void k_scan_add(int* __restrict__ out, const int* __restrict__ sums, int n) {
+  int i = blockIdx.x * kScanTile + threadIdx.x;
+  int add = sums[blockIdx.x];
+  for (int j = 0; j < kScanItems; ++j, i += kBlock)
+    if (i < n) out[i] += add;
+}
+
+static void scan_rec(const int* in, int* out, int n, hipStream_t s, int* scratch, size_t cap) {
+  int nb = (n + kScanTile - 1) / kScanTile;
+  if ((size_t)nb > cap) throw Error(SHAPLEY_EDEVICE, "scan scratch too small");
+  hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(kBlock), 0, s, in, out, scratch, n);
+  SHP_LAUNCH_CHECK();
+  if (nb > 1) {
+    scan_rec(scratch, scratch, nb, s, scratch + nb, cap - nb);
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kBlock), 0, s, out, scratch, n);
+    SHP_LAUNCH_CHECK();
+  }
+}
+
+void scan_exclusive(const int* in, int* out, int n, hipStream_t s, DBuf<int>& scratch) {
+  if (n <= 0) return;
+  size_t need = 0;
+  for (int m = n; m > 1; m = (m + kScanTile - 1) / kScanTile) need += (m + kScanTile - 1) / kScanTile;
+  need += 4;
+  scratch.ensure(need);
+  scan_rec(in, out, n, s, scratch.p, scratch.n);
+}
+
+}  // namespace shp

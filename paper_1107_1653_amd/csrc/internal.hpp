@@ -1,0 +1,218 @@
+// Internal data structures of libshapley: games, merged AMG levels, engine.
+#pragma once
+
+#include "../../include/shapley.h"
+#include "common.hpp"
+
+#include <memory>
+
+namespace shp {
+
+constexpr int PW = 4;            // max interpolation entries per fine row (ELL width)
+constexpr int kTileRows = 256;   // rows per level tile
+constexpr int kMaxUnion = 128;   // max entries of one state's level-0 pattern row
+constexpr int kMaxChat = 64;     // max interpolatory set size (extended+i)
+constexpr int kDenseMax = 1024;  // largest dense coarse block
+
+// POD view of one game for work-list kernels.
+struct GameDesc {
+  const int* rp;          // game CSR row pointer [nrows+1]
+  const int* ci;          // columns
+  const double* w;        // weights
+  const double* r;        // rewards [nrows]
+  const uint8_t* valid;   // [nrows] or null
+  const int* urp;         // level-0 pattern of the game: row pointer [n+1] (local)
+  const int* uci;         // level-0 pattern columns (local, sorted, incl. diagonal)
+  double* v;              // value [n]
+  int* alpha;             // MAX policy [n]
+  int* beta;              // MIN policy at alpha [n]
+  int* beta_in;           // improvement outputs [n]
+  int* alpha_c;
+  int* beta_c;
+  double* F;              // F(v) [n]
+  const double* bvals;    // Dirichlet values on the extended grid or null
+  int n, m1, m2, slot;
+  double mu;
+  int x_off;              // first row of this game in the merged level 0
+  int a_off;              // first nnz of this game in the merged level 0
+};
+
+// State range of one game for work-list kernels.
+struct GTile {
+  int game, s0, s1;
+};
+
+// Device-resident game (the payload of a shapley_game_t).
+struct Game {
+  int n = 0, m1 = 0, m2 = 0, nrows = 0;
+  int64_t nnz = 0;
+  double mu = 1.0;
+  DBuf<int> rp, ci;
+  DBuf<double> w, r;
+  DBuf<uint8_t> valid;
+  DBuf<int> urp, uci;
+  int unnz = 0;
+  DBuf<double> v, F;
+  DBuf<int> alpha, beta, beta_in, alpha_c, beta_c;
+  int dim = 0, s = 0;
+  DBuf<double> bvals;
+  bool has_bvals = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool solved = false;
+  // hierarchy handles own their levels (coarse -> fine)
+  std::vector<Game*> levels;
+  bool is_hierarchy() const { return !levels.empty(); }
+  Game* finest() { return levels.empty() ? this : levels.back(); }
+  size_t device_bytes() const;
+  ~Game();
+};
+
+// One merged (block-diagonal over games) AMG level.
+struct Level {
+  int n = 0, nnz = 0;
+  DBuf<int> rp, ci;
+  DBuf<double> a64, dinv64;
+  DBuf<float> a32, dinv32;
+  std::vector<int> goff;          // per slot offsets, size G+1
+  std::vector<char> present;      // slot has rows here
+  std::vector<char> cont;         // slot continues to the next level
+  DBuf<Tile> tiles;               // tiles of all present slots
+  int ntiles = 0;
+  DBuf<Tile> ctiles;              // tiles of continuing slots
+  int nctiles = 0;
+  // transfer to the next level (continuing slots)
+  int nc = 0;
+  DBuf<int> pc;                   // [n*PW], -1 = empty
+  DBuf<double> pv64;
+  DBuf<float> pv32;
+  DBuf<int> rrp, rci;             // R = P^T, CSR over the next level's rows
+  DBuf<double> rv64;
+  DBuf<float> rv32;
+  // dense inverses of terminal slots: blocks (row0, size, offset into dmat)
+  int nblk = 0, max_blk = 0;
+  DBuf<int> blk;                  // [3*nblk]
+  DBuf<double> dmat64;
+  DBuf<float> dmat32;
+  // cycle vectors
+  DBuf<double> x64, y64, b64, r64;
+  DBuf<float> x32, y32, b32, r32;
+  // setup scratch
+  DBuf<uint8_t> strong;           // [nnz]
+  DBuf<int> st_rp, st_ci;         // transpose of the strength pattern
+  DBuf<int8_t> cf;                // C/F/U state
+  DBuf<uint8_t> dir;              // Dirichlet (no off-diagonal) rows
+  DBuf<int> lam, cidx, tmp;
+  DBuf<uint64_t> key;
+};
+
+struct EngineOpts {
+  double eps = 0.0;
+  int precision = SHAPLEY_FP64;
+  int max_outer = 100000, max_inner = 100000, max_cycles = 200;
+  double lin_rtol = 1e-14, lin_atol = 0.0, tie_rtol = 1e-12;
+  double theta = -1.0;
+  int nu1 = 2, nu2 = 2;
+  double omega = 0.8;
+  int coarse_max = 100, max_levels = 25;
+  int verbose = 0;
+};
+
+EngineOpts engine_opts_from(const shapley_solve_opts& o, int dim);
+
+// Per-game policy-iteration progress inside the engine.
+struct SlotState {
+  Game* g = nullptr;
+  EngineOpts opt;
+  bool need_init = true;
+  bool init_alpha = false, init_beta = false;  // warm-start policies were given
+  bool done = false;
+  int k = 1, nk = 0;
+  int inner_total = 0, cycles_total = 0;
+  int status = SHAPLEY_OK;
+  bool converged = false;
+  double res = 0.0, res_l2 = 0.0;
+  double setup_s = 0, cycle_s = 0, improve_s = 0;
+  int levels = 0;
+  double opc = 0, gc = 0;
+  int inner_per_outer[64] = {0};
+  double bnorm = 0.0;
+};
+
+// Lock-step policy-iteration engine over a set of games (one slot per game).
+class Engine {
+ public:
+  explicit Engine(hipStream_t s);
+  ~Engine();
+  hipStream_t stream;
+  std::vector<SlotState*> slots;   // not owned
+  // Runs one PI step (solve + improve + decide) for every slot not done.
+  // Returns the number of slots still running.
+  int step();
+  void invalidate_layout() { layout_dirty = true; }
+  // Evaluates the improvement sweep at the slots' current v (no decisions).
+  void improve_only();
+
+ private:
+  bool layout_dirty = true;
+  int G = 0, N0 = 0, NNZ0 = 0;
+  std::vector<int> x_off, a_off;
+  std::vector<GameDesc> hdesc;
+  DBuf<GameDesc> ddesc;
+  DBuf<GTile> gtiles_all, gtiles_imp;  // state tiles (assembly / improvement)
+  std::vector<GTile> h_gtiles_all, h_gtiles_imp;
+  std::vector<Level> lv;
+  int nlev = 0;
+  // per-slot device scalars
+  DBuf<int> d_active, d_lin_active, d_cnt;    // cnt: [2*G] inner/outer change counts
+  DBuf<double> d_norm;                        // [4*G] res max, x max, b max, spare
+  DBuf<double> d_shap;                        // [2*G] shapley residual max, sum sq
+  DBuf<int> d_decision;
+  std::vector<int> h_active, h_lin_active;
+  // refinement storage on the merged level 0
+  DBuf<double> sol, rhs, d_bnorm;
+  // setup scratch
+  DBuf<int> s_cnt, s_cursor, s_scan, s_err, s_left, s_newc, s_gidx, s_gout, s_goff;
+  DBuf<Tile> s_tiles;
+  DBuf<double> s_dense;
+ public:
+  std::vector<std::pair<std::string, double>> prof;  // phase profile (SHAPLEY_PROFILE=1)
+ private:
+
+  void build_layout();
+  std::vector<int> running_slots() const;
+  void run_init(const std::vector<int>& run);
+  void assemble(const std::vector<int>& run, bool mixed);
+  void setup(const std::vector<int>& run, const EngineOpts& o);
+  void solve_linear(const std::vector<int>& run, const EngineOpts& o);
+  void improve(const std::vector<int>& run, double tie_rtol);
+  void apply_decisions(const std::vector<int>& code);
+  void build_tiles(Level& L, const std::vector<char>& keep, bool cont_only);
+};
+
+// FAMGpi transfers between two grid levels of the same game family.
+void fmg_transfer(Game* coarse, Game* fine, hipStream_t s);
+
+// kernels launched by the engine (defined in the .hip files)
+void launch_layout(const GameDesc* d, const GTile* t, int nt, int* rp0, int* ci0, int N0, int NNZ0,
+                   hipStream_t s);
+void launch_gather_v(const GameDesc* d, const GTile* t, int nt, const int* active, double* x0,
+                     hipStream_t s);
+void launch_scatter_v(const GameDesc* d, const GTile* t, int nt, const int* active, const double* x0,
+                      hipStream_t s);
+void launch_assemble(const GameDesc* d, const GTile* t, int nt, const int* active, const int* rp0,
+                     double* a64, float* a32, double* b0, double* dinv64, float* dinv32,
+                     double* bnorm, hipStream_t s);
+void launch_improve(const GameDesc* d, const GTile* t, int nt, const int* active, double tie_rtol,
+                    double* shap, int* cnt, hipStream_t s);
+void launch_apply(const GameDesc* d, const GTile* t, int nt, const int* decision, hipStream_t s);
+void launch_union_count(const int* rp, const int* ci, int n, int m1, int m2, int* cnt, int* err,
+                        hipStream_t s);
+void launch_union_fill(const int* rp, const int* ci, int n, int m1, int m2, const int* urp, int* uci,
+                       hipStream_t s);
+void launch_fmg(const Game* c, const Game* f, hipStream_t s);
+
+// device scan (exclusive) of n ints into out (out may alias in); returns total via *total_dev
+void scan_exclusive(const int* in, int* out, int n, hipStream_t s, DBuf<int>& scratch);
+
+}  // namespace shp

@@ -1,0 +1,142 @@
+"""End-to-end parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bar: final policies identical except at states whose top two action values
+differ by less than 1e-10 at the oracle's value; values within 1e-9
+(relative, sup-norm) in FP64 mode and 1e-6 in mixed mode.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1107_1653_amd as P
+from shapley_inputs import configs, games
+from tests.gpu_helpers import compare_with_oracle, log, solve_gpu
+
+pytestmark = pytest.mark.gpu
+
+LIMITS = dict(max_outer=500, max_inner=500)
+
+
+@pytest.mark.parametrize("s", [9, 17, 33])
+@pytest.mark.parametrize("prec,tol", [(P.SHAPLEY_FP64, 1e-9), (P.SHAPLEY_MIXED, 1e-6)])
+def test_isaacs2d_c0_family(s, prec, tol):
+    g = configs.c0(s=s)
+    log(f"isaacs2d s={s} prec={prec}")
+    ref = oracle.policy_iteration(g)
+    v, a, b, st = solve_gpu(g, precision=prec, **LIMITS)
+    err, ma, mb, tied = compare_with_oracle(g, v, a, b, ref, tol)
+    log(f"  err {err:.2e} outer {st['outer']} inner {st['inner_total']} cycles {st['cycles_total']} "
+        f"levels {st['levels']} tied {tied.sum()} (oracle {ref.outer}/{ref.inner_total})")
+    assert st["converged"] == 1
+    assert err <= tol
+    assert len(ma) == 0 and len(mb) == 0
+
+
+@pytest.mark.parametrize("seed,n,m1,m2,inv", [(0, 40, 2, 3, 0.0), (1, 60, 3, 2, 0.2), (2, 25, 1, 4, 0.0)])
+def test_random_games_dense_path(seed, n, m1, m2, inv):
+    """General (non-grid) games; n <= coarse_max exercises the dense solve."""
+    g = games.random_game(n, m1, m2, seed, mu=0.9, density=0.2, invalid_frac=inv)
+    log(f"random seed={seed} n={n}")
+    ref = oracle.policy_iteration(g)
+    v, a, b, st = solve_gpu(g, **LIMITS)
+    err, ma, mb, _ = compare_with_oracle(g, v, a, b, ref, 1e-9)
+    log(f"  err {err:.2e} outer {st['outer']} inner {st['inner_total']}")
+    assert err <= 1e-9 and len(ma) == 0 and len(mb) == 0
+
+
+@pytest.mark.parametrize("pts", [33, 65, 129])
+def test_obstacle_amgpi_from_stop_everywhere(pts):
+    g = configs.c1(points=pts)
+    log(f"obstacle pts={pts}")
+    a0 = np.zeros(g.n, np.int32)
+    ref = oracle.policy_iteration(g, alpha0=a0, beta0=a0)
+    v, a, b, st = solve_gpu(g, alpha0=a0, beta0=a0, **LIMITS)
+    err, ma, mb, tied = compare_with_oracle(g, v, a, b, ref, 1e-9)
+    log(f"  err {err:.2e} outer {st['outer']} (oracle {ref.outer}) levels {st['levels']}")
+    assert st["converged"] == 1 and err <= 1e-9 and len(ma) == 0
+
+
+def test_isaacs3d_small():
+    g = configs.c2(s=17)
+    log("isaacs3d s=17")
+    ref = oracle.policy_iteration(g)
+    for prec, tol in ((P.SHAPLEY_FP64, 1e-9), (P.SHAPLEY_MIXED, 1e-6)):
+        v, a, b, st = solve_gpu(g, precision=prec, **LIMITS)
+        err, ma, mb, tied = compare_with_oracle(g, v, a, b, ref, tol)
+        log(f"  prec {prec} err {err:.2e} levels {st['levels']} cycles {st['cycles_total']}")
+        assert err <= tol and len(ma) == 0 and len(mb) == 0
+
+
+def test_two_stopper_paper_example_on_gpu():
+    """Sec. 6.3 worked example: ||e||_inf = 1.16e-7 at 2049 points."""
+    g = games.two_stopper_game(2049)
+    x = np.arange(1, 2048) / 2048
+    u = games.two_stopper_exact(x)
+    v, a, b, st = solve_gpu(g, max_outer=2000, max_inner=2000)
+    e = np.max(np.abs(v - u))
+    log(f"two-stopper err_inf {e:.3e} outer {st['outer']}")
+    assert float(f"{e:.2e}") == pytest.approx(1.16e-7)
+
+
+def test_batch_matches_alone_and_oracle():
+    """Batched lock-step solve (one launch per level for all games) gives each
+    game the result it gets alone; both match the oracle."""
+    gs = [configs.c3_game(k, side, lam) for k, (side, lam) in
+          enumerate([(17, 0.3), (33, 5.0), (9, 1.0), (25, 0.1), (33, 9.0), (17, 2.0)])]
+    gs.append(configs.c1(points=33))
+    hs = [P.create_from(g) for g in gs]
+    try:
+        st = P.shapley_solve_batch(hs, P.shapley_default_opts(**LIMITS))
+        vb = [P.shapley_get_value(h) for h in hs]
+        pb = [P.shapley_get_policy(h) for h in hs]
+    finally:
+        for h in hs:
+            P.shapley_game_destroy(h)
+    for k, g in enumerate(gs):
+        ref = oracle.policy_iteration(g)
+        v, a, b, _ = solve_gpu(g, **LIMITS)
+        err_alone = np.max(np.abs(vb[k] - v)) / np.max(np.abs(v))
+        err, ma, mb, _ = compare_with_oracle(g, vb[k], pb[k][0], pb[k][1], ref, 1e-9)
+        log(f"  game {k} n={g.n} batch-vs-alone {err_alone:.2e} vs-oracle {err:.2e} outer {st[k]['outer']}")
+        assert err <= 1e-9 and len(ma) == 0 and len(mb) == 0
+        assert err_alone <= 1e-12
+        np.testing.assert_array_equal(pb[k][0], a)
+
+
+def test_famg_hierarchy_matches_finest_oracle():
+    """FAMGpi (Algorithm algo-FAMGPI) reaches the unique fixed point of the
+    finest game (Sec. 5.2)."""
+    levels = configs.c1_levels(points=129, coarsest_points=17)
+    ref = oracle.policy_iteration(levels[-1])
+    hs = [P.create_from(g) for g in levels]
+    H = P.shapley_game_create_hierarchy(hs)
+    try:
+        a0 = np.zeros(levels[0].n, np.int32)
+        for prec, tol in ((P.SHAPLEY_FP64, 1e-9), (P.SHAPLEY_MIXED, 1e-6)):
+            o = P.shapley_default_opts(method=P.SHAPLEY_FAMGPI, precision=prec, alpha0=a0, beta0=a0, **LIMITS)
+            st = P.shapley_solve(H, o)
+            v = P.shapley_get_value(H)
+            a, b = P.shapley_get_policy(H)
+            err, ma, mb, _ = compare_with_oracle(levels[-1], v, a, b, ref, tol)
+            log(f"  famg prec {prec} err {err:.2e} outer {st['outer']} fmg_levels {st['fmg_levels']}")
+            assert err <= tol and len(ma) == 0
+    finally:
+        P.shapley_game_destroy(H)
+
+
+def test_apply_operator_matches_oracle():
+    """F(v) and greedy policies of the HIP sweep equal the oracle's eq1 at random v."""
+    g = games.random_game(50, 3, 3, 77, mu=0.9, density=0.2, invalid_frac=0.2)
+    h = P.create_from(g)
+    try:
+        rng = np.random.default_rng(0)
+        for _ in range(3):
+            v = rng.normal(size=g.n)
+            F, a, b = P.shapley_apply_operator(h, v)
+            Fo = oracle.shapley_operator(g, v)
+            ao, bo = oracle.greedy(g, v)
+            np.testing.assert_allclose(F, Fo, rtol=0, atol=1e-13)
+            np.testing.assert_array_equal(a, ao)
+            np.testing.assert_array_equal(b, bo)
+    finally:
+        P.shapley_game_destroy(h)
