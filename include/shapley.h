@@ -219,6 +219,31 @@ int shapley_server_poll(shapley_server_t srv, uint64_t ticket, shapley_stats* st
 int shapley_server_step(shapley_server_t srv, int32_t* active);
 void shapley_server_destroy(shapley_server_t srv);
 
+/* ---------------------------------------------------------------- probe */
+
+/* Kernel families of the timing probe. */
+enum {
+  SHAPLEY_PROBE_SMOOTH = 0,   /* weighted-Jacobi relaxation, all AMG levels */
+  SHAPLEY_PROBE_RESID64 = 1,  /* FP64 residual of the iterative refinement */
+  SHAPLEY_PROBE_IMPROVE = 2,  /* policy improvement + Shapley residual sweep */
+  SHAPLEY_PROBE_RESID = 3,    /* cycle residual, all levels */
+  SHAPLEY_PROBE_RESTRICT = 4, /* restriction R r */
+  SHAPLEY_PROBE_PROLONG = 5,  /* prolongation + correction u += P e */
+  SHAPLEY_PROBE_RAP = 6,      /* Galerkin product (setup) */
+  SHAPLEY_PROBE_INTERP = 7    /* interpolation (setup) */
+};
+
+/* Enables (on != 0) or disables the timing probe of one kernel family and
+ * resets its totals.  While enabled, every launch of the family is bracketed
+ * by HIP events on its stream (this adds a little host overhead). */
+int shapley_probe_enable(int32_t family, int32_t on);
+
+/* Totals since the probe was enabled: launches, summed device time between
+ * the bracketing events (ms) and summed algorithmic bytes of the launches
+ * (bytes the kernel must read and write at minimum, each value once).
+ * Synchronises with the recorded events. */
+int shapley_probe_read(int32_t family, int64_t* launches, double* total_ms, double* total_bytes);
+
 #ifdef __cplusplus
 }
 #endif

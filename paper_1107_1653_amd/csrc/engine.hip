@@ -9,6 +9,7 @@
 // the next outer iteration or stops.  Games are merged block-diagonally into
 // every AMG level so that one launch per kernel serves all of them.
 #include "amg_kernels.hpp"
+#include "probe.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -167,18 +168,21 @@ void Engine::build_layout() {
 }
 
 void Engine::build_tiles(Level& L, const std::vector<char>& keep, bool cont_only) {
-  std::vector<Tile> t = make_tiles(L.goff, keep, kTileRows);
+  std::vector<Tile>& t = cont_only ? L.h_ctiles : L.h_tiles;
+  t = make_tiles(L.goff, keep, kTileRows);
+  int rows = 0;
+  for (const Tile& x : t) rows += x.r1 - x.r0;
   if (cont_only) {
     L.nctiles = (int)t.size();
+    L.rows_ctiles = rows;
     L.ctiles.ensure(std::max<size_t>(t.size(), 1));
     h2d(L.ctiles.p, t.data(), t.size(), stream);
   } else {
     L.ntiles = (int)t.size();
+    L.rows_tiles = rows;
     L.tiles.ensure(std::max<size_t>(t.size(), 1));
     h2d(L.tiles.p, t.data(), t.size(), stream);
   }
-  // pageable copies are staged before the call returns; keep the stream ordered
-  SHP_HIP(hipStreamSynchronize(stream));
 }
 
 void Engine::assemble(const std::vector<int>& run, bool mixed) {
@@ -348,8 +352,10 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         SHP_HIP(hipMemsetAsync(L.pc.p, 0xFF, sizeof(int) * (size_t)n * PW, stream));
         SHP_HIP(hipMemsetAsync(s_err.p, 0, sizeof(int) * 4, stream));
         // s_err[0]: interpolatory sets truncated, [1]: Galerkin hash overflow, [2]: singular block
+        probe_begin(kProbeInterp, stream);
         amg_interp(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, L.dinv64.p, L.strong.p, L.cf.p,
                    L.cidx.p, L.dir.p, L.pc.p, L.pv64.p, s_err.p, stream);
+        probe_end(kProbeInterp, stream, (double)L.rows_ctiles * (PW * 12) + (double)L.nnz * 13);
         pt.mark("interp");
         // ---- next level rows
         Level& Ln = lv[l + 1];
@@ -387,8 +393,10 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         Ln.nnz = cnnz;
         Ln.ci.ensure(std::max(cnnz, 1));
         Ln.a64.ensure(std::max(cnnz, 1));
+        probe_begin(kProbeRap, stream);
         amg_rap(nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, Ln.rp.p, nullptr,
                 Ln.ci.p, Ln.a64.p, s_err.p + 1, stream);
+        probe_end(kProbeRap, stream, (double)cnnz * 12 + (double)L.nnz * 12 + (double)n * PW * 12);
         if (mixed) {
           L.pv32.ensure((size_t)std::max(n, 1) * PW);
           amg_cast(L.pv64.p, L.pv32.p, (size_t)n * PW, stream);
@@ -464,6 +472,21 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
   }
 }
 
+// algorithmic bytes of the cycle kernels (each value read or written once)
+template <class T>
+static double bytes_smooth(const Level& L, bool first) {
+  const double sv = sizeof(T), rows = L.rows_ctiles;
+  if (first) return rows * 3 * sv;
+  const double nnz = L.n ? (double)L.nnz * rows / L.n : 0.0;
+  return rows * (4 + 4 * sv) + nnz * (4 + sv);
+}
+template <class T>
+static double bytes_resid(const Level& L) {
+  const double sv = sizeof(T), rows = L.rows_ctiles;
+  const double nnz = L.n ? (double)L.nnz * rows / L.n : 0.0;
+  return rows * (4 + 3 * sv) + nnz * (4 + sv);
+}
+
 template <class T>
 static T* vcycle_impl(Engine* e, std::vector<Level>& lv, int l, const EngineOpts& o, const int* act,
                       hipStream_t s) {
@@ -475,19 +498,33 @@ static T* vcycle_impl(Engine* e, std::vector<Level>& lv, int l, const EngineOpts
   if (L.nctiles) {
     const T* A = LV<T>::a(L);
     const T* D = LV<T>::d(L);
+    probe_begin(kProbeSmooth, s);
     cyc_smooth<T>(L.ctiles.p, L.nctiles, act, L.rp.p, L.ci.p, A, D, b, nullptr, cur, om, 1, s);
+    probe_end(kProbeSmooth, s, bytes_smooth<T>(L, true));
     for (int k = 1; k < o.nu1; ++k) {
+      probe_begin(kProbeSmooth, s);
       cyc_smooth<T>(L.ctiles.p, L.nctiles, act, L.rp.p, L.ci.p, A, D, b, cur, nxt, om, 0, s);
+      probe_end(kProbeSmooth, s, bytes_smooth<T>(L, false));
       std::swap(cur, nxt);
     }
     T* r = LV<T>::r(L);
+    probe_begin(kProbeResid, s);
     cyc_resid<T>(L.ctiles.p, L.nctiles, act, L.rp.p, L.ci.p, A, b, cur, r, s);
+    probe_end(kProbeResid, s, bytes_resid<T>(L));
     Level& Ln = lv[l + 1];
+    probe_begin(kProbeRestrict, s);
     cyc_restrict<T>(Ln.tiles.p, Ln.ntiles, act, L.rrp.p, L.rci.p, LV<T>::rv(L), r, LV<T>::b(Ln), s);
+    probe_end(kProbeRestrict, s,
+              (double)Ln.rows_tiles * (4 + sizeof(T)) + (double)L.rows_ctiles * (4 + 2 * sizeof(T)));
     T* xc = vcycle_impl<T>(e, lv, l + 1, o, act, s);
+    probe_begin(kProbeProlong, s);
     cyc_prolong<T>(L.ctiles.p, L.nctiles, act, L.pc.p, LV<T>::pv(L), xc, cur, s);
+    probe_end(kProbeProlong, s,
+              (double)L.rows_ctiles * (PW * (4 + sizeof(T)) + 2 * sizeof(T)) + (double)Ln.rows_tiles * sizeof(T));
     for (int k = 0; k < o.nu2; ++k) {
+      probe_begin(kProbeSmooth, s);
       cyc_smooth<T>(L.ctiles.p, L.nctiles, act, L.rp.p, L.ci.p, A, D, b, cur, nxt, om, 0, s);
+      probe_end(kProbeSmooth, s, bytes_smooth<T>(L, false));
       std::swap(cur, nxt);
     }
   }
@@ -508,12 +545,18 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
   while (true) {
     h2d(d_lin_active.p, h_lin_active.data(), G, stream);
     SHP_HIP(hipMemsetAsync(d_norm.p, 0, sizeof(double) * 4 * G, stream));
+    probe_begin(kProbeResid64, stream);
     if (mixed)
       cyc_resid64<float>(L0.tiles.p, L0.ntiles, d_lin_active.p, L0.rp.p, L0.ci.p, L0.a64.p, rhs.p, sol.p,
                          L0.b32.p, d_norm.p, stream);
     else
       cyc_resid64<double>(L0.tiles.p, L0.ntiles, d_lin_active.p, L0.rp.p, L0.ci.p, L0.a64.p, rhs.p, sol.p,
                           L0.b64.p, d_norm.p, stream);
+    {
+      const double rows = L0.rows_tiles;
+      const double nnz = L0.n ? (double)L0.nnz * rows / L0.n : 0.0;
+      probe_end(kProbeResid64, stream, rows * (4 + 8 + 8 + (mixed ? 4 : 8)) + nnz * 12);
+    }
     d2h(hn.data(), d_norm.p, 4 * G, stream);
     SHP_HIP(hipStreamSynchronize(stream));
     bool any = false;
@@ -552,11 +595,21 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
 }
 
 void Engine::improve(const std::vector<int>& run, double tie_rtol) {
-  (void)run;
   SHP_HIP(hipMemsetAsync(d_shap.p, 0, sizeof(double) * 2 * G, stream));
   SHP_HIP(hipMemsetAsync(d_cnt.p, 0, sizeof(int) * 2 * G, stream));
+  double bytes = 0.0;
+  if (probe_on(kProbeImprove))
+    for (int g : run) {
+      const Game* gm = slots[g]->g;
+      // per row: row pointer, reward, validity; per entry: column, weight;
+      // per state: value, F, and the five policy arrays
+      bytes += (double)gm->nrows * (4 + 8 + (gm->valid.p ? 1 : 0)) + (double)gm->nnz * 12 +
+               (double)gm->n * (8 + 8 + 5 * 4);
+    }
+  probe_begin(kProbeImprove, stream);
   launch_improve(ddesc.p, gtiles_imp.p, (int)h_gtiles_imp.size(), d_active.p, tie_rtol, d_shap.p, d_cnt.p,
                  stream);
+  probe_end(kProbeImprove, stream, bytes);
 }
 
 void Engine::apply_decisions(const std::vector<int>& code) {

@@ -81,6 +81,8 @@ struct Level {
   int ntiles = 0;
   DBuf<Tile> ctiles;              // tiles of continuing slots
   int nctiles = 0;
+  int rows_tiles = 0, rows_ctiles = 0;  // rows covered by tiles / ctiles
+  std::vector<Tile> h_tiles, h_ctiles;  // host copies (kept alive for async uploads)
   // transfer to the next level (continuing slots)
   int nc = 0;
   DBuf<int> pc;                   // [n*PW], -1 = empty

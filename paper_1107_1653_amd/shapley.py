@@ -34,7 +34,9 @@ EXPORTED = [
     "shapley_apply_operator", "shapley_game_info", "shapley_game_bytes", "shapley_game_destroy",
     "shapley_solve_batch", "shapley_server_create", "shapley_server_submit", "shapley_server_wait",
     "shapley_server_poll", "shapley_server_step", "shapley_server_destroy",
+    "shapley_probe_enable", "shapley_probe_read",
 ]
+PROBE = dict(smooth=0, resid64=1, improve=2, resid=3, restrict=4, prolong=5, rap=6, interp=7)
 
 
 class ShapleyError(RuntimeError):
@@ -109,6 +111,9 @@ def lib() -> C.CDLL:
         L.shapley_server_step.argtypes = [P, C.POINTER(C.c_int32)]
         L.shapley_server_destroy.argtypes = [P]
         L.shapley_server_destroy.restype = None
+        L.shapley_probe_enable.argtypes = [C.c_int32, C.c_int32]
+        L.shapley_probe_read.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                         C.POINTER(C.c_double)]
         _lib_handle = L
     return _lib_handle
 
@@ -289,6 +294,18 @@ def shapley_server_wait(srv, ticket: int, max_steps: int = 0):
 
 def shapley_server_destroy(srv) -> None:
     lib().shapley_server_destroy(srv)
+
+
+def shapley_probe_enable(family, on: bool = True) -> None:
+    fam = PROBE[family] if isinstance(family, str) else int(family)
+    _check(lib().shapley_probe_enable(fam, 1 if on else 0))
+
+
+def shapley_probe_read(family) -> dict:
+    fam = PROBE[family] if isinstance(family, str) else int(family)
+    n, ms, b = C.c_int64(), C.c_double(), C.c_double()
+    _check(lib().shapley_probe_read(fam, C.byref(n), C.byref(ms), C.byref(b)))
+    return dict(launches=n.value, ms=ms.value, bytes=b.value)
 
 
 # ---------------------------------------------------------------------------
