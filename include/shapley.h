@@ -88,6 +88,15 @@ typedef struct shapley_solve_opts {
   int32_t max_levels;
   int32_t verbose;       /* 1: one line per outer iteration on stderr */
   void* stream;          /* hipStream_t to order work on; NULL = handle's stream */
+  double reuse_frac;     /* keep the AMG splitting and interpolation of the last
+                            full setup (recomputing only the Galerkin products)
+                            while fewer than reuse_frac * n policy entries have
+                            changed since; 0 rebuilds the hierarchy every step */
+  double forcing;        /* inexact policy iteration: when > 0 each linear solve
+                            stops once ||b - A v||_inf <= forcing times the
+                            Shapley residual of the previous step (or the
+                            lin_rtol/lin_atol test, whichever is looser).
+                            0 (default) solves every system to lin_rtol. */
 } shapley_solve_opts;
 
 /* Per-solve statistics (the paper's table columns, Sec. 6, plus timings). */
@@ -112,7 +121,8 @@ typedef struct shapley_stats {
 /* Fills *o with the defaults: eps 0, FP64, AMGpi, c_fmg 1e-2, no warm start,
  * max_outer 100000, max_inner 100000, max_cycles 200, lin_rtol 1e-14,
  * lin_atol 0, tie_rtol 1e-12, theta auto, nu1 = nu2 = 2, omega 0.8,
- * coarse_max 100, max_levels 25, verbose 0, stream NULL. */
+ * coarse_max 64, max_levels 25, verbose 0, stream NULL, reuse_frac 0.05,
+ * forcing 0. */
 void shapley_default_opts(shapley_solve_opts* o);
 
 /* ---------------------------------------------------------------- games */

@@ -164,120 +164,163 @@ __global__ void k_gather_int(const int* __restrict__ src, const int* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// extended+i interpolation, truncated to PW entries per row (sum preserving)
+// extended+i interpolation with a register-resident interpolatory set: the
+// set of a row lives in a fixed-capacity register array (unrolled, predicated
+// loops, no dynamic indexing).  When the set is full, further candidates are
+// left out in enumeration order (direct strong C neighbours first, then those
+// reached through strong F neighbours), which keeps the formula consistent:
+// denominators and weights only range over the set that was kept.  Rows that
+// hit the cap are counted in `redo[0]`.
 // ---------------------------------------------------------------------------
-__device__ inline int find_in(const int* lst, int n, int v) {
-  for (int p = 0; p < n; ++p)
-    if (lst[p] == v) return p;
-  return -1;
-}
+constexpr int kFastChat = 24;
 
-__global__ __launch_bounds__(256) void k_interp(const Tile* __restrict__ tiles, const int* __restrict__ rp,
-                                                const int* __restrict__ ci, const double* __restrict__ a,
-                                                const double* __restrict__ dinv,
-                                                const uint8_t* __restrict__ strong,
-                                                const int8_t* __restrict__ cf, const int* __restrict__ cidx,
-                                                const uint8_t* __restrict__ dir, int* __restrict__ pc,
-                                                double* __restrict__ pv, int* __restrict__ overflow) {
+struct RegSet {
+  int c[kFastChat];
+  double w[kFastChat];
+  int n;
+  __device__ __forceinline__ int find(int v) const {
+    int r = -1;
+#pragma unroll
+    for (int p = 0; p < kFastChat; ++p) r = (p < n && c[p] == v) ? p : r;
+    return r;
+  }
+  // false when the set is full and v is new
+  __device__ __forceinline__ bool add(int v) {
+    if (find(v) >= 0) return true;
+    if (n >= kFastChat) return false;
+#pragma unroll
+    for (int p = 0; p < kFastChat; ++p)
+      if (p == n) c[p] = v;
+    ++n;
+    return true;
+  }
+  __device__ __forceinline__ void addw(int p, double x) {
+#pragma unroll
+    for (int q = 0; q < kFastChat; ++q)
+      if (q == p) w[q] += x;
+  }
+};
+
+__global__ __launch_bounds__(256) void k_interp_fast(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                                                     const int* __restrict__ ci, const double* __restrict__ a,
+                                                     const double* __restrict__ dinv,
+                                                     const uint8_t* __restrict__ strong,
+                                                     const int8_t* __restrict__ cf, const int* __restrict__ cidx,
+                                                     const uint8_t* __restrict__ dir, int* __restrict__ pc,
+                                                     double* __restrict__ pv, int* __restrict__ redo) {
   Tile t = tiles[blockIdx.x];
-  int i = t.r0 + threadIdx.x;
+  const int i = t.r0 + threadIdx.x;
   if (i >= t.r1) return;
   int* pci = pc + (size_t)i * PW;
   double* pvi = pv + (size_t)i * PW;
+#pragma unroll
   for (int q = 0; q < PW; ++q) { pci[q] = -1; pvi[q] = 0.0; }
   if (cf[i] == CF_C) { pci[0] = cidx[i]; pvi[0] = 1.0; return; }
   if (dir[i]) return;
-  int hc[kMaxChat];
-  double hw[kMaxChat];
-  int nh = 0;
-  bool ovf = false;
+  RegSet S;
+  S.n = 0;
+#pragma unroll
+  for (int p = 0; p < kFastChat; ++p) { S.c[p] = -1; S.w[p] = 0.0; }
   const int e0 = rp[i], e1 = rp[i + 1];
   double aii = 0.0;
+  bool ok = true;
   for (int e = e0; e < e1; ++e) {
-    int j = ci[e];
+    const int j = ci[e];
     if (j == i) { aii = a[e]; continue; }
-    if (strong[e] && cf[j] == CF_C && find_in(hc, nh, j) < 0) {
-      if (nh < kMaxChat) hc[nh++] = j; else ovf = true;
-    }
+    if (strong[e] && cf[j] == CF_C) ok &= S.add(j);
   }
   for (int e = e0; e < e1; ++e) {
-    int k = ci[e];
+    const int k = ci[e];
     if (k == i || !strong[e] || cf[k] != CF_F) continue;
     for (int e2 = rp[k]; e2 < rp[k + 1]; ++e2) {
-      int l = ci[e2];
-      if (strong[e2] && cf[l] == CF_C && find_in(hc, nh, l) < 0) {
-        if (nh < kMaxChat) hc[nh++] = l; else ovf = true;
-      }
+      const int l = ci[e2];
+      if (strong[e2] && cf[l] == CF_C) ok &= S.add(l);
     }
   }
-  if (ovf) atomicAdd(overflow, 1);
-  if (nh == 0) return;
-  for (int p = 0; p < nh; ++p) hw[p] = 0.0;
+  if (!ok) atomicAdd(redo, 1);
+  if (S.n == 0) return;
   double dd = aii;
   for (int e = e0; e < e1; ++e) {
-    int j = ci[e];
+    const int j = ci[e];
     if (j == i) continue;
-    double aij = a[e];
+    const double aij = a[e];
     if (aij == 0.0) continue;
-    int p = find_in(hc, nh, j);
-    if (p >= 0) { hw[p] += aij; continue; }
+    const int p = S.find(j);
+    if (p >= 0) { S.addw(p, aij); continue; }
     if (strong[e] && cf[j] == CF_F) {
-      // distribute a_ij over the interpolatory set through row k = j
       const int k = j;
       const bool kpos = dinv[k] >= 0.0;
       double den = 0.0;
       for (int e2 = rp[k]; e2 < rp[k + 1]; ++e2) {
-        int l = ci[e2];
+        const int l = ci[e2];
         if (l == k) continue;
-        double akl = a[e2];
-        double abar = kpos ? (akl < 0.0 ? akl : 0.0) : (akl > 0.0 ? akl : 0.0);
-        if (abar != 0.0 && (l == i || find_in(hc, nh, l) >= 0)) den += abar;
+        const double akl = a[e2];
+        const double abar = kpos ? (akl < 0.0 ? akl : 0.0) : (akl > 0.0 ? akl : 0.0);
+        if (abar != 0.0 && (l == i || S.find(l) >= 0)) den += abar;
       }
       if (den == 0.0) { dd += aij; continue; }
       for (int e2 = rp[k]; e2 < rp[k + 1]; ++e2) {
-        int l = ci[e2];
+        const int l = ci[e2];
         if (l == k) continue;
-        double akl = a[e2];
-        double abar = kpos ? (akl < 0.0 ? akl : 0.0) : (akl > 0.0 ? akl : 0.0);
+        const double akl = a[e2];
+        const double abar = kpos ? (akl < 0.0 ? akl : 0.0) : (akl > 0.0 ? akl : 0.0);
         if (abar == 0.0) continue;
         if (l == i) { dd += aij * abar / den; continue; }
-        int p2 = find_in(hc, nh, l);
-        if (p2 >= 0) hw[p2] += aij * abar / den;
+        const int p2 = S.find(l);
+        if (p2 >= 0) S.addw(p2, aij * abar / den);
       }
       continue;
     }
-    if (dir[j]) continue;  // Dirichlet neighbour: its error is zero after relaxation
-    dd += aij;             // weak connection: lumped into the diagonal
+    if (dir[j]) continue;
+    dd += aij;
   }
   if (dd == 0.0) return;
   double total = 0.0;
-  for (int p = 0; p < nh; ++p) { hw[p] = -hw[p] / dd; total += hw[p]; }
-  // keep the PW largest |w| (lowest position first on ties)
-  int keep[PW];
+#pragma unroll
+  for (int p = 0; p < kFastChat; ++p)
+    if (p < S.n) { S.w[p] = -S.w[p] / dd; total += S.w[p]; }
+  // the PW largest |w| (lowest position first on ties)
+  int kp[PW];
+  double kw[PW];
+  int kc[PW];
+  uint32_t used = 0u;
   int nk = 0;
-  for (int q = 0; q < PW && q < nh; ++q) {
+#pragma unroll
+  for (int q = 0; q < PW; ++q) {
     int best = -1;
-    double bw = -1.0;
-    for (int p = 0; p < nh; ++p) {
-      bool used = false;
-      for (int u = 0; u < nk; ++u) used |= (keep[u] == p);
-      if (!used && fabs(hw[p]) > bw) { bw = fabs(hw[p]); best = p; }
+    double bw = 0.0, bv = 0.0;
+    int bc = -1;
+#pragma unroll
+    for (int p = 0; p < kFastChat; ++p) {
+      const bool cand = p < S.n && !((used >> p) & 1u) && fabs(S.w[p]) > bw;
+      if (cand) { best = p; bw = fabs(S.w[p]); bv = S.w[p]; bc = S.c[p]; }
     }
-    if (best < 0 || bw == 0.0) break;
-    keep[nk++] = best;
+    kp[q] = best;
+    kw[q] = bv;
+    kc[q] = bc;
+    if (best >= 0) { used |= 1u << best; ++nk; }
   }
   double kept = 0.0;
-  for (int u = 0; u < nk; ++u) kept += hw[keep[u]];
-  double sc = (kept != 0.0) ? total / kept : 1.0;
-  // write sorted by coarse column
-  for (int u = 0; u < nk; ++u) {
-    int bu = u;
-    for (int u2 = u + 1; u2 < nk; ++u2)
-      if (cidx[hc[keep[u2]]] < cidx[hc[keep[bu]]]) bu = u2;
-    int tmp = keep[u]; keep[u] = keep[bu]; keep[bu] = tmp;
-    pci[u] = cidx[hc[keep[u]]];
-    pvi[u] = hw[keep[u]] * sc;
-  }
+#pragma unroll
+  for (int q = 0; q < PW; ++q)
+    if (q < nk) kept += kw[q];
+  const double sc = (kept != 0.0) ? total / kept : 1.0;
+  int cc[PW];
+#pragma unroll
+  for (int q = 0; q < PW; ++q) cc[q] = (q < nk) ? cidx[kc[q]] : INT_MAX;
+  // sort the kept entries by coarse column (at most PW, unrolled)
+#pragma unroll
+  for (int u = 0; u < PW; ++u)
+#pragma unroll
+    for (int v = 0; v + 1 < PW - u; ++v)
+      if (cc[v] > cc[v + 1]) {
+        int tc = cc[v]; cc[v] = cc[v + 1]; cc[v + 1] = tc;
+        double tw = kw[v]; kw[v] = kw[v + 1]; kw[v + 1] = tw;
+      }
+#pragma unroll
+  for (int q = 0; q < PW; ++q)
+    if (q < nk) { pci[q] = cc[q]; pvi[q] = kw[q] * sc; }
+  (void)kp;
 }
 
 // ---------------------------------------------------------------------------
@@ -527,6 +570,7 @@ __global__ __launch_bounds__(256) void k_dense_inv(const int* __restrict__ blk, 
   __shared__ int redi[256];
   const int row0 = blk[4 * blockIdx.x], nb = blk[4 * blockIdx.x + 1];
   const size_t doff = (size_t)blk[4 * blockIdx.x + 2];
+  if (nb <= kDenseWave) return;  // handled by the single-wave kernel
   double* M = work + 2 * doff;  // nb x 2nb, row-major
   const int W = 2 * nb;
   const int tid = threadIdx.x;
@@ -589,6 +633,108 @@ __global__ __launch_bounds__(256) void k_dense_inv(const int* __restrict__ blk, 
   for (size_t idx = tid; idx < (size_t)nb * nb; idx += blockDim.x) {
     int j = (int)(idx / nb), i = (int)(idx % nb);  // column-major output
     double v = M[(size_t)i * W + nb + j];
+    inv64[doff + idx] = v;
+    if (inv32) inv32[doff + idx] = (float)v;
+  }
+}
+
+// In-place Gauss-Jordan inversion with row pivoting for blocks of at most
+// kDenseWave unknowns: one workgroup, the block in LDS column-major with an
+// odd leading dimension (no bank conflicts); the elimination of a step is
+// spread over all threads (one thread per matrix entry).  Column swaps undo
+// the row pivoting at the end.
+constexpr int kDenseThreads = 256;
+
+__global__ __launch_bounds__(kDenseThreads) void k_dense_inv_wave(const int* __restrict__ blk,
+                                                                  const int* __restrict__ rp,
+                                                                  const int* __restrict__ ci,
+                                                                  const double* __restrict__ a,
+                                                                  double* __restrict__ inv64,
+                                                                  float* __restrict__ inv32,
+                                                                  int* __restrict__ err) {
+  __shared__ double M[kDenseWave * (kDenseWave + 1)];
+  __shared__ double colk[kDenseWave];
+  __shared__ double rowk[kDenseWave];
+  __shared__ double rv[kDenseThreads / 64];
+  __shared__ int ri[kDenseThreads / 64];
+  __shared__ int perm[kDenseWave];
+  const int row0 = blk[4 * blockIdx.x], nb = blk[4 * blockIdx.x + 1];
+  const size_t doff = (size_t)blk[4 * blockIdx.x + 2];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (nb > kDenseWave) return;  // handled by the general kernel
+  const int ld = nb | 1;
+  for (int idx = tid; idx < nb * ld; idx += kDenseThreads) M[idx] = 0.0;
+  __syncthreads();
+  for (int i = tid; i < nb; i += kDenseThreads) {
+    const int r = row0 + i;
+    for (int e = rp[r]; e < rp[r + 1]; ++e) {
+      const int c = ci[e] - row0;
+      if (c >= 0 && c < nb) M[c * ld + i] += a[e];
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    // pivot: largest |M[i][k]| for i >= k (lowest row on ties)
+    double bv = -1.0;
+    int bi = k;
+    for (int i = k + tid; i < nb; i += kDenseThreads) {
+      const double v = fabs(M[k * ld + i]);
+      if (v > bv) { bv = v; bi = i; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double v2 = __shfl_xor(bv, o);
+      const int i2 = __shfl_xor(bi, o);
+      if (v2 > bv || (v2 == bv && i2 < bi)) { bv = v2; bi = i2; }
+    }
+    if (lane == 0) { rv[wid] = bv; ri[wid] = bi; }
+    __syncthreads();
+    bv = rv[0];
+    bi = ri[0];
+    for (int w = 1; w < kDenseThreads / 64; ++w)
+      if (rv[w] > bv || (rv[w] == bv && ri[w] < bi)) { bv = rv[w]; bi = ri[w]; }
+    if (!(bv > 0.0)) {
+      if (tid == 0) atomicOr(err, 4);
+      return;
+    }
+    const int p = bi;
+    if (tid == 0) perm[k] = p;
+    if (p != k)
+      for (int j = tid; j < nb; j += kDenseThreads) {
+        const double t0 = M[j * ld + k];
+        M[j * ld + k] = M[j * ld + p];
+        M[j * ld + p] = t0;
+      }
+    __syncthreads();
+    const double inv = 1.0 / M[k * ld + k];
+    // pivot row (scaled, with the diagonal entry replaced by inv) and column
+    for (int j = tid; j < nb; j += kDenseThreads) {
+      rowk[j] = (j == k) ? inv : M[j * ld + k] * inv;
+      colk[j] = M[k * ld + j];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nb * nb; idx += kDenseThreads) {
+      const int j = idx / nb, i = idx - j * nb;
+      double v;
+      if (i == k) v = rowk[j];
+      else if (j == k) v = -colk[i] * inv;
+      else v = M[j * ld + i] - colk[i] * rowk[j];
+      M[j * ld + i] = v;
+    }
+    __syncthreads();
+  }
+  for (int k = nb - 1; k >= 0; --k) {
+    const int p = perm[k];
+    if (p != k)
+      for (int i = tid; i < nb; i += kDenseThreads) {
+        const double t0 = M[k * ld + i];
+        M[k * ld + i] = M[p * ld + i];
+        M[p * ld + i] = t0;
+      }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < nb * nb; idx += kDenseThreads) {
+    const int j = idx / nb, i = idx - j * nb;
+    const double v = M[j * ld + i];
     inv64[doff + idx] = v;
     if (inv32) inv32[doff + idx] = (float)v;
   }
@@ -782,10 +928,10 @@ void amg_gather_int(const int* src, const int* idx, int m, int* dst, hipStream_t
 }
 void amg_interp(const Tile* t, int nt, const int* rp, const int* ci, const double* a, const double* dinv,
                 const uint8_t* strong, const int8_t* cf, const int* cidx, const uint8_t* dir, int* pc,
-                double* pv, int* overflow, hipStream_t s) {
+                double* pv, int* capped, hipStream_t s) {
   if (!nt) return;
-  hipLaunchKernelGGL(k_interp, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, a, dinv, strong, cf, cidx, dir,
-                     pc, pv, overflow);
+  hipLaunchKernelGGL(k_interp_fast, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, a, dinv, strong, cf, cidx,
+                     dir, pc, pv, capped);
   SHP_LAUNCH_CHECK();
 }
 void amg_pt_count(const Tile* t, int nt, const int* pc, int* cnt, hipStream_t s) {
@@ -824,10 +970,14 @@ void amg_cast(const double* in, float* out, size_t n, hipStream_t s) {
   SHP_LAUNCH_CHECK();
 }
 void amg_dense_inv(const int* blk, int nblk, const int* rp, const int* ci, const double* a, double* work,
-                   double* inv64, float* inv32, int* err, hipStream_t s) {
+                   double* inv64, float* inv32, int* err, bool large, hipStream_t s) {
   if (!nblk) return;
-  hipLaunchKernelGGL(k_dense_inv, dim3(nblk), dim3(256), 0, s, blk, rp, ci, a, work, inv64, inv32, err);
+  hipLaunchKernelGGL(k_dense_inv_wave, dim3(nblk), dim3(kDenseThreads), 0, s, blk, rp, ci, a, inv64, inv32, err);
   SHP_LAUNCH_CHECK();
+  if (large) {
+    hipLaunchKernelGGL(k_dense_inv, dim3(nblk), dim3(256), 0, s, blk, rp, ci, a, work, inv64, inv32, err);
+    SHP_LAUNCH_CHECK();
+  }
 }
 
 template <class T>

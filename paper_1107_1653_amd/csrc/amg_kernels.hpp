@@ -25,7 +25,7 @@ void amg_is_c(const int8_t* cf, int* out, int n, hipStream_t s);
 void amg_gather_int(const int* src, const int* idx, int m, int* dst, hipStream_t s);
 void amg_interp(const Tile* t, int nt, const int* rp, const int* ci, const double* a, const double* dinv,
                 const uint8_t* strong, const int8_t* cf, const int* cidx, const uint8_t* dir, int* pc,
-                double* pv, int* overflow, hipStream_t s);
+                double* pv, int* capped, hipStream_t s);
 void amg_pt_count(const Tile* t, int nt, const int* pc, int* cnt, hipStream_t s);
 void amg_pt_fill(const Tile* t, int nt, const int* pc, const double* pv, const int* rrp, int* cursor,
                  int* rci, double* rv, hipStream_t s);
@@ -37,7 +37,7 @@ void amg_diag_inv(int n, const int* rp, const int* ci, const double* a, double* 
                   hipStream_t s);
 void amg_cast(const double* in, float* out, size_t n, hipStream_t s);
 void amg_dense_inv(const int* blk, int nblk, const int* rp, const int* ci, const double* a, double* work,
-                   double* inv64, float* inv32, int* err, hipStream_t s);
+                   double* inv64, float* inv32, int* err, bool large, hipStream_t s);
 
 template <class T>
 void cyc_smooth(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const T* a,

@@ -165,6 +165,8 @@ static void check_opts(const shapley_solve_opts& o) {
   SHP_REQUIRE(o.max_levels >= 1 && o.max_levels <= 64, "max_levels must lie in [1, 64]");
   SHP_REQUIRE(o.lin_rtol >= 0.0 && o.lin_atol >= 0.0 && o.tie_rtol >= 0.0, "tolerances must be >= 0");
   SHP_REQUIRE(o.c_fmg > 0.0, "c_fmg must be > 0");
+  SHP_REQUIRE(o.reuse_frac >= 0.0 && o.reuse_frac <= 1.0, "reuse_frac must lie in [0, 1]");
+  SHP_REQUIRE(std::isfinite(o.forcing) && o.forcing >= 0.0 && o.forcing < 1.0, "forcing must lie in [0, 1)");
 }
 
 static void load_warm_start(Game* g, const shapley_solve_opts& o, SlotState& S, hipStream_t s) {
@@ -272,10 +274,12 @@ void shapley_default_opts(shapley_solve_opts* o) {
   o->nu1 = 2;
   o->nu2 = 2;
   o->omega = 0.8;
-  o->coarse_max = 100;
+  o->coarse_max = 64;
   o->max_levels = 25;
   o->verbose = 0;
   o->stream = nullptr;
+  o->reuse_frac = 0.05;
+  o->forcing = 0.0;
 }
 
 int shapley_game_create(shapley_game_t* out, int64_t n, int32_t m1, int32_t m2, const int64_t* row_ptr,

@@ -349,7 +349,6 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         // ---- interpolation
         L.pc.ensure((size_t)std::max(n, 1) * PW);
         L.pv64.ensure((size_t)std::max(n, 1) * PW);
-        SHP_HIP(hipMemsetAsync(L.pc.p, 0xFF, sizeof(int) * (size_t)n * PW, stream));
         SHP_HIP(hipMemsetAsync(s_err.p, 0, sizeof(int) * 4, stream));
         // s_err[0]: interpolatory sets truncated, [1]: Galerkin hash overflow, [2]: singular block
         probe_begin(kProbeInterp, stream);
@@ -430,10 +429,11 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
       h2d(L.blk.p, hblk.data(), hblk.size(), stream);
       L.dmat64.ensure(doff);
       if (mixed) L.dmat32.ensure(doff);
-      s_dense.ensure(2 * doff);
+      const bool large = L.max_blk > kDenseWave;
+      if (large) s_dense.ensure(2 * doff);
       SHP_HIP(hipMemsetAsync(s_err.p, 0, sizeof(int) * 4, stream));
       amg_dense_inv(L.blk.p, L.nblk, L.rp.p, L.ci.p, L.a64.p, s_dense.p, L.dmat64.p,
-                    mixed ? L.dmat32.p : nullptr, s_err.p + 2, stream);
+                    mixed ? L.dmat32.p : nullptr, s_err.p + 2, large, stream);
       int herr[4] = {0, 0, 0, 0};
       d2h(herr, s_err.p, 4, stream);
       SHP_HIP(hipStreamSynchronize(stream));
@@ -470,6 +470,44 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
     slots[g]->opc = lv[0].nnz ? nnz_sum / lv[0].nnz : 1.0;
     slots[g]->gc = lv[0].n ? n_sum / lv[0].n : 1.0;
   }
+}
+
+// Numeric refresh of the last hierarchy: the C/F splitting, P and R = P^T
+// are kept and only the Galerkin products A_{l+1} = R A_l P, the diagonals,
+// the FP32 copies and the dense coarsest inverses are recomputed from the
+// freshly assembled level-0 matrix (whose sparsity pattern does not depend on
+// the policies).
+void Engine::refresh(const EngineOpts& o) {
+  const bool mixed = o.precision == SHAPLEY_MIXED;
+  PhaseTimer pt(this, prof);
+  SHP_HIP(hipMemsetAsync(s_err.p, 0, sizeof(int) * 4, stream));
+  for (int l = 0; l < nlev; ++l) {
+    Level& L = lv[l];
+    const int n = L.n;
+    if (l > 0) {
+      amg_diag_inv(n, L.rp.p, L.ci.p, L.a64.p, L.dinv64.p, mixed ? L.dinv32.p : nullptr, stream);
+      if (mixed) amg_cast(L.a64.p, L.a32.p, L.nnz, stream);
+    }
+    if (L.nctiles) {
+      amg_dirichlet(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, L.dir.p, stream);
+      amg_dir_scale(L.ctiles.p, L.nctiles, L.dir.p, 1.0 / o.omega, L.dinv64.p, mixed ? L.dinv32.p : nullptr,
+                    stream);
+      Level& Ln = lv[l + 1];
+      probe_begin(kProbeRap, stream);
+      amg_rap(L.nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, Ln.rp.p, nullptr,
+              Ln.ci.p, Ln.a64.p, s_err.p + 1, stream);
+      probe_end(kProbeRap, stream, (double)Ln.nnz * 12 + (double)L.nnz * 12 + (double)n * PW * 12);
+    }
+    if (L.nblk)
+      amg_dense_inv(L.blk.p, L.nblk, L.rp.p, L.ci.p, L.a64.p, s_dense.p, L.dmat64.p, mixed ? L.dmat32.p : nullptr,
+                    s_err.p + 2, L.max_blk > kDenseWave, stream);
+  }
+  int herr[4] = {0, 0, 0, 0};
+  d2h(herr, s_err.p, 4, stream);
+  SHP_HIP(hipStreamSynchronize(stream));
+  pt.mark("refresh");
+  if (herr[1] != 0) throw Error(SHAPLEY_EDEVICE, "Galerkin product failed during refresh");
+  if (herr[2] != 0) throw Error(SHAPLEY_EDEVICE, "singular coarsest block");
 }
 
 // algorithmic bytes of the cycle kernels (each value read or written once)
@@ -565,6 +603,10 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
       SlotState* S = slots[g];
       double rn = hn[4 * g], xn = hn[4 * g + 1];
       double tol = std::max(o.lin_rtol * std::max(hb[g], xn), o.lin_atol);
+      // inexact policy iteration: the linear solve only needs to be accurate
+      // to a fraction of the Shapley residual of the previous step
+      if (o.forcing > 0.0 && std::isfinite(S->res_prev) && S->res_prev > 0.0)
+        tol = std::max(tol, o.forcing * S->res_prev);
       auto& h = hist[g];
       h.push_back(rn);
       bool stop = false;
@@ -627,11 +669,15 @@ void Engine::run_init(const std::vector<int>& run) {
   for (int g : fresh) act[g] = 1;
   h2d(d_active.p, act.data(), G, stream);
   improve(fresh, slots[fresh[0]]->opt.tie_rtol);
+  std::vector<double> hs(2 * G);
+  d2h(hs.data(), d_shap.p, 2 * G, stream);
+  SHP_HIP(hipStreamSynchronize(stream));
   std::vector<int> code(G, 0);
   for (int g : fresh) {
     SlotState* S = slots[g];
     code[g] = !S->init_alpha ? 2 : (!S->init_beta ? 1 : 0);
     S->need_init = false;
+    S->res_prev = hs[2 * g];
   }
   apply_decisions(code);
 }
@@ -665,11 +711,32 @@ int Engine::step() {
   PhaseTimer pt(this, prof);
   assemble(run, mixed);
   pt.mark("assemble");
-  setup(run, o);
+  bool full = !have_hier || run != run_at_setup || o.reuse_frac <= 0.0 ||
+              (double)changes_since_setup > o.reuse_frac * std::max(1, N0) ||
+              last_cycles > std::max(2 * cycles_after_full, cycles_after_full + 6);
+  if (full) {
+    setup(run, o);
+    have_hier = true;
+    run_at_setup = run;
+    changes_since_setup = 0;
+    cycles_after_full = -1;
+    ++full_setups;
+  } else {
+    refresh(o);
+    ++refreshes;
+  }
   pt.mark("setup");
   SHP_HIP(hipStreamSynchronize(stream));
   double t1 = now_s();
-  solve_linear(run, o);
+  {
+    std::vector<int> before(G);
+    for (int g : run) before[g] = slots[g]->cycles_total;
+    solve_linear(run, o);
+    int mx = 0;
+    for (int g : run) mx = std::max(mx, slots[g]->cycles_total - before[g]);
+    last_cycles = mx;
+    if (cycles_after_full < 0) cycles_after_full = mx;
+  }
   pt.mark("solve");
   launch_scatter_v(ddesc.p, gtiles_all.p, (int)h_gtiles_all.size(), d_active.p, sol.p, stream);
   SHP_HIP(hipStreamSynchronize(stream));
@@ -692,6 +759,7 @@ int Engine::step() {
     S->improve_s += t3 - t2;
     const Game* gm = S->g;
     S->res = hs[2 * g];
+    S->res_prev = S->res;
     S->res_l2 = gm->n ? std::sqrt(hs[2 * g + 1] / gm->n) : 0.0;
     int nin = hc[2 * g], nout = hc[2 * g + 1];
     S->nk += 1;
@@ -715,6 +783,7 @@ int Engine::step() {
       S->done = true;
     } else if (nin > 0 && S->nk < S->opt.max_inner) {
       code[g] = 1;
+      changes_since_setup += nin;
     } else {
       if (S->k <= 64) S->inner_per_outer[S->k - 1] = S->nk;
       if (nout == 0) {
@@ -727,6 +796,7 @@ int Engine::step() {
         code[g] = 2;
         S->k += 1;
         S->nk = 0;
+        changes_since_setup += nout;
       }
     }
     if (!S->done) ++still;
@@ -753,6 +823,8 @@ EngineOpts engine_opts_from(const shapley_solve_opts& o, int dim) {
   e.coarse_max = o.coarse_max;
   e.max_levels = o.max_levels;
   e.verbose = o.verbose;
+  e.reuse_frac = o.reuse_frac;
+  e.forcing = o.forcing;
   return e;
 }
 

@@ -11,8 +11,8 @@ namespace shp {
 constexpr int PW = 4;            // max interpolation entries per fine row (ELL width)
 constexpr int kTileRows = 256;   // rows per level tile
 constexpr int kMaxUnion = 128;   // max entries of one state's level-0 pattern row
-constexpr int kMaxChat = 64;     // max interpolatory set size (extended+i)
 constexpr int kDenseMax = 1024;  // largest dense coarse block
+constexpr int kDenseWave = 88;   // blocks up to this size are inverted by one wavefront in LDS
 
 // POD view of one game for work-list kernels.
 struct GameDesc {
@@ -116,8 +116,10 @@ struct EngineOpts {
   double theta = -1.0;
   int nu1 = 2, nu2 = 2;
   double omega = 0.8;
-  int coarse_max = 100, max_levels = 25;
+  int coarse_max = 64, max_levels = 25;
   int verbose = 0;
+  double reuse_frac = 0.05;
+  double forcing = 0.0;
 };
 
 EngineOpts engine_opts_from(const shapley_solve_opts& o, int dim);
@@ -134,6 +136,7 @@ struct SlotState {
   int status = SHAPLEY_OK;
   bool converged = false;
   double res = 0.0, res_l2 = 0.0;
+  double res_prev = INFINITY;   // Shapley residual after the previous value step
   double setup_s = 0, cycle_s = 0, improve_s = 0;
   int levels = 0;
   double opc = 0, gc = 0;
@@ -151,7 +154,7 @@ class Engine {
   // Runs one PI step (solve + improve + decide) for every slot not done.
   // Returns the number of slots still running.
   int step();
-  void invalidate_layout() { layout_dirty = true; }
+  void invalidate_layout() { layout_dirty = true; have_hier = false; }
   // Evaluates the improvement sweep at the slots' current v (no decisions).
   void improve_only();
 
@@ -186,6 +189,15 @@ class Engine {
   void run_init(const std::vector<int>& run);
   void assemble(const std::vector<int>& run, bool mixed);
   void setup(const std::vector<int>& run, const EngineOpts& o);
+  void refresh(const EngineOpts& o);
+  // hierarchy reuse across policy-iteration steps
+  bool have_hier = false;
+  std::vector<int> run_at_setup;
+  int64_t changes_since_setup = 0;
+  int last_cycles = 0, cycles_after_full = -1;
+ public:
+  int full_setups = 0, refreshes = 0;
+ private:
   void solve_linear(const std::vector<int>& run, const EngineOpts& o);
   void improve(const std::vector<int>& run, double tie_rtol);
   void apply_decisions(const std::vector<int>& code);

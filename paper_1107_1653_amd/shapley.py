@@ -57,7 +57,7 @@ class shapley_solve_opts(C.Structure):
         ("lin_rtol", C.c_double), ("lin_atol", C.c_double), ("tie_rtol", C.c_double),
         ("theta", C.c_double), ("nu1", C.c_int32), ("nu2", C.c_int32), ("omega", C.c_double),
         ("coarse_max", C.c_int32), ("max_levels", C.c_int32), ("verbose", C.c_int32),
-        ("stream", C.c_void_p),
+        ("stream", C.c_void_p), ("reuse_frac", C.c_double), ("forcing", C.c_double),
     ]
 
 
