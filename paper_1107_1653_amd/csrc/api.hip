@@ -7,10 +7,6 @@
 #include <cmath>
 #include <numeric>
 
-struct shapley_game_s {
-  shp::Game* g;
-};
-
 namespace shp {
 
 static thread_local std::string g_last_error;

@@ -605,8 +605,12 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
       double tol = std::max(o.lin_rtol * std::max(hb[g], xn), o.lin_atol);
       // inexact policy iteration: the linear solve only needs to be accurate
       // to a fraction of the Shapley residual of the previous step
-      if (o.forcing > 0.0 && std::isfinite(S->res_prev) && S->res_prev > 0.0)
-        tol = std::max(tol, o.forcing * S->res_prev);
+      if (o.forcing > 0.0 && std::isfinite(S->res_prev) && S->res_prev > 0.0 && o.forcing * S->res_prev > tol) {
+        tol = o.forcing * S->res_prev;
+        S->loose = true;
+      } else {
+        S->loose = false;
+      }
       auto& h = hist[g];
       h.push_back(rn);
       bool stop = false;
@@ -760,6 +764,7 @@ int Engine::step() {
     const Game* gm = S->g;
     S->res = hs[2 * g];
     S->res_prev = S->res;
+    ++S->solves;
     S->res_l2 = gm->n ? std::sqrt(hs[2 * g + 1] / gm->n) : 0.0;
     int nin = hc[2 * g], nout = hc[2 * g + 1];
     S->nk += 1;
@@ -784,6 +789,12 @@ int Engine::step() {
     } else if (nin > 0 && S->nk < S->opt.max_inner) {
       code[g] = 1;
       changes_since_setup += nin;
+    } else if (S->loose) {
+      // policies look stable after an inexact solve: solve the same system
+      // to full accuracy before deciding
+      S->res_prev = 0.0;
+      S->nk -= 1;
+      S->inner_total -= 1;
     } else {
       if (S->k <= 64) S->inner_per_outer[S->k - 1] = S->nk;
       if (nout == 0) {

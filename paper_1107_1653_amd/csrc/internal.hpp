@@ -137,6 +137,8 @@ struct SlotState {
   bool converged = false;
   double res = 0.0, res_l2 = 0.0;
   double res_prev = INFINITY;   // Shapley residual after the previous value step
+  bool loose = false;           // the last linear solve used the forcing tolerance
+  int solves = 0;               // value steps performed (including accuracy re-solves)
   double setup_s = 0, cycle_s = 0, improve_s = 0;
   int levels = 0;
   double opc = 0, gc = 0;
@@ -230,3 +232,8 @@ void launch_fmg(const Game* c, const Game* f, hipStream_t s);
 void scan_exclusive(const int* in, int* out, int n, hipStream_t s, DBuf<int>& scratch);
 
 }  // namespace shp
+
+// payload of the opaque game handle of the C ABI
+struct shapley_game_s {
+  shp::Game* g;
+};

@@ -140,3 +140,72 @@ def test_apply_operator_matches_oracle():
             np.testing.assert_array_equal(b, bo)
     finally:
         P.shapley_game_destroy(h)
+
+
+def test_server_continuous_batching_matches_alone():
+    """Requests that arrive while others run are admitted as budget frees up;
+    each result is the one the game gets alone (and the oracle's)."""
+    specs = [(0, 17, 0.5, 2001), (1, 31, 2.0, 2002), (0, 33, 9.0, 2003), (1, 15, 0.3, 2004),
+             (0, 9, 1.0, 2005), (1, 33, 5.0, 2006)]
+    gs = [configs.c4_game(*sp) for sp in specs]
+    lv = configs.c1_levels(points=65, coarsest_points=17)
+    hs = [P.create_from(g) for g in gs]
+    H = P.shapley_game_create_hierarchy([P.create_from(g) for g in lv])
+    sizes = [P.shapley_game_bytes(h) for h in hs]
+    # a budget that holds about two requests at a time
+    srv = P.shapley_server_create(int(3 * max(sizes) * 4))
+    try:
+        o = P.shapley_default_opts(**LIMITS)
+        a0 = np.zeros(lv[0].n, np.int32)
+        of = P.shapley_default_opts(method=P.SHAPLEY_FAMGPI, alpha0=a0, beta0=a0, **LIMITS)
+        tickets = [P.shapley_server_submit(srv, hs[k], o) for k in range(3)]
+        steps = 0
+        max_active = 0
+        while steps < 3:
+            max_active = max(max_active, P.shapley_server_step(srv))
+            steps += 1
+        tickets += [P.shapley_server_submit(srv, hs[k], o) for k in range(3, 6)]
+        tf = P.shapley_server_submit(srv, H, of)
+        while True:
+            act = P.shapley_server_step(srv)
+            max_active = max(max_active, act)
+            steps += 1
+            if act == 0 or steps > 5000:
+                break
+        stats = [P.shapley_server_poll(srv, t) for t in tickets]
+        sf = P.shapley_server_poll(srv, tf)
+        assert all(s is not None for s in stats) and sf is not None
+        log(f"  server steps {steps} max active {max_active}")
+        for k, g in enumerate(gs):
+            v = P.shapley_get_value(hs[k])
+            a, b = P.shapley_get_policy(hs[k])
+            ref = oracle.policy_iteration(g)
+            va, aa, ba, _ = solve_gpu(g, **LIMITS)
+            err, ma, mb, _ = compare_with_oracle(g, v, a, b, ref, 1e-9)
+            alone = np.max(np.abs(v - va)) / np.max(np.abs(va))
+            log(f"  request {k} n={g.n} latency {stats[k]['seconds']*1e3:.1f} ms vs-oracle {err:.2e} "
+                f"vs-alone {alone:.2e}")
+            assert err <= 1e-9 and len(ma) == 0 and len(mb) == 0 and alone <= 1e-12
+        ref = oracle.policy_iteration(lv[-1])
+        v = P.shapley_get_value(H)
+        a, b = P.shapley_get_policy(H)
+        err, ma, mb, _ = compare_with_oracle(lv[-1], v, a, b, ref, 1e-9)
+        log(f"  famg request vs-oracle {err:.2e} grids {sf['fmg_levels']}")
+        assert err <= 1e-9 and len(ma) == 0 and sf["fmg_levels"] == len(lv)
+    finally:
+        P.shapley_server_destroy(srv)
+        for h in hs:
+            P.shapley_game_destroy(h)
+        P.shapley_game_destroy(H)
+
+
+def test_reuse_and_forcing_reach_the_same_fixed_point():
+    """Hierarchy reuse and inexact solves change the path, not the fixed point."""
+    g = configs.c1(points=65)
+    ref = oracle.policy_iteration(g)
+    a0 = np.zeros(g.n, np.int32)
+    for reuse, forcing in ((0.0, 0.0), (0.5, 0.0), (0.05, 0.1)):
+        v, a, b, st = solve_gpu(g, alpha0=a0, beta0=a0, reuse_frac=reuse, forcing=forcing, **LIMITS)
+        err, ma, mb, _ = compare_with_oracle(g, v, a, b, ref, 1e-9)
+        log(f"  reuse {reuse} forcing {forcing}: err {err:.2e} outer {st['outer']} cycles {st['cycles_total']}")
+        assert err <= 1e-9 and len(ma) == 0
