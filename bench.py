@@ -69,7 +69,7 @@ print(json.dumps(dict(seconds=dt, n=levels[-1].n, residual=res[-1].residual)))
     }
 
 
-def main() -> int:
+def parse_args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
@@ -82,10 +82,28 @@ def main() -> int:
     ap.add_argument("--roofline-kernel", default="auto")
     ap.add_argument("--forcing", type=float, default=0.1)
     ap.add_argument("--reuse", type=float, default=0.05)
-    args = ap.parse_args()
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4"])
+    ap.add_argument("--games", type=int, default=256, help="C3 batch size")
+    ap.add_argument("--requests", type=int, default=100, help="C4 requests")
+    ap.add_argument("--side", type=int, default=129, help="C2 interior points per side")
+    return ap.parse_args()
+
+
+def main() -> int:
+    args = parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         return 2
+    return {"c0": run_c0, "c1": run_c1, "c2": run_c2, "c3": run_c3, "c4": run_c4}[args.workload](args)
+
+
+def base_record(args, value, ms_per_step, dtype, config):
+    return {"metric": METRIC, "value": value, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def run_c1(args) -> int:
 
     import torch  # device synchronisation around the timed region only
     import paper_1107_1653_amd as P
@@ -209,6 +227,220 @@ def main() -> int:
     }
     P.shapley_game_destroy(H)
     print(json.dumps(out), flush=True)
+    return 0
+
+
+
+
+def _opts(P, prec, args, **kw):
+    return P.shapley_default_opts(eps=1e-8, precision=prec, max_outer=5000, max_inner=5000,
+                                  forcing=args.forcing, reuse_frac=args.reuse, **kw)
+
+
+def run_c0(args) -> int:
+    """Isaacs 2-D, 33x33 interior grid (n = 1089): plain PI latency over
+    at least 20 repeats, FP64 and mixed."""
+    import torch
+    import paper_1107_1653_amd as P
+    from shapley_inputs import configs
+    g = configs.c0()
+    h = P.create_from(g)
+    reps = max(args.steps, 20)
+    out = {}
+    for name, prec in (("fp64", P.SHAPLEY_FP64), ("mixed", P.SHAPLEY_MIXED)):
+        o = _opts(P, prec, args)
+        for _ in range(max(args.warmup, 1)):
+            P.shapley_solve(h, o)
+        torch.cuda.synchronize()
+        lat = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            st = P.shapley_solve(h, o)
+            lat.append(time.perf_counter() - t)
+        lat = 1e3 * np.array(lat)
+        out[name] = {"value": g.n / (np.mean(lat) * 1e-3), "p50_ms": float(np.percentile(lat, 50)),
+                     "p99_ms": float(np.percentile(lat, 99)), "residual": st["residual"],
+                     "outer": st["outer"], "inner": st["inner_total"]}
+    P.shapley_game_destroy(h)
+    rec = base_record(args, out["fp64"]["value"], out["fp64"]["p50_ms"], "f64",
+                      {"workload": "Isaacs 2-D 33x33 interior (n=1089), AMGpi FP64 to 1e-8", "repeats": reps})
+    rec["latency_ms"] = {"p50": out["fp64"]["p50_ms"], "p99": out["fp64"]["p99_ms"]}
+    rec["extra"] = out
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+def run_c2(args) -> int:
+    """Isaacs 3-D on 129^3: FP64 V-cycles vs FP32 V-cycles under FP64
+    refinement, AMGpi to 1e-8; the mixed result's distance to the FP64 one."""
+    import torch
+    import paper_1107_1653_amd as P
+    from shapley_inputs import configs
+    t0 = time.perf_counter()
+    g = configs.c2(s=args.side)
+    log(f"[bench] generated C2 n={g.n} in {time.perf_counter() - t0:.1f}s")
+    h = P.create_from(g)
+    out, vals = {}, {}
+    for name, prec in (("fp64", P.SHAPLEY_FP64), ("mixed", P.SHAPLEY_MIXED)):
+        o = _opts(P, prec, args)
+        for _ in range(args.warmup):
+            P.shapley_solve(h, o)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.steps):
+            t = time.perf_counter()
+            st = P.shapley_solve(h, o)
+            ts.append(time.perf_counter() - t)
+        vals[name] = P.shapley_get_value(h)
+        out[name] = {"value": g.n / float(np.mean(ts)), "ms_per_step": 1e3 * float(np.mean(ts)),
+                     "residual": st["residual"], "outer": st["outer"], "inner": st["inner_total"],
+                     "cycles": st["cycles_total"], "levels": st["levels"], "op_complexity": st["op_complexity"],
+                     "setup_ms": 1e3 * st["setup_seconds"], "cycle_ms": 1e3 * st["cycle_seconds"]}
+        log(f"[bench] C2 {name}: {out[name]['ms_per_step']:.1f} ms, residual {st['residual']:.1e}")
+    out["mixed"]["max_abs_diff_vs_fp64"] = float(np.max(np.abs(vals["mixed"] - vals["fp64"])))
+    P.shapley_game_destroy(h)
+    rec = base_record(args, out["fp64"]["value"], out["fp64"]["ms_per_step"], "f64",
+                      {"workload": f"Isaacs 3-D {args.side}^3 interior (n={g.n}), AMGpi to 1e-8"})
+    rec["extra"] = out
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+def run_c3(args) -> int:
+    """256 independent 2-D Isaacs games (sides 65/129/257): one lock-step
+    batched solve (one launch per kernel and level for all games) vs the same
+    games solved one after another, FP64 and mixed."""
+    import torch
+    import paper_1107_1653_amd as P
+    from shapley_inputs import configs
+    t0 = time.perf_counter()
+    side, lam = configs.c3_sizes(count=args.games)
+    gs = [configs.c3_game(k, side[k], lam[k]) for k in range(args.games)]
+    total = int(sum(g.n for g in gs))
+    log(f"[bench] generated {len(gs)} games, sum n = {total} in {time.perf_counter() - t0:.1f}s")
+    hs = [P.create_from(g) for g in gs]
+    out = {}
+    vals = {}
+    for name, prec in (("batched_fp64", P.SHAPLEY_FP64), ("batched_mixed", P.SHAPLEY_MIXED)):
+        o = _opts(P, prec, args)
+        for _ in range(args.warmup):
+            P.shapley_solve_batch(hs, o)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.steps):
+            t = time.perf_counter()
+            st = P.shapley_solve_batch(hs, o)
+            ts.append(time.perf_counter() - t)
+        vals[name] = [P.shapley_get_value(h) for h in hs[:8]]
+        out[name] = {"value": total / float(np.mean(ts)), "ms_per_step": 1e3 * float(np.mean(ts)),
+                     "max_residual": max(s["residual"] for s in st),
+                     "max_outer": max(s["outer"] for s in st)}
+        log(f"[bench] C3 {name}: {out[name]['ms_per_step']:.1f} ms")
+    o = _opts(P, P.SHAPLEY_FP64, args)
+    for h in hs[:4]:
+        P.shapley_solve(h, o)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for h in hs:
+        P.shapley_solve(h, o)
+    dt = time.perf_counter() - t
+    seq = [P.shapley_get_value(h) for h in hs[:8]]
+    out["sequential_fp64"] = {"value": total / dt, "ms_per_step": 1e3 * dt}
+    log(f"[bench] C3 sequential fp64: {1e3 * dt:.1f} ms")
+    out["batched_vs_alone_max_rel_diff"] = float(max(
+        np.max(np.abs(a - b)) / np.max(np.abs(b)) for a, b in zip(vals["batched_fp64"], seq)))
+    for h in hs:
+        P.shapley_game_destroy(h)
+    rec = base_record(args, out["batched_mixed"]["value"], out["batched_mixed"]["ms_per_step"], "f64",
+                      {"workload": f"{len(gs)} Isaacs 2-D games, sides 65/129/257 (sum n={total}), "
+                                   "batched AMGpi mixed to 1e-8", "games": len(gs)})
+    rec["extra"] = out
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+def run_c4(args) -> int:
+    """Serving: Poisson arrivals of Isaacs (AMGpi) and obstacle (FAMGpi on a
+    non-nested hierarchy) requests, sides log-uniform in [33, 1025], through
+    the continuous-batching server with a 200 GB budget.  First a closed loop
+    (everything queued at once) gives the saturation rate X_sat; then open
+    loops at 0.5 and 0.8 X_sat report p50/p99 latency and solves/s."""
+    import torch
+    import paper_1107_1653_amd as P
+    from shapley_inputs import configs
+    reqs = configs.c4_requests(count=args.requests)
+    t0 = time.perf_counter()
+    handles, sizes = [], []
+    for kind, side, lam, seed in reqs:
+        if kind == 0:
+            h = P.create_from(configs.c4_game(kind, side, lam, seed))
+            handles.append((h, False, None))
+        else:
+            lv = configs.obstacle_levels_for_side(side, seed, lam)
+            H = P.shapley_game_create_hierarchy([P.create_from(g) for g in lv])
+            handles.append((H, True, lv[0].n))
+        sizes.append(side * side)
+    total = int(sum(sizes))
+    log(f"[bench] created {len(handles)} requests (sum n = {total}) in {time.perf_counter() - t0:.1f}s")
+
+    def opts_for(is_h, n0):
+        if is_h:
+            a0 = np.zeros(n0, np.int32)
+            return _opts(P, P.SHAPLEY_MIXED, args, method=P.SHAPLEY_FAMGPI, alpha0=a0, beta0=a0)
+        return _opts(P, P.SHAPLEY_MIXED, args)
+
+    opts = [opts_for(is_h, n0) for (_, is_h, n0) in handles]
+
+    def run(rate):
+        srv = P.shapley_server_create(200 * 10 ** 9)
+        rng = np.random.default_rng(7)
+        arrivals = (np.zeros(len(handles)) if rate is None
+                    else np.cumsum(rng.exponential(1.0 / rate, size=len(handles))))
+        torch.cuda.synchronize()
+        start = time.perf_counter()
+        tickets = [None] * len(handles)
+        sub_t = [0.0] * len(handles)
+        nxt = 0
+        done = 0
+        lat = [None] * len(handles)
+        while done < len(handles):
+            now = time.perf_counter() - start
+            while nxt < len(handles) and arrivals[nxt] <= now:
+                tickets[nxt] = P.shapley_server_submit(srv, handles[nxt][0], opts[nxt])
+                sub_t[nxt] = arrivals[nxt]
+                nxt += 1
+            active = P.shapley_server_step(srv)
+            for i in range(nxt):
+                if lat[i] is None:
+                    st = P.shapley_server_poll(srv, tickets[i])
+                    if st is not None:
+                        lat[i] = (time.perf_counter() - start) - sub_t[i]
+                        done += 1
+            if active == 0 and nxt < len(handles):
+                time.sleep(max(0.0, min(0.01, arrivals[nxt] - (time.perf_counter() - start))))
+        wall = time.perf_counter() - start
+        P.shapley_server_destroy(srv)
+        lat = 1e3 * np.array(lat)
+        return {"solves_per_s": len(handles) / wall, "unknowns_per_s": total / wall, "wall_s": wall,
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))}
+
+    run(None)  # warm-up pass (allocations)
+    closed = run(None)
+    log(f"[bench] C4 closed loop: {closed}")
+    xs = closed["solves_per_s"]
+    o5 = run(0.5 * xs)
+    log(f"[bench] C4 open loop 0.5 X_sat: {o5}")
+    o8 = run(0.8 * xs)
+    log(f"[bench] C4 open loop 0.8 X_sat: {o8}")
+    for h, _, _ in handles:
+        P.shapley_game_destroy(h)
+    rec = base_record(args, closed["unknowns_per_s"], 1e3 * closed["wall_s"], "f64",
+                      {"workload": f"{len(handles)} serving requests (50/50 Isaacs/obstacle, sides log-uniform "
+                                   f"33..1025, sum n={total}), mixed precision, 200 GB budget",
+                       "requests": len(handles)})
+    rec["latency_ms"] = {"p50": o8["p50_ms"], "p99": o8["p99_ms"], "load": "0.8 X_sat"}
+    rec["extra"] = {"closed_loop": closed, "open_0.5": o5, "open_0.8": o8}
+    print(json.dumps(rec), flush=True)
     return 0
 
 
