@@ -130,6 +130,7 @@ def run_c1(args) -> int:
     if fam == "auto":
         for k in P.PROBE:
             P.shapley_probe_enable(k, True)
+        log("[bench] probing kernel families (one solve)")
         P.shapley_solve(H, o64)
         tot = {k: P.shapley_probe_read(k)["ms"] for k in P.PROBE}
         for k in P.PROBE:
@@ -145,10 +146,11 @@ def run_c1(args) -> int:
     lat = []
     st = None
     t_start = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         t = time.perf_counter()
         st = P.shapley_solve(H, o64)
         lat.append(time.perf_counter() - t)
+        log(f"[bench] step {k}: {1e3 * lat[-1]:.1f} ms")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     pr = P.shapley_probe_read(fam)

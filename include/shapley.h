@@ -116,6 +116,9 @@ typedef struct shapley_stats {
   double op_complexity;      /* sum nnz(A_l) / nnz(A_0) of the last hierarchy */
   double grid_complexity;    /* sum n_l / n_0 */
   int32_t inner_per_outer[64]; /* n_k for k = 1..64 */
+  int32_t setups_full;       /* AMG setups built from scratch */
+  int32_t setups_refresh;    /* numeric refreshes of a kept hierarchy */
+  int32_t value_steps;       /* linear systems solved, accuracy re-solves included */
 } shapley_stats;
 
 /* Fills *o with the defaults: eps 0, FP64, AMGpi, c_fmg 1e-2, no warm start,

@@ -164,163 +164,145 @@ __global__ void k_gather_int(const int* __restrict__ src, const int* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// extended+i interpolation with a register-resident interpolatory set: the
-// set of a row lives in a fixed-capacity register array (unrolled, predicated
-// loops, no dynamic indexing).  When the set is full, further candidates are
-// left out in enumeration order (direct strong C neighbours first, then those
-// reached through strong F neighbours), which keeps the formula consistent:
-// denominators and weights only range over the set that was kept.  Rows that
-// hit the cap are counted in `redo[0]`.
+// extended+i interpolation.  Each thread builds the interpolatory set of its
+// row (the strong C neighbours, then the strong C neighbours of its strong F
+// neighbours) in its own column of an LDS array -- no dynamic indexing of
+// registers, no scratch, no synchronisation between threads.  When the set
+// is full, later candidates are left out in that enumeration order; the
+// denominators and weights then only range over the kept set, so the
+// formula stays consistent.  Rows that hit the cap are counted in `capped`.
+// The PW largest weights are kept and rescaled to preserve the row sum.
 // ---------------------------------------------------------------------------
-constexpr int kFastChat = 24;
+constexpr int kIThreads = 64;
+constexpr int kIChat = 32;
 
-struct RegSet {
-  int c[kFastChat];
-  double w[kFastChat];
-  int n;
-  __device__ __forceinline__ int find(int v) const {
-    int r = -1;
-#pragma unroll
-    for (int p = 0; p < kFastChat; ++p) r = (p < n && c[p] == v) ? p : r;
-    return r;
-  }
-  // false when the set is full and v is new
-  __device__ __forceinline__ bool add(int v) {
-    if (find(v) >= 0) return true;
-    if (n >= kFastChat) return false;
-#pragma unroll
-    for (int p = 0; p < kFastChat; ++p)
-      if (p == n) c[p] = v;
-    ++n;
-    return true;
-  }
-  __device__ __forceinline__ void addw(int p, double x) {
-#pragma unroll
-    for (int q = 0; q < kFastChat; ++q)
-      if (q == p) w[q] += x;
-  }
-};
-
-__global__ __launch_bounds__(256) void k_interp_fast(const Tile* __restrict__ tiles, const int* __restrict__ rp,
-                                                     const int* __restrict__ ci, const double* __restrict__ a,
-                                                     const double* __restrict__ dinv,
-                                                     const uint8_t* __restrict__ strong,
-                                                     const int8_t* __restrict__ cf, const int* __restrict__ cidx,
-                                                     const uint8_t* __restrict__ dir, int* __restrict__ pc,
-                                                     double* __restrict__ pv, int* __restrict__ redo) {
-  Tile t = tiles[blockIdx.x];
-  const int i = t.r0 + threadIdx.x;
-  if (i >= t.r1) return;
-  int* pci = pc + (size_t)i * PW;
-  double* pvi = pv + (size_t)i * PW;
-#pragma unroll
-  for (int q = 0; q < PW; ++q) { pci[q] = -1; pvi[q] = 0.0; }
-  if (cf[i] == CF_C) { pci[0] = cidx[i]; pvi[0] = 1.0; return; }
-  if (dir[i]) return;
-  RegSet S;
-  S.n = 0;
-#pragma unroll
-  for (int p = 0; p < kFastChat; ++p) { S.c[p] = -1; S.w[p] = 0.0; }
-  const int e0 = rp[i], e1 = rp[i + 1];
-  double aii = 0.0;
-  bool ok = true;
-  for (int e = e0; e < e1; ++e) {
-    const int j = ci[e];
-    if (j == i) { aii = a[e]; continue; }
-    if (strong[e] && cf[j] == CF_C) ok &= S.add(j);
-  }
-  for (int e = e0; e < e1; ++e) {
-    const int k = ci[e];
-    if (k == i || !strong[e] || cf[k] != CF_F) continue;
-    for (int e2 = rp[k]; e2 < rp[k + 1]; ++e2) {
-      const int l = ci[e2];
-      if (strong[e2] && cf[l] == CF_C) ok &= S.add(l);
+__global__ __launch_bounds__(kIThreads) void k_interp_lds(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                                                          const int* __restrict__ ci, const double* __restrict__ a,
+                                                          const double* __restrict__ dinv,
+                                                          const uint8_t* __restrict__ strong,
+                                                          const int8_t* __restrict__ cf, const int* __restrict__ cidx,
+                                                          const uint8_t* __restrict__ dir, int* __restrict__ pc,
+                                                          double* __restrict__ pv, int* __restrict__ capped) {
+  __shared__ int lc[kIChat * kIThreads];
+  __shared__ double lw[kIChat * kIThreads];
+  // kTileRows / kIThreads blocks share one tile, each taking kIThreads rows
+  const Tile t = tiles[blockIdx.x / (kTileRows / kIThreads)];
+  const int sub = blockIdx.x % (kTileRows / kIThreads);
+  const int tid = threadIdx.x;
+  int* C = lc + tid;      // entry p at C[p * kIThreads]
+  double* Wt = lw + tid;
+  for (int i = t.r0 + sub * kIThreads + tid; i < t.r1 && i < t.r0 + (sub + 1) * kIThreads; i += kIThreads) {
+    int* pci = pc + (size_t)i * PW;
+    double* pvi = pv + (size_t)i * PW;
+    for (int q = 0; q < PW; ++q) { pci[q] = -1; pvi[q] = 0.0; }
+    if (cf[i] == CF_C) { pci[0] = cidx[i]; pvi[0] = 1.0; continue; }
+    if (dir[i]) continue;
+    int n = 0;
+    bool full = false;
+    auto find = [&](int v) -> int {
+      for (int p = 0; p < n; ++p)
+        if (C[p * kIThreads] == v) return p;
+      return -1;
+    };
+    auto add = [&](int v) {
+      if (find(v) >= 0) return;
+      if (n >= kIChat) { full = true; return; }
+      C[n * kIThreads] = v;
+      Wt[n * kIThreads] = 0.0;
+      ++n;
+    };
+    const int e0 = rp[i], e1 = rp[i + 1];
+    double aii = 0.0;
+    for (int e = e0; e < e1; ++e) {
+      const int j = ci[e];
+      if (j == i) { aii = a[e]; continue; }
+      if (strong[e] && cf[j] == CF_C) add(j);
     }
-  }
-  if (!ok) atomicAdd(redo, 1);
-  if (S.n == 0) return;
-  double dd = aii;
-  for (int e = e0; e < e1; ++e) {
-    const int j = ci[e];
-    if (j == i) continue;
-    const double aij = a[e];
-    if (aij == 0.0) continue;
-    const int p = S.find(j);
-    if (p >= 0) { S.addw(p, aij); continue; }
-    if (strong[e] && cf[j] == CF_F) {
-      const int k = j;
-      const bool kpos = dinv[k] >= 0.0;
-      double den = 0.0;
+    for (int e = e0; e < e1; ++e) {
+      const int k = ci[e];
+      if (k == i || !strong[e] || cf[k] != CF_F) continue;
       for (int e2 = rp[k]; e2 < rp[k + 1]; ++e2) {
         const int l = ci[e2];
-        if (l == k) continue;
-        const double akl = a[e2];
-        const double abar = kpos ? (akl < 0.0 ? akl : 0.0) : (akl > 0.0 ? akl : 0.0);
-        if (abar != 0.0 && (l == i || S.find(l) >= 0)) den += abar;
+        if (strong[e2] && cf[l] == CF_C) add(l);
       }
-      if (den == 0.0) { dd += aij; continue; }
-      for (int e2 = rp[k]; e2 < rp[k + 1]; ++e2) {
-        const int l = ci[e2];
-        if (l == k) continue;
-        const double akl = a[e2];
-        const double abar = kpos ? (akl < 0.0 ? akl : 0.0) : (akl > 0.0 ? akl : 0.0);
-        if (abar == 0.0) continue;
-        if (l == i) { dd += aij * abar / den; continue; }
-        const int p2 = S.find(l);
-        if (p2 >= 0) S.addw(p2, aij * abar / den);
-      }
-      continue;
     }
-    if (dir[j]) continue;
-    dd += aij;
-  }
-  if (dd == 0.0) return;
-  double total = 0.0;
-#pragma unroll
-  for (int p = 0; p < kFastChat; ++p)
-    if (p < S.n) { S.w[p] = -S.w[p] / dd; total += S.w[p]; }
-  // the PW largest |w| (lowest position first on ties)
-  int kp[PW];
-  double kw[PW];
-  int kc[PW];
-  uint32_t used = 0u;
-  int nk = 0;
-#pragma unroll
-  for (int q = 0; q < PW; ++q) {
-    int best = -1;
-    double bw = 0.0, bv = 0.0;
-    int bc = -1;
-#pragma unroll
-    for (int p = 0; p < kFastChat; ++p) {
-      const bool cand = p < S.n && !((used >> p) & 1u) && fabs(S.w[p]) > bw;
-      if (cand) { best = p; bw = fabs(S.w[p]); bv = S.w[p]; bc = S.c[p]; }
-    }
-    kp[q] = best;
-    kw[q] = bv;
-    kc[q] = bc;
-    if (best >= 0) { used |= 1u << best; ++nk; }
-  }
-  double kept = 0.0;
-#pragma unroll
-  for (int q = 0; q < PW; ++q)
-    if (q < nk) kept += kw[q];
-  const double sc = (kept != 0.0) ? total / kept : 1.0;
-  int cc[PW];
-#pragma unroll
-  for (int q = 0; q < PW; ++q) cc[q] = (q < nk) ? cidx[kc[q]] : INT_MAX;
-  // sort the kept entries by coarse column (at most PW, unrolled)
-#pragma unroll
-  for (int u = 0; u < PW; ++u)
-#pragma unroll
-    for (int v = 0; v + 1 < PW - u; ++v)
-      if (cc[v] > cc[v + 1]) {
-        int tc = cc[v]; cc[v] = cc[v + 1]; cc[v + 1] = tc;
-        double tw = kw[v]; kw[v] = kw[v + 1]; kw[v + 1] = tw;
+    if (full) atomicAdd(capped, 1);
+    if (n == 0) continue;
+    double dd = aii;
+    for (int e = e0; e < e1; ++e) {
+      const int j = ci[e];
+      if (j == i) continue;
+      const double aij = a[e];
+      if (aij == 0.0) continue;
+      const int p = find(j);
+      if (p >= 0) { Wt[p * kIThreads] += aij; continue; }
+      if (strong[e] && cf[j] == CF_F) {
+        // distribute a_ij over the kept set through row k = j
+        const int k = j;
+        const bool kpos = dinv[k] >= 0.0;
+        double den = 0.0;
+        for (int e2 = rp[k]; e2 < rp[k + 1]; ++e2) {
+          const int l = ci[e2];
+          if (l == k) continue;
+          const double akl = a[e2];
+          const double abar = kpos ? (akl < 0.0 ? akl : 0.0) : (akl > 0.0 ? akl : 0.0);
+          if (abar != 0.0 && (l == i || find(l) >= 0)) den += abar;
+        }
+        if (den == 0.0) { dd += aij; continue; }
+        for (int e2 = rp[k]; e2 < rp[k + 1]; ++e2) {
+          const int l = ci[e2];
+          if (l == k) continue;
+          const double akl = a[e2];
+          const double abar = kpos ? (akl < 0.0 ? akl : 0.0) : (akl > 0.0 ? akl : 0.0);
+          if (abar == 0.0) continue;
+          if (l == i) { dd += aij * abar / den; continue; }
+          const int p2 = find(l);
+          if (p2 >= 0) Wt[p2 * kIThreads] += aij * abar / den;
+        }
+        continue;
       }
-#pragma unroll
-  for (int q = 0; q < PW; ++q)
-    if (q < nk) { pci[q] = cc[q]; pvi[q] = kw[q] * sc; }
-  (void)kp;
+      if (dir[j]) continue;  // Dirichlet neighbour: its error vanishes after relaxation
+      dd += aij;             // weak connection: lumped into the diagonal
+    }
+    if (dd == 0.0) continue;
+    double total = 0.0;
+    for (int p = 0; p < n; ++p) {
+      const double w = -Wt[p * kIThreads] / dd;
+      Wt[p * kIThreads] = w;
+      total += w;
+    }
+    // the PW largest |w| (lowest position first on ties)
+    int kc[PW];
+    double kw[PW];
+    int nk = 0;
+    uint32_t used = 0u;
+    for (int q = 0; q < PW; ++q) {
+      int best = -1;
+      double bw = 0.0;
+      for (int p = 0; p < n; ++p) {
+        const double aw = fabs(Wt[p * kIThreads]);
+        if (!((used >> p) & 1u) && aw > bw) { best = p; bw = aw; }
+      }
+      if (best < 0) break;
+      used |= 1u << best;
+      kc[q] = cidx[C[best * kIThreads]];
+      kw[q] = Wt[best * kIThreads];
+      ++nk;
+    }
+    double kept = 0.0;
+    for (int q = 0; q < nk; ++q) kept += kw[q];
+    const double sc = (kept != 0.0) ? total / kept : 1.0;
+    // insertion sort of the kept entries by coarse column
+    for (int u = 1; u < nk; ++u) {
+      const int c0 = kc[u];
+      const double w0 = kw[u];
+      int v = u - 1;
+      while (v >= 0 && kc[v] > c0) { kc[v + 1] = kc[v]; kw[v + 1] = kw[v]; --v; }
+      kc[v + 1] = c0;
+      kw[v + 1] = w0;
+    }
+    for (int q = 0; q < nk; ++q) { pci[q] = kc[q]; pvi[q] = kw[q] * sc; }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -930,8 +912,8 @@ void amg_interp(const Tile* t, int nt, const int* rp, const int* ci, const doubl
                 const uint8_t* strong, const int8_t* cf, const int* cidx, const uint8_t* dir, int* pc,
                 double* pv, int* capped, hipStream_t s) {
   if (!nt) return;
-  hipLaunchKernelGGL(k_interp_fast, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, a, dinv, strong, cf, cidx,
-                     dir, pc, pv, capped);
+  hipLaunchKernelGGL(k_interp_lds, dim3(nt * (kTileRows / kIThreads)), dim3(kIThreads), 0, s, t, rp, ci, a,
+                     dinv, strong, cf, cidx, dir, pc, pv, capped);
   SHP_LAUNCH_CHECK();
 }
 void amg_pt_count(const Tile* t, int nt, const int* pc, int* cnt, hipStream_t s) {

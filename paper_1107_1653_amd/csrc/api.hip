@@ -205,6 +205,9 @@ static void fill_stats(const SlotState& S, shapley_stats* st, double seconds) {
   st->op_complexity = S.opc;
   st->grid_complexity = S.gc;
   std::memcpy(st->inner_per_outer, S.inner_per_outer, sizeof(st->inner_per_outer));
+  st->setups_full = S.setups_full;
+  st->setups_refresh = S.setups_refresh;
+  st->value_steps = S.solves;
 }
 
 // AMGpi on one game (the value step and improvement of every iteration run
@@ -329,7 +332,7 @@ int shapley_solve(shapley_game_t gh, const shapley_solve_opts* op, shapley_stats
       // FAMGpi (Algorithm algo-FAMGPI): coarse -> fine with eps_l = c h_l^2,
       // transfers of (v, alpha, beta) by I and U between consecutive levels.
       const int L = (int)g->levels.size();
-      int outer = 0, inner = 0, cycles = 0;
+      int outer = 0, inner = 0, cycles = 0, sfull = 0, sref = 0, vsteps = 0;
       double su = 0, cy = 0, im = 0;
       for (int l = 0; l < L; ++l) {
         Game* lg = g->levels[l];
@@ -342,6 +345,7 @@ int shapley_solve(shapley_game_t gh, const shapley_solve_opts* op, shapley_stats
         }
         int stt = run_amgpi(lg, o, eps, l == 0, s, S);
         outer += S.k; inner += S.inner_total; cycles += S.cycles_total;
+        sfull += S.setups_full; sref += S.setups_refresh; vsteps += S.solves;
         su += S.setup_s; cy += S.cycle_s; im += S.improve_s;
         if (stt != SHAPLEY_OK && stt != SHAPLEY_ENOCONV) { status = stt; break; }
         if (last) status = stt;
@@ -352,6 +356,7 @@ int shapley_solve(shapley_game_t gh, const shapley_solve_opts* op, shapley_stats
         st->fmg_levels = L;
         st->outer = outer; st->inner_total = inner; st->cycles_total = cycles;
         st->setup_seconds = su; st->cycle_seconds = cy; st->improve_seconds = im;
+        st->setups_full = sfull; st->setups_refresh = sref; st->value_steps = vsteps;
       }
     } else {
       status = run_amgpi(g->finest(), o, o.eps, true, s, S);

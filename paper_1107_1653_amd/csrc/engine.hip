@@ -219,6 +219,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
   }
   s_err.ensure(4);
   s_left.ensure(1);
+  SHP_HIP(hipMemsetAsync(s_err.p, 0, sizeof(int) * 4, stream));
   PhaseTimer pt(this, prof);
   nlev = 0;
   int l = 0;
@@ -271,10 +272,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
       // transpose of the strength pattern
       L.st_rp.ensure(n + 1);
       scan_exclusive(L.lam.p, L.st_rp.p, n + 1, stream, s_scan);
-      int st_nnz = 0;
-      d2h(&st_nnz, L.st_rp.p + n, 1, stream);
-      SHP_HIP(hipStreamSynchronize(stream));
-      L.st_ci.ensure(std::max(st_nnz, 1));
+      L.st_ci.ensure(std::max(L.nnz, 1));  // strong entries never exceed the entries of A
       s_cursor.ensure(n + 1);
       SHP_HIP(hipMemsetAsync(s_cursor.p, 0, sizeof(int) * (n + 1), stream));
       amg_strength_t(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.strong.p, L.st_rp.p, s_cursor.p, L.st_ci.p,
@@ -286,17 +284,21 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
       uint32_t salt = mix32(0x9E3779B9u * (uint32_t)(l + 1) + 12345u);
       amg_pmis_init(L.ctiles.p, L.nctiles, s_goff.p, L.dir.p, L.lam.p, salt, L.cf.p, L.key.p, stream);
       s_newc.ensure(std::max(n, 1));
-      for (int round = 0; round < 1000; ++round) {
-        amg_pmis_select(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.strong.p, L.st_rp.p, L.st_ci.p, L.cf.p,
-                        L.key.p, s_newc.p, stream);
-        SHP_HIP(hipMemsetAsync(s_left.p, 0, sizeof(int), stream));
-        amg_pmis_update(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.strong.p, L.cf.p, s_newc.p, s_left.p,
-                        stream);
+      // rounds run in pairs between checks of the undecided count (a round
+      // with nothing undecided changes nothing)
+      for (int round = 0; round < 1000; round += 2) {
+        for (int rr = 0; rr < 2; ++rr) {
+          amg_pmis_select(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.strong.p, L.st_rp.p, L.st_ci.p, L.cf.p,
+                          L.key.p, s_newc.p, stream);
+          SHP_HIP(hipMemsetAsync(s_left.p, 0, sizeof(int), stream));
+          amg_pmis_update(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.strong.p, L.cf.p, s_newc.p, s_left.p,
+                          stream);
+        }
         int left = 0;
         d2h(&left, s_left.p, 1, stream);
         SHP_HIP(hipStreamSynchronize(stream));
         if (left == 0) break;
-        if (round == 999) throw Error(SHAPLEY_EDEVICE, "PMIS did not terminate");
+        if (round >= 998) throw Error(SHAPLEY_EDEVICE, "PMIS did not terminate");
       }
       pt.mark("pmis");
       // ---- coarse numbering and per-game coarse sizes
@@ -349,8 +351,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         // ---- interpolation
         L.pc.ensure((size_t)std::max(n, 1) * PW);
         L.pv64.ensure((size_t)std::max(n, 1) * PW);
-        SHP_HIP(hipMemsetAsync(s_err.p, 0, sizeof(int) * 4, stream));
-        // s_err[0]: interpolatory sets truncated, [1]: Galerkin hash overflow, [2]: singular block
+        // s_err[0]: interpolatory sets truncated, [1]: Galerkin product flags, [2]: singular block
         probe_begin(kProbeInterp, stream);
         amg_interp(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, L.dinv64.p, L.strong.p, L.cf.p,
                    L.cidx.p, L.dir.p, L.pc.p, L.pv64.p, s_err.p, stream);
@@ -369,9 +370,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         amg_pt_count(L.ctiles.p, L.nctiles, L.pc.p, s_cnt.p, stream);
         L.rrp.ensure(nc + 1);
         scan_exclusive(s_cnt.p, L.rrp.p, nc + 1, stream, s_scan);
-        int rnnz = 0;
-        d2h(&rnnz, L.rrp.p + nc, 1, stream);
-        SHP_HIP(hipStreamSynchronize(stream));
+        const int rnnz = n * PW;  // upper bound of the entries of P^T
         L.rci.ensure(std::max(rnnz, 1));
         L.rv64.ensure(std::max(rnnz, 1));
         s_cursor.ensure(nc + 1);
@@ -402,16 +401,12 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
           L.rv32.ensure(std::max(rnnz, 1));
           amg_cast(L.rv64.p, L.rv32.p, rnnz, stream);
         }
-        int herr[4] = {0, 0, 0, 0};
-        d2h(herr, s_err.p, 4, stream);
-        SHP_HIP(hipStreamSynchronize(stream));
         pt.mark("rap");
-        if (herr[1] != 0)
-          throw Error(SHAPLEY_EDEVICE, "Galerkin product: coarse row too long (code " + std::to_string(herr[1]) + ")");
       }
     }
     // ---- dense inverses of the games that end at this level
-    std::vector<int> hblk;
+    std::vector<int>& hblk = L.h_blk;  // kept alive for the asynchronous upload
+    hblk.clear();
     size_t doff = 0;
     L.max_blk = 0;
     for (int g = 0; g < G; ++g) {
@@ -431,13 +426,8 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
       if (mixed) L.dmat32.ensure(doff);
       const bool large = L.max_blk > kDenseWave;
       if (large) s_dense.ensure(2 * doff);
-      SHP_HIP(hipMemsetAsync(s_err.p, 0, sizeof(int) * 4, stream));
       amg_dense_inv(L.blk.p, L.nblk, L.rp.p, L.ci.p, L.a64.p, s_dense.p, L.dmat64.p,
                     mixed ? L.dmat32.p : nullptr, s_err.p + 2, large, stream);
-      int herr[4] = {0, 0, 0, 0};
-      d2h(herr, s_err.p, 4, stream);
-      SHP_HIP(hipStreamSynchronize(stream));
-      if (herr[2] != 0) throw Error(SHAPLEY_EDEVICE, "singular coarsest block");
       pt.mark("dense");
     }
     // cycle vectors
@@ -461,6 +451,14 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
       break;
     }
     ++l;
+  }
+  {
+    int herr[4] = {0, 0, 0, 0};
+    d2h(herr, s_err.p, 4, stream);
+    SHP_HIP(hipStreamSynchronize(stream));
+    if (herr[1] != 0)
+      throw Error(SHAPLEY_EDEVICE, "Galerkin product: coarse row too long (code " + std::to_string(herr[1]) + ")");
+    if (herr[2] != 0) throw Error(SHAPLEY_EDEVICE, "singular coarsest block");
   }
   // statistics
   double nnz_sum = 0, n_sum = 0;
@@ -621,8 +619,9 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
         stop = true;
       } else if (cyc[g] >= o.max_cycles) {
         stop = true;
-      } else if (h.size() >= 5 && rn > 0.5 * h[h.size() - 4]) {
-        stop = true;  // stagnation: no halving over three cycles
+      } else if (h.size() >= 8 && rn > 0.5 * h[h.size() - 7]) {
+        stop = true;  // stagnation: no halving over six cycles
+        stagnated = true;
       }
       if (stop) h_lin_active[g] = 0; else any = true;
     }
@@ -715,9 +714,13 @@ int Engine::step() {
   PhaseTimer pt(this, prof);
   assemble(run, mixed);
   pt.mark("assemble");
-  bool full = !have_hier || run != run_at_setup || o.reuse_frac <= 0.0 ||
+  bool full = !have_hier || stagnated || run != run_at_setup || o.reuse_frac <= 0.0 ||
               (double)changes_since_setup > o.reuse_frac * std::max(1, N0) ||
               last_cycles > std::max(2 * cycles_after_full, cycles_after_full + 6);
+  stagnated = false;
+  for (int g : run) {
+    if (full) ++slots[g]->setups_full; else ++slots[g]->setups_refresh;
+  }
   if (full) {
     setup(run, o);
     have_hier = true;
@@ -779,8 +782,8 @@ int Engine::step() {
       continue;
     }
     if (S->opt.verbose)
-      fprintf(stderr, "[shapley] slot %d k %d nk %d res %.3e in %d out %d levels %d cycles %d\n", g, S->k,
-              S->nk, S->res, nin, nout, S->levels, S->cycles_total);
+      fprintf(stderr, "[shapley] slot %d k %d nk %d res %.3e in %d out %d levels %d cycles %d %s\n", g, S->k,
+              S->nk, S->res, nin, nout, S->levels, S->cycles_total, full ? "full" : "refresh");
     if (S->res <= S->opt.eps) {
       if (S->k <= 64) S->inner_per_outer[S->k - 1] = S->nk;
       code[g] = 2;
@@ -789,12 +792,15 @@ int Engine::step() {
     } else if (nin > 0 && S->nk < S->opt.max_inner) {
       code[g] = 1;
       changes_since_setup += nin;
-    } else if (S->loose) {
-      // policies look stable after an inexact solve: solve the same system
-      // to full accuracy before deciding
-      S->res_prev = 0.0;
+      S->resolves = 0;
+    } else if (nout == 0 && S->loose && S->resolves < 2) {
+      // both policies look stable after an inexact solve: solve the same
+      // system again, to forcing * eps (or to full accuracy when eps = 0),
+      // before stopping (at most twice in a row)
+      S->res_prev = S->opt.eps;
       S->nk -= 1;
       S->inner_total -= 1;
+      S->resolves += 1;
     } else {
       if (S->k <= 64) S->inner_per_outer[S->k - 1] = S->nk;
       if (nout == 0) {
@@ -808,6 +814,7 @@ int Engine::step() {
         S->k += 1;
         S->nk = 0;
         changes_since_setup += nout;
+        S->resolves = 0;
       }
     }
     if (!S->done) ++still;

@@ -83,6 +83,7 @@ struct Level {
   int nctiles = 0;
   int rows_tiles = 0, rows_ctiles = 0;  // rows covered by tiles / ctiles
   std::vector<Tile> h_tiles, h_ctiles;  // host copies (kept alive for async uploads)
+  std::vector<int> h_blk;
   // transfer to the next level (continuing slots)
   int nc = 0;
   DBuf<int> pc;                   // [n*PW], -1 = empty
@@ -138,7 +139,9 @@ struct SlotState {
   double res = 0.0, res_l2 = 0.0;
   double res_prev = INFINITY;   // Shapley residual after the previous value step
   bool loose = false;           // the last linear solve used the forcing tolerance
+  int resolves = 0;             // consecutive accuracy re-solves at stable policies
   int solves = 0;               // value steps performed (including accuracy re-solves)
+  int setups_full = 0, setups_refresh = 0;
   double setup_s = 0, cycle_s = 0, improve_s = 0;
   int levels = 0;
   double opc = 0, gc = 0;
@@ -197,6 +200,7 @@ class Engine {
   std::vector<int> run_at_setup;
   int64_t changes_since_setup = 0;
   int last_cycles = 0, cycles_after_full = -1;
+  bool stagnated = false;  // a linear solve stalled: rebuild the hierarchy
  public:
   int full_setups = 0, refreshes = 0;
  private:

@@ -69,6 +69,7 @@ class shapley_stats(C.Structure):
         ("setup_seconds", C.c_double), ("cycle_seconds", C.c_double), ("improve_seconds", C.c_double),
         ("op_complexity", C.c_double), ("grid_complexity", C.c_double),
         ("inner_per_outer", C.c_int32 * 64),
+        ("setups_full", C.c_int32), ("setups_refresh", C.c_int32), ("value_steps", C.c_int32),
     ]
 
     def as_dict(self) -> dict:
