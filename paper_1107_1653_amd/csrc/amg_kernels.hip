@@ -384,7 +384,7 @@ __global__ __launch_bounds__(kRapThreads) void k_rap(int nc, const int* __restri
                                                      const double* __restrict__ pv,
                                                      const int* __restrict__ crp, int* __restrict__ ccnt,
                                                      int* __restrict__ cci, double* __restrict__ cval,
-                                                     int* __restrict__ err) {
+                                                     int* __restrict__ err, const uint8_t* __restrict__ only) {
   __shared__ int rS[kRapRCap];
   __shared__ int rO[kRapRCap + 1];
   __shared__ double rV[kRapRCap];
@@ -398,6 +398,7 @@ __global__ __launch_bounds__(kRapThreads) void k_rap(int nc, const int* __restri
   const int I = blockIdx.x;
   const int tid = threadIdx.x;
   if (I >= nc) return;
+  if (only && !only[I]) return;  // incremental refresh: row unchanged
   const int p0 = rrp[I], P = rrp[I + 1] - p0;
   if (P > kRapRCap) {
     if (tid == 0) {
@@ -519,6 +520,49 @@ __global__ __launch_bounds__(kRapThreads) void k_rap(int nc, const int* __restri
 }
 
 // ---------------------------------------------------------------------------
+// incremental refresh: rows of level 0 whose values changed since the last
+// setup (the copy is updated in place), and the coarse rows they reach
+// through P (A_c row I depends on fine row i only when P[i, I] != 0).
+// ---------------------------------------------------------------------------
+__global__ void k_row_changed(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                              const double* __restrict__ a, double* __restrict__ prev,
+                              uint8_t* __restrict__ chg) {
+  Tile t = tiles[blockIdx.x];
+  int i = t.r0 + threadIdx.x;
+  if (i >= t.r1) return;
+  uint8_t c = 0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const double v = a[e];
+    if (v != prev[e]) { c = 1; prev[e] = v; }
+  }
+  chg[i] = c;
+}
+
+__global__ void k_mark_coarse(const Tile* __restrict__ tiles, const int* __restrict__ pc,
+                              const uint8_t* __restrict__ chg, uint8_t* __restrict__ cmark) {
+  Tile t = tiles[blockIdx.x];
+  int i = t.r0 + threadIdx.x;
+  if (i >= t.r1 || !chg[i]) return;
+  for (int q = 0; q < PW; ++q) {
+    const int c = pc[(size_t)i * PW + q];
+    if (c >= 0) cmark[c] = 1;
+  }
+}
+
+void amg_row_changed(const Tile* t, int nt, const int* rp, const double* a, double* prev, uint8_t* chg,
+                     hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_row_changed, dim3(nt), dim3(kTileRows), 0, s, t, rp, a, prev, chg);
+  SHP_LAUNCH_CHECK();
+}
+
+void amg_mark_coarse(const Tile* t, int nt, const int* pc, const uint8_t* chg, uint8_t* cmark, hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_mark_coarse, dim3(nt), dim3(kTileRows), 0, s, t, pc, chg, cmark);
+  SHP_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
 // level helpers
 // ---------------------------------------------------------------------------
 __global__ void k_diag_inv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
@@ -633,7 +677,8 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_inv_wave(const int* __r
                                                                   const double* __restrict__ a,
                                                                   double* __restrict__ inv64,
                                                                   float* __restrict__ inv32,
-                                                                  int* __restrict__ err) {
+                                                                  int* __restrict__ err,
+                                                                  const uint8_t* __restrict__ only) {
   __shared__ double M[kDenseWave * (kDenseWave + 1)];
   __shared__ double colk[kDenseWave];
   __shared__ double rowk[kDenseWave];
@@ -644,6 +689,11 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_inv_wave(const int* __r
   const size_t doff = (size_t)blk[4 * blockIdx.x + 2];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   if (nb > kDenseWave) return;  // handled by the general kernel
+  if (only) {  // incremental refresh: skip blocks none of whose rows changed
+    int any = 0;
+    for (int i = tid; i < nb; i += kDenseThreads) any |= only[row0 + i];
+    if (!__syncthreads_or(any)) return;
+  }
   const int ld = nb | 1;
   for (int idx = tid; idx < nb * ld; idx += kDenseThreads) M[idx] = 0.0;
   __syncthreads();
@@ -934,10 +984,10 @@ void amg_sort_rows(const int* rp, int* ci, double* v, int n, hipStream_t s) {
 }
 void amg_rap(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,
              const double* a, const int* pc, const double* pv, const int* crp, int* ccnt, int* cci,
-             double* cval, int* err, hipStream_t s) {
+             double* cval, int* err, hipStream_t s, const uint8_t* only) {
   if (!nc) return;
   hipLaunchKernelGGL(k_rap, dim3(nc), dim3(kRapThreads), 0, s, nc, rrp, rci, rv, rp, ci, a, pc, pv, crp, ccnt,
-                     cci, cval, err);
+                     cci, cval, err, only);
   SHP_LAUNCH_CHECK();
 }
 void amg_diag_inv(int n, const int* rp, const int* ci, const double* a, double* d64, float* d32,
@@ -952,9 +1002,10 @@ void amg_cast(const double* in, float* out, size_t n, hipStream_t s) {
   SHP_LAUNCH_CHECK();
 }
 void amg_dense_inv(const int* blk, int nblk, const int* rp, const int* ci, const double* a, double* work,
-                   double* inv64, float* inv32, int* err, bool large, hipStream_t s) {
+                   double* inv64, float* inv32, int* err, bool large, hipStream_t s, const uint8_t* only) {
   if (!nblk) return;
-  hipLaunchKernelGGL(k_dense_inv_wave, dim3(nblk), dim3(kDenseThreads), 0, s, blk, rp, ci, a, inv64, inv32, err);
+  hipLaunchKernelGGL(k_dense_inv_wave, dim3(nblk), dim3(kDenseThreads), 0, s, blk, rp, ci, a, inv64, inv32, err,
+                     only);
   SHP_LAUNCH_CHECK();
   if (large) {
     hipLaunchKernelGGL(k_dense_inv, dim3(nblk), dim3(256), 0, s, blk, rp, ci, a, work, inv64, inv32, err);

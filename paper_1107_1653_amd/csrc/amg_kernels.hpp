@@ -32,12 +32,16 @@ void amg_pt_fill(const Tile* t, int nt, const int* pc, const double* pv, const i
 void amg_sort_rows(const int* rp, int* ci, double* v, int n, hipStream_t s);
 void amg_rap(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,
              const double* a, const int* pc, const double* pv, const int* crp, int* ccnt, int* cci,
-             double* cval, int* err, hipStream_t s);
+             double* cval, int* err, hipStream_t s, const uint8_t* only = nullptr);
 void amg_diag_inv(int n, const int* rp, const int* ci, const double* a, double* d64, float* d32,
                   hipStream_t s);
 void amg_cast(const double* in, float* out, size_t n, hipStream_t s);
 void amg_dense_inv(const int* blk, int nblk, const int* rp, const int* ci, const double* a, double* work,
-                   double* inv64, float* inv32, int* err, bool large, hipStream_t s);
+                   double* inv64, float* inv32, int* err, bool large, hipStream_t s,
+                   const uint8_t* only = nullptr);
+void amg_row_changed(const Tile* t, int nt, const int* rp, const double* a, double* prev, uint8_t* chg,
+                     hipStream_t s);
+void amg_mark_coarse(const Tile* t, int nt, const int* pc, const uint8_t* chg, uint8_t* cmark, hipStream_t s);
 
 template <class T>
 void cyc_smooth(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const T* a,

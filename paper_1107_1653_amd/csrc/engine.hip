@@ -479,6 +479,11 @@ void Engine::refresh(const EngineOpts& o) {
   const bool mixed = o.precision == SHAPLEY_MIXED;
   PhaseTimer pt(this, prof);
   SHP_HIP(hipMemsetAsync(s_err.p, 0, sizeof(int) * 4, stream));
+  {
+    Level& L0 = lv[0];
+    L0.chg.ensure(std::max(L0.n, 1));
+    amg_row_changed(L0.tiles.p, L0.ntiles, L0.rp.p, L0.a64.p, L0.a_prev.p, L0.chg.p, stream);
+  }
   for (int l = 0; l < nlev; ++l) {
     Level& L = lv[l];
     const int n = L.n;
@@ -491,14 +496,17 @@ void Engine::refresh(const EngineOpts& o) {
       amg_dir_scale(L.ctiles.p, L.nctiles, L.dir.p, 1.0 / o.omega, L.dinv64.p, mixed ? L.dinv32.p : nullptr,
                     stream);
       Level& Ln = lv[l + 1];
+      Ln.chg.ensure(std::max(L.nc, 1));
+      SHP_HIP(hipMemsetAsync(Ln.chg.p, 0, std::max(L.nc, 1), stream));
+      amg_mark_coarse(L.ctiles.p, L.nctiles, L.pc.p, L.chg.p, Ln.chg.p, stream);
       probe_begin(kProbeRap, stream);
       amg_rap(L.nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, Ln.rp.p, nullptr,
-              Ln.ci.p, Ln.a64.p, s_err.p + 1, stream);
+              Ln.ci.p, Ln.a64.p, s_err.p + 1, stream, Ln.chg.p);
       probe_end(kProbeRap, stream, (double)Ln.nnz * 12 + (double)L.nnz * 12 + (double)n * PW * 12);
     }
     if (L.nblk)
       amg_dense_inv(L.blk.p, L.nblk, L.rp.p, L.ci.p, L.a64.p, s_dense.p, L.dmat64.p, mixed ? L.dmat32.p : nullptr,
-                    s_err.p + 2, L.max_blk > kDenseWave, stream);
+                    s_err.p + 2, L.max_blk > kDenseWave, stream, L.chg.p);
   }
   int herr[4] = {0, 0, 0, 0};
   d2h(herr, s_err.p, 4, stream);
@@ -723,6 +731,8 @@ int Engine::step() {
   }
   if (full) {
     setup(run, o);
+    lv[0].a_prev.ensure(std::max(NNZ0, 1));
+    d2d(lv[0].a_prev.p, lv[0].a64.p, NNZ0, stream);
     have_hier = true;
     run_at_setup = run;
     changes_since_setup = 0;

@@ -107,6 +107,8 @@ struct Level {
   DBuf<uint8_t> dir;              // Dirichlet (no off-diagonal) rows
   DBuf<int> lam, cidx, tmp;
   DBuf<uint64_t> key;
+  DBuf<uint8_t> chg;              // rows changed since the last setup (incremental refresh)
+  DBuf<double> a_prev;            // level 0: values the hierarchy was last built from
 };
 
 struct EngineOpts {
