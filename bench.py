@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "unknowns solved/s to 1e-8 Shapley residual, FP64 vs mixed; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+CALIB_BYTES = 1 << 30  # bytes read (and written) by the calibration kernel
 
 
 def log(*a):
@@ -86,6 +87,9 @@ def parse_args():
     ap.add_argument("--games", type=int, default=256, help="C3 batch size")
     ap.add_argument("--requests", type=int, default=100, help="C4 requests")
     ap.add_argument("--side", type=int, default=129, help="C2 interior points per side")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one elementwise kernel of known traffic (reads and writes "
+                         f"{CALIB_BYTES >> 20} MiB): the reference for hardware byte counters")
     return ap.parse_args()
 
 
@@ -103,11 +107,25 @@ def base_record(args, value, ms_per_step, dtype, config):
             "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
 
 
+def calibration_kernel():
+    """torch.neg over CALIB_BYTES of float32: one kernel that reads and writes
+    exactly CALIB_BYTES each (counter runs scale by what it reads)."""
+    import torch
+    x = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    del x, y
+
+
 def run_c1(args) -> int:
 
     import torch  # device synchronisation around the timed region only
     import paper_1107_1653_amd as P
     from shapley_inputs import configs
+    if args.calibrate_copy:
+        calibration_kernel()
 
     t0 = time.perf_counter()
     levels = configs.c1_levels(points=args.points, coarsest_points=33)

@@ -10,7 +10,9 @@ What it computes (Akian & Detournay, arXiv:1107.1653):
   * the value of a pair of pure stationary policies (alpha, beta), i.e. the
     solution of the linear system v = mu M^{alpha beta} v + r^{alpha beta}
     (Sec. 4.2, eq. (LSPI)), here with a sparse direct LU (SciPy SuperLU)
-    plus one FP64 refinement step;
+    plus one FP64 refinement step, or -- for 3-D grids of millions of states,
+    where the LU fill does not fit in memory -- BiCGSTAB with FP64 residual
+    re-checks (a reading; the fixed point is the same);
   * Hoffman-Karp / Puri policy iteration (Sec. 4.2, Algorithm PIalgo) whose
     inner loop is Howard's policy iteration for the MIN player (Sec. 4.1,
     Algorithm algo-MDP), stopped on the residual ||F(v) - v||_inf <= eps
@@ -122,13 +124,36 @@ def policy_system(g, alpha: np.ndarray, beta: np.ndarray, W=None):
     return A, b
 
 
-def evaluate_policies(g, alpha, beta, W=None) -> np.ndarray:
-    """Value of the pair (alpha, beta): sparse direct solve + one refinement."""
+def evaluate_policies(g, alpha, beta, W=None, solver: str = "direct",
+                      v_start: Optional[np.ndarray] = None) -> np.ndarray:
+    """Value of the pair (alpha, beta) (Sec. 4.2, eq. (LSPI)).
+
+    solver="direct": sparse LU + one refinement step.
+    solver="krylov": for systems whose LU fill does not fit in memory (3-D
+    grids of millions of states).  BiCGSTAB from `v_start` to a relative
+    residual of 1e-14, then FP64 residual re-checks with correction solves
+    until ||b - Av||_inf <= 1e-14 max(||b||_inf, ||v||_inf).  A reading, not
+    the paper's sparse direct solve; the fixed point it serves is the same.
+    """
     A, b = policy_system(g, alpha, beta, W)
-    lu = spla.splu(A.tocsc(), permc_spec="MMD_AT_PLUS_A")
-    v = lu.solve(b)
-    v += lu.solve(b - A @ v)
-    return v
+    if solver == "direct":
+        lu = spla.splu(A.tocsc(), permc_spec="MMD_AT_PLUS_A")
+        v = lu.solve(b)
+        v += lu.solve(b - A @ v)
+        return v
+    if solver != "krylov":
+        raise ValueError(f"unknown solver {solver!r}")
+    v = np.zeros(g.n) if v_start is None else np.asarray(v_start, dtype=np.float64).copy()
+    for _ in range(8):
+        r = b - A @ v
+        tol = 1e-14 * max(np.abs(b).max(initial=0.0), np.abs(v).max(initial=0.0))
+        if np.abs(r).max(initial=0.0) <= tol:
+            return v
+        # a breakdown (info < 0) still returns its last iterate; the FP64
+        # re-check above decides whether the correction was good enough
+        e, _ = spla.bicgstab(A, r, rtol=1e-14, atol=0.0, maxiter=20000)
+        v += e
+    raise RuntimeError("Krylov policy evaluation did not reach the FP64 residual bound")
 
 
 def _improve(g, Q, scale, alpha, beta):
@@ -171,7 +196,8 @@ def _improve(g, Q, scale, alpha, beta):
 
 def policy_iteration(g, alpha0=None, beta0=None, v0=None, eps: float = 0.0,
                      max_outer: int = 10000, max_inner: int = 10000,
-                     exact: Optional[np.ndarray] = None) -> OracleResult:
+                     exact: Optional[np.ndarray] = None,
+                     solver: str = "direct") -> OracleResult:
     """Hoffman-Karp / Puri policy iteration (Sec. 4.2, Algorithm PIalgo).
 
     The inner loop is Howard's algorithm for MIN at fixed alpha (Sec. 4.1,
@@ -206,7 +232,7 @@ def policy_iteration(g, alpha0=None, beta0=None, v0=None, eps: float = 0.0,
         while True:
             nk += 1
             inner_total += 1
-            v = evaluate_policies(g, alpha, beta, W)
+            v = evaluate_policies(g, alpha, beta, W, solver=solver, v_start=v)
             Q, scale = q_values(g, v, W)
             beta_in, F, alpha_out, beta_out = _improve(g, Q, scale, alpha, beta)
             res = float(np.max(np.abs(F - v))) if n else 0.0

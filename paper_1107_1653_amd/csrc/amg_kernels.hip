@@ -306,6 +306,360 @@ __global__ __launch_bounds__(kIThreads) void k_interp_lds(const Tile* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// extended+i interpolation, one wavefront per row (coarse levels, whose rows
+// are long).  Same formula as above without the set cap: the interpolatory
+// set (strong C neighbours and strong C neighbours of strong F neighbours)
+// is collected in an LDS hash and sorted; the sums run in fixed orders:
+//   * den_k (row k's same-sign entries towards the set and i): per k in row
+//     order, from pair terms staged in LDS;
+//   * the weight of a set member: direct entry first, then the distributed
+//     entries in the order of the F neighbours k in row i;
+//   * the lumped diagonal and the total: per lane, then a fixed tree.
+// A row with more than kIwK strong F neighbours or more than the hash holds
+// falls back to direct interpolation (its strong C neighbours only, strong F
+// neighbours lumped) and is counted in `capped`.
+// ---------------------------------------------------------------------------
+// HASH: slots for the interpolatory set of one row; KCAP: strong F
+// neighbours of one row; (k, entry) pairs are staged kIwStage at a time.
+constexpr int kIwStage = 256;
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <int kIwHash, int kIwK>
+__global__ __launch_bounds__(64) void k_interp_wave(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                                                    const int* __restrict__ ci, const double* __restrict__ a,
+                                                    const double* __restrict__ dinv,
+                                                    const uint8_t* __restrict__ strong,
+                                                    const int8_t* __restrict__ cf, const int* __restrict__ cidx,
+                                                    const uint8_t* __restrict__ dir, int* __restrict__ pc,
+                                                    double* __restrict__ pv, int* __restrict__ capped) {
+  __shared__ int hkey[kIwHash];
+  __shared__ int hpos[kIwHash];
+  __shared__ int mem[kIwHash];
+  __shared__ double W[kIwHash];
+  __shared__ int kcol[kIwK], kbeg[kIwK], koff[kIwK + 1];
+  __shared__ double kaik[kIwK], kden[kIwK], kabi[kIwK];
+  __shared__ uint8_t kneg[kIwK];
+  __shared__ int sq[kIwStage];
+  __shared__ double sc[kIwStage];
+  __shared__ int full_sh;
+
+  const Tile t = tiles[blockIdx.x / kTileRows];
+  const int i = t.r0 + (int)(blockIdx.x % kTileRows);
+  if (i >= t.r1) return;
+  const int lane = threadIdx.x;
+  if (lane < PW) {
+    pc[(size_t)i * PW + lane] = -1;
+    pv[(size_t)i * PW + lane] = 0.0;
+  }
+  const int8_t cfi = cf[i];
+  if (cfi == CF_C) {
+    if (lane == 0) { pc[(size_t)i * PW] = cidx[i]; pv[(size_t)i * PW] = 1.0; }
+    return;
+  }
+  if (dir[i]) return;
+  const int e0 = rp[i], len = rp[i + 1] - e0;
+  const unsigned hmask = kIwHash - 1;
+
+  auto insert = [&](int v) -> bool {
+    unsigned h = mix32((uint32_t)v) & hmask;
+    for (int pr = 0; pr < kIwHash; ++pr) {
+      const int old = atomicCAS(&hkey[h], -1, v);
+      if (old == -1 || old == v) return true;
+      h = (h + 1) & hmask;
+    }
+    return false;
+  };
+  auto lookup = [&](int v) -> int {
+    unsigned h = mix32((uint32_t)v) & hmask;
+    for (int pr = 0; pr < kIwHash; ++pr) {
+      const int k = hkey[h];
+      if (k == v) return hpos[h];
+      if (k == -1) return -1;
+      h = (h + 1) & hmask;
+    }
+    return -1;
+  };
+
+  bool direct = false;  // fallback: strong C neighbours only
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    for (int h = lane; h < kIwHash; h += 64) hkey[h] = -1;
+    if (lane == 0) full_sh = 0;
+    __syncthreads();
+    // ---- row i: strong C neighbours into the set, strong F neighbours listed in row order
+    int nK = 0;
+    bool bad = false;
+    for (int base = 0; base < len; base += 64) {
+      const bool in = base + lane < len;
+      const int e = e0 + base + lane;
+      int j = -1;
+      bool st = false;
+      double aij = 0.0;
+      if (in) { j = ci[e]; st = strong[e] != 0; aij = a[e]; }
+      const bool off = in && st && j != i;
+      const int8_t cj = off ? cf[j] : (int8_t)0;
+      if (off && cj == CF_C && !insert(j)) bad = true;
+      const bool isF = !direct && off && cj == CF_F;
+      const unsigned long long m = __ballot(isF);
+      const int pos = nK + __popcll(m & ((1ull << lane) - 1ull));
+      if (isF && pos < kIwK) { kcol[pos] = j; kaik[pos] = aij; }
+      nK += __popcll(m);
+    }
+    if (bad) atomicOr(&full_sh, 1);
+    if (nK > kIwK) atomicOr(&full_sh, 1);
+    __syncthreads();
+    if (full_sh) {
+      if (lane == 0) atomicAdd(capped, 1);
+      if (direct) return;  // even the direct set does not fit: no interpolation
+      direct = true;
+      __syncthreads();
+      continue;
+    }
+    // ---- rows of the strong F neighbours: offsets of their entries
+    int T = 0;
+    for (int base = 0; base < nK; base += 64) {
+      const int p = base + lane;
+      int ln = 0;
+      if (p < nK) {
+        const int k = kcol[p];
+        const int b = rp[k];
+        ln = rp[k + 1] - b;
+        kbeg[p] = b;
+        kneg[p] = dinv[k] < 0.0 ? 1 : 0;
+        kden[p] = 0.0;
+        kabi[p] = 0.0;
+      }
+      int v = ln;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(v, o);
+        if (lane >= o) v += y;
+      }
+      if (p < nK) koff[p + 1] = T + v;
+      T += __shfl(v, 63);
+    }
+    if (lane == 0) koff[0] = 0;
+    __syncthreads();
+    auto seg = [&](int f) {  // largest p with koff[p] <= f
+      int lo = 0, hi = nK - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (koff[mid] <= f) lo = mid; else hi = mid - 1;
+      }
+      return lo;
+    };
+    // ---- distance-two candidates
+    bad = false;
+    for (int f = lane; f < T; f += 64) {
+      const int p = seg(f);
+      const int e2 = kbeg[p] + (f - koff[p]);
+      const int l = ci[e2];
+      if (strong[e2] && l != kcol[p] && cf[l] == CF_C && !insert(l)) bad = true;
+    }
+    if (bad) atomicOr(&full_sh, 1);
+    __syncthreads();
+    if (full_sh) {
+      if (lane == 0) atomicAdd(capped, 1);
+      if (direct) return;
+      direct = true;
+      __syncthreads();
+      continue;
+    }
+    // ---- members: compact and sort by fine index
+    int m = 0;
+    for (int base = 0; base < kIwHash; base += 64) {
+      const int key = hkey[base + lane];
+      const unsigned long long bm = __ballot(key >= 0);
+      if (key >= 0) mem[m + __popcll(bm & ((1ull << lane) - 1ull))] = key;
+      m += __popcll(bm);
+    }
+    int P2 = 1;
+    while (P2 < m) P2 <<= 1;
+    for (int h = m + lane; h < P2; h += 64) mem[h] = INT_MAX;
+    __syncthreads();
+    for (int k2 = 2; k2 <= P2; k2 <<= 1) {
+      for (int jj = k2 >> 1; jj > 0; jj >>= 1) {
+        for (int idx = lane; idx < P2; idx += 64) {
+          const int ixj = idx ^ jj;
+          if (ixj > idx) {
+            const int x = mem[idx], y = mem[ixj];
+            const bool up = (idx & k2) == 0;
+            if ((x > y) == up) { mem[idx] = y; mem[ixj] = x; }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // position of each member in the sorted list, reachable through the hash
+    for (int q = lane; q < m; q += 64) {
+      const int v = mem[q];
+      unsigned h = mix32((uint32_t)v) & hmask;
+      while (hkey[h] != v) h = (h + 1) & hmask;
+      hpos[h] = q;
+      W[q] = 0.0;
+    }
+    __syncthreads();
+    // ---- den_k and abar_ki: terms of each pair staged, summed per k in row order
+    for (int c0 = 0; c0 < T; c0 += kIwStage) {
+      const int c1 = (T < c0 + kIwStage) ? T : c0 + kIwStage;
+      for (int f = c0 + lane; f < c1; f += 64) {
+        const int p = seg(f);
+        const int e2 = kbeg[p] + (f - koff[p]);
+        const int l = ci[e2];
+        const double akl = a[e2];
+        const double abar = kneg[p] ? (akl > 0.0 ? akl : 0.0) : (akl < 0.0 ? akl : 0.0);
+        double term = 0.0;
+        int q = -1;
+        if (l != kcol[p] && abar != 0.0) {
+          if (l == i) {
+            term = abar;
+            kabi[p] = abar;
+          } else {
+            q = lookup(l);
+            if (q >= 0) term = abar;
+          }
+        }
+        sc[f - c0] = term;
+        sq[f - c0] = q;
+      }
+      __syncthreads();
+      for (int p = lane; p < nK; p += 64) {
+        const int lo = koff[p] > c0 ? koff[p] : c0;
+        const int hi = koff[p + 1] < c1 ? koff[p + 1] : c1;
+        double d = kden[p];
+        for (int f = lo; f < hi; ++f) d += sc[f - c0];
+        kden[p] = d;
+      }
+      __syncthreads();
+    }
+    // ---- diagonal: a_ii, weak entries, parts of F neighbours sent back to i;
+    //      direct entries towards set members
+    double ddl = 0.0;
+    int rank = 0;
+    for (int base = 0; base < len; base += 64) {
+      const bool in = base + lane < len;
+      const int e = e0 + base + lane;
+      int j = -1;
+      bool st = false;
+      double aij = 0.0;
+      if (in) { j = ci[e]; st = strong[e] != 0; aij = a[e]; }
+      const bool off = in && j != i;
+      const int8_t cj = off ? cf[j] : (int8_t)0;
+      const bool isF = !direct && off && st && cj == CF_F;
+      const unsigned long long bm = __ballot(isF);
+      const int p = rank + __popcll(bm & ((1ull << lane) - 1ull));
+      rank += __popcll(bm);
+      if (in && j == i) ddl += aij;
+      if (!off || aij == 0.0) continue;
+      const int q = lookup(j);
+      if (q >= 0) { W[q] += aij; continue; }  // one entry per column: no conflicts
+      if (isF) {
+        const double den = kden[p];
+        ddl += den == 0.0 ? aij : aij * kabi[p] / den;
+        continue;
+      }
+      if (dir[j]) continue;
+      ddl += aij;
+    }
+    __syncthreads();
+    // ---- distributed entries: F neighbours in row order; each row k holds a
+    //      column at most once, so the lanes of one k never collide
+    for (int c0 = 0; c0 < T; c0 += kIwStage) {
+      const int c1 = (T < c0 + kIwStage) ? T : c0 + kIwStage;
+      for (int f = c0 + lane; f < c1; f += 64) {
+        const int p = seg(f);
+        const int e2 = kbeg[p] + (f - koff[p]);
+        const int l = ci[e2];
+        const double akl = a[e2];
+        const double abar = kneg[p] ? (akl > 0.0 ? akl : 0.0) : (akl < 0.0 ? akl : 0.0);
+        int q = -1;
+        double c = 0.0;
+        if (l != kcol[p] && l != i && abar != 0.0 && kden[p] != 0.0) {
+          q = lookup(l);
+          c = kaik[p] * abar / kden[p];
+        }
+        sq[f - c0] = q;
+        sc[f - c0] = c;
+      }
+      __syncthreads();
+      const int pa = seg(c0), pb = seg(c1 - 1);
+      for (int p = pa; p <= pb; ++p) {
+        const int lo = koff[p] > c0 ? koff[p] : c0;
+        const int hi = koff[p + 1] < c1 ? koff[p + 1] : c1;
+        for (int f = lo + lane; f < hi; f += 64) {
+          const int q = sq[f - c0];
+          if (q >= 0) W[q] += sc[f - c0];
+        }
+        __syncthreads();
+      }
+    }
+    const double dd = wave_sum(ddl);
+    if (dd == 0.0 || m == 0) return;
+    // ---- weights, their total, the PW largest (lowest column on ties)
+    double tl = 0.0;
+    for (int q = lane; q < m; q += 64) {
+      const double w = -W[q] / dd;
+      W[q] = w;
+      tl += w;
+    }
+    const double total = wave_sum(tl);
+    int kq[PW];
+    double kw[PW];
+    int nk = 0;
+#pragma unroll
+    for (int r = 0; r < PW; ++r) {
+      kq[r] = INT_MAX;
+      kw[r] = 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < PW; ++r) {
+      if (nk == r) {
+        double bw = 0.0;
+        int bq = INT_MAX;
+        for (int q = lane; q < m; q += 64) {
+          bool used = false;
+#pragma unroll
+          for (int u = 0; u < r; ++u) used |= kq[u] == q;
+          const double aw = fabs(W[q]);
+          if (!used && (aw > bw || (aw == bw && aw > 0.0 && q < bq))) { bw = aw; bq = q; }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+          const double ow = __shfl_xor(bw, o);
+          const int oq = __shfl_xor(bq, o);
+          if (ow > bw || (ow == bw && oq < bq)) { bw = ow; bq = oq; }
+        }
+        if (bq != INT_MAX && bw != 0.0) {
+          kq[r] = bq;
+          kw[r] = W[bq];
+          nk = r + 1;
+        }
+      }
+    }
+    if (lane == 0 && nk > 0) {
+      double kept = 0.0;
+#pragma unroll
+      for (int u = 0; u < PW; ++u)
+        if (u < nk) kept += kw[u];
+      const double scl = kept != 0.0 ? total / kept : 1.0;
+      // output sorted by column: the members are sorted by fine index and the
+      // coarse numbering is increasing in the fine index
+#pragma unroll
+      for (int u = 0; u < PW; ++u) {
+        if (u >= nk) continue;
+        int r = 0;
+#pragma unroll
+        for (int v = 0; v < PW; ++v) r += (v < nk && kq[v] < kq[u]) ? 1 : 0;
+        pc[(size_t)i * PW + r] = cidx[mem[kq[u]]];
+        pv[(size_t)i * PW + r] = kw[u] * scl;
+      }
+    }
+    return;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // R = P^T as CSR over coarse rows (entries sorted by fine row)
 // ---------------------------------------------------------------------------
 __global__ void k_pt_count(const Tile* __restrict__ tiles, const int* __restrict__ pc,
@@ -509,10 +863,22 @@ __global__ __launch_bounds__(kRapThreads) void k_rap(int nc, const int* __restri
       }
     }
     __syncthreads();
+    // slot order per output column: each wavefront walks all slots, 64 at a
+    // time, broadcasting (position, product) by shuffles; the owner adds
     const int ns = (fe - f0) * PW;
-    for (int t = 0; t < ns; ++t) {
-      const int pos = ppos[t];
-      if (pos >= 0 && (pos % kRapThreads) == tid) acc[pos] += pval[t];
+    const int lane = tid & 63;
+    for (int b0 = 0; b0 < ns; b0 += 64) {
+      const int sl = b0 + lane;
+      const int mp = sl < ns ? (int)ppos[sl] : -1;
+      const double mv = (mp >= 0) ? pval[sl] : 0.0;
+      const unsigned long long live = __ballot(mp >= 0);
+      if (live == 0ull) continue;
+      const int cnt = (ns - b0) < 64 ? (ns - b0) : 64;
+      for (int k = 0; k < cnt; ++k) {
+        const int pos = __shfl(mp, k);
+        const double val = __shfl(mv, k);
+        if (pos >= 0 && (pos % kRapThreads) == tid) acc[pos] += val;
+      }
     }
     __syncthreads();
   }
@@ -775,51 +1141,95 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_inv_wave(const int* __r
 // ---------------------------------------------------------------------------
 // cycle kernels (T = float for mixed precision, double for FP64 cycles)
 // ---------------------------------------------------------------------------
-template <class T>
+// Sparse rows in the cycle kernels: G lanes per row (G = 1 for the short rows
+// of grid stencils, 4 or 16 for the longer rows of coarse levels).  Each lane
+// walks the row with stride G, loading kRowUnroll entries before using them
+// so that the column and value loads of several entries are in flight
+// together; partial sums are combined in a fixed order (deterministic).
+constexpr int kRowUnroll = 4;
+
+// row r of a tile-based launch: G blocks share one tile of kTileRows rows
+template <int G>
+__device__ inline int tile_row(const Tile& t, int& gl) {
+  gl = threadIdx.x % G;
+  return t.r0 + (int)(blockIdx.x % G) * (kTileRows / G) + (int)threadIdx.x / G;
+}
+
+template <class T, class TX, int G>
+__device__ inline T row_dot(const int* __restrict__ ci, const T* __restrict__ a, const TX* __restrict__ x, int e0,
+                            int e1, int gl) {
+  T acc[kRowUnroll];
+#pragma unroll
+  for (int u = 0; u < kRowUnroll; ++u) acc[u] = 0;
+  int e = e0 + gl;
+  for (; e + (kRowUnroll - 1) * G < e1; e += kRowUnroll * G) {
+    int c[kRowUnroll];
+    T v[kRowUnroll];
+#pragma unroll
+    for (int u = 0; u < kRowUnroll; ++u) {
+      c[u] = ci[e + u * G];
+      v[u] = a[e + u * G];
+    }
+#pragma unroll
+    for (int u = 0; u < kRowUnroll; ++u) acc[u] += v[u] * (T)x[c[u]];
+  }
+  for (; e < e1; e += G) acc[0] += a[e] * (T)x[ci[e]];
+  T s = acc[0];
+#pragma unroll
+  for (int u = 1; u < kRowUnroll; ++u) s += acc[u];
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  return s;
+}
+
+template <class T, int G>
 __global__ __launch_bounds__(256) void k_smooth(const Tile* __restrict__ tiles, const int* __restrict__ act,
                                                 const int* __restrict__ rp, const int* __restrict__ ci,
                                                 const T* __restrict__ a, const T* __restrict__ dinv,
                                                 const T* __restrict__ b, const T* __restrict__ xin,
                                                 T* __restrict__ xout, T omega, int first) {
-  Tile t = tiles[blockIdx.x];
+  const Tile t = tiles[blockIdx.x / G];
   if (!act[t.game]) return;
-  int i = t.r0 + threadIdx.x;
-  if (i >= t.r1) return;
+  int gl;
+  const int i = tile_row<G>(t, gl);
+  const bool in = i < t.r1;
   if (first) {
-    xout[i] = omega * dinv[i] * b[i];
+    if (in && gl == 0) xout[i] = omega * dinv[i] * b[i];
     return;
   }
-  T s = b[i];
-  for (int e = rp[i]; e < rp[i + 1]; ++e) s -= a[e] * xin[ci[e]];
-  xout[i] = xin[i] + omega * dinv[i] * s;
+  const int e0 = in ? rp[i] : 0, e1 = in ? rp[i + 1] : 0;
+  const T ax = row_dot<T, T, G>(ci, a, xin, e0, e1, gl);  // all lanes: the shuffles need them
+  if (in && gl == 0) xout[i] = xin[i] + omega * dinv[i] * (b[i] - ax);
 }
 
-template <class T>
+template <class T, int G>
 __global__ __launch_bounds__(256) void k_resid(const Tile* __restrict__ tiles, const int* __restrict__ act,
                                                const int* __restrict__ rp, const int* __restrict__ ci,
                                                const T* __restrict__ a, const T* __restrict__ b,
                                                const T* __restrict__ x, T* __restrict__ r) {
-  Tile t = tiles[blockIdx.x];
+  const Tile t = tiles[blockIdx.x / G];
   if (!act[t.game]) return;
-  int i = t.r0 + threadIdx.x;
-  if (i >= t.r1) return;
-  T s = b[i];
-  for (int e = rp[i]; e < rp[i + 1]; ++e) s -= a[e] * x[ci[e]];
-  r[i] = s;
+  int gl;
+  const int i = tile_row<G>(t, gl);
+  const bool in = i < t.r1;
+  const int e0 = in ? rp[i] : 0, e1 = in ? rp[i + 1] : 0;
+  const T ax = row_dot<T, T, G>(ci, a, x, e0, e1, gl);
+  if (in && gl == 0) r[i] = b[i] - ax;
 }
 
-template <class T>
+template <class T, int G>
 __global__ __launch_bounds__(256) void k_restrict(const Tile* __restrict__ tiles, const int* __restrict__ act,
                                                   const int* __restrict__ rrp, const int* __restrict__ rci,
                                                   const T* __restrict__ rv, const T* __restrict__ rf,
                                                   T* __restrict__ bc) {
-  Tile t = tiles[blockIdx.x];
+  const Tile t = tiles[blockIdx.x / G];
   if (!act[t.game]) return;
-  int I = t.r0 + threadIdx.x;
-  if (I >= t.r1) return;
-  T s = 0;
-  for (int e = rrp[I]; e < rrp[I + 1]; ++e) s += rv[e] * rf[rci[e]];
-  bc[I] = s;
+  int gl;
+  const int I = tile_row<G>(t, gl);
+  const bool in = I < t.r1;
+  const int e0 = in ? rrp[I] : 0, e1 = in ? rrp[I + 1] : 0;
+  const T s = row_dot<T, T, G>(rci, rv, rf, e0, e1, gl);
+  if (in && gl == 0) bc[I] = s;
 }
 
 template <class T>
@@ -859,31 +1269,33 @@ __global__ __launch_bounds__(256) void k_dense_solve(const int* __restrict__ blk
 
 // FP64 residual of the refinement: r = b - A x, its copy in the cycle type,
 // and per-game max |r|, max |x|.
-template <class T>
+template <class T, int G>
 __global__ __launch_bounds__(256) void k_resid64(const Tile* __restrict__ tiles, const int* __restrict__ act,
                                                  const int* __restrict__ rp, const int* __restrict__ ci,
                                                  const double* __restrict__ a, const double* __restrict__ b,
                                                  const double* __restrict__ x, T* __restrict__ rc,
-                                                 double* __restrict__ norm) {
-  Tile t = tiles[blockIdx.x];
+                                                 Stripes norm) {
+  const Tile t = tiles[blockIdx.x / G];
   if (!act[t.game]) return;
-  int i = t.r0 + threadIdx.x;
+  int gl;
+  const int i = tile_row<G>(t, gl);
+  const bool in = i < t.r1;
   double rm = 0.0, xm = 0.0;
-  if (i < t.r1) {
-    double s = b[i];
-    for (int e = rp[i]; e < rp[i + 1]; ++e) s -= a[e] * x[ci[e]];
+  const int e0 = in ? rp[i] : 0, e1 = in ? rp[i + 1] : 0;
+  const double ax = row_dot<double, double, G>(ci, a, x, e0, e1, gl);
+  if (in && gl == 0) {
+    const double s = b[i] - ax;
     rc[i] = (T)s;
-    rm = fabs(s);
-    xm = fabs(x[i]);
+    const double xi = x[i];
+    rm = s == s ? fabs(s) : INFINITY;   // NaN must survive the maximum
+    xm = xi == xi ? fabs(xi) : INFINITY;
   }
   for (int o = 32; o > 0; o >>= 1) {
     rm = fmax(rm, __shfl_xor(rm, o));
     xm = fmax(xm, __shfl_xor(xm, o));
   }
-  if ((threadIdx.x & 63) == 0) {
-    atomic_max_nonneg(&norm[4 * t.game], rm);
-    atomic_max_nonneg(&norm[4 * t.game + 1], xm);
-  }
+  const double v[2] = {rm, xm};
+  block_fold<2, 0>(norm, t.game, v, 0u, nullptr);
 }
 
 template <class T>
@@ -960,10 +1372,17 @@ void amg_gather_int(const int* src, const int* idx, int m, int* dst, hipStream_t
 }
 void amg_interp(const Tile* t, int nt, const int* rp, const int* ci, const double* a, const double* dinv,
                 const uint8_t* strong, const int8_t* cf, const int* cidx, const uint8_t* dir, int* pc,
-                double* pv, int* capped, hipStream_t s) {
+                double* pv, int* capped, int wave, hipStream_t s) {
   if (!nt) return;
-  hipLaunchKernelGGL(k_interp_lds, dim3(nt * (kTileRows / kIThreads)), dim3(kIThreads), 0, s, t, rp, ci, a,
-                     dinv, strong, cf, cidx, dir, pc, pv, capped);
+  if (wave == 2)
+    hipLaunchKernelGGL((k_interp_wave<1024, 256>), dim3(nt * kTileRows), dim3(64), 0, s, t, rp, ci, a, dinv, strong,
+                       cf, cidx, dir, pc, pv, capped);
+  else if (wave == 1)
+    hipLaunchKernelGGL((k_interp_wave<512, 128>), dim3(nt * kTileRows), dim3(64), 0, s, t, rp, ci, a, dinv, strong,
+                       cf, cidx, dir, pc, pv, capped);
+  else
+    hipLaunchKernelGGL(k_interp_lds, dim3(nt * (kTileRows / kIThreads)), dim3(kIThreads), 0, s, t, rp, ci, a,
+                       dinv, strong, cf, cidx, dir, pc, pv, capped);
   SHP_LAUNCH_CHECK();
 }
 void amg_pt_count(const Tile* t, int nt, const int* pc, int* cnt, hipStream_t s) {
@@ -1013,26 +1432,35 @@ void amg_dense_inv(const int* blk, int nblk, const int* rp, const int* ci, const
   }
 }
 
+// lanes per row from the average row length of a level
+int row_group(double avg_len) { return avg_len <= 10.0 ? 1 : (avg_len <= 40.0 ? 4 : 16); }
+
+#define SHP_GROUP_LAUNCH(K, g, nt, s, ...)                                                         \
+  do {                                                                                            \
+    if ((g) == 16) hipLaunchKernelGGL((K<T, 16>), dim3((nt) * 16), dim3(kTileRows), 0, s, __VA_ARGS__); \
+    else if ((g) == 4) hipLaunchKernelGGL((K<T, 4>), dim3((nt) * 4), dim3(kTileRows), 0, s, __VA_ARGS__); \
+    else hipLaunchKernelGGL((K<T, 1>), dim3(nt), dim3(kTileRows), 0, s, __VA_ARGS__);             \
+  } while (0)
+
 template <class T>
 void cyc_smooth(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const T* a,
-                const T* dinv, const T* b, const T* xin, T* xout, T omega, int first, hipStream_t s) {
+                const T* dinv, const T* b, const T* xin, T* xout, T omega, int first, int g, hipStream_t s) {
   if (!nt) return;
-  hipLaunchKernelGGL(k_smooth<T>, dim3(nt), dim3(kTileRows), 0, s, t, act, rp, ci, a, dinv, b, xin, xout,
-                     omega, first);
+  SHP_GROUP_LAUNCH(k_smooth, first ? 1 : g, nt, s, t, act, rp, ci, a, dinv, b, xin, xout, omega, first);
   SHP_LAUNCH_CHECK();
 }
 template <class T>
 void cyc_resid(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const T* a, const T* b,
-               const T* x, T* r, hipStream_t s) {
+               const T* x, T* r, int g, hipStream_t s) {
   if (!nt) return;
-  hipLaunchKernelGGL(k_resid<T>, dim3(nt), dim3(kTileRows), 0, s, t, act, rp, ci, a, b, x, r);
+  SHP_GROUP_LAUNCH(k_resid, g, nt, s, t, act, rp, ci, a, b, x, r);
   SHP_LAUNCH_CHECK();
 }
 template <class T>
 void cyc_restrict(const Tile* t, int nt, const int* act, const int* rrp, const int* rci, const T* rv,
-                  const T* rf, T* bc, hipStream_t s) {
+                  const T* rf, T* bc, int g, hipStream_t s) {
   if (!nt) return;
-  hipLaunchKernelGGL(k_restrict<T>, dim3(nt), dim3(kTileRows), 0, s, t, act, rrp, rci, rv, rf, bc);
+  SHP_GROUP_LAUNCH(k_restrict, g, nt, s, t, act, rrp, rci, rv, rf, bc);
   SHP_LAUNCH_CHECK();
 }
 template <class T>
@@ -1050,9 +1478,9 @@ void cyc_dense(const int* blk, int nblk, const int* act, const T* inv, const T* 
 }
 template <class T>
 void cyc_resid64(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const double* a,
-                 const double* b, const double* x, T* rc, double* norm, hipStream_t s) {
+                 const double* b, const double* x, T* rc, Stripes norm, int g, hipStream_t s) {
   if (!nt) return;
-  hipLaunchKernelGGL(k_resid64<T>, dim3(nt), dim3(kTileRows), 0, s, t, act, rp, ci, a, b, x, rc, norm);
+  SHP_GROUP_LAUNCH(k_resid64, g, nt, s, t, act, rp, ci, a, b, x, rc, norm);
   SHP_LAUNCH_CHECK();
 }
 template <class T>
@@ -1064,16 +1492,16 @@ void cyc_update64(const Tile* t, int nt, const int* act, const T* e, double* x, 
 
 #define SHP_INST(T)                                                                                  \
   template void cyc_smooth<T>(const Tile*, int, const int*, const int*, const int*, const T*, const T*, \
-                              const T*, const T*, T*, T, int, hipStream_t);                          \
+                              const T*, const T*, T*, T, int, int, hipStream_t);                     \
   template void cyc_resid<T>(const Tile*, int, const int*, const int*, const int*, const T*, const T*,  \
-                             const T*, T*, hipStream_t);                                             \
+                             const T*, T*, int, hipStream_t);                                        \
   template void cyc_restrict<T>(const Tile*, int, const int*, const int*, const int*, const T*,        \
-                                const T*, T*, hipStream_t);                                          \
+                                const T*, T*, int, hipStream_t);                                     \
   template void cyc_prolong<T>(const Tile*, int, const int*, const int*, const T*, const T*, T*,       \
                                hipStream_t);                                                         \
   template void cyc_dense<T>(const int*, int, const int*, const T*, const T*, T*, hipStream_t);        \
   template void cyc_resid64<T>(const Tile*, int, const int*, const int*, const int*, const double*,    \
-                               const double*, const double*, T*, double*, hipStream_t);              \
+                               const double*, const double*, T*, Stripes, int, hipStream_t);         \
   template void cyc_update64<T>(const Tile*, int, const int*, const T*, double*, hipStream_t);
 SHP_INST(float)
 SHP_INST(double)

@@ -25,7 +25,7 @@ void amg_is_c(const int8_t* cf, int* out, int n, hipStream_t s);
 void amg_gather_int(const int* src, const int* idx, int m, int* dst, hipStream_t s);
 void amg_interp(const Tile* t, int nt, const int* rp, const int* ci, const double* a, const double* dinv,
                 const uint8_t* strong, const int8_t* cf, const int* cidx, const uint8_t* dir, int* pc,
-                double* pv, int* capped, hipStream_t s);
+                double* pv, int* capped, int wave, hipStream_t s);  // wave: 0 thread/row, 1 or 2 wave/row
 void amg_pt_count(const Tile* t, int nt, const int* pc, int* cnt, hipStream_t s);
 void amg_pt_fill(const Tile* t, int nt, const int* pc, const double* pv, const int* rrp, int* cursor,
                  int* rci, double* rv, hipStream_t s);
@@ -43,15 +43,17 @@ void amg_row_changed(const Tile* t, int nt, const int* rp, const double* a, doub
                      hipStream_t s);
 void amg_mark_coarse(const Tile* t, int nt, const int* pc, const uint8_t* chg, uint8_t* cmark, hipStream_t s);
 
+// lanes per sparse row (1, 4 or 16) for a level with this average row length
+int row_group(double avg_len);
 template <class T>
 void cyc_smooth(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const T* a,
-                const T* dinv, const T* b, const T* xin, T* xout, T omega, int first, hipStream_t s);
+                const T* dinv, const T* b, const T* xin, T* xout, T omega, int first, int g, hipStream_t s);
 template <class T>
 void cyc_resid(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const T* a, const T* b,
-               const T* x, T* r, hipStream_t s);
+               const T* x, T* r, int g, hipStream_t s);
 template <class T>
 void cyc_restrict(const Tile* t, int nt, const int* act, const int* rrp, const int* rci, const T* rv,
-                  const T* rf, T* bc, hipStream_t s);
+                  const T* rf, T* bc, int g, hipStream_t s);
 template <class T>
 void cyc_prolong(const Tile* t, int nt, const int* act, const int* pc, const T* pv, const T* xc, T* x,
                  hipStream_t s);
@@ -59,7 +61,7 @@ template <class T>
 void cyc_dense(const int* blk, int nblk, const int* act, const T* inv, const T* b, T* x, hipStream_t s);
 template <class T>
 void cyc_resid64(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const double* a,
-                 const double* b, const double* x, T* rc, double* norm, hipStream_t s);
+                 const double* b, const double* x, T* rc, Stripes norm, int g, hipStream_t s);
 template <class T>
 void cyc_update64(const Tile* t, int nt, const int* act, const T* e, double* x, hipStream_t s);
 

@@ -120,6 +120,61 @@ __device__ inline void atomic_max_nonneg(double* addr, double v) {
             static_cast<unsigned long long>(__double_as_longlong(v)));
 }
 
+// ---------------------------------------------------------------------------
+// Striped per-game reductions.  Thousands of workgroups folding a value into
+// one address serialise on that address (device-scope atomics); instead each
+// 256-thread workgroup combines its four wavefronts in LDS and folds the
+// result into one of kStripes copies (workgroup index mod kStripes).  A
+// finishing pass combines the copies per game, writes the result and clears
+// the copies for the next use.  Layout: [stripe][game (padded to 4)][4].
+// Maxima are of non-negative values; a NaN must be mapped to +inf by the
+// caller so that it survives the max.
+// ---------------------------------------------------------------------------
+constexpr int kStripes = 64;
+inline int stripe_games(int G) { return ((G > 1 ? G : 1) + 3) & ~3; }
+struct Stripes {
+  double* d;
+  int* i;
+  int gp;  // padded game count
+};
+__host__ __device__ inline size_t stripe_at(const Stripes& st, int stripe, int g, int q) {
+  return ((size_t)stripe * st.gp + g) * 4 + q;
+}
+
+// Every thread of the (256-thread) workgroup must call this; vd/vi hold the
+// values already reduced within each wavefront (lane 0's copy is used).
+// Bit q of sum_mask selects a sum for double quantity q, else a maximum.
+template <int ND, int NI>
+__device__ inline void block_fold(const Stripes& st, int g, const double* vd, unsigned sum_mask,
+                                  const int* vi) {
+  __shared__ double sd[4][ND > 0 ? ND : 1];
+  __shared__ int si[4][NI > 0 ? NI : 1];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    for (int q = 0; q < ND; ++q) sd[w][q] = vd[q];
+    for (int q = 0; q < NI; ++q) si[w][q] = vi[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    const int s = blockIdx.x % kStripes;
+    for (int q = 0; q < ND; ++q) {
+      const bool sum = (sum_mask >> q) & 1u;
+      double v = sd[0][q];
+      for (int k = 1; k < nw; ++k) v = sum ? v + sd[k][q] : fmax(v, sd[k][q]);
+      if (v != 0.0) {
+        double* a = st.d + stripe_at(st, s, g, q);
+        if (sum) atomicAdd(a, v); else atomic_max_nonneg(a, v);
+      }
+    }
+    for (int q = 0; q < NI; ++q) {
+      int v = si[0][q];
+      for (int k = 1; k < nw; ++k) v += si[k][q];
+      if (v) atomicAdd(st.i + stripe_at(st, s, g, q), v);
+    }
+  }
+}
+
 // 32-bit bijective mixer (murmur3 finaliser) -- deterministic PMIS weights
 __host__ __device__ inline uint32_t mix32(uint32_t x) {
   x ^= x >> 16; x *= 0x85ebca6bu;

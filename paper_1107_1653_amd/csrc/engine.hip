@@ -162,6 +162,15 @@ void Engine::build_layout() {
   d_norm.ensure(4 * std::max(G, 1));
   d_shap.ensure(2 * std::max(G, 1));
   d_decision.ensure(std::max(G, 1));
+  {
+    const int gp = stripe_games(G);
+    const size_t m = (size_t)kStripes * gp * 4;
+    fold_d.ensure(m);
+    fold_i.ensure(m);
+    SHP_HIP(hipMemsetAsync(fold_d.p, 0, sizeof(double) * m, stream));
+    SHP_HIP(hipMemsetAsync(fold_i.p, 0, sizeof(int) * m, stream));
+    fold = Stripes{fold_d.p, fold_i.p, gp};
+  }
   h_active.assign(G, 0);
   h_lin_active.assign(G, 0);
   layout_dirty = false;
@@ -198,12 +207,12 @@ void Engine::assemble(const std::vector<int>& run, bool mixed) {
   L0.x64.ensure(std::max(N0, 1));
   L0.y64.ensure(std::max(N0, 1));
   d_norm.ensure(4 * std::max(G, 1));
-  SHP_HIP(hipMemsetAsync(d_norm.p, 0, sizeof(double) * 4 * G, stream));
   // refinement storage: solution in sol (L0.tmp is int; use dedicated buffers)
   launch_gather_v(ddesc.p, gtiles_all.p, (int)h_gtiles_all.size(), d_active.p, sol.p, stream);
   launch_assemble(ddesc.p, gtiles_all.p, (int)h_gtiles_all.size(), d_active.p, L0.rp.p, L0.a64.p,
                   mixed ? L0.a32.p : nullptr, rhs.p, L0.dinv64.p, mixed ? L0.dinv32.p : nullptr,
-                  d_bnorm.p, stream);
+                  fold, stream);
+  launch_fold_finish(fold, G, 1, 0u, 0, d_bnorm.p, 1, nullptr, 0, stream);
   (void)run;
 }
 
@@ -228,6 +237,8 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
   while (true) {
     Level& L = lv[l];
     const int n = L.n;
+    L.gA = row_group((double)L.nnz / std::max(n, 1));
+    L.gR = 1;
     L.cont.assign(G, 0);
     bool any_cont = false;
     for (int g = 0; g < G; ++g) {
@@ -353,8 +364,12 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         L.pv64.ensure((size_t)std::max(n, 1) * PW);
         // s_err[0]: interpolatory sets truncated, [1]: Galerkin product flags, [2]: singular block
         probe_begin(kProbeInterp, stream);
+        // level 0 (grid stencils, short rows): one thread per row; coarse
+        // levels (long rows): one wavefront per row, with the larger LDS sets
+        // where rows average more than 32 entries
+        const int iw = l == 0 ? 0 : ((double)L.nnz > 32.0 * std::max(n, 1) ? 2 : 1);
         amg_interp(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, L.dinv64.p, L.strong.p, L.cf.p,
-                   L.cidx.p, L.dir.p, L.pc.p, L.pv64.p, s_err.p, stream);
+                   L.cidx.p, L.dir.p, L.pc.p, L.pv64.p, s_err.p, iw, stream);
         probe_end(kProbeInterp, stream, (double)L.rows_ctiles * (PW * 12) + (double)L.nnz * 13);
         pt.mark("interp");
         // ---- next level rows
@@ -385,10 +400,12 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         amg_rap(nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, nullptr, s_cnt.p,
                 nullptr, nullptr, s_err.p + 1, stream);
         scan_exclusive(s_cnt.p, Ln.rp.p, nc + 1, stream, s_scan);
-        int cnnz = 0;
+        int cnnz = 0, rnnz_used = 0;
         d2h(&cnnz, Ln.rp.p + nc, 1, stream);
+        d2h(&rnnz_used, L.rrp.p + nc, 1, stream);
         SHP_HIP(hipStreamSynchronize(stream));
         Ln.nnz = cnnz;
+        L.gR = row_group((double)rnnz_used / std::max(nc, 1));
         Ln.ci.ensure(std::max(cnnz, 1));
         Ln.a64.ensure(std::max(cnnz, 1));
         probe_begin(kProbeRap, stream);
@@ -543,21 +560,21 @@ static T* vcycle_impl(Engine* e, std::vector<Level>& lv, int l, const EngineOpts
     const T* A = LV<T>::a(L);
     const T* D = LV<T>::d(L);
     probe_begin(kProbeSmooth, s);
-    cyc_smooth<T>(L.ctiles.p, L.nctiles, act, L.rp.p, L.ci.p, A, D, b, nullptr, cur, om, 1, s);
+    cyc_smooth<T>(L.ctiles.p, L.nctiles, act, L.rp.p, L.ci.p, A, D, b, nullptr, cur, om, 1, 1, s);
     probe_end(kProbeSmooth, s, bytes_smooth<T>(L, true));
     for (int k = 1; k < o.nu1; ++k) {
       probe_begin(kProbeSmooth, s);
-      cyc_smooth<T>(L.ctiles.p, L.nctiles, act, L.rp.p, L.ci.p, A, D, b, cur, nxt, om, 0, s);
+      cyc_smooth<T>(L.ctiles.p, L.nctiles, act, L.rp.p, L.ci.p, A, D, b, cur, nxt, om, 0, L.gA, s);
       probe_end(kProbeSmooth, s, bytes_smooth<T>(L, false));
       std::swap(cur, nxt);
     }
     T* r = LV<T>::r(L);
     probe_begin(kProbeResid, s);
-    cyc_resid<T>(L.ctiles.p, L.nctiles, act, L.rp.p, L.ci.p, A, b, cur, r, s);
+    cyc_resid<T>(L.ctiles.p, L.nctiles, act, L.rp.p, L.ci.p, A, b, cur, r, L.gA, s);
     probe_end(kProbeResid, s, bytes_resid<T>(L));
     Level& Ln = lv[l + 1];
     probe_begin(kProbeRestrict, s);
-    cyc_restrict<T>(Ln.tiles.p, Ln.ntiles, act, L.rrp.p, L.rci.p, LV<T>::rv(L), r, LV<T>::b(Ln), s);
+    cyc_restrict<T>(Ln.tiles.p, Ln.ntiles, act, L.rrp.p, L.rci.p, LV<T>::rv(L), r, LV<T>::b(Ln), L.gR, s);
     probe_end(kProbeRestrict, s,
               (double)Ln.rows_tiles * (4 + sizeof(T)) + (double)L.rows_ctiles * (4 + 2 * sizeof(T)));
     T* xc = vcycle_impl<T>(e, lv, l + 1, o, act, s);
@@ -567,7 +584,7 @@ static T* vcycle_impl(Engine* e, std::vector<Level>& lv, int l, const EngineOpts
               (double)L.rows_ctiles * (PW * (4 + sizeof(T)) + 2 * sizeof(T)) + (double)Ln.rows_tiles * sizeof(T));
     for (int k = 0; k < o.nu2; ++k) {
       probe_begin(kProbeSmooth, s);
-      cyc_smooth<T>(L.ctiles.p, L.nctiles, act, L.rp.p, L.ci.p, A, D, b, cur, nxt, om, 0, s);
+      cyc_smooth<T>(L.ctiles.p, L.nctiles, act, L.rp.p, L.ci.p, A, D, b, cur, nxt, om, 0, L.gA, s);
       probe_end(kProbeSmooth, s, bytes_smooth<T>(L, false));
       std::swap(cur, nxt);
     }
@@ -588,19 +605,19 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
   SHP_HIP(hipStreamSynchronize(stream));
   while (true) {
     h2d(d_lin_active.p, h_lin_active.data(), G, stream);
-    SHP_HIP(hipMemsetAsync(d_norm.p, 0, sizeof(double) * 4 * G, stream));
     probe_begin(kProbeResid64, stream);
     if (mixed)
       cyc_resid64<float>(L0.tiles.p, L0.ntiles, d_lin_active.p, L0.rp.p, L0.ci.p, L0.a64.p, rhs.p, sol.p,
-                         L0.b32.p, d_norm.p, stream);
+                         L0.b32.p, fold, L0.gA, stream);
     else
       cyc_resid64<double>(L0.tiles.p, L0.ntiles, d_lin_active.p, L0.rp.p, L0.ci.p, L0.a64.p, rhs.p, sol.p,
-                          L0.b64.p, d_norm.p, stream);
+                          L0.b64.p, fold, L0.gA, stream);
     {
       const double rows = L0.rows_tiles;
       const double nnz = L0.n ? (double)L0.nnz * rows / L0.n : 0.0;
       probe_end(kProbeResid64, stream, rows * (4 + 8 + 8 + (mixed ? 4 : 8)) + nnz * 12);
     }
+    launch_fold_finish(fold, G, 2, 0u, 0, d_norm.p, 4, nullptr, 0, stream);
     d2h(hn.data(), d_norm.p, 4 * G, stream);
     SHP_HIP(hipStreamSynchronize(stream));
     bool any = false;
@@ -648,8 +665,6 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
 }
 
 void Engine::improve(const std::vector<int>& run, double tie_rtol) {
-  SHP_HIP(hipMemsetAsync(d_shap.p, 0, sizeof(double) * 2 * G, stream));
-  SHP_HIP(hipMemsetAsync(d_cnt.p, 0, sizeof(int) * 2 * G, stream));
   double bytes = 0.0;
   if (probe_on(kProbeImprove))
     for (int g : run) {
@@ -660,9 +675,9 @@ void Engine::improve(const std::vector<int>& run, double tie_rtol) {
                (double)gm->n * (8 + 8 + 5 * 4);
     }
   probe_begin(kProbeImprove, stream);
-  launch_improve(ddesc.p, gtiles_imp.p, (int)h_gtiles_imp.size(), d_active.p, tie_rtol, d_shap.p, d_cnt.p,
-                 stream);
+  launch_improve(ddesc.p, gtiles_imp.p, (int)h_gtiles_imp.size(), d_active.p, tie_rtol, fold, stream);
   probe_end(kProbeImprove, stream, bytes);
+  launch_fold_finish(fold, G, 2, 2u, 2, d_shap.p, 2, d_cnt.p, 2, stream);
 }
 
 void Engine::apply_decisions(const std::vector<int>& code) {
@@ -716,7 +731,6 @@ int Engine::step() {
   h_active.assign(G, 0);
   for (int g : run) h_active[g] = 1;
   h2d(d_active.p, h_active.data(), G, stream);
-  SHP_HIP(hipMemsetAsync(d_bnorm.p, 0, sizeof(double) * G, stream));
 
   double t0 = now_s();
   PhaseTimer pt(this, prof);

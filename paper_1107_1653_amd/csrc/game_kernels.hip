@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void k_assemble(const GameDesc* __restrict__ g
                                                   const int* __restrict__ active,
                                                   double* __restrict__ a64, float* __restrict__ a32,
                                                   double* __restrict__ b0, double* __restrict__ dinv64,
-                                                  float* __restrict__ dinv32, double* __restrict__ bnorm) {
+                                                  float* __restrict__ dinv32, Stripes bnorm) {
   GTile t = tiles[blockIdx.x];
   if (!active[t.game]) return;
   const GameDesc d = gd[t.game];
@@ -152,15 +152,15 @@ __global__ __launch_bounds__(256) void k_assemble(const GameDesc* __restrict__ g
     double di = diag != 0.0 ? 1.0 / diag : 0.0;
     dinv64[X] = di;
     if (dinv32) dinv32[X] = (float)di;
-    bmax = fabs(rb);
+    bmax = rb == rb ? fabs(rb) : INFINITY;
   }
   bmax = warp_max(bmax);
-  if ((threadIdx.x & 63) == 0) atomic_max_nonneg(&bnorm[t.game], bmax);
+  block_fold<1, 0>(bnorm, t.game, &bmax, 0u, nullptr);
 }
 
 void launch_assemble(const GameDesc* d, const GTile* t, int nt, const int* active, const int* rp0,
                      double* a64, float* a32, double* b0, double* dinv64, float* dinv32,
-                     double* bnorm, hipStream_t s) {
+                     Stripes bnorm, hipStream_t s) {
   (void)rp0;
   if (nt == 0) return;
   hipLaunchKernelGGL(k_assemble, dim3(nt), dim3(kBlock), 0, s, d, t, active, a64, a32, b0, dinv64,
@@ -183,7 +183,7 @@ void launch_assemble(const GameDesc* d, const GTile* t, int nt, const int* activ
 __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd,
                                                  const GTile* __restrict__ tiles,
                                                  const int* __restrict__ active, double tie_rtol,
-                                                 double* __restrict__ shap, int* __restrict__ cnt) {
+                                                 Stripes red) {
   __shared__ double sq[256];
   __shared__ double ss[256];
   __shared__ unsigned char sv[256];
@@ -271,28 +271,61 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
     d.beta_c[x] = bc;
     d.F[x] = F;
     double dv = F - d.v[x];
-    res = fabs(dv);
+    res = dv == dv ? fabs(dv) : INFINITY;
     res2 = dv * dv;
     chg_in = (bin != be) ? 1 : 0;
     chg_out = (ac != al) ? 1 : 0;
   }
-  // block reduction: one atomic per wavefront
-  res = warp_max(res);
-  res2 = warp_sum(res2);
-  chg_in = warp_sum_i(chg_in);
-  chg_out = warp_sum_i(chg_out);
-  if ((tid & 63) == 0 && tid < ns + 63) {
-    atomic_max_nonneg(&shap[2 * t.game], res);
-    atomicAdd(&shap[2 * t.game + 1], res2);
-    if (chg_in) atomicAdd(&cnt[2 * t.game], chg_in);
-    if (chg_out) atomicAdd(&cnt[2 * t.game + 1], chg_out);
-  }
+  // per-game max |F(v) - v|, sum (F(v) - v)^2 and change counts
+  const double vd[2] = {warp_max(res), warp_sum(res2)};
+  const int vi[2] = {warp_sum_i(chg_in), warp_sum_i(chg_out)};
+  block_fold<2, 2>(red, t.game, vd, 2u, vi);
 }
 
 void launch_improve(const GameDesc* d, const GTile* t, int nt, const int* active, double tie_rtol,
-                    double* shap, int* cnt, hipStream_t s) {
+                    Stripes red, hipStream_t s) {
   if (nt == 0) return;
-  hipLaunchKernelGGL(k_improve, dim3(nt), dim3(kBlock), 0, s, d, t, active, tie_rtol, shap, cnt);
+  hipLaunchKernelGGL(k_improve, dim3(nt), dim3(kBlock), 0, s, d, t, active, tie_rtol, red);
+  SHP_LAUNCH_CHECK();
+}
+
+// Combines the stripes of every game (nd double quantities, bit q of
+// sum_mask = sum else max; ni int sums), writes out_d[g * sd + q] and
+// out_i[g * si + q], and clears the stripes.
+__global__ void k_fold_finish(Stripes st, int G, int nd, unsigned sum_mask, int ni, double* __restrict__ out_d,
+                              int sd, int* __restrict__ out_i, int si) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = t >> 2, q = t & 3;
+  if (g >= G) return;
+  if (q < nd) {
+    const bool sum = (sum_mask >> q) & 1u;
+    double v = 0.0;
+#pragma unroll 16
+    for (int k = 0; k < kStripes; ++k) {
+      double* a = st.d + stripe_at(st, k, g, q);
+      const double x = *a;
+      *a = 0.0;
+      v = sum ? v + x : fmax(v, x);
+    }
+    out_d[(size_t)g * sd + q] = v;
+  }
+  if (q < ni) {
+    int v = 0;
+#pragma unroll 16
+    for (int k = 0; k < kStripes; ++k) {
+      int* a = st.i + stripe_at(st, k, g, q);
+      v += *a;
+      *a = 0;
+    }
+    out_i[(size_t)g * si + q] = v;
+  }
+}
+
+void launch_fold_finish(Stripes st, int G, int nd, unsigned sum_mask, int ni, double* out_d, int sd, int* out_i,
+                        int si, hipStream_t s) {
+  if (G <= 0) return;
+  hipLaunchKernelGGL(k_fold_finish, dim3(grid_for(4 * (int64_t)G)), dim3(kBlock), 0, s, st, G, nd, sum_mask, ni,
+                     out_d, sd, out_i, si);
   SHP_LAUNCH_CHECK();
 }
 

@@ -71,6 +71,7 @@ struct Game {
 // One merged (block-diagonal over games) AMG level.
 struct Level {
   int n = 0, nnz = 0;
+  int gA = 1, gR = 1;             // lanes per row of A and of R in the cycle kernels
   DBuf<int> rp, ci;
   DBuf<double> a64, dinv64;
   DBuf<float> a32, dinv32;
@@ -180,6 +181,10 @@ class Engine {
   DBuf<double> d_norm;                        // [4*G] res max, x max, b max, spare
   DBuf<double> d_shap;                        // [2*G] shapley residual max, sum sq
   DBuf<int> d_decision;
+  // striped reduction copies (kept cleared between uses)
+  DBuf<double> fold_d;
+  DBuf<int> fold_i;
+  Stripes fold{nullptr, nullptr, 0};
   std::vector<int> h_active, h_lin_active;
   // refinement storage on the merged level 0
   DBuf<double> sol, rhs, d_bnorm;
@@ -224,9 +229,11 @@ void launch_scatter_v(const GameDesc* d, const GTile* t, int nt, const int* acti
                       hipStream_t s);
 void launch_assemble(const GameDesc* d, const GTile* t, int nt, const int* active, const int* rp0,
                      double* a64, float* a32, double* b0, double* dinv64, float* dinv32,
-                     double* bnorm, hipStream_t s);
+                     Stripes bnorm, hipStream_t s);
 void launch_improve(const GameDesc* d, const GTile* t, int nt, const int* active, double tie_rtol,
-                    double* shap, int* cnt, hipStream_t s);
+                    Stripes red, hipStream_t s);
+void launch_fold_finish(Stripes st, int G, int nd, unsigned sum_mask, int ni, double* out_d, int sd, int* out_i,
+                        int si, hipStream_t s);
 void launch_apply(const GameDesc* d, const GTile* t, int nt, const int* decision, hipStream_t s);
 void launch_union_count(const int* rp, const int* ci, int n, int m1, int m2, int* cnt, int* err,
                         hipStream_t s);

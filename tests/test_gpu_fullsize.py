@@ -1,0 +1,207 @@
+"""Parity at the benchmark workloads' full sizes, in the launch shapes the
+benchmark times.
+
+* Obstacle problem, 1025 x 1025 points, FAMGpi: the oracle's fixed point is
+  stored at 1281 sampled states (tests/golden/obstacle_1025.json, written by
+  tests/golden/make_fullsize.py from the oracle alone).
+* 3-D Isaacs game, 129^3 interior points: same, 1282 sampled states
+  (tests/golden/isaacs3d_129.json).
+* 256 2-D Isaacs games batched: six sampled games against the oracle run here.
+* Serving: the first 16 requests of the serving stream through the server;
+  every request with side <= 250 against the oracle run here.
+
+Runs to the fixed point (eps = 0: no policy improves, exact linear solves)
+are held to the parity bar (FP64 1e-9, mixed 1e-6 relative, policies equal
+at untied states).  Runs with the benchmark's stop (||F(v) - v||_inf <= 1e-8)
+are held to what that stop guarantees: the reported residual, and
+||v - v*||_inf <= 1e-8 / (1 - mu_max), mu_max the largest row sum of the
+game's substochastic weights (F is a mu_max-contraction in the sup norm).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1107_1653_amd as P
+from shapley_inputs import configs
+from tests.gpu_helpers import compare_with_oracle, log
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+BENCH = dict(max_outer=5000, max_inner=5000, forcing=0.1, reuse_frac=0.05)
+
+
+def load(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        d = json.load(f)
+    for k in ("idx", "alpha", "beta"):
+        d[k] = np.asarray(d[k], dtype=np.int64)
+    d["v"] = np.asarray(d["v"], dtype=np.float64)
+    d["tied"] = np.asarray(d["tied"], dtype=bool)
+    return d
+
+
+def check_samples(fx, v, alpha, beta, tol, what):
+    idx = fx["idx"]
+    err = np.max(np.abs(v[idx] - fx["v"])) / fx["vmax_abs"]
+    untied = ~fx["tied"]
+    ma = int(np.sum((alpha[idx] != fx["alpha"]) & untied))
+    mb = int(np.sum((beta[idx] != fx["beta"]) & untied & (alpha[idx] == fx["alpha"])))
+    log(f"  {what}: sampled rel err {err:.2e} (tol {tol:g}), policy mismatches {ma}/{mb} "
+        f"at {untied.sum()} untied samples")
+    assert err <= tol
+    assert ma == 0 and mb == 0
+    return err
+
+
+def mu_max(g):
+    csum = np.concatenate([[0.0], np.cumsum(g.w)])
+    rows = csum[g.row_ptr[1:]] - csum[g.row_ptr[:-1]]
+    return g.mu * float(rows.max())
+
+
+def test_obstacle_1025_famg_full_size():
+    fx = load("obstacle_1025.json")
+    levels = configs.c1_levels(points=1025, coarsest_points=33)
+    g = levels[-1]
+    assert g.n == fx["n"]
+    hs = [P.create_from(x) for x in levels]
+    H = P.shapley_game_create_hierarchy(hs)
+    a0 = np.zeros(levels[0].n, np.int32)
+    try:
+        res = {}
+        for name, prec, eps, tol in (("fp64 fixed point", P.SHAPLEY_FP64, 0.0, 1e-9),
+                                     ("mixed fixed point", P.SHAPLEY_MIXED, 0.0, 1e-6),
+                                     ("fp64 bench stop", P.SHAPLEY_FP64, 1e-8, None),
+                                     ("mixed bench stop", P.SHAPLEY_MIXED, 1e-8, None)):
+            log(f"obstacle 1025 FAMGpi {name}")
+            o = P.shapley_default_opts(eps=eps, precision=prec, method=P.SHAPLEY_FAMGPI, alpha0=a0,
+                                       beta0=a0, **BENCH)
+            st = P.shapley_solve(H, o)
+            v = P.shapley_get_value(H)
+            a, b = P.shapley_get_policy(H)
+            res[name] = v
+            log(f"  outer {st['outer']} residual {st['residual']:.2e} grids {st['fmg_levels']}")
+            assert st["converged"] == 1
+            if tol is not None:
+                check_samples(fx, v, a, b, tol, name)
+            else:
+                assert st["residual"] <= 1e-8
+                bound = 1e-8 / (1.0 - mu_max(g))
+                err = np.max(np.abs(v[fx["idx"]] - fx["v"]))
+                log(f"  sampled |v - v*| {err:.2e} <= contraction bound {bound:.2e}")
+                assert err <= bound
+        d = np.max(np.abs(res["mixed bench stop"] - res["fp64 bench stop"])) / fx["vmax_abs"]
+        log(f"  mixed vs fp64 at the bench stop: {d:.2e}")
+        assert d <= 1e-6
+    finally:
+        P.shapley_game_destroy(H)
+
+
+def test_isaacs3d_129_full_size():
+    fx = load("isaacs3d_129.json")
+    g = configs.c2(s=129)
+    assert g.n == fx["n"]
+    h = P.create_from(g)
+    try:
+        for name, prec, eps, tol in (("fp64 fixed point", P.SHAPLEY_FP64, 0.0, 1e-9),
+                                     ("mixed fixed point", P.SHAPLEY_MIXED, 0.0, 1e-6),
+                                     ("mixed bench stop", P.SHAPLEY_MIXED, 1e-8, None)):
+            log(f"isaacs3d 129 AMGpi {name}")
+            o = P.shapley_default_opts(eps=eps, precision=prec, **BENCH)
+            st = P.shapley_solve(h, o)
+            v = P.shapley_get_value(h)
+            a, b = P.shapley_get_policy(h)
+            log(f"  outer {st['outer']} inner {st['inner_total']} residual {st['residual']:.2e} "
+                f"levels {st['levels']} op complexity {st['op_complexity']:.2f}")
+            assert st["converged"] == 1
+            if tol is not None:
+                check_samples(fx, v, a, b, tol, name)
+            else:
+                assert st["residual"] <= 1e-8
+                bound = 1e-8 / (1.0 - mu_max(g))
+                err = np.max(np.abs(v[fx["idx"]] - fx["v"]))
+                log(f"  sampled |v - v*| {err:.2e} <= contraction bound {bound:.2e}")
+                assert err <= bound
+    finally:
+        P.shapley_game_destroy(h)
+
+
+def test_batch_256_games_full_size():
+    side, lam = configs.c3_sizes(count=256)
+    gs = [configs.c3_game(k, side[k], lam[k]) for k in range(256)]
+    hs = [P.create_from(g) for g in gs]
+    # two sampled games of each side
+    pick = []
+    for s in (65, 129, 257):
+        pick += [int(k) for k in np.flatnonzero(side == s)[:2]]
+    try:
+        log(f"batch of 256 games, sum n = {sum(g.n for g in gs)}")
+        st = P.shapley_solve_batch(hs, P.shapley_default_opts(precision=P.SHAPLEY_MIXED, **BENCH))
+        assert all(s["converged"] == 1 for s in st)
+        for k in pick:
+            g = gs[k]
+            ref = oracle.policy_iteration(g)
+            v = P.shapley_get_value(hs[k])
+            a, b = P.shapley_get_policy(hs[k])
+            err, ma, mb, _ = compare_with_oracle(g, v, a, b, ref, 1e-6)
+            log(f"  game {k} side {side[k]} lambda {lam[k]:.3f}: rel err {err:.2e}, outer {st[k]['outer']}")
+            assert err <= 1e-6 and len(ma) == 0 and len(mb) == 0
+        st = P.shapley_solve_batch(hs, P.shapley_default_opts(eps=1e-8, precision=P.SHAPLEY_MIXED, **BENCH))
+        worst = max(s["residual"] for s in st)
+        log(f"  bench stop: worst residual {worst:.2e}")
+        assert all(s["converged"] == 1 for s in st) and worst <= 1e-8
+    finally:
+        for h in hs:
+            P.shapley_game_destroy(h)
+
+
+def test_serving_stream_full_size():
+    reqs = configs.c4_requests(count=1000)[:16]
+    handles = []
+    for kind, side, lam, seed in reqs:
+        if kind == 0:
+            g = configs.c4_game(kind, side, lam, seed)
+            handles.append((P.create_from(g), [g]))
+        else:
+            lv = configs.obstacle_levels_for_side(side, seed, lam)
+            handles.append((P.shapley_game_create_hierarchy([P.create_from(x) for x in lv]), lv))
+    srv = P.shapley_server_create(200 * 10 ** 9)
+    try:
+        tickets = []
+        for (h, lv), (kind, side, lam, seed) in zip(handles, reqs):
+            if kind == 0:
+                o = P.shapley_default_opts(precision=P.SHAPLEY_MIXED, **BENCH)
+            else:
+                a0 = np.zeros(lv[0].n, np.int32)
+                o = P.shapley_default_opts(precision=P.SHAPLEY_MIXED, method=P.SHAPLEY_FAMGPI, alpha0=a0,
+                                           beta0=a0, **BENCH)
+            tickets.append(P.shapley_server_submit(srv, h, o))
+        steps = 0
+        while P.shapley_server_step(srv) > 0:
+            steps += 1
+            assert steps < 100000
+        log(f"serving 16 requests: {steps} server steps")
+        for (h, lv), t, (kind, side, lam, seed) in zip(handles, tickets, reqs):
+            st = P.shapley_server_poll(srv, t)
+            assert st is not None and st["converged"] == 1
+            if side > 250:
+                log(f"  request seed {seed} side {side}: converged, outer {st['outer']} (no oracle run)")
+                continue
+            g = lv[-1]
+            if kind == 0:
+                ref = oracle.policy_iteration(g)
+            else:
+                ref = oracle.famg_pi(lv, eps=0.0, c=1e-2)[-1]
+            v = P.shapley_get_value(h)
+            a, b = P.shapley_get_policy(h)
+            err, ma, mb, _ = compare_with_oracle(g, v, a, b, ref, 1e-6)
+            log(f"  request seed {seed} kind {kind} side {side}: rel err {err:.2e}")
+            assert err <= 1e-6 and len(ma) == 0 and len(mb) == 0
+    finally:
+        P.shapley_server_destroy(srv)
+        for h, _ in handles:
+            P.shapley_game_destroy(h)

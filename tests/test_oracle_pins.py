@@ -381,3 +381,41 @@ def test_famg_matches_single_level_fixed_point():
     ref = oracle.policy_iteration(levels[-1])
     np.testing.assert_allclose(res[-1].v, ref.v, atol=1e-13)
     np.testing.assert_array_equal(res[-1].alpha, ref.alpha)
+
+
+# ---------------------------------------------------------------------------
+# the Krylov policy evaluation used where the sparse LU does not fit (3-D)
+# ---------------------------------------------------------------------------
+
+def test_krylov_evaluation_matches_dense_solve():
+    """BiCGSTAB + FP64 re-checks equals numpy's dense solve of (LSPI)."""
+    g = configs.c2(s=5)
+    rng = np.random.default_rng(11)
+    alpha = rng.integers(0, g.m1, g.n).astype(np.int32)
+    beta = rng.integers(0, g.m2, g.n).astype(np.int32)
+    v = oracle.evaluate_policies(g, alpha, beta, solver="krylov")
+    ref = dense_policy_value(g, alpha, beta)
+    np.testing.assert_allclose(v, ref, rtol=1e-12, atol=1e-15 * np.abs(ref).max())
+
+
+def test_krylov_policy_iteration_matches_value_iteration_3d():
+    """3-D Isaacs game (the workload family where the Krylov path is used):
+    policy iteration with Krylov evaluations reaches the fixed point found by
+    pure-Python value iteration."""
+    grid = Grid(3, 4)
+    rng = np.random.default_rng(5)
+    f = rng.uniform(-1.0, 1.0, grid.n)
+    g = games.isaacs_game(grid, f, 5.0)
+    res = oracle.policy_iteration(g, solver="krylov")
+    assert res.converged
+    vi = value_iteration(g)
+    np.testing.assert_allclose(res.v, vi, rtol=1e-12, atol=1e-14)
+
+
+def test_krylov_torus_closed_form():
+    s, lam, r0 = 16, 0.3, -0.4
+    grid = Grid(2, s, periodic=True)
+    g = games.isaacs_game(grid, np.full(grid.n, r0), lam)
+    res = oracle.policy_iteration(g, solver="krylov")
+    np.testing.assert_allclose(res.v, r0 / lam, rtol=1e-12)
+    assert np.all(res.alpha == 1) and np.all(res.beta == 1)
