@@ -705,21 +705,24 @@ __global__ void k_sort_rows(const int* __restrict__ rp, int* __restrict__ ci, do
 }
 
 // ---------------------------------------------------------------------------
-// Galerkin product A_c = R A P, one workgroup of kRapThreads per coarse row.
+// Galerkin product A_c = R A P, one workgroup of NT threads per coarse row.
 // The row's (R entry, A entry) pairs are flattened over the lanes so that
-// their loads issue in parallel.  Phase 1 collects the distinct coarse
-// columns in an LDS hash set (sized to the row) and sorts them.  Phase 2
-// (numeric) writes the products of a chunk of pairs to LDS at fixed slots of
-// the enumeration order (R entry, A entry, P slot); the lane owning an output
-// column (column index mod kRapThreads) adds its products slot by slot, so
-// the sums are bit-reproducible whatever the batch and the launch shape.
+// their loads issue in parallel.  The distinct coarse columns of the row are
+// either collected in an LDS hash set and sorted (full setup), or read from
+// the existing coarse matrix (numeric refresh: same pattern).  The products
+// of a chunk of pairs are written to LDS at fixed slots of the enumeration
+// order (R entry, A entry, P slot); the lane owning an output column (column
+// position mod NT) adds its products slot by slot, so the sums are
+// bit-reproducible whatever the batch, the launch shape and the mode.
+// Full setup: each row goes to a scratch area at an upper-bound offset with
+// its length; a compaction then copies the rows into the final CSR.
 // err bits: 1 hash full, 2 R row too long, 4 too many distinct columns.
 // ---------------------------------------------------------------------------
-constexpr int kRapThreads = 128;
 constexpr int kRapRCap = 256;      // max entries of one R row
 constexpr int kRapHash = 2048;     // hash slots (>= 2 x products when possible)
-constexpr int kRapND = 1024;       // max distinct columns of one coarse row
+constexpr int kRapND = kRapMaxCols;  // max distinct columns of one coarse row
 constexpr int kRapChunk = 256;     // (R, A) pairs per product chunk
+enum { kRapFused = 0, kRapKnown = 1 };
 
 __device__ inline int rap_locate(const int* rO, int P, int f) {
   int lo = 0, hi = P - 1;  // largest p with rO[p] <= f
@@ -730,159 +733,259 @@ __device__ inline int rap_locate(const int* rO, int P, int f) {
   return lo;
 }
 
-__global__ __launch_bounds__(kRapThreads) void k_rap(int nc, const int* __restrict__ rrp,
-                                                     const int* __restrict__ rci,
-                                                     const double* __restrict__ rv,
-                                                     const int* __restrict__ rp, const int* __restrict__ ci,
-                                                     const double* __restrict__ a, const int* __restrict__ pc,
-                                                     const double* __restrict__ pv,
-                                                     const int* __restrict__ crp, int* __restrict__ ccnt,
-                                                     int* __restrict__ cci, double* __restrict__ cval,
-                                                     int* __restrict__ err, const uint8_t* __restrict__ only) {
+// upper bound of the distinct columns of each coarse row: min(PW x pairs, kRapND)
+__global__ void k_rap_bound(int nc, const int* __restrict__ rrp, const int* __restrict__ rci,
+                            const int* __restrict__ rp, int* __restrict__ ub) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const int p0 = rrp[I], p1 = rrp[I + 1];
+  if (p1 - p0 > kRapRCap) { ub[I] = 0; return; }
+  long long E = 0;
+  for (int p = p0; p < p1; ++p) {
+    const int i = rci[p];
+    E += rp[i + 1] - rp[i];
+  }
+  const long long b = E * PW;
+  ub[I] = (int)(b < kRapND ? b : kRapND);
+}
+
+template <int NT, int MODE>
+__global__ __launch_bounds__(NT) void k_rap(int nc, const int* __restrict__ rrp, const int* __restrict__ rci,
+                                            const double* __restrict__ rv, const int* __restrict__ rp,
+                                            const int* __restrict__ ci, const double* __restrict__ a,
+                                            const int* __restrict__ pc, const double* __restrict__ pv,
+                                            const int* __restrict__ toff, int* __restrict__ tcnt,
+                                            int* __restrict__ tcol, double* __restrict__ tval,
+                                            const int* __restrict__ crp, const int* __restrict__ cci,
+                                            double* __restrict__ cval, int* __restrict__ err,
+                                            const uint8_t* __restrict__ only) {
   __shared__ int rS[kRapRCap];
   __shared__ int rO[kRapRCap + 1];
   __shared__ double rV[kRapRCap];
   __shared__ double ubuf[kRapHash / 2];  // hash table, later the product values
   __shared__ int lst[kRapND];
-  __shared__ double acc[kRapND];
-  __shared__ short ppos[kRapChunk * PW];
+  __shared__ int skey[kRapChunk * PW];  // (position << 10 | slot) of each product
   __shared__ int nd_sh;
   int* tab = reinterpret_cast<int*>(ubuf);
   double* pval = ubuf;
   const int I = blockIdx.x;
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  // output column at position pos is owned by lane pos % NT, register pos / NT
+  constexpr int R = kRapND / NT;
+  double reg[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) reg[j] = 0.0;
   if (I >= nc) return;
   if (only && !only[I]) return;  // incremental refresh: row unchanged
   const int p0 = rrp[I], P = rrp[I + 1] - p0;
   if (P > kRapRCap) {
     if (tid == 0) {
       atomicOr(err, 2);
-      if (ccnt) ccnt[I] = 0;
+      if (MODE == kRapFused) tcnt[I] = 0;
     }
     return;
   }
-  for (int t = tid; t < P; t += kRapThreads) {
-    int i = rci[p0 + t];
-    int b = rp[i];
+  for (int t = tid; t < P; t += NT) {
+    const int i = rci[p0 + t];
+    const int b = rp[i];
     rS[t] = b;
     rO[t + 1] = rp[i + 1] - b;
     rV[t] = rv[p0 + t];
   }
   __syncthreads();
-  if (tid == 0) {
-    rO[0] = 0;
-    for (int t = 0; t < P; ++t) rO[t + 1] += rO[t];
-    nd_sh = 0;
+  if (tid < 64) {  // offsets of the pairs of each R entry (one wavefront scan)
+    int carry = 0;
+    for (int base = 0; base < P; base += 64) {
+      const int t = base + lane;
+      int v = t < P ? rO[t + 1] : 0;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(v, o);
+        if (lane >= o) v += y;
+      }
+      if (t < P) rO[t + 1] = carry + v;
+      carry += __shfl(v, 63);
+    }
+    if (lane == 0) {
+      rO[0] = 0;
+      nd_sh = 0;
+    }
   }
   __syncthreads();
   const int E = rO[P];
-  int hs = 64;
-  while (hs < 2 * PW * E && hs < kRapHash) hs <<= 1;
-  for (int h = tid; h < hs; h += kRapThreads) tab[h] = -1;
-  __syncthreads();
-  bool full = false;
-  for (int f = tid; f < E; f += kRapThreads) {
-    const int p = rap_locate(rO, P, f);
-    const int k = ci[rS[p] + (f - rO[p])];
-    for (int q = 0; q < PW; ++q) {
-      int J = pc[(size_t)k * PW + q];
-      if (J < 0) continue;
-      unsigned h = mix32((uint32_t)J) & (hs - 1);
-      int probes = 0;
-      while (true) {
-        int old = atomicCAS(&tab[h], -1, J);
-        if (old == -1 || old == J) break;
-        h = (h + 1) & (hs - 1);
-        if (++probes >= hs) { full = true; break; }
-      }
-    }
-  }
-  if (full) atomicOr(err, 1);
-  __syncthreads();
-  bool over = false;
-  for (int h = tid; h < hs; h += kRapThreads) {
-    int J = tab[h];
-    if (J >= 0) {
-      int pos = atomicAdd(&nd_sh, 1);
-      if (pos < kRapND) lst[pos] = J; else over = true;
-    }
-  }
-  if (over) atomicOr(err, 4);
-  __syncthreads();
-  const int nd = nd_sh < kRapND ? nd_sh : kRapND;
-  if (ccnt) {  // symbolic pass
-    if (tid == 0) ccnt[I] = nd;
-    return;
-  }
-  int P2 = 1;
-  while (P2 < nd) P2 <<= 1;
-  for (int h = nd + tid; h < P2; h += kRapThreads) lst[h] = INT_MAX;
-  __syncthreads();
-  for (int k2 = 2; k2 <= P2; k2 <<= 1) {
-    for (int j = k2 >> 1; j > 0; j >>= 1) {
-      for (int idx = tid; idx < P2; idx += kRapThreads) {
-        int ixj = idx ^ j;
-        if (ixj > idx) {
-          int x = lst[idx], y = lst[ixj];
-          bool up = (idx & k2) == 0;
-          if ((x > y) == up) { lst[idx] = y; lst[ixj] = x; }
+  int nd;
+  if (MODE == kRapFused) {
+    int hs = 64;
+    while (hs < 2 * PW * E && hs < kRapHash) hs <<= 1;
+    for (int h = tid; h < hs; h += NT) tab[h] = -1;
+    __syncthreads();
+    bool full = false;
+    for (int f = tid; f < E; f += NT) {
+      const int p = rap_locate(rO, P, f);
+      const int k = ci[rS[p] + (f - rO[p])];
+      for (int q = 0; q < PW; ++q) {
+        const int J = pc[(size_t)k * PW + q];
+        if (J < 0) continue;
+        unsigned h = mix32((uint32_t)J) & (hs - 1);
+        int probes = 0;
+        while (true) {
+          const int old = atomicCAS(&tab[h], -1, J);
+          if (old == -1 || old == J) break;
+          h = (h + 1) & (hs - 1);
+          if (++probes >= hs) { full = true; break; }
         }
       }
-      __syncthreads();
     }
-  }
-  const int base = crp[I];
-  for (int h = tid; h < nd; h += kRapThreads) {
-    cci[base + h] = lst[h];
-    acc[h] = 0.0;
+    if (full) atomicOr(err, 1);
+    __syncthreads();
+    bool over = false;
+    for (int h = tid; h < hs; h += NT) {
+      const int J = tab[h];
+      if (J >= 0) {
+        const int pos = atomicAdd(&nd_sh, 1);
+        if (pos < kRapND) lst[pos] = J; else over = true;
+      }
+    }
+    if (over) atomicOr(err, 4);
+    __syncthreads();
+    nd = nd_sh < kRapND ? nd_sh : kRapND;
+    int P2 = 1;
+    while (P2 < nd) P2 <<= 1;
+    for (int h = nd + tid; h < P2; h += NT) lst[h] = INT_MAX;
+    __syncthreads();
+    for (int k2 = 2; k2 <= P2; k2 <<= 1) {
+      for (int j = k2 >> 1; j > 0; j >>= 1) {
+        for (int idx = tid; idx < P2; idx += NT) {
+          const int ixj = idx ^ j;
+          if (ixj > idx) {
+            const int x = lst[idx], y = lst[ixj];
+            const bool up = (idx & k2) == 0;
+            if ((x > y) == up) { lst[idx] = y; lst[ixj] = x; }
+          }
+        }
+        __syncthreads();
+      }
+    }
+  } else {
+    const int base = crp[I];
+    nd = crp[I + 1] - base;
+    if (nd > kRapND) {
+      if (tid == 0) atomicOr(err, 4);
+      return;
+    }
+    for (int h = tid; h < nd; h += NT) lst[h] = cci[base + h];
   }
   __syncthreads();
   for (int f0 = 0; f0 < E; f0 += kRapChunk) {
     const int fe = (E < f0 + kRapChunk) ? E : f0 + kRapChunk;
-    for (int f = f0 + tid; f < fe; f += kRapThreads) {
+    for (int f = f0 + tid; f < fe; f += NT) {
       const int p = rap_locate(rO, P, f);
       const int e = rS[p] + (f - rO[p]);
       const int k = ci[e];
       const double ra = rV[p] * a[e];
       for (int q = 0; q < PW; ++q) {
         const int slot = (f - f0) * PW + q;
-        int J = pc[(size_t)k * PW + q];
-        short pos = -1;
-        if (J >= 0) {
+        const int J = pc[(size_t)k * PW + q];
+        int key = INT_MAX;
+        double val = 0.0;
+        if (J >= 0 && nd > 0) {
           int lo = 0, hi = nd - 1;
           while (lo < hi) {
-            int mid = (lo + hi) >> 1;
+            const int mid = (lo + hi) >> 1;
             if (lst[mid] < J) lo = mid + 1; else hi = mid;
           }
           if (lst[lo] == J) {
-            pos = (short)lo;
-            pval[slot] = ra * pv[(size_t)k * PW + q];
+            key = (lo << 10) | slot;
+            val = ra * pv[(size_t)k * PW + q];
           }
         }
-        ppos[slot] = pos;
+        skey[slot] = key;
+        pval[slot] = val;
       }
     }
-    __syncthreads();
-    // slot order per output column: each wavefront walks all slots, 64 at a
-    // time, broadcasting (position, product) by shuffles; the owner adds
+    // products sorted by (output position, slot): each output column's
+    // products become one run in slot order, which its owner sums in that
+    // order (the same order for any launch shape)
     const int ns = (fe - f0) * PW;
-    const int lane = tid & 63;
-    for (int b0 = 0; b0 < ns; b0 += 64) {
-      const int sl = b0 + lane;
-      const int mp = sl < ns ? (int)ppos[sl] : -1;
-      const double mv = (mp >= 0) ? pval[sl] : 0.0;
-      const unsigned long long live = __ballot(mp >= 0);
-      if (live == 0ull) continue;
-      const int cnt = (ns - b0) < 64 ? (ns - b0) : 64;
-      for (int k = 0; k < cnt; ++k) {
-        const int pos = __shfl(mp, k);
-        const double val = __shfl(mv, k);
-        if (pos >= 0 && (pos % kRapThreads) == tid) acc[pos] += val;
+    int NS2 = 1;
+    while (NS2 < ns) NS2 <<= 1;
+    for (int t = ns + tid; t < NS2; t += NT) skey[t] = INT_MAX;
+    __syncthreads();
+    for (int k2 = 2; k2 <= NS2; k2 <<= 1) {
+      for (int j = k2 >> 1; j > 0; j >>= 1) {
+        for (int idx = tid; idx < NS2; idx += NT) {
+          const int ixj = idx ^ j;
+          if (ixj > idx) {
+            const int x = skey[idx], y = skey[ixj];
+            const bool up = (idx & k2) == 0;
+            if ((x > y) == up) {
+              skey[idx] = y;
+              skey[ixj] = x;
+              const double vx = pval[idx];
+              pval[idx] = pval[ixj];
+              pval[ixj] = vx;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    auto lower = [&](int key) {  // first index with skey >= key
+      int lo = 0, hi = NS2;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (skey[mid] < key) lo = mid + 1; else hi = mid;
+      }
+      return lo;
+    };
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int pos = j * NT + tid;
+      if (pos < nd) {
+        const int t1 = lower((pos + 1) << 10);
+        double acc = reg[j];
+        for (int t = lower(pos << 10); t < t1; ++t) acc += pval[t];
+        reg[j] = acc;
       }
     }
     __syncthreads();
   }
-  for (int h = tid; h < nd; h += kRapThreads) cval[base + h] = acc[h];
+  if (MODE == kRapFused) {
+    const int o = toff[I];
+    const int cap = toff[I + 1] - o;
+    if (nd > cap) {  // cannot happen: nd <= min(PW x pairs, kRapND)
+      if (tid == 0) { atomicOr(err, 4); tcnt[I] = 0; }
+      return;
+    }
+    for (int h = tid; h < nd; h += NT) tcol[o + h] = lst[h];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int h = j * NT + tid;
+      if (h < nd) tval[o + h] = reg[j];
+    }
+    if (tid == 0) tcnt[I] = nd;
+  } else {
+    const int base = crp[I];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int h = j * NT + tid;
+      if (h < nd) cval[base + h] = reg[j];
+    }
+  }
+}
+
+// rows of the scratch area into the final CSR (one wavefront per row)
+__global__ __launch_bounds__(64) void k_rap_compact(int nc, const int* __restrict__ toff,
+                                                    const int* __restrict__ tcol, const double* __restrict__ tval,
+                                                    const int* __restrict__ crp, int* __restrict__ cci,
+                                                    double* __restrict__ cval) {
+  const int I = blockIdx.x;
+  if (I >= nc) return;
+  const int o = toff[I], base = crp[I], nd = crp[I + 1] - base;
+  for (int h = threadIdx.x; h < nd; h += 64) {
+    cci[base + h] = tcol[o + h];
+    cval[base + h] = tval[o + h];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1401,12 +1504,38 @@ void amg_sort_rows(const int* rp, int* ci, double* v, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(n)), dim3(kBlock), 0, s, rp, ci, v, n);
   SHP_LAUNCH_CHECK();
 }
-void amg_rap(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,
-             const double* a, const int* pc, const double* pv, const int* crp, int* ccnt, int* cci,
-             double* cval, int* err, hipStream_t s, const uint8_t* only) {
+void amg_rap_bound(int nc, const int* rrp, const int* rci, const int* rp, int* ub, hipStream_t s) {
   if (!nc) return;
-  hipLaunchKernelGGL(k_rap, dim3(nc), dim3(kRapThreads), 0, s, nc, rrp, rci, rv, rp, ci, a, pc, pv, crp, ccnt,
-                     cci, cval, err, only);
+  hipLaunchKernelGGL(k_rap_bound, dim3(grid_for(nc)), dim3(kBlock), 0, s, nc, rrp, rci, rp, ub);
+  SHP_LAUNCH_CHECK();
+}
+// levels with few coarse rows get more lanes per row (their time is the
+// latency of one row); the results do not depend on the choice
+#define SHP_RAP_LAUNCH(MODE, ...)                                                                  \
+  do {                                                                                            \
+    if (nc < 8192) hipLaunchKernelGGL((k_rap<256, MODE>), dim3(nc), dim3(256), 0, s, __VA_ARGS__); \
+    else hipLaunchKernelGGL((k_rap<128, MODE>), dim3(nc), dim3(128), 0, s, __VA_ARGS__);           \
+  } while (0)
+void amg_rap_fused(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,
+                   const double* a, const int* pc, const double* pv, const int* toff, int* tcnt, int* tcol,
+                   double* tval, int* err, hipStream_t s) {
+  if (!nc) return;
+  SHP_RAP_LAUNCH(kRapFused, nc, rrp, rci, rv, rp, ci, a, pc, pv, toff, tcnt, tcol, tval, nullptr, nullptr, nullptr,
+                 err, nullptr);
+  SHP_LAUNCH_CHECK();
+}
+void amg_rap_compact(int nc, const int* toff, const int* tcol, const double* tval, const int* crp, int* cci,
+                     double* cval, hipStream_t s) {
+  if (!nc) return;
+  hipLaunchKernelGGL(k_rap_compact, dim3(nc), dim3(64), 0, s, nc, toff, tcol, tval, crp, cci, cval);
+  SHP_LAUNCH_CHECK();
+}
+void amg_rap_known(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,
+                   const double* a, const int* pc, const double* pv, const int* crp, const int* cci, double* cval,
+                   int* err, hipStream_t s, const uint8_t* only) {
+  if (!nc) return;
+  SHP_RAP_LAUNCH(kRapKnown, nc, rrp, rci, rv, rp, ci, a, pc, pv, nullptr, nullptr, nullptr, nullptr, crp, cci, cval,
+                 err, only);
   SHP_LAUNCH_CHECK();
 }
 void amg_diag_inv(int n, const int* rp, const int* ci, const double* a, double* d64, float* d32,

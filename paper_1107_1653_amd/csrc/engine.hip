@@ -393,12 +393,23 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         amg_pt_fill(L.ctiles.p, L.nctiles, L.pc.p, L.pv64.p, L.rrp.p, s_cursor.p, L.rci.p, L.rv64.p, stream);
         amg_sort_rows(L.rrp.p, L.rci.p, L.rv64.p, nc, stream);
         pt.mark("transpose");
-        // ---- Galerkin product
+        // ---- Galerkin product: bounds, one fused pass into scratch rows,
+        // row pointers, compaction
         Ln.rp.ensure(nc + 1);
         s_cnt.ensure(nc + 1);
+        s_toff.ensure(nc + 1);
         SHP_HIP(hipMemsetAsync(s_cnt.p + nc, 0, sizeof(int), stream));
-        amg_rap(nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, nullptr, s_cnt.p,
-                nullptr, nullptr, s_err.p + 1, stream);
+        amg_rap_bound(nc, L.rrp.p, L.rci.p, L.rp.p, s_cnt.p, stream);
+        scan_exclusive(s_cnt.p, s_toff.p, nc + 1, stream, s_scan);
+        // sum of the bounds <= PW * (pairs) <= PW * PW * nnz(A)
+        const size_t tcap = std::max<size_t>(
+            1, std::min((size_t)PW * PW * (size_t)std::max(L.nnz, 1), (size_t)nc * (size_t)kRapMaxCols));
+        s_tcol.ensure(tcap);
+        s_tval.ensure(tcap);
+        probe_begin(kProbeRap, stream);
+        amg_rap_fused(nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, s_toff.p, s_cnt.p,
+                      s_tcol.p, s_tval.p, s_err.p + 1, stream);
+        probe_end(kProbeRap, stream, (double)L.nnz * 12 + (double)n * PW * 12 + (double)nc * 8);
         scan_exclusive(s_cnt.p, Ln.rp.p, nc + 1, stream, s_scan);
         int cnnz = 0, rnnz_used = 0;
         d2h(&cnnz, Ln.rp.p + nc, 1, stream);
@@ -408,10 +419,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         L.gR = row_group((double)rnnz_used / std::max(nc, 1));
         Ln.ci.ensure(std::max(cnnz, 1));
         Ln.a64.ensure(std::max(cnnz, 1));
-        probe_begin(kProbeRap, stream);
-        amg_rap(nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, Ln.rp.p, nullptr,
-                Ln.ci.p, Ln.a64.p, s_err.p + 1, stream);
-        probe_end(kProbeRap, stream, (double)cnnz * 12 + (double)L.nnz * 12 + (double)n * PW * 12);
+        amg_rap_compact(nc, s_toff.p, s_tcol.p, s_tval.p, Ln.rp.p, Ln.ci.p, Ln.a64.p, stream);
         if (mixed) {
           L.pv32.ensure((size_t)std::max(n, 1) * PW);
           amg_cast(L.pv64.p, L.pv32.p, (size_t)n * PW, stream);
@@ -517,8 +525,8 @@ void Engine::refresh(const EngineOpts& o) {
       SHP_HIP(hipMemsetAsync(Ln.chg.p, 0, std::max(L.nc, 1), stream));
       amg_mark_coarse(L.ctiles.p, L.nctiles, L.pc.p, L.chg.p, Ln.chg.p, stream);
       probe_begin(kProbeRap, stream);
-      amg_rap(L.nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, Ln.rp.p, nullptr,
-              Ln.ci.p, Ln.a64.p, s_err.p + 1, stream, Ln.chg.p);
+      amg_rap_known(L.nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, Ln.rp.p, Ln.ci.p,
+                    Ln.a64.p, s_err.p + 1, stream, Ln.chg.p);
       probe_end(kProbeRap, stream, (double)Ln.nnz * 12 + (double)L.nnz * 12 + (double)n * PW * 12);
     }
     if (L.nblk)

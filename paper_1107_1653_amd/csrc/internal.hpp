@@ -190,6 +190,8 @@ class Engine {
   DBuf<double> sol, rhs, d_bnorm;
   // setup scratch
   DBuf<int> s_cnt, s_cursor, s_scan, s_err, s_left, s_newc, s_gidx, s_gout, s_goff;
+  DBuf<int> s_toff, s_tcol;   // Galerkin product scratch rows (offsets, columns)
+  DBuf<double> s_tval;        // and values
   DBuf<Tile> s_tiles;
   DBuf<double> s_dense;
  public:
