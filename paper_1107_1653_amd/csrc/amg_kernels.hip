@@ -98,7 +98,9 @@ __global__ void k_pmis_select(const Tile* __restrict__ tiles, const int* __restr
                               const int* __restrict__ ci, const uint8_t* __restrict__ strong,
                               const int* __restrict__ st_rp, const int* __restrict__ st_ci,
                               const int8_t* __restrict__ cf, const uint64_t* __restrict__ key,
-                              int* __restrict__ newc) {
+                              int* __restrict__ newc, int* __restrict__ left) {
+  // the following update kernel counts the undecided rows into *left
+  if (blockIdx.x == 0 && threadIdx.x == 0) *left = 0;
   Tile t = tiles[blockIdx.x];
   int i = t.r0 + threadIdx.x;
   if (i >= t.r1) return;
@@ -1446,10 +1448,10 @@ void amg_pmis_init(const Tile* t, int nt, const int* goff, const uint8_t* dir, c
 }
 void amg_pmis_select(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
                      const int* st_rp, const int* st_ci, const int8_t* cf, const uint64_t* key,
-                     int* newc, hipStream_t s) {
+                     int* newc, int* left, hipStream_t s) {
   if (!nt) return;
   hipLaunchKernelGGL(k_pmis_select, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, strong, st_rp, st_ci,
-                     cf, key, newc);
+                     cf, key, newc, left);
   SHP_LAUNCH_CHECK();
 }
 void amg_pmis_update(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,

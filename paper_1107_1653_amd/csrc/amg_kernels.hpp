@@ -17,7 +17,7 @@ void amg_pmis_init(const Tile* t, int nt, const int* goff, const uint8_t* dir, c
                    uint32_t salt, int8_t* cf, uint64_t* key, hipStream_t s);
 void amg_pmis_select(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
                      const int* st_rp, const int* st_ci, const int8_t* cf, const uint64_t* key,
-                     int* newc, hipStream_t s);
+                     int* newc, int* left, hipStream_t s);
 void amg_pmis_update(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
                      int8_t* cf, const int* newc, int* left, hipStream_t s);
 void amg_fill_cf(const Tile* t, int nt, int8_t* cf, int8_t val, hipStream_t s);

@@ -214,6 +214,7 @@ static void fill_stats(const SlotState& S, shapley_stats* st, double seconds) {
 // in the engine); returns the slot's status.
 static int run_amgpi(Game* g, const shapley_solve_opts& o, double eps, bool warm_from_opts,
                      hipStream_t s, SlotState& S) {
+  const bool keep = o.stream == nullptr;  // the game's own stream
   S = SlotState();
   S.g = g;
   S.opt = engine_opts_from(o, g->dim);
@@ -223,10 +224,11 @@ static int run_amgpi(Game* g, const shapley_solve_opts& o, double eps, bool warm
   } else {
     S.init_alpha = S.init_beta = true;  // v, alpha, beta already on the device
   }
-  Engine eng(s);
-  eng.slots.push_back(&S);
-  while (eng.step() > 0) {
+  EngineLease eng(s, keep);
+  eng->slots.push_back(&S);
+  while (eng->step() > 0) {
   }
+  SHP_HIP(hipStreamSynchronize(s));
   g->solved = true;
   return S.status;
 }
@@ -288,6 +290,7 @@ int shapley_game_create(shapley_game_t* out, int64_t n, int32_t m1, int32_t m2, 
     SHP_REQUIRE(out != nullptr, "out must not be null");
     Game* g = create_game(n, m1, m2, row_ptr, col, w, r, mu, valid, grid, flags, stream);
     *out = new shapley_game_s{g};
+    games_alive_add(1);
   });
 }
 
@@ -314,6 +317,7 @@ int shapley_game_create_hierarchy(shapley_game_t* out, int32_t nlev, shapley_gam
     h->n = f->n; h->m1 = f->m1; h->m2 = f->m2; h->dim = f->dim; h->s = f->s;
     h->stream = f->stream;
     *out = new shapley_game_s{h};
+    games_alive_add(1 - nlev);  // the level handles were absorbed
   });
 }
 
@@ -384,16 +388,17 @@ int shapley_solve_batch(shapley_game_t* games, int32_t count, const shapley_solv
     }
     hipStream_t s = o.stream ? (hipStream_t)o.stream : games[0]->g->stream;
     double t0 = now_s();
-    Engine eng(s);
+    EngineLease eng(s, o.stream == nullptr);
     for (int i = 0; i < count; ++i) {
       Game* g = games[i]->g;
       S[i].g = g;
       S[i].opt = engine_opts_from(o, g->dim);
       load_warm_start(g, o, S[i], s);
-      eng.slots.push_back(&S[i]);
+      eng->slots.push_back(&S[i]);
     }
-    while (eng.step() > 0) {
+    while (eng->step() > 0) {
     }
+    SHP_HIP(hipStreamSynchronize(s));
     double t1 = now_s();
     for (int i = 0; i < count; ++i) {
       games[i]->g->solved = true;
@@ -500,8 +505,19 @@ int shapley_game_bytes(shapley_game_t gh, size_t* bytes) {
 
 void shapley_game_destroy(shapley_game_t gh) {
   if (!gh) return;
+  try {
+    if (gh->g) {
+      engine_cache_drop(gh->g->stream);
+      for (Game* l : gh->g->levels) engine_cache_drop(l->stream);
+    }
+  } catch (...) {
+  }
   delete gh->g;
   delete gh;
+  try {
+    games_alive_add(-1);
+  } catch (...) {
+  }
 }
 
 }  // extern "C"

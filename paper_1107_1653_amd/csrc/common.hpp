@@ -120,6 +120,20 @@ __device__ inline void atomic_max_nonneg(double* addr, double v) {
             static_cast<unsigned long long>(__double_as_longlong(v)));
 }
 
+// Device fill by a kernel: on this runtime a memset call costs tens of
+// microseconds of queue time, a kernel launch a few.
+template <class T>
+__global__ void k_fill(T* __restrict__ p, T v, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+template <class T>
+inline void fill_async(T* p, T v, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, p, v, n);
+  SHP_LAUNCH_CHECK();
+}
+
 // ---------------------------------------------------------------------------
 // Striped per-game reductions.  Thousands of workgroups folding a value into
 // one address serialise on that address (device-scope atomics); instead each

@@ -12,6 +12,9 @@
 #include "probe.hpp"
 
 #include <algorithm>
+#include <exception>
+#include <map>
+#include <mutex>
 #include <chrono>
 #include <cmath>
 
@@ -91,11 +94,101 @@ struct PhaseTimer {
 };
 
 Engine::Engine(hipStream_t s) : stream(s) {}
+
+void* Engine::pin_take(size_t bytes) {
+  bytes = (bytes + 63) & ~(size_t)63;
+  if (pin_used + bytes > pin_cap) {
+    // a fresh, larger arena; the full one may still be the source or the
+    // target of queued copies and is released at the next synchronisation
+    if (pin) pin_old.push_back(pin);
+    pin = nullptr;
+    pin_cap = std::max<size_t>(bytes, std::max<size_t>(2 * pin_cap, 1 << 16));
+    SHP_HIP(hipHostMalloc((void**)&pin, pin_cap, hipHostMallocDefault));
+    pin_used = 0;
+  }
+  void* p = pin + pin_used;
+  pin_used += bytes;
+  return p;
+}
+
+void Engine::sync() {
+  SHP_HIP(hipStreamSynchronize(stream));
+  pin_used = 0;
+  for (char* q : pin_old) SHP_HIP(hipHostFree(q));
+  pin_old.clear();
+}
+
+void Engine::reset() {
+  slots.clear();
+  layout_dirty = true;
+  have_hier = false;
+  run_at_setup.clear();
+  changes_since_setup = 0;
+  last_cycles = 0;
+  cycles_after_full = -1;
+  stagnated = false;
+  full_setups = refreshes = 0;
+}
+
+namespace {
+// idle engines per stream; never destroyed at process exit (the runtime may
+// already be gone then), emptied when the last game handle is destroyed
+std::mutex g_cache_mu;
+auto& g_cache = *new std::map<hipStream_t, std::unique_ptr<Engine>>();
+int g_games_alive = 0;
+}  // namespace
+
+void games_alive_add(int delta) {
+  std::map<hipStream_t, std::unique_ptr<Engine>> drop;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_games_alive += delta;
+    if (g_games_alive <= 0) {
+      g_games_alive = 0;
+      drop.swap(g_cache);  // last game gone: release the workspace
+    }
+  }
+}
+
+void engine_cache_drop(hipStream_t s) {
+  std::unique_ptr<Engine> drop;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  auto it = g_cache.find(s);
+  if (it == g_cache.end()) return;
+  drop = std::move(it->second);
+  g_cache.erase(it);
+}
+
+EngineLease::EngineLease(hipStream_t s, bool keep)
+    : s_(s), keep_(keep), uncaught_(std::uncaught_exceptions()) {
+  if (keep) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find(s);
+    if (it != g_cache.end()) {
+      e_ = std::move(it->second);
+      g_cache.erase(it);
+    }
+  }
+  if (!e_) e_.reset(new Engine(s));
+  e_->reset();
+}
+
+EngineLease::~EngineLease() {
+  if (!keep_ || std::uncaught_exceptions() > uncaught_) return;  // not kept: destroyed here
+  e_->reset();
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  if (g_games_alive > 0 && !g_cache.count(s_)) g_cache[s_] = std::move(e_);
+}
 Engine::~Engine() {
   if (profiling() && !prof.empty()) {
     fprintf(stderr, "[shapley profile]");
     for (auto& p : prof) fprintf(stderr, " %s=%.2fms", p.first.c_str(), 1e3 * p.second);
     fprintf(stderr, "\n");
+  }
+  if (pin || !pin_old.empty()) {
+    (void)hipStreamSynchronize(stream);
+    if (pin) (void)hipHostFree(pin);
+    for (char* q : pin_old) (void)hipHostFree(q);
   }
 }
 
@@ -139,11 +232,11 @@ void Engine::build_layout() {
     for (int x = 0; x < gm->n; x += spb) h_gtiles_imp.push_back({g, x, std::min(x + spb, gm->n)});
   }
   ddesc.ensure(std::max(G, 1));
-  h2d(ddesc.p, hdesc.data(), G, stream);
+  up(ddesc.p, hdesc.data(), G);
   gtiles_all.ensure(std::max<size_t>(h_gtiles_all.size(), 1));
-  h2d(gtiles_all.p, h_gtiles_all.data(), h_gtiles_all.size(), stream);
+  up(gtiles_all.p, h_gtiles_all.data(), h_gtiles_all.size());
   gtiles_imp.ensure(std::max<size_t>(h_gtiles_imp.size(), 1));
-  h2d(gtiles_imp.p, h_gtiles_imp.data(), h_gtiles_imp.size(), stream);
+  up(gtiles_imp.p, h_gtiles_imp.data(), h_gtiles_imp.size());
 
   int maxlev = 2;
   for (auto* s : slots) maxlev = std::max(maxlev, s->opt.max_levels + 1);
@@ -167,8 +260,8 @@ void Engine::build_layout() {
     const size_t m = (size_t)kStripes * gp * 4;
     fold_d.ensure(m);
     fold_i.ensure(m);
-    SHP_HIP(hipMemsetAsync(fold_d.p, 0, sizeof(double) * m, stream));
-    SHP_HIP(hipMemsetAsync(fold_i.p, 0, sizeof(int) * m, stream));
+    fill_async(fold_d.p, 0.0, m, stream);
+    fill_async(fold_i.p, 0, m, stream);
     fold = Stripes{fold_d.p, fold_i.p, gp};
   }
   h_active.assign(G, 0);
@@ -185,12 +278,12 @@ void Engine::build_tiles(Level& L, const std::vector<char>& keep, bool cont_only
     L.nctiles = (int)t.size();
     L.rows_ctiles = rows;
     L.ctiles.ensure(std::max<size_t>(t.size(), 1));
-    h2d(L.ctiles.p, t.data(), t.size(), stream);
+    up(L.ctiles.p, t.data(), t.size());
   } else {
     L.ntiles = (int)t.size();
     L.rows_tiles = rows;
     L.tiles.ensure(std::max<size_t>(t.size(), 1));
-    h2d(L.tiles.p, t.data(), t.size(), stream);
+    up(L.tiles.p, t.data(), t.size());
   }
 }
 
@@ -228,7 +321,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
   }
   s_err.ensure(4);
   s_left.ensure(1);
-  SHP_HIP(hipMemsetAsync(s_err.p, 0, sizeof(int) * 4, stream));
+  fill_async(s_err.p, 0, 4, stream);
   PhaseTimer pt(this, prof);
   nlev = 0;
   int l = 0;
@@ -270,10 +363,10 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
       L.key.ensure(std::max(n, 1));
       L.cidx.ensure(n + 1);
       L.tmp.ensure(n + 1);
-      SHP_HIP(hipMemsetAsync(L.lam.p, 0, sizeof(int) * (n + 1), stream));
-      SHP_HIP(hipMemsetAsync(L.cf.p, 0xFE, n, stream));  // CF_X for rows of terminal games
-      SHP_HIP(hipMemsetAsync(L.strong.p, 0, L.nnz, stream));
-      SHP_HIP(hipMemsetAsync(L.dir.p, 1, n, stream));
+      fill_async(L.lam.p, 0, (size_t)n + 1, stream);
+      fill_async(L.cf.p, (int8_t)-2, (size_t)n, stream);  // CF_X for rows of terminal games
+      fill_async(L.strong.p, (uint8_t)0, (size_t)L.nnz, stream);
+      fill_async(L.dir.p, (uint8_t)1, (size_t)n, stream);
       amg_dirichlet(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, L.dir.p, stream);
       amg_strength(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, L.dir.p, theta, L.strong.p, L.lam.p,
                    stream);
@@ -285,45 +378,44 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
       scan_exclusive(L.lam.p, L.st_rp.p, n + 1, stream, s_scan);
       L.st_ci.ensure(std::max(L.nnz, 1));  // strong entries never exceed the entries of A
       s_cursor.ensure(n + 1);
-      SHP_HIP(hipMemsetAsync(s_cursor.p, 0, sizeof(int) * (n + 1), stream));
+      fill_async(s_cursor.p, 0, (size_t)n + 1, stream);
       amg_strength_t(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.strong.p, L.st_rp.p, s_cursor.p, L.st_ci.p,
                      stream);
       pt.mark("strength");
       // ---- PMIS
       s_goff.ensure(G + 1);
-      h2d(s_goff.p, L.goff.data(), G + 1, stream);
+      up(s_goff.p, L.goff.data(), G + 1);
       uint32_t salt = mix32(0x9E3779B9u * (uint32_t)(l + 1) + 12345u);
       amg_pmis_init(L.ctiles.p, L.nctiles, s_goff.p, L.dir.p, L.lam.p, salt, L.cf.p, L.key.p, stream);
       s_newc.ensure(std::max(n, 1));
       // rounds run in pairs between checks of the undecided count (a round
       // with nothing undecided changes nothing)
-      for (int round = 0; round < 1000; round += 2) {
-        for (int rr = 0; rr < 2; ++rr) {
+      for (int round = 0, burst = 4; round < 1000; round += burst, burst = 2) {
+        for (int rr = 0; rr < burst; ++rr) {
           amg_pmis_select(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.strong.p, L.st_rp.p, L.st_ci.p, L.cf.p,
-                          L.key.p, s_newc.p, stream);
-          SHP_HIP(hipMemsetAsync(s_left.p, 0, sizeof(int), stream));
+                          L.key.p, s_newc.p, s_left.p, stream);
           amg_pmis_update(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.strong.p, L.cf.p, s_newc.p, s_left.p,
                           stream);
         }
-        int left = 0;
-        d2h(&left, s_left.p, 1, stream);
-        SHP_HIP(hipStreamSynchronize(stream));
-        if (left == 0) break;
+        const int* left = down(s_left.p, 1);
+        sync();
+        if (*left == 0) break;
         if (round >= 998) throw Error(SHAPLEY_EDEVICE, "PMIS did not terminate");
       }
       pt.mark("pmis");
       // ---- coarse numbering and per-game coarse sizes
       auto number = [&](std::vector<int>& ncg) {
         amg_is_c(L.cf.p, L.tmp.p, n, stream);
-        SHP_HIP(hipMemsetAsync(L.tmp.p + n, 0, sizeof(int), stream));
+        fill_async(L.tmp.p + n, 0, 1, stream);
         scan_exclusive(L.tmp.p, L.cidx.p, n + 1, stream, s_scan);
         s_gidx.ensure(G + 1);
         s_gout.ensure(G + 1);
-        h2d(s_gidx.p, L.goff.data(), G + 1, stream);
+        up(s_gidx.p, L.goff.data(), G + 1);
         amg_gather_int(L.cidx.p, s_gidx.p, G + 1, s_gout.p, stream);
         std::vector<int> cpre(G + 1);
-        d2h(cpre.data(), s_gout.p, G + 1, stream);
-        SHP_HIP(hipStreamSynchronize(stream));
+        const int* cp = down(s_gout.p, G + 1);
+        sync();
+        cpre.assign(cp, cp + G + 1);
         ncg.assign(G, 0);
         for (int g = 0; g < G; ++g) ncg[g] = cpre[g + 1] - cpre[g];
         return cpre;
@@ -348,9 +440,8 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         for (int g = 0; g < G; ++g) term[g] = L.present[g] && !L.cont[g];
         std::vector<Tile> tt = make_tiles(L.goff, term, kTileRows);
         s_tiles.ensure(std::max<size_t>(tt.size(), 1));
-        h2d(s_tiles.p, tt.data(), tt.size(), stream);
+        up(s_tiles.p, tt.data(), tt.size());
         amg_fill_cf(s_tiles.p, (int)tt.size(), L.cf.p, (int8_t)-2, stream);
-        SHP_HIP(hipStreamSynchronize(stream));
         any_cont = false;
         for (int g = 0; g < G; ++g) any_cont |= (bool)L.cont[g];
         build_tiles(L, L.cont, true);
@@ -381,7 +472,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         for (int g = 0; g < G; ++g) Ln.present[g] = L.cont[g] && ncg[g] > 0;
         // ---- R = P^T
         s_cnt.ensure(nc + 1);
-        SHP_HIP(hipMemsetAsync(s_cnt.p, 0, sizeof(int) * (nc + 1), stream));
+        fill_async(s_cnt.p, 0, (size_t)nc + 1, stream);
         amg_pt_count(L.ctiles.p, L.nctiles, L.pc.p, s_cnt.p, stream);
         L.rrp.ensure(nc + 1);
         scan_exclusive(s_cnt.p, L.rrp.p, nc + 1, stream, s_scan);
@@ -389,7 +480,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         L.rci.ensure(std::max(rnnz, 1));
         L.rv64.ensure(std::max(rnnz, 1));
         s_cursor.ensure(nc + 1);
-        SHP_HIP(hipMemsetAsync(s_cursor.p, 0, sizeof(int) * (nc + 1), stream));
+        fill_async(s_cursor.p, 0, (size_t)nc + 1, stream);
         amg_pt_fill(L.ctiles.p, L.nctiles, L.pc.p, L.pv64.p, L.rrp.p, s_cursor.p, L.rci.p, L.rv64.p, stream);
         amg_sort_rows(L.rrp.p, L.rci.p, L.rv64.p, nc, stream);
         pt.mark("transpose");
@@ -398,7 +489,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         Ln.rp.ensure(nc + 1);
         s_cnt.ensure(nc + 1);
         s_toff.ensure(nc + 1);
-        SHP_HIP(hipMemsetAsync(s_cnt.p + nc, 0, sizeof(int), stream));
+        fill_async(s_cnt.p + nc, 0, 1, stream);
         amg_rap_bound(nc, L.rrp.p, L.rci.p, L.rp.p, s_cnt.p, stream);
         scan_exclusive(s_cnt.p, s_toff.p, nc + 1, stream, s_scan);
         // sum of the bounds <= PW * (pairs) <= PW * PW * nnz(A)
@@ -412,9 +503,11 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         probe_end(kProbeRap, stream, (double)L.nnz * 12 + (double)n * PW * 12 + (double)nc * 8);
         scan_exclusive(s_cnt.p, Ln.rp.p, nc + 1, stream, s_scan);
         int cnnz = 0, rnnz_used = 0;
-        d2h(&cnnz, Ln.rp.p + nc, 1, stream);
-        d2h(&rnnz_used, L.rrp.p + nc, 1, stream);
-        SHP_HIP(hipStreamSynchronize(stream));
+        const int* pc_nnz = down(Ln.rp.p + nc, 1);
+        const int* pr_nnz = down(L.rrp.p + nc, 1);
+        sync();
+        cnnz = *pc_nnz;
+        rnnz_used = *pr_nnz;
         Ln.nnz = cnnz;
         L.gR = row_group((double)rnnz_used / std::max(nc, 1));
         Ln.ci.ensure(std::max(cnnz, 1));
@@ -446,7 +539,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
     L.nblk = (int)hblk.size() / 4;
     if (L.nblk) {
       L.blk.ensure(hblk.size());
-      h2d(L.blk.p, hblk.data(), hblk.size(), stream);
+      up(L.blk.p, hblk.data(), hblk.size());
       L.dmat64.ensure(doff);
       if (mixed) L.dmat32.ensure(doff);
       const bool large = L.max_blk > kDenseWave;
@@ -479,8 +572,9 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
   }
   {
     int herr[4] = {0, 0, 0, 0};
-    d2h(herr, s_err.p, 4, stream);
-    SHP_HIP(hipStreamSynchronize(stream));
+    const int* pe = down(s_err.p, 4);
+    sync();
+    std::memcpy(herr, pe, sizeof(herr));
     if (herr[1] != 0)
       throw Error(SHAPLEY_EDEVICE, "Galerkin product: coarse row too long (code " + std::to_string(herr[1]) + ")");
     if (herr[2] != 0) throw Error(SHAPLEY_EDEVICE, "singular coarsest block");
@@ -503,7 +597,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
 void Engine::refresh(const EngineOpts& o) {
   const bool mixed = o.precision == SHAPLEY_MIXED;
   PhaseTimer pt(this, prof);
-  SHP_HIP(hipMemsetAsync(s_err.p, 0, sizeof(int) * 4, stream));
+  fill_async(s_err.p, 0, 4, stream);
   {
     Level& L0 = lv[0];
     L0.chg.ensure(std::max(L0.n, 1));
@@ -522,7 +616,7 @@ void Engine::refresh(const EngineOpts& o) {
                     stream);
       Level& Ln = lv[l + 1];
       Ln.chg.ensure(std::max(L.nc, 1));
-      SHP_HIP(hipMemsetAsync(Ln.chg.p, 0, std::max(L.nc, 1), stream));
+      fill_async(Ln.chg.p, (uint8_t)0, (size_t)std::max(L.nc, 1), stream);
       amg_mark_coarse(L.ctiles.p, L.nctiles, L.pc.p, L.chg.p, Ln.chg.p, stream);
       probe_begin(kProbeRap, stream);
       amg_rap_known(L.nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, Ln.rp.p, Ln.ci.p,
@@ -534,8 +628,9 @@ void Engine::refresh(const EngineOpts& o) {
                     s_err.p + 2, L.max_blk > kDenseWave, stream, L.chg.p);
   }
   int herr[4] = {0, 0, 0, 0};
-  d2h(herr, s_err.p, 4, stream);
-  SHP_HIP(hipStreamSynchronize(stream));
+  const int* pe = down(s_err.p, 4);
+  sync();
+  std::memcpy(herr, pe, sizeof(herr));
   pt.mark("refresh");
   if (herr[1] != 0) throw Error(SHAPLEY_EDEVICE, "Galerkin product failed during refresh");
   if (herr[2] != 0) throw Error(SHAPLEY_EDEVICE, "singular coarsest block");
@@ -605,14 +700,24 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
   const bool mixed = o.precision == SHAPLEY_MIXED;
   Level& L0 = lv[0];
   h_lin_active.assign(G, 0);
-  for (int g : run) h_lin_active[g] = 1;
-  std::vector<int> cyc(G, 0);
-  std::vector<std::vector<double>> hist(G);
-  std::vector<double> hn(4 * G), hb(G);
-  d2h(hb.data(), d_bnorm.p, G, stream);
-  SHP_HIP(hipStreamSynchronize(stream));
-  while (true) {
-    h2d(d_lin_active.p, h_lin_active.data(), G, stream);
+  h_lin.assign(G, LinCtl{});
+  for (int g : run) {
+    const SlotState* S = slots[g];
+    h_lin_active[g] = 1;
+    LinCtl& c = h_lin[g];
+    c.rtol = S->opt.lin_rtol;
+    c.atol = S->opt.lin_atol;
+    c.forcing = S->opt.forcing;
+    c.res_prev = S->res_prev;
+    c.max_cycles = S->opt.max_cycles;
+  }
+  d_lin.ensure(std::max(G, 1));
+  up(d_lin_active.p, h_lin_active.data(), G);
+  up(d_lin.p, h_lin.data(), G);
+  // The stop test runs on the device after every FP64 residual; cycles are
+  // queued in chunks ending with a residual and its test, the first chunk as
+  // long as the previous solve (cycles of games that stopped return at once).
+  auto resid_check = [&]() {
     probe_begin(kProbeResid64, stream);
     if (mixed)
       cyc_resid64<float>(L0.tiles.p, L0.ntiles, d_lin_active.p, L0.rp.p, L0.ci.p, L0.a64.p, rhs.p, sol.p,
@@ -625,50 +730,39 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
       const double nnz = L0.n ? (double)L0.nnz * rows / L0.n : 0.0;
       probe_end(kProbeResid64, stream, rows * (4 + 8 + 8 + (mixed ? 4 : 8)) + nnz * 12);
     }
-    launch_fold_finish(fold, G, 2, 0u, 0, d_norm.p, 4, nullptr, 0, stream);
-    d2h(hn.data(), d_norm.p, 4 * G, stream);
-    SHP_HIP(hipStreamSynchronize(stream));
-    bool any = false;
-    for (int g : run) {
-      if (!h_lin_active[g]) continue;
-      SlotState* S = slots[g];
-      double rn = hn[4 * g], xn = hn[4 * g + 1];
-      double tol = std::max(o.lin_rtol * std::max(hb[g], xn), o.lin_atol);
-      // inexact policy iteration: the linear solve only needs to be accurate
-      // to a fraction of the Shapley residual of the previous step
-      if (o.forcing > 0.0 && std::isfinite(S->res_prev) && S->res_prev > 0.0 && o.forcing * S->res_prev > tol) {
-        tol = o.forcing * S->res_prev;
-        S->loose = true;
+    launch_lin_check(fold, G, d_bnorm.p, d_lin.p, d_lin_active.p, d_norm.p, stream);
+  };
+  resid_check();
+  int chunk = std::max(1, std::min(last_cycles, 16));
+  while (true) {
+    for (int c = 0; c < chunk; ++c) {
+      if (mixed) {
+        float* e = vcycle_impl<float>(this, lv, 0, o, d_lin_active.p, stream);
+        cyc_update64<float>(L0.tiles.p, L0.ntiles, d_lin_active.p, e, sol.p, stream);
       } else {
-        S->loose = false;
+        double* e = vcycle_impl<double>(this, lv, 0, o, d_lin_active.p, stream);
+        cyc_update64<double>(L0.tiles.p, L0.ntiles, d_lin_active.p, e, sol.p, stream);
       }
-      auto& h = hist[g];
-      h.push_back(rn);
-      bool stop = false;
-      if (!std::isfinite(rn)) {
-        stop = true;
-        S->status = SHAPLEY_EDEVICE;
-      } else if (rn <= tol) {
-        stop = true;
-      } else if (cyc[g] >= o.max_cycles) {
-        stop = true;
-      } else if (h.size() >= 8 && rn > 0.5 * h[h.size() - 7]) {
-        stop = true;  // stagnation: no halving over six cycles
-        stagnated = true;
-      }
-      if (stop) h_lin_active[g] = 0; else any = true;
+      resid_check();
     }
+    const int* pa = down(d_lin_active.p, G);
+    sync();
+    h_lin_active.assign(pa, pa + G);
+    bool any = false;
+    for (int g : run) any |= h_lin_active[g] != 0;
     if (!any) break;
-    h2d(d_lin_active.p, h_lin_active.data(), G, stream);
-    if (mixed) {
-      float* e = vcycle_impl<float>(this, lv, 0, o, d_lin_active.p, stream);
-      cyc_update64<float>(L0.tiles.p, L0.ntiles, d_lin_active.p, e, sol.p, stream);
-    } else {
-      double* e = vcycle_impl<double>(this, lv, 0, o, d_lin_active.p, stream);
-      cyc_update64<double>(L0.tiles.p, L0.ntiles, d_lin_active.p, e, sol.p, stream);
-    }
-    for (int g : run)
-      if (h_lin_active[g]) { ++cyc[g]; ++slots[g]->cycles_total; }
+    chunk = 1;
+  }
+  const LinCtl* pl = down(d_lin.p, G);
+  sync();
+  h_lin.assign(pl, pl + G);
+  for (int g : run) {
+    SlotState* S = slots[g];
+    const LinCtl& c = h_lin[g];
+    S->cycles_total += c.cyc;
+    S->loose = (c.flags & 1) != 0;
+    if (c.flags & 4) S->status = SHAPLEY_EDEVICE;
+    if (c.flags & 2) stagnated = true;
   }
 }
 
@@ -688,10 +782,13 @@ void Engine::improve(const std::vector<int>& run, double tie_rtol) {
   launch_fold_finish(fold, G, 2, 2u, 2, d_shap.p, 2, d_cnt.p, 2, stream);
 }
 
+// The decisions are applied asynchronously (the host copy stays alive in a
+// member until the next step); callers synchronise the stream before
+// reading results.
 void Engine::apply_decisions(const std::vector<int>& code) {
-  h2d(d_decision.p, code.data(), G, stream);
+  h_decision = code;
+  up(d_decision.p, h_decision.data(), G);
   launch_apply(ddesc.p, gtiles_all.p, (int)h_gtiles_all.size(), d_decision.p, stream);
-  SHP_HIP(hipStreamSynchronize(stream));
 }
 
 void Engine::run_init(const std::vector<int>& run) {
@@ -701,11 +798,12 @@ void Engine::run_init(const std::vector<int>& run) {
   if (fresh.empty()) return;
   std::vector<int> act(G, 0);
   for (int g : fresh) act[g] = 1;
-  h2d(d_active.p, act.data(), G, stream);
+  up(d_active.p, act.data(), G);
   improve(fresh, slots[fresh[0]]->opt.tie_rtol);
   std::vector<double> hs(2 * G);
-  d2h(hs.data(), d_shap.p, 2 * G, stream);
-  SHP_HIP(hipStreamSynchronize(stream));
+  const double* ps = down(d_shap.p, 2 * G);
+  sync();
+  hs.assign(ps, ps + 2 * G);
   std::vector<int> code(G, 0);
   for (int g : fresh) {
     SlotState* S = slots[g];
@@ -721,9 +819,9 @@ void Engine::improve_only() {
   std::vector<int> all;
   for (int g = 0; g < G; ++g) all.push_back(g);
   std::vector<int> act(G, 1);
-  h2d(d_active.p, act.data(), G, stream);
+  up(d_active.p, act.data(), G);
   improve(all, slots.empty() ? 1e-12 : slots[0]->opt.tie_rtol);
-  SHP_HIP(hipStreamSynchronize(stream));
+  sync();
 }
 
 int Engine::step() {
@@ -738,7 +836,7 @@ int Engine::step() {
   d_bnorm.ensure(std::max(G, 1));
   h_active.assign(G, 0);
   for (int g : run) h_active[g] = 1;
-  h2d(d_active.p, h_active.data(), G, stream);
+  up(d_active.p, h_active.data(), G);
 
   double t0 = now_s();
   PhaseTimer pt(this, prof);
@@ -765,8 +863,7 @@ int Engine::step() {
     ++refreshes;
   }
   pt.mark("setup");
-  SHP_HIP(hipStreamSynchronize(stream));
-  double t1 = now_s();
+  double t1 = now_s();  // setup and refresh end with a synchronisation
   {
     std::vector<int> before(G);
     for (int g : run) before[g] = slots[g]->cycles_total;
@@ -777,15 +874,16 @@ int Engine::step() {
     if (cycles_after_full < 0) cycles_after_full = mx;
   }
   pt.mark("solve");
+  double t2 = now_s();  // solve_linear ends with a synchronisation
   launch_scatter_v(ddesc.p, gtiles_all.p, (int)h_gtiles_all.size(), d_active.p, sol.p, stream);
-  SHP_HIP(hipStreamSynchronize(stream));
-  double t2 = now_s();
   improve(run, o.tie_rtol);
   std::vector<double> hs(2 * G);
   std::vector<int> hc(2 * G);
-  d2h(hs.data(), d_shap.p, 2 * G, stream);
-  d2h(hc.data(), d_cnt.p, 2 * G, stream);
-  SHP_HIP(hipStreamSynchronize(stream));
+  const double* ps = down(d_shap.p, 2 * G);
+  const int* pcn = down(d_cnt.p, 2 * G);
+  sync();
+  hs.assign(ps, ps + 2 * G);
+  hc.assign(pcn, pcn + 2 * G);
   double t3 = now_s();
   pt.mark("improve");
 

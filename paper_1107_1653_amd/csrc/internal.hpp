@@ -4,6 +4,7 @@
 #include "../../include/shapley.h"
 #include "common.hpp"
 
+#include <cstring>
 #include <memory>
 
 namespace shp {
@@ -152,6 +153,16 @@ struct SlotState {
   double bnorm = 0.0;
 };
 
+// Per-game control of the refinement loop (FP64 residual, stop test, cycle
+// count), kept on the device so that several cycles can be queued between
+// two host checks.  flags: 1 forcing tolerance used, 2 stagnated (no halving
+// over six cycles), 4 non-finite residual, 8 cycle limit reached.
+struct LinCtl {
+  double rtol, atol, forcing, res_prev;
+  double hist[8];  // last residual norms, entry i at hist[i % 8]
+  int max_cycles, cyc, nh, flags;
+};
+
 // Lock-step policy-iteration engine over a set of games (one slot per game).
 class Engine {
  public:
@@ -163,11 +174,37 @@ class Engine {
   // Returns the number of slots still running.
   int step();
   void invalidate_layout() { layout_dirty = true; have_hier = false; }
+  // Small host <-> device transfers go through a pinned bump arena (pageable
+  // copies are staged and can wait for the whole queue); the arena is reset
+  // at every synchronisation of the engine's stream.
+  void sync();
+  template <class T>
+  void up(T* dst, const T* src, size_t n) {
+    if (n == 0) return;
+    void* st = pin_take(sizeof(T) * n);
+    std::memcpy(st, src, sizeof(T) * n);
+    SHP_HIP(hipMemcpyAsync(dst, st, sizeof(T) * n, hipMemcpyHostToDevice, stream));
+  }
+  // device -> pinned arena; the returned pointer is valid after sync() until
+  // the next transfer
+  template <class T>
+  const T* down(const T* src, size_t n) {
+    T* st = static_cast<T*>(pin_take(sizeof(T) * std::max<size_t>(n, 1)));
+    if (n) SHP_HIP(hipMemcpyAsync(st, src, sizeof(T) * n, hipMemcpyDeviceToHost, stream));
+    return st;
+  }
+  // Forgets the slots and the hierarchy; keeps the device buffers, so that
+  // a reused engine allocates nothing for games no larger than before.
+  void reset();
   // Evaluates the improvement sweep at the slots' current v (no decisions).
   void improve_only();
 
  private:
   bool layout_dirty = true;
+  char* pin = nullptr;
+  std::vector<char*> pin_old;  // full arenas, released at the next sync()
+  size_t pin_cap = 0, pin_used = 0;
+  void* pin_take(size_t bytes);
   int G = 0, N0 = 0, NNZ0 = 0;
   std::vector<int> x_off, a_off;
   std::vector<GameDesc> hdesc;
@@ -181,6 +218,9 @@ class Engine {
   DBuf<double> d_norm;                        // [4*G] res max, x max, b max, spare
   DBuf<double> d_shap;                        // [2*G] shapley residual max, sum sq
   DBuf<int> d_decision;
+  DBuf<LinCtl> d_lin;
+  std::vector<LinCtl> h_lin;
+  std::vector<int> h_decision;
   // striped reduction copies (kept cleared between uses)
   DBuf<double> fold_d;
   DBuf<int> fold_i;
@@ -219,6 +259,26 @@ class Engine {
   void build_tiles(Level& L, const std::vector<char>& keep, bool cont_only);
 };
 
+// Engines (with their device workspace) are kept per game stream between
+// solves; a lease takes the idle engine of a stream or makes one, and gives
+// it back unless the solve failed or `keep` is false (a caller's stream,
+// whose lifetime the library does not know).  Destroying a game drops the
+// engine of its stream first.
+class EngineLease {
+ public:
+  EngineLease(hipStream_t s, bool keep);
+  ~EngineLease();
+  Engine& operator*() { return *e_; }
+  Engine* operator->() { return e_.get(); }
+ private:
+  std::unique_ptr<Engine> e_;
+  hipStream_t s_;
+  bool keep_;
+  int uncaught_;
+};
+void games_alive_add(int delta);      // game handles created (+1) / destroyed (-1)
+void engine_cache_drop(hipStream_t s);  // before a stream is destroyed
+
 // FAMGpi transfers between two grid levels of the same game family.
 void fmg_transfer(Game* coarse, Game* fine, hipStream_t s);
 
@@ -236,6 +296,10 @@ void launch_improve(const GameDesc* d, const GTile* t, int nt, const int* active
                     Stripes red, hipStream_t s);
 void launch_fold_finish(Stripes st, int G, int nd, unsigned sum_mask, int ni, double* out_d, int sd, int* out_i,
                         int si, hipStream_t s);
+// combines the FP64-residual stripes (max |r|, max |x|) and takes the stop
+// decision of each game whose lin_active flag is set
+void launch_lin_check(Stripes st, int G, const double* bnorm, LinCtl* ctl, int* lin_active, double* norm,
+                      hipStream_t s);
 void launch_apply(const GameDesc* d, const GTile* t, int nt, const int* decision, hipStream_t s);
 void launch_union_count(const int* rp, const int* ci, int n, int m1, int m2, int* cnt, int* err,
                         hipStream_t s);

@@ -150,6 +150,7 @@ static int server_step(shapley_server_s* srv) {
     eng.invalidate_layout();
   }
   eng.step();
+  SHP_HIP(hipStreamSynchronize(srv->stream));
   std::vector<Request*> keep;
   bool moved = false;
   for (Request* r : srv->active) {

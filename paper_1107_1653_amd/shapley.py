@@ -88,6 +88,14 @@ def lib() -> C.CDLL:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_1107_1653_amd.build`")
+        # PyTorch ships its own HIP runtime under the same soname.  Loaded
+        # first, it is the one the library binds to, so that PyTorch's
+        # streams and device pointers can be handed to the library; loaded
+        # second, the process would hold two runtimes that do not share them.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.shapley_last_error.restype = C.c_char_p

@@ -209,3 +209,33 @@ def test_reuse_and_forcing_reach_the_same_fixed_point():
         err, ma, mb, _ = compare_with_oracle(g, v, a, b, ref, 1e-9)
         log(f"  reuse {reuse} forcing {forcing}: err {err:.2e} outer {st['outer']} cycles {st['cycles_total']}")
         assert err <= 1e-9 and len(ma) == 0
+
+
+def test_workspace_reuse_and_release():
+    """Solves reuse the workspace kept for a game's stream: repeated solves,
+    batches and hierarchies give identical results, and destroying games in
+    any order releases the workspace without touching destroyed streams."""
+    import torch
+    ga, gb = configs.c0(s=17), configs.c1(points=33)
+    ha, hb = P.create_from(ga), P.create_from(gb)
+    o = P.shapley_default_opts(**LIMITS)
+    P.shapley_solve(ha, o)
+    v1 = P.shapley_get_value(ha)
+    P.shapley_solve(hb, o)
+    P.shapley_solve(ha, o)                       # engine reused after another game
+    v2 = P.shapley_get_value(ha)
+    np.testing.assert_array_equal(v1, v2)
+    P.shapley_solve_batch([hb, ha], o)            # cached under hb's stream
+    v3 = P.shapley_get_value(ha)
+    assert np.max(np.abs(v3 - v1)) <= 1e-12 * np.max(np.abs(v1))
+    s = torch.cuda.Stream()
+    os_ = P.shapley_default_opts(stream=s.cuda_stream, **LIMITS)  # caller's stream: not kept
+    P.shapley_solve(ha, os_)
+    np.testing.assert_array_equal(P.shapley_get_value(ha), v1)
+    P.shapley_game_destroy(hb)                    # drops the batch engine first
+    P.shapley_game_destroy(ha)
+    hc = P.create_from(ga)
+    P.shapley_solve(hc, o)
+    np.testing.assert_array_equal(P.shapley_get_value(hc), v1)
+    P.shapley_game_destroy(hc)
+    log("  workspace reuse ok")
