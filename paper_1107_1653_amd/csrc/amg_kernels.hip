@@ -726,6 +726,34 @@ constexpr int kRapND = kRapMaxCols;  // max distinct columns of one coarse row
 constexpr int kRapChunk = 256;     // (R, A) pairs per product chunk
 enum { kRapFused = 0, kRapKnown = 1 };
 
+// ascending bitonic sort of one value per lane across a wavefront (64 lanes)
+__device__ inline void wave_sort64(int& key, double& val) {
+  const int lane = threadIdx.x & 63;
+  for (int k2 = 2; k2 <= 64; k2 <<= 1) {
+    for (int j = k2 >> 1; j > 0; j >>= 1) {
+      const int ok = __shfl_xor(key, j);
+      const double ov = __shfl_xor(val, j);
+      const bool up = (lane & k2) == 0;
+      const bool low = (lane & j) == 0;
+      if ((up == low) ? (ok < key) : (ok > key)) {
+        key = ok;
+        val = ov;
+      }
+    }
+  }
+}
+__device__ inline void wave_sort64(int& key) {
+  const int lane = threadIdx.x & 63;
+  for (int k2 = 2; k2 <= 64; k2 <<= 1) {
+    for (int j = k2 >> 1; j > 0; j >>= 1) {
+      const int ok = __shfl_xor(key, j);
+      const bool up = (lane & k2) == 0;
+      const bool low = (lane & j) == 0;
+      if ((up == low) ? (ok < key) : (ok > key)) key = ok;
+    }
+  }
+}
+
 __device__ inline int rap_locate(const int* rO, int P, int f) {
   int lo = 0, hi = P - 1;  // largest p with rO[p] <= f
   while (lo < hi) {
@@ -853,6 +881,15 @@ __global__ __launch_bounds__(NT) void k_rap(int nc, const int* __restrict__ rrp,
     nd = nd_sh < kRapND ? nd_sh : kRapND;
     int P2 = 1;
     while (P2 < nd) P2 <<= 1;
+    if (P2 <= 64) {  // one wavefront sorts in registers
+      if (tid < 64) {
+        int key = lane < nd ? lst[lane] : INT_MAX;
+        wave_sort64(key);
+        if (lane < nd) lst[lane] = key;
+      }
+      __syncthreads();
+      P2 = 1;  // nothing left for the block-wide network below
+    }
     for (int h = nd + tid; h < P2; h += NT) lst[h] = INT_MAX;
     __syncthreads();
     for (int k2 = 2; k2 <= P2; k2 <<= 1) {
@@ -905,48 +942,38 @@ __global__ __launch_bounds__(NT) void k_rap(int nc, const int* __restrict__ rrp,
         pval[slot] = val;
       }
     }
-    // products sorted by (output position, slot): each output column's
-    // products become one run in slot order, which its owner sums in that
-    // order (the same order for any launch shape)
+    // products sorted by (output position, slot) within runs of 64 slots
+    // (one wavefront sorts a run in registers); each output column's
+    // products of a run are then contiguous, in slot order, and its owner
+    // adds them run by run, i.e. in slot order (the same order for any
+    // launch shape)
     const int ns = (fe - f0) * PW;
-    int NS2 = 1;
-    while (NS2 < ns) NS2 <<= 1;
-    for (int t = ns + tid; t < NS2; t += NT) skey[t] = INT_MAX;
+    const int nruns = (ns + 63) >> 6;
     __syncthreads();
-    for (int k2 = 2; k2 <= NS2; k2 <<= 1) {
-      for (int j = k2 >> 1; j > 0; j >>= 1) {
-        for (int idx = tid; idx < NS2; idx += NT) {
-          const int ixj = idx ^ j;
-          if (ixj > idx) {
-            const int x = skey[idx], y = skey[ixj];
-            const bool up = (idx & k2) == 0;
-            if ((x > y) == up) {
-              skey[idx] = y;
-              skey[ixj] = x;
-              const double vx = pval[idx];
-              pval[idx] = pval[ixj];
-              pval[ixj] = vx;
-            }
-          }
-        }
-        __syncthreads();
-      }
+    for (int r = tid >> 6; r < nruns; r += NT / 64) {
+      const int sl = (r << 6) + lane;
+      int key = sl < ns ? skey[sl] : INT_MAX;
+      double val = sl < ns ? pval[sl] : 0.0;
+      wave_sort64(key, val);
+      skey[sl] = key;  // sl < 64 * nruns <= kRapChunk * PW
+      pval[sl] = val;
     }
-    auto lower = [&](int key) {  // first index with skey >= key
-      int lo = 0, hi = NS2;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (skey[mid] < key) lo = mid + 1; else hi = mid;
-      }
-      return lo;
-    };
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       const int pos = j * NT + tid;
       if (pos < nd) {
-        const int t1 = lower((pos + 1) << 10);
+        const int k0 = pos << 10, k1 = (pos + 1) << 10;
         double acc = reg[j];
-        for (int t = lower(pos << 10); t < t1; ++t) acc += pval[t];
+        for (int r = 0; r < nruns; ++r) {
+          const int b = r << 6;
+          int lo = 0, hi = 64;  // first index of the run with key >= k0
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (skey[b + mid] < k0) lo = mid + 1; else hi = mid;
+          }
+          for (int t = b + lo; t < b + 64 && skey[t] < k1; ++t) acc += pval[t];
+        }
         reg[j] = acc;
       }
     }
