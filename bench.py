@@ -76,7 +76,7 @@ def parse_args():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--points", type=int, default=1025)
-    ap.add_argument("--cpu-points", type=int, default=513)
+    ap.add_argument("--cpu-points", type=int, default=1025)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--amgpi", action="store_true")
@@ -105,6 +105,26 @@ def base_record(args, value, ms_per_step, dtype, config):
     return {"metric": METRIC, "value": value, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_obstacle1025_famg_fp64.json")
+
+
+def measured_traffic(family):
+    """HBM bytes per launch of a kernel family from the committed counter
+    summary, or None when it is missing or the kernel sources changed since."""
+    from paper_1107_1653_amd import rocprof_summary
+    try:
+        with open(TRAFFIC_FILE) as f:
+            d = json.load(f)
+    except OSError:
+        return None, "no counter summary"
+    if d.get("source_sha256") != rocprof_summary.source_hash():
+        return None, "kernel sources changed since the counters were taken"
+    fam = d.get("families", {}).get(family)
+    if fam is None:
+        return None, "family not in the counter summary"
+    return fam["bytes_per_launch"], os.path.relpath(TRAFFIC_FILE, ROOT)
 
 
 def calibration_kernel():
@@ -209,8 +229,9 @@ def run_c1(args) -> int:
         log(f"[bench] AMGpi FP64: {dt:.2f} s, outer {sa['outer']}")
 
     achieved = (pr["bytes"] / max(pr["launches"], 1)) / (pr["ms"] / max(pr["launches"], 1) * 1e-3) / 1e9
+    traffic, tsrc = measured_traffic(fam)
     roof = {"bound": "hbm", "kernel": fam, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": tsrc,
             "launches": pr["launches"], "avg_launch_us": 1e3 * pr["ms"] / max(pr["launches"], 1),
             "alg_bytes_per_launch": pr["bytes"] / max(pr["launches"], 1)}
 

@@ -26,6 +26,31 @@ __global__ void k_dirichlet(const Tile* __restrict__ tiles, const int* __restric
   dir[i] = any ? 0 : 1;
 }
 
+// numeric refresh of the relaxation data of a level's rows in one pass:
+// Dirichlet flag (no nonzero off-diagonal entry), 1/a_ii (recomputed, or kept
+// when `keep_diag`, e.g. from the assembly), divided by omega on Dirichlet
+// rows so that the weighted relaxation solves them exactly
+__global__ void k_diag_dir(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                           const int* __restrict__ ci, const double* __restrict__ a, int keep_diag,
+                           double inv_omega, uint8_t* __restrict__ dir, double* __restrict__ d64,
+                           float* __restrict__ d32) {
+  const Tile t = tiles[blockIdx.x];
+  const int i = t.r0 + threadIdx.x;
+  if (i >= t.r1) return;
+  bool any = false;
+  double d = 0.0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const int c = ci[e];
+    const double x = a[e];
+    if (c == i) d += x; else if (x != 0.0) any = true;
+  }
+  double di = keep_diag ? d64[i] : (d != 0.0 ? 1.0 / d : 0.0);
+  if (!any) di *= inv_omega;
+  dir[i] = any ? 0 : 1;
+  d64[i] = di;
+  if (d32) d32[i] = (float)di;
+}
+
 __global__ void k_dir_scale(const Tile* __restrict__ tiles, const uint8_t* __restrict__ dir, double f,
                             double* __restrict__ d64, float* __restrict__ d32) {
   Tile t = tiles[blockIdx.x];
@@ -691,20 +716,6 @@ __global__ void k_pt_fill(const Tile* __restrict__ tiles, const int* __restrict_
   }
 }
 
-__global__ void k_sort_rows(const int* __restrict__ rp, int* __restrict__ ci, double* __restrict__ v,
-                            int n) {
-  int I = blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= n) return;
-  int e0 = rp[I], e1 = rp[I + 1];
-  for (int e = e0 + 1; e < e1; ++e) {
-    int c = ci[e];
-    double x = v[e];
-    int f = e - 1;
-    while (f >= e0 && ci[f] > c) { ci[f + 1] = ci[f]; v[f + 1] = v[f]; --f; }
-    ci[f + 1] = c;
-    v[f + 1] = x;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Galerkin product A_c = R A P, one workgroup of NT threads per coarse row.
@@ -751,6 +762,35 @@ __device__ inline void wave_sort64(int& key) {
       const bool low = (lane & j) == 0;
       if ((up == low) ? (ok < key) : (ok > key)) key = ok;
     }
+  }
+}
+
+// rows of R = P^T sorted by column, one wavefront per row (rows longer than
+// a wavefront, rare, by one lane)
+__global__ __launch_bounds__(256) void k_sort_rows_wave(const int* __restrict__ rp, int* __restrict__ ci,
+                                                        double* __restrict__ v, int n) {
+  const int I = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (I >= n) return;  // uniform per wavefront
+  const int e0 = rp[I], len = rp[I + 1] - e0;
+  if (len <= 64) {
+    int key = lane < len ? ci[e0 + lane] : INT_MAX;
+    double val = lane < len ? v[e0 + lane] : 0.0;
+    wave_sort64(key, val);
+    if (lane < len) {
+      ci[e0 + lane] = key;
+      v[e0 + lane] = val;
+    }
+    return;
+  }
+  if (lane != 0) return;
+  for (int e = e0 + 1; e < e0 + len; ++e) {
+    const int c = ci[e];
+    const double x = v[e];
+    int f = e - 1;
+    while (f >= e0 && ci[f] > c) { ci[f + 1] = ci[f]; v[f + 1] = v[f]; --f; }
+    ci[f + 1] = c;
+    v[f + 1] = x;
   }
 }
 
@@ -1448,6 +1488,13 @@ void amg_dirichlet(const Tile* t, int nt, const int* rp, const int* ci, const do
   hipLaunchKernelGGL(k_dirichlet, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, a, dir);
   SHP_LAUNCH_CHECK();
 }
+void amg_diag_dir(const Tile* t, int nt, const int* rp, const int* ci, const double* a, bool keep_diag,
+                  double inv_omega, uint8_t* dir, double* d64, float* d32, hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_diag_dir, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, a, keep_diag ? 1 : 0, inv_omega, dir,
+                     d64, d32);
+  SHP_LAUNCH_CHECK();
+}
 void amg_dir_scale(const Tile* t, int nt, const uint8_t* dir, double f, double* d64, float* d32,
                    hipStream_t s) {
   if (!nt) return;
@@ -1530,7 +1577,7 @@ void amg_pt_fill(const Tile* t, int nt, const int* pc, const double* pv, const i
 }
 void amg_sort_rows(const int* rp, int* ci, double* v, int n, hipStream_t s) {
   if (!n) return;
-  hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(n)), dim3(kBlock), 0, s, rp, ci, v, n);
+  hipLaunchKernelGGL(k_sort_rows_wave, dim3((n + 3) / 4), dim3(256), 0, s, rp, ci, v, n);
   SHP_LAUNCH_CHECK();
 }
 void amg_rap_bound(int nc, const int* rrp, const int* rci, const int* rp, int* ub, hipStream_t s) {

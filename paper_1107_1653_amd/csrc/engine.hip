@@ -606,14 +606,12 @@ void Engine::refresh(const EngineOpts& o) {
   for (int l = 0; l < nlev; ++l) {
     Level& L = lv[l];
     const int n = L.n;
-    if (l > 0) {
-      amg_diag_inv(n, L.rp.p, L.ci.p, L.a64.p, L.dinv64.p, mixed ? L.dinv32.p : nullptr, stream);
-      if (mixed) amg_cast(L.a64.p, L.a32.p, L.nnz, stream);
-    }
+    if (l > 0 && mixed) amg_cast(L.a64.p, L.a32.p, L.nnz, stream);
     if (L.nctiles) {
-      amg_dirichlet(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, L.dir.p, stream);
-      amg_dir_scale(L.ctiles.p, L.nctiles, L.dir.p, 1.0 / o.omega, L.dinv64.p, mixed ? L.dinv32.p : nullptr,
-                    stream);
+      // relaxation data of the smoothed rows (level 0 keeps the assembled
+      // diagonal); rows of games that end here use the dense inverse instead
+      amg_diag_dir(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, l == 0, 1.0 / o.omega, L.dir.p, L.dinv64.p,
+                   mixed ? L.dinv32.p : nullptr, stream);
       Level& Ln = lv[l + 1];
       Ln.chg.ensure(std::max(L.nc, 1));
       fill_async(Ln.chg.p, (uint8_t)0, (size_t)std::max(L.nc, 1), stream);

@@ -1,0 +1,161 @@
+"""Summaries of rocprofv3 output for this library's kernels.
+
+    python -m paper_1107_1653_amd.rocprof_summary trace <results.db> [--top N]
+        per-kernel calls / total / average duration from a --kernel-trace
+        results database, and the same per probe family
+    python -m paper_1107_1653_amd.rocprof_summary traffic <fetch.csv> <write.csv> --out <json>
+        HBM bytes per launch of each probe family from two --pmc runs
+        (FETCH_SIZE, then WRITE_SIZE, output format csv) of a benchmark run
+        made with --calibrate-copy: both counters are scaled by what they
+        read for the calibration kernel, which reads and writes a known size
+
+Probe families are the kernel groups the library can time with HIP events
+(shapley_probe_enable): smooth, resid64, improve, resid, restrict, prolong,
+rap (Galerkin product, both passes), interp.
+"""
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+import sqlite3
+import sys
+
+CALIB_BYTES = 1 << 30  # must match the benchmark's calibration kernel
+
+_FAMILIES = (  # (substring of the kernel name, family); first match wins
+    ("k_resid64", "resid64"),
+    ("k_smooth", "smooth"),
+    ("k_improve", "improve"),
+    ("k_resid<", "resid"),
+    ("k_restrict", "restrict"),
+    ("k_prolong", "prolong"),
+    ("k_rap<", "rap"),
+    ("k_interp", "interp"),
+)
+
+
+def family_of(name: str):
+    for key, fam in _FAMILIES:
+        if key in name:
+            return fam
+    return None
+
+
+def short_name(name: str) -> str:
+    return name.split("(")[0].replace("void ", "").strip()
+
+
+def source_hash() -> str:
+    """sha256 over the HIP sources and headers of the library (kernels and
+    launch code): traffic figures are valid only for the sources measured."""
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(here)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(here, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def kernel_stats(db_path: str):
+    db = sqlite3.connect(db_path)
+    cur = db.cursor()
+    cols = [r[1] for r in cur.execute("pragma table_info(kernels)")]
+    ni = cols.index("name") if "name" in cols else cols.index("kernel_name")
+    si, ei = cols.index("start"), cols.index("end")
+    agg = collections.defaultdict(lambda: [0, 0.0])
+    for r in cur.execute("select * from kernels"):
+        a = agg[short_name(r[ni])]
+        a[0] += 1
+        a[1] += (r[ei] - r[si]) / 1e3  # ns -> us
+    db.close()
+    return sorted(((k, c, t, t / c) for k, (c, t) in agg.items()), key=lambda x: -x[2])
+
+
+def trace_summary(db_path: str, top: int = 25) -> str:
+    rows = kernel_stats(db_path)
+    total = sum(r[2] for r in rows)
+    lines = [f"total kernel time {total / 1e3:.2f} ms over {sum(r[1] for r in rows)} launches", "",
+             "| kernel | calls | total ms | avg us | share |", "|---|---|---|---|---|"]
+    for k, c, t, a in rows[:top]:
+        lines.append(f"| `{k}` | {c} | {t / 1e3:.2f} | {a:.2f} | {100 * t / total:.1f}% |")
+    fam = collections.defaultdict(lambda: [0, 0.0])
+    for k, c, t, a in rows:
+        f = family_of(k)
+        if f:
+            fam[f][0] += c
+            fam[f][1] += t
+    lines += ["", "| probe family | calls | total ms | avg us per launch |", "|---|---|---|---|"]
+    for f, (c, t) in sorted(fam.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"| {f} | {c} | {t / 1e3:.2f} | {t / c:.2f} |")
+    return "\n".join(lines)
+
+
+def _load_counter(path: str, counter: str):
+    out = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter:
+                out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return out
+
+
+def traffic(fetch_csv: str, write_csv: str) -> dict:
+    fetch = _load_counter(fetch_csv, "FETCH_SIZE")
+    write = _load_counter(write_csv, "WRITE_SIZE")
+    cal_f = [v for k, v in fetch if "neg_kernel" in k]
+    cal_w = [v for k, v in write if "neg_kernel" in k]
+    if not cal_f or not cal_w:
+        raise RuntimeError("no calibration kernel in the counter runs (use --calibrate-copy)")
+    ff = CALIB_BYTES / (cal_f[0] * 1024.0)  # counters are in KiB
+    fw = CALIB_BYTES / (cal_w[0] * 1024.0)
+    fam = collections.defaultdict(lambda: {"launches": 0, "fetch_kib": 0.0, "write_kib": 0.0})
+    for k, v in fetch:
+        f = family_of(k)
+        if f:
+            fam[f]["launches"] += 1
+            fam[f]["fetch_kib"] += v
+    for k, v in write:
+        f = family_of(k)
+        if f:
+            fam[f]["write_kib"] += v
+    out = {"calibration": {"bytes": CALIB_BYTES, "fetch_kib": cal_f[0], "write_kib": cal_w[0],
+                           "fetch_factor": ff, "write_factor": fw},
+           "families": {}}
+    for f, d in fam.items():
+        n = max(d["launches"], 1)
+        fb = ff * d["fetch_kib"] * 1024.0 / n
+        wb = fw * d["write_kib"] * 1024.0 / n
+        out["families"][f] = {"launches": d["launches"], "fetch_bytes_per_launch": fb,
+                              "write_bytes_per_launch": wb, "bytes_per_launch": fb + wb}
+    return out
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("db")
+    t.add_argument("--top", type=int, default=25)
+    c = sub.add_parser("traffic")
+    c.add_argument("fetch_csv")
+    c.add_argument("write_csv")
+    c.add_argument("--out", required=True)
+    c.add_argument("--command", default="")
+    a = ap.parse_args(argv)
+    if a.cmd == "trace":
+        print(trace_summary(a.db, a.top))
+    else:
+        d = traffic(a.fetch_csv, a.write_csv)
+        d["source_sha256"] = source_hash()
+        d["command"] = a.command
+        with open(a.out, "w") as f:
+            json.dump(d, f, indent=1)
+        print(json.dumps(d["families"], indent=1))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
