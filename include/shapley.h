@@ -243,7 +243,8 @@ enum {
   SHAPLEY_PROBE_RESTRICT = 4, /* restriction R r */
   SHAPLEY_PROBE_PROLONG = 5,  /* prolongation + correction u += P e */
   SHAPLEY_PROBE_RAP = 6,      /* Galerkin product (setup) */
-  SHAPLEY_PROBE_INTERP = 7    /* interpolation (setup) */
+  SHAPLEY_PROBE_INTERP = 7,   /* interpolation (setup) */
+  SHAPLEY_PROBE_TAIL = 8      /* coarse levels of a game's V-cycle in one workgroup */
 };
 
 /* Enables (on != 0) or disables the timing probe of one kernel family and

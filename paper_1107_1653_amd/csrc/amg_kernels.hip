@@ -1420,6 +1420,97 @@ __global__ __launch_bounds__(256) void k_prolong(const Tile* __restrict__ tiles,
   x[i] = s;
 }
 
+// V-cycle tail of one game per workgroup (see amg_kernels.hpp).  Same steps
+// as the level-by-level cycle: nu1 weighted-Jacobi sweeps from zero, residual,
+// restriction, the coarser levels, prolongation and correction, nu2 sweeps;
+// the dense inverse on the game's last level.
+template <class T>
+__global__ __launch_bounds__(kTailThreads) void k_tail(const int* __restrict__ games, int l0, int nlev, int G,
+                                                       const TailLev<T>* __restrict__ lvs,
+                                                       const TailGL* __restrict__ gls, const int* __restrict__ act,
+                                                       T omega, int nu1, int nu2, int out_y) {
+  const int g = games[blockIdx.x];
+  if (!act[g]) return;
+  const int tid = threadIdx.x;
+  unsigned parity = 0;  // bit l: the level-l iterate is in y
+  int deep = l0;
+  // ---- down
+  for (int l = l0; l < nlev; ++l) {
+    const TailGL q = gls[(size_t)l * G + g];
+    const TailLev<T> L = lvs[l];
+    deep = l;
+    if (q.flags & kTailDense) {
+      const int nb = q.r1 - q.r0;
+      for (int i = tid; i < nb; i += kTailThreads) {
+        T acc = 0;
+        for (int j = 0; j < nb; ++j) acc += L.dm[(size_t)q.doff + (size_t)j * nb + i] * L.b[q.r0 + j];
+        L.x[q.r0 + i] = acc;
+      }
+      __syncthreads();
+      break;
+    }
+    if (!(q.flags & kTailCont)) break;
+    T* cur = L.x;
+    T* nxt = L.y;
+    for (int i = q.r0 + tid; i < q.r1; i += kTailThreads) cur[i] = omega * L.d[i] * L.b[i];
+    __syncthreads();
+    for (int k = 1; k < nu1; ++k) {
+      for (int i = q.r0 + tid; i < q.r1; i += kTailThreads)
+        nxt[i] = cur[i] + omega * L.d[i] * (L.b[i] - row_dot<T, T, 1>(L.ci, L.a, cur, L.rp[i], L.rp[i + 1], 0));
+      __syncthreads();
+      T* t = cur; cur = nxt; nxt = t;
+    }
+    if (cur == L.y) parity |= 1u << l;
+    if (!(q.flags & kTailNext)) break;  // no coarse rows: smoothing only
+    for (int i = q.r0 + tid; i < q.r1; i += kTailThreads)
+      L.r[i] = L.b[i] - row_dot<T, T, 1>(L.ci, L.a, cur, L.rp[i], L.rp[i + 1], 0);
+    __syncthreads();
+    const TailGL qn = gls[(size_t)(l + 1) * G + g];
+    const TailLev<T> Ln = lvs[l + 1];
+    for (int I = qn.r0 + tid; I < qn.r1; I += kTailThreads)
+      Ln.b[I] = row_dot<T, T, 1>(L.rci, L.rv, L.r, L.rrp[I], L.rrp[I + 1], 0);
+    __syncthreads();
+  }
+  // ---- up
+  for (int l = deep; l >= l0; --l) {
+    const TailGL q = gls[(size_t)l * G + g];
+    if (!(q.flags & kTailCont) || (q.flags & kTailDense)) continue;  // the dense result is in x
+    const TailLev<T> L = lvs[l];
+    T* cur = ((parity >> l) & 1u) ? L.y : L.x;
+    T* nxt = ((parity >> l) & 1u) ? L.x : L.y;
+    if (l < deep) {
+      const TailLev<T> Ln = lvs[l + 1];
+      const T* xc = ((parity >> (l + 1)) & 1u) ? Ln.y : Ln.x;
+      for (int i = q.r0 + tid; i < q.r1; i += kTailThreads) {
+        T acc = cur[i];
+#pragma unroll
+        for (int k = 0; k < PW; ++k) {
+          const int c = L.pc[(size_t)i * PW + k];
+          if (c >= 0) acc += L.pv[(size_t)i * PW + k] * xc[c];
+        }
+        cur[i] = acc;
+      }
+      __syncthreads();
+    }
+    for (int k = 0; k < nu2; ++k) {
+      for (int i = q.r0 + tid; i < q.r1; i += kTailThreads)
+        nxt[i] = cur[i] + omega * L.d[i] * (L.b[i] - row_dot<T, T, 1>(L.ci, L.a, cur, L.rp[i], L.rp[i + 1], 0));
+      __syncthreads();
+      T* t = cur; cur = nxt; nxt = t;
+    }
+    if (cur == L.y) parity |= 1u << l; else parity &= ~(1u << l);
+  }
+  // ---- result on level l0 where the caller expects it
+  const int in_y = (parity >> l0) & 1u;
+  if (in_y != out_y) {
+    const TailGL q = gls[(size_t)l0 * G + g];
+    const TailLev<T> L = lvs[l0];
+    const T* src = in_y ? L.y : L.x;
+    T* dst = in_y ? L.x : L.y;
+    for (int i = q.r0 + tid; i < q.r1; i += kTailThreads) dst[i] = src[i];
+  }
+}
+
 // x_blk = inv_blk b_blk, one workgroup per block; inv is column-major
 template <class T>
 __global__ __launch_bounds__(256) void k_dense_solve(const int* __restrict__ blk, const int* __restrict__ act,
@@ -1695,6 +1786,15 @@ void cyc_update64(const Tile* t, int nt, const int* act, const T* e, double* x, 
   SHP_LAUNCH_CHECK();
 }
 
+template <class T>
+void cyc_tail(const int* games, int ngames, int l0, int nlev, int G, const TailLev<T>* lv, const TailGL* gl,
+              const int* act, T omega, int nu1, int nu2, int out_y, hipStream_t s) {
+  if (ngames <= 0) return;
+  hipLaunchKernelGGL(k_tail<T>, dim3(ngames), dim3(kTailThreads), 0, s, games, l0, nlev, G, lv, gl, act, omega, nu1,
+                     nu2, out_y);
+  SHP_LAUNCH_CHECK();
+}
+
 #define SHP_INST(T)                                                                                  \
   template void cyc_smooth<T>(const Tile*, int, const int*, const int*, const int*, const T*, const T*, \
                               const T*, const T*, T*, T, int, int, hipStream_t);                     \
@@ -1707,7 +1807,9 @@ void cyc_update64(const Tile* t, int nt, const int* act, const T* e, double* x, 
   template void cyc_dense<T>(const int*, int, const int*, const T*, const T*, T*, hipStream_t);        \
   template void cyc_resid64<T>(const Tile*, int, const int*, const int*, const int*, const double*,    \
                                const double*, const double*, T*, Stripes, int, hipStream_t);         \
-  template void cyc_update64<T>(const Tile*, int, const int*, const T*, double*, hipStream_t);
+  template void cyc_update64<T>(const Tile*, int, const int*, const T*, double*, hipStream_t);          \
+  template void cyc_tail<T>(const int*, int, int, int, int, const TailLev<T>*, const TailGL*, const int*, T, int, \
+                            int, int, hipStream_t);
 SHP_INST(float)
 SHP_INST(double)
 #undef SHP_INST

@@ -579,6 +579,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
       throw Error(SHAPLEY_EDEVICE, "Galerkin product: coarse row too long (code " + std::to_string(herr[1]) + ")");
     if (herr[2] != 0) throw Error(SHAPLEY_EDEVICE, "singular coarsest block");
   }
+  build_tail(mixed);
   // statistics
   double nnz_sum = 0, n_sum = 0;
   for (int k = 0; k < nlev; ++k) { nnz_sum += lv[k].nnz; n_sum += lv[k].n; }
@@ -586,6 +587,84 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
     slots[g]->levels = nlev;
     slots[g]->opc = lv[0].nnz ? nnz_sum / lv[0].nnz : 1.0;
     slots[g]->gc = lv[0].n ? n_sum / lv[0].n : 1.0;
+  }
+}
+
+// Splits every level between the level-by-level cycle and the per-game tails
+// (a game's tail starts on its first level with at most kTailRows rows) and
+// uploads the tail tables.  Pointers stay valid through numeric refreshes.
+void Engine::build_tail(bool mixed) {
+  h_lt.assign(G, nlev);
+  for (int g = 0; g < G; ++g) {
+    for (int l = 0; l < nlev; ++l) {
+      const Level& L = lv[l];
+      if (!L.present[g]) break;
+      if (L.goff[g + 1] - L.goff[g] <= kTailRows) {
+        h_lt[g] = l;
+        break;
+      }
+      if (!L.cont[g]) break;  // ends on a level larger than a tail
+    }
+  }
+  std::vector<TailGL> gl((size_t)std::max(nlev, 1) * std::max(G, 1), TailGL{0, 0, 0, 0});
+  std::vector<TailLev<double>> t64(std::max(nlev, 1));
+  std::vector<TailLev<float>> t32(std::max(nlev, 1));
+  for (int l = 0; l < nlev; ++l) {
+    Level& L = lv[l];
+    std::vector<int> doff(G, -1);
+    for (size_t k = 0; k + 3 < L.h_blk.size(); k += 4) doff[L.h_blk[k + 3]] = L.h_blk[k + 2];
+    std::vector<char> keepv(G, 0), keepr(G, 0);
+    L.h_vblk.clear();
+    L.h_tailg.clear();
+    for (int g = 0; g < G; ++g) {
+      if (!L.present[g]) continue;
+      TailGL& q = gl[(size_t)l * G + g];
+      q.r0 = L.goff[g];
+      q.r1 = L.goff[g + 1];
+      q.flags = kTailPresent | (L.cont[g] ? kTailCont : 0);
+      if (doff[g] >= 0) {
+        q.flags |= kTailDense;
+        q.doff = doff[g];
+      }
+      if (l + 1 < nlev && lv[l + 1].present[g]) q.flags |= kTailNext;
+      keepv[g] = L.cont[g] && h_lt[g] > l;
+      keepr[g] = l > 0 && h_lt[g] > l - 1;
+      if (h_lt[g] == l) L.h_tailg.push_back(g);
+    }
+    for (size_t k = 0; k + 3 < L.h_blk.size(); k += 4)
+      if (h_lt[L.h_blk[k + 3]] > l) L.h_vblk.insert(L.h_vblk.end(), L.h_blk.begin() + k, L.h_blk.begin() + k + 4);
+    auto upload = [&](std::vector<Tile>& h, DBuf<Tile>& d, int& nt, int& rows, const std::vector<char>& keep) {
+      h = make_tiles(L.goff, keep, kTileRows);
+      nt = (int)h.size();
+      rows = 0;
+      for (const Tile& x : h) rows += x.r1 - x.r0;
+      d.ensure(std::max<size_t>(h.size(), 1));
+      up(d.p, h.data(), h.size());
+    };
+    upload(L.h_vctiles, L.vctiles, L.nvctiles, L.rows_vctiles, keepv);
+    upload(L.h_rtiles, L.rtiles, L.nrtiles, L.rows_rtiles, keepr);
+    L.nvblk = (int)L.h_vblk.size() / 4;
+    L.vblk.ensure(std::max<size_t>(L.h_vblk.size(), 1));
+    up(L.vblk.p, L.h_vblk.data(), L.h_vblk.size());
+    L.ntailg = (int)L.h_tailg.size();
+    L.tailg.ensure(std::max<size_t>(L.h_tailg.size(), 1));
+    up(L.tailg.p, L.h_tailg.data(), L.h_tailg.size());
+    L.upper = L.nvctiles > 0 || L.nvblk > 0;
+    if (mixed)
+      t32[l] = TailLev<float>{L.rp.p, L.ci.p, L.a32.p, L.dinv32.p, L.x32.p, L.y32.p, L.b32.p, L.r32.p,
+                              L.rrp.p, L.rci.p, L.rv32.p, L.pc.p, L.pv32.p, L.dmat32.p};
+    else
+      t64[l] = TailLev<double>{L.rp.p, L.ci.p, L.a64.p, L.dinv64.p, L.x64.p, L.y64.p, L.b64.p, L.r64.p,
+                               L.rrp.p, L.rci.p, L.rv64.p, L.pc.p, L.pv64.p, L.dmat64.p};
+  }
+  d_tailgl.ensure(gl.size());
+  up(d_tailgl.p, gl.data(), gl.size());
+  if (mixed) {
+    d_tail32.ensure(t32.size());
+    up(d_tail32.p, t32.data(), t32.size());
+  } else {
+    d_tail64.ensure(t64.size());
+    up(d_tail64.p, t64.data(), t64.size());
   }
 }
 
@@ -637,18 +716,24 @@ void Engine::refresh(const EngineOpts& o) {
 // algorithmic bytes of the cycle kernels (each value read or written once)
 template <class T>
 static double bytes_smooth(const Level& L, bool first) {
-  const double sv = sizeof(T), rows = L.rows_ctiles;
+  const double sv = sizeof(T), rows = L.rows_vctiles;
   if (first) return rows * 3 * sv;
   const double nnz = L.n ? (double)L.nnz * rows / L.n : 0.0;
   return rows * (4 + 4 * sv) + nnz * (4 + sv);
 }
 template <class T>
 static double bytes_resid(const Level& L) {
-  const double sv = sizeof(T), rows = L.rows_ctiles;
+  const double sv = sizeof(T), rows = L.rows_vctiles;
   const double nnz = L.n ? (double)L.nnz * rows / L.n : 0.0;
   return rows * (4 + 3 * sv) + nnz * (4 + sv);
 }
 
+template <class T>
+static T* vcycle_level(Engine* e, std::vector<Level>& lv, int l, const EngineOpts& o, const int* act,
+                       hipStream_t s);
+
+// Level-by-level part of the V-cycle on level l: the games whose tail starts
+// deeper.  Returns the buffer (x or y) holding the level's result.
 template <class T>
 static T* vcycle_impl(Engine* e, std::vector<Level>& lv, int l, const EngineOpts& o, const int* act,
                       hipStream_t s) {
@@ -657,41 +742,68 @@ static T* vcycle_impl(Engine* e, std::vector<Level>& lv, int l, const EngineOpts
   T* nxt = LV<T>::y(L);
   T* b = LV<T>::b(L);
   const T om = (T)o.omega;
-  if (L.nctiles) {
+  if (L.nvctiles) {
     const T* A = LV<T>::a(L);
     const T* D = LV<T>::d(L);
     probe_begin(kProbeSmooth, s);
-    cyc_smooth<T>(L.ctiles.p, L.nctiles, act, L.rp.p, L.ci.p, A, D, b, nullptr, cur, om, 1, 1, s);
+    cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, D, b, nullptr, cur, om, 1, 1, s);
     probe_end(kProbeSmooth, s, bytes_smooth<T>(L, true));
     for (int k = 1; k < o.nu1; ++k) {
       probe_begin(kProbeSmooth, s);
-      cyc_smooth<T>(L.ctiles.p, L.nctiles, act, L.rp.p, L.ci.p, A, D, b, cur, nxt, om, 0, L.gA, s);
+      cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, D, b, cur, nxt, om, 0, L.gA, s);
       probe_end(kProbeSmooth, s, bytes_smooth<T>(L, false));
       std::swap(cur, nxt);
     }
     T* r = LV<T>::r(L);
     probe_begin(kProbeResid, s);
-    cyc_resid<T>(L.ctiles.p, L.nctiles, act, L.rp.p, L.ci.p, A, b, cur, r, L.gA, s);
+    cyc_resid<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, b, cur, r, L.gA, s);
     probe_end(kProbeResid, s, bytes_resid<T>(L));
     Level& Ln = lv[l + 1];
     probe_begin(kProbeRestrict, s);
-    cyc_restrict<T>(Ln.tiles.p, Ln.ntiles, act, L.rrp.p, L.rci.p, LV<T>::rv(L), r, LV<T>::b(Ln), L.gR, s);
+    cyc_restrict<T>(Ln.rtiles.p, Ln.nrtiles, act, L.rrp.p, L.rci.p, LV<T>::rv(L), r, LV<T>::b(Ln), L.gR, s);
     probe_end(kProbeRestrict, s,
-              (double)Ln.rows_tiles * (4 + sizeof(T)) + (double)L.rows_ctiles * (4 + 2 * sizeof(T)));
-    T* xc = vcycle_impl<T>(e, lv, l + 1, o, act, s);
+              (double)Ln.rows_rtiles * (4 + sizeof(T)) + (double)L.rows_vctiles * (4 + 2 * sizeof(T)));
+    T* xc = vcycle_level<T>(e, lv, l + 1, o, act, s);
     probe_begin(kProbeProlong, s);
-    cyc_prolong<T>(L.ctiles.p, L.nctiles, act, L.pc.p, LV<T>::pv(L), xc, cur, s);
+    cyc_prolong<T>(L.vctiles.p, L.nvctiles, act, L.pc.p, LV<T>::pv(L), xc, cur, s);
     probe_end(kProbeProlong, s,
-              (double)L.rows_ctiles * (PW * (4 + sizeof(T)) + 2 * sizeof(T)) + (double)Ln.rows_tiles * sizeof(T));
+              (double)L.rows_vctiles * (PW * (4 + sizeof(T)) + 2 * sizeof(T)) + (double)Ln.rows_rtiles * sizeof(T));
     for (int k = 0; k < o.nu2; ++k) {
       probe_begin(kProbeSmooth, s);
-      cyc_smooth<T>(L.ctiles.p, L.nctiles, act, L.rp.p, L.ci.p, A, D, b, cur, nxt, om, 0, L.gA, s);
+      cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, D, b, cur, nxt, om, 0, L.gA, s);
       probe_end(kProbeSmooth, s, bytes_smooth<T>(L, false));
       std::swap(cur, nxt);
     }
   }
-  if (L.nblk) cyc_dense<T>(L.blk.p, L.nblk, act, LV<T>::dm(L), b, cur, s);
+  if (L.nvblk) cyc_dense<T>(L.vblk.p, L.nvblk, act, LV<T>::dm(L), b, cur, s);
   return cur;
+}
+
+// V-cycle on level l: the level-by-level part, then one launch for the games
+// whose tail starts here, writing into the same buffer.
+template <class T>
+static T* vcycle_level(Engine* e, std::vector<Level>& lv, int l, const EngineOpts& o, const int* act,
+                       hipStream_t s) {
+  Level& L = lv[l];
+  T* res = L.upper ? vcycle_impl<T>(e, lv, l, o, act, s) : LV<T>::x(L);
+  if (L.ntailg) {
+    double bytes = 0.0;
+    if (probe_on(kProbeTail))
+      for (int k = l; k < e->num_levels(); ++k) {
+        const Level& Lk = lv[k];
+        const double rows = Lk.n ? (double)Lk.n : 0.0, sv = sizeof(T);
+        // tail games' share of the level, (nu1 + nu2 + 1) sweeps of matrix and vectors
+        double share = 0.0;
+        for (int g : L.h_tailg) share += Lk.goff[g + 1] - Lk.goff[g];
+        const double nnz = rows > 0 ? (double)Lk.nnz * share / rows : 0.0;
+        bytes += (o.nu1 + o.nu2 + 1) * (share * (4 + 3 * sv) + nnz * (4 + sv));
+      }
+    probe_begin(kProbeTail, s);
+    cyc_tail<T>(L.tailg.p, L.ntailg, l, e->num_levels(), e->num_slots(), e->tail_levels((T*)nullptr),
+                e->tail_games(), act, (T)o.omega, o.nu1, o.nu2, res == LV<T>::y(L) ? 1 : 0, s);
+    probe_end(kProbeTail, s, bytes);
+  }
+  return res;
 }
 
 void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
@@ -735,10 +847,10 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
   while (true) {
     for (int c = 0; c < chunk; ++c) {
       if (mixed) {
-        float* e = vcycle_impl<float>(this, lv, 0, o, d_lin_active.p, stream);
+        float* e = vcycle_level<float>(this, lv, 0, o, d_lin_active.p, stream);
         cyc_update64<float>(L0.tiles.p, L0.ntiles, d_lin_active.p, e, sol.p, stream);
       } else {
-        double* e = vcycle_impl<double>(this, lv, 0, o, d_lin_active.p, stream);
+        double* e = vcycle_level<double>(this, lv, 0, o, d_lin_active.p, stream);
         cyc_update64<double>(L0.tiles.p, L0.ntiles, d_lin_active.p, e, sol.p, stream);
       }
       resid_check();

@@ -70,6 +70,38 @@ struct Game {
 };
 
 // One merged (block-diagonal over games) AMG level.
+// ---------------------------------------------------------------------------
+// V-cycle tail: once a game's rows on a level are few (kTailRows), the rest of
+// its V-cycle (that level and all coarser ones, down to its dense solve) runs
+// in one workgroup of one launch, one workgroup per game, instead of a launch
+// per kernel and level.
+// ---------------------------------------------------------------------------
+constexpr int kTailRows = 2048;
+constexpr int kTailThreads = 1024;
+enum { kTailPresent = 1, kTailCont = 2, kTailDense = 4, kTailNext = 8 };
+template <class T>
+struct TailLev {  // one level's matrices and cycle vectors
+  const int* rp;
+  const int* ci;
+  const T* a;
+  const T* d;
+  T* x;
+  T* y;
+  T* b;
+  T* r;
+  const int* rrp;  // R = P^T to the next level
+  const int* rci;
+  const T* rv;
+  const int* pc;   // P from the next level
+  const T* pv;
+  const T* dm;     // dense inverses (column-major blocks)
+};
+struct TailGL {  // one game on one level
+  int r0, r1;    // its rows
+  int flags;     // kTail*
+  int doff;      // offset of its dense inverse (kTailDense)
+};
+
 struct Level {
   int n = 0, nnz = 0;
   int gA = 1, gR = 1;             // lanes per row of A and of R in the cycle kernels
@@ -86,6 +118,16 @@ struct Level {
   int rows_tiles = 0, rows_ctiles = 0;  // rows covered by tiles / ctiles
   std::vector<Tile> h_tiles, h_ctiles;  // host copies (kept alive for async uploads)
   std::vector<int> h_blk;
+  // split for the V-cycle tail: rows handled level by level (games whose tail
+  // starts deeper), rows receiving their restriction that way, and the games
+  // whose tail starts on this level
+  DBuf<Tile> vctiles, rtiles;
+  int nvctiles = 0, nrtiles = 0, rows_vctiles = 0, rows_rtiles = 0;
+  std::vector<Tile> h_vctiles, h_rtiles;
+  DBuf<int> vblk, tailg;
+  int nvblk = 0, ntailg = 0;
+  std::vector<int> h_vblk, h_tailg;
+  bool upper = false;             // level-by-level work on this level
   // transfer to the next level (continuing slots)
   int nc = 0;
   DBuf<int> pc;                   // [n*PW], -1 = empty
@@ -174,6 +216,11 @@ class Engine {
   // Returns the number of slots still running.
   int step();
   void invalidate_layout() { layout_dirty = true; have_hier = false; }
+  int num_levels() const { return nlev; }
+  int num_slots() const { return G; }
+  const TailGL* tail_games() const { return d_tailgl.p; }
+  const TailLev<double>* tail_levels(double*) const { return d_tail64.p; }
+  const TailLev<float>* tail_levels(float*) const { return d_tail32.p; }
   // Small host <-> device transfers go through a pinned bump arena (pageable
   // copies are staged and can wait for the whole queue); the arena is reset
   // at every synchronisation of the engine's stream.
@@ -218,6 +265,12 @@ class Engine {
   DBuf<double> d_norm;                        // [4*G] res max, x max, b max, spare
   DBuf<double> d_shap;                        // [2*G] shapley residual max, sum sq
   DBuf<int> d_decision;
+  // V-cycle tail tables (built at setup)
+  DBuf<TailGL> d_tailgl;
+  DBuf<TailLev<double>> d_tail64;
+  DBuf<TailLev<float>> d_tail32;
+  std::vector<int> h_lt;  // first tail level of each game (nlev: none)
+  void build_tail(bool mixed);
   DBuf<LinCtl> d_lin;
   std::vector<LinCtl> h_lin;
   std::vector<int> h_decision;

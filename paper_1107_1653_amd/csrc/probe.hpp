@@ -15,7 +15,8 @@ enum {
   kProbeProlong = 5,
   kProbeRap = 6,
   kProbeInterp = 7,
-  kProbeFamilies = 8
+  kProbeTail = 8,     // V-cycle tail (coarse levels of a game in one workgroup)
+  kProbeFamilies = 9
 };
 
 bool probe_on(int fam);

@@ -33,6 +33,7 @@ _FAMILIES = (  # (substring of the kernel name, family); first match wins
     ("k_prolong", "prolong"),
     ("k_rap<", "rap"),
     ("k_interp", "interp"),
+    ("k_tail<", "tail"),
 )
 
 

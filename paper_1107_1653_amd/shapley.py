@@ -36,7 +36,7 @@ EXPORTED = [
     "shapley_server_poll", "shapley_server_step", "shapley_server_destroy",
     "shapley_probe_enable", "shapley_probe_read",
 ]
-PROBE = dict(smooth=0, resid64=1, improve=2, resid=3, restrict=4, prolong=5, rap=6, interp=7)
+PROBE = dict(smooth=0, resid64=1, improve=2, resid=3, restrict=4, prolong=5, rap=6, interp=7, tail=8)
 
 
 class ShapleyError(RuntimeError):
