@@ -820,15 +820,14 @@ __global__ void k_rap_bound(int nc, const int* __restrict__ rrp, const int* __re
 }
 
 template <int NT, int MODE>
-__global__ __launch_bounds__(NT) void k_rap(int nc, const int* __restrict__ rrp, const int* __restrict__ rci,
-                                            const double* __restrict__ rv, const int* __restrict__ rp,
-                                            const int* __restrict__ ci, const double* __restrict__ a,
-                                            const int* __restrict__ pc, const double* __restrict__ pv,
-                                            const int* __restrict__ toff, int* __restrict__ tcnt,
-                                            int* __restrict__ tcol, double* __restrict__ tval,
-                                            const int* __restrict__ crp, const int* __restrict__ cci,
-                                            double* __restrict__ cval, int* __restrict__ err,
-                                            const uint8_t* __restrict__ only) {
+__device__ __forceinline__ void rap_row(int I, const int* __restrict__ rrp, const int* __restrict__ rci,
+                                        const double* __restrict__ rv, const int* __restrict__ rp,
+                                        const int* __restrict__ ci, const double* __restrict__ a,
+                                        const int* __restrict__ pc, const double* __restrict__ pv,
+                                        const int* __restrict__ toff, int* __restrict__ tcnt,
+                                        int* __restrict__ tcol, double* __restrict__ tval,
+                                        const int* __restrict__ crp, const int* __restrict__ cci,
+                                        double* __restrict__ cval, int* __restrict__ err) {
   __shared__ int rS[kRapRCap];
   __shared__ int rO[kRapRCap + 1];
   __shared__ double rV[kRapRCap];
@@ -838,7 +837,6 @@ __global__ __launch_bounds__(NT) void k_rap(int nc, const int* __restrict__ rrp,
   __shared__ int nd_sh;
   int* tab = reinterpret_cast<int*>(ubuf);
   double* pval = ubuf;
-  const int I = blockIdx.x;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   // output column at position pos is owned by lane pos % NT, register pos / NT
@@ -846,8 +844,6 @@ __global__ __launch_bounds__(NT) void k_rap(int nc, const int* __restrict__ rrp,
   double reg[R];
 #pragma unroll
   for (int j = 0; j < R; ++j) reg[j] = 0.0;
-  if (I >= nc) return;
-  if (only && !only[I]) return;  // incremental refresh: row unchanged
   const int p0 = rrp[I], P = rrp[I + 1] - p0;
   if (P > kRapRCap) {
     if (tid == 0) {
@@ -1040,6 +1036,219 @@ __global__ __launch_bounds__(NT) void k_rap(int nc, const int* __restrict__ rrp,
       const int h = j * NT + tid;
       if (h < nd) cval[base + h] = reg[j];
     }
+  }
+}
+
+// one workgroup per coarse row
+template <int NT, int MODE>
+__global__ __launch_bounds__(NT) void k_rap(int nc, const int* __restrict__ rrp, const int* __restrict__ rci,
+                                            const double* __restrict__ rv, const int* __restrict__ rp,
+                                            const int* __restrict__ ci, const double* __restrict__ a,
+                                            const int* __restrict__ pc, const double* __restrict__ pv,
+                                            const int* __restrict__ toff, int* __restrict__ tcnt,
+                                            int* __restrict__ tcol, double* __restrict__ tval,
+                                            const int* __restrict__ crp, const int* __restrict__ cci,
+                                            double* __restrict__ cval, int* __restrict__ err,
+                                            const uint8_t* __restrict__ only) {
+  const int I = blockIdx.x;
+  if (I >= nc) return;
+  if (only && !only[I]) return;  // incremental refresh: row unchanged
+  rap_row<NT, MODE>(I, rrp, rci, rv, rp, ci, a, pc, pv, toff, tcnt, tcol, tval, crp, cci, cval, err);
+}
+
+// the rows listed in big[1 .. big[0]] (too large for the wavefront kernel)
+template <int NT, int MODE>
+__global__ __launch_bounds__(NT) void k_rap_list(const int* __restrict__ big, const int* __restrict__ rrp,
+                                                 const int* __restrict__ rci, const double* __restrict__ rv,
+                                                 const int* __restrict__ rp, const int* __restrict__ ci,
+                                                 const double* __restrict__ a, const int* __restrict__ pc,
+                                                 const double* __restrict__ pv, const int* __restrict__ toff,
+                                                 int* __restrict__ tcnt, int* __restrict__ tcol,
+                                                 double* __restrict__ tval, const int* __restrict__ crp,
+                                                 const int* __restrict__ cci, double* __restrict__ cval,
+                                                 int* __restrict__ err) {
+  const int cnt = big[0];
+  for (int k = blockIdx.x; k < cnt; k += gridDim.x) {
+    rap_row<NT, MODE>(big[1 + k], rrp, rci, rv, rp, ci, a, pc, pv, toff, tcnt, tcol, tval, crp, cci, cval, err);
+    __syncthreads();  // the next row reuses the LDS
+  }
+}
+
+// LDS ordering between the lanes of one wavefront
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Coarse rows with at most kSmR entries of R and kSmN distinct columns, one
+// wavefront per row and four rows per workgroup (the large levels, whose rows
+// are short).  The (R, A) pairs are taken kSmE at a time; products are summed
+// in runs of 64 slots, i.e. in slot order as in rap_row, so the result is the
+// same bit for bit; a row that does not fit is appended to big[1 ..] for
+// k_rap_list.
+constexpr int kSmR = 32, kSmE = 64, kSmN = 64, kSmHash = 512;
+template <int MODE>
+__global__ __launch_bounds__(256) void k_rap_small(int nc, const int* __restrict__ rrp, const int* __restrict__ rci,
+                                                   const double* __restrict__ rv, const int* __restrict__ rp,
+                                                   const int* __restrict__ ci, const double* __restrict__ a,
+                                                   const int* __restrict__ pc, const double* __restrict__ pv,
+                                                   const int* __restrict__ toff, int* __restrict__ tcnt,
+                                                   int* __restrict__ tcol, double* __restrict__ tval,
+                                                   const int* __restrict__ crp, const int* __restrict__ cci,
+                                                   double* __restrict__ cval, const uint8_t* __restrict__ only,
+                                                   int* __restrict__ big) {
+  constexpr int SS = kSmE * PW;  // product slots
+  static_assert(kSmHash * sizeof(int) <= SS * sizeof(double), "hash must fit in the product buffer");
+  __shared__ int s_rS[4][kSmR];
+  __shared__ int s_rO[4][kSmR + 1];
+  __shared__ double s_rV[4][kSmR];
+  __shared__ double s_buf[4][SS];  // hash table, later the product values
+  __shared__ int s_lst[4][kSmN];
+  __shared__ int s_key[4][SS];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int I = blockIdx.x * 4 + w;
+  if (I >= nc) return;  // per wavefront; nothing below synchronises the workgroup
+  if (only && !only[I]) return;
+  int* rS = s_rS[w];
+  int* rO = s_rO[w];
+  double* rV = s_rV[w];
+  int* lst = s_lst[w];
+  int* skey = s_key[w];
+  double* pval = s_buf[w];
+  int* tab = reinterpret_cast<int*>(s_buf[w]);
+  auto to_big = [&]() {
+    if (lane == 0) big[1 + atomicAdd(big, 1)] = I;
+  };
+  const int p0 = rrp[I], P = rrp[I + 1] - p0;
+  if (P > kSmR) { to_big(); return; }
+  int b = 0, ln = 0;
+  double rvv = 0.0;
+  if (lane < P) {
+    const int i = rci[p0 + lane];
+    b = rp[i];
+    ln = rp[i + 1] - b;
+    rvv = rv[p0 + lane];
+  }
+  int v = ln;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(v, o);
+    if (lane >= o) v += y;
+  }
+  const int E = __shfl(v, 63);
+  if (lane < P) {
+    rS[lane] = b;
+    rO[lane + 1] = v;
+    rV[lane] = rvv;
+  }
+  if (lane == 0) rO[0] = 0;
+  wave_lds_sync();
+  int nd;
+  if (MODE == kRapFused) {
+    for (int h = lane; h < kSmHash; h += 64) tab[h] = -1;
+    wave_lds_sync();
+    // a key left out of a full table only happens beyond kSmN keys, where
+    // the row goes to the workgroup kernel anyway
+    for (int f = lane; f < E; f += 64) {
+      const int p = rap_locate(rO, P, f);
+      const int k = ci[rS[p] + (f - rO[p])];
+      for (int q = 0; q < PW; ++q) {
+        const int J = pc[(size_t)k * PW + q];
+        if (J < 0) continue;
+        unsigned h = mix32((uint32_t)J) & (kSmHash - 1);
+        for (int pr = 0; pr < kSmHash; ++pr) {
+          const int old = atomicCAS(&tab[h], -1, J);
+          if (old == -1 || old == J) break;
+          h = (h + 1) & (kSmHash - 1);
+        }
+      }
+    }
+    wave_lds_sync();
+    nd = 0;
+    for (int base = 0; base < kSmHash; base += 64) {
+      const int key = tab[base + lane];
+      const unsigned long long m = __ballot(key >= 0);
+      const int pos = nd + __popcll(m & ((1ull << lane) - 1ull));
+      if (key >= 0 && pos < kSmN) lst[pos] = key;
+      nd += __popcll(m);
+    }
+    if (nd > kSmN) { to_big(); return; }
+    wave_lds_sync();
+    int key = lane < nd ? lst[lane] : INT_MAX;
+    wave_sort64(key);
+    if (lane < nd) lst[lane] = key;
+  } else {
+    const int base = crp[I];
+    nd = crp[I + 1] - base;
+    if (nd > kSmN) { to_big(); return; }
+    if (lane < nd) lst[lane] = cci[base + lane];
+  }
+  wave_lds_sync();
+  double acc = 0.0;  // lane < nd: output column at position lane
+  for (int f0 = 0; f0 < E; f0 += kSmE) {
+    const int fe = (E < f0 + kSmE) ? E : f0 + kSmE;
+    const int f = f0 + lane;
+    if (f < fe) {
+      const int p = rap_locate(rO, P, f);
+      const int e = rS[p] + (f - rO[p]);
+      const int k = ci[e];
+      const double ra = rV[p] * a[e];
+      for (int q = 0; q < PW; ++q) {
+        const int slot = lane * PW + q;
+        const int J = pc[(size_t)k * PW + q];
+        int key = INT_MAX;
+        double val = 0.0;
+        if (J >= 0 && nd > 0) {
+          int lo = 0, hi = nd - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (lst[mid] < J) lo = mid + 1; else hi = mid;
+          }
+          if (lst[lo] == J) {
+            key = (lo << 10) | slot;
+            val = ra * pv[(size_t)k * PW + q];
+          }
+        }
+        skey[slot] = key;
+        pval[slot] = val;
+      }
+    }
+    wave_lds_sync();
+    const int ns = (fe - f0) * PW;
+    const int nruns = (ns + 63) >> 6;
+    for (int r = 0; r < nruns; ++r) {
+      const int sl = (r << 6) + lane;
+      int key = sl < ns ? skey[sl] : INT_MAX;
+      double val = sl < ns ? pval[sl] : 0.0;
+      wave_sort64(key, val);
+      skey[sl] = key;
+      pval[sl] = val;
+    }
+    wave_lds_sync();
+    if (lane < nd) {
+      const int k0 = lane << 10, k1 = (lane + 1) << 10;
+      for (int r = 0; r < nruns; ++r) {
+        const int bb = r << 6;
+        int lo = 0, hi = 64;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (skey[bb + mid] < k0) lo = mid + 1; else hi = mid;
+        }
+        for (int t = bb + lo; t < bb + 64 && skey[t] < k1; ++t) acc += pval[t];
+      }
+    }
+    wave_lds_sync();  // the next chunk overwrites the slots
+  }
+  if (MODE == kRapFused) {
+    const int o = toff[I];
+    if (lane < nd) {
+      tcol[o + lane] = lst[lane];
+      tval[o + lane] = acc;
+    }
+    if (lane == 0) tcnt[I] = nd;
+  } else {
+    const int base = crp[I];
+    if (lane < nd) cval[base + lane] = acc;
   }
 }
 
@@ -1676,20 +1885,34 @@ void amg_rap_bound(int nc, const int* rrp, const int* rci, const int* rp, int* u
   hipLaunchKernelGGL(k_rap_bound, dim3(grid_for(nc)), dim3(kBlock), 0, s, nc, rrp, rci, rp, ub);
   SHP_LAUNCH_CHECK();
 }
-// levels with few coarse rows get more lanes per row (their time is the
-// latency of one row); the results do not depend on the choice
-#define SHP_RAP_LAUNCH(MODE, ...)                                                                  \
-  do {                                                                                            \
-    if (nc < 8192) hipLaunchKernelGGL((k_rap<256, MODE>), dim3(nc), dim3(256), 0, s, __VA_ARGS__); \
-    else hipLaunchKernelGGL((k_rap<128, MODE>), dim3(nc), dim3(128), 0, s, __VA_ARGS__);           \
-  } while (0)
+// Levels with few coarse rows (long rows): one workgroup of 256 lanes per
+// row.  Larger levels (short rows): the wavefront kernel, then the rows it
+// could not take with 128 lanes each.  The results do not depend on the path.
+template <int MODE>
+static void rap_launch(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,
+                       const double* a, const int* pc, const double* pv, const int* toff, int* tcnt, int* tcol,
+                       double* tval, const int* crp, const int* cci, double* cval, int* err, const uint8_t* only,
+                       int* big, hipStream_t s) {
+  if (nc < 8192) {
+    hipLaunchKernelGGL((k_rap<256, MODE>), dim3(nc), dim3(256), 0, s, nc, rrp, rci, rv, rp, ci, a, pc, pv, toff,
+                       tcnt, tcol, tval, crp, cci, cval, err, only);
+    SHP_LAUNCH_CHECK();
+    return;
+  }
+  fill_async(big, 0, 1, s);
+  hipLaunchKernelGGL((k_rap_small<MODE>), dim3((nc + 3) / 4), dim3(256), 0, s, nc, rrp, rci, rv, rp, ci, a, pc, pv,
+                     toff, tcnt, tcol, tval, crp, cci, cval, only, big);
+  SHP_LAUNCH_CHECK();
+  hipLaunchKernelGGL((k_rap_list<128, MODE>), dim3(std::min(nc, 2048)), dim3(128), 0, s, big, rrp, rci, rv, rp, ci,
+                     a, pc, pv, toff, tcnt, tcol, tval, crp, cci, cval, err);
+  SHP_LAUNCH_CHECK();
+}
 void amg_rap_fused(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,
                    const double* a, const int* pc, const double* pv, const int* toff, int* tcnt, int* tcol,
-                   double* tval, int* err, hipStream_t s) {
+                   double* tval, int* err, int* big, hipStream_t s) {
   if (!nc) return;
-  SHP_RAP_LAUNCH(kRapFused, nc, rrp, rci, rv, rp, ci, a, pc, pv, toff, tcnt, tcol, tval, nullptr, nullptr, nullptr,
-                 err, nullptr);
-  SHP_LAUNCH_CHECK();
+  rap_launch<kRapFused>(nc, rrp, rci, rv, rp, ci, a, pc, pv, toff, tcnt, tcol, tval, nullptr, nullptr, nullptr, err,
+                        nullptr, big, s);
 }
 void amg_rap_compact(int nc, const int* toff, const int* tcol, const double* tval, const int* crp, int* cci,
                      double* cval, hipStream_t s) {
@@ -1699,11 +1922,10 @@ void amg_rap_compact(int nc, const int* toff, const int* tcol, const double* tva
 }
 void amg_rap_known(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,
                    const double* a, const int* pc, const double* pv, const int* crp, const int* cci, double* cval,
-                   int* err, hipStream_t s, const uint8_t* only) {
+                   int* err, int* big, hipStream_t s, const uint8_t* only) {
   if (!nc) return;
-  SHP_RAP_LAUNCH(kRapKnown, nc, rrp, rci, rv, rp, ci, a, pc, pv, nullptr, nullptr, nullptr, nullptr, crp, cci, cval,
-                 err, only);
-  SHP_LAUNCH_CHECK();
+  rap_launch<kRapKnown>(nc, rrp, rci, rv, rp, ci, a, pc, pv, nullptr, nullptr, nullptr, nullptr, crp, cci, cval, err,
+                        only, big, s);
 }
 void amg_diag_inv(int n, const int* rp, const int* ci, const double* a, double* d64, float* d32,
                   hipStream_t s) {

@@ -33,19 +33,19 @@ void amg_pt_fill(const Tile* t, int nt, const int* pc, const double* pv, const i
                  int* rci, double* rv, hipStream_t s);
 void amg_sort_rows(const int* rp, int* ci, double* v, int n, hipStream_t s);
 constexpr int kRapMaxCols = 1024;  // distinct columns of one coarse row
-// Galerkin product.  Full setup: bounds -> exclusive scan into toff ->
+// Galerkin product (`big`: scratch of nc + 1 ints).  Full setup: bounds -> exclusive scan into toff ->
 // fused (row lengths into tcnt, rows into the scratch tcol/tval) -> scan of
 // tcnt into the coarse row pointers -> compaction.  Refresh: values of the
 // rows flagged in `only` (all when null) into the existing pattern.
 void amg_rap_bound(int nc, const int* rrp, const int* rci, const int* rp, int* ub, hipStream_t s);
 void amg_rap_fused(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,
                    const double* a, const int* pc, const double* pv, const int* toff, int* tcnt, int* tcol,
-                   double* tval, int* err, hipStream_t s);
+                   double* tval, int* err, int* big, hipStream_t s);
 void amg_rap_compact(int nc, const int* toff, const int* tcol, const double* tval, const int* crp, int* cci,
                      double* cval, hipStream_t s);
 void amg_rap_known(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,
                    const double* a, const int* pc, const double* pv, const int* crp, const int* cci, double* cval,
-                   int* err, hipStream_t s, const uint8_t* only);
+                   int* err, int* big, hipStream_t s, const uint8_t* only);
 void amg_diag_inv(int n, const int* rp, const int* ci, const double* a, double* d64, float* d32,
                   hipStream_t s);
 void amg_cast(const double* in, float* out, size_t n, hipStream_t s);

@@ -498,8 +498,9 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         s_tcol.ensure(tcap);
         s_tval.ensure(tcap);
         probe_begin(kProbeRap, stream);
+        s_big.ensure((size_t)nc + 1);
         amg_rap_fused(nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, s_toff.p, s_cnt.p,
-                      s_tcol.p, s_tval.p, s_err.p + 1, stream);
+                      s_tcol.p, s_tval.p, s_err.p + 1, s_big.p, stream);
         probe_end(kProbeRap, stream, (double)L.nnz * 12 + (double)n * PW * 12 + (double)nc * 8);
         scan_exclusive(s_cnt.p, Ln.rp.p, nc + 1, stream, s_scan);
         int cnnz = 0, rnnz_used = 0;
@@ -696,8 +697,9 @@ void Engine::refresh(const EngineOpts& o) {
       fill_async(Ln.chg.p, (uint8_t)0, (size_t)std::max(L.nc, 1), stream);
       amg_mark_coarse(L.ctiles.p, L.nctiles, L.pc.p, L.chg.p, Ln.chg.p, stream);
       probe_begin(kProbeRap, stream);
+      s_big.ensure((size_t)L.nc + 1);
       amg_rap_known(L.nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, Ln.rp.p, Ln.ci.p,
-                    Ln.a64.p, s_err.p + 1, stream, Ln.chg.p);
+                    Ln.a64.p, s_err.p + 1, s_big.p, stream, Ln.chg.p);
       probe_end(kProbeRap, stream, (double)Ln.nnz * 12 + (double)L.nnz * 12 + (double)n * PW * 12);
     }
     if (L.nblk)

@@ -284,6 +284,7 @@ class Engine {
   // setup scratch
   DBuf<int> s_cnt, s_cursor, s_scan, s_err, s_left, s_newc, s_gidx, s_gout, s_goff;
   DBuf<int> s_toff, s_tcol;   // Galerkin product scratch rows (offsets, columns)
+  DBuf<int> s_big;            // Galerkin product: rows left to the workgroup kernel
   DBuf<double> s_tval;        // and values
   DBuf<Tile> s_tiles;
   DBuf<double> s_dense;

@@ -11,7 +11,7 @@
 
 Probe families are the kernel groups the library can time with HIP events
 (shapley_probe_enable): smooth, resid64, improve, resid, restrict, prolong,
-rap (Galerkin product, both passes), interp.
+rap (Galerkin product, both passes), interp, tail.
 """
 import argparse
 import collections
@@ -32,6 +32,8 @@ _FAMILIES = (  # (substring of the kernel name, family); first match wins
     ("k_restrict", "restrict"),
     ("k_prolong", "prolong"),
     ("k_rap<", "rap"),
+    ("k_rap_small", "rap"),
+    ("k_rap_list", "rap"),
     ("k_interp", "interp"),
     ("k_tail<", "tail"),
 )
