@@ -26,31 +26,6 @@ __global__ void k_dirichlet(const Tile* __restrict__ tiles, const int* __restric
   dir[i] = any ? 0 : 1;
 }
 
-// numeric refresh of the relaxation data of a level's rows in one pass:
-// Dirichlet flag (no nonzero off-diagonal entry), 1/a_ii (recomputed, or kept
-// when `keep_diag`, e.g. from the assembly), divided by omega on Dirichlet
-// rows so that the weighted relaxation solves them exactly
-__global__ void k_diag_dir(const Tile* __restrict__ tiles, const int* __restrict__ rp,
-                           const int* __restrict__ ci, const double* __restrict__ a, int keep_diag,
-                           double inv_omega, uint8_t* __restrict__ dir, double* __restrict__ d64,
-                           float* __restrict__ d32) {
-  const Tile t = tiles[blockIdx.x];
-  const int i = t.r0 + threadIdx.x;
-  if (i >= t.r1) return;
-  bool any = false;
-  double d = 0.0;
-  for (int e = rp[i]; e < rp[i + 1]; ++e) {
-    const int c = ci[e];
-    const double x = a[e];
-    if (c == i) d += x; else if (x != 0.0) any = true;
-  }
-  double di = keep_diag ? d64[i] : (d != 0.0 ? 1.0 / d : 0.0);
-  if (!any) di *= inv_omega;
-  dir[i] = any ? 0 : 1;
-  d64[i] = di;
-  if (d32) d32[i] = (float)di;
-}
-
 __global__ void k_dir_scale(const Tile* __restrict__ tiles, const uint8_t* __restrict__ dir, double f,
                             double* __restrict__ d64, float* __restrict__ d32) {
   Tile t = tiles[blockIdx.x];
@@ -794,6 +769,27 @@ __global__ __launch_bounds__(256) void k_sort_rows_wave(const int* __restrict__ 
   }
 }
 
+// ascending bitonic sort of 128 keys, elements `lane` (k0) and `lane + 64`
+// (k1) of each lane
+__device__ inline void wave_sort128(int& k0, int& k1) {
+  const int lane = threadIdx.x & 63;
+  for (int k2 = 2; k2 <= 128; k2 <<= 1) {
+    for (int j = k2 >> 1; j > 0; j >>= 1) {
+      if (j == 64) {  // partners in the same lane; k2 = 128: ascending
+        const int lo = k0 < k1 ? k0 : k1, hi = k0 < k1 ? k1 : k0;
+        k0 = lo;
+        k1 = hi;
+        continue;
+      }
+      const int o0 = __shfl_xor(k0, j), o1 = __shfl_xor(k1, j);
+      const bool low = (lane & j) == 0;
+      const bool up0 = (lane & k2) == 0, up1 = ((lane + 64) & k2) == 0;
+      if ((up0 == low) ? (o0 < k0) : (o0 > k0)) k0 = o0;
+      if ((up1 == low) ? (o1 < k1) : (o1 > k1)) k1 = o1;
+    }
+  }
+}
+
 __device__ inline int rap_locate(const int* rO, int P, int f) {
   int lo = 0, hi = P - 1;  // largest p with rO[p] <= f
   while (lo < hi) {
@@ -1087,7 +1083,7 @@ __device__ inline void wave_lds_sync() {
 // in runs of 64 slots, i.e. in slot order as in rap_row, so the result is the
 // same bit for bit; a row that does not fit is appended to big[1 ..] for
 // k_rap_list.
-constexpr int kSmR = 32, kSmE = 64, kSmN = 64, kSmHash = 512;
+constexpr int kSmR = 64, kSmE = 64, kSmN = 128, kSmHash = 512;
 template <int MODE>
 __global__ __launch_bounds__(256) void k_rap_small(int nc, const int* __restrict__ rrp, const int* __restrict__ rci,
                                                    const double* __restrict__ rv, const int* __restrict__ rp,
@@ -1122,24 +1118,28 @@ __global__ __launch_bounds__(256) void k_rap_small(int nc, const int* __restrict
   };
   const int p0 = rrp[I], P = rrp[I + 1] - p0;
   if (P > kSmR) { to_big(); return; }
-  int b = 0, ln = 0;
-  double rvv = 0.0;
-  if (lane < P) {
-    const int i = rci[p0 + lane];
-    b = rp[i];
-    ln = rp[i + 1] - b;
-    rvv = rv[p0 + lane];
-  }
-  int v = ln;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(v, o);
-    if (lane >= o) v += y;
-  }
-  const int E = __shfl(v, 63);
-  if (lane < P) {
-    rS[lane] = b;
-    rO[lane + 1] = v;
-    rV[lane] = rvv;
+  int E = 0;  // R entries 64 at a time, offsets by a wavefront scan
+  for (int base = 0; base < P; base += 64) {
+    const int t = base + lane;
+    int b = 0, ln = 0;
+    double rvv = 0.0;
+    if (t < P) {
+      const int i = rci[p0 + t];
+      b = rp[i];
+      ln = rp[i + 1] - b;
+      rvv = rv[p0 + t];
+    }
+    int v = ln;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(v, o);
+      if (lane >= o) v += y;
+    }
+    if (t < P) {
+      rS[t] = b;
+      rO[t + 1] = E + v;
+      rV[t] = rvv;
+    }
+    E += __shfl(v, 63);
   }
   if (lane == 0) rO[0] = 0;
   wave_lds_sync();
@@ -1174,17 +1174,19 @@ __global__ __launch_bounds__(256) void k_rap_small(int nc, const int* __restrict
     }
     if (nd > kSmN) { to_big(); return; }
     wave_lds_sync();
-    int key = lane < nd ? lst[lane] : INT_MAX;
-    wave_sort64(key);
-    if (lane < nd) lst[lane] = key;
+    int key0 = lane < nd ? lst[lane] : INT_MAX;
+    int key1 = lane + 64 < nd ? lst[lane + 64] : INT_MAX;
+    wave_sort128(key0, key1);
+    if (lane < nd) lst[lane] = key0;
+    if (lane + 64 < nd) lst[lane + 64] = key1;
   } else {
     const int base = crp[I];
     nd = crp[I + 1] - base;
     if (nd > kSmN) { to_big(); return; }
-    if (lane < nd) lst[lane] = cci[base + lane];
+    for (int h = lane; h < nd; h += 64) lst[h] = cci[base + h];
   }
   wave_lds_sync();
-  double acc = 0.0;  // lane < nd: output column at position lane
+  double acc0 = 0.0, acc1 = 0.0;  // output columns at positions lane, lane + 64
   for (int f0 = 0; f0 < E; f0 += kSmE) {
     const int fe = (E < f0 + kSmE) ? E : f0 + kSmE;
     const int f = f0 + lane;
@@ -1225,8 +1227,11 @@ __global__ __launch_bounds__(256) void k_rap_small(int nc, const int* __restrict
       pval[sl] = val;
     }
     wave_lds_sync();
-    if (lane < nd) {
-      const int k0 = lane << 10, k1 = (lane + 1) << 10;
+    for (int h = 0; h < 2; ++h) {
+      const int pos = lane + 64 * h;
+      if (pos >= nd) continue;
+      const int k0 = pos << 10, k1 = (pos + 1) << 10;
+      double acc = h ? acc1 : acc0;
       for (int r = 0; r < nruns; ++r) {
         const int bb = r << 6;
         int lo = 0, hi = 64;
@@ -1236,6 +1241,7 @@ __global__ __launch_bounds__(256) void k_rap_small(int nc, const int* __restrict
         }
         for (int t = bb + lo; t < bb + 64 && skey[t] < k1; ++t) acc += pval[t];
       }
+      if (h) acc1 = acc; else acc0 = acc;
     }
     wave_lds_sync();  // the next chunk overwrites the slots
   }
@@ -1243,12 +1249,17 @@ __global__ __launch_bounds__(256) void k_rap_small(int nc, const int* __restrict
     const int o = toff[I];
     if (lane < nd) {
       tcol[o + lane] = lst[lane];
-      tval[o + lane] = acc;
+      tval[o + lane] = acc0;
+    }
+    if (lane + 64 < nd) {
+      tcol[o + lane + 64] = lst[lane + 64];
+      tval[o + lane + 64] = acc1;
     }
     if (lane == 0) tcnt[I] = nd;
   } else {
     const int base = crp[I];
-    if (lane < nd) cval[base + lane] = acc;
+    if (lane < nd) cval[base + lane] = acc0;
+    if (lane + 64 < nd) cval[base + lane + 64] = acc1;
   }
 }
 
@@ -1598,6 +1609,41 @@ __global__ __launch_bounds__(256) void k_resid(const Tile* __restrict__ tiles, c
   if (in && gl == 0) r[i] = b[i] - ax;
 }
 
+// numeric refresh of the relaxation data of a level's rows in one pass, G
+// lanes per row: Dirichlet flag (no nonzero off-diagonal entry), 1/a_ii
+// (recomputed, or kept when `keep_diag`, e.g. from the assembly), divided by
+// omega on Dirichlet rows so that the weighted relaxation solves them exactly
+template <int G>
+__global__ __launch_bounds__(256) void k_diag_dir(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                                                  const int* __restrict__ ci, const double* __restrict__ a,
+                                                  int keep_diag, double inv_omega, uint8_t* __restrict__ dir,
+                                                  double* __restrict__ d64, float* __restrict__ d32) {
+  const Tile t = tiles[blockIdx.x / G];
+  int gl;
+  const int i = tile_row<G>(t, gl);
+  const bool in = i < t.r1;
+  int any = 0;
+  double d = 0.0;  // one diagonal entry per row: the sum over lanes is exact
+  if (in) {
+    for (int e = rp[i] + gl; e < rp[i + 1]; e += G) {
+      const int c = ci[e];
+      const double x = a[e];
+      if (c == i) d += x; else if (x != 0.0) any = 1;
+    }
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    d += __shfl_xor(d, o);
+    any |= __shfl_xor(any, o);
+  }
+  if (!in || gl != 0) return;
+  double di = keep_diag ? d64[i] : (d != 0.0 ? 1.0 / d : 0.0);
+  if (!any) di *= inv_omega;
+  dir[i] = any ? 0 : 1;
+  d64[i] = di;
+  if (d32) d32[i] = (float)di;
+}
+
 template <class T, int G>
 __global__ __launch_bounds__(256) void k_restrict(const Tile* __restrict__ tiles, const int* __restrict__ act,
                                                   const int* __restrict__ rrp, const int* __restrict__ rci,
@@ -1789,10 +1835,15 @@ void amg_dirichlet(const Tile* t, int nt, const int* rp, const int* ci, const do
   SHP_LAUNCH_CHECK();
 }
 void amg_diag_dir(const Tile* t, int nt, const int* rp, const int* ci, const double* a, bool keep_diag,
-                  double inv_omega, uint8_t* dir, double* d64, float* d32, hipStream_t s) {
+                  double inv_omega, uint8_t* dir, double* d64, float* d32, int g, hipStream_t s) {
   if (!nt) return;
-  hipLaunchKernelGGL(k_diag_dir, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, a, keep_diag ? 1 : 0, inv_omega, dir,
-                     d64, d32);
+  const int kd = keep_diag ? 1 : 0;
+  if (g == 16)
+    hipLaunchKernelGGL(k_diag_dir<16>, dim3(nt * 16), dim3(kTileRows), 0, s, t, rp, ci, a, kd, inv_omega, dir, d64, d32);
+  else if (g == 4)
+    hipLaunchKernelGGL(k_diag_dir<4>, dim3(nt * 4), dim3(kTileRows), 0, s, t, rp, ci, a, kd, inv_omega, dir, d64, d32);
+  else
+    hipLaunchKernelGGL(k_diag_dir<1>, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, a, kd, inv_omega, dir, d64, d32);
   SHP_LAUNCH_CHECK();
 }
 void amg_dir_scale(const Tile* t, int nt, const uint8_t* dir, double f, double* d64, float* d32,

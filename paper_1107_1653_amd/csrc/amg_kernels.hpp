@@ -8,7 +8,7 @@ namespace shp {
 void amg_dirichlet(const Tile* t, int nt, const int* rp, const int* ci, const double* a, uint8_t* dir,
                    hipStream_t s);
 void amg_diag_dir(const Tile* t, int nt, const int* rp, const int* ci, const double* a, bool keep_diag,
-                  double inv_omega, uint8_t* dir, double* d64, float* d32, hipStream_t s);
+                  double inv_omega, uint8_t* dir, double* d64, float* d32, int g, hipStream_t s);
 void amg_dir_scale(const Tile* t, int nt, const uint8_t* dir, double f, double* d64, float* d32,
                    hipStream_t s);
 void amg_strength(const Tile* t, int nt, const int* rp, const int* ci, const double* a,

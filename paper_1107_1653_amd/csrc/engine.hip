@@ -691,7 +691,7 @@ void Engine::refresh(const EngineOpts& o) {
       // relaxation data of the smoothed rows (level 0 keeps the assembled
       // diagonal); rows of games that end here use the dense inverse instead
       amg_diag_dir(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, l == 0, 1.0 / o.omega, L.dir.p, L.dinv64.p,
-                   mixed ? L.dinv32.p : nullptr, stream);
+                   mixed ? L.dinv32.p : nullptr, L.gA, stream);
       Level& Ln = lv[l + 1];
       Ln.chg.ensure(std::max(L.nc, 1));
       fill_async(Ln.chg.p, (uint8_t)0, (size_t)std::max(L.nc, 1), stream);
