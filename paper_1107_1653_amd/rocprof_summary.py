@@ -39,6 +39,16 @@ _FAMILIES = (  # (substring of the kernel name, family); first match wins
 )
 
 
+# kernels that complete a launch of their family rather than start one: the
+# Galerkin product of a large level is the wavefront kernel followed by the
+# workgroup kernel over the rows it left (one probe launch, two kernels)
+_CONTINUATIONS = ("k_rap_list",)
+
+
+def starts_launch(name: str) -> bool:
+    return not any(k in name for k in _CONTINUATIONS)
+
+
 def family_of(name: str):
     for key, fam in _FAMILIES:
         if key in name:
@@ -88,9 +98,9 @@ def trace_summary(db_path: str, top: int = 25) -> str:
     for k, c, t, a in rows:
         f = family_of(k)
         if f:
-            fam[f][0] += c
+            fam[f][0] += c if starts_launch(k) else 0
             fam[f][1] += t
-    lines += ["", "| probe family | calls | total ms | avg us per launch |", "|---|---|---|---|"]
+    lines += ["", "| probe family | launches | total ms | avg us per launch |", "|---|---|---|---|"]
     for f, (c, t) in sorted(fam.items(), key=lambda kv: -kv[1][1]):
         lines.append(f"| {f} | {c} | {t / 1e3:.2f} | {t / c:.2f} |")
     return "\n".join(lines)
@@ -118,7 +128,7 @@ def traffic(fetch_csv: str, write_csv: str) -> dict:
     for k, v in fetch:
         f = family_of(k)
         if f:
-            fam[f]["launches"] += 1
+            fam[f]["launches"] += 1 if starts_launch(k) else 0
             fam[f]["fetch_kib"] += v
     for k, v in write:
         f = family_of(k)
