@@ -1675,55 +1675,109 @@ __global__ __launch_bounds__(256) void k_prolong(const Tile* __restrict__ tiles,
   x[i] = s;
 }
 
-// V-cycle tail of one game per workgroup (see amg_kernels.hpp).  Same steps
-// as the level-by-level cycle: nu1 weighted-Jacobi sweeps from zero, residual,
+// row_dot<T, T, 1> with the vector entries produced by f(column): the same
+// products in the same order, hence the same result as on an array
+template <class T, class F>
+__device__ inline T row_dot1_f(const int* __restrict__ ci, const T* __restrict__ a, F f, int e0, int e1) {
+  T acc[kRowUnroll];
+#pragma unroll
+  for (int u = 0; u < kRowUnroll; ++u) acc[u] = 0;
+  int e = e0;
+  for (; e + (kRowUnroll - 1) < e1; e += kRowUnroll) {
+    int c[kRowUnroll];
+    T v[kRowUnroll];
+#pragma unroll
+    for (int u = 0; u < kRowUnroll; ++u) {
+      c[u] = ci[e + u];
+      v[u] = a[e + u];
+    }
+#pragma unroll
+    for (int u = 0; u < kRowUnroll; ++u) acc[u] += v[u] * f(c[u]);
+  }
+  for (; e < e1; ++e) acc[0] += a[e] * f(ci[e]);
+  T s = acc[0];
+#pragma unroll
+  for (int u = 1; u < kRowUnroll; ++u) s += acc[u];
+  return s;
+}
+
+// V-cycle tail of one game per workgroup (see internal.hpp).  Same steps as
+// the level-by-level cycle: nu1 weighted-Jacobi sweeps from zero, residual,
 // restriction, the coarser levels, prolongation and correction, nu2 sweeps;
-// the dense inverse on the game's last level.
+// the dense inverse on the game's last level.  The iterates of every tail
+// level live in LDS (two vectors per level, dynamic LDS sized by the host);
+// matrices, right-hand sides and the level-l0 result are in global memory.
 template <class T>
 __global__ __launch_bounds__(kTailThreads) void k_tail(const int* __restrict__ games, int l0, int nlev, int G,
                                                        const TailLev<T>* __restrict__ lvs,
                                                        const TailGL* __restrict__ gls, const int* __restrict__ act,
                                                        T omega, int nu1, int nu2, int out_y) {
+  extern __shared__ unsigned char tail_lds[];
+  __shared__ int off[kTailMaxLevels];  // by level - l0
+  T* lds = reinterpret_cast<T*>(tail_lds);
   const int g = games[blockIdx.x];
   if (!act[g]) return;
   const int tid = threadIdx.x;
-  unsigned parity = 0;  // bit l: the level-l iterate is in y
+  if (tid == 0) {  // the level-l vectors: x at off[l - l0], y at off[l - l0] + rows
+    int o = 0;
+    for (int l = l0; l < nlev && l - l0 < kTailMaxLevels; ++l) {
+      const TailGL q = gls[(size_t)l * G + g];
+      if (!(q.flags & kTailPresent)) break;
+      off[l - l0] = o;
+      o += 2 * (q.r1 - q.r0);
+    }
+  }
+  __syncthreads();
+  unsigned parity = 0;  // bit l - l0: the level-l iterate is in y
   int deep = l0;
   // ---- down
   for (int l = l0; l < nlev; ++l) {
     const TailGL q = gls[(size_t)l * G + g];
     const TailLev<T> L = lvs[l];
+    const int r0 = q.r0, n = q.r1 - q.r0;
+    T* xv = lds + off[l - l0];
+    T* yv = xv + n;
     deep = l;
     if (q.flags & kTailDense) {
-      const int nb = q.r1 - q.r0;
-      for (int i = tid; i < nb; i += kTailThreads) {
+      for (int i = tid; i < n; i += kTailThreads) {
         T acc = 0;
-        for (int j = 0; j < nb; ++j) acc += L.dm[(size_t)q.doff + (size_t)j * nb + i] * L.b[q.r0 + j];
-        L.x[q.r0 + i] = acc;
+        for (int j = 0; j < n; ++j) acc += L.dm[(size_t)q.doff + (size_t)j * n + i] * L.b[r0 + j];
+        xv[i] = acc;
       }
       __syncthreads();
       break;
     }
     if (!(q.flags & kTailCont)) break;
-    T* cur = L.x;
-    T* nxt = L.y;
-    for (int i = q.r0 + tid; i < q.r1; i += kTailThreads) cur[i] = omega * L.d[i] * L.b[i];
+    T* cur = xv;
+    T* nxt = yv;
+    for (int i = tid; i < n; i += kTailThreads) cur[i] = omega * L.d[r0 + i] * L.b[r0 + i];
     __syncthreads();
     for (int k = 1; k < nu1; ++k) {
-      for (int i = q.r0 + tid; i < q.r1; i += kTailThreads)
-        nxt[i] = cur[i] + omega * L.d[i] * (L.b[i] - row_dot<T, T, 1>(L.ci, L.a, cur, L.rp[i], L.rp[i + 1], 0));
+      const T* c0 = cur;
+      for (int i = tid; i < n; i += kTailThreads) {
+        const int r = r0 + i;
+        nxt[i] = cur[i] + omega * L.d[r] *
+                              (L.b[r] - row_dot1_f<T>(L.ci, L.a, [&](int j) -> T { return c0[j - r0]; }, L.rp[r],
+                                                      L.rp[r + 1]));
+      }
       __syncthreads();
       T* t = cur; cur = nxt; nxt = t;
     }
-    if (cur == L.y) parity |= 1u << l;
+    if (cur == yv) parity |= 1u << (l - l0);
     if (!(q.flags & kTailNext)) break;  // no coarse rows: smoothing only
-    for (int i = q.r0 + tid; i < q.r1; i += kTailThreads)
-      L.r[i] = L.b[i] - row_dot<T, T, 1>(L.ci, L.a, cur, L.rp[i], L.rp[i + 1], 0);
+    T* rr = nxt;                         // the free vector holds the residual
+    {
+      const T* c0 = cur;
+      for (int i = tid; i < n; i += kTailThreads) {
+        const int r = r0 + i;
+        rr[i] = L.b[r] - row_dot1_f<T>(L.ci, L.a, [&](int j) -> T { return c0[j - r0]; }, L.rp[r], L.rp[r + 1]);
+      }
+    }
     __syncthreads();
     const TailGL qn = gls[(size_t)(l + 1) * G + g];
     const TailLev<T> Ln = lvs[l + 1];
     for (int I = qn.r0 + tid; I < qn.r1; I += kTailThreads)
-      Ln.b[I] = row_dot<T, T, 1>(L.rci, L.rv, L.r, L.rrp[I], L.rrp[I + 1], 0);
+      Ln.b[I] = row_dot1_f<T>(L.rci, L.rv, [&](int i) -> T { return rr[i - r0]; }, L.rrp[I], L.rrp[I + 1]);
     __syncthreads();
   }
   // ---- up
@@ -1731,39 +1785,47 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const int* __restrict__ g
     const TailGL q = gls[(size_t)l * G + g];
     if (!(q.flags & kTailCont) || (q.flags & kTailDense)) continue;  // the dense result is in x
     const TailLev<T> L = lvs[l];
-    T* cur = ((parity >> l) & 1u) ? L.y : L.x;
-    T* nxt = ((parity >> l) & 1u) ? L.x : L.y;
+    const int r0 = q.r0, n = q.r1 - q.r0;
+    T* xv = lds + off[l - l0];
+    T* yv = xv + n;
+    T* cur = ((parity >> (l - l0)) & 1u) ? yv : xv;
+    T* nxt = ((parity >> (l - l0)) & 1u) ? xv : yv;
     if (l < deep) {
-      const TailLev<T> Ln = lvs[l + 1];
-      const T* xc = ((parity >> (l + 1)) & 1u) ? Ln.y : Ln.x;
-      for (int i = q.r0 + tid; i < q.r1; i += kTailThreads) {
+      const TailGL qn = gls[(size_t)(l + 1) * G + g];
+      const int n1 = qn.r1 - qn.r0;
+      const T* xc = lds + off[l + 1 - l0] + (((parity >> (l + 1 - l0)) & 1u) ? n1 : 0);
+      for (int i = tid; i < n; i += kTailThreads) {
+        const int r = r0 + i;
         T acc = cur[i];
 #pragma unroll
         for (int k = 0; k < PW; ++k) {
-          const int c = L.pc[(size_t)i * PW + k];
-          if (c >= 0) acc += L.pv[(size_t)i * PW + k] * xc[c];
+          const int c = L.pc[(size_t)r * PW + k];
+          if (c >= 0) acc += L.pv[(size_t)r * PW + k] * xc[c - qn.r0];
         }
         cur[i] = acc;
       }
       __syncthreads();
     }
     for (int k = 0; k < nu2; ++k) {
-      for (int i = q.r0 + tid; i < q.r1; i += kTailThreads)
-        nxt[i] = cur[i] + omega * L.d[i] * (L.b[i] - row_dot<T, T, 1>(L.ci, L.a, cur, L.rp[i], L.rp[i + 1], 0));
+      const T* c0 = cur;
+      for (int i = tid; i < n; i += kTailThreads) {
+        const int r = r0 + i;
+        nxt[i] = cur[i] + omega * L.d[r] *
+                              (L.b[r] - row_dot1_f<T>(L.ci, L.a, [&](int j) -> T { return c0[j - r0]; }, L.rp[r],
+                                                      L.rp[r + 1]));
+      }
       __syncthreads();
       T* t = cur; cur = nxt; nxt = t;
     }
-    if (cur == L.y) parity |= 1u << l; else parity &= ~(1u << l);
+    if (cur == yv) parity |= 1u << (l - l0); else parity &= ~(1u << (l - l0));
   }
-  // ---- result on level l0 where the caller expects it
-  const int in_y = (parity >> l0) & 1u;
-  if (in_y != out_y) {
-    const TailGL q = gls[(size_t)l0 * G + g];
-    const TailLev<T> L = lvs[l0];
-    const T* src = in_y ? L.y : L.x;
-    T* dst = in_y ? L.x : L.y;
-    for (int i = q.r0 + tid; i < q.r1; i += kTailThreads) dst[i] = src[i];
-  }
+  // ---- the level-l0 result where the caller expects it
+  const TailGL q = gls[(size_t)l0 * G + g];
+  const TailLev<T> L = lvs[l0];
+  const int n = q.r1 - q.r0;
+  const T* src = lds + off[0] + ((parity & 1u) ? n : 0);
+  T* dst = out_y ? L.y : L.x;
+  for (int i = tid; i < n; i += kTailThreads) dst[q.r0 + i] = src[i];
 }
 
 // x_blk = inv_blk b_blk, one workgroup per block; inv is column-major
@@ -2061,10 +2123,11 @@ void cyc_update64(const Tile* t, int nt, const int* act, const T* e, double* x, 
 
 template <class T>
 void cyc_tail(const int* games, int ngames, int l0, int nlev, int G, const TailLev<T>* lv, const TailGL* gl,
-              const int* act, T omega, int nu1, int nu2, int out_y, hipStream_t s) {
+              const int* act, T omega, int nu1, int nu2, int out_y, int lds_rows, hipStream_t s) {
   if (ngames <= 0) return;
-  hipLaunchKernelGGL(k_tail<T>, dim3(ngames), dim3(kTailThreads), 0, s, games, l0, nlev, G, lv, gl, act, omega, nu1,
-                     nu2, out_y);
+  const size_t lds = 2 * sizeof(T) * (size_t)std::max(lds_rows, 1);
+  hipLaunchKernelGGL(k_tail<T>, dim3(ngames), dim3(kTailThreads), lds, s, games, l0, nlev, G, lv, gl, act, omega,
+                     nu1, nu2, out_y);
   SHP_LAUNCH_CHECK();
 }
 
@@ -2082,7 +2145,7 @@ void cyc_tail(const int* games, int ngames, int l0, int nlev, int G, const TailL
                                const double*, const double*, T*, Stripes, int, hipStream_t);         \
   template void cyc_update64<T>(const Tile*, int, const int*, const T*, double*, hipStream_t);          \
   template void cyc_tail<T>(const int*, int, int, int, int, const TailLev<T>*, const TailGL*, const int*, T, int, \
-                            int, int, hipStream_t);
+                            int, int, int, hipStream_t);
 SHP_INST(float)
 SHP_INST(double)
 #undef SHP_INST

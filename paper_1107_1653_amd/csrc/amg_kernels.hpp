@@ -57,10 +57,11 @@ void amg_row_changed(const Tile* t, int nt, const int* rp, const double* a, doub
 void amg_mark_coarse(const Tile* t, int nt, const int* pc, const uint8_t* chg, uint8_t* cmark, hipStream_t s);
 
 // games[k] (k < ngames) start their tail on level `l0`; the result on level l0
-// is left in y when out_y, else in x
+// is left in y when out_y, else in x; lds_rows: the largest sum over the tail
+// levels of a game's rows (two LDS vectors per level)
 template <class T>
 void cyc_tail(const int* games, int ngames, int l0, int nlev, int G, const TailLev<T>* lv, const TailGL* gl,
-              const int* act, T omega, int nu1, int nu2, int out_y, hipStream_t s);
+              const int* act, T omega, int nu1, int nu2, int out_y, int lds_rows, hipStream_t s);
 
 // lanes per sparse row (1, 4 or 16) for a level with this average row length
 int row_group(double avg_len);

@@ -595,16 +595,24 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
 // (a game's tail starts on its first level with at most kTailRows rows) and
 // uploads the tail tables.  Pointers stay valid through numeric refreshes.
 void Engine::build_tail(bool mixed) {
+  const int cap = kTailLdsBytes / (2 * (mixed ? (int)sizeof(float) : (int)sizeof(double)));
   h_lt.assign(G, nlev);
+  std::vector<int> lds_rows(std::max(nlev, 1), 0);
   for (int g = 0; g < G; ++g) {
-    for (int l = 0; l < nlev; ++l) {
-      const Level& L = lv[l];
-      if (!L.present[g]) break;
-      if (L.goff[g + 1] - L.goff[g] <= kTailRows) {
+    int last = -1;  // the game's last level
+    for (int l = 0; l < nlev && lv[l].present[g]; ++l) {
+      last = l;
+      if (!lv[l].cont[g]) break;
+    }
+    // rows of the game summed over levels l..last
+    std::vector<long> cum(last + 2, 0);
+    for (int l = last; l >= 0; --l) cum[l] = cum[l + 1] + (lv[l].goff[g + 1] - lv[l].goff[g]);
+    for (int l = 0; l <= last; ++l) {
+      if (lv[l].goff[g + 1] - lv[l].goff[g] <= kTailRows && cum[l] <= cap && last - l < kTailMaxLevels) {
         h_lt[g] = l;
+        lds_rows[l] = std::max(lds_rows[l], (int)cum[l]);
         break;
       }
-      if (!L.cont[g]) break;  // ends on a level larger than a tail
     }
   }
   std::vector<TailGL> gl((size_t)std::max(nlev, 1) * std::max(G, 1), TailGL{0, 0, 0, 0});
@@ -648,6 +656,7 @@ void Engine::build_tail(bool mixed) {
     L.vblk.ensure(std::max<size_t>(L.h_vblk.size(), 1));
     up(L.vblk.p, L.h_vblk.data(), L.h_vblk.size());
     L.ntailg = (int)L.h_tailg.size();
+    L.tail_lds_rows = lds_rows[l];
     L.tailg.ensure(std::max<size_t>(L.h_tailg.size(), 1));
     up(L.tailg.p, L.h_tailg.data(), L.h_tailg.size());
     L.upper = L.nvctiles > 0 || L.nvblk > 0;
@@ -802,7 +811,7 @@ static T* vcycle_level(Engine* e, std::vector<Level>& lv, int l, const EngineOpt
       }
     probe_begin(kProbeTail, s);
     cyc_tail<T>(L.tailg.p, L.ntailg, l, e->num_levels(), e->num_slots(), e->tail_levels((T*)nullptr),
-                e->tail_games(), act, (T)o.omega, o.nu1, o.nu2, res == LV<T>::y(L) ? 1 : 0, s);
+                e->tail_games(), act, (T)o.omega, o.nu1, o.nu2, res == LV<T>::y(L) ? 1 : 0, L.tail_lds_rows, s);
     probe_end(kProbeTail, s, bytes);
   }
   return res;

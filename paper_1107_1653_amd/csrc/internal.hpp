@@ -78,6 +78,10 @@ struct Game {
 // ---------------------------------------------------------------------------
 constexpr int kTailRows = 2048;
 constexpr int kTailThreads = 1024;
+// the tail keeps two iterate vectors per level in LDS: a game's rows summed
+// over its tail levels are at most kTailLdsBytes / (2 * sizeof(T))
+constexpr int kTailLdsBytes = 60 * 1024;
+constexpr int kTailMaxLevels = 32;  // levels in one game's tail
 enum { kTailPresent = 1, kTailCont = 2, kTailDense = 4, kTailNext = 8 };
 template <class T>
 struct TailLev {  // one level's matrices and cycle vectors
@@ -126,6 +130,7 @@ struct Level {
   std::vector<Tile> h_vctiles, h_rtiles;
   DBuf<int> vblk, tailg;
   int nvblk = 0, ntailg = 0;
+  int tail_lds_rows = 0;  // largest sum of rows over the tail levels of a game whose tail starts here
   std::vector<int> h_vblk, h_tailg;
   bool upper = false;             // level-by-level work on this level
   // transfer to the next level (continuing slots)
