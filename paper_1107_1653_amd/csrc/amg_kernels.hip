@@ -5,6 +5,7 @@
 // prolongation + correction, dense coarse solve, FP64 residual of the
 // iterative refinement.  Every row kernel takes a tile list (row ranges of
 // one game each) so one launch covers all games of a merged level.
+#include <utility>
 #include "amg_kernels.hpp"
 
 #include <climits>
@@ -1077,6 +1078,194 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// ---------------------------------------------------------------------------
+// Galerkin product of small levels through dense per-game blocks.  The coarse
+// levels of a hierarchy have few rows, each collecting many fine rows, so the
+// row-wise product has little parallelism and long rows to merge; here every
+// entry of AP = A P (per game: fine rows x coarse columns) and then of
+// R (AP) is computed by its own thread, each a sum in a fixed order (A row in
+// CSR order and the P slots in order; R row in order), so the result does not
+// depend on the launch shape.  An entry of R A P belongs to the pattern when
+// some product reaches it (the same structural pattern as the row-wise
+// product).
+// ---------------------------------------------------------------------------
+// the game g < G with off[g] <= t < off[g + 1] (the last one with off[g] <= t)
+__device__ __forceinline__ int drap_game(const long long* __restrict__ off, int G, long long t) {
+  int lo = 0, hi = G - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// one wavefront per fine row i: the products a_ij p_jJ (A row in CSR order,
+// P slots in order) go through LDS in chunks of 64; a chunk is sorted by
+// (J, position), each run of equal J summed by a segmented scan and added to
+// the row's dense accumulator, chunk after chunk
+template <bool TOUCH>
+__global__ __launch_bounds__(kBlock) void k_drap_ap(int nf, const long long* __restrict__ tab, int G,
+                                                    const int* __restrict__ rp, const int* __restrict__ ci,
+                                                    const double* __restrict__ a, const int* __restrict__ pc,
+                                                    const double* __restrict__ pv, double* __restrict__ ap,
+                                                    uint8_t* __restrict__ apt) {
+  constexpr int W = kBlock / 64;
+  __shared__ double acc_s[W][kDrapMaxCols];
+  __shared__ uint8_t hit_s[W][kDrapMaxCols];
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * W + wid;
+  if (i >= nf) return;
+  const long long* fo = tab;
+  const long long* co = tab + (G + 1);
+  const long long* ao = tab + 2 * (G + 1);
+  const int g = drap_game(fo, G, i);
+  const int ncg = (int)(co[g + 1] - co[g]);
+  if (ncg == 0) return;  // the game ends on this level
+  const int c0 = (int)co[g];
+  double* acc = acc_s[wid];
+  uint8_t* hit = hit_s[wid];
+  for (int J = lane; J < ncg; J += 64) {
+    acc[J] = 0.0;
+    hit[J] = 0;
+  }
+  wave_lds_sync();
+  const int e0 = rp[i], slots = (rp[i + 1] - e0) * PW;
+  for (int s0 = 0; s0 < slots; s0 += 64) {
+    const int sl = s0 + lane;
+    int key = INT_MAX;
+    double val = 0.0;
+    if (sl < slots) {
+      const int e = e0 + sl / PW, q = sl % PW;
+      const int j = ci[e];
+      const int J = pc[(size_t)j * PW + q];
+      if (J >= 0) {
+        key = ((J - c0) << 6) | lane;
+        val = a[e] * pv[(size_t)j * PW + q];
+      }
+    }
+    wave_sort64(key, val);
+    const int Jk = key == INT_MAX ? -1 : key >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {  // segmented inclusive scan over runs of equal J
+      const double y = __shfl_up(val, o);
+      const int Jy = __shfl_up(Jk, o);
+      if (lane >= o && Jy == Jk) val += y;
+    }
+    const int Jn = __shfl_down(Jk, 1);
+    if (Jk >= 0 && (lane == 63 || Jn != Jk)) {  // last of its run: the run's sum
+      acc[Jk] += val;
+      hit[Jk] = 1;
+    }
+    wave_lds_sync();
+  }
+  const long long base = ao[g] + (long long)(i - fo[g]) * ncg;
+  for (int J = lane; J < ncg; J += 64) {
+    ap[base + J] = acc[J];
+    if (TOUCH) apt[base + J] = hit[J];
+  }
+}
+
+// coarse entry (I, J) of game g: sum over the R row of I, in order
+__device__ __forceinline__ double drap_entry(int p0, int p1, const int* __restrict__ rci,
+                                             const double* __restrict__ rv, const double* __restrict__ ap,
+                                             long long base, long long ncg) {
+  double acc = 0.0;
+  for (int p = p0; p < p1; ++p) acc += rv[p] * ap[base + (long long)rci[p] * ncg];
+  return acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_drap_ac(long long total, const long long* __restrict__ tab, int G,
+                                                    const int* __restrict__ rrp, const int* __restrict__ rci,
+                                                    const double* __restrict__ rv, const double* __restrict__ ap,
+                                                    const uint8_t* __restrict__ apt, double* __restrict__ ac,
+                                                    uint8_t* __restrict__ acf) {
+  const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= total) return;
+  const long long* fo = tab;
+  const long long* co = tab + (G + 1);
+  const long long* ao = tab + 2 * (G + 1);
+  const long long* qo = tab + 3 * (G + 1);
+  const int g = drap_game(qo, G, t);
+  const long long ncg = co[g + 1] - co[g];
+  const long long loc = t - qo[g];
+  const int I = (int)(co[g] + loc / ncg);
+  const long long base = ao[g] - fo[g] * ncg + loc % ncg;  // AP entry (i, J) at base + i * ncg
+  const int p0 = rrp[I], p1 = rrp[I + 1];
+  int hit = 0;
+  for (int p = p0; p < p1; ++p) hit |= apt[base + (long long)rci[p] * ncg];
+  ac[t] = drap_entry(p0, p1, rci, rv, ap, base, ncg);
+  acf[t] = (uint8_t)(hit != 0);
+}
+
+// one wavefront per coarse row: entries of the pattern
+__global__ __launch_bounds__(kBlock) void k_drap_count(int nc, const long long* __restrict__ tab, int G,
+                                                       const uint8_t* __restrict__ acf, int* __restrict__ cnt) {
+  const int I = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (I >= nc) return;
+  const long long* co = tab + (G + 1);
+  const long long* qo = tab + 3 * (G + 1);
+  const int g = drap_game(co, G, I);
+  const long long ncg = co[g + 1] - co[g];
+  const long long base = qo[g] + (I - co[g]) * ncg;
+  int c = 0;
+  for (long long J = lane; J < ncg; J += 64) c += acf[base + J] ? 1 : 0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  if (lane == 0) cnt[I] = c;
+}
+
+// one wavefront per coarse row: the pattern's entries in column order
+__global__ __launch_bounds__(kBlock) void k_drap_compact(int nc, const long long* __restrict__ tab, int G,
+                                                         const double* __restrict__ ac,
+                                                         const uint8_t* __restrict__ acf,
+                                                         const int* __restrict__ crp, int* __restrict__ cci,
+                                                         double* __restrict__ cval) {
+  const int I = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (I >= nc) return;
+  const long long* co = tab + (G + 1);
+  const long long* qo = tab + 3 * (G + 1);
+  const int g = drap_game(co, G, I);
+  const long long ncg = co[g + 1] - co[g];
+  const long long base = qo[g] + (I - co[g]) * ncg;
+  int o = crp[I];
+  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (long long J0 = 0; J0 < ncg; J0 += 64) {
+    const long long J = J0 + lane;
+    const bool f = J < ncg && acf[base + J];
+    const unsigned long long m = __ballot(f);
+    if (f) {
+      const int pos = o + __popcll(m & below);
+      cci[pos] = (int)(co[g] + J);
+      cval[pos] = ac[base + J];
+    }
+    o += __popcll(m);
+  }
+}
+
+// refresh: values of the known pattern, one wavefront per coarse row, the
+// same sums as k_drap_ac
+__global__ __launch_bounds__(kBlock) void k_drap_known(int nc, const long long* __restrict__ tab, int G,
+                                                       const int* __restrict__ rrp, const int* __restrict__ rci,
+                                                       const double* __restrict__ rv, const double* __restrict__ ap,
+                                                       const int* __restrict__ crp, const int* __restrict__ cci,
+                                                       double* __restrict__ cval, const uint8_t* __restrict__ only) {
+  const int I = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (I >= nc) return;
+  if (only && !only[I]) return;
+  const long long* fo = tab;
+  const long long* co = tab + (G + 1);
+  const long long* ao = tab + 2 * (G + 1);
+  const int g = drap_game(co, G, I);
+  const long long ncg = co[g + 1] - co[g];
+  const long long base0 = ao[g] - fo[g] * ncg - co[g];
+  const int p0 = rrp[I], p1 = rrp[I + 1];
+  for (int e = crp[I] + lane; e < crp[I + 1]; e += 64) cval[e] = drap_entry(p0, p1, rci, rv, ap, base0 + cci[e], ncg);
+}
+
+
 // Coarse rows with at most kSmR entries of R and kSmN distinct columns, one
 // wavefront per row and four rows per workgroup (the large levels, whose rows
 // are short).  The (R, A) pairs are taken kSmE at a time; products are summed
@@ -1422,111 +1611,113 @@ __global__ __launch_bounds__(256) void k_dense_inv(const int* __restrict__ blk, 
   }
 }
 
-// In-place Gauss-Jordan inversion with row pivoting for blocks of at most
-// kDenseWave unknowns: one workgroup, the block in LDS column-major with an
-// odd leading dimension (no bank conflicts); the elimination of a step is
-// spread over all threads (one thread per matrix entry).  Column swaps undo
-// the row pivoting at the end.
-constexpr int kDenseThreads = 256;
-
-__global__ __launch_bounds__(kDenseThreads) void k_dense_inv_wave(const int* __restrict__ blk,
-                                                                  const int* __restrict__ rp,
-                                                                  const int* __restrict__ ci,
-                                                                  const double* __restrict__ a,
-                                                                  double* __restrict__ inv64,
-                                                                  float* __restrict__ inv32,
-                                                                  int* __restrict__ err,
-                                                                  const uint8_t* __restrict__ only) {
-  __shared__ double M[kDenseWave * (kDenseWave + 1)];
-  __shared__ double colk[kDenseWave];
-  __shared__ double rowk[kDenseWave];
-  __shared__ double rv[kDenseThreads / 64];
-  __shared__ int ri[kDenseThreads / 64];
-  __shared__ int perm[kDenseWave];
+// In-place Gauss-Jordan inversion with partial pivoting for blocks of at
+// most NB <= kDenseWave unknowns: one thread per row of the block, the row in
+// registers.  Pivot rows are not swapped: step k takes the row p not yet used
+// as a pivot with the largest |M[p][k]| (magnitudes compared on their leading
+// 56 bits, the lowest row first among equal ones), scales it and eliminates
+// column k from every other row.  Each step shifts the rows one register to
+// the left and appends the new column of the inverse on the right, so that
+// column k is always in v[0] and every register index is a constant: after
+// nb steps v[NB - nb + j] holds column j of the in-place result M, and with
+// p_k the pivot row of step k, inv[k][p_j] = M[p_k][j].
+template <int NB, int NT>
+__global__ __launch_bounds__(NT) void k_dense_inv_reg(const int* __restrict__ blk, const int* __restrict__ rp,
+                                                      const int* __restrict__ ci, const double* __restrict__ a,
+                                                      double* __restrict__ inv64, float* __restrict__ inv32,
+                                                      int* __restrict__ err, const uint8_t* __restrict__ only) {
+  static_assert(NT % 64 == 0 && NB <= NT && NT <= 256, "one thread per row, at most four wavefronts");
+  constexpr int CW = NB <= 64 ? NB : (NB + 1) / 2;  // columns staged through LDS at a time
+  constexpr int LD = NT + 1;
+  __shared__ double S[CW * LD];
+  __shared__ double piv[2][NB];
+  __shared__ unsigned long long best[2][NT / 64];
+  __shared__ int perm[NB];
   const int row0 = blk[4 * blockIdx.x], nb = blk[4 * blockIdx.x + 1];
   const size_t doff = (size_t)blk[4 * blockIdx.x + 2];
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  if (nb > kDenseWave) return;  // handled by the general kernel
-  if (only) {  // incremental refresh: skip blocks none of whose rows changed
+  const int i = threadIdx.x, lane = i & 63, w = i >> 6;
+  if (nb > NB) return;  // a larger block: the workgroup kernel
+  if (only) {           // incremental refresh: skip blocks none of whose rows changed
     int any = 0;
-    for (int i = tid; i < nb; i += kDenseThreads) any |= only[row0 + i];
+    for (int r = i; r < nb; r += NT) any |= only[row0 + r];
     if (!__syncthreads_or(any)) return;
   }
-  const int ld = nb | 1;
-  for (int idx = tid; idx < nb * ld; idx += kDenseThreads) M[idx] = 0.0;
-  __syncthreads();
-  for (int i = tid; i < nb; i += kDenseThreads) {
-    const int r = row0 + i;
-    for (int e = rp[r]; e < rp[r + 1]; ++e) {
-      const int c = ci[e] - row0;
-      if (c >= 0 && c < nb) M[c * ld + i] += a[e];
-    }
-  }
-  __syncthreads();
-  for (int k = 0; k < nb; ++k) {
-    // pivot: largest |M[i][k]| for i >= k (lowest row on ties)
-    double bv = -1.0;
-    int bi = k;
-    for (int i = k + tid; i < nb; i += kDenseThreads) {
-      const double v = fabs(M[k * ld + i]);
-      if (v > bv) { bv = v; bi = i; }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double v2 = __shfl_xor(bv, o);
-      const int i2 = __shfl_xor(bi, o);
-      if (v2 > bv || (v2 == bv && i2 < bi)) { bv = v2; bi = i2; }
-    }
-    if (lane == 0) { rv[wid] = bv; ri[wid] = bi; }
+  double v[NB];
+#pragma unroll
+  for (int c0 = 0; c0 < NB; c0 += CW) {
+    for (int idx = i; idx < CW * LD; idx += NT) S[idx] = 0.0;
     __syncthreads();
-    bv = rv[0];
-    bi = ri[0];
-    for (int w = 1; w < kDenseThreads / 64; ++w)
-      if (rv[w] > bv || (rv[w] == bv && ri[w] < bi)) { bv = rv[w]; bi = ri[w]; }
-    if (!(bv > 0.0)) {
-      if (tid == 0) atomicOr(err, 4);
+    if (i < nb) {
+      const int r = row0 + i;
+      for (int e = rp[r]; e < rp[r + 1]; ++e) {
+        const int c = ci[e] - row0 - c0;
+        if (c >= 0 && c < CW && c0 + c < nb) S[c * LD + i] += a[e];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < CW; ++j)
+      if (c0 + j < NB) v[c0 + j] = S[j * LD + i];
+    __syncthreads();
+  }
+  bool used = i >= nb;
+  int myk = 0;
+  for (int k = 0; k < nb; ++k) {
+    const int buf = k & 1;
+    unsigned long long key = 0;
+    if (!used) {
+      const double m = fabs(v[0]);
+      if (m == m) key = ((unsigned long long)__double_as_longlong(m) & ~0xFFull) | (unsigned long long)(255 - i);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long k2 = __shfl_xor(key, o);
+      key = k2 > key ? k2 : key;
+    }
+    if (NT > 64) {
+      if (lane == 0) best[buf][w] = key;
+      __syncthreads();
+      key = best[buf][0];
+#pragma unroll
+      for (int u = 1; u < NT / 64; ++u) key = best[buf][u] > key ? best[buf][u] : key;
+    }
+    if ((key >> 8) == 0) {  // no nonzero pivot left (uniform): singular block
+      if (i == 0) atomicOr(err, 4);
       return;
     }
-    const int p = bi;
-    if (tid == 0) perm[k] = p;
-    if (p != k)
-      for (int j = tid; j < nb; j += kDenseThreads) {
-        const double t0 = M[j * ld + k];
-        M[j * ld + k] = M[j * ld + p];
-        M[j * ld + p] = t0;
-      }
-    __syncthreads();
-    const double inv = 1.0 / M[k * ld + k];
-    // pivot row (scaled, with the diagonal entry replaced by inv) and column
-    for (int j = tid; j < nb; j += kDenseThreads) {
-      rowk[j] = (j == k) ? inv : M[j * ld + k] * inv;
-      colk[j] = M[k * ld + j];
+    const int p = 255 - (int)(key & 0xFF);
+    double* pv = piv[buf];
+    if (i == p) {
+      const double inv = 1.0 / v[0];
+#pragma unroll
+      for (int j = 0; j + 1 < NB; ++j) pv[j] = v[j + 1] * inv;
+      pv[NB - 1] = inv;
+      perm[k] = p;
+      used = true;
+      myk = k;
     }
     __syncthreads();
-    for (int idx = tid; idx < nb * nb; idx += kDenseThreads) {
-      const int j = idx / nb, i = idx - j * nb;
-      double v;
-      if (i == k) v = rowk[j];
-      else if (j == k) v = -colk[i] * inv;
-      else v = M[j * ld + i] - colk[i] * rowk[j];
-      M[j * ld + i] = v;
+    if (i == p) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) v[j] = pv[j];
+    } else {
+      const double f = v[0];
+#pragma unroll
+      for (int j = 0; j + 1 < NB; ++j) v[j] = v[j + 1] - f * pv[j];
+      v[NB - 1] = -f * pv[NB - 1];
     }
-    __syncthreads();
   }
-  for (int k = nb - 1; k >= 0; --k) {
-    const int p = perm[k];
-    if (p != k)
-      for (int i = tid; i < nb; i += kDenseThreads) {
-        const double t0 = M[k * ld + i];
-        M[k * ld + i] = M[p * ld + i];
-        M[p * ld + i] = t0;
+  __syncthreads();
+  if (i < nb) {
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      const int j = r - (NB - nb);
+      if (j >= 0) {
+        const size_t o = doff + (size_t)perm[j] * nb + myk;
+        inv64[o] = v[r];
+        if (inv32) inv32[o] = (float)v[r];
       }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < nb * nb; idx += kDenseThreads) {
-    const int j = idx / nb, i = idx - j * nb;
-    const double v = M[j * ld + i];
-    inv64[doff + idx] = v;
-    if (inv32) inv32[doff + idx] = (float)v;
+    }
   }
 }
 
@@ -2040,6 +2231,38 @@ void amg_rap_known(int nc, const int* rrp, const int* rci, const double* rv, con
   rap_launch<kRapKnown>(nc, rrp, rci, rv, rp, ci, a, pc, pv, nullptr, nullptr, nullptr, nullptr, crp, cci, cval, err,
                         only, big, s);
 }
+static unsigned drap_blocks(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+void amg_drap_full(int nf, int nc, const long long* tab, int G, long long ac_total, const int* rp, const int* ci,
+                   const double* a, const int* pc, const double* pv, const int* rrp, const int* rci, const double* rv,
+                   double* ap, uint8_t* apt, double* ac, uint8_t* acf, int* cnt, hipStream_t s) {
+  if (nc <= 0) return;
+  hipLaunchKernelGGL(k_drap_ap<true>, dim3(drap_blocks(64LL * nf)), dim3(kBlock), 0, s, nf, tab, G, rp, ci, a, pc,
+                     pv, ap, apt);
+  SHP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_drap_ac, dim3(drap_blocks(ac_total)), dim3(kBlock), 0, s, ac_total, tab, G, rrp, rci, rv, ap,
+                     apt, ac, acf);
+  SHP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_drap_count, dim3(drap_blocks(64LL * nc)), dim3(kBlock), 0, s, nc, tab, G, acf, cnt);
+  SHP_LAUNCH_CHECK();
+}
+void amg_drap_compact(int nc, const long long* tab, int G, const double* ac, const uint8_t* acf, const int* crp,
+                      int* cci, double* cval, hipStream_t s) {
+  if (nc <= 0) return;
+  hipLaunchKernelGGL(k_drap_compact, dim3(drap_blocks(64LL * nc)), dim3(kBlock), 0, s, nc, tab, G, ac, acf, crp, cci,
+                     cval);
+  SHP_LAUNCH_CHECK();
+}
+void amg_drap_known(int nf, int nc, const long long* tab, int G, const int* rp, const int* ci, const double* a,
+                    const int* pc, const double* pv, const int* rrp, const int* rci, const double* rv, double* ap,
+                    const int* crp, const int* cci, double* cval, hipStream_t s, const uint8_t* only) {
+  if (nc <= 0) return;
+  hipLaunchKernelGGL(k_drap_ap<false>, dim3(drap_blocks(64LL * nf)), dim3(kBlock), 0, s, nf, tab, G, rp, ci, a, pc,
+                     pv, ap, (uint8_t*)nullptr);
+  SHP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_drap_known, dim3(drap_blocks(64LL * nc)), dim3(kBlock), 0, s, nc, tab, G, rrp, rci, rv, ap,
+                     crp, cci, cval, only);
+  SHP_LAUNCH_CHECK();
+}
 void amg_diag_inv(int n, const int* rp, const int* ci, const double* a, double* d64, float* d32,
                   hipStream_t s) {
   if (!n) return;
@@ -2052,12 +2275,18 @@ void amg_cast(const double* in, float* out, size_t n, hipStream_t s) {
   SHP_LAUNCH_CHECK();
 }
 void amg_dense_inv(const int* blk, int nblk, const int* rp, const int* ci, const double* a, double* work,
-                   double* inv64, float* inv32, int* err, bool large, hipStream_t s, const uint8_t* only) {
+                   double* inv64, float* inv32, int* err, int max_nb, hipStream_t s, const uint8_t* only) {
   if (!nblk) return;
-  hipLaunchKernelGGL(k_dense_inv_wave, dim3(nblk), dim3(kDenseThreads), 0, s, blk, rp, ci, a, inv64, inv32, err,
-                     only);
+  static_assert(kDenseWave == 96, "register kernel sizes");
+  if (max_nb <= 32)
+    hipLaunchKernelGGL((k_dense_inv_reg<32, 64>), dim3(nblk), dim3(64), 0, s, blk, rp, ci, a, inv64, inv32, err, only);
+  else if (max_nb <= 64)
+    hipLaunchKernelGGL((k_dense_inv_reg<64, 64>), dim3(nblk), dim3(64), 0, s, blk, rp, ci, a, inv64, inv32, err, only);
+  else
+    hipLaunchKernelGGL((k_dense_inv_reg<96, 128>), dim3(nblk), dim3(128), 0, s, blk, rp, ci, a, inv64, inv32, err,
+                       only);
   SHP_LAUNCH_CHECK();
-  if (large) {
+  if (max_nb > kDenseWave) {
     hipLaunchKernelGGL(k_dense_inv, dim3(nblk), dim3(256), 0, s, blk, rp, ci, a, work, inv64, inv32, err);
     SHP_LAUNCH_CHECK();
   }

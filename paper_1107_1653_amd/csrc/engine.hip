@@ -484,23 +484,61 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         amg_pt_fill(L.ctiles.p, L.nctiles, L.pc.p, L.pv64.p, L.rrp.p, s_cursor.p, L.rci.p, L.rv64.p, stream);
         amg_sort_rows(L.rrp.p, L.rci.p, L.rv64.p, nc, stream);
         pt.mark("transpose");
-        // ---- Galerkin product: bounds, one fused pass into scratch rows,
-        // row pointers, compaction
+        // ---- Galerkin product.  Small next levels: dense per-game blocks.
+        // Otherwise row-wise: bounds, one fused pass into scratch rows, row
+        // pointers, compaction.
         Ln.rp.ensure(nc + 1);
         s_cnt.ensure(nc + 1);
         s_toff.ensure(nc + 1);
         fill_async(s_cnt.p + nc, 0, 1, stream);
-        amg_rap_bound(nc, L.rrp.p, L.rci.p, L.rp.p, s_cnt.p, stream);
-        scan_exclusive(s_cnt.p, s_toff.p, nc + 1, stream, s_scan);
-        // sum of the bounds <= PW * (pairs) <= PW * PW * nnz(A)
-        const size_t tcap = std::max<size_t>(
-            1, std::min((size_t)PW * PW * (size_t)std::max(L.nnz, 1), (size_t)nc * (size_t)kRapMaxCols));
-        s_tcol.ensure(tcap);
-        s_tval.ensure(tcap);
+        {
+          long long ap = 0, ac = 0;
+          int maxc = 0;
+          for (int g = 0; g < G; ++g) {
+            const long long ncg = cpre[g + 1] - cpre[g];
+            maxc = std::max(maxc, (int)ncg);
+            ap += ncg * (L.goff[g + 1] - L.goff[g]);
+            ac += ncg * ncg;
+          }
+          L.drap = maxc <= kDrapMaxCols && ap <= kDrapMaxEntries && ac <= kDrapMaxEntries;
+          L.drap_ap = ap;
+          L.drap_ac = ac;
+          if (L.drap) {
+            std::vector<long long>& t = L.h_drap_tab;  // kept alive for the asynchronous upload
+            t.assign(4 * (size_t)(G + 1), 0);
+            for (int g = 0; g <= G; ++g) {
+              t[g] = L.goff[g];
+              t[(G + 1) + g] = cpre[g];
+            }
+            for (int g = 0; g < G; ++g) {
+              const long long ncg = cpre[g + 1] - cpre[g];
+              t[2 * (G + 1) + g + 1] = t[2 * (G + 1) + g] + ncg * (L.goff[g + 1] - L.goff[g]);
+              t[3 * (G + 1) + g + 1] = t[3 * (G + 1) + g] + ncg * ncg;
+            }
+            L.drap_tab.ensure(t.size());
+            up(L.drap_tab.p, t.data(), t.size());
+          }
+        }
         probe_begin(kProbeRap, stream);
-        s_big.ensure((size_t)nc + 1);
-        amg_rap_fused(nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, s_toff.p, s_cnt.p,
-                      s_tcol.p, s_tval.p, s_err.p + 1, s_big.p, stream);
+        if (L.drap) {
+          s_dap.ensure(std::max<long long>(L.drap_ap, 1));
+          s_dapt.ensure(std::max<long long>(L.drap_ap, 1));
+          s_dac.ensure(std::max<long long>(L.drap_ac, 1));
+          s_dacf.ensure(std::max<long long>(L.drap_ac, 1));
+          amg_drap_full(n, nc, L.drap_tab.p, G, L.drap_ac, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, L.rrp.p,
+                        L.rci.p, L.rv64.p, s_dap.p, s_dapt.p, s_dac.p, s_dacf.p, s_cnt.p, stream);
+        } else {
+          amg_rap_bound(nc, L.rrp.p, L.rci.p, L.rp.p, s_cnt.p, stream);
+          scan_exclusive(s_cnt.p, s_toff.p, nc + 1, stream, s_scan);
+          // sum of the bounds <= PW * (pairs) <= PW * PW * nnz(A)
+          const size_t tcap = std::max<size_t>(
+              1, std::min((size_t)PW * PW * (size_t)std::max(L.nnz, 1), (size_t)nc * (size_t)kRapMaxCols));
+          s_tcol.ensure(tcap);
+          s_tval.ensure(tcap);
+          s_big.ensure((size_t)nc + 1);
+          amg_rap_fused(nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, s_toff.p,
+                        s_cnt.p, s_tcol.p, s_tval.p, s_err.p + 1, s_big.p, stream);
+        }
         probe_end(kProbeRap, stream, (double)L.nnz * 12 + (double)n * PW * 12 + (double)nc * 8);
         scan_exclusive(s_cnt.p, Ln.rp.p, nc + 1, stream, s_scan);
         int cnnz = 0, rnnz_used = 0;
@@ -513,7 +551,10 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         L.gR = row_group((double)rnnz_used / std::max(nc, 1));
         Ln.ci.ensure(std::max(cnnz, 1));
         Ln.a64.ensure(std::max(cnnz, 1));
-        amg_rap_compact(nc, s_toff.p, s_tcol.p, s_tval.p, Ln.rp.p, Ln.ci.p, Ln.a64.p, stream);
+        if (L.drap)
+          amg_drap_compact(nc, L.drap_tab.p, G, s_dac.p, s_dacf.p, Ln.rp.p, Ln.ci.p, Ln.a64.p, stream);
+        else
+          amg_rap_compact(nc, s_toff.p, s_tcol.p, s_tval.p, Ln.rp.p, Ln.ci.p, Ln.a64.p, stream);
         if (mixed) {
           L.pv32.ensure((size_t)std::max(n, 1) * PW);
           amg_cast(L.pv64.p, L.pv32.p, (size_t)n * PW, stream);
@@ -546,7 +587,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
       const bool large = L.max_blk > kDenseWave;
       if (large) s_dense.ensure(2 * doff);
       amg_dense_inv(L.blk.p, L.nblk, L.rp.p, L.ci.p, L.a64.p, s_dense.p, L.dmat64.p,
-                    mixed ? L.dmat32.p : nullptr, s_err.p + 2, large, stream);
+                    mixed ? L.dmat32.p : nullptr, s_err.p + 2, L.max_blk, stream);
       pt.mark("dense");
     }
     // cycle vectors
@@ -706,14 +747,20 @@ void Engine::refresh(const EngineOpts& o) {
       fill_async(Ln.chg.p, (uint8_t)0, (size_t)std::max(L.nc, 1), stream);
       amg_mark_coarse(L.ctiles.p, L.nctiles, L.pc.p, L.chg.p, Ln.chg.p, stream);
       probe_begin(kProbeRap, stream);
-      s_big.ensure((size_t)L.nc + 1);
-      amg_rap_known(L.nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, Ln.rp.p, Ln.ci.p,
-                    Ln.a64.p, s_err.p + 1, s_big.p, stream, Ln.chg.p);
+      if (L.drap) {
+        s_dap.ensure(std::max<long long>(L.drap_ap, 1));
+        amg_drap_known(L.n, L.nc, L.drap_tab.p, G, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, L.rrp.p, L.rci.p,
+                       L.rv64.p, s_dap.p, Ln.rp.p, Ln.ci.p, Ln.a64.p, stream, Ln.chg.p);
+      } else {
+        s_big.ensure((size_t)L.nc + 1);
+        amg_rap_known(L.nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, Ln.rp.p,
+                      Ln.ci.p, Ln.a64.p, s_err.p + 1, s_big.p, stream, Ln.chg.p);
+      }
       probe_end(kProbeRap, stream, (double)Ln.nnz * 12 + (double)L.nnz * 12 + (double)n * PW * 12);
     }
     if (L.nblk)
       amg_dense_inv(L.blk.p, L.nblk, L.rp.p, L.ci.p, L.a64.p, s_dense.p, L.dmat64.p, mixed ? L.dmat32.p : nullptr,
-                    s_err.p + 2, L.max_blk > kDenseWave, stream, L.chg.p);
+                    s_err.p + 2, L.max_blk, stream, L.chg.p);
   }
   int herr[4] = {0, 0, 0, 0};
   const int* pe = down(s_err.p, 4);

@@ -13,7 +13,7 @@ constexpr int PW = 4;            // max interpolation entries per fine row (ELL 
 constexpr int kTileRows = 256;   // rows per level tile
 constexpr int kMaxUnion = 128;   // max entries of one state's level-0 pattern row
 constexpr int kDenseMax = 1024;  // largest dense coarse block
-constexpr int kDenseWave = 88;   // blocks up to this size are inverted by one wavefront in LDS
+constexpr int kDenseWave = 96;   // blocks up to this size: one thread per row, rows in registers
 
 // POD view of one game for work-list kernels.
 struct GameDesc {
@@ -141,6 +141,11 @@ struct Level {
   DBuf<int> rrp, rci;             // R = P^T, CSR over the next level's rows
   DBuf<double> rv64;
   DBuf<float> rv32;
+  // Galerkin product through dense per-game blocks (small next levels)
+  bool drap = false;
+  long long drap_ap = 0, drap_ac = 0;  // dense entries of AP and of R A P
+  DBuf<long long> drap_tab;       // offset tables (fine rows, coarse rows, AP, R A P), 4 x (G+1)
+  std::vector<long long> h_drap_tab;
   // dense inverses of terminal slots: blocks (row0, size, offset into dmat)
   int nblk = 0, max_blk = 0;
   DBuf<int> blk;                  // [3*nblk]
@@ -291,6 +296,8 @@ class Engine {
   DBuf<int> s_toff, s_tcol;   // Galerkin product scratch rows (offsets, columns)
   DBuf<int> s_big;            // Galerkin product: rows left to the workgroup kernel
   DBuf<double> s_tval;        // and values
+  DBuf<double> s_dap, s_dac;  // dense Galerkin product scratch: AP, R A P
+  DBuf<uint8_t> s_dapt, s_dacf;  // and their structural flags
   DBuf<Tile> s_tiles;
   DBuf<double> s_dense;
  public:

@@ -34,6 +34,10 @@ _FAMILIES = (  # (substring of the kernel name, family); first match wins
     ("k_rap<", "rap"),
     ("k_rap_small", "rap"),
     ("k_rap_list", "rap"),
+    ("k_drap_ap", "rap"),
+    ("k_drap_ac", "rap"),
+    ("k_drap_count", "rap"),
+    ("k_drap_known", "rap"),
     ("k_interp", "interp"),
     ("k_tail<", "tail"),
 )
@@ -41,8 +45,9 @@ _FAMILIES = (  # (substring of the kernel name, family); first match wins
 
 # kernels that complete a launch of their family rather than start one: the
 # Galerkin product of a large level is the wavefront kernel followed by the
-# workgroup kernel over the rows it left (one probe launch, two kernels)
-_CONTINUATIONS = ("k_rap_list",)
+# workgroup kernel over the rows it left (one probe launch, two kernels); the
+# dense product of a small level starts with AP and continues with R (AP)
+_CONTINUATIONS = ("k_rap_list", "k_drap_ac", "k_drap_count", "k_drap_known")
 
 
 def starts_launch(name: str) -> bool:
