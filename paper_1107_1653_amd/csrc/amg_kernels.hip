@@ -1929,11 +1929,14 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const int* __restrict__ g
     T* xv = lds + off[l - l0];
     T* yv = xv + n;
     deep = l;
-    if (q.flags & kTailDense) {
-      for (int i = tid; i < n; i += kTailThreads) {
+    if (q.flags & kTailDense) {  // x = inv b: one wavefront per row, lanes over columns
+      const int lane = tid & 63;
+      for (int i = tid >> 6; i < n; i += kTailThreads / 64) {
         T acc = 0;
-        for (int j = 0; j < n; ++j) acc += L.dm[(size_t)q.doff + (size_t)j * n + i] * L.b[r0 + j];
-        xv[i] = acc;
+        for (int j = lane; j < n; j += 64) acc += L.dm[(size_t)q.doff + (size_t)j * n + i] * L.b[r0 + j];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (lane == 0) xv[i] = acc;
       }
       __syncthreads();
       break;

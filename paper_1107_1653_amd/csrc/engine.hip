@@ -645,11 +645,15 @@ void Engine::build_tail(bool mixed) {
       last = l;
       if (!lv[l].cont[g]) break;
     }
-    // rows of the game summed over levels l..last
-    std::vector<long> cum(last + 2, 0);
-    for (int l = last; l >= 0; --l) cum[l] = cum[l + 1] + (lv[l].goff[g + 1] - lv[l].goff[g]);
+    // rows of the game summed over levels l..last, and their largest level
+    std::vector<long> cum(last + 2, 0), big(last + 2, 0);
+    for (int l = last; l >= 0; --l) {
+      const long rows = lv[l].goff[g + 1] - lv[l].goff[g];
+      cum[l] = cum[l + 1] + rows;
+      big[l] = std::max(big[l + 1], rows);
+    }
     for (int l = 0; l <= last; ++l) {
-      if (lv[l].goff[g + 1] - lv[l].goff[g] <= kTailRows && cum[l] <= cap && last - l < kTailMaxLevels) {
+      if (big[l] <= kTailRows && cum[l] <= cap && last - l < kTailMaxLevels) {
         h_lt[g] = l;
         lds_rows[l] = std::max(lds_rows[l], (int)cum[l]);
         break;
