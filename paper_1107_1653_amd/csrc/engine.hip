@@ -1014,7 +1014,13 @@ int Engine::step() {
   PhaseTimer pt(this, prof);
   assemble(run, mixed);
   pt.mark("assemble");
-  bool full = !have_hier || stagnated || run != run_at_setup || o.reuse_frac <= 0.0 ||
+  // the hierarchy serves any subset of the games it was built for (the
+  // levels are block diagonal over games; finished games are skipped)
+  std::vector<int> rs = run, hs_ = run_at_setup;
+  std::sort(rs.begin(), rs.end());
+  std::sort(hs_.begin(), hs_.end());
+  const bool subset = std::includes(hs_.begin(), hs_.end(), rs.begin(), rs.end());
+  bool full = !have_hier || stagnated || !subset || o.reuse_frac <= 0.0 ||
               (double)changes_since_setup > o.reuse_frac * std::max(1, N0) ||
               last_cycles > std::max(2 * cycles_after_full, cycles_after_full + 6);
   stagnated = false;
