@@ -331,14 +331,17 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-template <int kIwHash, int kIwK>
-__global__ __launch_bounds__(64) void k_interp_wave(const Tile* __restrict__ tiles, const int* __restrict__ rp,
-                                                    const int* __restrict__ ci, const double* __restrict__ a,
-                                                    const double* __restrict__ dinv,
-                                                    const uint8_t* __restrict__ strong,
-                                                    const int8_t* __restrict__ cf, const int* __restrict__ cidx,
-                                                    const uint8_t* __restrict__ dir, int* __restrict__ pc,
-                                                    double* __restrict__ pv, int* __restrict__ capped) {
+// DEFER: a row that does not fit is appended to defer[1 ..] (count in
+// defer[0]) and left to a larger instance, instead of falling back to direct
+// interpolation; the larger instance then computes exactly what it computes
+// for any row.
+template <int kIwHash, int kIwK, bool DEFER>
+__device__ __forceinline__ void interp_row(int i, const int* __restrict__ rp, const int* __restrict__ ci,
+                                           const double* __restrict__ a, const double* __restrict__ dinv,
+                                           const uint8_t* __restrict__ strong, const int8_t* __restrict__ cf,
+                                           const int* __restrict__ cidx, const uint8_t* __restrict__ dir,
+                                           int* __restrict__ pc, double* __restrict__ pv, int* __restrict__ capped,
+                                           int* __restrict__ defer) {
   __shared__ int hkey[kIwHash];
   __shared__ int hpos[kIwHash];
   __shared__ int mem[kIwHash];
@@ -350,9 +353,6 @@ __global__ __launch_bounds__(64) void k_interp_wave(const Tile* __restrict__ til
   __shared__ double sc[kIwStage];
   __shared__ int full_sh;
 
-  const Tile t = tiles[blockIdx.x / kTileRows];
-  const int i = t.r0 + (int)(blockIdx.x % kTileRows);
-  if (i >= t.r1) return;
   const int lane = threadIdx.x;
   if (lane < PW) {
     pc[(size_t)i * PW + lane] = -1;
@@ -415,6 +415,10 @@ __global__ __launch_bounds__(64) void k_interp_wave(const Tile* __restrict__ til
     if (nK > kIwK) atomicOr(&full_sh, 1);
     __syncthreads();
     if (full_sh) {
+      if (DEFER) {
+        if (lane == 0) defer[1 + atomicAdd(defer, 1)] = i;
+        return;
+      }
       if (lane == 0) atomicAdd(capped, 1);
       if (direct) return;  // even the direct set does not fit: no interpolation
       direct = true;
@@ -464,6 +468,10 @@ __global__ __launch_bounds__(64) void k_interp_wave(const Tile* __restrict__ til
     if (bad) atomicOr(&full_sh, 1);
     __syncthreads();
     if (full_sh) {
+      if (DEFER) {
+        if (lane == 0) defer[1 + atomicAdd(defer, 1)] = i;
+        return;
+      }
       if (lane == 0) atomicAdd(capped, 1);
       if (direct) return;
       direct = true;
@@ -659,6 +667,38 @@ __global__ __launch_bounds__(64) void k_interp_wave(const Tile* __restrict__ til
       }
     }
     return;
+  }
+}
+
+// one wavefront per row of the tiles
+template <int kIwHash, int kIwK, bool DEFER>
+__global__ __launch_bounds__(64) void k_interp_wave(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                                                    const int* __restrict__ ci, const double* __restrict__ a,
+                                                    const double* __restrict__ dinv,
+                                                    const uint8_t* __restrict__ strong,
+                                                    const int8_t* __restrict__ cf, const int* __restrict__ cidx,
+                                                    const uint8_t* __restrict__ dir, int* __restrict__ pc,
+                                                    double* __restrict__ pv, int* __restrict__ capped,
+                                                    int* __restrict__ defer) {
+  const Tile t = tiles[blockIdx.x / kTileRows];
+  const int i = t.r0 + (int)(blockIdx.x % kTileRows);
+  if (i >= t.r1) return;
+  interp_row<kIwHash, kIwK, DEFER>(i, rp, ci, a, dinv, strong, cf, cidx, dir, pc, pv, capped, defer);
+}
+
+// the rows deferred by the smaller instance, one wavefront each in turn
+template <int kIwHash, int kIwK>
+__global__ __launch_bounds__(64) void k_interp_wave_list(const int* __restrict__ list, const int* __restrict__ rp,
+                                                         const int* __restrict__ ci, const double* __restrict__ a,
+                                                         const double* __restrict__ dinv,
+                                                         const uint8_t* __restrict__ strong,
+                                                         const int8_t* __restrict__ cf, const int* __restrict__ cidx,
+                                                         const uint8_t* __restrict__ dir, int* __restrict__ pc,
+                                                         double* __restrict__ pv, int* __restrict__ capped) {
+  const int cnt = list[0];
+  for (int k = blockIdx.x; k < cnt; k += gridDim.x) {
+    interp_row<kIwHash, kIwK, false>(list[1 + k], rp, ci, a, dinv, strong, cf, cidx, dir, pc, pv, capped, nullptr);
+    __syncthreads();  // the next row reuses the LDS
   }
 }
 
@@ -2158,15 +2198,21 @@ void amg_gather_int(const int* src, const int* idx, int m, int* dst, hipStream_t
 }
 void amg_interp(const Tile* t, int nt, const int* rp, const int* ci, const double* a, const double* dinv,
                 const uint8_t* strong, const int8_t* cf, const int* cidx, const uint8_t* dir, int* pc,
-                double* pv, int* capped, int wave, hipStream_t s) {
+                double* pv, int* capped, int wave, int* defer, int rows, hipStream_t s) {
   if (!nt) return;
   if (wave == 2)
-    hipLaunchKernelGGL((k_interp_wave<1024, 256>), dim3(nt * kTileRows), dim3(64), 0, s, t, rp, ci, a, dinv, strong,
-                       cf, cidx, dir, pc, pv, capped);
-  else if (wave == 1)
-    hipLaunchKernelGGL((k_interp_wave<512, 128>), dim3(nt * kTileRows), dim3(64), 0, s, t, rp, ci, a, dinv, strong,
-                       cf, cidx, dir, pc, pv, capped);
-  else
+    hipLaunchKernelGGL((k_interp_wave<1024, 256, false>), dim3(nt * kTileRows), dim3(64), 0, s, t, rp, ci, a, dinv,
+                       strong, cf, cidx, dir, pc, pv, capped, (int*)nullptr);
+  else if (wave == 1) {
+    // a small instance (twice the wavefronts per CU) for all rows, then the
+    // rows it could not hold
+    fill_async(defer, 0, 1, s);
+    hipLaunchKernelGGL((k_interp_wave<256, 64, true>), dim3(nt * kTileRows), dim3(64), 0, s, t, rp, ci, a, dinv,
+                       strong, cf, cidx, dir, pc, pv, capped, defer);
+    SHP_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_interp_wave_list<512, 128>), dim3(std::max(1, std::min(rows, 2048))), dim3(64), 0, s, defer,
+                       rp, ci, a, dinv, strong, cf, cidx, dir, pc, pv, capped);
+  } else
     hipLaunchKernelGGL(k_interp_lds, dim3(nt * (kTileRows / kIThreads)), dim3(kIThreads), 0, s, t, rp, ci, a,
                        dinv, strong, cf, cidx, dir, pc, pv, capped);
   SHP_LAUNCH_CHECK();

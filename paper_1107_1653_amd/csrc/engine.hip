@@ -459,8 +459,9 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         // levels (long rows): one wavefront per row, with the larger LDS sets
         // where rows average more than 32 entries
         const int iw = l == 0 ? 0 : ((double)L.nnz > 32.0 * std::max(n, 1) ? 2 : 1);
+        s_defer.ensure((size_t)L.rows_ctiles + 1);
         amg_interp(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, L.dinv64.p, L.strong.p, L.cf.p,
-                   L.cidx.p, L.dir.p, L.pc.p, L.pv64.p, s_err.p, iw, stream);
+                   L.cidx.p, L.dir.p, L.pc.p, L.pv64.p, s_err.p, iw, s_defer.p, L.rows_ctiles, stream);
         probe_end(kProbeInterp, stream, (double)L.rows_ctiles * (PW * 12) + (double)L.nnz * 13);
         pt.mark("interp");
         // ---- next level rows

@@ -295,6 +295,7 @@ class Engine {
   DBuf<int> s_cnt, s_cursor, s_scan, s_err, s_left, s_newc, s_gidx, s_gout, s_goff;
   DBuf<int> s_toff, s_tcol;   // Galerkin product scratch rows (offsets, columns)
   DBuf<int> s_big;            // Galerkin product: rows left to the workgroup kernel
+  DBuf<int> s_defer;          // interpolation: rows left to the larger instance
   DBuf<double> s_tval;        // and values
   DBuf<double> s_dap, s_dac;  // dense Galerkin product scratch: AP, R A P
   DBuf<uint8_t> s_dapt, s_dacf;  // and their structural flags
