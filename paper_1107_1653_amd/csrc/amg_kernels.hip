@@ -99,9 +99,11 @@ __global__ void k_pmis_select(const Tile* __restrict__ tiles, const int* __restr
                               const int* __restrict__ ci, const uint8_t* __restrict__ strong,
                               const int* __restrict__ st_rp, const int* __restrict__ st_ci,
                               const int8_t* __restrict__ cf, const uint64_t* __restrict__ key,
-                              int* __restrict__ newc, int* __restrict__ left) {
-  // the following update kernel counts the undecided rows into *left
-  if (blockIdx.x == 0 && threadIdx.x == 0) *left = 0;
+                              int* __restrict__ newc, int* __restrict__ left, int round) {
+  // the following update kernel counts the undecided rows into left[round & 1];
+  // once a round has left none undecided, later rounds do nothing
+  if (blockIdx.x == 0 && threadIdx.x == 0) left[round & 1] = 0;
+  if (round > 0 && left[(round - 1) & 1] == 0) return;
   Tile t = tiles[blockIdx.x];
   int i = t.r0 + threadIdx.x;
   if (i >= t.r1) return;
@@ -128,7 +130,8 @@ __global__ void k_pmis_select(const Tile* __restrict__ tiles, const int* __restr
 __global__ void k_pmis_update(const Tile* __restrict__ tiles, const int* __restrict__ rp,
                               const int* __restrict__ ci, const uint8_t* __restrict__ strong,
                               int8_t* __restrict__ cf, const int* __restrict__ newc,
-                              int* __restrict__ left) {
+                              int* __restrict__ left, int round) {
+  if (round > 0 && left[(round - 1) & 1] == 0) return;
   Tile t = tiles[blockIdx.x];
   int i = t.r0 + threadIdx.x;
   int und = 0;
@@ -146,7 +149,7 @@ __global__ void k_pmis_update(const Tile* __restrict__ tiles, const int* __restr
     }
   }
   for (int o = 32; o > 0; o >>= 1) und += __shfl_xor(und, o);
-  if ((threadIdx.x & 63) == 0 && und) atomicAdd(left, und);
+  if ((threadIdx.x & 63) == 0 && und) atomicAdd(&left[round & 1], und);
 }
 
 __global__ void k_fill_cf(const Tile* __restrict__ tiles, int8_t* __restrict__ cf, int8_t val) {
@@ -2169,16 +2172,16 @@ void amg_pmis_init(const Tile* t, int nt, const int* goff, const uint8_t* dir, c
 }
 void amg_pmis_select(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
                      const int* st_rp, const int* st_ci, const int8_t* cf, const uint64_t* key,
-                     int* newc, int* left, hipStream_t s) {
+                     int* newc, int* left, int round, hipStream_t s) {
   if (!nt) return;
   hipLaunchKernelGGL(k_pmis_select, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, strong, st_rp, st_ci,
-                     cf, key, newc, left);
+                     cf, key, newc, left, round);
   SHP_LAUNCH_CHECK();
 }
 void amg_pmis_update(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
-                     int8_t* cf, const int* newc, int* left, hipStream_t s) {
+                     int8_t* cf, const int* newc, int* left, int round, hipStream_t s) {
   if (!nt) return;
-  hipLaunchKernelGGL(k_pmis_update, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, strong, cf, newc, left);
+  hipLaunchKernelGGL(k_pmis_update, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, strong, cf, newc, left, round);
   SHP_LAUNCH_CHECK();
 }
 void amg_fill_cf(const Tile* t, int nt, int8_t* cf, int8_t val, hipStream_t s) {

@@ -250,10 +250,12 @@ void Engine::build_layout() {
   L0.goff = x_off;
 
   d_active.ensure(std::max(G, 1));
-  d_lin_active.ensure(std::max(G, 1));
-  d_cnt.ensure(2 * std::max(G, 1));
+  h_active_dev.clear();
   d_norm.ensure(4 * std::max(G, 1));
-  d_shap.ensure(2 * std::max(G, 1));
+  d_shap.ensure(3 * std::max(G, 1));
+  d_cnt = reinterpret_cast<int*>(d_shap.p + 2 * std::max(G, 1));
+  d_lin.ensure(2 * std::max(G, 1));  // LinCtl is larger than an int
+  d_lin_active = reinterpret_cast<int*>(d_lin.p + std::max(G, 1));
   d_decision.ensure(std::max(G, 1));
   {
     const int gp = stripe_games(G);
@@ -320,7 +322,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
     theta = dim >= 3 ? 0.5 : 0.25;
   }
   s_err.ensure(4);
-  s_left.ensure(1);
+  s_left.ensure(2);
   fill_async(s_err.p, 0, 4, stream);
   PhaseTimer pt(this, prof);
   nlev = 0;
@@ -388,37 +390,41 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
       uint32_t salt = mix32(0x9E3779B9u * (uint32_t)(l + 1) + 12345u);
       amg_pmis_init(L.ctiles.p, L.nctiles, s_goff.p, L.dir.p, L.lam.p, salt, L.cf.p, L.key.p, stream);
       s_newc.ensure(std::max(n, 1));
-      // rounds run in pairs between checks of the undecided count (a round
-      // with nothing undecided changes nothing)
-      for (int round = 0, burst = 4; round < 1000; round += burst, burst = 2) {
-        for (int rr = 0; rr < burst; ++rr) {
+      // rounds are queued in bursts; the undecided count is checked with the
+      // coarse numbering below (rounds after the last undecided row do nothing)
+      int round = 0;
+      auto pmis_rounds = [&](int k) {
+        for (int rr = 0; rr < k; ++rr, ++round) {
           amg_pmis_select(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.strong.p, L.st_rp.p, L.st_ci.p, L.cf.p,
-                          L.key.p, s_newc.p, s_left.p, stream);
-          amg_pmis_update(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.strong.p, L.cf.p, s_newc.p, s_left.p,
+                          L.key.p, s_newc.p, s_left.p, round, stream);
+          amg_pmis_update(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.strong.p, L.cf.p, s_newc.p, s_left.p, round,
                           stream);
         }
-        const int* left = down(s_left.p, 1);
-        sync();
-        if (*left == 0) break;
-        if (round >= 998) throw Error(SHAPLEY_EDEVICE, "PMIS did not terminate");
-      }
+      };
+      pmis_rounds(6);
       pt.mark("pmis");
       // ---- coarse numbering and per-game coarse sizes
       auto number = [&](std::vector<int>& ncg) {
-        amg_is_c(L.cf.p, L.tmp.p, n, stream);
-        fill_async(L.tmp.p + n, 0, 1, stream);
-        scan_exclusive(L.tmp.p, L.cidx.p, n + 1, stream, s_scan);
-        s_gidx.ensure(G + 1);
-        s_gout.ensure(G + 1);
-        up(s_gidx.p, L.goff.data(), G + 1);
-        amg_gather_int(L.cidx.p, s_gidx.p, G + 1, s_gout.p, stream);
-        std::vector<int> cpre(G + 1);
-        const int* cp = down(s_gout.p, G + 1);
-        sync();
-        cpre.assign(cp, cp + G + 1);
-        ncg.assign(G, 0);
-        for (int g = 0; g < G; ++g) ncg[g] = cpre[g + 1] - cpre[g];
-        return cpre;
+        while (true) {
+          amg_is_c(L.cf.p, L.tmp.p, n, stream);
+          fill_async(L.tmp.p + n, 0, 1, stream);
+          scan_exclusive(L.tmp.p, L.cidx.p, n + 1, stream, s_scan);
+          s_gout.ensure(G + 1);
+          amg_gather_int(L.cidx.p, s_goff.p, G + 1, s_gout.p, stream);
+          std::vector<int> cpre(G + 1);
+          const int* cp = down(s_gout.p, G + 1);
+          const int* left = down(s_left.p + ((round - 1) & 1), 1);
+          sync();
+          if (*left != 0) {  // PMIS not finished: more rounds, then number again
+            if (round >= 1000) throw Error(SHAPLEY_EDEVICE, "PMIS did not terminate");
+            pmis_rounds(4);
+            continue;
+          }
+          cpre.assign(cp, cp + G + 1);
+          ncg.assign(G, 0);
+          for (int g = 0; g < G; ++g) ncg[g] = cpre[g + 1] - cpre[g];
+          return cpre;
+        }
       };
       std::vector<int> ncg;
       std::vector<int> cpre = number(ncg);
@@ -884,51 +890,55 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
     c.res_prev = S->res_prev;
     c.max_cycles = S->opt.max_cycles;
   }
-  d_lin.ensure(std::max(G, 1));
-  up(d_lin_active.p, h_lin_active.data(), G);
-  up(d_lin.p, h_lin.data(), G);
+  // controls and active flags in one transfer
+  const int Gm = std::max(G, 1);
+  h_linbuf.assign(2 * (size_t)Gm, LinCtl{});
+  std::copy(h_lin.begin(), h_lin.end(), h_linbuf.begin());
+  std::memcpy(h_linbuf.data() + Gm, h_lin_active.data(), sizeof(int) * G);
+  up(d_lin.p, h_linbuf.data(), 2 * (size_t)Gm);
   // The stop test runs on the device after every FP64 residual; cycles are
   // queued in chunks ending with a residual and its test, the first chunk as
   // long as the previous solve (cycles of games that stopped return at once).
   auto resid_check = [&]() {
     probe_begin(kProbeResid64, stream);
     if (mixed)
-      cyc_resid64<float>(L0.tiles.p, L0.ntiles, d_lin_active.p, L0.rp.p, L0.ci.p, L0.a64.p, rhs.p, sol.p,
+      cyc_resid64<float>(L0.tiles.p, L0.ntiles, d_lin_active, L0.rp.p, L0.ci.p, L0.a64.p, rhs.p, sol.p,
                          L0.b32.p, fold, L0.gA, stream);
     else
-      cyc_resid64<double>(L0.tiles.p, L0.ntiles, d_lin_active.p, L0.rp.p, L0.ci.p, L0.a64.p, rhs.p, sol.p,
+      cyc_resid64<double>(L0.tiles.p, L0.ntiles, d_lin_active, L0.rp.p, L0.ci.p, L0.a64.p, rhs.p, sol.p,
                           L0.b64.p, fold, L0.gA, stream);
     {
       const double rows = L0.rows_tiles;
       const double nnz = L0.n ? (double)L0.nnz * rows / L0.n : 0.0;
       probe_end(kProbeResid64, stream, rows * (4 + 8 + 8 + (mixed ? 4 : 8)) + nnz * 12);
     }
-    launch_lin_check(fold, G, d_bnorm.p, d_lin.p, d_lin_active.p, d_norm.p, stream);
+    launch_lin_check(fold, G, d_bnorm.p, d_lin.p, d_lin_active, d_norm.p, stream);
   };
   resid_check();
   int chunk = std::max(1, std::min(last_cycles, 16));
   while (true) {
     for (int c = 0; c < chunk; ++c) {
       if (mixed) {
-        float* e = vcycle_level<float>(this, lv, 0, o, d_lin_active.p, stream);
-        cyc_update64<float>(L0.tiles.p, L0.ntiles, d_lin_active.p, e, sol.p, stream);
+        float* e = vcycle_level<float>(this, lv, 0, o, d_lin_active, stream);
+        cyc_update64<float>(L0.tiles.p, L0.ntiles, d_lin_active, e, sol.p, stream);
       } else {
-        double* e = vcycle_level<double>(this, lv, 0, o, d_lin_active.p, stream);
-        cyc_update64<double>(L0.tiles.p, L0.ntiles, d_lin_active.p, e, sol.p, stream);
+        double* e = vcycle_level<double>(this, lv, 0, o, d_lin_active, stream);
+        cyc_update64<double>(L0.tiles.p, L0.ntiles, d_lin_active, e, sol.p, stream);
       }
       resid_check();
     }
-    const int* pa = down(d_lin_active.p, G);
+    const LinCtl* pl = down(d_lin.p, 2 * (size_t)Gm);
     sync();
+    const int* pa = reinterpret_cast<const int*>(pl + Gm);
     h_lin_active.assign(pa, pa + G);
     bool any = false;
     for (int g : run) any |= h_lin_active[g] != 0;
-    if (!any) break;
+    if (!any) {
+      h_lin.assign(pl, pl + G);
+      break;
+    }
     chunk = 1;
   }
-  const LinCtl* pl = down(d_lin.p, G);
-  sync();
-  h_lin.assign(pl, pl + G);
   for (int g : run) {
     SlotState* S = slots[g];
     const LinCtl& c = h_lin[g];
@@ -952,7 +962,7 @@ void Engine::improve(const std::vector<int>& run, double tie_rtol) {
   probe_begin(kProbeImprove, stream);
   launch_improve(ddesc.p, gtiles_imp.p, (int)h_gtiles_imp.size(), d_active.p, tie_rtol, fold, stream);
   probe_end(kProbeImprove, stream, bytes);
-  launch_fold_finish(fold, G, 2, 2u, 2, d_shap.p, 2, d_cnt.p, 2, stream);
+  launch_fold_finish(fold, G, 2, 2u, 2, d_shap.p, 2, d_cnt, 2, stream);
 }
 
 // The decisions are applied asynchronously (the host copy stays alive in a
@@ -972,6 +982,7 @@ void Engine::run_init(const std::vector<int>& run) {
   std::vector<int> act(G, 0);
   for (int g : fresh) act[g] = 1;
   up(d_active.p, act.data(), G);
+  h_active_dev = act;
   improve(fresh, slots[fresh[0]]->opt.tie_rtol);
   std::vector<double> hs(2 * G);
   const double* ps = down(d_shap.p, 2 * G);
@@ -993,6 +1004,7 @@ void Engine::improve_only() {
   for (int g = 0; g < G; ++g) all.push_back(g);
   std::vector<int> act(G, 1);
   up(d_active.p, act.data(), G);
+  h_active_dev = act;
   improve(all, slots.empty() ? 1e-12 : slots[0]->opt.tie_rtol);
   sync();
 }
@@ -1009,7 +1021,10 @@ int Engine::step() {
   d_bnorm.ensure(std::max(G, 1));
   h_active.assign(G, 0);
   for (int g : run) h_active[g] = 1;
-  up(d_active.p, h_active.data(), G);
+  if (h_active != h_active_dev) {
+    up(d_active.p, h_active.data(), G);
+    h_active_dev = h_active;
+  }
 
   double t0 = now_s();
   PhaseTimer pt(this, prof);
@@ -1058,8 +1073,8 @@ int Engine::step() {
   improve(run, o.tie_rtol);
   std::vector<double> hs(2 * G);
   std::vector<int> hc(2 * G);
-  const double* ps = down(d_shap.p, 2 * G);
-  const int* pcn = down(d_cnt.p, 2 * G);
+  const double* ps = down(d_shap.p, 3 * (size_t)std::max(G, 1));  // residuals, then the counts
+  const int* pcn = reinterpret_cast<const int*>(ps + 2 * std::max(G, 1));
   sync();
   hs.assign(ps, ps + 2 * G);
   hc.assign(pcn, pcn + 2 * G);

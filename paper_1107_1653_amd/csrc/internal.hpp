@@ -271,9 +271,11 @@ class Engine {
   std::vector<Level> lv;
   int nlev = 0;
   // per-slot device scalars
-  DBuf<int> d_active, d_lin_active, d_cnt;    // cnt: [2*G] inner/outer change counts
+  DBuf<int> d_active;
+  std::vector<int> h_active_dev;              // what d_active holds
   DBuf<double> d_norm;                        // [4*G] res max, x max, b max, spare
-  DBuf<double> d_shap;                        // [2*G] shapley residual max, sum sq
+  DBuf<double> d_shap;                        // [2*G] shapley residual max, sum sq, then cnt
+  int* d_cnt = nullptr;                       // [2*G] inner/outer change counts (inside d_shap)
   DBuf<int> d_decision;
   // V-cycle tail tables (built at setup)
   DBuf<TailGL> d_tailgl;
@@ -281,7 +283,9 @@ class Engine {
   DBuf<TailLev<float>> d_tail32;
   std::vector<int> h_lt;  // first tail level of each game (nlev: none)
   void build_tail(bool mixed);
-  DBuf<LinCtl> d_lin;
+  DBuf<LinCtl> d_lin;                         // [G] controls, then the active flags
+  int* d_lin_active = nullptr;                // [G] (inside d_lin)
+  std::vector<LinCtl> h_linbuf;
   std::vector<LinCtl> h_lin;
   std::vector<int> h_decision;
   // striped reduction copies (kept cleared between uses)
