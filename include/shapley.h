@@ -193,6 +193,31 @@ int shapley_game_info(shapley_game_t g, int64_t* n, int32_t* m1, int32_t* m2);
 /* Device bytes held by the handle. */
 int shapley_game_bytes(shapley_game_t g, size_t* bytes);
 
+/* Inspection of the algebraic multigrid hierarchy (Sec. 4.3) built by the
+ * last shapley_solve of g, run alone on the handle's own stream (opts.stream
+ * NULL; for a hierarchy handle, the finest grid's).  Level 0 is the operator
+ * I - mu P of the last policy pair the hierarchy was built or refreshed from;
+ * level l+1 is the Galerkin product P_l^T A_l P_l.
+ *   info: levels (count), pw (slots per row of P), n, nnz (of A_level) and nc
+ *         (rows of level+1, 0 on the last level).
+ *   rp[n+1], ci[nnz], a[nnz]: A_level in CSR, columns sorted within a row.
+ *   pc[n*pw], pv[n*pw]: P_level by rows (column index into level+1, -1 for
+ *         an empty slot), written only when nc > 0.
+ * Host arrays owned by the caller, each may be NULL (call first with NULL
+ * arrays for the sizes).  Synchronises the handle's stream.  Errors:
+ * SHAPLEY_EINVAL when no such hierarchy is held (another solve ran on the
+ * stream since, or the game was solved in a batch) or level is out of
+ * range. */
+typedef struct shapley_level_info {
+  int32_t levels;
+  int32_t pw;
+  int64_t n;
+  int64_t nnz;
+  int64_t nc;
+} shapley_level_info;
+int shapley_hierarchy_level(shapley_game_t g, int32_t level, shapley_level_info* info, int32_t* rp, int32_t* ci,
+                            double* a, int32_t* pc, double* pv);
+
 void shapley_game_destroy(shapley_game_t g);
 
 /* ---------------------------------------------------------------- batch */

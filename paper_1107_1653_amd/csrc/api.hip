@@ -496,6 +496,26 @@ int shapley_game_info(shapley_game_t gh, int64_t* n, int32_t* m1, int32_t* m2) {
   });
 }
 
+int shapley_hierarchy_level(shapley_game_t gh, int32_t level, shapley_level_info* info, int32_t* rp, int32_t* ci,
+                            double* a, int32_t* pc, double* pv) {
+  return guarded([&] {
+    SHP_REQUIRE(gh && gh->g, "null game");
+    Game* g = gh->g->finest();
+    Engine* e = engine_cached(g->stream);
+    SHP_REQUIRE(e && e->hier_game == g, "no AMG hierarchy of this game (solve it alone on its own stream first)");
+    int levels = 0;
+    int64_t n = 0, nnz = 0, nc = 0;
+    e->level_export(level, &levels, &n, &nnz, &nc, rp, ci, a, pc, pv);
+    if (info) {
+      info->levels = levels;
+      info->pw = PW;
+      info->n = n;
+      info->nnz = nnz;
+      info->nc = nc;
+    }
+  });
+}
+
 int shapley_game_bytes(shapley_game_t gh, size_t* bytes) {
   return guarded([&] {
     SHP_REQUIRE(gh && gh->g && bytes, "null argument");

@@ -159,6 +159,29 @@ void engine_cache_drop(hipStream_t s) {
   g_cache.erase(it);
 }
 
+Engine* engine_cached(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  auto it = g_cache.find(s);
+  return it == g_cache.end() ? nullptr : it->second.get();
+}
+
+void Engine::level_export(int l, int* levels, int64_t* n, int64_t* nnz, int64_t* nc, int32_t* rp, int32_t* ci,
+                          double* a, int32_t* pc, double* pv) {
+  if (l < 0 || l >= nlev) throw Error(SHAPLEY_EINVAL, "level out of range");
+  const Level& L = lv[l];
+  const int cn = l + 1 < nlev ? L.nc : 0;
+  if (levels) *levels = nlev;
+  if (n) *n = L.n;
+  if (nnz) *nnz = L.nnz;
+  if (nc) *nc = cn;
+  SHP_HIP(hipStreamSynchronize(stream));
+  if (rp) SHP_HIP(hipMemcpy(rp, L.rp.p, sizeof(int) * ((size_t)L.n + 1), hipMemcpyDeviceToHost));
+  if (ci && L.nnz) SHP_HIP(hipMemcpy(ci, L.ci.p, sizeof(int) * (size_t)L.nnz, hipMemcpyDeviceToHost));
+  if (a && L.nnz) SHP_HIP(hipMemcpy(a, L.a64.p, sizeof(double) * (size_t)L.nnz, hipMemcpyDeviceToHost));
+  if (cn && pc) SHP_HIP(hipMemcpy(pc, L.pc.p, sizeof(int) * (size_t)L.n * PW, hipMemcpyDeviceToHost));
+  if (cn && pv) SHP_HIP(hipMemcpy(pv, L.pv64.p, sizeof(double) * (size_t)L.n * PW, hipMemcpyDeviceToHost));
+}
+
 EngineLease::EngineLease(hipStream_t s, bool keep)
     : s_(s), keep_(keep), uncaught_(std::uncaught_exceptions()) {
   if (keep) {
@@ -629,6 +652,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
     if (herr[2] != 0) throw Error(SHAPLEY_EDEVICE, "singular coarsest block");
   }
   build_tail(mixed);
+  hier_game = G == 1 ? slots[0]->g : nullptr;
   // statistics
   double nnz_sum = 0, n_sum = 0;
   for (int k = 0; k < nlev; ++k) { nnz_sum += lv[k].nnz; n_sum += lv[k].n; }

@@ -255,6 +255,11 @@ class Engine {
   void reset();
   // Evaluates the improvement sweep at the slots' current v (no decisions).
   void improve_only();
+  const Game* hier_game = nullptr;  // the game of a one-game hierarchy (inspection)
+  // Copies level l of a one-game hierarchy to the host (synchronous): sizes,
+  // A_l (CSR) and, when a coarser level exists, P_l (PW slots per row).
+  void level_export(int l, int* levels, int64_t* n, int64_t* nnz, int64_t* nc, int32_t* rp, int32_t* ci,
+                    double* a, int32_t* pc, double* pv);
 
  private:
   bool layout_dirty = true;
@@ -349,6 +354,7 @@ class EngineLease {
 };
 void games_alive_add(int delta);      // game handles created (+1) / destroyed (-1)
 void engine_cache_drop(hipStream_t s);  // before a stream is destroyed
+Engine* engine_cached(hipStream_t s);   // the idle engine cached for s, or null
 
 // FAMGpi transfers between two grid levels of the same game family.
 void fmg_transfer(Game* coarse, Game* fine, hipStream_t s);

@@ -31,7 +31,8 @@ SHAPLEY_HOST_PTRS = 0
 EXPORTED = [
     "shapley_last_error", "shapley_default_opts", "shapley_game_create",
     "shapley_game_create_hierarchy", "shapley_solve", "shapley_get_value", "shapley_get_policy",
-    "shapley_apply_operator", "shapley_game_info", "shapley_game_bytes", "shapley_game_destroy",
+    "shapley_apply_operator", "shapley_game_info", "shapley_game_bytes", "shapley_hierarchy_level",
+    "shapley_game_destroy",
     "shapley_solve_batch", "shapley_server_create", "shapley_server_submit", "shapley_server_wait",
     "shapley_server_poll", "shapley_server_step", "shapley_server_destroy",
     "shapley_probe_enable", "shapley_probe_read",
@@ -59,6 +60,11 @@ class shapley_solve_opts(C.Structure):
         ("coarse_max", C.c_int32), ("max_levels", C.c_int32), ("verbose", C.c_int32),
         ("stream", C.c_void_p), ("reuse_frac", C.c_double), ("forcing", C.c_double),
     ]
+
+
+class shapley_level_info(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("pw", C.c_int32), ("n", C.c_int64), ("nnz", C.c_int64),
+                ("nc", C.c_int64)]
 
 
 class shapley_stats(C.Structure):
@@ -109,6 +115,7 @@ def lib() -> C.CDLL:
         L.shapley_apply_operator.argtypes = [P, P, P, P, P]
         L.shapley_game_info.argtypes = [P, P, P, P]
         L.shapley_game_bytes.argtypes = [P, C.POINTER(C.c_size_t)]
+        L.shapley_hierarchy_level.argtypes = [P, C.c_int32, C.POINTER(shapley_level_info), P, P, P, P, P]
         L.shapley_game_destroy.argtypes = [P]
         L.shapley_game_destroy.restype = None
         L.shapley_solve_batch.argtypes = [C.POINTER(P), C.c_int32, C.POINTER(shapley_solve_opts),
@@ -248,6 +255,23 @@ def shapley_apply_operator(g, v):
     b = np.empty(n, dtype=np.int32)
     _check(lib().shapley_apply_operator(g, _ptr(vv), _ptr(F), _ptr(a), _ptr(b)))
     return F, a, b
+
+
+def shapley_hierarchy_level(g, level: int) -> dict:
+    """Level `level` of the AMG hierarchy of g's last solve: A (CSR arrays
+    rp, ci, a), P (pc, pv of shape (n, pw), only when nc > 0) and the sizes."""
+    info = shapley_level_info()
+    _check(lib().shapley_hierarchy_level(g, int(level), C.byref(info), None, None, None, None, None))
+    n, nnz, nc, pw = info.n, info.nnz, info.nc, info.pw
+    rp = np.empty(n + 1, np.int32)
+    ci = np.empty(max(nnz, 1), np.int32)
+    a = np.empty(max(nnz, 1), np.float64)
+    pc = np.empty((n, pw), np.int32) if nc else None
+    pv = np.empty((n, pw), np.float64) if nc else None
+    _check(lib().shapley_hierarchy_level(g, int(level), C.byref(info), _ptr(rp), _ptr(ci), _ptr(a), _ptr(pc),
+                                         _ptr(pv)))
+    return {"levels": info.levels, "n": n, "nnz": nnz, "nc": nc, "pw": pw, "rp": rp, "ci": ci[:nnz],
+            "a": a[:nnz], "pc": pc, "pv": pv}
 
 
 def shapley_game_bytes(g) -> int:
