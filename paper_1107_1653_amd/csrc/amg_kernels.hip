@@ -1808,6 +1808,37 @@ __device__ inline T row_dot(const int* __restrict__ ci, const T* __restrict__ a,
   return s;
 }
 
+// row_dot<T, T, G> with the vector entries produced by f(column): the same
+// products in the same order
+template <class T, int G, class F>
+__device__ inline T row_dot_fn(const int* __restrict__ ci, const T* __restrict__ a, F f, int e0, int e1, int gl) {
+  T acc[kRowUnroll];
+#pragma unroll
+  for (int u = 0; u < kRowUnroll; ++u) acc[u] = 0;
+  int e = e0 + gl;
+  for (; e + (kRowUnroll - 1) * G < e1; e += kRowUnroll * G) {
+    int c[kRowUnroll];
+    T v[kRowUnroll];
+#pragma unroll
+    for (int u = 0; u < kRowUnroll; ++u) {
+      c[u] = ci[e + u * G];
+      v[u] = a[e + u * G];
+    }
+#pragma unroll
+    for (int u = 0; u < kRowUnroll; ++u) acc[u] += v[u] * f(c[u]);
+  }
+  for (; e < e1; e += G) acc[0] += a[e] * f(ci[e]);
+  T s = acc[0];
+#pragma unroll
+  for (int u = 1; u < kRowUnroll; ++u) s += acc[u];
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  return s;
+}
+
+// first = 1: the first sweep from zero, x = omega D^-1 b; first = 2: the first
+// two sweeps from zero in one pass (the first sweep's values recomputed where
+// the second reads them, the same operations as the two passes)
 template <class T, int G>
 __global__ __launch_bounds__(256) void k_smooth(const Tile* __restrict__ tiles, const int* __restrict__ act,
                                                 const int* __restrict__ rp, const int* __restrict__ ci,
@@ -1819,11 +1850,19 @@ __global__ __launch_bounds__(256) void k_smooth(const Tile* __restrict__ tiles, 
   int gl;
   const int i = tile_row<G>(t, gl);
   const bool in = i < t.r1;
-  if (first) {
+  if (first == 1) {
     if (in && gl == 0) xout[i] = omega * dinv[i] * b[i];
     return;
   }
   const int e0 = in ? rp[i] : 0, e1 = in ? rp[i + 1] : 0;
+  if (first == 2) {
+    const T ax = row_dot_fn<T, G>(ci, a, [&](int j) -> T { return omega * dinv[j] * b[j]; }, e0, e1, gl);
+    if (in && gl == 0) {
+      const T x1 = omega * dinv[i] * b[i];
+      xout[i] = x1 + omega * dinv[i] * (b[i] - ax);
+    }
+    return;
+  }
   const T ax = row_dot<T, T, G>(ci, a, xin, e0, e1, gl);  // all lanes: the shuffles need them
   if (in && gl == 0) xout[i] = xin[i] + omega * dinv[i] * (b[i] - ax);
 }
@@ -2358,7 +2397,7 @@ template <class T>
 void cyc_smooth(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const T* a,
                 const T* dinv, const T* b, const T* xin, T* xout, T omega, int first, int g, hipStream_t s) {
   if (!nt) return;
-  SHP_GROUP_LAUNCH(k_smooth, first ? 1 : g, nt, s, t, act, rp, ci, a, dinv, b, xin, xout, omega, first);
+  SHP_GROUP_LAUNCH(k_smooth, first == 1 ? 1 : g, nt, s, t, act, rp, ci, a, dinv, b, xin, xout, omega, first);
   SHP_LAUNCH_CHECK();
 }
 template <class T>

@@ -838,10 +838,18 @@ static T* vcycle_impl(Engine* e, std::vector<Level>& lv, int l, const EngineOpts
   if (L.nvctiles) {
     const T* A = LV<T>::a(L);
     const T* D = LV<T>::d(L);
+    int k = 1;
     probe_begin(kProbeSmooth, s);
-    cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, D, b, nullptr, cur, om, 1, 1, s);
-    probe_end(kProbeSmooth, s, bytes_smooth<T>(L, true));
-    for (int k = 1; k < o.nu1; ++k) {
+    if (o.nu1 >= 2) {  // the first two sweeps in one pass
+      cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, D, b, nullptr, nxt, om, 2, L.gA, s);
+      probe_end(kProbeSmooth, s, bytes_smooth<T>(L, false) - (double)L.rows_vctiles * sizeof(T));
+      std::swap(cur, nxt);
+      k = 2;
+    } else {
+      cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, D, b, nullptr, cur, om, 1, 1, s);
+      probe_end(kProbeSmooth, s, bytes_smooth<T>(L, true));
+    }
+    for (; k < o.nu1; ++k) {
       probe_begin(kProbeSmooth, s);
       cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, D, b, cur, nxt, om, 0, L.gA, s);
       probe_end(kProbeSmooth, s, bytes_smooth<T>(L, false));
