@@ -684,7 +684,9 @@ void Engine::build_tail(bool mixed) {
       big[l] = std::max(big[l + 1], rows);
     }
     for (int l = 0; l <= last; ++l) {
-      if (big[l] <= kTailRows && cum[l] <= cap && last - l < kTailMaxLevels) {
+      // the tail start level's entries (estimated from the level's average row)
+      const double est_nnz = lv[l].n ? (double)lv[l].nnz * (lv[l].goff[g + 1] - lv[l].goff[g]) / lv[l].n : 0.0;
+      if (big[l] <= kTailRows && cum[l] <= cap && est_nnz <= kTailNnz && last - l < kTailMaxLevels) {
         h_lt[g] = l;
         lds_rows[l] = std::max(lds_rows[l], (int)cum[l]);
         break;

@@ -77,6 +77,7 @@ struct Game {
 // per kernel and level.
 // ---------------------------------------------------------------------------
 constexpr int kTailRows = 2048;
+constexpr int kTailNnz = 16384;  // entries of the tail's first level (one CU streams them per sweep)
 constexpr int kTailThreads = 1024;
 // the tail keeps two iterate vectors per level in LDS: a game's rows summed
 // over its tail levels are at most kTailLdsBytes / (2 * sizeof(T))
