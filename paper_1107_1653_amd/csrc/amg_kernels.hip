@@ -1654,6 +1654,9 @@ __global__ __launch_bounds__(256) void k_dense_inv(const int* __restrict__ blk, 
   }
 }
 
+// maximum over the lanes of a wavefront (ROCm device library)
+extern "C" __device__ unsigned long long __ockl_wfred_max_u64(unsigned long long);
+
 // In-place Gauss-Jordan inversion with partial pivoting for blocks of at
 // most NB <= kDenseWave unknowns: one thread per row of the block, the row in
 // registers.  Pivot rows are not swapped: step k takes the row p not yet used
@@ -1712,11 +1715,7 @@ __global__ __launch_bounds__(NT) void k_dense_inv_reg(const int* __restrict__ bl
       const double m = fabs(v[0]);
       if (m == m) key = ((unsigned long long)__double_as_longlong(m) & ~0xFFull) | (unsigned long long)(255 - i);
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const unsigned long long k2 = __shfl_xor(key, o);
-      key = k2 > key ? k2 : key;
-    }
+    key = __ockl_wfred_max_u64(key);
     if (NT > 64) {
       if (lane == 0) best[buf][w] = key;
       __syncthreads();
