@@ -82,7 +82,7 @@ def parse_args():
     ap.add_argument("--amgpi", action="store_true")
     ap.add_argument("--roofline-kernel", default="auto")
     ap.add_argument("--forcing", type=float, default=0.1)
-    ap.add_argument("--reuse", type=float, default=0.05)
+    ap.add_argument("--reuse", type=float, default=0.5)
     ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4"])
     ap.add_argument("--games", type=int, default=256, help="C3 batch size")
     ap.add_argument("--requests", type=int, default=100, help="C4 requests")
@@ -157,7 +157,7 @@ def run_c1(args) -> int:
 
     def opts(prec):
         # inexact policy iteration: each linear solve to 0.1 x the previous
-        # Shapley residual; AMG splitting reused while < 5% of policies change
+        # Shapley residual; AMG splitting reused while < 50% of policies change
         return P.shapley_default_opts(eps=1e-8, precision=prec, method=P.SHAPLEY_FAMGPI, alpha0=a0,
                                       beta0=a0, max_outer=5000, max_inner=5000, forcing=args.forcing,
                                       reuse_frac=args.reuse)

@@ -124,7 +124,7 @@ typedef struct shapley_stats {
 /* Fills *o with the defaults: eps 0, FP64, AMGpi, c_fmg 1e-2, no warm start,
  * max_outer 100000, max_inner 100000, max_cycles 200, lin_rtol 1e-14,
  * lin_atol 0, tie_rtol 1e-12, theta auto, nu1 = nu2 = 2, omega 0.8,
- * coarse_max 64, max_levels 25, verbose 0, stream NULL, reuse_frac 0.05,
+ * coarse_max 64, max_levels 25, verbose 0, stream NULL, reuse_frac 0.5,
  * forcing 0. */
 void shapley_default_opts(shapley_solve_opts* o);
 

@@ -279,7 +279,7 @@ void shapley_default_opts(shapley_solve_opts* o) {
   o->max_levels = 25;
   o->verbose = 0;
   o->stream = nullptr;
-  o->reuse_frac = 0.05;
+  o->reuse_frac = 0.5;
   o->forcing = 0.0;
 }
 

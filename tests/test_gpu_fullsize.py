@@ -31,7 +31,7 @@ from tests.gpu_helpers import compare_with_oracle, log
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-BENCH = dict(max_outer=5000, max_inner=5000, forcing=0.1, reuse_frac=0.05)
+BENCH = dict(max_outer=5000, max_inner=5000, forcing=0.1, reuse_frac=0.5)
 
 
 def load(name):
