@@ -96,7 +96,7 @@ def parse_args():
 def main() -> int:
     args = parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 (sharding across GPUs is not implemented)"}))
         return 2
     return {"c0": run_c0, "c1": run_c1, "c2": run_c2, "c3": run_c3, "c4": run_c4}[args.workload](args)
 

@@ -267,7 +267,7 @@ def policy_iteration(g, alpha0=None, beta0=None, v0=None, eps: float = 0.0,
 
 
 # ----------------------------------------------------------------------------
-# FAMGpi transfers and driver (Sec. 5.2, Algorithm algo-FAMGPI)
+# FAMGpi transfers and the coarse-to-fine loop (Sec. 5.2, Algorithm algo-FAMGPI)
 # ----------------------------------------------------------------------------
 
 def _axis_weights(s_c: int, s_f: int):
