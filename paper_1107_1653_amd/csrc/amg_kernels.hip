@@ -1843,7 +1843,8 @@ __global__ __launch_bounds__(256) void k_smooth(const Tile* __restrict__ tiles, 
                                                 const int* __restrict__ rp, const int* __restrict__ ci,
                                                 const T* __restrict__ a, const T* __restrict__ dinv,
                                                 const T* __restrict__ b, const T* __restrict__ xin,
-                                                T* __restrict__ xout, T omega, int first) {
+                                                T* __restrict__ xout, T omega, int first,
+                                                double* __restrict__ sol) {
   const Tile t = tiles[blockIdx.x / G];
   if (!act[t.game]) return;
   int gl;
@@ -1863,7 +1864,11 @@ __global__ __launch_bounds__(256) void k_smooth(const Tile* __restrict__ tiles, 
     return;
   }
   const T ax = row_dot<T, T, G>(ci, a, xin, e0, e1, gl);  // all lanes: the shuffles need them
-  if (in && gl == 0) xout[i] = xin[i] + omega * dinv[i] * (b[i] - ax);
+  if (in && gl == 0) {
+    const T xi = xin[i] + omega * dinv[i] * (b[i] - ax);
+    xout[i] = xi;
+    if (sol) sol[i] += (double)xi;  // level 0's last sweep: the FP64 update of the refinement
+  }
 }
 
 template <class T, int G>
@@ -1983,7 +1988,8 @@ template <class T>
 __global__ __launch_bounds__(kTailThreads) void k_tail(const int* __restrict__ games, int l0, int nlev, int G,
                                                        const TailLev<T>* __restrict__ lvs,
                                                        const TailGL* __restrict__ gls, const int* __restrict__ act,
-                                                       T omega, int nu1, int nu2, int out_y) {
+                                                       T omega, int nu1, int nu2, int out_y,
+                                                       double* __restrict__ sol) {
   extern __shared__ unsigned char tail_lds[];
   __shared__ int off[kTailMaxLevels];  // by level - l0
   T* lds = reinterpret_cast<T*>(tail_lds);
@@ -2100,7 +2106,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const int* __restrict__ g
   const int n = q.r1 - q.r0;
   const T* src = lds + off[0] + ((parity & 1u) ? n : 0);
   T* dst = out_y ? L.y : L.x;
-  for (int i = tid; i < n; i += kTailThreads) dst[q.r0 + i] = src[i];
+  for (int i = tid; i < n; i += kTailThreads) {
+    dst[q.r0 + i] = src[i];
+    if (sol) sol[q.r0 + i] += (double)src[i];  // level 0: the FP64 update of the refinement
+  }
 }
 
 // x_blk = inv_blk b_blk, one workgroup per block; inv is column-major
@@ -2125,13 +2134,9 @@ __global__ __launch_bounds__(256) void k_dense_solve(const int* __restrict__ blk
 // FP64 residual of the refinement: r = b - A x, its copy in the cycle type,
 // and per-game max |r|, max |x|.
 template <class T, int G>
-__global__ __launch_bounds__(256) void k_resid64(const Tile* __restrict__ tiles, const int* __restrict__ act,
-                                                 const int* __restrict__ rp, const int* __restrict__ ci,
-                                                 const double* __restrict__ a, const double* __restrict__ b,
-                                                 const double* __restrict__ x, T* __restrict__ rc,
-                                                 Stripes norm) {
-  const Tile t = tiles[blockIdx.x / G];
-  if (!act[t.game]) return;
+__device__ inline void resid64_block(const Tile& t, const int* __restrict__ rp, const int* __restrict__ ci,
+                                     const double* __restrict__ a, const double* __restrict__ b,
+                                     const double* __restrict__ x, T* __restrict__ rc, const Stripes& norm) {
   int gl;
   const int i = tile_row<G>(t, gl);
   const bool in = i < t.r1;
@@ -2151,6 +2156,19 @@ __global__ __launch_bounds__(256) void k_resid64(const Tile* __restrict__ tiles,
   }
   const double v[2] = {rm, xm};
   block_fold<2, 0>(norm, t.game, v, 0u, nullptr);
+}
+
+// FP64 residual r = b - A x (copied to rc in the cycle type) and per-game
+// maxima of |r| and |x| folded into the stripes
+template <class T, int G>
+__global__ __launch_bounds__(256) void k_resid64(const Tile* __restrict__ tiles, const int* __restrict__ act,
+                                                 const int* __restrict__ rp, const int* __restrict__ ci,
+                                                 const double* __restrict__ a, const double* __restrict__ b,
+                                                 const double* __restrict__ x, T* __restrict__ rc,
+                                                 Stripes norm) {
+  const Tile t = tiles[blockIdx.x / G];
+  if (!act[t.game]) return;
+  resid64_block<T, G>(t, rp, ci, a, b, x, rc, norm);
 }
 
 template <class T>
@@ -2394,9 +2412,10 @@ int row_group(double avg_len) { return avg_len <= 10.0 ? 1 : (avg_len <= 40.0 ? 
 
 template <class T>
 void cyc_smooth(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const T* a,
-                const T* dinv, const T* b, const T* xin, T* xout, T omega, int first, int g, hipStream_t s) {
+                const T* dinv, const T* b, const T* xin, T* xout, T omega, int first, int g, hipStream_t s,
+                double* sol) {
   if (!nt) return;
-  SHP_GROUP_LAUNCH(k_smooth, first == 1 ? 1 : g, nt, s, t, act, rp, ci, a, dinv, b, xin, xout, omega, first);
+  SHP_GROUP_LAUNCH(k_smooth, first == 1 ? 1 : g, nt, s, t, act, rp, ci, a, dinv, b, xin, xout, omega, first, sol);
   SHP_LAUNCH_CHECK();
 }
 template <class T>
@@ -2442,17 +2461,18 @@ void cyc_update64(const Tile* t, int nt, const int* act, const T* e, double* x, 
 
 template <class T>
 void cyc_tail(const int* games, int ngames, int l0, int nlev, int G, const TailLev<T>* lv, const TailGL* gl,
-              const int* act, T omega, int nu1, int nu2, int out_y, int lds_rows, hipStream_t s) {
+              const int* act, T omega, int nu1, int nu2, int out_y, int lds_rows, hipStream_t s,
+              double* sol) {
   if (ngames <= 0) return;
   const size_t lds = 2 * sizeof(T) * (size_t)std::max(lds_rows, 1);
   hipLaunchKernelGGL(k_tail<T>, dim3(ngames), dim3(kTailThreads), lds, s, games, l0, nlev, G, lv, gl, act, omega,
-                     nu1, nu2, out_y);
+                     nu1, nu2, out_y, sol);
   SHP_LAUNCH_CHECK();
 }
 
 #define SHP_INST(T)                                                                                  \
   template void cyc_smooth<T>(const Tile*, int, const int*, const int*, const int*, const T*, const T*, \
-                              const T*, const T*, T*, T, int, int, hipStream_t);                     \
+                              const T*, const T*, T*, T, int, int, hipStream_t, double*);            \
   template void cyc_resid<T>(const Tile*, int, const int*, const int*, const int*, const T*, const T*,  \
                              const T*, T*, int, hipStream_t);                                        \
   template void cyc_restrict<T>(const Tile*, int, const int*, const int*, const int*, const T*,        \
@@ -2464,7 +2484,7 @@ void cyc_tail(const int* games, int ngames, int l0, int nlev, int G, const TailL
                                const double*, const double*, T*, Stripes, int, hipStream_t);         \
   template void cyc_update64<T>(const Tile*, int, const int*, const T*, double*, hipStream_t);          \
   template void cyc_tail<T>(const int*, int, int, int, int, const TailLev<T>*, const TailGL*, const int*, T, int, \
-                            int, int, int, hipStream_t);
+                            int, int, int, hipStream_t, double*);
 SHP_INST(float)
 SHP_INST(double)
 #undef SHP_INST

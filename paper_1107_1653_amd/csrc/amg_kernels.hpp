@@ -81,13 +81,15 @@ void amg_mark_coarse(const Tile* t, int nt, const int* pc, const uint8_t* chg, u
 // levels of a game's rows (two LDS vectors per level)
 template <class T>
 void cyc_tail(const int* games, int ngames, int l0, int nlev, int G, const TailLev<T>* lv, const TailGL* gl,
-              const int* act, T omega, int nu1, int nu2, int out_y, int lds_rows, hipStream_t s);
+              const int* act, T omega, int nu1, int nu2, int out_y, int lds_rows, hipStream_t s,
+              double* sol = nullptr);  // sol: also sol += result on level l0 (FP64)
 
 // lanes per sparse row (1, 4 or 16) for a level with this average row length
 int row_group(double avg_len);
 template <class T>
 void cyc_smooth(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const T* a,
-                const T* dinv, const T* b, const T* xin, T* xout, T omega, int first, int g, hipStream_t s);
+                const T* dinv, const T* b, const T* xin, T* xout, T omega, int first, int g, hipStream_t s,
+                double* sol = nullptr);  // sol: also sol += xout (FP64), sweeps with first == 0
 template <class T>
 void cyc_resid(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const T* a, const T* b,
                const T* x, T* r, int g, hipStream_t s);

@@ -831,7 +831,7 @@ static T* vcycle_level(Engine* e, std::vector<Level>& lv, int l, const EngineOpt
 // deeper.  Returns the buffer (x or y) holding the level's result.
 template <class T>
 static T* vcycle_impl(Engine* e, std::vector<Level>& lv, int l, const EngineOpts& o, const int* act,
-                      hipStream_t s) {
+                      hipStream_t s, double* sol) {
   Level& L = lv[l];
   T* cur = LV<T>::x(L);
   T* nxt = LV<T>::y(L);
@@ -866,14 +866,15 @@ static T* vcycle_impl(Engine* e, std::vector<Level>& lv, int l, const EngineOpts
     cyc_restrict<T>(Ln.rtiles.p, Ln.nrtiles, act, L.rrp.p, L.rci.p, LV<T>::rv(L), r, LV<T>::b(Ln), L.gR, s);
     probe_end(kProbeRestrict, s,
               (double)Ln.rows_rtiles * (4 + sizeof(T)) + (double)L.rows_vctiles * (4 + 2 * sizeof(T)));
-    T* xc = vcycle_level<T>(e, lv, l + 1, o, act, s);
+    T* xc = vcycle_level<T>(e, lv, l + 1, o, act, s, nullptr);
     probe_begin(kProbeProlong, s);
     cyc_prolong<T>(L.vctiles.p, L.nvctiles, act, L.pc.p, LV<T>::pv(L), xc, cur, s);
     probe_end(kProbeProlong, s,
               (double)L.rows_vctiles * (PW * (4 + sizeof(T)) + 2 * sizeof(T)) + (double)Ln.rows_rtiles * sizeof(T));
     for (int k = 0; k < o.nu2; ++k) {
       probe_begin(kProbeSmooth, s);
-      cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, D, b, cur, nxt, om, 0, L.gA, s);
+      cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, D, b, cur, nxt, om, 0, L.gA, s,
+                    k + 1 == o.nu2 ? sol : nullptr);
       probe_end(kProbeSmooth, s, bytes_smooth<T>(L, false));
       std::swap(cur, nxt);
     }
@@ -886,9 +887,9 @@ static T* vcycle_impl(Engine* e, std::vector<Level>& lv, int l, const EngineOpts
 // whose tail starts here, writing into the same buffer.
 template <class T>
 static T* vcycle_level(Engine* e, std::vector<Level>& lv, int l, const EngineOpts& o, const int* act,
-                       hipStream_t s) {
+                       hipStream_t s, double* sol) {
   Level& L = lv[l];
-  T* res = L.upper ? vcycle_impl<T>(e, lv, l, o, act, s) : LV<T>::x(L);
+  T* res = L.upper ? vcycle_impl<T>(e, lv, l, o, act, s, sol) : LV<T>::x(L);
   if (L.ntailg) {
     double bytes = 0.0;
     if (probe_on(kProbeTail))
@@ -903,7 +904,8 @@ static T* vcycle_level(Engine* e, std::vector<Level>& lv, int l, const EngineOpt
       }
     probe_begin(kProbeTail, s);
     cyc_tail<T>(L.tailg.p, L.ntailg, l, e->num_levels(), e->num_slots(), e->tail_levels((T*)nullptr),
-                e->tail_games(), act, (T)o.omega, o.nu1, o.nu2, res == LV<T>::y(L) ? 1 : 0, L.tail_lds_rows, s);
+                e->tail_games(), act, (T)o.omega, o.nu1, o.nu2, res == LV<T>::y(L) ? 1 : 0, L.tail_lds_rows, s,
+                sol);
     probe_end(kProbeTail, s, bytes);
   }
   return res;
@@ -948,16 +950,21 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
     }
     launch_lin_check(fold, G, d_bnorm.p, d_lin.p, d_lin_active, d_norm.p, stream);
   };
+  // every level-0 row ends its cycle in a post-smoothing sweep or in a tail
+  const bool fuse_update = o.nu2 >= 1 && L0.nvblk == 0;
   resid_check();
   int chunk = std::max(1, std::min(last_cycles, 16));
   while (true) {
     for (int c = 0; c < chunk; ++c) {
+      // the last post-smoothing sweep of level 0 (or the tail that ends on
+      // it) adds the correction to the FP64 iterate; otherwise a separate pass
+      double* fused = fuse_update ? sol.p : nullptr;
       if (mixed) {
-        float* e = vcycle_level<float>(this, lv, 0, o, d_lin_active, stream);
-        cyc_update64<float>(L0.tiles.p, L0.ntiles, d_lin_active, e, sol.p, stream);
+        float* e = vcycle_level<float>(this, lv, 0, o, d_lin_active, stream, fused);
+        if (!fused) cyc_update64<float>(L0.tiles.p, L0.ntiles, d_lin_active, e, sol.p, stream);
       } else {
-        double* e = vcycle_level<double>(this, lv, 0, o, d_lin_active, stream);
-        cyc_update64<double>(L0.tiles.p, L0.ntiles, d_lin_active, e, sol.p, stream);
+        double* e = vcycle_level<double>(this, lv, 0, o, d_lin_active, stream, fused);
+        if (!fused) cyc_update64<double>(L0.tiles.p, L0.ntiles, d_lin_active, e, sol.p, stream);
       }
       resid_check();
     }

@@ -327,46 +327,7 @@ __global__ void k_fold_finish(Stripes st, int G, int nd, unsigned sum_mask, int 
 __global__ void k_lin_check(Stripes st, int G, const double* __restrict__ bnorm, LinCtl* __restrict__ ctl,
                             int* __restrict__ act, double* __restrict__ norm) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= G) return;
-  double rn = 0.0, xn = 0.0;
-#pragma unroll 16
-  for (int k = 0; k < kStripes; ++k) {
-    double* a0 = st.d + stripe_at(st, k, g, 0);
-    double* a1 = st.d + stripe_at(st, k, g, 1);
-    rn = fmax(rn, *a0);
-    xn = fmax(xn, *a1);
-    *a0 = 0.0;
-    *a1 = 0.0;
-  }
-  norm[4 * g] = rn;
-  norm[4 * g + 1] = xn;
-  if (!act[g]) return;
-  LinCtl c = ctl[g];
-  double tol = fmax(c.rtol * fmax(bnorm[g], xn), c.atol);
-  int flags = c.flags & ~1;
-  if (c.forcing > 0.0 && isfinite(c.res_prev) && c.res_prev > 0.0 && c.forcing * c.res_prev > tol) {
-    tol = c.forcing * c.res_prev;
-    flags |= 1;
-  }
-  const int n = c.nh;
-  c.hist[n & 7] = rn;
-  c.nh = n + 1;
-  bool stop = false;
-  if (!isfinite(rn)) {
-    stop = true;
-    flags |= 4;
-  } else if (rn <= tol) {
-    stop = true;
-  } else if (c.cyc >= c.max_cycles) {
-    stop = true;
-    flags |= 8;
-  } else if (n + 1 >= 8 && rn > 0.5 * c.hist[(n - 6) & 7]) {
-    stop = true;  // no halving over six cycles
-    flags |= 2;
-  }
-  if (stop) act[g] = 0; else c.cyc += 1;
-  c.flags = flags;
-  ctl[g] = c;
+  if (g < G) lin_check_game(st, g, bnorm, ctl, act, norm);
 }
 
 void launch_lin_check(Stripes st, int G, const double* bnorm, LinCtl* ctl, int* lin_active, double* norm,

@@ -216,6 +216,53 @@ struct LinCtl {
   int max_cycles, cyc, nh, flags;
 };
 
+// The stop test of game g after an FP64 residual: folds the residual and
+// iterate maxima out of the stripes (and clears them), records them in
+// norm[4g], norm[4g+1], and for an active game decides whether its solve
+// stops (act[g] = 0) or takes another cycle.
+__device__ inline void lin_check_game(const Stripes& st, int g, const double* __restrict__ bnorm,
+                                      LinCtl* __restrict__ ctl, int* __restrict__ act, double* __restrict__ norm) {
+  double rn = 0.0, xn = 0.0;
+#pragma unroll 16
+  for (int k = 0; k < kStripes; ++k) {
+    double* a0 = st.d + stripe_at(st, k, g, 0);
+    double* a1 = st.d + stripe_at(st, k, g, 1);
+    rn = fmax(rn, *a0);
+    xn = fmax(xn, *a1);
+    *a0 = 0.0;
+    *a1 = 0.0;
+  }
+  norm[4 * g] = rn;
+  norm[4 * g + 1] = xn;
+  if (!act[g]) return;
+  LinCtl c = ctl[g];
+  double tol = fmax(c.rtol * fmax(bnorm[g], xn), c.atol);
+  int flags = c.flags & ~1;
+  if (c.forcing > 0.0 && isfinite(c.res_prev) && c.res_prev > 0.0 && c.forcing * c.res_prev > tol) {
+    tol = c.forcing * c.res_prev;
+    flags |= 1;
+  }
+  const int n = c.nh;
+  c.hist[n & 7] = rn;
+  c.nh = n + 1;
+  bool stop = false;
+  if (!isfinite(rn)) {
+    stop = true;
+    flags |= 4;
+  } else if (rn <= tol) {
+    stop = true;
+  } else if (c.cyc >= c.max_cycles) {
+    stop = true;
+    flags |= 8;
+  } else if (n + 1 >= 8 && rn > 0.5 * c.hist[(n - 6) & 7]) {
+    stop = true;  // no halving over six cycles
+    flags |= 2;
+  }
+  if (stop) act[g] = 0; else c.cyc += 1;
+  c.flags = flags;
+  ctl[g] = c;
+}
+
 // Lock-step policy-iteration engine over a set of games (one slot per game).
 class Engine {
  public:
