@@ -102,7 +102,10 @@ __global__ void k_pmis_select(const Tile* __restrict__ tiles, const int* __restr
                               int* __restrict__ newc, int* __restrict__ left, int round) {
   // the following update kernel counts the undecided rows into left[round & 1];
   // once a round has left none undecided, later rounds do nothing
-  if (blockIdx.x == 0 && threadIdx.x == 0) left[round & 1] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    left[round & 1] = 0;
+    if (round > 0 && left[(round - 1) & 1] == 0) atomicMin(&left[2], round);  // first round with nothing to do
+  }
   if (round > 0 && left[(round - 1) & 1] == 0) return;
   Tile t = tiles[blockIdx.x];
   int i = t.r0 + threadIdx.x;

@@ -22,8 +22,9 @@ void amg_pmis_select(const Tile* t, int nt, const int* rp, const int* ci, const 
                      int* newc, int* left, int round, hipStream_t s);
 void amg_pmis_update(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
                      int8_t* cf, const int* newc, int* left, int round, hipStream_t s);
-// PMIS round `round` (0, 1, ...): left[2] holds the undecided counts of the
+// PMIS round `round` (0, 1, ...): left[0..1] hold the undecided counts of the
 // last two rounds; a round after one that left nothing undecided does nothing
+// and lowers left[2] (set to a large value before round 0) to its number
 void amg_fill_cf(const Tile* t, int nt, int8_t* cf, int8_t val, hipStream_t s);
 void amg_is_c(const int8_t* cf, int* out, int n, hipStream_t s);
 void amg_gather_int(const int* src, const int* idx, int m, int* dst, hipStream_t s);

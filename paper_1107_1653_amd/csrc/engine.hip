@@ -12,6 +12,8 @@
 #include "probe.hpp"
 
 #include <algorithm>
+#include <array>
+#include <climits>
 #include <exception>
 #include <map>
 #include <mutex>
@@ -345,7 +347,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
     theta = dim >= 3 ? 0.5 : 0.25;
   }
   s_err.ensure(4);
-  s_left.ensure(2);
+  s_left.ensure(3);
   fill_async(s_err.p, 0, 4, stream);
   PhaseTimer pt(this, prof);
   nlev = 0;
@@ -424,7 +426,10 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
                           stream);
         }
       };
-      pmis_rounds(6);
+      // as many rounds as this level needed last time, plus one
+      if ((int)pmis_need.size() <= l) pmis_need.resize(l + 1, 5);
+      fill_async(s_left.p + 2, INT_MAX, 1, stream);
+      pmis_rounds(std::max(2, std::min(pmis_need[l] + 1, 12)));
       pt.mark("pmis");
       // ---- coarse numbering and per-game coarse sizes
       auto number = [&](std::vector<int>& ncg) {
@@ -436,13 +441,15 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
           amg_gather_int(L.cidx.p, s_goff.p, G + 1, s_gout.p, stream);
           std::vector<int> cpre(G + 1);
           const int* cp = down(s_gout.p, G + 1);
-          const int* left = down(s_left.p + ((round - 1) & 1), 1);
+          const int* left = down(s_left.p, 3);
           sync();
-          if (*left != 0) {  // PMIS not finished: more rounds, then number again
+          if (left[(round - 1) & 1] != 0) {  // PMIS not finished: more rounds, then number again
             if (round >= 1000) throw Error(SHAPLEY_EDEVICE, "PMIS did not terminate");
             pmis_rounds(4);
             continue;
           }
+          // rounds that did work: up to the first idle one, or all of them
+          pmis_need[l] = left[2] < round ? left[2] : round;
           cpre.assign(cp, cp + G + 1);
           ncg.assign(G, 0);
           for (int g = 0; g < G; ++g) ncg[g] = cpre[g + 1] - cpre[g];
@@ -693,6 +700,17 @@ void Engine::build_tail(bool mixed) {
       }
     }
   }
+  // host image of the tables, each at a 256-byte aligned offset
+  std::vector<char>& hpack = h_tailpack;
+  hpack.clear();
+  auto pack = [&](const auto* data, size_t n) -> size_t {
+    const size_t o = (hpack.size() + 255) & ~(size_t)255;
+    const size_t bytes = sizeof(*data) * n;
+    hpack.resize(o + std::max<size_t>(bytes, 1), 0);
+    if (bytes) std::memcpy(hpack.data() + o, data, bytes);
+    return o;
+  };
+  std::vector<std::array<size_t, 4>> off(std::max(nlev, 1));
   std::vector<TailGL> gl((size_t)std::max(nlev, 1) * std::max(G, 1), TailGL{0, 0, 0, 0});
   std::vector<TailLev<double>> t64(std::max(nlev, 1));
   std::vector<TailLev<float>> t32(std::max(nlev, 1));
@@ -720,23 +738,21 @@ void Engine::build_tail(bool mixed) {
     }
     for (size_t k = 0; k + 3 < L.h_blk.size(); k += 4)
       if (h_lt[L.h_blk[k + 3]] > l) L.h_vblk.insert(L.h_vblk.end(), L.h_blk.begin() + k, L.h_blk.begin() + k + 4);
-    auto upload = [&](std::vector<Tile>& h, DBuf<Tile>& d, int& nt, int& rows, const std::vector<char>& keep) {
+    auto tiles_of = [&](std::vector<Tile>& h, int& nt, int& rows, const std::vector<char>& keep) {
       h = make_tiles(L.goff, keep, kTileRows);
       nt = (int)h.size();
       rows = 0;
       for (const Tile& x : h) rows += x.r1 - x.r0;
-      d.ensure(std::max<size_t>(h.size(), 1));
-      up(d.p, h.data(), h.size());
     };
-    upload(L.h_vctiles, L.vctiles, L.nvctiles, L.rows_vctiles, keepv);
-    upload(L.h_rtiles, L.rtiles, L.nrtiles, L.rows_rtiles, keepr);
+    tiles_of(L.h_vctiles, L.nvctiles, L.rows_vctiles, keepv);
+    tiles_of(L.h_rtiles, L.nrtiles, L.rows_rtiles, keepr);
+    off[l][0] = pack(L.h_vctiles.data(), L.h_vctiles.size());
+    off[l][1] = pack(L.h_rtiles.data(), L.h_rtiles.size());
+    off[l][2] = pack(L.h_vblk.data(), L.h_vblk.size());
+    off[l][3] = pack(L.h_tailg.data(), L.h_tailg.size());
     L.nvblk = (int)L.h_vblk.size() / 4;
-    L.vblk.ensure(std::max<size_t>(L.h_vblk.size(), 1));
-    up(L.vblk.p, L.h_vblk.data(), L.h_vblk.size());
     L.ntailg = (int)L.h_tailg.size();
     L.tail_lds_rows = lds_rows[l];
-    L.tailg.ensure(std::max<size_t>(L.h_tailg.size(), 1));
-    up(L.tailg.p, L.h_tailg.data(), L.h_tailg.size());
     L.upper = L.nvctiles > 0 || L.nvblk > 0;
     if (mixed)
       t32[l] = TailLev<float>{L.rp.p, L.ci.p, L.a32.p, L.dinv32.p, L.x32.p, L.y32.p, L.b32.p, L.r32.p,
@@ -745,15 +761,22 @@ void Engine::build_tail(bool mixed) {
       t64[l] = TailLev<double>{L.rp.p, L.ci.p, L.a64.p, L.dinv64.p, L.x64.p, L.y64.p, L.b64.p, L.r64.p,
                                L.rrp.p, L.rci.p, L.rv64.p, L.pc.p, L.pv64.p, L.dmat64.p};
   }
-  d_tailgl.ensure(gl.size());
-  up(d_tailgl.p, gl.data(), gl.size());
-  if (mixed) {
-    d_tail32.ensure(t32.size());
-    up(d_tail32.p, t32.data(), t32.size());
-  } else {
-    d_tail64.ensure(t64.size());
-    up(d_tail64.p, t64.data(), t64.size());
+  const size_t o_gl = pack(gl.data(), gl.size());
+  const size_t o_t = mixed ? pack(t32.data(), t32.size()) : pack(t64.data(), t64.size());
+  // one upload of all tables
+  d_tailpack.ensure(std::max<size_t>(hpack.size(), 1));
+  up(d_tailpack.p, hpack.data(), hpack.size());
+  char* base = d_tailpack.p;
+  for (int l = 0; l < nlev; ++l) {
+    Level& L = lv[l];
+    L.vctiles.p = reinterpret_cast<Tile*>(base + off[l][0]);
+    L.rtiles.p = reinterpret_cast<Tile*>(base + off[l][1]);
+    L.vblk.p = reinterpret_cast<int*>(base + off[l][2]);
+    L.tailg.p = reinterpret_cast<int*>(base + off[l][3]);
   }
+  d_tailgl.p = reinterpret_cast<TailGL*>(base + o_gl);
+  d_tail32.p = mixed ? reinterpret_cast<TailLev<float>*>(base + o_t) : nullptr;
+  d_tail64.p = mixed ? nullptr : reinterpret_cast<TailLev<double>*>(base + o_t);
 }
 
 // Numeric refresh of the last hierarchy: the C/F splitting, P and R = P^T

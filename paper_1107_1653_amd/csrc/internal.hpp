@@ -69,6 +69,12 @@ struct Game {
   ~Game();
 };
 
+// A device pointer into a buffer owned elsewhere.
+template <class T>
+struct DPtr {
+  T* p = nullptr;
+};
+
 // One merged (block-diagonal over games) AMG level.
 // ---------------------------------------------------------------------------
 // V-cycle tail: once a game's rows on a level are few (kTailRows), the rest of
@@ -126,10 +132,10 @@ struct Level {
   // split for the V-cycle tail: rows handled level by level (games whose tail
   // starts deeper), rows receiving their restriction that way, and the games
   // whose tail starts on this level
-  DBuf<Tile> vctiles, rtiles;
+  DPtr<Tile> vctiles, rtiles;     // inside the engine's packed tail tables
   int nvctiles = 0, nrtiles = 0, rows_vctiles = 0, rows_rtiles = 0;
   std::vector<Tile> h_vctiles, h_rtiles;
-  DBuf<int> vblk, tailg;
+  DPtr<int> vblk, tailg;
   int nvblk = 0, ntailg = 0;
   int tail_lds_rows = 0;  // largest sum of rows over the tail levels of a game whose tail starts here
   std::vector<int> h_vblk, h_tailg;
@@ -303,6 +309,7 @@ class Engine {
   void reset();
   // Evaluates the improvement sweep at the slots' current v (no decisions).
   void improve_only();
+  std::vector<int> pmis_need;        // PMIS rounds each level needed at its last setup
   const Game* hier_game = nullptr;  // the game of a one-game hierarchy (inspection)
   // Copies level l of a one-game hierarchy to the host (synchronous): sizes,
   // A_l (CSR) and, when a coarser level exists, P_l (PW slots per row).
@@ -331,9 +338,11 @@ class Engine {
   int* d_cnt = nullptr;                       // [2*G] inner/outer change counts (inside d_shap)
   DBuf<int> d_decision;
   // V-cycle tail tables (built at setup)
-  DBuf<TailGL> d_tailgl;
-  DBuf<TailLev<double>> d_tail64;
-  DBuf<TailLev<float>> d_tail32;
+  DBuf<char> d_tailpack;          // all tables built by build_tail, one upload
+  std::vector<char> h_tailpack;
+  DPtr<TailGL> d_tailgl;
+  DPtr<TailLev<double>> d_tail64;
+  DPtr<TailLev<float>> d_tail32;
   std::vector<int> h_lt;  // first tail level of each game (nlev: none)
   void build_tail(bool mixed);
   DBuf<LinCtl> d_lin;                         // [G] controls, then the active flags
