@@ -1992,7 +1992,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const int* __restrict__ g
                                                        const TailLev<T>* __restrict__ lvs,
                                                        const TailGL* __restrict__ gls, const int* __restrict__ act,
                                                        T omega, int nu1, int nu2, int out_y,
-                                                       double* __restrict__ sol) {
+                                                       double* __restrict__ sol, TailRefine rf) {
   extern __shared__ unsigned char tail_lds[];
   __shared__ int off[kTailMaxLevels];  // by level - l0
   T* lds = reinterpret_cast<T*>(tail_lds);
@@ -2009,109 +2009,147 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const int* __restrict__ g
     }
   }
   __syncthreads();
-  unsigned parity = 0;  // bit l - l0: the level-l iterate is in y
-  int deep = l0;
-  // ---- down
-  for (int l = l0; l < nlev; ++l) {
-    const TailGL q = gls[(size_t)l * G + g];
-    const TailLev<T> L = lvs[l];
-    const int r0 = q.r0, n = q.r1 - q.r0;
-    T* xv = lds + off[l - l0];
-    T* yv = xv + n;
-    deep = l;
-    if (q.flags & kTailDense) {  // x = inv b: one wavefront per row, lanes over columns
-      const int lane = tid & 63;
-      for (int i = tid >> 6; i < n; i += kTailThreads / 64) {
-        T acc = 0;
-        for (int j = lane; j < n; j += 64) acc += L.dm[(size_t)q.doff + (size_t)j * n + i] * L.b[r0 + j];
+  __shared__ double s_rm[kTailThreads / 64], s_xm[kTailThreads / 64];
+  __shared__ int s_go;
+  const int ncyc = rf.cycles > 0 ? rf.cycles : 1;
+  for (int cyc = 0; cyc < ncyc; ++cyc) {
+    unsigned parity = 0;  // bit l - l0: the level-l iterate is in y
+    int deep = l0;
+    // ---- down
+    for (int l = l0; l < nlev; ++l) {
+      const TailGL q = gls[(size_t)l * G + g];
+      const TailLev<T> L = lvs[l];
+      const int r0 = q.r0, n = q.r1 - q.r0;
+      T* xv = lds + off[l - l0];
+      T* yv = xv + n;
+      deep = l;
+      if (q.flags & kTailDense) {  // x = inv b: one wavefront per row, lanes over columns
+        const int lane = tid & 63;
+        for (int i = tid >> 6; i < n; i += kTailThreads / 64) {
+          T acc = 0;
+          for (int j = lane; j < n; j += 64) acc += L.dm[(size_t)q.doff + (size_t)j * n + i] * L.b[r0 + j];
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-        if (lane == 0) xv[i] = acc;
-      }
-      __syncthreads();
-      break;
-    }
-    if (!(q.flags & kTailCont)) break;
-    T* cur = xv;
-    T* nxt = yv;
-    for (int i = tid; i < n; i += kTailThreads) cur[i] = omega * L.d[r0 + i] * L.b[r0 + i];
-    __syncthreads();
-    for (int k = 1; k < nu1; ++k) {
-      const T* c0 = cur;
-      for (int i = tid; i < n; i += kTailThreads) {
-        const int r = r0 + i;
-        nxt[i] = cur[i] + omega * L.d[r] *
-                              (L.b[r] - row_dot1_f<T>(L.ci, L.a, [&](int j) -> T { return c0[j - r0]; }, L.rp[r],
-                                                      L.rp[r + 1]));
-      }
-      __syncthreads();
-      T* t = cur; cur = nxt; nxt = t;
-    }
-    if (cur == yv) parity |= 1u << (l - l0);
-    if (!(q.flags & kTailNext)) break;  // no coarse rows: smoothing only
-    T* rr = nxt;                         // the free vector holds the residual
-    {
-      const T* c0 = cur;
-      for (int i = tid; i < n; i += kTailThreads) {
-        const int r = r0 + i;
-        rr[i] = L.b[r] - row_dot1_f<T>(L.ci, L.a, [&](int j) -> T { return c0[j - r0]; }, L.rp[r], L.rp[r + 1]);
-      }
-    }
-    __syncthreads();
-    const TailGL qn = gls[(size_t)(l + 1) * G + g];
-    const TailLev<T> Ln = lvs[l + 1];
-    for (int I = qn.r0 + tid; I < qn.r1; I += kTailThreads)
-      Ln.b[I] = row_dot1_f<T>(L.rci, L.rv, [&](int i) -> T { return rr[i - r0]; }, L.rrp[I], L.rrp[I + 1]);
-    __syncthreads();
-  }
-  // ---- up
-  for (int l = deep; l >= l0; --l) {
-    const TailGL q = gls[(size_t)l * G + g];
-    if (!(q.flags & kTailCont) || (q.flags & kTailDense)) continue;  // the dense result is in x
-    const TailLev<T> L = lvs[l];
-    const int r0 = q.r0, n = q.r1 - q.r0;
-    T* xv = lds + off[l - l0];
-    T* yv = xv + n;
-    T* cur = ((parity >> (l - l0)) & 1u) ? yv : xv;
-    T* nxt = ((parity >> (l - l0)) & 1u) ? xv : yv;
-    if (l < deep) {
-      const TailGL qn = gls[(size_t)(l + 1) * G + g];
-      const int n1 = qn.r1 - qn.r0;
-      const T* xc = lds + off[l + 1 - l0] + (((parity >> (l + 1 - l0)) & 1u) ? n1 : 0);
-      for (int i = tid; i < n; i += kTailThreads) {
-        const int r = r0 + i;
-        T acc = cur[i];
-#pragma unroll
-        for (int k = 0; k < PW; ++k) {
-          const int c = L.pc[(size_t)r * PW + k];
-          if (c >= 0) acc += L.pv[(size_t)r * PW + k] * xc[c - qn.r0];
+          for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+          if (lane == 0) xv[i] = acc;
         }
-        cur[i] = acc;
+        __syncthreads();
+        break;
+      }
+      if (!(q.flags & kTailCont)) break;
+      T* cur = xv;
+      T* nxt = yv;
+      for (int i = tid; i < n; i += kTailThreads) cur[i] = omega * L.d[r0 + i] * L.b[r0 + i];
+      __syncthreads();
+      for (int k = 1; k < nu1; ++k) {
+        const T* c0 = cur;
+        for (int i = tid; i < n; i += kTailThreads) {
+          const int r = r0 + i;
+          nxt[i] = cur[i] + omega * L.d[r] *
+                                (L.b[r] - row_dot1_f<T>(L.ci, L.a, [&](int j) -> T { return c0[j - r0]; }, L.rp[r],
+                                                        L.rp[r + 1]));
+        }
+        __syncthreads();
+        T* t = cur; cur = nxt; nxt = t;
+      }
+      if (cur == yv) parity |= 1u << (l - l0);
+      if (!(q.flags & kTailNext)) break;  // no coarse rows: smoothing only
+      T* rr = nxt;                         // the free vector holds the residual
+      {
+        const T* c0 = cur;
+        for (int i = tid; i < n; i += kTailThreads) {
+          const int r = r0 + i;
+          rr[i] = L.b[r] - row_dot1_f<T>(L.ci, L.a, [&](int j) -> T { return c0[j - r0]; }, L.rp[r], L.rp[r + 1]);
+        }
       }
       __syncthreads();
-    }
-    for (int k = 0; k < nu2; ++k) {
-      const T* c0 = cur;
-      for (int i = tid; i < n; i += kTailThreads) {
-        const int r = r0 + i;
-        nxt[i] = cur[i] + omega * L.d[r] *
-                              (L.b[r] - row_dot1_f<T>(L.ci, L.a, [&](int j) -> T { return c0[j - r0]; }, L.rp[r],
-                                                      L.rp[r + 1]));
-      }
+      const TailGL qn = gls[(size_t)(l + 1) * G + g];
+      const TailLev<T> Ln = lvs[l + 1];
+      for (int I = qn.r0 + tid; I < qn.r1; I += kTailThreads)
+        Ln.b[I] = row_dot1_f<T>(L.rci, L.rv, [&](int i) -> T { return rr[i - r0]; }, L.rrp[I], L.rrp[I + 1]);
       __syncthreads();
-      T* t = cur; cur = nxt; nxt = t;
     }
-    if (cur == yv) parity |= 1u << (l - l0); else parity &= ~(1u << (l - l0));
-  }
-  // ---- the level-l0 result where the caller expects it
-  const TailGL q = gls[(size_t)l0 * G + g];
-  const TailLev<T> L = lvs[l0];
-  const int n = q.r1 - q.r0;
-  const T* src = lds + off[0] + ((parity & 1u) ? n : 0);
-  T* dst = out_y ? L.y : L.x;
-  for (int i = tid; i < n; i += kTailThreads) {
-    dst[q.r0 + i] = src[i];
-    if (sol) sol[q.r0 + i] += (double)src[i];  // level 0: the FP64 update of the refinement
+    // ---- up
+    for (int l = deep; l >= l0; --l) {
+      const TailGL q = gls[(size_t)l * G + g];
+      if (!(q.flags & kTailCont) || (q.flags & kTailDense)) continue;  // the dense result is in x
+      const TailLev<T> L = lvs[l];
+      const int r0 = q.r0, n = q.r1 - q.r0;
+      T* xv = lds + off[l - l0];
+      T* yv = xv + n;
+      T* cur = ((parity >> (l - l0)) & 1u) ? yv : xv;
+      T* nxt = ((parity >> (l - l0)) & 1u) ? xv : yv;
+      if (l < deep) {
+        const TailGL qn = gls[(size_t)(l + 1) * G + g];
+        const int n1 = qn.r1 - qn.r0;
+        const T* xc = lds + off[l + 1 - l0] + (((parity >> (l + 1 - l0)) & 1u) ? n1 : 0);
+        for (int i = tid; i < n; i += kTailThreads) {
+          const int r = r0 + i;
+          T acc = cur[i];
+#pragma unroll
+          for (int k = 0; k < PW; ++k) {
+            const int c = L.pc[(size_t)r * PW + k];
+            if (c >= 0) acc += L.pv[(size_t)r * PW + k] * xc[c - qn.r0];
+          }
+          cur[i] = acc;
+        }
+        __syncthreads();
+      }
+      for (int k = 0; k < nu2; ++k) {
+        const T* c0 = cur;
+        for (int i = tid; i < n; i += kTailThreads) {
+          const int r = r0 + i;
+          nxt[i] = cur[i] + omega * L.d[r] *
+                                (L.b[r] - row_dot1_f<T>(L.ci, L.a, [&](int j) -> T { return c0[j - r0]; }, L.rp[r],
+                                                        L.rp[r + 1]));
+        }
+        __syncthreads();
+        T* t = cur; cur = nxt; nxt = t;
+      }
+      if (cur == yv) parity |= 1u << (l - l0); else parity &= ~(1u << (l - l0));
+    }
+    // ---- the level-l0 result where the caller expects it
+    const TailGL q = gls[(size_t)l0 * G + g];
+    const TailLev<T> L = lvs[l0];
+    const int n = q.r1 - q.r0;
+    const T* src = lds + off[0] + ((parity & 1u) ? n : 0);
+    T* dst = out_y ? L.y : L.x;
+    for (int i = tid; i < n; i += kTailThreads) {
+      dst[q.r0 + i] = src[i];
+      if (sol) sol[q.r0 + i] += (double)src[i];  // level 0: the FP64 update of the refinement
+    }
+    if (rf.cycles == 0) break;
+    // ---- refinement (l0 == 0): FP64 residual of the game's rows into level 0's
+    //      right-hand side, then the stop test
+    __syncthreads();
+    double rm = 0.0, xm = 0.0;
+    for (int i = q.r0 + tid; i < q.r1; i += kTailThreads) {
+      const double ax = row_dot1_f<double>(L.ci, rf.a64, [&](int j) -> double { return sol[j]; }, L.rp[i],
+                                           L.rp[i + 1]);
+      const double r = rf.rhs[i] - ax;
+      L.b[i] = (T)r;
+      const double xi = sol[i];
+      rm = fmax(rm, r == r ? fabs(r) : INFINITY);  // NaN must survive the maximum
+      xm = fmax(xm, xi == xi ? fabs(xi) : INFINITY);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      rm = fmax(rm, __shfl_xor(rm, o));
+      xm = fmax(xm, __shfl_xor(xm, o));
+    }
+    if ((tid & 63) == 0) {
+      s_rm[tid >> 6] = rm;
+      s_xm[tid >> 6] = xm;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int w = 1; w < kTailThreads / 64; ++w) {
+        rm = fmax(rm, s_rm[w]);
+        xm = fmax(xm, s_xm[w]);
+      }
+      s_go = lin_decide(g, rm, xm, rf.bnorm, rf.ctl, rf.act, rf.norm) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_go) break;
   }
 }
 
@@ -2465,11 +2503,13 @@ void cyc_update64(const Tile* t, int nt, const int* act, const T* e, double* x, 
 template <class T>
 void cyc_tail(const int* games, int ngames, int l0, int nlev, int G, const TailLev<T>* lv, const TailGL* gl,
               const int* act, T omega, int nu1, int nu2, int out_y, int lds_rows, hipStream_t s,
-              double* sol) {
+              double* sol, const TailRefine* rf) {
   if (ngames <= 0) return;
   const size_t lds = 2 * sizeof(T) * (size_t)std::max(lds_rows, 1);
+  TailRefine r{};
+  if (rf) r = *rf;
   hipLaunchKernelGGL(k_tail<T>, dim3(ngames), dim3(kTailThreads), lds, s, games, l0, nlev, G, lv, gl, act, omega,
-                     nu1, nu2, out_y, sol);
+                     nu1, nu2, out_y, sol, r);
   SHP_LAUNCH_CHECK();
 }
 
@@ -2487,7 +2527,7 @@ void cyc_tail(const int* games, int ngames, int l0, int nlev, int G, const TailL
                                const double*, const double*, T*, Stripes, int, hipStream_t);         \
   template void cyc_update64<T>(const Tile*, int, const int*, const T*, double*, hipStream_t);          \
   template void cyc_tail<T>(const int*, int, int, int, int, const TailLev<T>*, const TailGL*, const int*, T, int, \
-                            int, int, int, hipStream_t, double*);
+                            int, int, int, hipStream_t, double*, const TailRefine*);
 SHP_INST(float)
 SHP_INST(double)
 #undef SHP_INST

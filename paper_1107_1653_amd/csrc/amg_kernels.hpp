@@ -83,7 +83,8 @@ void amg_mark_coarse(const Tile* t, int nt, const int* pc, const uint8_t* chg, u
 template <class T>
 void cyc_tail(const int* games, int ngames, int l0, int nlev, int G, const TailLev<T>* lv, const TailGL* gl,
               const int* act, T omega, int nu1, int nu2, int out_y, int lds_rows, hipStream_t s,
-              double* sol = nullptr);  // sol: also sol += result on level l0 (FP64)
+              double* sol = nullptr,  // sol: also sol += result on level l0 (FP64)
+              const TailRefine* rf = nullptr);  // l0 == 0: refinement cycles in the launch
 
 // lanes per sparse row (1, 4 or 16) for a level with this average row length
 int row_group(double avg_len);

@@ -910,7 +910,7 @@ static T* vcycle_impl(Engine* e, std::vector<Level>& lv, int l, const EngineOpts
 // whose tail starts here, writing into the same buffer.
 template <class T>
 static T* vcycle_level(Engine* e, std::vector<Level>& lv, int l, const EngineOpts& o, const int* act,
-                       hipStream_t s, double* sol) {
+                       hipStream_t s, double* sol, const TailRefine* rf = nullptr) {
   Level& L = lv[l];
   T* res = L.upper ? vcycle_impl<T>(e, lv, l, o, act, s, sol) : LV<T>::x(L);
   if (L.ntailg) {
@@ -928,8 +928,9 @@ static T* vcycle_level(Engine* e, std::vector<Level>& lv, int l, const EngineOpt
     probe_begin(kProbeTail, s);
     cyc_tail<T>(L.tailg.p, L.ntailg, l, e->num_levels(), e->num_slots(), e->tail_levels((T*)nullptr),
                 e->tail_games(), act, (T)o.omega, o.nu1, o.nu2, res == LV<T>::y(L) ? 1 : 0, L.tail_lds_rows, s,
-                sol);
-    probe_end(kProbeTail, s, bytes);
+                sol, rf);
+    probe_end(kProbeTail, s, rf ? 0.0 : bytes);  // refinement: bytes once the cycles are known
+    if (rf) e->tail_cycle_bytes = bytes;
   }
   return res;
 }
@@ -976,6 +977,26 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
   // every level-0 row ends its cycle in a post-smoothing sweep or in a tail
   const bool fuse_update = o.nu2 >= 1 && L0.nvblk == 0;
   resid_check();
+  if (fuse_update && !L0.upper && L0.ntailg > 0) {
+    // every game's tail starts on level 0: all its cycles, FP64 residuals and
+    // stop tests in one launch of the tail kernel
+    int maxc = 1;
+    for (int g : run) maxc = std::max(maxc, slots[g]->opt.max_cycles);
+    TailRefine rf{L0.a64.p, rhs.p, d_bnorm.p, d_lin.p, d_lin_active, d_norm.p, maxc + 1};
+    tail_cycle_bytes = 0.0;
+    if (mixed)
+      vcycle_level<float>(this, lv, 0, o, d_lin_active, stream, sol.p, &rf);
+    else
+      vcycle_level<double>(this, lv, 0, o, d_lin_active, stream, sol.p, &rf);
+    const LinCtl* pl = down(d_lin.p, 2 * (size_t)Gm);
+    sync();
+    h_lin.assign(pl, pl + G);
+    if (probe_on(kProbeTail)) {
+      double cyc = 0.0;
+      for (int g : run) cyc = std::max(cyc, (double)h_lin[g].cyc);
+      probe_add_bytes(kProbeTail, tail_cycle_bytes * cyc);
+    }
+  } else {
   int chunk = std::max(1, std::min(last_cycles, 16));
   while (true) {
     for (int c = 0; c < chunk; ++c) {
@@ -1002,6 +1023,7 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
       break;
     }
     chunk = 1;
+  }
   }
   for (int g : run) {
     SlotState* S = slots[g];

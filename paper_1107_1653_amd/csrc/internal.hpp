@@ -226,6 +226,8 @@ struct LinCtl {
 // iterate maxima out of the stripes (and clears them), records them in
 // norm[4g], norm[4g+1], and for an active game decides whether its solve
 // stops (act[g] = 0) or takes another cycle.
+__device__ inline bool lin_decide(int g, double rn, double xn, const double* __restrict__ bnorm,
+                                  LinCtl* __restrict__ ctl, int* __restrict__ act, double* __restrict__ norm);
 __device__ inline void lin_check_game(const Stripes& st, int g, const double* __restrict__ bnorm,
                                       LinCtl* __restrict__ ctl, int* __restrict__ act, double* __restrict__ norm) {
   double rn = 0.0, xn = 0.0;
@@ -238,9 +240,15 @@ __device__ inline void lin_check_game(const Stripes& st, int g, const double* __
     *a0 = 0.0;
     *a1 = 0.0;
   }
+  lin_decide(g, rn, xn, bnorm, ctl, act, norm);
+}
+// The decision part of the stop test from max |r| and max |x| of game g;
+// returns whether the game's solve goes on.
+__device__ inline bool lin_decide(int g, double rn, double xn, const double* __restrict__ bnorm,
+                                  LinCtl* __restrict__ ctl, int* __restrict__ act, double* __restrict__ norm) {
   norm[4 * g] = rn;
   norm[4 * g + 1] = xn;
-  if (!act[g]) return;
+  if (!act[g]) return false;
   LinCtl c = ctl[g];
   double tol = fmax(c.rtol * fmax(bnorm[g], xn), c.atol);
   int flags = c.flags & ~1;
@@ -267,7 +275,22 @@ __device__ inline void lin_check_game(const Stripes& st, int g, const double* __
   if (stop) act[g] = 0; else c.cyc += 1;
   c.flags = flags;
   ctl[g] = c;
+  return !stop;
 }
+
+// Refinement inside the tail kernel (games whose tail starts on level 0):
+// after each cycle the correction is added to sol, the FP64 residual of the
+// game's rows becomes level 0's right-hand side and the stop test decides;
+// up to `cycles` cycles in one launch.
+struct TailRefine {
+  const double* a64;   // level-0 matrix values (FP64), pattern of level 0
+  const double* rhs;   // b of A v = b (FP64)
+  const double* bnorm;
+  LinCtl* ctl;
+  int* act;            // the same flags the kernel reads, written by the stop test
+  double* norm;
+  int cycles;          // 0: one cycle, no refinement
+};
 
 // Lock-step policy-iteration engine over a set of games (one slot per game).
 class Engine {
@@ -310,6 +333,7 @@ class Engine {
   // Evaluates the improvement sweep at the slots' current v (no decisions).
   void improve_only();
   std::vector<int> pmis_need;        // PMIS rounds each level needed at its last setup
+  double tail_cycle_bytes = 0.0;     // algorithmic bytes of one tail cycle (probe)
   const Game* hier_game = nullptr;  // the game of a one-game hierarchy (inspection)
   // Copies level l of a one-game hierarchy to the host (synchronous): sizes,
   // A_l (CSR) and, when a coarser level exists, P_l (PW slots per row).

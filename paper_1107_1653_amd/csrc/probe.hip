@@ -67,6 +67,12 @@ void probe_end(int fam, hipStream_t s, double bytes) {
   f.bytes += bytes;
 }
 
+void probe_add_bytes(int fam, double bytes) {
+  if (!probe_on(fam)) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_fam[fam].bytes += bytes;
+}
+
 void probe_enable(int fam, bool on) {
   std::lock_guard<std::mutex> lk(g_mu);
   Family& f = g_fam[fam];

@@ -22,6 +22,8 @@ enum {
 bool probe_on(int fam);
 void probe_begin(int fam, hipStream_t s);
 void probe_end(int fam, hipStream_t s, double bytes);
+// bytes of a launch known only after it ran (a launch that loops on the device)
+void probe_add_bytes(int fam, double bytes);
 void probe_enable(int fam, bool on);
 void probe_read(int fam, int64_t* launches, double* ms, double* bytes);
 
