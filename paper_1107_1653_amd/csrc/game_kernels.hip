@@ -134,18 +134,30 @@ __global__ __launch_bounds__(256) void k_assemble(const GameDesc* __restrict__ g
   double bmax = 0.0;
   int x = t.s0 + threadIdx.x;
   if (x < t.s1) {
-    int s = (x * d.m1 + d.alpha[x]) * d.m2 + d.beta[x];
-    int e = d.rp[s], e1 = d.rp[s + 1];
-    double diag = 0.0;
-    for (int j = d.urp[x], j1 = d.urp[x + 1]; j < j1; ++j) {
-      int c = d.uci[j];
-      double val = (c == x) ? 1.0 : 0.0;
-      while (e < e1 && d.ci[e] < c) ++e;
-      while (e < e1 && d.ci[e] == c) { val -= d.mu * d.w[e]; ++e; }
-      a64[d.a_off + j] = val;
-      if (a32) a32[d.a_off + j] = (float)val;
-      if (c == x) diag = val;
+    const int s = (x * d.m1 + d.alpha[x]) * d.m2 + d.beta[x];
+    const int e0 = d.rp[s], e1 = d.rp[s + 1];
+    const int j0 = d.urp[x], j1 = d.urp[x + 1];
+    // the identity row on the level-0 pattern, then each entry of the chosen
+    // row subtracted at its column (found by bisection: the pattern row is
+    // sorted and holds every column of the state's rows), in row order
+    int jd = j0;
+    for (int j = j0; j < j1; ++j) {
+      const int c = d.uci[j];
+      a64[d.a_off + j] = c == x ? 1.0 : 0.0;
+      if (c == x) jd = j;
     }
+    for (int e = e0; e < e1; ++e) {
+      const int c = d.ci[e];
+      int lo = j0, hi = j1 - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (d.uci[mid] < c) lo = mid + 1; else hi = mid;
+      }
+      a64[d.a_off + lo] -= d.mu * d.w[e];
+    }
+    double diag = a64[d.a_off + jd];
+    if (a32)
+      for (int j = j0; j < j1; ++j) a32[d.a_off + j] = (float)a64[d.a_off + j];
     int X = d.x_off + x;
     double rb = d.r[s];
     b0[X] = rb;
