@@ -1149,15 +1149,15 @@ __device__ __forceinline__ int drap_game(const long long* __restrict__ off, int 
 // P slots in order) go through LDS in chunks of 64; a chunk is sorted by
 // (J, position), each run of equal J summed by a segmented scan and added to
 // the row's dense accumulator, chunk after chunk
-template <bool TOUCH>
+template <bool TOUCH, int MAXC>
 __global__ __launch_bounds__(kBlock) void k_drap_ap(int nf, const long long* __restrict__ tab, int G,
                                                     const int* __restrict__ rp, const int* __restrict__ ci,
                                                     const double* __restrict__ a, const int* __restrict__ pc,
                                                     const double* __restrict__ pv, double* __restrict__ ap,
                                                     uint8_t* __restrict__ apt) {
   constexpr int W = kBlock / 64;
-  __shared__ double acc_s[W][kDrapMaxCols];
-  __shared__ uint8_t hit_s[W][kDrapMaxCols];
+  __shared__ double acc_s[W][MAXC];
+  __shared__ uint8_t hit_s[W][MAXC];
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = blockIdx.x * W + wid;
   if (i >= nf) return;
@@ -2381,12 +2381,16 @@ void amg_rap_known(int nc, const int* rrp, const int* rci, const double* rv, con
                         only, big, s);
 }
 static unsigned drap_blocks(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
-void amg_drap_full(int nf, int nc, const long long* tab, int G, long long ac_total, const int* rp, const int* ci,
-                   const double* a, const int* pc, const double* pv, const int* rrp, const int* rci, const double* rv,
-                   double* ap, uint8_t* apt, double* ac, uint8_t* acf, int* cnt, hipStream_t s) {
+void amg_drap_full(int nf, int nc, int maxc, const long long* tab, int G, long long ac_total, const int* rp,
+                   const int* ci, const double* a, const int* pc, const double* pv, const int* rrp, const int* rci,
+                   const double* rv, double* ap, uint8_t* apt, double* ac, uint8_t* acf, int* cnt, hipStream_t s) {
   if (nc <= 0) return;
-  hipLaunchKernelGGL(k_drap_ap<true>, dim3(drap_blocks(64LL * nf)), dim3(kBlock), 0, s, nf, tab, G, rp, ci, a, pc,
-                     pv, ap, apt);
+  if (maxc <= kDrapSmallCols)
+    hipLaunchKernelGGL((k_drap_ap<true, kDrapSmallCols>), dim3(drap_blocks(64LL * nf)), dim3(kBlock), 0, s, nf, tab, G,
+                       rp, ci, a, pc, pv, ap, apt);
+  else
+    hipLaunchKernelGGL((k_drap_ap<true, kDrapMaxCols>), dim3(drap_blocks(64LL * nf)), dim3(kBlock), 0, s, nf, tab, G,
+                       rp, ci, a, pc, pv, ap, apt);
   SHP_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_drap_ac, dim3(drap_blocks(ac_total)), dim3(kBlock), 0, s, ac_total, tab, G, rrp, rci, rv, ap,
                      apt, ac, acf);
@@ -2401,12 +2405,17 @@ void amg_drap_compact(int nc, const long long* tab, int G, const double* ac, con
                      cval);
   SHP_LAUNCH_CHECK();
 }
-void amg_drap_known(int nf, int nc, const long long* tab, int G, const int* rp, const int* ci, const double* a,
-                    const int* pc, const double* pv, const int* rrp, const int* rci, const double* rv, double* ap,
-                    const int* crp, const int* cci, double* cval, hipStream_t s, const uint8_t* only) {
+void amg_drap_known(int nf, int nc, int maxc, const long long* tab, int G, const int* rp, const int* ci,
+                    const double* a, const int* pc, const double* pv, const int* rrp, const int* rci,
+                    const double* rv, double* ap, const int* crp, const int* cci, double* cval, hipStream_t s,
+                    const uint8_t* only) {
   if (nc <= 0) return;
-  hipLaunchKernelGGL(k_drap_ap<false>, dim3(drap_blocks(64LL * nf)), dim3(kBlock), 0, s, nf, tab, G, rp, ci, a, pc,
-                     pv, ap, (uint8_t*)nullptr);
+  if (maxc <= kDrapSmallCols)
+    hipLaunchKernelGGL((k_drap_ap<false, kDrapSmallCols>), dim3(drap_blocks(64LL * nf)), dim3(kBlock), 0, s, nf, tab,
+                       G, rp, ci, a, pc, pv, ap, (uint8_t*)nullptr);
+  else
+    hipLaunchKernelGGL((k_drap_ap<false, kDrapMaxCols>), dim3(drap_blocks(64LL * nf)), dim3(kBlock), 0, s, nf, tab,
+                       G, rp, ci, a, pc, pv, ap, (uint8_t*)nullptr);
   SHP_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_drap_known, dim3(drap_blocks(64LL * nc)), dim3(kBlock), 0, s, nc, tab, G, rrp, rci, rv, ap,
                      crp, cci, cval, only);

@@ -54,19 +54,28 @@ void amg_rap_known(int nc, const int* rrp, const int* rci, const double* rv, con
 // Galerkin product of a small level through dense per-game blocks.  tab
 // holds four tables of G + 1 offsets: fine rows, coarse rows, AP entries
 // (sum of n_f * n_c over the games before) and coarse dense entries (sum of
-// n_c^2).  nf, nc: rows of the level and of the next one.  ap/apt: [ap_total] scratch, ac/acf: [ac_total] scratch.  Full
+// n_c^2).  nf, nc: rows of the level and of the next one; maxc: the largest
+// n_c of a game (<= kDrapMaxCols).  ap/apt: [ap_total] scratch, ac/acf: [ac_total] scratch.  Full
 // setup: amg_drap_full (row lengths into cnt), scan of cnt into the coarse
 // row pointers, amg_drap_compact.  Refresh: amg_drap_known.
-constexpr int kDrapMaxCols = 1024;            // coarse rows of one game
-constexpr long long kDrapMaxEntries = 1 << 21;  // sum over games of n_f * n_c, and of n_c^2
-void amg_drap_full(int nf, int nc, const long long* tab, int G, long long ac_total, const int* rp, const int* ci,
-                   const double* a, const int* pc, const double* pv, const int* rrp, const int* rci, const double* rv,
-                   double* ap, uint8_t* apt, double* ac, uint8_t* acf, int* cnt, hipStream_t s);
+constexpr int kDrapMaxCols = 2048;             // coarse rows of one game (LDS row of the AP kernel)
+constexpr long long kDrapMaxEntries = 1 << 25;  // sum over games of n_f * n_c, and of n_c^2
+// A level takes the dense blocks when its games' next levels are small
+// (<= 1024 rows, <= 2^21 dense entries) or when the dense AP is at most
+// kDrapDensity times the products of the row-wise path (dense coarse
+// operators, e.g. 3-D coarse levels)
+constexpr int kDrapSmallCols = 1024;
+constexpr long long kDrapSmallEntries = 1 << 21;
+constexpr long long kDrapDensity = 16;
+void amg_drap_full(int nf, int nc, int maxc, const long long* tab, int G, long long ac_total, const int* rp,
+                   const int* ci, const double* a, const int* pc, const double* pv, const int* rrp, const int* rci,
+                   const double* rv, double* ap, uint8_t* apt, double* ac, uint8_t* acf, int* cnt, hipStream_t s);
 void amg_drap_compact(int nc, const long long* tab, int G, const double* ac, const uint8_t* acf, const int* crp,
                       int* cci, double* cval, hipStream_t s);
-void amg_drap_known(int nf, int nc, const long long* tab, int G, const int* rp, const int* ci, const double* a,
-                    const int* pc, const double* pv, const int* rrp, const int* rci, const double* rv, double* ap,
-                    const int* crp, const int* cci, double* cval, hipStream_t s, const uint8_t* only);
+void amg_drap_known(int nf, int nc, int maxc, const long long* tab, int G, const int* rp, const int* ci,
+                    const double* a, const int* pc, const double* pv, const int* rrp, const int* rci,
+                    const double* rv, double* ap, const int* crp, const int* cci, double* cval, hipStream_t s,
+                    const uint8_t* only);
 void amg_diag_inv(int n, const int* rp, const int* ci, const double* a, double* d64, float* d32,
                   hipStream_t s);
 void amg_cast(const double* in, float* out, size_t n, hipStream_t s);

@@ -537,8 +537,11 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
             ap += ncg * (L.goff[g + 1] - L.goff[g]);
             ac += ncg * ncg;
           }
-          L.drap = maxc <= kDrapMaxCols && ap <= kDrapMaxEntries && ac <= kDrapMaxEntries;
+          const bool small = maxc <= kDrapSmallCols && ap <= kDrapSmallEntries && ac <= kDrapSmallEntries;
+          const bool dense = ap <= kDrapDensity * PW * (long long)L.nnz;
+          L.drap = maxc <= kDrapMaxCols && ap <= kDrapMaxEntries && ac <= kDrapMaxEntries && (small || dense);
           L.drap_ap = ap;
+          L.drap_maxc = maxc;
           L.drap_ac = ac;
           if (L.drap) {
             std::vector<long long>& t = L.h_drap_tab;  // kept alive for the asynchronous upload
@@ -562,8 +565,9 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
           s_dapt.ensure(std::max<long long>(L.drap_ap, 1));
           s_dac.ensure(std::max<long long>(L.drap_ac, 1));
           s_dacf.ensure(std::max<long long>(L.drap_ac, 1));
-          amg_drap_full(n, nc, L.drap_tab.p, G, L.drap_ac, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, L.rrp.p,
-                        L.rci.p, L.rv64.p, s_dap.p, s_dapt.p, s_dac.p, s_dacf.p, s_cnt.p, stream);
+          amg_drap_full(n, nc, L.drap_maxc, L.drap_tab.p, G, L.drap_ac, L.rp.p, L.ci.p, L.a64.p, L.pc.p,
+                        L.pv64.p, L.rrp.p, L.rci.p, L.rv64.p, s_dap.p, s_dapt.p, s_dac.p, s_dacf.p, s_cnt.p,
+                        stream);
         } else {
           amg_rap_bound(nc, L.rrp.p, L.rci.p, L.rp.p, s_cnt.p, stream);
           scan_exclusive(s_cnt.p, s_toff.p, nc + 1, stream, s_scan);
@@ -809,8 +813,8 @@ void Engine::refresh(const EngineOpts& o) {
       probe_begin(kProbeRap, stream);
       if (L.drap) {
         s_dap.ensure(std::max<long long>(L.drap_ap, 1));
-        amg_drap_known(L.n, L.nc, L.drap_tab.p, G, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, L.rrp.p, L.rci.p,
-                       L.rv64.p, s_dap.p, Ln.rp.p, Ln.ci.p, Ln.a64.p, stream, Ln.chg.p);
+        amg_drap_known(L.n, L.nc, L.drap_maxc, L.drap_tab.p, G, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p,
+                       L.rrp.p, L.rci.p, L.rv64.p, s_dap.p, Ln.rp.p, Ln.ci.p, Ln.a64.p, stream, Ln.chg.p);
       } else {
         s_big.ensure((size_t)L.nc + 1);
         amg_rap_known(L.nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, Ln.rp.p,

@@ -151,6 +151,7 @@ struct Level {
   // Galerkin product through dense per-game blocks (small next levels)
   bool drap = false;
   long long drap_ap = 0, drap_ac = 0;  // dense entries of AP and of R A P
+  int drap_maxc = 0;                    // rows of the largest game's next level
   DBuf<long long> drap_tab;       // offset tables (fine rows, coarse rows, AP, R A P), 4 x (G+1)
   std::vector<long long> h_drap_tab;
   // dense inverses of terminal slots: blocks (row0, size, offset into dmat)
