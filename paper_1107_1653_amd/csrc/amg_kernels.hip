@@ -1661,6 +1661,108 @@ __global__ __launch_bounds__(256) void k_dense_inv(const int* __restrict__ blk, 
 extern "C" __device__ unsigned long long __ockl_wfred_max_u64(unsigned long long);
 
 // In-place Gauss-Jordan inversion with partial pivoting for blocks of at
+// most 64 unknowns, four wavefronts: lane i of wavefront w holds row i's
+// entries in columns 16w .. 16w+15 in registers.  Step k: the wavefront that
+// owns column k picks the pivot (the unused row with the largest |M[i][k]|,
+// compared on the leading 56 bits, the lowest row first) and publishes the
+// column; every wavefront then reads the pivot row's entries of its columns
+// from the pivot lane and eliminates.  Rows are not swapped; with p_k the
+// pivot row of step k the in-place result M holds inv[k][p_j] = M[p_k][j].
+__device__ __forceinline__ double lane_read(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__global__ __launch_bounds__(256) void k_dense_inv_cols(const int* __restrict__ blk, const int* __restrict__ rp,
+                                                        const int* __restrict__ ci, const double* __restrict__ a,
+                                                        double* __restrict__ inv64, float* __restrict__ inv32,
+                                                        int* __restrict__ err, const uint8_t* __restrict__ only) {
+  constexpr int CB = 16, LD = 65;
+  __shared__ double S[64 * LD];
+  __shared__ double colk[2][64];
+  __shared__ int pk[2];
+  __shared__ int perm[64];
+  const int row0 = blk[4 * blockIdx.x], nb = blk[4 * blockIdx.x + 1];
+  const size_t doff = (size_t)blk[4 * blockIdx.x + 2];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (nb > 64) return;  // a larger block: another kernel
+  if (only) {           // incremental refresh: skip blocks none of whose rows changed
+    int any = 0;
+    for (int r = threadIdx.x; r < nb; r += 256) any |= only[row0 + r];
+    if (!__syncthreads_or(any)) return;
+  }
+  for (int idx = threadIdx.x; idx < 64 * LD; idx += 256) S[idx] = 0.0;
+  __syncthreads();
+  if (w == 0 && lane < nb) {  // row `lane` into column-major staging
+    const int r = row0 + lane;
+    for (int e = rp[r]; e < rp[r + 1]; ++e) {
+      const int c = ci[e] - row0;
+      if (c >= 0 && c < nb) S[c * LD + lane] += a[e];
+    }
+  }
+  __syncthreads();
+  double v[CB];
+#pragma unroll
+  for (int jj = 0; jj < CB; ++jj) v[jj] = S[(CB * w + jj) * LD + lane];
+  bool used = lane >= nb;
+  int myk = 0;
+  for (int kb = 0; kb * CB < nb; ++kb) {
+#pragma unroll
+    for (int kk = 0; kk < CB; ++kk) {
+      const int k = kb * CB + kk;
+      if (k < nb) {  // uniform over the workgroup
+        const int buf = k & 1;
+        if (w == kb) {
+          unsigned long long key = 0;
+          if (!used) {
+            const double m = fabs(v[kk]);
+            if (m == m)
+              key = ((unsigned long long)__double_as_longlong(m) & ~0xFFull) | (unsigned long long)(255 - lane);
+          }
+          key = __ockl_wfred_max_u64(key);
+          colk[buf][lane] = v[kk];
+          if (lane == 0) pk[buf] = (key >> 8) == 0 ? -1 : 255 - (int)(key & 0xFF);
+        }
+        __syncthreads();
+        const int p = pk[buf];
+        if (p < 0) {  // no nonzero pivot left (uniform): singular block
+          if (threadIdx.x == 0) atomicOr(err, 4);
+          return;
+        }
+        const double inv = 1.0 / colk[buf][p];
+        const double f = colk[buf][lane] * inv;  // M[i][k] / pivot
+        const bool piv = lane == p;
+#pragma unroll
+        for (int jj = 0; jj < CB; ++jj) {
+          const double pr = lane_read(v[jj], p);
+          v[jj] = piv ? pr * inv : v[jj] - f * pr;
+        }
+        if (w == kb) v[kk] = piv ? inv : -f;
+        if (piv) {
+          used = true;
+          myk = k;
+          if (w == 0) perm[k] = p;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (lane < nb) {
+#pragma unroll
+    for (int jj = 0; jj < CB; ++jj) {
+      const int j = CB * w + jj;
+      if (j < nb) {
+        const size_t o = doff + (size_t)perm[j] * nb + myk;
+        inv64[o] = v[jj];
+        if (inv32) inv32[o] = (float)v[jj];
+      }
+    }
+  }
+}
+
+// In-place Gauss-Jordan inversion with partial pivoting for blocks of at
 // most NB <= kDenseWave unknowns: one thread per row of the block, the row in
 // registers.  Pivot rows are not swapped: step k takes the row p not yet used
 // as a pivot with the largest |M[p][k]| (magnitudes compared on their leading
@@ -2436,10 +2538,8 @@ void amg_dense_inv(const int* blk, int nblk, const int* rp, const int* ci, const
                    double* inv64, float* inv32, int* err, int max_nb, hipStream_t s, const uint8_t* only) {
   if (!nblk) return;
   static_assert(kDenseWave == 96, "register kernel sizes");
-  if (max_nb <= 32)
-    hipLaunchKernelGGL((k_dense_inv_reg<32, 64>), dim3(nblk), dim3(64), 0, s, blk, rp, ci, a, inv64, inv32, err, only);
-  else if (max_nb <= 64)
-    hipLaunchKernelGGL((k_dense_inv_reg<64, 64>), dim3(nblk), dim3(64), 0, s, blk, rp, ci, a, inv64, inv32, err, only);
+  if (max_nb <= 64)
+    hipLaunchKernelGGL(k_dense_inv_cols, dim3(nblk), dim3(256), 0, s, blk, rp, ci, a, inv64, inv32, err, only);
   else
     hipLaunchKernelGGL((k_dense_inv_reg<96, 128>), dim3(nblk), dim3(128), 0, s, blk, rp, ci, a, inv64, inv32, err,
                        only);
