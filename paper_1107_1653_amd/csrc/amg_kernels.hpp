@@ -61,11 +61,13 @@ void amg_rap_known(int nc, const int* rrp, const int* rci, const double* rv, con
 constexpr int kDrapMaxCols = 2048;             // coarse rows of one game (LDS row of the AP kernel)
 constexpr long long kDrapMaxEntries = 1 << 25;  // sum over games of n_f * n_c, and of n_c^2
 // A level takes the dense blocks when its games' next levels are small
-// (<= 1024 rows, <= 2^21 dense entries) or when the dense AP is at most
-// kDrapDensity times the products of the row-wise path (dense coarse
-// operators, e.g. 3-D coarse levels)
+// (<= 1024 rows, <= 2^21 dense entries) or when its rows are long (>=
+// kDrapRowLen entries on average) and the dense AP is at most kDrapDensity
+// times the products of the row-wise path (dense coarse operators, e.g. 3-D
+// coarse levels)
 constexpr int kDrapSmallCols = 1024;
 constexpr long long kDrapSmallEntries = 1 << 21;
+constexpr long long kDrapRowLen = 32;
 constexpr long long kDrapDensity = 16;
 void amg_drap_full(int nf, int nc, int maxc, const long long* tab, int G, long long ac_total, const int* rp,
                    const int* ci, const double* a, const int* pc, const double* pv, const int* rrp, const int* rci,

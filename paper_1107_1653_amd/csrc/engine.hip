@@ -538,7 +538,8 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
             ac += ncg * ncg;
           }
           const bool small = maxc <= kDrapSmallCols && ap <= kDrapSmallEntries && ac <= kDrapSmallEntries;
-          const bool dense = ap <= kDrapDensity * PW * (long long)L.nnz;
+          const bool dense = (long long)L.nnz >= kDrapRowLen * (long long)n &&
+                             ap <= kDrapDensity * PW * (long long)L.nnz;
           L.drap = maxc <= kDrapMaxCols && ap <= kDrapMaxEntries && ac <= kDrapMaxEntries && (small || dense);
           L.drap_ap = ap;
           L.drap_maxc = maxc;
