@@ -1,0 +1,118 @@
+"""Host side of the measurement path (CPU): the rocprofv3 summaries the
+profiles are made with, the bench's counter-traffic lookup and its one-GPU
+contract.  No GPU is used."""
+import csv
+import json
+import os
+import sqlite3
+import subprocess
+import sys
+
+import pytest
+
+from paper_1107_1653_amd import rocprof_summary as rs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def write_counters(path, counter, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for name, value in rows:
+            w.writerow({"Kernel_Name": name, "Counter_Name": counter, "Counter_Value": value})
+
+
+def test_traffic_is_scaled_by_the_calibration_kernel(tmp_path):
+    cal = rs.CALIB_BYTES
+    # the calibration kernel reads as FETCH_SIZE half of what it moves and
+    # writes its full size: factors 2 and 1
+    fetch = [("void at::native::neg_kernel(...)", cal / 2 / 1024),
+             ("void shp::k_smooth<double, 4>(...)", 1000.0),
+             ("void shp::k_smooth<double, 1>(...)", 3000.0),
+             ("void shp::k_rap_small<0>(...)", 500.0),
+             ("void shp::k_rap_list<128, 0>(...)", 100.0),  # completes the previous launch
+             ("shp::k_drap_ap<true, 1024>(...)", 40.0),
+             ("shp::k_drap_ac(...)", 20.0),
+             ("shp::k_drap_count(...)", 4.0),
+             ("shp::k_scan_block(...)", 7.0)]                # no family
+    write = [("void at::native::neg_kernel(...)", cal / 1024),
+             ("void shp::k_smooth<double, 4>(...)", 10.0),
+             ("void shp::k_smooth<double, 1>(...)", 30.0),
+             ("void shp::k_rap_small<0>(...)", 50.0),
+             ("void shp::k_rap_list<128, 0>(...)", 10.0),
+             ("shp::k_drap_ap<true, 1024>(...)", 4.0),
+             ("shp::k_drap_ac(...)", 2.0),
+             ("shp::k_drap_count(...)", 0.0),
+             ("shp::k_scan_block(...)", 1.0)]
+    fcsv, wcsv = tmp_path / "f.csv", tmp_path / "w.csv"
+    write_counters(fcsv, "FETCH_SIZE", fetch)
+    write_counters(wcsv, "WRITE_SIZE", write)
+    d = rs.traffic(str(fcsv), str(wcsv))
+    assert d["calibration"]["fetch_factor"] == pytest.approx(2.0)
+    assert d["calibration"]["write_factor"] == pytest.approx(1.0)
+    sm = d["families"]["smooth"]
+    assert sm["launches"] == 2
+    assert sm["fetch_bytes_per_launch"] == pytest.approx(2.0 * 4000.0 * 1024 / 2)
+    assert sm["write_bytes_per_launch"] == pytest.approx(40.0 * 1024 / 2)
+    rap = d["families"]["rap"]
+    # two launches (the row-wise and the dense product); the list kernel and
+    # the dense product's later kernels continue a launch
+    assert rap["launches"] == 2
+    assert rap["fetch_bytes_per_launch"] == pytest.approx(2.0 * 664.0 * 1024 / 2)
+    assert rap["bytes_per_launch"] == pytest.approx(rap["fetch_bytes_per_launch"] + 66.0 * 1024 / 2)
+    assert "scan" not in d["families"]
+
+
+def test_traffic_needs_the_calibration_kernel(tmp_path):
+    fcsv, wcsv = tmp_path / "f.csv", tmp_path / "w.csv"
+    write_counters(fcsv, "FETCH_SIZE", [("shp::k_improve(...)", 1.0)])
+    write_counters(wcsv, "WRITE_SIZE", [("shp::k_improve(...)", 1.0)])
+    with pytest.raises(RuntimeError):
+        rs.traffic(str(fcsv), str(wcsv))
+
+
+def test_trace_summary_counts_launches_per_family(tmp_path):
+    db = tmp_path / "t.db"
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, start integer, end integer)")
+    rows = [("void shp::k_tail<double>(int)", 0, 20000), ("void shp::k_tail<double>(int)", 30000, 70000),
+            ("void shp::k_rap_small<1>(int)", 0, 5000), ("void shp::k_rap_list<128, 1>(int)", 6000, 8000),
+            ("shp::k_drap_ap<false, 2048>(int)", 0, 1000), ("shp::k_drap_known(int)", 1000, 4000)]
+    con.executemany("insert into kernels values (?, ?, ?)", rows)
+    con.commit()
+    con.close()
+    stats = {k: (c, t) for k, c, t, _ in rs.kernel_stats(str(db))}
+    assert stats["shp::k_tail<double>"] == (2, pytest.approx(60.0))
+    text = rs.trace_summary(str(db))
+    fam = {}
+    for line in text.splitlines():
+        parts = [p.strip() for p in line.strip("|").split("|")]
+        if len(parts) == 4 and parts[0] in ("tail", "rap"):
+            fam[parts[0]] = (int(parts[1]), float(parts[2]), float(parts[3]))
+    assert fam["tail"] == (2, pytest.approx(0.06), pytest.approx(30.0))
+    # rap: the wavefront kernel and the dense AP start launches (2); the list
+    # kernel and the dense R(AP) pass continue them; 11 us in all
+    assert fam["rap"] == (2, pytest.approx(0.011, abs=0.005), pytest.approx(5.5))  # total printed to 0.01 ms
+
+
+def test_bench_reports_no_traffic_for_changed_sources(tmp_path, monkeypatch):
+    sys.path.insert(0, ROOT)
+    import bench
+    f = tmp_path / "traffic.json"
+    f.write_text(json.dumps({"source_sha256": "0" * 64, "families": {"rap": {"bytes_per_launch": 1.0}}}))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    value, why = bench.measured_traffic("rap")
+    assert value is None and "changed" in why
+    f.write_text(json.dumps({"source_sha256": rs.source_hash(), "families": {"rap": {"bytes_per_launch": 5.0}}}))
+    value, why = bench.measured_traffic("rap")
+    assert value == 5.0
+    value, why = bench.measured_traffic("tail")
+    assert value is None
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
