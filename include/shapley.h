@@ -110,7 +110,9 @@ typedef struct shapley_stats {
   double residual;           /* final ||F(v) - v||_inf */
   double residual_l2;        /* final discrete L2 norm sqrt(mean((F(v)-v)^2)) */
   double seconds;            /* wall time of the solve (device-resident data) */
-  double setup_seconds;      /* AMG setups */
+  double setup_seconds;      /* AMG setups (host wall time; a numeric refresh
+                                does not wait for the device, its device time
+                                is then counted in cycle_seconds) */
   double cycle_seconds;      /* refinement + V-cycles */
   double improve_seconds;    /* assembly + improvement sweeps */
   double op_complexity;      /* sum nnz(A_l) / nnz(A_0) of the last hierarchy */

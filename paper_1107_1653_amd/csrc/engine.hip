@@ -827,13 +827,20 @@ void Engine::refresh(const EngineOpts& o) {
       amg_dense_inv(L.blk.p, L.nblk, L.rp.p, L.ci.p, L.a64.p, s_dense.p, L.dmat64.p, mixed ? L.dmat32.p : nullptr,
                     s_err.p + 2, L.max_blk, stream, L.chg.p);
   }
-  int herr[4] = {0, 0, 0, 0};
-  const int* pe = down(s_err.p, 4);
-  sync();
-  std::memcpy(herr, pe, sizeof(herr));
+  // the error flags are read with the linear solve's first synchronisation
+  // (no synchronisation of its own)
+  err_pending = true;
   pt.mark("refresh");
-  if (herr[1] != 0) throw Error(SHAPLEY_EDEVICE, "Galerkin product failed during refresh");
-  if (herr[2] != 0) throw Error(SHAPLEY_EDEVICE, "singular coarsest block");
+}
+
+// Error flags of a refresh, downloaded with a transfer of the caller's and
+// checked after its synchronisation.
+const int* Engine::refresh_errors_down() { return err_pending ? down(s_err.p, 4) : nullptr; }
+void Engine::refresh_errors_check(const int* pe) {
+  if (!pe) return;
+  err_pending = false;
+  if (pe[1] != 0) throw Error(SHAPLEY_EDEVICE, "Galerkin product failed during refresh");
+  if (pe[2] != 0) throw Error(SHAPLEY_EDEVICE, "singular coarsest block");
 }
 
 // algorithmic bytes of the cycle kernels (each value read or written once)
@@ -994,7 +1001,9 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
     else
       vcycle_level<double>(this, lv, 0, o, d_lin_active, stream, sol.p, &rf);
     const LinCtl* pl = down(d_lin.p, 2 * (size_t)Gm);
+    const int* pe = refresh_errors_down();
     sync();
+    refresh_errors_check(pe);
     h_lin.assign(pl, pl + G);
     if (probe_on(kProbeTail)) {
       double cyc = 0.0;
@@ -1018,7 +1027,9 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
       resid_check();
     }
     const LinCtl* pl = down(d_lin.p, 2 * (size_t)Gm);
+    const int* pe = refresh_errors_down();
     sync();
+    refresh_errors_check(pe);
     const int* pa = reinterpret_cast<const int*>(pl + Gm);
     h_lin_active.assign(pa, pa + G);
     bool any = false;
@@ -1148,7 +1159,7 @@ int Engine::step() {
     ++refreshes;
   }
   pt.mark("setup");
-  double t1 = now_s();  // setup and refresh end with a synchronisation
+  double t1 = now_s();  // a full setup ends with a synchronisation; a refresh does not
   {
     std::vector<int> before(G);
     for (int g : run) before[g] = slots[g]->cycles_total;

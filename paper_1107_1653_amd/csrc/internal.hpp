@@ -335,6 +335,9 @@ class Engine {
   void improve_only();
   std::vector<int> pmis_need;        // PMIS rounds each level needed at its last setup
   double tail_cycle_bytes = 0.0;     // algorithmic bytes of one tail cycle (probe)
+  bool err_pending = false;          // a refresh's error flags not read yet
+  const int* refresh_errors_down();
+  void refresh_errors_check(const int* pe);
   const Game* hier_game = nullptr;  // the game of a one-game hierarchy (inspection)
   // Copies level l of a one-game hierarchy to the host (synchronous): sizes,
   // A_l (CSR) and, when a coarser level exists, P_l (PW slots per row).
