@@ -28,6 +28,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "unknowns solved/s to 1e-8 Shapley residual, FP64 vs mixed; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+# HBM-streaming kernel families reported on the finest level
+STREAMING = ("smooth", "resid", "resid64", "improve")
 CALIB_BYTES = 1 << 30  # bytes read (and written) by the calibration kernel
 
 
@@ -211,8 +213,24 @@ def run_c1(args) -> int:
         extra["mixed"] = {"value": n / float(np.mean(lm)), "ms_per_step": 1e3 * float(np.mean(lm)),
                           "residual": sm["residual"]}
         log(f"[bench] FAMGpi mixed: {1e3 * np.mean(lm):.1f} ms/solve, residual {sm['residual']:.2e}")
-    v64 = None
+    # the streaming kernels on the finest grid's level 0, timed with HIP
+    # events in one more (untimed) solve: relaxation, cycle residual, FP64
+    # residual, policy improvement
+    for k in STREAMING:
+        P.shapley_probe_enable(k, True)
     P.shapley_solve(H, o64)
+    streaming = {}
+    for k in STREAMING:
+        r = P.shapley_probe_read_large(k, 0.5)
+        P.shapley_probe_enable(k, False)
+        if r["launches"] == 0:
+            continue
+        gbs = r["bytes"] / (r["ms"] * 1e-3) / 1e9
+        streaming[k] = {"achieved": gbs, "frac": gbs / HBM_PEAK_GBS, "launches": r["launches"],
+                        "avg_launch_us": 1e3 * r["ms"] / r["launches"],
+                        "alg_bytes_per_launch": r["bytes"] / r["launches"]}
+    log("[bench] finest-level streaming kernels: " +
+        ", ".join(f"{k} {v['achieved']:.0f} GB/s ({v['avg_launch_us']:.1f} us)" for k, v in streaming.items()))
     v64 = P.shapley_get_value(H)
     if not args.no_mixed:
         extra["mixed"]["max_abs_diff_vs_fp64"] = float(np.max(np.abs(vm - v64)))
@@ -263,6 +281,10 @@ def run_c1(args) -> int:
                   "residual": st["residual"], "setup_ms": 1e3 * st["setup_seconds"],
                   "cycle_ms": 1e3 * st["cycle_seconds"]},
         "roofline": roof,
+        "streaming": {"peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "launches": "launches of at least half the largest algorithmic bytes of the family "
+                                  f"(level 0 of the {args.points}x{args.points} grid)",
+                      "kernels": streaming},
         "cpu_baseline": cpu,
         "extra": extra,
     }

@@ -285,6 +285,17 @@ int shapley_probe_enable(int32_t family, int32_t on);
  * Synchronises with the recorded events. */
 int shapley_probe_read(int32_t family, int64_t* launches, double* total_ms, double* total_bytes);
 
+/* The same totals over the largest launches only: those whose algorithmic
+ * bytes are at least frac (0 < frac <= 1) times the largest launch's since
+ * the probe was enabled.  A family's launches on the finest level of the
+ * largest game are its largest, so frac = 0.5 isolates them (the next level
+ * of a 2-D grid holds about a quarter of the rows).  Synchronises like
+ * shapley_probe_read.  SHAPLEY_EINVAL on a bad family or frac;
+ * SHAPLEY_ENOMEM when more than 2^20 launches were probed since enabling
+ * (per-launch records are kept up to that many). */
+int shapley_probe_read_large(int32_t family, double frac, int64_t* launches, double* total_ms,
+                             double* total_bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1314,11 +1314,17 @@ __global__ __launch_bounds__(kBlock) void k_drap_known(int nc, const long long* 
 
 // Coarse rows with at most kSmR entries of R and kSmN distinct columns, one
 // wavefront per row and four rows per workgroup (the large levels, whose rows
-// are short).  The (R, A) pairs are taken kSmE at a time; products are summed
-// in runs of 64 slots, i.e. in slot order as in rap_row, so the result is the
-// same bit for bit; a row that does not fit is appended to big[1 ..] for
-// k_rap_list.
-constexpr int kSmR = 64, kSmE = 64, kSmN = 128, kSmHash = 512;
+// are short); a row that does not fit is appended to big[1 ..] for
+// k_rap_list.  The nonzero products r_Ii a_ik p_kJ are generated in the order
+// of R's row, A's row and P's slots (32 (R, A) pairs at a time, two lanes per
+// pair) and queued in LDS; each run of 64 queued products is sorted by
+// (output column, queue order) on keys alone, and the first product of each
+// column adds the column's products of the run to the column's sum, one after
+// the other.  Every column is thus the sequential sum of its products in
+// generation order, as in rap_row: the two kernels agree bit for bit.
+constexpr int kSmR = 64, kSmN = 128, kSmHash = 512;
+constexpr int kSmRing = 256;  // queued products: < 64 left over + <= 128 new
+
 template <int MODE>
 __global__ __launch_bounds__(256) void k_rap_small(int nc, const int* __restrict__ rrp, const int* __restrict__ rci,
                                                    const double* __restrict__ rv, const int* __restrict__ rp,
@@ -1329,14 +1335,15 @@ __global__ __launch_bounds__(256) void k_rap_small(int nc, const int* __restrict
                                                    const int* __restrict__ crp, const int* __restrict__ cci,
                                                    double* __restrict__ cval, const uint8_t* __restrict__ only,
                                                    int* __restrict__ big) {
-  constexpr int SS = kSmE * PW;  // product slots
-  static_assert(kSmHash * sizeof(int) <= SS * sizeof(double), "hash must fit in the product buffer");
+  static_assert(kSmHash * sizeof(int) <= kSmRing * sizeof(double), "hash must fit in the product queue");
+  static_assert((kSmRing & (kSmRing - 1)) == 0 && kSmRing >= 63 + 32 * PW, "queue too small");
   __shared__ int s_rS[4][kSmR];
   __shared__ int s_rO[4][kSmR + 1];
   __shared__ double s_rV[4][kSmR];
-  __shared__ double s_buf[4][SS];  // hash table, later the product values
+  __shared__ double s_buf[4][kSmRing];  // hash table, later the queued product values
   __shared__ int s_lst[4][kSmN];
-  __shared__ int s_key[4][SS];
+  __shared__ int s_qpos[4][kSmRing];    // output position of each queued product
+  __shared__ double s_acc[4][kSmN];     // the row's sums by output position
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int I = blockIdx.x * 4 + w;
   if (I >= nc) return;  // per wavefront; nothing below synchronises the workgroup
@@ -1345,8 +1352,9 @@ __global__ __launch_bounds__(256) void k_rap_small(int nc, const int* __restrict
   int* rO = s_rO[w];
   double* rV = s_rV[w];
   int* lst = s_lst[w];
-  int* skey = s_key[w];
-  double* pval = s_buf[w];
+  int* qpos = s_qpos[w];
+  double* qval = s_buf[w];
+  double* acc = s_acc[w];
   int* tab = reinterpret_cast<int*>(s_buf[w]);
   auto to_big = [&]() {
     if (lane == 0) big[1 + atomicAdd(big, 1)] = I;
@@ -1420,81 +1428,85 @@ __global__ __launch_bounds__(256) void k_rap_small(int nc, const int* __restrict
     if (nd > kSmN) { to_big(); return; }
     for (int h = lane; h < nd; h += 64) lst[h] = cci[base + h];
   }
-  wave_lds_sync();
-  double acc0 = 0.0, acc1 = 0.0;  // output columns at positions lane, lane + 64
-  for (int f0 = 0; f0 < E; f0 += kSmE) {
-    const int fe = (E < f0 + kSmE) ? E : f0 + kSmE;
-    const int f = f0 + lane;
-    if (f < fe) {
+  for (int h = lane; h < nd; h += 64) acc[h] = 0.0;
+  wave_lds_sync();  // the hash table is dead: its space queues products
+  int head = 0, tail = 0;  // queue counters (indices modulo kSmRing)
+  // the cnt (1..64) products at the head of the queue into the sums
+  auto run = [&](int cnt) {
+    const int idx = (head + lane) & (kSmRing - 1);
+    const bool live = lane < cnt;
+    const double v = live ? qval[idx] : 0.0;
+    int key = live ? (qpos[idx] << 6) | lane : INT_MAX;
+    wave_sort64(key);
+    const double x = __shfl(v, key & 63);  // the product now at this lane
+    const int pos = key >> 6;
+    const int prev = __shfl_up(pos, 1);
+    const bool edge = key != INT_MAX && (lane == 0 || prev != pos);  // first product of a column
+    const unsigned long long bounds = __ballot(edge || (key == INT_MAX && (lane == 0 || prev != pos)));
+    const unsigned long long above = lane == 63 ? 0ull : (bounds >> (lane + 1));
+    const int len = above ? __ffsll((long long)above) : 64 - lane;
+    int most = edge ? len : 0;
+    for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o));
+    double sum = edge ? acc[pos] : 0.0;
+    for (int j = 0; j < most; ++j) {
+      const double y = __shfl(x, lane + j);
+      if (edge && j < len) sum += y;
+    }
+    if (edge) acc[pos] = sum;
+    head += cnt;
+    wave_lds_sync();
+  };
+  for (int g0 = 0; g0 < E; g0 += 32) {
+    const int f = g0 + (lane >> 1);
+    int n_new = 0, np[2];
+    double nv[2];
+    if (f < E && nd > 0) {
       const int p = rap_locate(rO, P, f);
       const int e = rS[p] + (f - rO[p]);
       const int k = ci[e];
       const double ra = rV[p] * a[e];
-      for (int q = 0; q < PW; ++q) {
-        const int slot = lane * PW + q;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int q = 2 * (lane & 1) + u;
         const int J = pc[(size_t)k * PW + q];
-        int key = INT_MAX;
-        double val = 0.0;
-        if (J >= 0 && nd > 0) {
-          int lo = 0, hi = nd - 1;
-          while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (lst[mid] < J) lo = mid + 1; else hi = mid;
-          }
-          if (lst[lo] == J) {
-            key = (lo << 10) | slot;
-            val = ra * pv[(size_t)k * PW + q];
-          }
-        }
-        skey[slot] = key;
-        pval[slot] = val;
-      }
-    }
-    wave_lds_sync();
-    const int ns = (fe - f0) * PW;
-    const int nruns = (ns + 63) >> 6;
-    for (int r = 0; r < nruns; ++r) {
-      const int sl = (r << 6) + lane;
-      int key = sl < ns ? skey[sl] : INT_MAX;
-      double val = sl < ns ? pval[sl] : 0.0;
-      wave_sort64(key, val);
-      skey[sl] = key;
-      pval[sl] = val;
-    }
-    wave_lds_sync();
-    for (int h = 0; h < 2; ++h) {
-      const int pos = lane + 64 * h;
-      if (pos >= nd) continue;
-      const int k0 = pos << 10, k1 = (pos + 1) << 10;
-      double acc = h ? acc1 : acc0;
-      for (int r = 0; r < nruns; ++r) {
-        const int bb = r << 6;
-        int lo = 0, hi = 64;
+        if (J < 0) continue;
+        int lo = 0, hi = nd - 1;
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
-          if (skey[bb + mid] < k0) lo = mid + 1; else hi = mid;
+          if (lst[mid] < J) lo = mid + 1; else hi = mid;
         }
-        for (int t = bb + lo; t < bb + 64 && skey[t] < k1; ++t) acc += pval[t];
+        if (lst[lo] == J) {
+          np[n_new] = lo;
+          nv[n_new] = ra * pv[(size_t)k * PW + q];
+          ++n_new;
+        }
       }
-      if (h) acc1 = acc; else acc0 = acc;
     }
-    wave_lds_sync();  // the next chunk overwrites the slots
+    int incl = n_new;  // queue offsets in (pair, slot) order
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
+    }
+    const int at = tail + incl - n_new;
+    for (int u = 0; u < n_new; ++u) {
+      qpos[(at + u) & (kSmRing - 1)] = np[u];
+      qval[(at + u) & (kSmRing - 1)] = nv[u];
+    }
+    tail += __shfl(incl, 63);
+    wave_lds_sync();
+    while (tail - head >= 64) run(64);
   }
+  if (tail > head) run(tail - head);
   if (MODE == kRapFused) {
     const int o = toff[I];
-    if (lane < nd) {
-      tcol[o + lane] = lst[lane];
-      tval[o + lane] = acc0;
-    }
-    if (lane + 64 < nd) {
-      tcol[o + lane + 64] = lst[lane + 64];
-      tval[o + lane + 64] = acc1;
+    for (int h = lane; h < nd; h += 64) {
+      tcol[o + h] = lst[h];
+      tval[o + h] = acc[h];
     }
     if (lane == 0) tcnt[I] = nd;
   } else {
     const int base = crp[I];
-    if (lane < nd) cval[base + lane] = acc0;
-    if (lane + 64 < nd) cval[base + lane + 64] = acc1;
+    for (int h = lane; h < nd; h += 64) cval[base + h] = acc[h];
   }
 }
 

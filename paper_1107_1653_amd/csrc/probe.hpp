@@ -26,5 +26,8 @@ void probe_end(int fam, hipStream_t s, double bytes);
 void probe_add_bytes(int fam, double bytes);
 void probe_enable(int fam, bool on);
 void probe_read(int fam, int64_t* launches, double* ms, double* bytes);
+// totals over the launches whose algorithmic bytes are >= frac x the largest
+// launch's; false when the per-launch records overflowed
+bool probe_read_large(int fam, double frac, int64_t* launches, double* ms, double* bytes);
 
 }  // namespace shp

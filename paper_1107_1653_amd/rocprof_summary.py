@@ -1,8 +1,10 @@
 """Summaries of rocprofv3 output for this library's kernels.
 
-    python -m paper_1107_1653_amd.rocprof_summary trace <results.db> [--top N]
+    python -m paper_1107_1653_amd.rocprof_summary trace <results.db> [--top N] [--largest F,...]
         per-kernel calls / total / average duration from a --kernel-trace
-        results database, and the same per probe family
+        results database, and the same per probe family; with --largest,
+        also each kernel of those families at its largest grid (for the
+        streaming kernels: their launches on the finest level)
     python -m paper_1107_1653_amd.rocprof_summary traffic <fetch.csv> <write.csv> --out <json>
         HBM bytes per launch of each probe family from two --pmc runs
         (FETCH_SIZE, then WRITE_SIZE, output format csv) of a benchmark run
@@ -92,7 +94,45 @@ def kernel_stats(db_path: str):
     return sorted(((k, c, t, t / c) for k, (c, t) in agg.items()), key=lambda x: -x[2])
 
 
-def trace_summary(db_path: str, top: int = 25) -> str:
+def _grid_column(cols, axis):
+    for name in (f"grid_{axis}", f"grid_size_{axis}"):
+        if name in cols:
+            return cols.index(name)
+    return None
+
+
+def largest_launches(db_path: str, families):
+    """Per kernel of the given probe families: the launches at the largest
+    grid the kernel ran with (kernel, grid size, launches, average us)."""
+    db = sqlite3.connect(db_path)
+    cur = db.cursor()
+    cols = [r[1] for r in cur.execute("pragma table_info(kernels)")]
+    ni = cols.index("name") if "name" in cols else cols.index("kernel_name")
+    si, ei = cols.index("start"), cols.index("end")
+    gi = [g for g in (_grid_column(cols, a) for a in "xyz") if g is not None]
+    if not gi:
+        raise RuntimeError("no grid size column in the kernels table")
+    per = collections.defaultdict(lambda: collections.defaultdict(lambda: [0, 0.0]))
+    for r in cur.execute("select * from kernels"):
+        k = short_name(r[ni])
+        if family_of(k) not in families:
+            continue
+        grid = 1
+        for g in gi:
+            grid *= max(int(r[g] or 1), 1)
+        a = per[k][grid]
+        a[0] += 1
+        a[1] += (r[ei] - r[si]) / 1e3
+    db.close()
+    out = []
+    for k, by_grid in per.items():
+        grid = max(by_grid)
+        c, t = by_grid[grid]
+        out.append((k, grid, c, t / c))
+    return sorted(out, key=lambda x: (family_of(x[0]), -x[1]))
+
+
+def trace_summary(db_path: str, top: int = 25, largest=()) -> str:
     rows = kernel_stats(db_path)
     total = sum(r[2] for r in rows)
     lines = [f"total kernel time {total / 1e3:.2f} ms over {sum(r[1] for r in rows)} launches", "",
@@ -108,6 +148,10 @@ def trace_summary(db_path: str, top: int = 25) -> str:
     lines += ["", "| probe family | launches | total ms | avg us per launch |", "|---|---|---|---|"]
     for f, (c, t) in sorted(fam.items(), key=lambda kv: -kv[1][1]):
         lines.append(f"| {f} | {c} | {t / 1e3:.2f} | {t / c:.2f} |")
+    if largest:
+        lines += ["", "| kernel at its largest grid | grid size | launches | avg us |", "|---|---|---|---|"]
+        for k, g, c, a in largest_launches(db_path, largest):
+            lines.append(f"| `{k}` | {g} | {c} | {a:.2f} |")
     return "\n".join(lines)
 
 
@@ -157,6 +201,7 @@ def main(argv=None) -> int:
     t = sub.add_parser("trace")
     t.add_argument("db")
     t.add_argument("--top", type=int, default=25)
+    t.add_argument("--largest", default="", help="comma-separated probe families")
     c = sub.add_parser("traffic")
     c.add_argument("fetch_csv")
     c.add_argument("write_csv")
@@ -164,7 +209,8 @@ def main(argv=None) -> int:
     c.add_argument("--command", default="")
     a = ap.parse_args(argv)
     if a.cmd == "trace":
-        print(trace_summary(a.db, a.top))
+        fams = tuple(f for f in a.largest.split(",") if f)
+        print(trace_summary(a.db, a.top, fams))
     else:
         d = traffic(a.fetch_csv, a.write_csv)
         d["source_sha256"] = source_hash()

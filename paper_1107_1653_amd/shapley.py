@@ -35,7 +35,7 @@ EXPORTED = [
     "shapley_game_destroy",
     "shapley_solve_batch", "shapley_server_create", "shapley_server_submit", "shapley_server_wait",
     "shapley_server_poll", "shapley_server_step", "shapley_server_destroy",
-    "shapley_probe_enable", "shapley_probe_read",
+    "shapley_probe_enable", "shapley_probe_read", "shapley_probe_read_large",
 ]
 PROBE = dict(smooth=0, resid64=1, improve=2, resid=3, restrict=4, prolong=5, rap=6, interp=7, tail=8)
 
@@ -130,6 +130,8 @@ def lib() -> C.CDLL:
         L.shapley_probe_enable.argtypes = [C.c_int32, C.c_int32]
         L.shapley_probe_read.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                          C.POINTER(C.c_double)]
+        L.shapley_probe_read_large.argtypes = [C.c_int32, C.c_double, C.POINTER(C.c_int64),
+                                               C.POINTER(C.c_double), C.POINTER(C.c_double)]
         _lib_handle = L
     return _lib_handle
 
@@ -338,6 +340,13 @@ def shapley_probe_read(family) -> dict:
     fam = PROBE[family] if isinstance(family, str) else int(family)
     n, ms, b = C.c_int64(), C.c_double(), C.c_double()
     _check(lib().shapley_probe_read(fam, C.byref(n), C.byref(ms), C.byref(b)))
+    return dict(launches=n.value, ms=ms.value, bytes=b.value)
+
+
+def shapley_probe_read_large(family, frac: float = 0.5) -> dict:
+    fam = PROBE[family] if isinstance(family, str) else int(family)
+    n, ms, b = C.c_int64(), C.c_double(), C.c_double()
+    _check(lib().shapley_probe_read_large(fam, float(frac), C.byref(n), C.byref(ms), C.byref(b)))
     return dict(launches=n.value, ms=ms.value, bytes=b.value)
 
 

@@ -52,6 +52,22 @@ def test_default_options_match_header_documentation():
     assert ctypes.sizeof(P.shapley_solve_opts) == P.shapley_solve_opts.forcing.offset + 8
 
 
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_probe_arguments_are_checked():
+    # no launches probed: nothing touches a device
+    import paper_1107_1653_amd as P
+    P.shapley_probe_enable("smooth", True)
+    assert P.shapley_probe_read_large("smooth", 0.5) == dict(launches=0, ms=0.0, bytes=0.0)
+    for frac in (0.0, -1.0, 1.5, float("nan")):
+        with pytest.raises(P.ShapleyError):
+            P.shapley_probe_read_large("smooth", frac)
+    P.shapley_probe_enable("smooth", False)
+    lib = ctypes.CDLL(LIB)
+    n, ms, b = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    assert lib.shapley_probe_read_large(99, ctypes.c_double(0.5), ctypes.byref(n), ctypes.byref(ms),
+                                        ctypes.byref(b)) == P.SHAPLEY_EINVAL
+
+
 def test_bench_refuses_more_than_one_gpu():
     out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                          capture_output=True, text=True, timeout=120)

@@ -75,11 +75,18 @@ def test_traffic_needs_the_calibration_kernel(tmp_path):
 def test_trace_summary_counts_launches_per_family(tmp_path):
     db = tmp_path / "t.db"
     con = sqlite3.connect(db)
-    con.execute("create table kernels (name text, start integer, end integer)")
+    con.execute("create table kernels (name text, start integer, end integer, grid_size_x integer, "
+                "grid_size_y integer, grid_size_z integer)")
     rows = [("void shp::k_tail<double>(int)", 0, 20000), ("void shp::k_tail<double>(int)", 30000, 70000),
             ("void shp::k_rap_small<1>(int)", 0, 5000), ("void shp::k_rap_list<128, 1>(int)", 6000, 8000),
             ("shp::k_drap_ap<false, 2048>(int)", 0, 1000), ("shp::k_drap_known(int)", 1000, 4000)]
-    con.executemany("insert into kernels values (?, ?, ?)", rows)
+    rows = [r + (256, 1, 1) for r in rows]
+    # a streaming kernel on two levels: its largest grid is the finest level
+    rows += [("void shp::k_smooth<double, 4>(int)", 0, 30000, 4 << 20, 1, 1),
+             ("void shp::k_smooth<double, 4>(int)", 0, 34000, 4 << 20, 1, 1),
+             ("void shp::k_smooth<double, 4>(int)", 0, 9000, 1 << 20, 1, 1),
+             ("void shp::k_smooth<double, 16>(int)", 0, 2000, 1 << 18, 1, 1)]
+    con.executemany("insert into kernels values (?, ?, ?, ?, ?, ?)", rows)
     con.commit()
     con.close()
     stats = {k: (c, t) for k, c, t, _ in rs.kernel_stats(str(db))}
@@ -94,6 +101,10 @@ def test_trace_summary_counts_launches_per_family(tmp_path):
     # rap: the wavefront kernel and the dense AP start launches (2); the list
     # kernel and the dense R(AP) pass continue them; 11 us in all
     assert fam["rap"] == (2, pytest.approx(0.011, abs=0.005), pytest.approx(5.5))  # total printed to 0.01 ms
+    big = {k: (g, c, a) for k, g, c, a in rs.largest_launches(str(db), ("smooth",))}
+    assert big == {"shp::k_smooth<double, 4>": (4 << 20, 2, pytest.approx(32.0)),
+                   "shp::k_smooth<double, 16>": (1 << 18, 1, pytest.approx(2.0))}
+    assert "| `shp::k_smooth<double, 4>` | 4194304 | 2 | 32.00 |" in rs.trace_summary(str(db), largest=("smooth",))
 
 
 def test_bench_reports_no_traffic_for_changed_sources(tmp_path, monkeypatch):
