@@ -756,8 +756,14 @@ __global__ void k_pt_fill(const Tile* __restrict__ tiles, const int* __restrict_
 constexpr int kRapRCap = 256;      // max entries of one R row
 constexpr int kRapHash = 2048;     // hash slots (>= 2 x products when possible)
 constexpr int kRapND = kRapMaxCols;  // max distinct columns of one coarse row
-constexpr int kRapChunk = 256;     // (R, A) pairs per product chunk
 enum { kRapFused = 0, kRapKnown = 1 };
+
+// LDS ordering between the lanes of one wavefront
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // ascending bitonic sort of one value per lane across a wavefront (64 lanes)
 __device__ inline void wave_sort64(int& key, double& val) {
@@ -846,6 +852,39 @@ __device__ inline int rap_locate(const int* rO, int P, int f) {
   return lo;
 }
 
+// The cnt (1..64) queued products at queue counter head (positions qpos,
+// values qval, ring of mask + 1 entries) into the sums acc[position]: the run
+// is sorted by (position, queue order) on keys alone, and the first product
+// of each position adds the position's products of the run to its sum one
+// after the other, so each sum takes its products in queue order.  Positions
+// of one run are owned by this wavefront alone.
+__device__ __forceinline__ void rap_run(int cnt, int head, const int* __restrict__ qpos,
+                                        const double* __restrict__ qval, int mask, double* __restrict__ acc) {
+  const int lane = threadIdx.x & 63;
+  const int idx = (head + lane) & mask;
+  const bool live = lane < cnt;
+  const double v = live ? qval[idx] : 0.0;
+  int key = live ? (qpos[idx] << 6) | lane : INT_MAX;
+  wave_sort64(key);
+  const double x = __shfl(v, key & 63);  // the product now at this lane
+  const int pos = key >> 6;
+  const int prev = __shfl_up(pos, 1);
+  const bool first = lane == 0 || prev != pos;
+  const bool edge = key != INT_MAX && first;  // first product of a position
+  const unsigned long long bounds = __ballot(first);
+  const unsigned long long above = lane == 63 ? 0ull : (bounds >> (lane + 1));
+  const int len = above ? __ffsll((long long)above) : 64 - lane;
+  int most = edge ? len : 0;
+  for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o));
+  double sum = edge ? acc[pos] : 0.0;
+  for (int j = 0; j < most; ++j) {
+    const double y = __shfl(x, lane + j);
+    if (edge && j < len) sum += y;
+  }
+  if (edge) acc[pos] = sum;
+  wave_lds_sync();
+}
+
 // upper bound of the distinct columns of each coarse row: min(PW x pairs, kRapND)
 __global__ void k_rap_bound(int nc, const int* __restrict__ rrp, const int* __restrict__ rci,
                             const int* __restrict__ rp, int* __restrict__ ub) {
@@ -862,6 +901,15 @@ __global__ void k_rap_bound(int nc, const int* __restrict__ rrp, const int* __re
   ub[I] = (int)(b < kRapND ? b : kRapND);
 }
 
+// One coarse row I of R A P by a workgroup of NT lanes (rows too long for
+// one wavefront).  The (R, A) pairs are taken NT at a time, one per lane; the
+// lanes' nonzero products r_Ii a_ik p_kJ are stored in generation order (R's
+// row, A's row, P's slots) by a workgroup scan; wavefront w then queues, in
+// that order, the products of its own range of output positions and adds
+// them to their sums run by run (rap_run).  Every sum takes its products in
+// generation order, as in k_rap_small: the two kernels agree bit for bit.
+constexpr int kRapRing = 128;  // per-wavefront queue: < 64 left over + <= 64 new
+
 template <int NT, int MODE>
 __device__ __forceinline__ void rap_row(int I, const int* __restrict__ rrp, const int* __restrict__ rci,
                                         const double* __restrict__ rv, const int* __restrict__ rp,
@@ -871,22 +919,25 @@ __device__ __forceinline__ void rap_row(int I, const int* __restrict__ rrp, cons
                                         int* __restrict__ tcol, double* __restrict__ tval,
                                         const int* __restrict__ crp, const int* __restrict__ cci,
                                         double* __restrict__ cval, int* __restrict__ err) {
+  constexpr int W = NT / 64;
+  constexpr int CP = NT * PW;  // products of one chunk at most
+  constexpr int UB = (kRapHash / 2 > CP) ? kRapHash / 2 : CP;
+  static_assert(kRapRing >= 127 && (kRapRing & (kRapRing - 1)) == 0, "queue too small");
   __shared__ int rS[kRapRCap];
   __shared__ int rO[kRapRCap + 1];
   __shared__ double rV[kRapRCap];
-  __shared__ double ubuf[kRapHash / 2];  // hash table, later the product values
+  __shared__ double ubuf[UB];  // hash table, later the chunk's product values
+  __shared__ int cpos[CP];     // output position of each product of the chunk
   __shared__ int lst[kRapND];
-  __shared__ int skey[kRapChunk * PW];  // (position << 10 | slot) of each product
+  __shared__ double acc[kRapND];
+  __shared__ int qpos[W][kRapRing];
+  __shared__ double qval[W][kRapRing];
+  __shared__ int wsum[W];
   __shared__ int nd_sh;
   int* tab = reinterpret_cast<int*>(ubuf);
-  double* pval = ubuf;
+  double* cv = ubuf;
   const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  // output column at position pos is owned by lane pos % NT, register pos / NT
-  constexpr int R = kRapND / NT;
-  double reg[R];
-#pragma unroll
-  for (int j = 0; j < R; ++j) reg[j] = 0.0;
+  const int lane = tid & 63, w = tid >> 6;
   const int p0 = rrp[I], P = rrp[I + 1] - p0;
   if (P > kRapRCap) {
     if (tid == 0) {
@@ -967,7 +1018,7 @@ __device__ __forceinline__ void rap_row(int I, const int* __restrict__ rrp, cons
         if (lane < nd) lst[lane] = key;
       }
       __syncthreads();
-      P2 = 1;  // nothing left for the block-wide network below
+      P2 = 1;  // nothing left for the workgroup network below
     }
     for (int h = nd + tid; h < P2; h += NT) lst[h] = INT_MAX;
     __syncthreads();
@@ -993,71 +1044,83 @@ __device__ __forceinline__ void rap_row(int I, const int* __restrict__ rrp, cons
     }
     for (int h = tid; h < nd; h += NT) lst[h] = cci[base + h];
   }
-  __syncthreads();
-  for (int f0 = 0; f0 < E; f0 += kRapChunk) {
-    const int fe = (E < f0 + kRapChunk) ? E : f0 + kRapChunk;
-    for (int f = f0 + tid; f < fe; f += NT) {
+  for (int h = tid; h < nd; h += NT) acc[h] = 0.0;
+  __syncthreads();  // the hash table is dead: its space holds chunk products
+  const int own0 = (int)((long long)nd * w / W), own1 = (int)((long long)nd * (w + 1) / W);
+  int* myq = qpos[w];
+  double* myv = qval[w];
+  int head = 0, tail = 0;  // this wavefront's queue counters
+  for (int f0 = 0; f0 < E; f0 += NT) {
+    const int f = f0 + tid;
+    int np[PW];
+    double nv[PW];
+    unsigned valid = 0;  // bit q: slot q has a product
+    if (f < E && nd > 0) {
       const int p = rap_locate(rO, P, f);
       const int e = rS[p] + (f - rO[p]);
       const int k = ci[e];
       const double ra = rV[p] * a[e];
-      for (int q = 0; q < PW; ++q) {
-        const int slot = (f - f0) * PW + q;
-        const int J = pc[(size_t)k * PW + q];
-        int key = INT_MAX;
-        double val = 0.0;
-        if (J >= 0 && nd > 0) {
-          int lo = 0, hi = nd - 1;
-          while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (lst[mid] < J) lo = mid + 1; else hi = mid;
-          }
-          if (lst[lo] == J) {
-            key = (lo << 10) | slot;
-            val = ra * pv[(size_t)k * PW + q];
-          }
-        }
-        skey[slot] = key;
-        pval[slot] = val;
-      }
-    }
-    // products sorted by (output position, slot) within runs of 64 slots
-    // (one wavefront sorts a run in registers); each output column's
-    // products of a run are then contiguous, in slot order, and its owner
-    // adds them run by run, i.e. in slot order (the same order for any
-    // launch shape)
-    const int ns = (fe - f0) * PW;
-    const int nruns = (ns + 63) >> 6;
-    __syncthreads();
-    for (int r = tid >> 6; r < nruns; r += NT / 64) {
-      const int sl = (r << 6) + lane;
-      int key = sl < ns ? skey[sl] : INT_MAX;
-      double val = sl < ns ? pval[sl] : 0.0;
-      wave_sort64(key, val);
-      skey[sl] = key;  // sl < 64 * nruns <= kRapChunk * PW
-      pval[sl] = val;
-    }
-    __syncthreads();
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-      const int pos = j * NT + tid;
-      if (pos < nd) {
-        const int k0 = pos << 10, k1 = (pos + 1) << 10;
-        double acc = reg[j];
-        for (int r = 0; r < nruns; ++r) {
-          const int b = r << 6;
-          int lo = 0, hi = 64;  // first index of the run with key >= k0
-          while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (skey[b + mid] < k0) lo = mid + 1; else hi = mid;
-          }
-          for (int t = b + lo; t < b + 64 && skey[t] < k1; ++t) acc += pval[t];
+      for (int q = 0; q < PW; ++q) {
+        np[q] = 0;
+        nv[q] = 0.0;
+        const int J = pc[(size_t)k * PW + q];
+        if (J < 0) continue;
+        int lo = 0, hi = nd - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (lst[mid] < J) lo = mid + 1; else hi = mid;
         }
-        reg[j] = acc;
+        if (lst[lo] == J) {
+          np[q] = lo;
+          nv[q] = ra * pv[(size_t)k * PW + q];
+          valid |= 1u << q;
+        }
       }
     }
+    const int n_new = __popc(valid);
+    int incl = n_new;  // chunk offsets in (pair, slot) order: workgroup scan
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[w] = incl;
     __syncthreads();
+    int at = incl - n_new, total = 0;
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+      if (u < w) at += wsum[u];
+      total += wsum[u];
+    }
+#pragma unroll
+    for (int q = 0; q < PW; ++q)
+      if (valid >> q & 1u) {
+        const int o = at + __popc(valid & ((1u << q) - 1u));
+        cpos[o] = np[q];
+        cv[o] = nv[q];
+      }
+    __syncthreads();
+    for (int base = 0; base < total; base += 64) {  // this wavefront's products, in order
+      const int t = base + lane;
+      const int pp = t < total ? cpos[t] : -1;
+      const bool mine = pp >= own0 && pp < own1;
+      const unsigned long long m = __ballot(mine);
+      if (mine) {
+        const int idx = (tail + __popcll(m & ((1ull << lane) - 1ull))) & (kRapRing - 1);
+        myq[idx] = pp;
+        myv[idx] = cv[t];
+      }
+      tail += __popcll(m);
+      wave_lds_sync();
+      if (tail - head >= 64) {
+        rap_run(64, head, myq, myv, kRapRing - 1, acc);
+        head += 64;
+      }
+    }
+    __syncthreads();  // the next chunk overwrites the products and wsum
   }
+  if (tail > head) rap_run(tail - head, head, myq, myv, kRapRing - 1, acc);
+  __syncthreads();
   if (MODE == kRapFused) {
     const int o = toff[I];
     const int cap = toff[I + 1] - o;
@@ -1065,20 +1128,14 @@ __device__ __forceinline__ void rap_row(int I, const int* __restrict__ rrp, cons
       if (tid == 0) { atomicOr(err, 4); tcnt[I] = 0; }
       return;
     }
-    for (int h = tid; h < nd; h += NT) tcol[o + h] = lst[h];
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      const int h = j * NT + tid;
-      if (h < nd) tval[o + h] = reg[j];
+    for (int h = tid; h < nd; h += NT) {
+      tcol[o + h] = lst[h];
+      tval[o + h] = acc[h];
     }
     if (tid == 0) tcnt[I] = nd;
   } else {
     const int base = crp[I];
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      const int h = j * NT + tid;
-      if (h < nd) cval[base + h] = reg[j];
-    }
+    for (int h = tid; h < nd; h += NT) cval[base + h] = acc[h];
   }
 }
 
@@ -1117,12 +1174,6 @@ __global__ __launch_bounds__(NT) void k_rap_list(const int* __restrict__ big, co
   }
 }
 
-// LDS ordering between the lanes of one wavefront
-__device__ inline void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // ---------------------------------------------------------------------------
 // Galerkin product of small levels through dense per-game blocks.  The coarse
@@ -1431,35 +1482,11 @@ __global__ __launch_bounds__(256) void k_rap_small(int nc, const int* __restrict
   for (int h = lane; h < nd; h += 64) acc[h] = 0.0;
   wave_lds_sync();  // the hash table is dead: its space queues products
   int head = 0, tail = 0;  // queue counters (indices modulo kSmRing)
-  // the cnt (1..64) products at the head of the queue into the sums
-  auto run = [&](int cnt) {
-    const int idx = (head + lane) & (kSmRing - 1);
-    const bool live = lane < cnt;
-    const double v = live ? qval[idx] : 0.0;
-    int key = live ? (qpos[idx] << 6) | lane : INT_MAX;
-    wave_sort64(key);
-    const double x = __shfl(v, key & 63);  // the product now at this lane
-    const int pos = key >> 6;
-    const int prev = __shfl_up(pos, 1);
-    const bool edge = key != INT_MAX && (lane == 0 || prev != pos);  // first product of a column
-    const unsigned long long bounds = __ballot(edge || (key == INT_MAX && (lane == 0 || prev != pos)));
-    const unsigned long long above = lane == 63 ? 0ull : (bounds >> (lane + 1));
-    const int len = above ? __ffsll((long long)above) : 64 - lane;
-    int most = edge ? len : 0;
-    for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o));
-    double sum = edge ? acc[pos] : 0.0;
-    for (int j = 0; j < most; ++j) {
-      const double y = __shfl(x, lane + j);
-      if (edge && j < len) sum += y;
-    }
-    if (edge) acc[pos] = sum;
-    head += cnt;
-    wave_lds_sync();
-  };
   for (int g0 = 0; g0 < E; g0 += 32) {
     const int f = g0 + (lane >> 1);
-    int n_new = 0, np[2];
-    double nv[2];
+    int np[2] = {0, 0};
+    double nv[2] = {0.0, 0.0};
+    unsigned valid = 0;  // bit u: slot 2 (lane & 1) + u has a product
     if (f < E && nd > 0) {
       const int p = rap_locate(rO, P, f);
       const int e = rS[p] + (f - rO[p]);
@@ -1476,27 +1503,33 @@ __global__ __launch_bounds__(256) void k_rap_small(int nc, const int* __restrict
           if (lst[mid] < J) lo = mid + 1; else hi = mid;
         }
         if (lst[lo] == J) {
-          np[n_new] = lo;
-          nv[n_new] = ra * pv[(size_t)k * PW + q];
-          ++n_new;
+          np[u] = lo;
+          nv[u] = ra * pv[(size_t)k * PW + q];
+          valid |= 1u << u;
         }
       }
     }
+    const int n_new = __popc(valid);
     int incl = n_new;  // queue offsets in (pair, slot) order
     for (int o = 1; o < 64; o <<= 1) {
       const int y = __shfl_up(incl, o);
       if (lane >= o) incl += y;
     }
     const int at = tail + incl - n_new;
-    for (int u = 0; u < n_new; ++u) {
-      qpos[(at + u) & (kSmRing - 1)] = np[u];
-      qval[(at + u) & (kSmRing - 1)] = nv[u];
+    if (valid & 1u) {
+      qpos[at & (kSmRing - 1)] = np[0];
+      qval[at & (kSmRing - 1)] = nv[0];
+    }
+    if (valid & 2u) {
+      const int o = (at + (valid & 1u)) & (kSmRing - 1);
+      qpos[o] = np[1];
+      qval[o] = nv[1];
     }
     tail += __shfl(incl, 63);
     wave_lds_sync();
-    while (tail - head >= 64) run(64);
+    for (; tail - head >= 64; head += 64) rap_run(64, head, qpos, qval, kSmRing - 1, acc);
   }
-  if (tail > head) run(tail - head);
+  if (tail > head) rap_run(tail - head, head, qpos, qval, kSmRing - 1, acc);
   if (MODE == kRapFused) {
     const int o = toff[I];
     for (int h = lane; h < nd; h += 64) {
