@@ -183,29 +183,27 @@ __global__ void k_gather_int(const int* __restrict__ src, const int* __restrict_
 // The PW largest weights are kept and rescaled to preserve the row sum.
 // ---------------------------------------------------------------------------
 constexpr int kIThreads = 64;
-constexpr int kIChat = 32;
+constexpr int kIChat = 32;       // set cap of the interpolation formula
+constexpr int kIChatSmall = 16;  // first pass (grid stencils of 2-D problems fit)
 
-__global__ __launch_bounds__(kIThreads) void k_interp_lds(const Tile* __restrict__ tiles, const int* __restrict__ rp,
-                                                          const int* __restrict__ ci, const double* __restrict__ a,
-                                                          const double* __restrict__ dinv,
-                                                          const uint8_t* __restrict__ strong,
-                                                          const int8_t* __restrict__ cf, const int* __restrict__ cidx,
-                                                          const uint8_t* __restrict__ dir, int* __restrict__ pc,
-                                                          double* __restrict__ pv, int* __restrict__ capped) {
-  __shared__ int lc[kIChat * kIThreads];
-  __shared__ double lw[kIChat * kIThreads];
-  // kTileRows / kIThreads blocks share one tile, each taking kIThreads rows
-  const Tile t = tiles[blockIdx.x / (kTileRows / kIThreads)];
-  const int sub = blockIdx.x % (kTileRows / kIThreads);
-  const int tid = threadIdx.x;
-  int* C = lc + tid;      // entry p at C[p * kIThreads]
-  double* Wt = lw + tid;
-  for (int i = t.r0 + sub * kIThreads + tid; i < t.r1 && i < t.r0 + (sub + 1) * kIThreads; i += kIThreads) {
+// Row i.  The set lives in this thread's column of the block's LDS arrays (C,
+// Wt: entry p at [p * kIThreads]).  DEFER: a row whose set would exceed CAP
+// is appended to defer[1 ..] for the kIChat instance instead of being capped;
+// any other row is computed exactly as by that instance.
+template <int CAP, bool DEFER>
+__device__ __forceinline__ void interp_lds_row(int i, int* C, double* Wt, const int* __restrict__ rp,
+                                               const int* __restrict__ ci, const double* __restrict__ a,
+                                               const double* __restrict__ dinv, const uint8_t* __restrict__ strong,
+                                               const int8_t* __restrict__ cf, const int* __restrict__ cidx,
+                                               const uint8_t* __restrict__ dir, int* __restrict__ pc,
+                                               double* __restrict__ pv, int* __restrict__ capped,
+                                               int* __restrict__ defer) {
+  {
     int* pci = pc + (size_t)i * PW;
     double* pvi = pv + (size_t)i * PW;
     for (int q = 0; q < PW; ++q) { pci[q] = -1; pvi[q] = 0.0; }
-    if (cf[i] == CF_C) { pci[0] = cidx[i]; pvi[0] = 1.0; continue; }
-    if (dir[i]) continue;
+    if (cf[i] == CF_C) { pci[0] = cidx[i]; pvi[0] = 1.0; return; }
+    if (dir[i]) return;
     int n = 0;
     bool full = false;
     auto find = [&](int v) -> int {
@@ -215,7 +213,7 @@ __global__ __launch_bounds__(kIThreads) void k_interp_lds(const Tile* __restrict
     };
     auto add = [&](int v) {
       if (find(v) >= 0) return;
-      if (n >= kIChat) { full = true; return; }
+      if (n >= CAP) { full = true; return; }
       C[n * kIThreads] = v;
       Wt[n * kIThreads] = 0.0;
       ++n;
@@ -235,8 +233,14 @@ __global__ __launch_bounds__(kIThreads) void k_interp_lds(const Tile* __restrict
         if (strong[e2] && cf[l] == CF_C) add(l);
       }
     }
-    if (full) atomicAdd(capped, 1);
-    if (n == 0) continue;
+    if (full) {
+      if (DEFER) {
+        defer[1 + atomicAdd(defer, 1)] = i;
+        return;
+      }
+      atomicAdd(capped, 1);
+    }
+    if (n == 0) return;
     double dd = aii;
     for (int e = e0; e < e1; ++e) {
       const int j = ci[e];
@@ -273,7 +277,7 @@ __global__ __launch_bounds__(kIThreads) void k_interp_lds(const Tile* __restrict
       if (dir[j]) continue;  // Dirichlet neighbour: its error vanishes after relaxation
       dd += aij;             // weak connection: lumped into the diagonal
     }
-    if (dd == 0.0) continue;
+    if (dd == 0.0) return;
     double total = 0.0;
     for (int p = 0; p < n; ++p) {
       const double w = -Wt[p * kIThreads] / dd;
@@ -312,6 +316,44 @@ __global__ __launch_bounds__(kIThreads) void k_interp_lds(const Tile* __restrict
     }
     for (int q = 0; q < nk; ++q) { pci[q] = kc[q]; pvi[q] = kw[q] * sc; }
   }
+}
+
+// one thread per row of the tiles (kTileRows / kIThreads blocks per tile)
+template <int CAP, bool DEFER>
+__global__ __launch_bounds__(kIThreads) void k_interp_lds(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                                                          const int* __restrict__ ci, const double* __restrict__ a,
+                                                          const double* __restrict__ dinv,
+                                                          const uint8_t* __restrict__ strong,
+                                                          const int8_t* __restrict__ cf, const int* __restrict__ cidx,
+                                                          const uint8_t* __restrict__ dir, int* __restrict__ pc,
+                                                          double* __restrict__ pv, int* __restrict__ capped,
+                                                          int* __restrict__ defer) {
+  __shared__ int lc[CAP * kIThreads];
+  __shared__ double lw[CAP * kIThreads];
+  const Tile t = tiles[blockIdx.x / (kTileRows / kIThreads)];
+  const int sub = blockIdx.x % (kTileRows / kIThreads);
+  const int i = t.r0 + sub * kIThreads + (int)threadIdx.x;
+  if (i >= t.r1) return;
+  interp_lds_row<CAP, DEFER>(i, lc + threadIdx.x, lw + threadIdx.x, rp, ci, a, dinv, strong, cf, cidx, dir, pc, pv,
+                             capped, defer);
+}
+
+// the rows deferred by the small-set instance, one thread each
+__global__ __launch_bounds__(kIThreads) void k_interp_lds_list(const int* __restrict__ list,
+                                                               const int* __restrict__ rp, const int* __restrict__ ci,
+                                                               const double* __restrict__ a,
+                                                               const double* __restrict__ dinv,
+                                                               const uint8_t* __restrict__ strong,
+                                                               const int8_t* __restrict__ cf,
+                                                               const int* __restrict__ cidx,
+                                                               const uint8_t* __restrict__ dir, int* __restrict__ pc,
+                                                               double* __restrict__ pv, int* __restrict__ capped) {
+  __shared__ int lc[kIChat * kIThreads];
+  __shared__ double lw[kIChat * kIThreads];
+  const int cnt = list[0];
+  for (int k = blockIdx.x * kIThreads + (int)threadIdx.x; k < cnt; k += gridDim.x * kIThreads)
+    interp_lds_row<kIChat, false>(list[1 + k], lc + threadIdx.x, lw + threadIdx.x, rp, ci, a, dinv, strong, cf, cidx,
+                                  dir, pc, pv, capped, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -2459,9 +2501,16 @@ void amg_interp(const Tile* t, int nt, const int* rp, const int* ci, const doubl
     SHP_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_interp_wave_list<512, 128>), dim3(std::max(1, std::min(rows, 2048))), dim3(64), 0, s, defer,
                        rp, ci, a, dinv, strong, cf, cidx, dir, pc, pv, capped);
-  } else
-    hipLaunchKernelGGL(k_interp_lds, dim3(nt * (kTileRows / kIThreads)), dim3(kIThreads), 0, s, t, rp, ci, a,
-                       dinv, strong, cf, cidx, dir, pc, pv, capped);
+  } else {
+    // the small set first (twice the wavefronts per CU), then the rows it
+    // could not hold
+    fill_async(defer, 0, 1, s);
+    hipLaunchKernelGGL((k_interp_lds<kIChatSmall, true>), dim3(nt * (kTileRows / kIThreads)), dim3(kIThreads), 0, s,
+                       t, rp, ci, a, dinv, strong, cf, cidx, dir, pc, pv, capped, defer);
+    SHP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_interp_lds_list, dim3(std::max(1, std::min((rows + kIThreads - 1) / kIThreads, 1024))),
+                       dim3(kIThreads), 0, s, defer, rp, ci, a, dinv, strong, cf, cidx, dir, pc, pv, capped);
+  }
   SHP_LAUNCH_CHECK();
 }
 void amg_pt_count(const Tile* t, int nt, const int* pc, int* cnt, hipStream_t s) {
