@@ -371,8 +371,8 @@ __global__ __launch_bounds__(kIThreads) void k_interp_lds_list(const int* __rest
 // neighbours lumped) and is counted in `capped`.
 // ---------------------------------------------------------------------------
 // HASH: slots for the interpolatory set of one row; KCAP: strong F
-// neighbours of one row; (k, entry) pairs are staged kIwStage at a time.
-constexpr int kIwStage = 256;
+// neighbours of one row; STAGE: (k, entry) pairs staged at a time (the sums
+// take their terms in the same order for any STAGE).
 
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -383,7 +383,7 @@ __device__ inline double wave_sum(double v) {
 // defer[0]) and left to a larger instance, instead of falling back to direct
 // interpolation; the larger instance then computes exactly what it computes
 // for any row.
-template <int kIwHash, int kIwK, bool DEFER>
+template <int kIwHash, int kIwK, int STAGE, bool DEFER>
 __device__ __forceinline__ void interp_row(int i, const int* __restrict__ rp, const int* __restrict__ ci,
                                            const double* __restrict__ a, const double* __restrict__ dinv,
                                            const uint8_t* __restrict__ strong, const int8_t* __restrict__ cf,
@@ -397,8 +397,8 @@ __device__ __forceinline__ void interp_row(int i, const int* __restrict__ rp, co
   __shared__ int kcol[kIwK], kbeg[kIwK], koff[kIwK + 1];
   __shared__ double kaik[kIwK], kden[kIwK], kabi[kIwK];
   __shared__ uint8_t kneg[kIwK];
-  __shared__ int sq[kIwStage];
-  __shared__ double sc[kIwStage];
+  __shared__ int sq[STAGE];
+  __shared__ double sc[STAGE];
   __shared__ int full_sh;
 
   const int lane = threadIdx.x;
@@ -561,8 +561,8 @@ __device__ __forceinline__ void interp_row(int i, const int* __restrict__ rp, co
     }
     __syncthreads();
     // ---- den_k and abar_ki: terms of each pair staged, summed per k in row order
-    for (int c0 = 0; c0 < T; c0 += kIwStage) {
-      const int c1 = (T < c0 + kIwStage) ? T : c0 + kIwStage;
+    for (int c0 = 0; c0 < T; c0 += STAGE) {
+      const int c1 = (T < c0 + STAGE) ? T : c0 + STAGE;
       for (int f = c0 + lane; f < c1; f += 64) {
         const int p = seg(f);
         const int e2 = kbeg[p] + (f - koff[p]);
@@ -625,8 +625,8 @@ __device__ __forceinline__ void interp_row(int i, const int* __restrict__ rp, co
     __syncthreads();
     // ---- distributed entries: F neighbours in row order; each row k holds a
     //      column at most once, so the lanes of one k never collide
-    for (int c0 = 0; c0 < T; c0 += kIwStage) {
-      const int c1 = (T < c0 + kIwStage) ? T : c0 + kIwStage;
+    for (int c0 = 0; c0 < T; c0 += STAGE) {
+      const int c1 = (T < c0 + STAGE) ? T : c0 + STAGE;
       for (int f = c0 + lane; f < c1; f += 64) {
         const int p = seg(f);
         const int e2 = kbeg[p] + (f - koff[p]);
@@ -719,7 +719,7 @@ __device__ __forceinline__ void interp_row(int i, const int* __restrict__ rp, co
 }
 
 // one wavefront per row of the tiles
-template <int kIwHash, int kIwK, bool DEFER>
+template <int kIwHash, int kIwK, int STAGE, bool DEFER>
 __global__ __launch_bounds__(64) void k_interp_wave(const Tile* __restrict__ tiles, const int* __restrict__ rp,
                                                     const int* __restrict__ ci, const double* __restrict__ a,
                                                     const double* __restrict__ dinv,
@@ -731,7 +731,7 @@ __global__ __launch_bounds__(64) void k_interp_wave(const Tile* __restrict__ til
   const Tile t = tiles[blockIdx.x / kTileRows];
   const int i = t.r0 + (int)(blockIdx.x % kTileRows);
   if (i >= t.r1) return;
-  interp_row<kIwHash, kIwK, DEFER>(i, rp, ci, a, dinv, strong, cf, cidx, dir, pc, pv, capped, defer);
+  interp_row<kIwHash, kIwK, STAGE, DEFER>(i, rp, ci, a, dinv, strong, cf, cidx, dir, pc, pv, capped, defer);
 }
 
 // the rows deferred by the smaller instance, one wavefront each in turn
@@ -745,7 +745,8 @@ __global__ __launch_bounds__(64) void k_interp_wave_list(const int* __restrict__
                                                          double* __restrict__ pv, int* __restrict__ capped) {
   const int cnt = list[0];
   for (int k = blockIdx.x; k < cnt; k += gridDim.x) {
-    interp_row<kIwHash, kIwK, false>(list[1 + k], rp, ci, a, dinv, strong, cf, cidx, dir, pc, pv, capped, nullptr);
+    interp_row<kIwHash, kIwK, 256, false>(list[1 + k], rp, ci, a, dinv, strong, cf, cidx, dir, pc, pv, capped,
+                                          nullptr);
     __syncthreads();  // the next row reuses the LDS
   }
 }
@@ -2490,13 +2491,13 @@ void amg_interp(const Tile* t, int nt, const int* rp, const int* ci, const doubl
                 double* pv, int* capped, int wave, int* defer, int rows, hipStream_t s) {
   if (!nt) return;
   if (wave == 2)
-    hipLaunchKernelGGL((k_interp_wave<1024, 256, false>), dim3(nt * kTileRows), dim3(64), 0, s, t, rp, ci, a, dinv,
-                       strong, cf, cidx, dir, pc, pv, capped, (int*)nullptr);
+    hipLaunchKernelGGL((k_interp_wave<1024, 256, 256, false>), dim3(nt * kTileRows), dim3(64), 0, s, t, rp, ci, a,
+                       dinv, strong, cf, cidx, dir, pc, pv, capped, (int*)nullptr);
   else if (wave == 1) {
-    // a small instance (twice the wavefronts per CU) for all rows, then the
-    // rows it could not hold
+    // a small instance (about 5 KB of LDS per row: twice the rows per CU of
+    // the next size) for all rows, then the rows it could not hold
     fill_async(defer, 0, 1, s);
-    hipLaunchKernelGGL((k_interp_wave<256, 64, true>), dim3(nt * kTileRows), dim3(64), 0, s, t, rp, ci, a, dinv,
+    hipLaunchKernelGGL((k_interp_wave<128, 32, 128, true>), dim3(nt * kTileRows), dim3(64), 0, s, t, rp, ci, a, dinv,
                        strong, cf, cidx, dir, pc, pv, capped, defer);
     SHP_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_interp_wave_list<512, 128>), dim3(std::max(1, std::min(rows, 2048))), dim3(64), 0, s, defer,
