@@ -105,7 +105,7 @@ void launch_scatter_v(const GameDesc* d, const GTile* t, int nt, const int* acti
 }
 
 // ---------------------------------------------------------------------------
-// K1: policy-system assembly.  Row x of A = I - mu M^{alpha beta} and
+// Policy-system assembly.  Row x of A = I - mu M^{alpha beta} and
 // b = r^{alpha beta} (Sec. 4.2, eq. (LSPI)), written into the fixed level-0
 // pattern of the game (explicit zeros where the chosen row has no entry).
 // ---------------------------------------------------------------------------
@@ -181,7 +181,7 @@ void launch_assemble(const GameDesc* d, const GTile* t, int nt, const int* activ
 }
 
 // ---------------------------------------------------------------------------
-// K14 + K15: policy improvement and Shapley residual in one sweep.
+// Policy improvement and Shapley residual in one sweep.
 //   Q(x,a,b) = r(x,a,b) + mu sum_y w(y|x,a,b) v(y)   (the bracket of eq. (eq1))
 //   beta_in(x)  : MIN's improvement at alpha(x)       (Algorithm algo-MDP, step 2)
 //   F(x)        : max_a min_b Q                        (eq. (eq1))
@@ -190,8 +190,12 @@ void launch_assemble(const GameDesc* d, const GTile* t, int nt, const int* activ
 // Ties: the incumbent is kept unless another action is better by more than
 // tie_rtol times the rounding scale |r| + mu sum |w v| of the compared rows;
 // otherwise the lowest index attaining the extremum is taken.
-// One thread per row computes Q into LDS; one thread per state reduces.
+// The products w v of the tile's entries (contiguous in the CSR) are formed
+// with coalesced loads, kImpStage at a time, into LDS; one thread per row then
+// adds its row's products in entry order into Q; one thread per state reduces.
 // ---------------------------------------------------------------------------
+constexpr int kImpStage = 1024;
+
 __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd,
                                                  const GTile* __restrict__ tiles,
                                                  const int* __restrict__ active, double tie_rtol,
@@ -199,22 +203,33 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
   __shared__ double sq[256];
   __shared__ double ss[256];
   __shared__ unsigned char sv[256];
+  __shared__ double sp[kImpStage];
   GTile t = tiles[blockIdx.x];
   if (active && !active[t.game]) return;
   const GameDesc d = gd[t.game];
   const int K = d.m1 * d.m2;
   const int ns = t.s1 - t.s0;
   const int tid = threadIdx.x;
-  if (tid < ns * K) {
-    int x = t.s0 + tid / K;
-    int row = x * K + tid % K;
-    bool ok = d.valid ? (d.valid[row] != 0) : true;
-    double acc = 0.0, sacc = 0.0;
-    for (int e = d.rp[row], e1 = d.rp[row + 1]; e < e1; ++e) {
-      double p = d.w[e] * d.v[d.ci[e]];
+  const int row0 = t.s0 * K;  // the tile's rows: row0 + [0, ns K)
+  const bool mine = tid < ns * K;
+  const int row = row0 + tid;
+  const int e0 = mine ? d.rp[row] : 0, e1 = mine ? d.rp[row + 1] : 0;
+  const int eb = d.rp[row0], ee = d.rp[row0 + ns * K];
+  double acc = 0.0, sacc = 0.0;
+  for (int c0 = eb; c0 < ee; c0 += kImpStage) {
+    const int c1 = ee < c0 + kImpStage ? ee : c0 + kImpStage;
+    for (int e = c0 + tid; e < c1; e += 256) sp[e - c0] = d.w[e] * d.v[d.ci[e]];
+    __syncthreads();
+    const int lo = e0 > c0 ? e0 : c0, hi = e1 < c1 ? e1 : c1;
+    for (int e = lo; e < hi; ++e) {
+      const double p = sp[e - c0];
       acc += p;
       sacc += fabs(p);
     }
+    __syncthreads();
+  }
+  if (mine) {
+    bool ok = d.valid ? (d.valid[row] != 0) : true;
     double rr = d.r[row];
     sq[tid] = rr + d.mu * acc;
     ss[tid] = fabs(rr) + d.mu * sacc;
@@ -381,7 +396,7 @@ void launch_apply(const GameDesc* d, const GTile* t, int nt, const int* decision
 }
 
 // ---------------------------------------------------------------------------
-// K16: FAMGpi transfers (Sec. 5.2).  Value interpolation I: multilinear on the
+// FAMGpi transfers (Sec. 5.2).  Value interpolation I: multilinear on the
 // coarse grid extended by its Dirichlet nodes (on nested dyadic grids this is
 // the paper's average of the coarse neighbours within distance h_l).
 // Strategy interpolation U: copy the coarse node at floor(i (s_c+1)/(s_f+1))
