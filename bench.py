@@ -231,6 +231,12 @@ def run_c1(args) -> int:
                         "alg_bytes_per_launch": r["bytes"] / r["launches"]}
     log("[bench] finest-level streaming kernels: " +
         ", ".join(f"{k} {v['achieved']:.0f} GB/s ({v['avg_launch_us']:.1f} us)" for k, v in streaming.items()))
+    # sizes of the finest grid's first AMG levels (the launches above)
+    first = P.shapley_hierarchy_level(H, 0, sizes_only=True)
+    fine_levels = []
+    for lvl in range(min(3, first["levels"])):
+        d = P.shapley_hierarchy_level(H, lvl, sizes_only=True)
+        fine_levels.append({"level": lvl, "n": int(d["n"]), "nnz": int(d["nnz"])})
     v64 = P.shapley_get_value(H)
     if not args.no_mixed:
         extra["mixed"]["max_abs_diff_vs_fp64"] = float(np.max(np.abs(vm - v64)))
@@ -282,9 +288,9 @@ def run_c1(args) -> int:
                   "cycle_ms": 1e3 * st["cycle_seconds"]},
         "roofline": roof,
         "streaming": {"peak": HBM_PEAK_GBS, "unit": "GB/s",
-                      "launches": "launches of at least half the largest algorithmic bytes of the family "
-                                  f"(level 0 of the {args.points}x{args.points} grid)",
-                      "kernels": streaming},
+                      "launches": "launches moving at least half the largest algorithmic bytes of the family "
+                                  f"(the first AMG levels of the {args.points}x{args.points} grid), HIP events",
+                      "levels": fine_levels, "kernels": streaming},
         "cpu_baseline": cpu,
         "extra": extra,
     }

@@ -48,8 +48,10 @@ _FAMILIES = (  # (substring of the kernel name, family); first match wins
 # kernels that complete a launch of their family rather than start one: the
 # Galerkin product of a large level is the wavefront kernel followed by the
 # workgroup kernel over the rows it left (one probe launch, two kernels); the
-# dense product of a small level starts with AP and continues with R (AP)
-_CONTINUATIONS = ("k_rap_list", "k_drap_ac", "k_drap_count", "k_drap_known")
+# dense product of a small level starts with AP and continues with R (AP);
+# interpolation redoes the rows its first pass deferred in a list kernel
+_CONTINUATIONS = ("k_rap_list", "k_drap_ac", "k_drap_count", "k_drap_known", "k_interp_wave_list",
+                  "k_interp_lds_list")
 
 
 def starts_launch(name: str) -> bool:

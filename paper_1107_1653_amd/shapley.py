@@ -259,12 +259,15 @@ def shapley_apply_operator(g, v):
     return F, a, b
 
 
-def shapley_hierarchy_level(g, level: int) -> dict:
+def shapley_hierarchy_level(g, level: int, sizes_only: bool = False) -> dict:
     """Level `level` of the AMG hierarchy of g's last solve: A (CSR arrays
-    rp, ci, a), P (pc, pv of shape (n, pw), only when nc > 0) and the sizes."""
+    rp, ci, a), P (pc, pv of shape (n, pw), only when nc > 0) and the sizes
+    (the sizes alone with sizes_only)."""
     info = shapley_level_info()
     _check(lib().shapley_hierarchy_level(g, int(level), C.byref(info), None, None, None, None, None))
     n, nnz, nc, pw = info.n, info.nnz, info.nc, info.pw
+    if sizes_only:
+        return {"levels": info.levels, "n": n, "nnz": nnz, "nc": nc, "pw": pw}
     rp = np.empty(n + 1, np.int32)
     ci = np.empty(max(nnz, 1), np.int32)
     a = np.empty(max(nnz, 1), np.float64)
