@@ -195,6 +195,16 @@ int shapley_game_info(shapley_game_t g, int64_t* n, int32_t* m1, int32_t* m2);
 /* Device bytes held by the handle. */
 int shapley_game_bytes(shapley_game_t g, size_t* bytes);
 
+/* Lanes per sparse row in the V-cycle's relaxation, residual and restriction
+ * kernels (Sec. 4.3, the multigrid cycle): 0 (default) lets the library time
+ * 1, 2 and 4 lanes on each large level at its first setup and keep the
+ * fastest per size class (levels under 2^18 entries take a rule on the
+ * average row length); 1, 2 or 4 forces that count for every level of later
+ * setups.  Row sums are formed in the same order for every count, so results
+ * do not depend on this setting.  Process-wide.  Errors: SHAPLEY_EINVAL for
+ * any other value. */
+int shapley_tune_lanes(int32_t lanes);
+
 /* Inspection of the algebraic multigrid hierarchy (Sec. 4.3) built by the
  * last shapley_solve of g, run alone on the handle's own stream (opts.stream
  * NULL; for a hierarchy handle, the finest grid's).  Level 0 is the operator

@@ -1959,12 +1959,16 @@ __global__ __launch_bounds__(NT) void k_dense_inv_reg(const int* __restrict__ bl
 // ---------------------------------------------------------------------------
 // cycle kernels (T = float for mixed precision, double for FP64 cycles)
 // ---------------------------------------------------------------------------
-// Sparse rows in the cycle kernels: G lanes per row (G = 1 for the short rows
-// of grid stencils, 4 or 16 for the longer rows of coarse levels).  Each lane
-// walks the row with stride G, loading kRowUnroll entries before using them
-// so that the column and value loads of several entries are in flight
-// together; partial sums are combined in a fixed order (deterministic).
-constexpr int kRowUnroll = 4;
+// Sparse rows in the cycle kernels: G lanes per row, G in {1, 2, 4}.
+// A row's sum does not depend on G: entry t of the row (t = 0, 1, ...) goes
+// to partial sum t mod kAcc, each partial sum adds its entries in order, and
+// the kAcc partial sums are combined by a fixed butterfly (v_u += v_{u+o} for
+// u < o, o = kAcc/2, ..., 1).  Lane gl holds the partial sums u = gl + G j; the
+// butterfly steps with o >= G run inside the lane, the others across lanes by
+// xor shuffles, with the same operands in the same order.  The lane count is
+// therefore a pure speed choice (tuned per level) and every row sum is the
+// same bit for bit whatever the batch.
+constexpr int kAcc = 4;
 
 // row r of a tile-based launch: G blocks share one tile of kTileRows rows
 template <int G>
@@ -1973,59 +1977,56 @@ __device__ inline int tile_row(const Tile& t, int& gl) {
   return t.r0 + (int)(blockIdx.x % G) * (kTileRows / G) + (int)threadIdx.x / G;
 }
 
-template <class T, class TX, int G>
-__device__ inline T row_dot(const int* __restrict__ ci, const T* __restrict__ a, const TX* __restrict__ x, int e0,
-                            int e1, int gl) {
-  T acc[kRowUnroll];
+// sum of a[e] f(ci[e]) over the row's entries [e0, e1); all G lanes of the
+// row call it (the shuffles need them)
+template <class T, int G, class F>
+__device__ inline T row_sum(const int* __restrict__ ci, const T* __restrict__ a, F f, int e0, int e1, int gl) {
+  static_assert(G >= 1 && G <= kAcc && (kAcc % G) == 0, "lane count must divide kAcc");
+  constexpr int J = kAcc / G;  // partial sums per lane
+  T acc[J];
 #pragma unroll
-  for (int u = 0; u < kRowUnroll; ++u) acc[u] = 0;
-  int e = e0 + gl;
-  for (; e + (kRowUnroll - 1) * G < e1; e += kRowUnroll * G) {
-    int c[kRowUnroll];
-    T v[kRowUnroll];
+  for (int j = 0; j < J; ++j) acc[j] = 0;
+  int base = e0;
+  constexpr int UN = J >= 4 ? 1 : 4 / J;  // chunks in flight: four entries' loads per lane
+#pragma unroll UN
+  for (; base + kAcc <= e1; base += kAcc) {  // whole chunks: loads first, all in flight
+    int c[J];
+    T v[J];
 #pragma unroll
-    for (int u = 0; u < kRowUnroll; ++u) {
-      c[u] = ci[e + u * G];
-      v[u] = a[e + u * G];
+    for (int j = 0; j < J; ++j) {
+      c[j] = ci[base + gl + G * j];
+      v[j] = a[base + gl + G * j];
     }
 #pragma unroll
-    for (int u = 0; u < kRowUnroll; ++u) acc[u] += v[u] * (T)x[c[u]];
+    for (int j = 0; j < J; ++j) acc[j] += v[j] * f(c[j]);
   }
-  for (; e < e1; e += G) acc[0] += a[e] * (T)x[ci[e]];
+  if (base < e1) {  // the last, partial chunk
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int e = base + gl + G * j;
+      if (e < e1) acc[j] += a[e] * f(ci[e]);
+    }
+  }
+#pragma unroll
+  for (int o = kAcc / 2; o >= G; o >>= 1) {
+#pragma unroll
+    for (int j = 0; j < o / G; ++j) acc[j] = acc[j] + acc[j + o / G];
+  }
   T s = acc[0];
 #pragma unroll
-  for (int u = 1; u < kRowUnroll; ++u) s += acc[u];
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  for (int o = G / 2; o > 0; o >>= 1) s = s + __shfl_xor(s, o);
   return s;
 }
 
-// row_dot<T, T, G> with the vector entries produced by f(column): the same
-// products in the same order
+template <class T, class TX, int G>
+__device__ inline T row_dot(const int* __restrict__ ci, const T* __restrict__ a, const TX* __restrict__ x, int e0,
+                            int e1, int gl) {
+  return row_sum<T, G>(ci, a, [&](int j) -> T { return (T)x[j]; }, e0, e1, gl);
+}
+
 template <class T, int G, class F>
 __device__ inline T row_dot_fn(const int* __restrict__ ci, const T* __restrict__ a, F f, int e0, int e1, int gl) {
-  T acc[kRowUnroll];
-#pragma unroll
-  for (int u = 0; u < kRowUnroll; ++u) acc[u] = 0;
-  int e = e0 + gl;
-  for (; e + (kRowUnroll - 1) * G < e1; e += kRowUnroll * G) {
-    int c[kRowUnroll];
-    T v[kRowUnroll];
-#pragma unroll
-    for (int u = 0; u < kRowUnroll; ++u) {
-      c[u] = ci[e + u * G];
-      v[u] = a[e + u * G];
-    }
-#pragma unroll
-    for (int u = 0; u < kRowUnroll; ++u) acc[u] += v[u] * f(c[u]);
-  }
-  for (; e < e1; e += G) acc[0] += a[e] * f(ci[e]);
-  T s = acc[0];
-#pragma unroll
-  for (int u = 1; u < kRowUnroll; ++u) s += acc[u];
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  return s;
+  return row_sum<T, G>(ci, a, f, e0, e1, gl);
 }
 
 // first = 1: the first sweep from zero, x = omega D^-1 b; first = 2: the first
@@ -2147,27 +2148,30 @@ __global__ __launch_bounds__(256) void k_prolong(const Tile* __restrict__ tiles,
 
 // row_dot<T, T, 1> with the vector entries produced by f(column): the same
 // products in the same order, hence the same result as on an array
+// one lane per row (the V-cycle tail, whose levels belong to one game: its
+// sums need not match the level kernels'), four partial sums
 template <class T, class F>
 __device__ inline T row_dot1_f(const int* __restrict__ ci, const T* __restrict__ a, F f, int e0, int e1) {
-  T acc[kRowUnroll];
+  constexpr int U = 4;
+  T acc[U];
 #pragma unroll
-  for (int u = 0; u < kRowUnroll; ++u) acc[u] = 0;
+  for (int u = 0; u < U; ++u) acc[u] = 0;
   int e = e0;
-  for (; e + (kRowUnroll - 1) < e1; e += kRowUnroll) {
-    int c[kRowUnroll];
-    T v[kRowUnroll];
+  for (; e + (U - 1) < e1; e += U) {
+    int c[U];
+    T v[U];
 #pragma unroll
-    for (int u = 0; u < kRowUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       c[u] = ci[e + u];
       v[u] = a[e + u];
     }
 #pragma unroll
-    for (int u = 0; u < kRowUnroll; ++u) acc[u] += v[u] * f(c[u]);
+    for (int u = 0; u < U; ++u) acc[u] += v[u] * f(c[u]);
   }
   for (; e < e1; ++e) acc[0] += a[e] * f(ci[e]);
   T s = acc[0];
 #pragma unroll
-  for (int u = 1; u < kRowUnroll; ++u) s += acc[u];
+  for (int u = 1; u < U; ++u) s += acc[u];
   return s;
 }
 
@@ -2646,13 +2650,13 @@ void amg_dense_inv(const int* blk, int nblk, const int* rp, const int* ci, const
 }
 
 // lanes per row from the average row length of a level
-int row_group(double avg_len) { return avg_len <= 10.0 ? 1 : (avg_len <= 40.0 ? 4 : 16); }
+int row_group(double avg_len) { return avg_len <= 10.0 ? 1 : 4; }
 
-#define SHP_GROUP_LAUNCH(K, g, nt, s, ...)                                                         \
-  do {                                                                                            \
-    if ((g) == 16) hipLaunchKernelGGL((K<T, 16>), dim3((nt) * 16), dim3(kTileRows), 0, s, __VA_ARGS__); \
-    else if ((g) == 4) hipLaunchKernelGGL((K<T, 4>), dim3((nt) * 4), dim3(kTileRows), 0, s, __VA_ARGS__); \
-    else hipLaunchKernelGGL((K<T, 1>), dim3(nt), dim3(kTileRows), 0, s, __VA_ARGS__);             \
+#define SHP_GROUP_LAUNCH(K, g, nt, s, ...)                                                              \
+  do {                                                                                                 \
+    if ((g) == 4) hipLaunchKernelGGL((K<T, 4>), dim3((nt) * 4), dim3(kTileRows), 0, s, __VA_ARGS__);    \
+    else if ((g) == 2) hipLaunchKernelGGL((K<T, 2>), dim3((nt) * 2), dim3(kTileRows), 0, s, __VA_ARGS__);    \
+    else hipLaunchKernelGGL((K<T, 1>), dim3(nt), dim3(kTileRows), 0, s, __VA_ARGS__);                  \
   } while (0)
 
 template <class T>

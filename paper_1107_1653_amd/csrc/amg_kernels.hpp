@@ -97,7 +97,7 @@ void cyc_tail(const int* games, int ngames, int l0, int nlev, int G, const TailL
               double* sol = nullptr,  // sol: also sol += result on level l0 (FP64)
               const TailRefine* rf = nullptr);  // l0 == 0: refinement cycles in the launch
 
-// lanes per sparse row (1, 4 or 16) for a level with this average row length
+// lanes per sparse row (1 or 4) for a level with this average row length
 int row_group(double avg_len);
 template <class T>
 void cyc_smooth(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const T* a,

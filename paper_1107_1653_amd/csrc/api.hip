@@ -516,6 +516,15 @@ int shapley_hierarchy_level(shapley_game_t gh, int32_t level, shapley_level_info
   });
 }
 
+int shapley_tune_lanes(int32_t lanes) {
+  if (lanes != 0 && lanes != 1 && lanes != 2 && lanes != 4) {
+    shp::set_last_error("lanes must be 0, 1, 2 or 4");
+    return SHAPLEY_EINVAL;
+  }
+  shp::set_forced_lanes(lanes);
+  return SHAPLEY_OK;
+}
+
 int shapley_game_bytes(shapley_game_t gh, size_t* bytes) {
   return guarded([&] {
     SHP_REQUIRE(gh && gh->g && bytes, "null argument");

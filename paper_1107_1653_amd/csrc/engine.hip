@@ -336,6 +336,102 @@ void Engine::assemble(const std::vector<int>& run, bool mixed) {
   (void)run;
 }
 
+// ---- lanes per sparse row (a speed choice only: the cycle kernels' row sums
+// are the same bit for bit for every lane count)
+namespace {
+std::mutex g_tune_mu;
+std::map<std::array<int, 3>, int> g_tuned;  // (value bytes, log2 rows, 4 log2 entries per row) -> lanes
+int g_forced = 0;
+constexpr int64_t kTuneMinNnz = 1 << 18;    // smaller levels take the rule (timing noise)
+// the timed sweeps start from cold caches, as in a V-cycle where the other
+// levels pass through between two sweeps of a level: a buffer larger than the
+// last-level cache is written before each (one per device, kept for the
+// process)
+constexpr size_t kFlushDoubles = size_t(36) << 20;  // 288 MiB
+std::map<int, double*> g_flush;
+double* flush_buffer() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  auto it = g_flush.find(dev);
+  if (it != g_flush.end()) return it->second;
+  double* p = nullptr;
+  if (hipMalloc(&p, kFlushDoubles * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  g_flush[dev] = p;
+  return p;
+}
+}  // namespace
+
+void set_forced_lanes(int lanes) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_forced = lanes;
+}
+int forced_lanes() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_forced;
+}
+
+int Engine::tune_lanes(Level& L, bool mixed) {
+  const int n = L.n;
+  const double avg = (double)L.nnz / std::max(n, 1);
+  const int forced = forced_lanes();
+  if (forced) return forced;
+  const int rule = row_group(avg);
+  if ((int64_t)L.nnz < kTuneMinNnz || L.ntiles == 0) return rule;
+  const std::array<int, 3> key{mixed ? 4 : 8, (int)std::floor(std::log2((double)n)),
+                               (int)std::floor(4.0 * std::log2(std::max(avg, 1.0)))};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) return it->second;
+  }
+  // one relaxation sweep of the level per candidate (inputs: any finite
+  // vectors of the level; the output goes to scratch), best of three after a
+  // first run
+  s_tune.ensure(std::max(n, 1));
+  s_ones.ensure(std::max(G, 1));
+  fill_async(s_ones.p, 1, (size_t)std::max(G, 1), stream);
+  double* flush;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    flush = flush_buffer();
+  }
+  hipEvent_t e0, e1;
+  SHP_HIP(hipEventCreate(&e0));
+  SHP_HIP(hipEventCreate(&e1));
+  int best = rule;
+  float best_ms = INFINITY;
+  for (int g : {1, 2, 4}) {
+    float ms_min = INFINITY;
+    for (int rep = 0; rep < 4; ++rep) {
+      if (flush) fill_async(flush, 0.0, kFlushDoubles, stream);
+      SHP_HIP(hipEventRecord(e0, stream));
+      if (mixed)
+        cyc_smooth<float>(L.tiles.p, L.ntiles, s_ones.p, L.rp.p, L.ci.p, L.a32.p, L.dinv32.p, L.dinv32.p,
+                          L.dinv32.p, reinterpret_cast<float*>(s_tune.p), 0.8f, 0, g, stream, nullptr);
+      else
+        cyc_smooth<double>(L.tiles.p, L.ntiles, s_ones.p, L.rp.p, L.ci.p, L.a64.p, L.dinv64.p, L.dinv64.p,
+                           L.dinv64.p, s_tune.p, 0.8, 0, g, stream, nullptr);
+      SHP_HIP(hipEventRecord(e1, stream));
+      SHP_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      SHP_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (rep > 0) ms_min = std::min(ms_min, ms);  // the first run also loads the code
+    }
+    if (ms_min < best_ms) {
+      best_ms = ms_min;
+      best = g;
+    }
+  }
+  SHP_HIP(hipEventDestroy(e0));
+  SHP_HIP(hipEventDestroy(e1));
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[key] = best;
+  return best;
+}
+
 void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
   const bool mixed = o.precision == SHAPLEY_MIXED;
   std::vector<char> present(G, 0);
@@ -357,7 +453,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
   while (true) {
     Level& L = lv[l];
     const int n = L.n;
-    L.gA = row_group((double)L.nnz / std::max(n, 1));
+    L.gA = row_group((double)L.nnz / std::max(n, 1));  // tuned below once the level is complete
     L.gR = 1;
     L.cont.assign(G, 0);
     bool any_cont = false;
@@ -379,6 +475,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
       }
     }
     build_tiles(L, L.present, false);
+    L.gA = tune_lanes(L, mixed);
     pt.mark("diag+tiles");
     if (any_cont) {
       build_tiles(L, L.cont, true);
@@ -590,7 +687,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         cnnz = *pc_nnz;
         rnnz_used = *pr_nnz;
         Ln.nnz = cnnz;
-        L.gR = row_group((double)rnnz_used / std::max(nc, 1));
+        L.gR = forced_lanes() ? forced_lanes() : row_group((double)rnnz_used / std::max(nc, 1));
         Ln.ci.ensure(std::max(cnnz, 1));
         Ln.a64.ensure(std::max(cnnz, 1));
         if (L.drap)

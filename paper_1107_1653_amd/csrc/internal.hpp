@@ -395,6 +395,8 @@ class Engine {
   DBuf<uint8_t> s_dapt, s_dacf;  // and their structural flags
   DBuf<Tile> s_tiles;
   DBuf<double> s_dense;
+  DBuf<double> s_tune;  // lane-count tuning: output of the timed sweeps
+  DBuf<int> s_ones;     // lane-count tuning: every game active
  public:
   std::vector<std::pair<std::string, double>> prof;  // phase profile (SHAPLEY_PROFILE=1)
  private:
@@ -418,7 +420,14 @@ class Engine {
   void improve(const std::vector<int>& run, double tie_rtol);
   void apply_decisions(const std::vector<int>& code);
   void build_tiles(Level& L, const std::vector<char>& keep, bool cont_only);
+  // lanes per row of level L's relaxation and residual sweeps (row sums do
+  // not depend on it): timed on large levels, cached per size class
+  int tune_lanes(Level& L, bool mixed);
 };
+
+// Forced lanes per sparse row in the cycle kernels (0: tuned per level).
+void set_forced_lanes(int lanes);
+int forced_lanes();
 
 // Engines (with their device workspace) are kept per game stream between
 // solves; a lease takes the idle engine of a stream or makes one, and gives

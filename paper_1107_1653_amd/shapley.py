@@ -35,7 +35,7 @@ EXPORTED = [
     "shapley_game_destroy",
     "shapley_solve_batch", "shapley_server_create", "shapley_server_submit", "shapley_server_wait",
     "shapley_server_poll", "shapley_server_step", "shapley_server_destroy",
-    "shapley_probe_enable", "shapley_probe_read", "shapley_probe_read_large",
+    "shapley_probe_enable", "shapley_probe_read", "shapley_probe_read_large", "shapley_tune_lanes",
 ]
 PROBE = dict(smooth=0, resid64=1, improve=2, resid=3, restrict=4, prolong=5, rap=6, interp=7, tail=8)
 
@@ -132,6 +132,7 @@ def lib() -> C.CDLL:
                                          C.POINTER(C.c_double)]
         L.shapley_probe_read_large.argtypes = [C.c_int32, C.c_double, C.POINTER(C.c_int64),
                                                C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.shapley_tune_lanes.argtypes = [C.c_int32]
         _lib_handle = L
     return _lib_handle
 
@@ -344,6 +345,11 @@ def shapley_probe_read(family) -> dict:
     n, ms, b = C.c_int64(), C.c_double(), C.c_double()
     _check(lib().shapley_probe_read(fam, C.byref(n), C.byref(ms), C.byref(b)))
     return dict(launches=n.value, ms=ms.value, bytes=b.value)
+
+
+def shapley_tune_lanes(lanes: int = 0) -> None:
+    """Lanes per sparse row in the cycle kernels: 0 tunes per level, 1/2/4 force."""
+    _check(lib().shapley_tune_lanes(int(lanes)))
 
 
 def shapley_probe_read_large(family, frac: float = 0.5) -> dict:

@@ -68,6 +68,17 @@ def test_probe_arguments_are_checked():
                                         ctypes.byref(b)) == P.SHAPLEY_EINVAL
 
 
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_lane_control_arguments():
+    # the setting only takes effect at later setups: no device call here
+    import paper_1107_1653_amd as P
+    for bad in (3, 8, 16, -1):
+        with pytest.raises(P.ShapleyError):
+            P.shapley_tune_lanes(bad)
+    for ok in (1, 2, 4, 0):
+        P.shapley_tune_lanes(ok)
+
+
 def test_bench_refuses_more_than_one_gpu():
     out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                          capture_output=True, text=True, timeout=120)
