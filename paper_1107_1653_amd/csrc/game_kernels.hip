@@ -122,6 +122,8 @@ __device__ inline int warp_sum_i(int v) {
   return v;
 }
 
+constexpr int kAsmRow = 8;  // pattern rows built in registers
+
 __global__ __launch_bounds__(256) void k_assemble(const GameDesc* __restrict__ gd,
                                                   const GTile* __restrict__ tiles,
                                                   const int* __restrict__ active,
@@ -138,26 +140,53 @@ __global__ __launch_bounds__(256) void k_assemble(const GameDesc* __restrict__ g
     const int e0 = d.rp[s], e1 = d.rp[s + 1];
     const int j0 = d.urp[x], j1 = d.urp[x + 1];
     // the identity row on the level-0 pattern, then each entry of the chosen
-    // row subtracted at its column (found by bisection: the pattern row is
-    // sorted and holds every column of the state's rows), in row order
-    int jd = j0;
-    for (int j = j0; j < j1; ++j) {
-      const int c = d.uci[j];
-      a64[d.a_off + j] = c == x ? 1.0 : 0.0;
-      if (c == x) jd = j;
-    }
-    for (int e = e0; e < e1; ++e) {
-      const int c = d.ci[e];
-      int lo = j0, hi = j1 - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (d.uci[mid] < c) lo = mid + 1; else hi = mid;
+    // row subtracted at its column, in row order (the pattern row is sorted
+    // and holds every column of the state's rows)
+    double diag = 0.0;
+    if (j1 - j0 <= kAsmRow) {
+      // short pattern rows (grid stencils): the row is built in registers
+      // and written once
+      int col[kAsmRow];
+      double val[kAsmRow];
+#pragma unroll
+      for (int k = 0; k < kAsmRow; ++k) {
+        col[k] = j0 + k < j1 ? d.uci[j0 + k] : -1;
+        val[k] = col[k] == x ? 1.0 : 0.0;
       }
-      a64[d.a_off + lo] -= d.mu * d.w[e];
+      for (int e = e0; e < e1; ++e) {
+        const int c = d.ci[e];
+        const double mw = d.mu * d.w[e];
+#pragma unroll
+        for (int k = 0; k < kAsmRow; ++k)
+          if (col[k] == c) val[k] -= mw;
+      }
+#pragma unroll
+      for (int k = 0; k < kAsmRow; ++k) {
+        if (j0 + k >= j1) break;
+        a64[d.a_off + j0 + k] = val[k];
+        if (a32) a32[d.a_off + j0 + k] = (float)val[k];
+        if (col[k] == x) diag = val[k];
+      }
+    } else {
+      int jd = j0;
+      for (int j = j0; j < j1; ++j) {
+        const int c = d.uci[j];
+        a64[d.a_off + j] = c == x ? 1.0 : 0.0;
+        if (c == x) jd = j;
+      }
+      for (int e = e0; e < e1; ++e) {  // column by bisection
+        const int c = d.ci[e];
+        int lo = j0, hi = j1 - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (d.uci[mid] < c) lo = mid + 1; else hi = mid;
+        }
+        a64[d.a_off + lo] -= d.mu * d.w[e];
+      }
+      diag = a64[d.a_off + jd];
+      if (a32)
+        for (int j = j0; j < j1; ++j) a32[d.a_off + j] = (float)a64[d.a_off + j];
     }
-    double diag = a64[d.a_off + jd];
-    if (a32)
-      for (int j = j0; j < j1; ++j) a32[d.a_off + j] = (float)a64[d.a_off + j];
     int X = d.x_off + x;
     double rb = d.r[s];
     b0[X] = rb;
