@@ -2494,10 +2494,16 @@ void amg_interp(const Tile* t, int nt, const int* rp, const int* ci, const doubl
                 const uint8_t* strong, const int8_t* cf, const int* cidx, const uint8_t* dir, int* pc,
                 double* pv, int* capped, int wave, int* defer, int rows, hipStream_t s) {
   if (!nt) return;
-  if (wave == 2)
-    hipLaunchKernelGGL((k_interp_wave<1024, 256, 256, false>), dim3(nt * kTileRows), dim3(64), 0, s, t, rp, ci, a,
-                       dinv, strong, cf, cidx, dir, pc, pv, capped, (int*)nullptr);
-  else if (wave == 1) {
+  if (wave == 2) {
+    // long rows: the 512-slot instance (18 KB of LDS per row) for all rows,
+    // then the rows it could not hold with the largest one (33 KB)
+    fill_async(defer, 0, 1, s);
+    hipLaunchKernelGGL((k_interp_wave<512, 128, 256, true>), dim3(nt * kTileRows), dim3(64), 0, s, t, rp, ci, a, dinv,
+                       strong, cf, cidx, dir, pc, pv, capped, defer);
+    SHP_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_interp_wave_list<1024, 256>), dim3(std::max(1, std::min(rows, 2048))), dim3(64), 0, s,
+                       defer, rp, ci, a, dinv, strong, cf, cidx, dir, pc, pv, capped);
+  } else if (wave == 1) {
     // a small instance (about 5 KB of LDS per row: twice the rows per CU of
     // the next size) for all rows, then the rows it could not hold
     fill_async(defer, 0, 1, s);
