@@ -928,9 +928,10 @@ __device__ __forceinline__ void rap_run(int cnt, int head, const int* __restrict
   wave_lds_sync();
 }
 
-// upper bound of the distinct columns of each coarse row: min(PW x pairs, kRapND)
+// upper bound of the distinct columns of each coarse row: min(pw x pairs,
+// kRapND), pw = the filled slots per row of P (PW, or 1 for the identity)
 __global__ void k_rap_bound(int nc, const int* __restrict__ rrp, const int* __restrict__ rci,
-                            const int* __restrict__ rp, int* __restrict__ ub) {
+                            const int* __restrict__ rp, int* __restrict__ ub, int pw) {
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nc) return;
   const int p0 = rrp[I], p1 = rrp[I + 1];
@@ -940,7 +941,7 @@ __global__ void k_rap_bound(int nc, const int* __restrict__ rrp, const int* __re
     const int i = rci[p];
     E += rp[i + 1] - rp[i];
   }
-  const long long b = E * PW;
+  const long long b = E * pw;
   ub[I] = (int)(b < kRapND ? b : kRapND);
 }
 
@@ -2540,9 +2541,29 @@ void amg_sort_rows(const int* rp, int* ci, double* v, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_sort_rows_wave, dim3((n + 3) / 4), dim3(256), 0, s, rp, ci, v, n);
   SHP_LAUNCH_CHECK();
 }
-void amg_rap_bound(int nc, const int* rrp, const int* rci, const int* rp, int* ub, hipStream_t s) {
+void amg_rap_bound(int nc, const int* rrp, const int* rci, const int* rp, int* ub, int pw, hipStream_t s) {
   if (!nc) return;
-  hipLaunchKernelGGL(k_rap_bound, dim3(grid_for(nc)), dim3(kBlock), 0, s, nc, rrp, rci, rp, ub);
+  hipLaunchKernelGGL(k_rap_bound, dim3(grid_for(nc)), dim3(kBlock), 0, s, nc, rrp, rci, rp, ub, pw);
+  SHP_LAUNCH_CHECK();
+}
+// identity operators over n rows: R = I in CSR (rrp, rci, rv) and P = I in
+// the ELL layout (pc, pv; one filled slot per row)
+__global__ void k_identity_ops(int n, int* __restrict__ rrp, int* __restrict__ rci, double* __restrict__ rv,
+                               int* __restrict__ pc, double* __restrict__ pv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  rrp[i] = i;
+  if (i == n) return;
+  rci[i] = i;
+  rv[i] = 1.0;
+#pragma unroll
+  for (int q = 0; q < PW; ++q) {
+    pc[(size_t)i * PW + q] = q == 0 ? i : -1;
+    pv[(size_t)i * PW + q] = q == 0 ? 1.0 : 0.0;
+  }
+}
+void amg_identity_ops(int n, int* rrp, int* rci, double* rv, int* pc, double* pv, hipStream_t s) {
+  hipLaunchKernelGGL(k_identity_ops, dim3(grid_for(n + 1)), dim3(kBlock), 0, s, n, rrp, rci, rv, pc, pv);
   SHP_LAUNCH_CHECK();
 }
 // Levels with few coarse rows (long rows): one workgroup of 256 lanes per

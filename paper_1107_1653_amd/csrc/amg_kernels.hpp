@@ -42,7 +42,15 @@ constexpr int kRapMaxCols = 1024;  // distinct columns of one coarse row
 // fused (row lengths into tcnt, rows into the scratch tcol/tval) -> scan of
 // tcnt into the coarse row pointers -> compaction.  Refresh: values of the
 // rows flagged in `only` (all when null) into the existing pattern.
-void amg_rap_bound(int nc, const int* rrp, const int* rci, const int* rp, int* ub, hipStream_t s);
+void amg_rap_bound(int nc, const int* rrp, const int* rci, const int* rp, int* ub, int pw, hipStream_t s);
+// R = I (CSR, n rows) and P = I (ELL width PW) over n rows: the Galerkin
+// kernels with these operands compute A P (R = I) and R (AP) (P = I) exactly
+// (every product is multiplied by 1.0)
+void amg_identity_ops(int n, int* rrp, int* rci, double* rv, int* pc, double* pv, hipStream_t s);
+// levels averaging at least this many entries per row form A P first (the
+// rows of P are then read once per fine row, not once per coarse row reaching
+// it) and R (AP) after
+constexpr int kApRowLen = 16;
 void amg_rap_fused(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,
                    const double* a, const int* pc, const double* pv, const int* toff, int* tcnt, int* tcol,
                    double* tval, int* err, int* big, hipStream_t s);

@@ -455,6 +455,8 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
     const int n = L.n;
     L.gA = row_group((double)L.nnz / std::max(n, 1));  // tuned below once the level is complete
     L.gR = 1;
+    L.apf = false;
+    L.drap = false;
     L.cont.assign(G, 0);
     bool any_cont = false;
     for (int g = 0; g < G; ++g) {
@@ -667,16 +669,61 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
                         L.pv64.p, L.rrp.p, L.rci.p, L.rv64.p, s_dap.p, s_dapt.p, s_dac.p, s_dacf.p, s_cnt.p,
                         stream);
         } else {
-          amg_rap_bound(nc, L.rrp.p, L.rci.p, L.rp.p, s_cnt.p, stream);
+          // the single pass R A P, or for long rows A P first and R (AP) after
+          const int* Arp = L.rp.p;
+          const int* Aci = L.ci.p;
+          const double* Aa = L.a64.p;
+          const int* Ppc = L.pc.p;
+          const double* Ppv = L.pv64.p;
+          int pwf = PW;                 // filled slots per row of the right operand
+          size_t opnnz = (size_t)std::max(L.nnz, 1);
+          L.apf = (long long)L.nnz >= (long long)kApRowLen * n;
+          if (L.apf) {
+            L.id_rp.ensure((size_t)n + 1);
+            L.id_ci.ensure(std::max(n, 1));
+            L.id_rv.ensure(std::max(n, 1));
+            L.id_pc.ensure((size_t)std::max(n, 1) * PW);
+            L.id_pv.ensure((size_t)std::max(n, 1) * PW);
+            amg_identity_ops(n, L.id_rp.p, L.id_ci.p, L.id_rv.p, L.id_pc.p, L.id_pv.p, stream);
+            s_cnt.ensure((size_t)n + 1);
+            s_toff.ensure((size_t)n + 1);
+            s_big.ensure((size_t)n + 1);
+            fill_async(s_cnt.p + n, 0, 1, stream);
+            amg_rap_bound(n, L.id_rp.p, L.id_ci.p, L.rp.p, s_cnt.p, PW, stream);
+            scan_exclusive(s_cnt.p, s_toff.p, n + 1, stream, s_scan);
+            const size_t tcap1 = std::max<size_t>(
+                1, std::min((size_t)PW * (size_t)std::max(L.nnz, 1), (size_t)n * (size_t)kRapMaxCols));
+            s_tcol.ensure(tcap1);
+            s_tval.ensure(tcap1);
+            amg_rap_fused(n, L.id_rp.p, L.id_ci.p, L.id_rv.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p,
+                          s_toff.p, s_cnt.p, s_tcol.p, s_tval.p, s_err.p + 1, s_big.p, stream);
+            L.ap_rp.ensure((size_t)n + 1);
+            scan_exclusive(s_cnt.p, L.ap_rp.p, n + 1, stream, s_scan);
+            const int* pap = down(L.ap_rp.p + n, 1);
+            sync();
+            L.ap_nnz = *pap;
+            L.ap_ci.ensure(std::max(L.ap_nnz, 1));
+            L.ap_v.ensure(std::max(L.ap_nnz, 1));
+            amg_rap_compact(n, s_toff.p, s_tcol.p, s_tval.p, L.ap_rp.p, L.ap_ci.p, L.ap_v.p, stream);
+            Arp = L.ap_rp.p;
+            Aci = L.ap_ci.p;
+            Aa = L.ap_v.p;
+            Ppc = L.id_pc.p;
+            Ppv = L.id_pv.p;
+            pwf = 1;
+            opnnz = (size_t)std::max(L.ap_nnz, 1);
+            fill_async(s_cnt.p + nc, 0, 1, stream);  // the scan's last entry (step 1 used the space)
+          }
+          amg_rap_bound(nc, L.rrp.p, L.rci.p, Arp, s_cnt.p, pwf, stream);
           scan_exclusive(s_cnt.p, s_toff.p, nc + 1, stream, s_scan);
-          // sum of the bounds <= PW * (pairs) <= PW * PW * nnz(A)
+          // sum of the bounds <= pwf * (pairs) <= pwf * PW * nnz(operand)
           const size_t tcap = std::max<size_t>(
-              1, std::min((size_t)PW * PW * (size_t)std::max(L.nnz, 1), (size_t)nc * (size_t)kRapMaxCols));
+              1, std::min((size_t)pwf * PW * opnnz, (size_t)nc * (size_t)kRapMaxCols));
           s_tcol.ensure(tcap);
           s_tval.ensure(tcap);
-          s_big.ensure((size_t)nc + 1);
-          amg_rap_fused(nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, s_toff.p,
-                        s_cnt.p, s_tcol.p, s_tval.p, s_err.p + 1, s_big.p, stream);
+          s_big.ensure((size_t)std::max(n, nc) + 1);
+          amg_rap_fused(nc, L.rrp.p, L.rci.p, L.rv64.p, Arp, Aci, Aa, Ppc, Ppv, s_toff.p, s_cnt.p, s_tcol.p,
+                        s_tval.p, s_err.p + 1, s_big.p, stream);
         }
         probe_end(kProbeRap, stream, (double)L.nnz * 12 + (double)n * PW * 12 + (double)nc * 8);
         scan_exclusive(s_cnt.p, Ln.rp.p, nc + 1, stream, s_scan);
@@ -913,6 +960,13 @@ void Engine::refresh(const EngineOpts& o) {
         s_dap.ensure(std::max<long long>(L.drap_ap, 1));
         amg_drap_known(L.n, L.nc, L.drap_maxc, L.drap_tab.p, G, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p,
                        L.rrp.p, L.rci.p, L.rv64.p, s_dap.p, Ln.rp.p, Ln.ci.p, Ln.a64.p, stream, Ln.chg.p);
+      } else if (L.apf) {
+        // A P rows of the changed fine rows, then the coarse rows they reach
+        s_big.ensure((size_t)std::max(n, L.nc) + 1);
+        amg_rap_known(n, L.id_rp.p, L.id_ci.p, L.id_rv.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, L.ap_rp.p,
+                      L.ap_ci.p, L.ap_v.p, s_err.p + 1, s_big.p, stream, L.chg.p);
+        amg_rap_known(L.nc, L.rrp.p, L.rci.p, L.rv64.p, L.ap_rp.p, L.ap_ci.p, L.ap_v.p, L.id_pc.p, L.id_pv.p,
+                      Ln.rp.p, Ln.ci.p, Ln.a64.p, s_err.p + 1, s_big.p, stream, Ln.chg.p);
       } else {
         s_big.ensure((size_t)L.nc + 1);
         amg_rap_known(L.nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, Ln.rp.p,

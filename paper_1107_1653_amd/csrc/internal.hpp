@@ -148,6 +148,14 @@ struct Level {
   DBuf<int> rrp, rci;             // R = P^T, CSR over the next level's rows
   DBuf<double> rv64;
   DBuf<float> rv32;
+  // Galerkin product as R (A P) (long rows): A P kept for refreshes, with
+  // the identity operators it is formed with
+  bool apf = false;
+  int ap_nnz = 0;
+  DBuf<int> ap_rp, ap_ci;
+  DBuf<double> ap_v;
+  DBuf<int> id_rp, id_ci, id_pc;
+  DBuf<double> id_rv, id_pv;
   // Galerkin product through dense per-game blocks (small next levels)
   bool drap = false;
   long long drap_ap = 0, drap_ac = 0;  // dense entries of AP and of R A P

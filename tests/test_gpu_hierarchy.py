@@ -4,7 +4,9 @@ here with scipy.sparse:
 
 * every coarse operator is the Galerkin product A_{l+1} = P_l^T A_l P_l of
   the level above and its prolongation (large levels take the row-wise
-  product, small ones the dense per-game blocks: both are covered);
+  product -- as R A P, or as R (A P) on levels averaging 16 or more entries
+  per row --, small ones the dense per-game blocks: all are covered, after
+  full setups and after the numeric refreshes of later policy steps);
 * P_l has at most pw distinct entries per row, columns inside the next
   level, and the coarse points are injected: every coarse index J is a fine
   row whose only entry is (J, 1);
@@ -103,6 +105,20 @@ def test_galerkin_hierarchy_isaacs3d():
                                                        precision=P.SHAPLEY_MIXED))
         assert st["converged"] == 1
         check_hierarchy(h, "isaacs3d 17")
+    finally:
+        P.shapley_game_destroy(h)
+
+
+def test_galerkin_hierarchy_isaacs3d_long_rows():
+    # 33^3: the coarse levels above the dense blocks average more than 16
+    # entries per row and take R (A P)
+    g = configs.c2(s=33)
+    h = P.create_from(g)
+    try:
+        st = P.shapley_solve(h, P.shapley_default_opts(max_outer=500, max_inner=500, forcing=0.1, reuse_frac=0.5))
+        assert st["converged"] == 1
+        log(f"  isaacs3d 33: full setups {st['setups_full']} refreshes {st['setups_refresh']}")
+        check_hierarchy(h, "isaacs3d 33")
     finally:
         P.shapley_game_destroy(h)
 
