@@ -387,10 +387,10 @@ int Engine::tune_lanes(Level& L, bool mixed) {
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) return it->second;
   }
-  // one relaxation sweep of the level per candidate (inputs: any finite
-  // vectors of the level; the output goes to scratch), best of three after a
-  // first run
-  s_tune.ensure(std::max(n, 1));
+  // per candidate, the level's kernels of one V-cycle visit: the fused first
+  // two sweeps, a plain sweep and the residual (inputs: any finite vectors of
+  // the level; outputs to scratch), best of three after a first run
+  s_tune.ensure(2 * (size_t)std::max(n, 1));
   s_ones.ensure(std::max(G, 1));
   fill_async(s_ones.p, 1, (size_t)std::max(G, 1), stream);
   double* flush;
@@ -408,12 +408,23 @@ int Engine::tune_lanes(Level& L, bool mixed) {
     for (int rep = 0; rep < 4; ++rep) {
       if (flush) fill_async(flush, 0.0, kFlushDoubles, stream);
       SHP_HIP(hipEventRecord(e0, stream));
-      if (mixed)
-        cyc_smooth<float>(L.tiles.p, L.ntiles, s_ones.p, L.rp.p, L.ci.p, L.a32.p, L.dinv32.p, L.dinv32.p,
-                          L.dinv32.p, reinterpret_cast<float*>(s_tune.p), 0.8f, 0, g, stream, nullptr);
-      else
-        cyc_smooth<double>(L.tiles.p, L.ntiles, s_ones.p, L.rp.p, L.ci.p, L.a64.p, L.dinv64.p, L.dinv64.p,
-                           L.dinv64.p, s_tune.p, 0.8, 0, g, stream, nullptr);
+      if (mixed) {
+        float* o1 = reinterpret_cast<float*>(s_tune.p);
+        float* o2 = o1 + std::max(n, 1);
+        cyc_smooth<float>(L.tiles.p, L.ntiles, s_ones.p, L.rp.p, L.ci.p, L.a32.p, L.dinv32.p, L.dinv32.p, nullptr,
+                          o1, 0.8f, 2, g, stream, nullptr);
+        cyc_smooth<float>(L.tiles.p, L.ntiles, s_ones.p, L.rp.p, L.ci.p, L.a32.p, L.dinv32.p, L.dinv32.p, o1, o2,
+                          0.8f, 0, g, stream, nullptr);
+        cyc_resid<float>(L.tiles.p, L.ntiles, s_ones.p, L.rp.p, L.ci.p, L.a32.p, L.dinv32.p, o2, o1, g, stream);
+      } else {
+        double* o1 = s_tune.p;
+        double* o2 = o1 + std::max(n, 1);
+        cyc_smooth<double>(L.tiles.p, L.ntiles, s_ones.p, L.rp.p, L.ci.p, L.a64.p, L.dinv64.p, L.dinv64.p, nullptr,
+                           o1, 0.8, 2, g, stream, nullptr);
+        cyc_smooth<double>(L.tiles.p, L.ntiles, s_ones.p, L.rp.p, L.ci.p, L.a64.p, L.dinv64.p, L.dinv64.p, o1, o2,
+                           0.8, 0, g, stream, nullptr);
+        cyc_resid<double>(L.tiles.p, L.ntiles, s_ones.p, L.rp.p, L.ci.p, L.a64.p, L.dinv64.p, o2, o1, g, stream);
+      }
       SHP_HIP(hipEventRecord(e1, stream));
       SHP_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
