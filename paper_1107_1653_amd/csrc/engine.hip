@@ -545,7 +545,6 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
       auto number = [&](std::vector<int>& ncg) {
         while (true) {
           amg_is_c(L.cf.p, L.tmp.p, n, stream);
-          fill_async(L.tmp.p + n, 0, 1, stream);
           scan_exclusive(L.tmp.p, L.cidx.p, n + 1, stream, s_scan);
           s_gout.ensure(G + 1);
           amg_gather_int(L.cidx.p, s_goff.p, G + 1, s_gout.p, stream);
@@ -637,7 +636,6 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         Ln.rp.ensure(nc + 1);
         s_cnt.ensure(nc + 1);
         s_toff.ensure(nc + 1);
-        fill_async(s_cnt.p + nc, 0, 1, stream);
         {
           long long ap = 0, ac = 0;
           int maxc = 0;
@@ -699,7 +697,6 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
             s_cnt.ensure((size_t)n + 1);
             s_toff.ensure((size_t)n + 1);
             s_big.ensure((size_t)n + 1);
-            fill_async(s_cnt.p + n, 0, 1, stream);
             amg_rap_bound(n, L.id_rp.p, L.id_ci.p, L.rp.p, s_cnt.p, PW, stream);
             scan_exclusive(s_cnt.p, s_toff.p, n + 1, stream, s_scan);
             const size_t tcap1 = std::max<size_t>(
@@ -723,7 +720,6 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
             Ppv = L.id_pv.p;
             pwf = 1;
             opnnz = (size_t)std::max(L.ap_nnz, 1);
-            fill_async(s_cnt.p + nc, 0, 1, stream);  // the scan's last entry (step 1 used the space)
           }
           amg_rap_bound(nc, L.rrp.p, L.rci.p, Arp, s_cnt.p, pwf, stream);
           scan_exclusive(s_cnt.p, s_toff.p, nc + 1, stream, s_scan);

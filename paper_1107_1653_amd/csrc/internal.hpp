@@ -486,7 +486,10 @@ void launch_union_fill(const int* rp, const int* ci, int n, int m1, int m2, cons
                        hipStream_t s);
 void launch_fmg(const Game* c, const Game* f, hipStream_t s);
 
-// device scan (exclusive) of n ints into out (out may alias in); returns total via *total_dev
+// device scan (exclusive) of n ints into out (out may alias in):
+// out[i] = in[0] + ... + in[i-1] for i < n.  in[n-1] reaches no output, so a
+// count array scanned over n = rows + 1 entries (out[rows] = the total) needs
+// no zero in its last slot
 void scan_exclusive(const int* in, int* out, int n, hipStream_t s, DBuf<int>& scratch);
 
 }  // namespace shp
