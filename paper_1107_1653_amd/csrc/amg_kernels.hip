@@ -1249,13 +1249,14 @@ __global__ __launch_bounds__(kBlock) void k_drap_ap(int nf, const long long* __r
                                                     const int* __restrict__ rp, const int* __restrict__ ci,
                                                     const double* __restrict__ a, const int* __restrict__ pc,
                                                     const double* __restrict__ pv, double* __restrict__ ap,
-                                                    uint8_t* __restrict__ apt) {
+                                                    uint8_t* __restrict__ apt, const uint8_t* __restrict__ only) {
   constexpr int W = kBlock / 64;
   __shared__ double acc_s[W][MAXC];
   __shared__ uint8_t hit_s[W][MAXC];
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = blockIdx.x * W + wid;
   if (i >= nf) return;
+  if (only && !only[i]) return;  // refresh: row i of A, hence of A P, unchanged
   const long long* fo = tab;
   const long long* co = tab + (G + 1);
   const long long* ao = tab + 2 * (G + 1);
@@ -2615,10 +2616,10 @@ void amg_drap_full(int nf, int nc, int maxc, const long long* tab, int G, long l
   if (nc <= 0) return;
   if (maxc <= kDrapSmallCols)
     hipLaunchKernelGGL((k_drap_ap<true, kDrapSmallCols>), dim3(drap_blocks(64LL * nf)), dim3(kBlock), 0, s, nf, tab, G,
-                       rp, ci, a, pc, pv, ap, apt);
+                       rp, ci, a, pc, pv, ap, apt, (const uint8_t*)nullptr);
   else
     hipLaunchKernelGGL((k_drap_ap<true, kDrapMaxCols>), dim3(drap_blocks(64LL * nf)), dim3(kBlock), 0, s, nf, tab, G,
-                       rp, ci, a, pc, pv, ap, apt);
+                       rp, ci, a, pc, pv, ap, apt, (const uint8_t*)nullptr);
   SHP_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_drap_ac, dim3(drap_blocks(ac_total)), dim3(kBlock), 0, s, ac_total, tab, G, rrp, rci, rv, ap,
                      apt, ac, acf);
@@ -2636,14 +2637,14 @@ void amg_drap_compact(int nc, const long long* tab, int G, const double* ac, con
 void amg_drap_known(int nf, int nc, int maxc, const long long* tab, int G, const int* rp, const int* ci,
                     const double* a, const int* pc, const double* pv, const int* rrp, const int* rci,
                     const double* rv, double* ap, const int* crp, const int* cci, double* cval, hipStream_t s,
-                    const uint8_t* only) {
+                    const uint8_t* only, const uint8_t* only_f) {
   if (nc <= 0) return;
   if (maxc <= kDrapSmallCols)
     hipLaunchKernelGGL((k_drap_ap<false, kDrapSmallCols>), dim3(drap_blocks(64LL * nf)), dim3(kBlock), 0, s, nf, tab,
-                       G, rp, ci, a, pc, pv, ap, (uint8_t*)nullptr);
+                       G, rp, ci, a, pc, pv, ap, (uint8_t*)nullptr, only_f);
   else
     hipLaunchKernelGGL((k_drap_ap<false, kDrapMaxCols>), dim3(drap_blocks(64LL * nf)), dim3(kBlock), 0, s, nf, tab,
-                       G, rp, ci, a, pc, pv, ap, (uint8_t*)nullptr);
+                       G, rp, ci, a, pc, pv, ap, (uint8_t*)nullptr, only_f);
   SHP_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_drap_known, dim3(drap_blocks(64LL * nc)), dim3(kBlock), 0, s, nc, tab, G, rrp, rci, rv, ap,
                      crp, cci, cval, only);

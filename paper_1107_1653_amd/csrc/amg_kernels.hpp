@@ -85,7 +85,7 @@ void amg_drap_compact(int nc, const long long* tab, int G, const double* ac, con
 void amg_drap_known(int nf, int nc, int maxc, const long long* tab, int G, const int* rp, const int* ci,
                     const double* a, const int* pc, const double* pv, const int* rrp, const int* rci,
                     const double* rv, double* ap, const int* crp, const int* cci, double* cval, hipStream_t s,
-                    const uint8_t* only);
+                    const uint8_t* only, const uint8_t* only_f);
 void amg_diag_inv(int n, const int* rp, const int* ci, const double* a, double* d64, float* d32,
                   hipStream_t s);
 void amg_cast(const double* in, float* out, size_t n, hipStream_t s);

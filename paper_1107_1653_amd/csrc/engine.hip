@@ -670,12 +670,12 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         }
         probe_begin(kProbeRap, stream);
         if (L.drap) {
-          s_dap.ensure(std::max<long long>(L.drap_ap, 1));
+          L.dap.ensure(std::max<long long>(L.drap_ap, 1));
           s_dapt.ensure(std::max<long long>(L.drap_ap, 1));
           s_dac.ensure(std::max<long long>(L.drap_ac, 1));
           s_dacf.ensure(std::max<long long>(L.drap_ac, 1));
           amg_drap_full(n, nc, L.drap_maxc, L.drap_tab.p, G, L.drap_ac, L.rp.p, L.ci.p, L.a64.p, L.pc.p,
-                        L.pv64.p, L.rrp.p, L.rci.p, L.rv64.p, s_dap.p, s_dapt.p, s_dac.p, s_dacf.p, s_cnt.p,
+                        L.pv64.p, L.rrp.p, L.rci.p, L.rv64.p, L.dap.p, s_dapt.p, s_dac.p, s_dacf.p, s_cnt.p,
                         stream);
         } else {
           // the single pass R A P, or for long rows A P first and R (AP) after
@@ -964,9 +964,9 @@ void Engine::refresh(const EngineOpts& o) {
       amg_mark_coarse(L.ctiles.p, L.nctiles, L.pc.p, L.chg.p, Ln.chg.p, stream);
       probe_begin(kProbeRap, stream);
       if (L.drap) {
-        s_dap.ensure(std::max<long long>(L.drap_ap, 1));
+        // the A P rows of the changed fine rows, then the coarse rows they reach
         amg_drap_known(L.n, L.nc, L.drap_maxc, L.drap_tab.p, G, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p,
-                       L.rrp.p, L.rci.p, L.rv64.p, s_dap.p, Ln.rp.p, Ln.ci.p, Ln.a64.p, stream, Ln.chg.p);
+                       L.rrp.p, L.rci.p, L.rv64.p, L.dap.p, Ln.rp.p, Ln.ci.p, Ln.a64.p, stream, Ln.chg.p, L.chg.p);
       } else if (L.apf) {
         // A P rows of the changed fine rows, then the coarse rows they reach
         s_big.ensure((size_t)std::max(n, L.nc) + 1);

@@ -161,6 +161,7 @@ struct Level {
   long long drap_ap = 0, drap_ac = 0;  // dense entries of AP and of R A P
   int drap_maxc = 0;                    // rows of the largest game's next level
   DBuf<long long> drap_tab;       // offset tables (fine rows, coarse rows, AP, R A P), 4 x (G+1)
+  DBuf<double> dap;               // the dense A P blocks, kept for refreshes
   std::vector<long long> h_drap_tab;
   // dense inverses of terminal slots: blocks (row0, size, offset into dmat)
   int nblk = 0, max_blk = 0;
@@ -399,7 +400,7 @@ class Engine {
   DBuf<int> s_big;            // Galerkin product: rows left to the workgroup kernel
   DBuf<int> s_defer;          // interpolation: rows left to the larger instance
   DBuf<double> s_tval;        // and values
-  DBuf<double> s_dap, s_dac;  // dense Galerkin product scratch: AP, R A P
+  DBuf<double> s_dac;         // dense Galerkin product scratch: R A P
   DBuf<uint8_t> s_dapt, s_dacf;  // and their structural flags
   DBuf<Tile> s_tiles;
   DBuf<double> s_dense;
