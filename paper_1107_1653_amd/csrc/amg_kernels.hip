@@ -95,6 +95,48 @@ __global__ void k_pmis_init(const Tile* __restrict__ tiles, const int* __restric
 
 // A point joins C when its weight beats every undecided strong neighbour
 // (both directions of the strength graph).
+__device__ __forceinline__ int pmis_select_row(int i, const int* __restrict__ rp, const int* __restrict__ ci,
+                                               const uint8_t* __restrict__ strong, const int* __restrict__ st_rp,
+                                               const int* __restrict__ st_ci, const int8_t* __restrict__ cf,
+                                               const uint64_t* __restrict__ key) {
+  if (cf[i] != CF_U) return 0;
+  const uint64_t ki = key[i];
+  bool best = true;
+  for (int e = rp[i]; e < rp[i + 1] && best; ++e)
+    if (strong[e]) {
+      const int j = ci[e];
+      if (cf[j] == CF_U && key[j] >= ki) best = false;
+    }
+  for (int e = st_rp[i]; e < st_rp[i + 1] && best; ++e) {
+    const int j = st_ci[e];
+    if (cf[j] == CF_U && key[j] >= ki) best = false;
+  }
+  return best ? 1 : 0;
+}
+
+// New C points are fixed; an undecided point depending strongly on a C point
+// becomes F.  Returns 1 when row i stays undecided.  (A neighbour being set
+// concurrently is read either way with the same outcome: a new C point is
+// also flagged in newc, and an F point is not C.)
+__device__ __forceinline__ int pmis_update_row(int i, const int* __restrict__ rp, const int* __restrict__ ci,
+                                               const uint8_t* __restrict__ strong, int8_t* __restrict__ cf,
+                                               const int* __restrict__ newc) {
+  if (newc[i]) {
+    cf[i] = CF_C;
+    return 0;
+  }
+  if (cf[i] != CF_U) return 0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (strong[e]) {
+      const int j = ci[e];
+      if (cf[j] == CF_C || newc[j]) {
+        cf[i] = CF_F;
+        return 0;
+      }
+    }
+  return 1;
+}
+
 __global__ void k_pmis_select(const Tile* __restrict__ tiles, const int* __restrict__ rp,
                               const int* __restrict__ ci, const uint8_t* __restrict__ strong,
                               const int* __restrict__ st_rp, const int* __restrict__ st_ci,
@@ -110,26 +152,10 @@ __global__ void k_pmis_select(const Tile* __restrict__ tiles, const int* __restr
   Tile t = tiles[blockIdx.x];
   int i = t.r0 + threadIdx.x;
   if (i >= t.r1) return;
-  int sel = 0;
-  if (cf[i] == CF_U) {
-    uint64_t ki = key[i];
-    bool best = true;
-    for (int e = rp[i]; e < rp[i + 1] && best; ++e)
-      if (strong[e]) {
-        int j = ci[e];
-        if (cf[j] == CF_U && key[j] >= ki) best = false;
-      }
-    for (int e = st_rp[i]; e < st_rp[i + 1] && best; ++e) {
-      int j = st_ci[e];
-      if (cf[j] == CF_U && key[j] >= ki) best = false;
-    }
-    sel = best ? 1 : 0;
-  }
-  newc[i] = sel;
+  newc[i] = pmis_select_row(i, rp, ci, strong, st_rp, st_ci, cf, key);
 }
 
-// New C points are fixed; undecided points depending strongly on a C point
-// become F.  `left` counts the points still undecided.
+// `left` counts the points still undecided.
 __global__ void k_pmis_update(const Tile* __restrict__ tiles, const int* __restrict__ rp,
                               const int* __restrict__ ci, const uint8_t* __restrict__ strong,
                               int8_t* __restrict__ cf, const int* __restrict__ newc,
@@ -138,21 +164,58 @@ __global__ void k_pmis_update(const Tile* __restrict__ tiles, const int* __restr
   Tile t = tiles[blockIdx.x];
   int i = t.r0 + threadIdx.x;
   int und = 0;
-  if (i < t.r1) {
-    if (newc[i]) {
-      cf[i] = CF_C;
-    } else if (cf[i] == CF_U) {
-      bool f = false;
-      for (int e = rp[i]; e < rp[i + 1]; ++e)
-        if (strong[e]) {
-          int j = ci[e];
-          if (cf[j] == CF_C || newc[j]) { f = true; break; }
-        }
-      if (f) cf[i] = CF_F; else und = 1;
-    }
-  }
+  if (i < t.r1) und = pmis_update_row(i, rp, ci, strong, cf, newc);
   for (int o = 32; o > 0; o >>= 1) und += __shfl_xor(und, o);
   if ((threadIdx.x & 63) == 0 && und) atomicAdd(&left[round & 1], und);
+}
+
+// All rounds of a small level in one workgroup (rounds separated by
+// workgroup barriers instead of launches; the same rounds as the two kernels
+// above).  Stops after the first round that leaves no point undecided, or
+// after max_rounds.  left[0] = left[1] = points still undecided, left[2] =
+// rounds run.
+constexpr int kPmisSmallThreads = 1024;
+__global__ __launch_bounds__(kPmisSmallThreads) void k_pmis_small(
+    const Tile* __restrict__ tiles, int nt, const int* __restrict__ rp, const int* __restrict__ ci,
+    const uint8_t* __restrict__ strong, const int* __restrict__ st_rp, const int* __restrict__ st_ci,
+    int8_t* __restrict__ cf, const uint64_t* __restrict__ key, int* __restrict__ newc, int* __restrict__ left,
+    int max_rounds) {
+  __shared__ int s_und[kPmisSmallThreads / 64];
+  __shared__ int s_tot;
+  const int tid = threadIdx.x;
+  const int total = nt * kTileRows;
+  int rounds = 0, und_all = 0;
+  while (rounds < max_rounds) {
+    for (int t = tid; t < total; t += kPmisSmallThreads) {
+      const Tile tl = tiles[t / kTileRows];
+      const int i = tl.r0 + t % kTileRows;
+      if (i < tl.r1) newc[i] = pmis_select_row(i, rp, ci, strong, st_rp, st_ci, cf, key);
+    }
+    __syncthreads();
+    int und = 0;
+    for (int t = tid; t < total; t += kPmisSmallThreads) {
+      const Tile tl = tiles[t / kTileRows];
+      const int i = tl.r0 + t % kTileRows;
+      if (i < tl.r1) und += pmis_update_row(i, rp, ci, strong, cf, newc);
+    }
+    for (int o = 32; o > 0; o >>= 1) und += __shfl_xor(und, o);
+    if ((tid & 63) == 0) s_und[tid >> 6] = und;
+    __syncthreads();
+    if (tid == 0) {
+      int sum = 0;
+      for (int w = 0; w < kPmisSmallThreads / 64; ++w) sum += s_und[w];
+      s_tot = sum;
+    }
+    __syncthreads();
+    und_all = s_tot;
+    ++rounds;
+    if (und_all == 0) break;
+  }
+  if (tid == 0) {
+    left[0] = und_all;
+    left[1] = und_all;
+    left[2] = rounds;
+  }
 }
 
 __global__ void k_fill_cf(const Tile* __restrict__ tiles, int8_t* __restrict__ cf, int8_t val) {
@@ -2475,6 +2538,14 @@ void amg_pmis_update(const Tile* t, int nt, const int* rp, const int* ci, const 
                      int8_t* cf, const int* newc, int* left, int round, hipStream_t s) {
   if (!nt) return;
   hipLaunchKernelGGL(k_pmis_update, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, strong, cf, newc, left, round);
+  SHP_LAUNCH_CHECK();
+}
+void amg_pmis_small(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong, const int* st_rp,
+                    const int* st_ci, int8_t* cf, const uint64_t* key, int* newc, int* left, int max_rounds,
+                    hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_pmis_small, dim3(1), dim3(kPmisSmallThreads), 0, s, t, nt, rp, ci, strong, st_rp, st_ci, cf,
+                     key, newc, left, max_rounds);
   SHP_LAUNCH_CHECK();
 }
 void amg_fill_cf(const Tile* t, int nt, int8_t* cf, int8_t val, hipStream_t s) {

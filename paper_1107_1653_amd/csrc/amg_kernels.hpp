@@ -22,6 +22,13 @@ void amg_pmis_select(const Tile* t, int nt, const int* rp, const int* ci, const 
                      int* newc, int* left, int round, hipStream_t s);
 void amg_pmis_update(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
                      int8_t* cf, const int* newc, int* left, int round, hipStream_t s);
+// all PMIS rounds of a small level (tiles covering at most kPmisSmallRows rows,
+// one row per thread) in one workgroup; left[0] = points still undecided (0:
+// done), left[2] = rounds run
+constexpr int kPmisSmallRows = 1024;
+void amg_pmis_small(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong, const int* st_rp,
+                    const int* st_ci, int8_t* cf, const uint64_t* key, int* newc, int* left, int max_rounds,
+                    hipStream_t s);
 // PMIS round `round` (0, 1, ...): left[0..1] hold the undecided counts of the
 // last two rounds; a round after one that left nothing undecided does nothing
 // and lowers left[2] (set to a large value before round 0) to its number

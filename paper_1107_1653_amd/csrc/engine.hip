@@ -536,10 +536,18 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
                           stream);
         }
       };
-      // as many rounds as this level needed last time, plus one
+      // as many rounds as this level needed last time, plus one; a small
+      // level runs all its rounds in one workgroup (counted as one round:
+      // left[0] then holds the points still undecided)
       if ((int)pmis_need.size() <= l) pmis_need.resize(l + 1, 5);
       fill_async(s_left.p + 2, INT_MAX, 1, stream);
-      pmis_rounds(std::max(2, std::min(pmis_need[l] + 1, 12)));
+      if (L.nctiles * kTileRows <= kPmisSmallRows) {
+        amg_pmis_small(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.strong.p, L.st_rp.p, L.st_ci.p, L.cf.p, L.key.p,
+                       s_newc.p, s_left.p, 64, stream);
+        round = 1;
+      } else {
+        pmis_rounds(std::max(2, std::min(pmis_need[l] + 1, 12)));
+      }
       pt.mark("pmis");
       // ---- coarse numbering and per-game coarse sizes
       auto number = [&](std::vector<int>& ncg) {
