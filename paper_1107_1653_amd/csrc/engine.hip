@@ -398,9 +398,9 @@ int Engine::tune_lanes(Level& L, bool mixed) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     flush = flush_buffer();
   }
-  hipEvent_t e0, e1;
-  SHP_HIP(hipEventCreate(&e0));
-  SHP_HIP(hipEventCreate(&e1));
+  hipEvent_t e0, e1;  // timing only: no system-scope fence
+  SHP_HIP(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+  SHP_HIP(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
   int best = rule;
   float best_ms = INFINITY;
   for (int g : {1, 2, 4}) {

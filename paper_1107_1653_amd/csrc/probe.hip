@@ -53,8 +53,10 @@ void flush(Family& f) {
 
 hipEvent_t take(Family& f) {
   if (f.pool.empty()) {
+    // timing only: no system-scope fence (no cache writeback and invalidation
+    // at each record, which would slow the work being timed)
     hipEvent_t e;
-    SHP_HIP(hipEventCreate(&e));
+    SHP_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     return e;
   }
   hipEvent_t e = f.pool.back();
