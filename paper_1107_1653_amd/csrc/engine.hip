@@ -676,8 +676,12 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
             up(L.drap_tab.p, t.data(), t.size());
           }
         }
-        probe_begin(kProbeRap, stream);
+        // probed launches: the dense product, the single pass R A P, or each
+        // pass of R (A P) (the product kernels only: bounds, scans and the
+        // synchronisation between the passes left out)
+        const double rap_bytes = (double)L.nnz * 12 + (double)n * PW * 12 + (double)nc * 8;
         if (L.drap) {
+          probe_begin(kProbeRap, stream);
           L.dap.ensure(std::max<long long>(L.drap_ap, 1));
           s_dapt.ensure(std::max<long long>(L.drap_ap, 1));
           s_dac.ensure(std::max<long long>(L.drap_ac, 1));
@@ -685,6 +689,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
           amg_drap_full(n, nc, L.drap_maxc, L.drap_tab.p, G, L.drap_ac, L.rp.p, L.ci.p, L.a64.p, L.pc.p,
                         L.pv64.p, L.rrp.p, L.rci.p, L.rv64.p, L.dap.p, s_dapt.p, s_dac.p, s_dacf.p, s_cnt.p,
                         stream);
+          probe_end(kProbeRap, stream, rap_bytes);
         } else {
           // the single pass R A P, or for long rows A P first and R (AP) after
           const int* Arp = L.rp.p;
@@ -705,19 +710,22 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
             s_cnt.ensure((size_t)n + 1);
             s_toff.ensure((size_t)n + 1);
             s_big.ensure((size_t)n + 1);
-            amg_rap_bound(n, L.id_rp.p, L.id_ci.p, L.rp.p, s_cnt.p, PW, stream);
-            scan_exclusive(s_cnt.p, s_toff.p, n + 1, stream, s_scan);
             const size_t tcap1 = std::max<size_t>(
                 1, std::min((size_t)PW * (size_t)std::max(L.nnz, 1), (size_t)n * (size_t)kRapMaxCols));
             s_tcol.ensure(tcap1);
             s_tval.ensure(tcap1);
+            amg_rap_bound(n, L.id_rp.p, L.id_ci.p, L.rp.p, s_cnt.p, PW, stream);
+            scan_exclusive(s_cnt.p, s_toff.p, n + 1, stream, s_scan);
+            probe_begin(kProbeRap, stream);
             amg_rap_fused(n, L.id_rp.p, L.id_ci.p, L.id_rv.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p,
                           s_toff.p, s_cnt.p, s_tcol.p, s_tval.p, s_err.p + 1, s_big.p, stream);
+            probe_end(kProbeRap, stream, (double)L.nnz * 12 + (double)n * PW * 12);
             L.ap_rp.ensure((size_t)n + 1);
             scan_exclusive(s_cnt.p, L.ap_rp.p, n + 1, stream, s_scan);
             const int* pap = down(L.ap_rp.p + n, 1);
             sync();
             L.ap_nnz = *pap;
+            probe_add_bytes(kProbeRap, (double)L.ap_nnz * 12);  // A P written by that pass
             L.ap_ci.ensure(std::max(L.ap_nnz, 1));
             L.ap_v.ensure(std::max(L.ap_nnz, 1));
             amg_rap_compact(n, s_toff.p, s_tcol.p, s_tval.p, L.ap_rp.p, L.ap_ci.p, L.ap_v.p, stream);
@@ -729,18 +737,19 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
             pwf = 1;
             opnnz = (size_t)std::max(L.ap_nnz, 1);
           }
-          amg_rap_bound(nc, L.rrp.p, L.rci.p, Arp, s_cnt.p, pwf, stream);
-          scan_exclusive(s_cnt.p, s_toff.p, nc + 1, stream, s_scan);
           // sum of the bounds <= pwf * (pairs) <= pwf * PW * nnz(operand)
           const size_t tcap = std::max<size_t>(
               1, std::min((size_t)pwf * PW * opnnz, (size_t)nc * (size_t)kRapMaxCols));
           s_tcol.ensure(tcap);
           s_tval.ensure(tcap);
           s_big.ensure((size_t)std::max(n, nc) + 1);
+          amg_rap_bound(nc, L.rrp.p, L.rci.p, Arp, s_cnt.p, pwf, stream);
+          scan_exclusive(s_cnt.p, s_toff.p, nc + 1, stream, s_scan);
+          probe_begin(kProbeRap, stream);
           amg_rap_fused(nc, L.rrp.p, L.rci.p, L.rv64.p, Arp, Aci, Aa, Ppc, Ppv, s_toff.p, s_cnt.p, s_tcol.p,
                         s_tval.p, s_err.p + 1, s_big.p, stream);
+          probe_end(kProbeRap, stream, L.apf ? (double)L.ap_nnz * 12 + (double)nc * 8 : rap_bytes);
         }
-        probe_end(kProbeRap, stream, (double)L.nnz * 12 + (double)n * PW * 12 + (double)nc * 8);
         scan_exclusive(s_cnt.p, Ln.rp.p, nc + 1, stream, s_scan);
         int cnnz = 0, rnnz_used = 0;
         const int* pc_nnz = down(Ln.rp.p + nc, 1);
@@ -970,24 +979,30 @@ void Engine::refresh(const EngineOpts& o) {
       Ln.chg.ensure(std::max(L.nc, 1));
       fill_async(Ln.chg.p, (uint8_t)0, (size_t)std::max(L.nc, 1), stream);
       amg_mark_coarse(L.ctiles.p, L.nctiles, L.pc.p, L.chg.p, Ln.chg.p, stream);
-      probe_begin(kProbeRap, stream);
       if (L.drap) {
+        probe_begin(kProbeRap, stream);
         // the A P rows of the changed fine rows, then the coarse rows they reach
         amg_drap_known(L.n, L.nc, L.drap_maxc, L.drap_tab.p, G, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p,
                        L.rrp.p, L.rci.p, L.rv64.p, L.dap.p, Ln.rp.p, Ln.ci.p, Ln.a64.p, stream, Ln.chg.p, L.chg.p);
+        probe_end(kProbeRap, stream, (double)Ln.nnz * 12 + (double)L.nnz * 12 + (double)n * PW * 12);
       } else if (L.apf) {
         // A P rows of the changed fine rows, then the coarse rows they reach
         s_big.ensure((size_t)std::max(n, L.nc) + 1);
+        probe_begin(kProbeRap, stream);
         amg_rap_known(n, L.id_rp.p, L.id_ci.p, L.id_rv.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, L.ap_rp.p,
                       L.ap_ci.p, L.ap_v.p, s_err.p + 1, s_big.p, stream, L.chg.p);
+        probe_end(kProbeRap, stream, (double)L.ap_nnz * 12 + (double)L.nnz * 12 + (double)n * PW * 12);
+        probe_begin(kProbeRap, stream);
         amg_rap_known(L.nc, L.rrp.p, L.rci.p, L.rv64.p, L.ap_rp.p, L.ap_ci.p, L.ap_v.p, L.id_pc.p, L.id_pv.p,
                       Ln.rp.p, Ln.ci.p, Ln.a64.p, s_err.p + 1, s_big.p, stream, Ln.chg.p);
+        probe_end(kProbeRap, stream, (double)Ln.nnz * 12 + (double)L.ap_nnz * 12);
       } else {
         s_big.ensure((size_t)L.nc + 1);
+        probe_begin(kProbeRap, stream);
         amg_rap_known(L.nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, Ln.rp.p,
                       Ln.ci.p, Ln.a64.p, s_err.p + 1, s_big.p, stream, Ln.chg.p);
+        probe_end(kProbeRap, stream, (double)Ln.nnz * 12 + (double)L.nnz * 12 + (double)n * PW * 12);
       }
-      probe_end(kProbeRap, stream, (double)Ln.nnz * 12 + (double)L.nnz * 12 + (double)n * PW * 12);
     }
     if (L.nblk)
       amg_dense_inv(L.blk.p, L.nblk, L.rp.p, L.ci.p, L.a64.p, s_dense.p, L.dmat64.p, mixed ? L.dmat32.p : nullptr,
