@@ -77,6 +77,52 @@ __global__ void k_strength_t(const Tile* __restrict__ tiles, const int* __restri
     }
 }
 
+// the same two passes with one wavefront per row (levels with long rows):
+// the row maximum by a wavefront reduction (the maximum does not depend on
+// the order), the flags and counts by the lanes over the entries
+__global__ __launch_bounds__(256) void k_strength_w(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                                                    const int* __restrict__ ci, const double* __restrict__ a,
+                                                    const uint8_t* __restrict__ dir, double theta,
+                                                    uint8_t* __restrict__ strong, int* __restrict__ lam) {
+  const Tile t = tiles[blockIdx.x / (kTileRows / 4)];
+  const int i = t.r0 + (int)(blockIdx.x % (kTileRows / 4)) * 4 + (int)(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= t.r1) return;  // per wavefront
+  const int e0 = rp[i], e1 = rp[i + 1];
+  const bool di = dir[i] != 0;
+  double m = 0.0;
+  if (!di)
+    for (int e = e0 + lane; e < e1; e += 64) {
+      const int j = ci[e];
+      if (j != i && !dir[j]) m = fmax(m, -a[e]);
+    }
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  for (int e = e0 + lane; e < e1; e += 64) {
+    const int j = ci[e];
+    const bool st = !di && j != i && !dir[j] && m > 0.0 && -a[e] >= theta * m;
+    strong[e] = st ? 1 : 0;
+    if (st) atomicAdd(&lam[j], 1);
+  }
+}
+
+// transpose with one wavefront per row (the order within a transposed row
+// follows the atomics, as above; PMIS does not depend on it)
+__global__ __launch_bounds__(256) void k_strength_t_w(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                                                      const int* __restrict__ ci, const uint8_t* __restrict__ strong,
+                                                      const int* __restrict__ st_rp, int* __restrict__ cursor,
+                                                      int* __restrict__ st_ci) {
+  const Tile t = tiles[blockIdx.x / (kTileRows / 4)];
+  const int i = t.r0 + (int)(blockIdx.x % (kTileRows / 4)) * 4 + (int)(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= t.r1) return;
+  for (int e = rp[i] + lane; e < rp[i + 1]; e += 64)
+    if (strong[e]) {
+      const int j = ci[e];
+      const int pos = atomicAdd(&cursor[j], 1);
+      st_ci[st_rp[j] + pos] = i;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // PMIS (parallel maximal independent set) C/F splitting
 // ---------------------------------------------------------------------------
@@ -2508,16 +2554,24 @@ void amg_dir_scale(const Tile* t, int nt, const uint8_t* dir, double f, double* 
   SHP_LAUNCH_CHECK();
 }
 void amg_strength(const Tile* t, int nt, const int* rp, const int* ci, const double* a,
-                  const uint8_t* dir, double theta, uint8_t* strong, int* lam, hipStream_t s) {
+                  const uint8_t* dir, double theta, uint8_t* strong, int* lam, bool wide, hipStream_t s) {
   if (!nt) return;
-  hipLaunchKernelGGL(k_strength, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, a, dir, theta, strong, lam);
+  if (wide)
+    hipLaunchKernelGGL(k_strength_w, dim3(nt * (kTileRows / 4)), dim3(256), 0, s, t, rp, ci, a, dir, theta, strong,
+                       lam);
+  else
+    hipLaunchKernelGGL(k_strength, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, a, dir, theta, strong, lam);
   SHP_LAUNCH_CHECK();
 }
 void amg_strength_t(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
-                    const int* st_rp, int* cursor, int* st_ci, hipStream_t s) {
+                    const int* st_rp, int* cursor, int* st_ci, bool wide, hipStream_t s) {
   if (!nt) return;
-  hipLaunchKernelGGL(k_strength_t, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, strong, st_rp, cursor,
-                     st_ci);
+  if (wide)
+    hipLaunchKernelGGL(k_strength_t_w, dim3(nt * (kTileRows / 4)), dim3(256), 0, s, t, rp, ci, strong, st_rp,
+                       cursor, st_ci);
+  else
+    hipLaunchKernelGGL(k_strength_t, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, strong, st_rp, cursor,
+                       st_ci);
   SHP_LAUNCH_CHECK();
 }
 void amg_pmis_init(const Tile* t, int nt, const int* goff, const uint8_t* dir, const int* lam,

@@ -11,10 +11,11 @@ void amg_diag_dir(const Tile* t, int nt, const int* rp, const int* ci, const dou
                   double inv_omega, uint8_t* dir, double* d64, float* d32, int g, hipStream_t s);
 void amg_dir_scale(const Tile* t, int nt, const uint8_t* dir, double f, double* d64, float* d32,
                    hipStream_t s);
+// wide: one wavefront per row (levels whose rows are long)
 void amg_strength(const Tile* t, int nt, const int* rp, const int* ci, const double* a,
-                  const uint8_t* dir, double theta, uint8_t* strong, int* lam, hipStream_t s);
+                  const uint8_t* dir, double theta, uint8_t* strong, int* lam, bool wide, hipStream_t s);
 void amg_strength_t(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
-                    const int* st_rp, int* cursor, int* st_ci, hipStream_t s);
+                    const int* st_rp, int* cursor, int* st_ci, bool wide, hipStream_t s);
 void amg_pmis_init(const Tile* t, int nt, const int* goff, const uint8_t* dir, const int* lam,
                    uint32_t salt, int8_t* cf, uint64_t* key, hipStream_t s);
 void amg_pmis_select(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,

@@ -505,7 +505,8 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
       fill_async(L.strong.p, (uint8_t)0, (size_t)L.nnz, stream);
       fill_async(L.dir.p, (uint8_t)1, (size_t)n, stream);
       amg_dirichlet(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, L.dir.p, stream);
-      amg_strength(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, L.dir.p, theta, L.strong.p, L.lam.p,
+      const bool wide_rows = (long long)L.nnz > (long long)kApRowLen * n;  // one wavefront per row
+      amg_strength(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, L.dir.p, theta, L.strong.p, L.lam.p, wide_rows,
                    stream);
       // Dirichlet rows are relaxed exactly (unit weight)
       amg_dir_scale(L.ctiles.p, L.nctiles, L.dir.p, 1.0 / o.omega, L.dinv64.p, mixed ? L.dinv32.p : nullptr,
@@ -516,7 +517,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
       L.st_ci.ensure(std::max(L.nnz, 1));  // strong entries never exceed the entries of A
       s_cursor.ensure(n + 1);
       fill_async(s_cursor.p, 0, (size_t)n + 1, stream);
-      amg_strength_t(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.strong.p, L.st_rp.p, s_cursor.p, L.st_ci.p,
+      amg_strength_t(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.strong.p, L.st_rp.p, s_cursor.p, L.st_ci.p, wide_rows,
                      stream);
       pt.mark("strength");
       // ---- PMIS
