@@ -215,6 +215,69 @@ __global__ void k_pmis_update(const Tile* __restrict__ tiles, const int* __restr
   if ((threadIdx.x & 63) == 0 && und) atomicAdd(&left[round & 1], und);
 }
 
+// The same two kernels with one wavefront per row (levels with long rows):
+// the lanes test the entries, a ballot decides the row; the outcome is the
+// one the kernels above give.
+__global__ __launch_bounds__(256) void k_pmis_select_w(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                                                       const int* __restrict__ ci, const uint8_t* __restrict__ strong,
+                                                       const int* __restrict__ st_rp, const int* __restrict__ st_ci,
+                                                       const int8_t* __restrict__ cf, const uint64_t* __restrict__ key,
+                                                       int* __restrict__ newc, int* __restrict__ left, int round) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    left[round & 1] = 0;
+    if (round > 0 && left[(round - 1) & 1] == 0) atomicMin(&left[2], round);
+  }
+  if (round > 0 && left[(round - 1) & 1] == 0) return;
+  const Tile t = tiles[blockIdx.x / (kTileRows / 4)];
+  const int i = t.r0 + (int)(blockIdx.x % (kTileRows / 4)) * 4 + (int)(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= t.r1) return;  // per wavefront
+  if (cf[i] != CF_U) {
+    if (lane == 0) newc[i] = 0;
+    return;
+  }
+  const uint64_t ki = key[i];
+  bool beaten = false;
+  for (int e = rp[i] + lane; e < rp[i + 1] && !beaten; e += 64)
+    if (strong[e]) {
+      const int j = ci[e];
+      beaten = cf[j] == CF_U && key[j] >= ki;
+    }
+  for (int e = st_rp[i] + lane; e < st_rp[i + 1] && !beaten; e += 64) {
+    const int j = st_ci[e];
+    beaten = cf[j] == CF_U && key[j] >= ki;
+  }
+  const bool any = __ballot(beaten) != 0;
+  if (lane == 0) newc[i] = any ? 0 : 1;
+}
+
+__global__ __launch_bounds__(256) void k_pmis_update_w(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                                                       const int* __restrict__ ci, const uint8_t* __restrict__ strong,
+                                                       int8_t* __restrict__ cf, const int* __restrict__ newc,
+                                                       int* __restrict__ left, int round) {
+  if (round > 0 && left[(round - 1) & 1] == 0) return;
+  const Tile t = tiles[blockIdx.x / (kTileRows / 4)];
+  const int i = t.r0 + (int)(blockIdx.x % (kTileRows / 4)) * 4 + (int)(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= t.r1) return;
+  if (newc[i]) {
+    if (lane == 0) cf[i] = CF_C;
+    return;
+  }
+  if (cf[i] != CF_U) return;
+  bool hit = false;
+  for (int e = rp[i] + lane; e < rp[i + 1] && !hit; e += 64)
+    if (strong[e]) {
+      const int j = ci[e];
+      hit = cf[j] == CF_C || newc[j];
+    }
+  const bool any = __ballot(hit) != 0;
+  if (lane == 0) {
+    if (any) cf[i] = CF_F;
+    else atomicAdd(&left[round & 1], 1);
+  }
+}
+
 // All rounds of a small level in one workgroup (rounds separated by
 // workgroup barriers instead of launches; the same rounds as the two kernels
 // above).  Stops after the first round that leaves no point undecided, or
@@ -2582,16 +2645,24 @@ void amg_pmis_init(const Tile* t, int nt, const int* goff, const uint8_t* dir, c
 }
 void amg_pmis_select(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
                      const int* st_rp, const int* st_ci, const int8_t* cf, const uint64_t* key,
-                     int* newc, int* left, int round, hipStream_t s) {
+                     int* newc, int* left, int round, bool wide, hipStream_t s) {
   if (!nt) return;
-  hipLaunchKernelGGL(k_pmis_select, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, strong, st_rp, st_ci,
-                     cf, key, newc, left, round);
+  if (wide)
+    hipLaunchKernelGGL(k_pmis_select_w, dim3(nt * (kTileRows / 4)), dim3(256), 0, s, t, rp, ci, strong, st_rp,
+                       st_ci, cf, key, newc, left, round);
+  else
+    hipLaunchKernelGGL(k_pmis_select, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, strong, st_rp, st_ci,
+                       cf, key, newc, left, round);
   SHP_LAUNCH_CHECK();
 }
 void amg_pmis_update(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
-                     int8_t* cf, const int* newc, int* left, int round, hipStream_t s) {
+                     int8_t* cf, const int* newc, int* left, int round, bool wide, hipStream_t s) {
   if (!nt) return;
-  hipLaunchKernelGGL(k_pmis_update, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, strong, cf, newc, left, round);
+  if (wide)
+    hipLaunchKernelGGL(k_pmis_update_w, dim3(nt * (kTileRows / 4)), dim3(256), 0, s, t, rp, ci, strong, cf, newc,
+                       left, round);
+  else
+    hipLaunchKernelGGL(k_pmis_update, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, strong, cf, newc, left, round);
   SHP_LAUNCH_CHECK();
 }
 void amg_pmis_small(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong, const int* st_rp,

@@ -20,9 +20,9 @@ void amg_pmis_init(const Tile* t, int nt, const int* goff, const uint8_t* dir, c
                    uint32_t salt, int8_t* cf, uint64_t* key, hipStream_t s);
 void amg_pmis_select(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
                      const int* st_rp, const int* st_ci, const int8_t* cf, const uint64_t* key,
-                     int* newc, int* left, int round, hipStream_t s);
+                     int* newc, int* left, int round, bool wide, hipStream_t s);
 void amg_pmis_update(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
-                     int8_t* cf, const int* newc, int* left, int round, hipStream_t s);
+                     int8_t* cf, const int* newc, int* left, int round, bool wide, hipStream_t s);
 // all PMIS rounds of a small level (tiles covering at most kPmisSmallRows rows,
 // one row per thread) in one workgroup; left[0] = points still undecided (0:
 // done), left[2] = rounds run

@@ -529,12 +529,15 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
       // rounds are queued in bursts; the undecided count is checked with the
       // coarse numbering below (rounds after the last undecided row do nothing)
       int round = 0;
+      // PMIS rounds take a wavefront per row only where one thread per row
+      // would leave the chip mostly idle (long rows, few of them)
+      const bool wide_pmis = wide_rows && n < (1 << 17);
       auto pmis_rounds = [&](int k) {
         for (int rr = 0; rr < k; ++rr, ++round) {
           amg_pmis_select(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.strong.p, L.st_rp.p, L.st_ci.p, L.cf.p,
-                          L.key.p, s_newc.p, s_left.p, round, stream);
+                          L.key.p, s_newc.p, s_left.p, round, wide_pmis, stream);
           amg_pmis_update(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.strong.p, L.cf.p, s_newc.p, s_left.p, round,
-                          stream);
+                          wide_pmis, stream);
         }
       };
       // as many rounds as this level needed last time, plus one; a small
