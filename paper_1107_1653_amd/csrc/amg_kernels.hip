@@ -2592,6 +2592,25 @@ __global__ __launch_bounds__(256) void k_update64(const Tile* __restrict__ tiles
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+// the per-level flags before strength and PMIS, in one launch: lam = 0
+// (n + 1 entries), cf = -2 (rows of games that end on this level) and dir = 1 (n), strong = 0 (nnz)
+__global__ void k_level_init(int n, int nnz, int* __restrict__ lam, int8_t* __restrict__ cf,
+                             uint8_t* __restrict__ dir, uint8_t* __restrict__ strong) {
+  const int m = max(n + 1, nnz);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+    if (i <= n) lam[i] = 0;
+    if (i < n) {
+      cf[i] = -2;
+      dir[i] = 1;
+    }
+    if (i < nnz) strong[i] = 0;
+  }
+}
+void amg_level_init(int n, int nnz, int* lam, int8_t* cf, uint8_t* dir, uint8_t* strong, hipStream_t s) {
+  const int m = std::max(n + 1, nnz);
+  hipLaunchKernelGGL(k_level_init, dim3(grid_for(m)), dim3(kBlock), 0, s, n, nnz, lam, cf, dir, strong);
+  SHP_LAUNCH_CHECK();
+}
 void amg_dirichlet(const Tile* t, int nt, const int* rp, const int* ci, const double* a, uint8_t* dir,
                    hipStream_t s) {
   if (!nt) return;

@@ -5,6 +5,8 @@
 
 namespace shp {
 
+// lam[0..n] = 0, cf[0..n) = -2, dir[0..n) = 1, strong[0..nnz) = 0
+void amg_level_init(int n, int nnz, int* lam, int8_t* cf, uint8_t* dir, uint8_t* strong, hipStream_t s);
 void amg_dirichlet(const Tile* t, int nt, const int* rp, const int* ci, const double* a, uint8_t* dir,
                    hipStream_t s);
 void amg_diag_dir(const Tile* t, int nt, const int* rp, const int* ci, const double* a, bool keep_diag,

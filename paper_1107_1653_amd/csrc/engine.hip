@@ -500,10 +500,8 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
       L.key.ensure(std::max(n, 1));
       L.cidx.ensure(n + 1);
       L.tmp.ensure(n + 1);
-      fill_async(L.lam.p, 0, (size_t)n + 1, stream);
-      fill_async(L.cf.p, (int8_t)-2, (size_t)n, stream);  // CF_X for rows of terminal games
-      fill_async(L.strong.p, (uint8_t)0, (size_t)L.nnz, stream);
-      fill_async(L.dir.p, (uint8_t)1, (size_t)n, stream);
+      // cf = -2 on rows of terminal games, which no tile covers
+      amg_level_init(n, L.nnz, L.lam.p, L.cf.p, L.dir.p, L.strong.p, stream);
       amg_dirichlet(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, L.dir.p, stream);
       const bool wide_rows = (long long)L.nnz > (long long)kApRowLen * n;  // one wavefront per row
       amg_strength(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, L.dir.p, theta, L.strong.p, L.lam.p, wide_rows,
