@@ -356,3 +356,35 @@ def scale_rows_to_stochastic(g: Game) -> Game:
         a, b = g.row_ptr[i], g.row_ptr[i + 1]
         w[a:b] /= w[a:b].sum()
     return dataclasses.replace(g, w=w)
+
+
+def with_copied_action(g: Game, player: int, src: int, pos: int, dr: float = 0.0) -> Game:
+    """Copy of `g` with one more action for `player` (1 = MAX, 2 = MIN),
+    inserted at index `pos`, whose rows repeat those of action `src` (indices
+    before the insertion) at every state, with `dr` added to their rewards.
+    With dr = 0 every state has two actions of identical value: a planted
+    exact tie (Sec. 2: argmax and argmin are sets)."""
+    m1, m2 = g.m1, g.m2
+    m1n, m2n = (m1 + 1, m2) if player == 1 else (m1, m2 + 1)
+    src_rows = []  # for each new row (x, a, b): the old row it copies
+    for x in range(g.n):
+        for a in range(m1n):
+            for b in range(m2n):
+                if player == 1:
+                    ao = src if a == pos else (a if a < pos else a - 1)
+                    bo = b
+                else:
+                    ao = a
+                    bo = src if b == pos else (b if b < pos else b - 1)
+                src_rows.append(((x * m1 + ao) * m2 + bo, (a == pos) if player == 1 else (b == pos)))
+    idx = np.array([s for s, _ in src_rows], dtype=np.int64)
+    new = np.array([c for _, c in src_rows], dtype=bool)
+    counts = g.row_ptr[idx + 1] - g.row_ptr[idx]
+    row_ptr = np.zeros(len(idx) + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    take = np.concatenate([np.arange(g.row_ptr[i], g.row_ptr[i + 1]) for i in idx]).astype(np.int64)
+    r = g.r[idx].copy()
+    r[new] += dr
+    valid = None if g.valid is None else g.valid[idx].copy()
+    return Game(g.n, m1n, m2n, row_ptr, g.col[take].copy(), g.w[take].copy(), r, g.mu, valid, g.grid,
+                meta=dict(g.meta, copied=(player, src, pos, dr)))

@@ -164,8 +164,17 @@ def test_server_continuous_batching_matches_alone():
         while steps < 3:
             max_active = max(max_active, P.shapley_server_step(srv))
             steps += 1
+        running_early = [t for t in tickets if P.shapley_server_poll(srv, t) is None]
         tickets += [P.shapley_server_submit(srv, hs[k], o) for k in range(3, 6)]
         tf = P.shapley_server_submit(srv, H, of)
+        # the later requests are admitted while earlier ones are on the device
+        act = P.shapley_server_step(srv)
+        steps += 1
+        overlap = [t for t in running_early if P.shapley_server_poll(srv, t) is None]
+        max_active = max(max_active, act)
+        log(f"  running when the second wave was submitted: {len(running_early)}, "
+            f"info {P.shapley_server_info(srv)}")
+        assert running_early and max_active >= 2
         while True:
             act = P.shapley_server_step(srv)
             max_active = max(max_active, act)
@@ -239,3 +248,46 @@ def test_workspace_reuse_and_release():
     np.testing.assert_array_equal(P.shapley_get_value(hc), v1)
     P.shapley_game_destroy(hc)
     log("  workspace reuse ok")
+
+
+def test_planted_exact_ties_greedy_and_solve():
+    """Copied actions plant exact ties (bit-identical rows) at every state.
+    The HIP greedy sweep at random v takes the lowest index attaining each
+    extremum, exactly as the oracle's (Sec. 2: argmax/argmin are sets; the
+    reading fixes the lowest index); policy iteration reaches the value of the
+    game without the copies, and its choices at tied states are extrema."""
+    base = configs.c0(s=17)
+    g = games.with_copied_action(games.with_copied_action(base, 1, 1, 3), 2, 0, 1)
+    h = P.create_from(g)
+    try:
+        rng = np.random.default_rng(3)
+        for k in range(3):
+            v = rng.normal(size=g.n) * 0.1
+            F, a, b = P.shapley_apply_operator(h, v)
+            ao, bo = oracle.greedy(g, v)
+            np.testing.assert_allclose(F, oracle.shapley_operator(g, v), rtol=0, atol=1e-13)
+            np.testing.assert_array_equal(a, ao)
+            np.testing.assert_array_equal(b, bo)
+    finally:
+        P.shapley_game_destroy(h)
+    ref0 = oracle.policy_iteration(base)
+    ref = oracle.policy_iteration(g)
+    for prec, tol in ((P.SHAPLEY_FP64, 1e-9), (P.SHAPLEY_MIXED, 1e-6)):
+        v, a, b, st = solve_gpu(g, precision=prec, **LIMITS)
+        err, ma, mb, tied = compare_with_oracle(g, v, a, b, ref, tol)
+        e0 = np.max(np.abs(v - ref0.v)) / np.max(np.abs(ref0.v))
+        log(f"  planted ties prec {prec}: err {err:.2e} vs untied game {e0:.2e} tied {tied.sum()}/{g.n}")
+        assert st["converged"] == 1 and err <= tol and e0 <= tol
+        assert tied.sum() > g.n // 4
+        assert len(ma) == 0 and len(mb) == 0
+
+
+def test_planted_ties_random_general_game():
+    """Random general game with invalid pairs and copied actions (dense path)."""
+    base = games.random_game(50, 2, 3, 91, mu=0.9, density=0.2, invalid_frac=0.2)
+    g = games.with_copied_action(games.with_copied_action(base, 1, 0, 2), 2, 2, 1)
+    ref = oracle.policy_iteration(g)
+    v, a, b, st = solve_gpu(g, **LIMITS)
+    err, ma, mb, tied = compare_with_oracle(g, v, a, b, ref, 1e-9)
+    log(f"  random planted ties: err {err:.2e} tied {tied.sum()}/{g.n}")
+    assert err <= 1e-9 and len(ma) == 0 and len(mb) == 0 and tied.any()

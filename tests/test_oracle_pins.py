@@ -184,6 +184,180 @@ def test_one_player_matches_linear_program(seed):
 
 
 # ---------------------------------------------------------------------------
+# greedy selectors and the tie rule.  argmax and argmin are sets (Sec. 2); the
+# reading used by both sides: the lowest index attaining the extremum, and in
+# policy iteration (Algorithm algo-MDP step 2, Algorithm PIalgo step 2) the
+# incumbent kept unless another action beats it by more than a rounding bound.
+# Exact ties are planted by copying an action (its rows repeat bit for bit).
+# ---------------------------------------------------------------------------
+
+def q_loops(g, v):
+    """Q[x][a][b] = r + mu sum w v by plain loops (None for invalid pairs)."""
+    rows = rows_of(g)
+    Q = []
+    for x in range(g.n):
+        Qa = []
+        for a in range(g.m1):
+            Qb = []
+            for b in range(g.m2):
+                if not valid_of(g, x, a, b):
+                    Qb.append(None)
+                    continue
+                i = (x * g.m1 + a) * g.m2 + b
+                cols, ws = rows[i]
+                Qb.append(g.r[i] + g.mu * sum(w * v[c] for c, w in zip(cols, ws)))
+            Qa.append(Qb)
+        Q.append(Qa)
+    return Q
+
+
+def lowest_argmin(vals):
+    best, arg = math.inf, -1
+    for k, q in enumerate(vals):
+        if q is not None and q < best:
+            best, arg = q, k
+    return arg, best
+
+
+def greedy_loops(g, v):
+    """Lowest-index argmax_a min_b Q and the lowest-index argmin_b at it."""
+    Q = q_loops(g, v)
+    alpha, beta = [], []
+    for x in range(g.n):
+        best, ba = -math.inf, -1
+        for a in range(g.m1):
+            _, mn = lowest_argmin(Q[x][a])
+            if mn < math.inf and mn > best:
+                best, ba = mn, a
+        alpha.append(ba)
+        beta.append(lowest_argmin(Q[x][ba])[0])
+    return np.array(alpha), np.array(beta)
+
+
+def tie_game(seed, n=40, inv=0.0):
+    """MAX's action 2 repeats its action 0; MIN's new action 1 repeats its old
+    action 2, which moves to index 3 (the copy has the lower index)."""
+    base = games.random_game(n, 2, 3, seed, mu=0.9, density=0.3, invalid_frac=inv)
+    return games.with_copied_action(games.with_copied_action(base, 1, 0, 2), 2, 2, 1)
+
+
+@pytest.mark.parametrize("seed,inv", [(50, 0.0), (51, 0.25), (52, 0.4)])
+def test_greedy_matches_plain_loops_with_invalid_actions_and_ties(seed, inv):
+    g = tie_game(seed, inv=inv)
+    rng = np.random.default_rng(seed)
+    ties_a = ties_b = 0
+    for _ in range(4):
+        v = rng.normal(size=g.n)
+        a_ref, b_ref = greedy_loops(g, v)
+        a, b = oracle.greedy(g, v)
+        np.testing.assert_array_equal(a, a_ref)
+        np.testing.assert_array_equal(b, b_ref)
+        Q = q_loops(g, v)
+        for x in range(g.n):
+            inner = [lowest_argmin(Q[x][k])[1] for k in range(g.m1)]
+            ties_a += inner[0] == max(inner) and inner[0] < math.inf
+            qa = Q[x][a_ref[x]]
+            ties_b += qa[1] is not None and qa[1] == lowest_argmin(qa)[1]
+            assert qa[1] == qa[3]
+        # chosen actions are valid and attain the extremum
+        for x in range(g.n):
+            assert valid_of(g, x, a[x], b[x])
+    assert ties_a > 0 and ties_b > 0   # the planted ties were exercised
+
+
+def test_improve_keeps_incumbent_at_planted_ties():
+    """With (alpha, beta) incumbents: a tied incumbent is kept, a strictly
+    beaten one is replaced by the lowest index attaining the extremum, and MIN's
+    answer at a changed alpha has no incumbent (lowest index)."""
+    g = tie_game(60, n=60)
+    rng = np.random.default_rng(60)
+    v = rng.normal(size=g.n)
+    Q = q_loops(g, v)
+    Qo, scale = oracle.q_values(g, v)
+    margin = 1e-9
+    a_inc = np.zeros(g.n, np.int32)
+    b_inc = np.zeros(g.n, np.int32)
+    expect_a, expect_bin = {}, {}
+    for x in range(g.n):
+        inner = [lowest_argmin(Q[x][k])[1] for k in range(g.m1)]
+        top = max(inner)
+        if inner[0] == top and inner[1] < top - margin:
+            a_inc[x] = 2 if x % 2 else 1           # tied copy kept / beaten action replaced by 0
+            expect_a[x] = 2 if x % 2 else 0
+        elif inner[1] == top and inner[0] < top - margin:
+            a_inc[x] = 2
+            expect_a[x] = 1
+        else:
+            a_inc[x] = 1
+        qa = Q[x][a_inc[x]]
+        mn = lowest_argmin(qa)[1]
+        if qa[3] == mn and qa[0] > mn + margin:
+            b_inc[x] = 3 if x % 2 else 0           # tied original kept / beaten b replaced by the copy (1)
+            expect_bin[x] = 3 if x % 2 else 1
+        else:
+            b_inc[x] = lowest_argmin(qa)[0]
+    beta_in, F, alpha_out, beta_out = oracle.shapley_oracle._improve(g, Qo, scale, a_inc, b_inc)
+    assert len(expect_a) >= 10 and len(expect_bin) >= 10
+    for x, e in expect_a.items():
+        assert alpha_out[x] == e, x
+    for x, e in expect_bin.items():
+        assert beta_in[x] == e, x
+    for x in range(g.n):
+        assert F[x] == max(lowest_argmin(Q[x][k])[1] for k in range(g.m1))
+        if alpha_out[x] != a_inc[x]:
+            assert beta_out[x] == lowest_argmin(Q[x][alpha_out[x]])[0]
+        else:
+            assert beta_out[x] == beta_in[x]
+
+
+@pytest.mark.parametrize("player", [1, 2])
+def test_tie_tolerance_is_a_rounding_bound(player):
+    """An incumbent worse by a few units in the last place is kept; one worse
+    by 1e-9 is replaced (the copy is the incumbent, the original the best)."""
+    base = games.random_game(40, 2, 2, 70 + player, mu=0.9, density=0.3)
+    rng = np.random.default_rng(player)
+    v = rng.normal(size=base.n)
+    for dr, kept in ((4e-16, True), (1e-9, False)):
+        # MAX prefers larger values, MIN smaller ones: the copy is worse by |dr|
+        g = games.with_copied_action(base, player, 0, 2, dr=-dr if player == 1 else dr)
+        Q = q_loops(g, v)
+        Qo, scale = oracle.q_values(g, v)
+        inc_a = np.full(g.n, 2 if player == 1 else 0, np.int32)
+        inc_b = np.full(g.n, 2 if player == 2 else 0, np.int32)
+        for x in range(g.n):
+            if player == 2:
+                inc_a[x] = 0
+        beta_in, F, alpha_out, _ = oracle.shapley_oracle._improve(g, Qo, scale, inc_a, inc_b)
+        checked = 0
+        for x in range(g.n):
+            if player == 1:
+                inner = [lowest_argmin(Q[x][k])[1] for k in range(g.m1)]
+                if inner[0] != max(inner[:2]) or inner[0] - inner[1] < 1e-6:
+                    continue
+                checked += 1
+                assert alpha_out[x] == (2 if kept else 0)
+            else:
+                qa = Q[x][0]
+                if qa[0] - qa[1] > -1e-6:
+                    continue
+                checked += 1
+                assert beta_in[x] == (2 if kept else 0)
+        assert checked >= 5
+
+
+def test_copied_actions_leave_the_value_unchanged():
+    """Adding a copy of an action changes no value of the game (eq. (eq1) takes
+    the same max and min); the policies found attain v*."""
+    base = games.random_game(25, 2, 3, 80, mu=0.9, density=0.3, invalid_frac=0.2)
+    g = games.with_copied_action(games.with_copied_action(base, 1, 1, 0), 2, 0, 3)
+    r0 = oracle.policy_iteration(base)
+    r1 = oracle.policy_iteration(g)
+    assert r0.converged and r1.converged
+    np.testing.assert_allclose(r1.v, r0.v, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(dense_policy_value(g, r1.alpha, r1.beta), r0.v, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
 # closed forms
 # ---------------------------------------------------------------------------
 
