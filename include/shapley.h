@@ -61,6 +61,16 @@ typedef struct shapley_grid {
 
 enum { SHAPLEY_FP64 = 0, SHAPLEY_MIXED = 1 };
 enum { SHAPLEY_AMGPI = 0, SHAPLEY_FAMGPI = 1 };
+/* Relaxation of the multigrid cycle (Sec. 4.3: u <- S u + S0 f):
+ *   SHAPLEY_SMOOTH_JACOBI  weighted Jacobi, u += omega D^-1 (f - A u)
+ *   SHAPLEY_SMOOTH_L1      l1-Jacobi, u += D1^-1 (f - A u) with
+ *                          D1_ii = sum_j |a_ij| (no weight)
+ *   SHAPLEY_SMOOTH_CF      C/F relaxation (the ordering of the paper's
+ *                          smoother, Sec. 6): each sweep relaxes the coarse
+ *                          points of the level's C/F splitting, then the fine
+ *                          points with the updated coarse values (weighted
+ *                          Jacobi within each set) */
+enum { SHAPLEY_SMOOTH_JACOBI = 0, SHAPLEY_SMOOTH_L1 = 1, SHAPLEY_SMOOTH_CF = 2 };
 
 /* Solve options.  Fill with shapley_default_opts() first. */
 typedef struct shapley_solve_opts {
@@ -97,6 +107,10 @@ typedef struct shapley_solve_opts {
                             Shapley residual of the previous step (or the
                             lin_rtol/lin_atol test, whichever is looser).
                             0 (default) solves every system to lin_rtol. */
+  int32_t smoother;      /* SHAPLEY_SMOOTH_*; default SHAPLEY_SMOOTH_JACOBI */
+  int32_t gamma;         /* cycle index of Algorithm MGcycle: 1 = V-cycle
+                            (default), 2 = W-cycle (the coarse problem is
+                            visited twice per level) */
 } shapley_solve_opts;
 
 /* Per-solve statistics (the paper's table columns, Sec. 6, plus timings). */
@@ -127,16 +141,20 @@ typedef struct shapley_stats {
  * max_outer 100000, max_inner 100000, max_cycles 200, lin_rtol 1e-14,
  * lin_atol 0, tie_rtol 1e-12, theta auto, nu1 = nu2 = 2, omega 0.8,
  * coarse_max 64, max_levels 25, verbose 0, stream NULL, reuse_frac 0.5,
- * forcing 0. */
+ * forcing 0, smoother SHAPLEY_SMOOTH_JACOBI, gamma 1. */
 void shapley_default_opts(shapley_solve_opts* o);
 
 /* ---------------------------------------------------------------- games */
 
 /* Flags of shapley_game_create. */
-#define SHAPLEY_HOST_PTRS 0u
+#define SHAPLEY_HOST_PTRS 0u    /* every array is a host array */
+#define SHAPLEY_DEVICE_PTRS 1u  /* every array (and grid->bvals) is device memory of the
+                                   current HIP device, e.g. a PyTorch tensor's storage */
 
 /*
- * Creates a game handle from its transition stencils (Sec. 2): states
+ * Creates a game handle from its transition stencils: the finite game of
+ * Sec. 2 (states, action sets A(x) and B(x,a), transition probabilities
+ * p(y|x,a,b), rewards r(x,a,b) and discount mu of eq. (eq1)): states
  * X = {0..n-1}, m1 actions for MAX and m2 for MIN at every state (invalid
  * pairs are masked by `valid`).  Row (x, a, b) = (x*m1 + a)*m2 + b holds the
  * sparse row y -> w = p(y|x,a,b) in CSR form and the reward r(x,a,b).
@@ -150,10 +168,19 @@ void shapley_default_opts(shapley_solve_opts* o);
  *   valid    optional [n*m1*m2] uint8 (1 = pair allowed); every state needs a
  *            valid a and every valid a a valid b.  NULL = all valid.
  *   grid     optional geometric description (for FAMGpi), or NULL
- *   flags    SHAPLEY_HOST_PTRS (all arrays are host arrays, copied)
+ *   flags    SHAPLEY_HOST_PTRS: all arrays are host arrays (checked and
+ *            copied on the host);  SHAPLEY_DEVICE_PTRS: all arrays, including
+ *            grid->bvals, are device memory of the current device (checked by
+ *            a kernel, copied device to device; nothing goes through the
+ *            host but row_ptr[n*m1*m2] and the check's result).  Either way
+ *            the library copies the arrays and the caller keeps ownership.
+ *            Rows whose columns are not ascending are sorted (stable).
  *   stream   hipStream_t for the copies and later work; NULL = a new stream
- *            owned by the handle
- * Errors: SHAPLEY_EINVAL on any violated condition, SHAPLEY_ENOMEM.
+ *            owned by the handle.  With device pointers, the arrays must be
+ *            ready when the call starts (the caller synchronises its own
+ *            stream first, or passes that stream here).
+ * Errors: SHAPLEY_EINVAL on any violated condition (the game is not
+ * created), SHAPLEY_ENOMEM, SHAPLEY_EDEVICE.
  */
 int shapley_game_create(shapley_game_t* out, int64_t n, int32_t m1, int32_t m2,
                         const int64_t* row_ptr, const int32_t* col, const double* w,
@@ -172,27 +199,54 @@ int shapley_game_create(shapley_game_t* out, int64_t n, int32_t m1, int32_t m2,
  */
 int shapley_game_create_hierarchy(shapley_game_t* out, int32_t nlev, shapley_game_t* levels);
 
-/* Solves the game (or hierarchy).  o may be NULL (defaults); st may be NULL.
- * Returns SHAPLEY_ENOCONV (with results and stats filled) if a limit was hit. */
+/* Solves the game: the fixed point v of the Shapley operator F of eq. (eq1)
+ * (Sec. 2) and optimal pure stationary strategies, by policy iteration with an
+ * algebraic-multigrid solve of each policy system (AMGpi, Sec. 5.1: the
+ * two-player scheme of Algorithm PIalgo whose inner loop is Algorithm
+ * algo-MDP, systems (LSPI) solved by the cycles of Algorithm MGcycle), or, for
+ * a hierarchy with method SHAPLEY_FAMGPI, by full multilevel policy iteration
+ * (Sec. 5.2, Algorithm algo-FAMGPI).  Warm starts alpha0/beta0/v0 (host
+ * arrays) are the arguments (alpha, beta, v) of AMGpi in Algorithm
+ * algo-FAMGPI: alpha0 must name an available action (one with a valid b) and
+ * (alpha0, beta0) a valid pair at every state, else SHAPLEY_EINVAL before any
+ * change.  o may be NULL (defaults); st may be NULL.
+ * Errors: SHAPLEY_EINVAL (options, warm start), SHAPLEY_ENOCONV (an iteration
+ * limit was hit, or MIN's inner loop was cut by max_inner and MAX has no
+ * improvement left while the residual is above eps: the value, strategies and
+ * stats of the last step are readable), SHAPLEY_EDEVICE (non-finite values or
+ * a HIP error), SHAPLEY_ENOMEM. */
 int shapley_solve(shapley_game_t g, const shapley_solve_opts* o, shapley_stats* st);
 
-/* Copies the current value (n doubles) to v (host, or device if on_device != 0). */
+/* Copies the current value v (n doubles; after a converged solve the fixed
+ * point of eq. (eq1), Sec. 2) to v: a host array, or device memory of the
+ * handle's device if on_device != 0.  Synchronises the handle's stream.
+ * Errors: SHAPLEY_EINVAL (null argument), SHAPLEY_EDEVICE. */
 int shapley_get_value(shapley_game_t g, double* v, int32_t on_device);
 
-/* Copies the current policies: alpha[n] (MAX), beta[n] (MIN at alpha(x));
- * beta_all (optional, n*m1) receives MIN's lowest-index argmin at every a for
- * the current value.  Host arrays; any may be NULL. */
+/* Copies the current pure stationary strategies (Sec. 2): alpha[n], MAX's
+ * action at each state, and beta[n], MIN's action at (x, alpha(x)); beta_all
+ * (optional, n*m1, row-major by state) receives MIN's lowest-index argmin of
+ * the bracket of eq. (eq1) at every a for the current value (the strategy
+ * beta(x, a) of Sec. 2 on all of X x A).  Host arrays; any may be NULL.  With
+ * the value these form the checkpoint a later solve takes as warm start.
+ * Errors: SHAPLEY_EINVAL (null game), SHAPLEY_EDEVICE. */
 int shapley_get_policy(shapley_game_t g, int32_t* alpha, int32_t* beta, int32_t* beta_all);
 
-/* Evaluates F(v) (Sec. 2, eq. (eq1)) of the current value: F[n] (host) and
- * the greedy policies at v (any output may be NULL). */
+/* Evaluates the Shapley operator F(v) (Sec. 2, eq. (eq1)) at the host vector
+ * v[n]: F[n] and the greedy strategies at v, alpha = lowest-index argmax_a of
+ * min_b and beta = lowest-index argmin_b at alpha (host arrays, any output
+ * may be NULL).  The handle's value and strategies are left unchanged.
+ * Errors: SHAPLEY_EINVAL (null argument), SHAPLEY_EDEVICE. */
 int shapley_apply_operator(shapley_game_t g, const double* v, double* F, int32_t* alpha,
                            int32_t* beta);
 
-/* n, m1, m2 of a handle (the finest level for hierarchies). */
+/* n = |X|, m1 and m2 (Sec. 2) of a handle (the finest level for
+ * hierarchies).  Errors: SHAPLEY_EINVAL (null game). */
 int shapley_game_info(shapley_game_t g, int64_t* n, int32_t* m1, int32_t* m2);
 
-/* Device bytes held by the handle. */
+/* Device bytes held by the handle (transitions, rewards, pattern, value and
+ * strategies; the solver's workspace is not counted).  The request loop's
+ * HBM budget admission builds on it.  Errors: SHAPLEY_EINVAL. */
 int shapley_game_bytes(shapley_game_t g, size_t* bytes);
 
 /* Lanes per sparse row in the V-cycle's relaxation, residual and restriction
@@ -230,6 +284,9 @@ typedef struct shapley_level_info {
 int shapley_hierarchy_level(shapley_game_t g, int32_t level, shapley_level_info* info, int32_t* rp, int32_t* ci,
                             double* a, int32_t* pc, double* pv);
 
+/* Releases the handle (a hierarchy releases its levels) and the device
+ * memory it holds; NULL is ignored.  The handle must not be in use by a
+ * solve or by a server ticket that has not completed. */
 void shapley_game_destroy(shapley_game_t g);
 
 /* ---------------------------------------------------------------- batch */
@@ -247,15 +304,28 @@ int shapley_solve_batch(shapley_game_t* games, int32_t count, const shapley_solv
 /* ---------------------------------------------------------------- server */
 
 /*
- * A request loop with continuous batching: submitted games (or hierarchies)
- * are admitted while their estimated device footprint fits the budget,
- * advanced together one policy-iteration step at a time (one merged launch
- * per kernel), and leave as they converge, freeing their budget.
+ * A request loop with continuous batching (the serving mode of the solver; the
+ * solve of each request is that of shapley_solve, AMGpi of Sec. 5.1 or FAMGpi
+ * of Sec. 5.2): submitted games (or hierarchies) are admitted in FIFO order
+ * while their estimated device footprint fits the budget.  Requests admitted
+ * in the same step with equal engine options (precision, AMG and cycle
+ * options, tie_rtol) form a cohort: one lock-step engine with merged
+ * launches and an AMG hierarchy kept on the device until the cohort's last
+ * member leaves; members that converge leave without a rebuild.  Cohorts
+ * run concurrently on streams of their own (one host thread each), so
+ * requests admitted while others run overlap with them on the device.  An
+ * FAMGpi request moves to a new cohort at each finer grid.  At 16 cohorts,
+ * new requests join the compatible cohort with the fewest running unknowns.
  *   hbm_budget  bytes of device memory the server may hold for requests
+ *   stream      NULL: streams owned by the server (cohorts concurrent); a
+ *               caller's hipStream_t: every cohort on it, one after another
+ * Errors: SHAPLEY_EINVAL (null out, zero budget), SHAPLEY_EDEVICE.
  */
 int shapley_server_create(shapley_server_t* out, size_t hbm_budget, void* stream);
 /* Queues g (ownership stays with the caller; do not use or destroy g until
- * its ticket completes).  Thread-safe. */
+ * its ticket completes).  Options and warm starts are checked here as in
+ * shapley_solve.  Thread-safe.  Errors: SHAPLEY_EINVAL, SHAPLEY_ENOMEM when
+ * the request's footprint alone exceeds the whole budget. */
 int shapley_server_submit(shapley_server_t srv, shapley_game_t g, const shapley_solve_opts* o,
                           uint64_t* ticket);
 /* Runs scheduling steps until the ticket completes or `max_steps` steps pass
@@ -265,8 +335,21 @@ int shapley_server_wait(shapley_server_t srv, uint64_t ticket, int32_t max_steps
 /* Non-blocking: SHAPLEY_OK if the ticket completed (stats filled), else EAGAIN. */
 int shapley_server_poll(shapley_server_t srv, uint64_t ticket, shapley_stats* st);
 /* Runs one scheduling step (admission + one PI step of all active requests).
- * *active receives the number of requests still on the device. */
+ * *active receives the number of requests not yet completed (on the device
+ * or queued).  A request whose solve fails completes with the error code of
+ * the failure (poll/wait return it and shapley_last_error its message); the
+ * other members of its cohort complete with the same code. */
 int shapley_server_step(shapley_server_t srv, int32_t* active);
+/* Occupancy of the request loop. */
+typedef struct shapley_server_stats {
+  int32_t queued;        /* submitted, not admitted */
+  int32_t active;        /* admitted, not completed */
+  int32_t cohorts;       /* engines with running members */
+  int32_t reserved;
+  size_t budget_used;    /* estimated device bytes of the active requests */
+  size_t budget;
+} shapley_server_stats;
+int shapley_server_info(shapley_server_t srv, shapley_server_stats* st);
 void shapley_server_destroy(shapley_server_t srv);
 
 /* ---------------------------------------------------------------- probe */

@@ -2212,12 +2212,24 @@ __global__ __launch_bounds__(256) void k_smooth(const Tile* __restrict__ tiles, 
                                                 const T* __restrict__ a, const T* __restrict__ dinv,
                                                 const T* __restrict__ b, const T* __restrict__ xin,
                                                 T* __restrict__ xout, T omega, int first,
-                                                double* __restrict__ sol) {
+                                                double* __restrict__ sol, const int8_t* __restrict__ cfm,
+                                                int cfphase) {
   const Tile t = tiles[blockIdx.x / G];
   if (!act[t.game]) return;
   int gl;
   const int i = tile_row<G>(t, gl);
   const bool in = i < t.r1;
+  if (cfm) {
+    // C/F relaxation: this half sweep relaxes the coarse points (cfphase 1)
+    // or the others (cfphase -1) and carries the rest over unchanged
+    const int e0 = in ? rp[i] : 0, e1 = in ? rp[i + 1] : 0;
+    const T ax = row_dot<T, T, G>(ci, a, xin, e0, e1, gl);
+    if (in && gl == 0) {
+      const bool mine = (cfm[i] == CF_C) == (cfphase == 1);
+      xout[i] = mine ? xin[i] + omega * dinv[i] * (b[i] - ax) : xin[i];
+    }
+    return;
+  }
   if (first == 1) {
     if (in && gl == 0) xout[i] = omega * dinv[i] * b[i];
     return;
@@ -2905,9 +2917,28 @@ int row_group(double avg_len) { return avg_len <= 10.0 ? 1 : 4; }
 template <class T>
 void cyc_smooth(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const T* a,
                 const T* dinv, const T* b, const T* xin, T* xout, T omega, int first, int g, hipStream_t s,
-                double* sol) {
+                double* sol, const int8_t* cf, int cfphase) {
   if (!nt) return;
-  SHP_GROUP_LAUNCH(k_smooth, first == 1 ? 1 : g, nt, s, t, act, rp, ci, a, dinv, b, xin, xout, omega, first, sol);
+  SHP_GROUP_LAUNCH(k_smooth, first == 1 && !cf ? 1 : g, nt, s, t, act, rp, ci, a, dinv, b, xin, xout, omega, first,
+                   sol, cf, cfphase);
+  SHP_LAUNCH_CHECK();
+}
+
+// l1-Jacobi diagonal: d_i = 1 / sum_j |a_ij| over the rows of the tiles
+__global__ void k_l1_diag(const Tile* __restrict__ tiles, const int* __restrict__ rp, const double* __restrict__ a,
+                          double* __restrict__ d64, float* __restrict__ d32) {
+  const Tile t = tiles[blockIdx.x];
+  const int i = t.r0 + threadIdx.x;
+  if (i >= t.r1) return;
+  double s = 0.0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) s += fabs(a[e]);
+  const double di = s != 0.0 ? 1.0 / s : 0.0;
+  d64[i] = di;
+  if (d32) d32[i] = (float)di;
+}
+void amg_l1_diag(const Tile* t, int nt, const int* rp, const double* a, double* d64, float* d32, hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_l1_diag, dim3(nt), dim3(kTileRows), 0, s, t, rp, a, d64, d32);
   SHP_LAUNCH_CHECK();
 }
 template <class T>
@@ -2966,7 +2997,8 @@ void cyc_tail(const int* games, int ngames, int l0, int nlev, int G, const TailL
 
 #define SHP_INST(T)                                                                                  \
   template void cyc_smooth<T>(const Tile*, int, const int*, const int*, const int*, const T*, const T*, \
-                              const T*, const T*, T*, T, int, int, hipStream_t, double*);            \
+                              const T*, const T*, T*, T, int, int, hipStream_t, double*,             \
+                              const int8_t*, int);                                                   \
   template void cyc_resid<T>(const Tile*, int, const int*, const int*, const int*, const T*, const T*,  \
                              const T*, T*, int, hipStream_t);                                        \
   template void cyc_restrict<T>(const Tile*, int, const int*, const int*, const int*, const T*,        \

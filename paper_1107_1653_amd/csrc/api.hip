@@ -36,16 +36,117 @@ static double now_s() {
     if (!(cond)) throw Error(SHAPLEY_EINVAL, msg); \
   } while (0)
 
+// Level-0 pattern, state and policy arrays and the grid description of a game
+// whose transition arrays are on the device (shared by both create paths).
+static void finish_game(Game* g, const shapley_grid* grid, bool device_ptrs) {
+  hipStream_t s = g->stream;
+  const int n = g->n;
+  // level-0 pattern: union of the columns of a state's rows plus the diagonal
+  g->urp.alloc(n + 1);
+  DBuf<int> cnt(n + 1), scr;
+  fill_async(cnt.p + n, 0, 1, s);
+  launch_union_count(g->rp.p, g->ci.p, n, g->m1, g->m2, cnt.p, nullptr, s);
+  scan_exclusive(cnt.p, g->urp.p, n + 1, s, scr);
+  int unnz = 0;
+  d2h(&unnz, g->urp.p + n, 1, s);
+  SHP_HIP(hipStreamSynchronize(s));
+  g->unnz = unnz;
+  g->uci.alloc(std::max(unnz, 1));
+  launch_union_fill(g->rp.p, g->ci.p, n, g->m1, g->m2, g->urp.p, g->uci.p, s);
+  g->v.alloc(n); g->F.alloc(n);
+  g->alpha.alloc(n); g->beta.alloc(n); g->beta_in.alloc(n); g->alpha_c.alloc(n); g->beta_c.alloc(n);
+  fill_async(g->v.p, 0.0, n, s);
+  fill_async(g->alpha.p, 0, n, s);
+  fill_async(g->beta.p, 0, n, s);
+  if (grid) {
+    g->dim = grid->dim;
+    g->s = grid->s;
+    if (grid->bvals) {
+      int64_t ne = 1;
+      for (int k = 0; k < grid->dim; ++k) ne *= (grid->s + 2);
+      g->bvals.alloc(ne);
+      if (device_ptrs) d2d(g->bvals.p, grid->bvals, ne, s);
+      else h2d(g->bvals.p, grid->bvals, ne, s);
+      g->has_bvals = true;
+    }
+  }
+  SHP_HIP(hipStreamSynchronize(s));
+}
+
+static void check_grid(const shapley_grid* grid, int64_t n64) {
+  if (!grid) return;
+  SHP_REQUIRE(grid->dim >= 1 && grid->dim <= 3 && grid->s >= 1, "grid: dim in 1..3 and s >= 1");
+  int64_t p = 1;
+  for (int k = 0; k < grid->dim; ++k) p *= grid->s;
+  SHP_REQUIRE(p == n64, "grid: s^dim must equal n");
+}
+
+static void make_stream(Game* g, void* stream) {
+  if (stream) {
+    g->stream = (hipStream_t)stream;
+  } else {
+    SHP_HIP(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+    g->own_stream = true;
+  }
+}
+
+// Arrays in device memory: the same conditions as for host arrays, checked by
+// a kernel (one synchronisation), then device-to-device copies; rows whose
+// columns are not ascending are sorted on the device (stable, as on the host).
+static Game* create_game_device(int n, int m1, int m2, const int64_t* row_ptr, const int32_t* col,
+                                const double* w, const double* r, double mu, const uint8_t* valid,
+                                const shapley_grid* grid, void* stream) {
+  const int nrows = n * m1 * m2;
+  std::unique_ptr<Game> g(new Game());
+  g->n = n; g->m1 = m1; g->m2 = m2; g->nrows = nrows; g->mu = mu;
+  make_stream(g.get(), stream);
+  hipStream_t s = g->stream;
+  int64_t nnz = 0;
+  d2h(&nnz, row_ptr + nrows, 1, s);
+  SHP_HIP(hipStreamSynchronize(s));
+  SHP_REQUIRE(nnz >= 0 && nnz < INT32_MAX, "number of transitions must be below 2^31");
+  SHP_REQUIRE(nnz == 0 || (col && w), "null input array");
+  DBuf<int> err(1);
+  const int bits = check_game_device(row_ptr, col, w, r, valid, n, m1 * m2, nnz, err.p, s);
+  SHP_REQUIRE(!(bits & kChkRp0), "row_ptr[0] must be 0");
+  SHP_REQUIRE(!(bits & kChkRp), "row_ptr must be non-decreasing");
+  SHP_REQUIRE(!(bits & kChkCol), "column index out of range");
+  SHP_REQUIRE(!(bits & kChkW), "transition weights must be finite and >= 0");
+  SHP_REQUIRE(!(bits & kChkSum), "row sum of transition weights exceeds 1");
+  SHP_REQUIRE(!(bits & kChkR), "rewards must be finite");
+  SHP_REQUIRE(!(bits & kChkEmpty), "empty action set at a state");
+  g->nnz = nnz;
+  g->rp.alloc(nrows + 1);
+  g->ci.alloc(std::max<int64_t>(nnz, 1));
+  g->w.alloc(std::max<int64_t>(nnz, 1));
+  g->r.alloc(nrows);
+  launch_rp_narrow(row_ptr, g->rp.p, nrows + 1, s);
+  d2d(g->ci.p, col, nnz, s);
+  d2d(g->w.p, w, nnz, s);
+  if (bits & kChkUnsorted) launch_sort_pairs(g->rp.p, g->ci.p, g->w.p, nrows, s);
+  d2d(g->r.p, r, nrows, s);
+  if (valid) {
+    g->valid.alloc(nrows);
+    d2d(g->valid.p, valid, nrows, s);
+  }
+  finish_game(g.get(), grid, true);
+  return g.release();
+}
+
 static Game* create_game(int64_t n64, int m1, int m2, const int64_t* row_ptr, const int32_t* col,
                          const double* w, const double* r, double mu, const uint8_t* valid,
                          const shapley_grid* grid, uint32_t flags, void* stream) {
-  SHP_REQUIRE(flags == SHAPLEY_HOST_PTRS, "unsupported flags");
+  SHP_REQUIRE(flags == SHAPLEY_HOST_PTRS || flags == SHAPLEY_DEVICE_PTRS, "unsupported flags");
   SHP_REQUIRE(n64 >= 1 && m1 >= 1 && m2 >= 1, "n, m1 and m2 must be positive");
   SHP_REQUIRE((int64_t)m1 * m2 <= 256, "m1 * m2 must not exceed 256");
   const int64_t nrows64 = n64 * m1 * m2;
   SHP_REQUIRE(nrows64 < INT32_MAX, "n * m1 * m2 must be below 2^31");
-  SHP_REQUIRE(row_ptr && r && (row_ptr[nrows64] == 0 || (col && w)), "null input array");
+  SHP_REQUIRE(row_ptr && r, "null input array");
   SHP_REQUIRE(std::isfinite(mu) && mu > 0.0 && mu <= 1.0, "mu must lie in (0, 1]");
+  check_grid(grid, n64);
+  if (flags == SHAPLEY_DEVICE_PTRS)
+    return create_game_device((int)n64, m1, m2, row_ptr, col, w, r, mu, valid, grid, stream);
+  SHP_REQUIRE(row_ptr[nrows64] == 0 || (col && w), "null input array");
   SHP_REQUIRE(row_ptr[0] == 0, "row_ptr[0] must be 0");
   const int n = (int)n64, nrows = (int)nrows64;
   const int64_t nnz = row_ptr[nrows];
@@ -55,7 +156,7 @@ static Game* create_game(int64_t n64, int m1, int m2, const int64_t* row_ptr, co
   std::vector<double> w_sorted;
   bool need_sort = false;
   for (int i = 0; i < nrows; ++i) {
-    SHP_REQUIRE(row_ptr[i + 1] >= row_ptr[i], "row_ptr must be non-decreasing");
+    SHP_REQUIRE(row_ptr[i + 1] >= row_ptr[i] && row_ptr[i + 1] <= nnz, "row_ptr must be non-decreasing");
     rp32[i] = (int)row_ptr[i];
     double sum = 0.0;
     for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
@@ -91,20 +192,9 @@ static Game* create_game(int64_t n64, int m1, int m2, const int64_t* row_ptr, co
     colp = ci_sorted.data();
     wp = w_sorted.data();
   }
-  if (grid) {
-    SHP_REQUIRE(grid->dim >= 1 && grid->dim <= 3 && grid->s >= 1, "grid: dim in 1..3 and s >= 1");
-    int64_t p = 1;
-    for (int k = 0; k < grid->dim; ++k) p *= grid->s;
-    SHP_REQUIRE(p == n64, "grid: s^dim must equal n");
-  }
   std::unique_ptr<Game> g(new Game());
   g->n = n; g->m1 = m1; g->m2 = m2; g->nrows = nrows; g->nnz = nnz; g->mu = mu;
-  if (stream) {
-    g->stream = (hipStream_t)stream;
-  } else {
-    SHP_HIP(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
-    g->own_stream = true;
-  }
+  make_stream(g.get(), stream);
   hipStream_t s = g->stream;
   g->rp.alloc(nrows + 1);
   g->ci.alloc(std::max<int64_t>(nnz, 1));
@@ -118,39 +208,11 @@ static Game* create_game(int64_t n64, int m1, int m2, const int64_t* row_ptr, co
     g->valid.alloc(nrows);
     h2d(g->valid.p, valid, nrows, s);
   }
-  // level-0 pattern: union of the columns of a state's rows plus the diagonal
-  g->urp.alloc(n + 1);
-  DBuf<int> cnt(n + 1), scr;
-  SHP_HIP(hipMemsetAsync(cnt.p + n, 0, sizeof(int), s));
-  launch_union_count(g->rp.p, g->ci.p, n, m1, m2, cnt.p, nullptr, s);
-  scan_exclusive(cnt.p, g->urp.p, n + 1, s, scr);
-  int unnz = 0;
-  d2h(&unnz, g->urp.p + n, 1, s);
-  SHP_HIP(hipStreamSynchronize(s));
-  g->unnz = unnz;
-  g->uci.alloc(std::max(unnz, 1));
-  launch_union_fill(g->rp.p, g->ci.p, n, m1, m2, g->urp.p, g->uci.p, s);
-  g->v.alloc(n); g->F.alloc(n);
-  g->alpha.alloc(n); g->beta.alloc(n); g->beta_in.alloc(n); g->alpha_c.alloc(n); g->beta_c.alloc(n);
-  SHP_HIP(hipMemsetAsync(g->v.p, 0, sizeof(double) * n, s));
-  SHP_HIP(hipMemsetAsync(g->alpha.p, 0, sizeof(int) * n, s));
-  SHP_HIP(hipMemsetAsync(g->beta.p, 0, sizeof(int) * n, s));
-  if (grid) {
-    g->dim = grid->dim;
-    g->s = grid->s;
-    if (grid->bvals) {
-      int64_t ne = 1;
-      for (int k = 0; k < grid->dim; ++k) ne *= (grid->s + 2);
-      g->bvals.alloc(ne);
-      h2d(g->bvals.p, grid->bvals, ne, s);
-      g->has_bvals = true;
-    }
-  }
-  SHP_HIP(hipStreamSynchronize(s));
+  finish_game(g.get(), grid, false);
   return g.release();
 }
 
-static void check_opts(const shapley_solve_opts& o) {
+void check_solve_opts(const shapley_solve_opts& o) {
   SHP_REQUIRE(std::isfinite(o.eps) && o.eps >= 0.0, "eps must be >= 0");
   SHP_REQUIRE(o.precision == SHAPLEY_FP64 || o.precision == SHAPLEY_MIXED, "bad precision");
   SHP_REQUIRE(o.method == SHAPLEY_AMGPI || o.method == SHAPLEY_FAMGPI, "bad method");
@@ -163,26 +225,56 @@ static void check_opts(const shapley_solve_opts& o) {
   SHP_REQUIRE(o.c_fmg > 0.0, "c_fmg must be > 0");
   SHP_REQUIRE(o.reuse_frac >= 0.0 && o.reuse_frac <= 1.0, "reuse_frac must lie in [0, 1]");
   SHP_REQUIRE(std::isfinite(o.forcing) && o.forcing >= 0.0 && o.forcing < 1.0, "forcing must lie in [0, 1)");
+  SHP_REQUIRE(o.smoother == SHAPLEY_SMOOTH_JACOBI || o.smoother == SHAPLEY_SMOOTH_L1 ||
+                  o.smoother == SHAPLEY_SMOOTH_CF,
+              "bad smoother");
+  SHP_REQUIRE(o.gamma == 1 || o.gamma == 2, "gamma must be 1 (V-cycle) or 2 (W-cycle)");
+  SHP_REQUIRE(std::isfinite(o.theta) && std::isfinite(o.omega) && std::isfinite(o.c_fmg) &&
+                  std::isfinite(o.lin_rtol) && std::isfinite(o.lin_atol) && std::isfinite(o.tie_rtol) &&
+                  std::isfinite(o.reuse_frac),
+              "options must be finite");
 }
+
+}  // namespace shp
+
+// Warm-start strategies of a solve (host arrays, n entries; beta0 optional):
+// alpha0(x) must be an available action (one with a valid b) and (alpha0,
+// beta0) a valid pair at every state.  Checked on the device against the
+// game's validity mask before anything is modified; EINVAL otherwise.
+void shp::check_warm_start(Game* g, const int32_t* alpha0, const int32_t* beta0, hipStream_t s) {
+  if (!alpha0) return;
+  const int n = g->n;
+  for (int x = 0; x < n; ++x) SHP_REQUIRE(alpha0[x] >= 0 && alpha0[x] < g->m1, "alpha0 out of range");
+  if (beta0)
+    for (int x = 0; x < n; ++x) SHP_REQUIRE(beta0[x] >= 0 && beta0[x] < g->m2, "beta0 out of range");
+  if (!g->valid.p) return;
+  DBuf<int> tmp(2 * (size_t)n + 1);
+  h2d(tmp.p, alpha0, n, s);
+  if (beta0) h2d(tmp.p + n, beta0, n, s);
+  const int bits = check_policy_device(tmp.p, beta0 ? tmp.p + n : nullptr, g->valid.p, n, g->m1, g->m2,
+                                       tmp.p + 2 * n, s);
+  SHP_REQUIRE(!(bits & 1), "alpha0 names an action with no valid b at some state");
+  SHP_REQUIRE(!(bits & 2), "(alpha0, beta0) is not a valid pair at some state");
+}
+
+namespace shp {
 
 static void load_warm_start(Game* g, const shapley_solve_opts& o, SlotState& S, hipStream_t s) {
   const int n = g->n;
+  check_warm_start(g, o.alpha0, o.beta0, s);
   if (o.v0) h2d(g->v.p, o.v0, n, s);
-  else SHP_HIP(hipMemsetAsync(g->v.p, 0, sizeof(double) * n, s));
+  else fill_async(g->v.p, 0.0, n, s);
   if (o.alpha0) {
-    for (int x = 0; x < n; ++x)
-      SHP_REQUIRE(o.alpha0[x] >= 0 && o.alpha0[x] < g->m1, "alpha0 out of range");
     h2d(g->alpha.p, o.alpha0, n, s);
     S.init_alpha = true;
   } else {
-    SHP_HIP(hipMemsetAsync(g->alpha.p, 0xFF, sizeof(int) * n, s));
+    fill_async(g->alpha.p, -1, n, s);
   }
   if (o.alpha0 && o.beta0) {
-    for (int x = 0; x < n; ++x) SHP_REQUIRE(o.beta0[x] >= 0 && o.beta0[x] < g->m2, "beta0 out of range");
     h2d(g->beta.p, o.beta0, n, s);
     S.init_beta = true;
   } else {
-    SHP_HIP(hipMemsetAsync(g->beta.p, 0xFF, sizeof(int) * n, s));
+    fill_async(g->beta.p, -1, n, s);
   }
   SHP_HIP(hipStreamSynchronize(s));
 }
@@ -281,6 +373,8 @@ void shapley_default_opts(shapley_solve_opts* o) {
   o->stream = nullptr;
   o->reuse_frac = 0.5;
   o->forcing = 0.0;
+  o->smoother = SHAPLEY_SMOOTH_JACOBI;
+  o->gamma = 1;
 }
 
 int shapley_game_create(shapley_game_t* out, int64_t n, int32_t m1, int32_t m2, const int64_t* row_ptr,
@@ -305,7 +399,11 @@ int shapley_game_create_hierarchy(shapley_game_t* out, int32_t nlev, shapley_gam
       SHP_REQUIRE(g->dim >= 1, "every level needs a grid description");
       if (dim < 0) dim = g->dim;
       SHP_REQUIRE(g->dim == dim, "levels must share the grid dimension");
-      if (l > 0) SHP_REQUIRE(g->s > levels[l - 1]->g->s, "levels must be ordered coarse -> fine");
+      if (l > 0) {
+        SHP_REQUIRE(g->s > levels[l - 1]->g->s, "levels must be ordered coarse -> fine");
+        SHP_REQUIRE(g->m1 == levels[l - 1]->g->m1 && g->m2 == levels[l - 1]->g->m2,
+                    "levels must have the same numbers of actions");
+      }
     }
     Game* h = new Game();
     for (int l = 0; l < nlev; ++l) {
@@ -324,10 +422,10 @@ int shapley_game_create_hierarchy(shapley_game_t* out, int32_t nlev, shapley_gam
 int shapley_solve(shapley_game_t gh, const shapley_solve_opts* op, shapley_stats* st) {
   int status = SHAPLEY_OK;
   int rc = guarded([&] {
-    SHP_REQUIRE(gh && gh->g, "null game");
     shapley_solve_opts o;
     if (op) o = *op; else shapley_default_opts(&o);
-    check_opts(o);
+    check_solve_opts(o);  // before the handle: no device state is needed to reject options
+    SHP_REQUIRE(gh && gh->g, "null game");
     Game* g = gh->g;
     hipStream_t s = o.stream ? (hipStream_t)o.stream : g->finest()->stream;
     double t0 = now_s();
@@ -376,10 +474,10 @@ int shapley_solve_batch(shapley_game_t* games, int32_t count, const shapley_solv
                         shapley_stats* stats) {
   int status = SHAPLEY_OK;
   int rc = guarded([&] {
-    SHP_REQUIRE(games && count >= 1, "bad batch arguments");
     shapley_solve_opts o;
     if (op) o = *op; else shapley_default_opts(&o);
-    check_opts(o);
+    check_solve_opts(o);
+    SHP_REQUIRE(games && count >= 1, "bad batch arguments");
     SHP_REQUIRE(o.alpha0 == nullptr && o.beta0 == nullptr && o.v0 == nullptr,
                 "warm starts are not accepted in batch mode");
     std::vector<SlotState> S(count);
@@ -442,7 +540,7 @@ int shapley_get_policy(shapley_game_t gh, int32_t* alpha, int32_t* beta, int32_t
       for (int a = 0; a < g->m1; ++a) {
         std::vector<int> av(g->n, a);
         h2d(g->alpha.p, av.data(), g->n, s);
-        SHP_HIP(hipMemsetAsync(g->beta.p, 0xFF, sizeof(int) * g->n, s));
+        fill_async(g->beta.p, -1, g->n, s);
         eng.improve_only();
         d2h(col.data(), g->beta_in.p, g->n, s);
         SHP_HIP(hipStreamSynchronize(s));
@@ -468,8 +566,8 @@ int shapley_apply_operator(shapley_game_t gh, const double* v, double* F, int32_
     d2h(keep_b.data(), g->beta.p, n, s);
     SHP_HIP(hipStreamSynchronize(s));
     h2d(g->v.p, v, n, s);
-    SHP_HIP(hipMemsetAsync(g->alpha.p, 0xFF, sizeof(int) * n, s));
-    SHP_HIP(hipMemsetAsync(g->beta.p, 0xFF, sizeof(int) * n, s));
+    fill_async(g->alpha.p, -1, n, s);
+    fill_async(g->beta.p, -1, n, s);
     SlotState S;
     S.g = g;
     Engine eng(s);

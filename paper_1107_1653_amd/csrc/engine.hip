@@ -833,7 +833,9 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
       throw Error(SHAPLEY_EDEVICE, "Galerkin product: coarse row too long (code " + std::to_string(herr[1]) + ")");
     if (herr[2] != 0) throw Error(SHAPLEY_EDEVICE, "singular coarsest block");
   }
-  build_tail(mixed);
+  // the tail kernel runs V-cycles with (weighted or l1) Jacobi sweeps; W-cycles
+  // and C/F relaxation take every level level by level
+  build_tail(mixed, o.gamma == 1 && o.smoother != SHAPLEY_SMOOTH_CF);
   hier_game = G == 1 ? slots[0]->g : nullptr;
   // statistics
   double nnz_sum = 0, n_sum = 0;
@@ -848,11 +850,11 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
 // Splits every level between the level-by-level cycle and the per-game tails
 // (a game's tail starts on its first level with at most kTailRows rows) and
 // uploads the tail tables.  Pointers stay valid through numeric refreshes.
-void Engine::build_tail(bool mixed) {
+void Engine::build_tail(bool mixed, bool allow) {
   const int cap = kTailLdsBytes / (2 * (mixed ? (int)sizeof(float) : (int)sizeof(double)));
   h_lt.assign(G, nlev);
   std::vector<int> lds_rows(std::max(nlev, 1), 0);
-  for (int g = 0; g < G; ++g) {
+  for (int g = 0; g < G && allow; ++g) {
     int last = -1;  // the game's last level
     for (int l = 0; l < nlev && lv[l].present[g]; ++l) {
       last = l;
@@ -1043,36 +1045,67 @@ static double bytes_resid(const Level& L) {
 
 template <class T>
 static T* vcycle_level(Engine* e, std::vector<Level>& lv, int l, const EngineOpts& o, const int* act,
-                       hipStream_t s);
+                       hipStream_t s, double* sol, const TailRefine* rf = nullptr, T* start = nullptr);
 
-// Level-by-level part of the V-cycle on level l: the games whose tail starts
-// deeper.  Returns the buffer (x or y) holding the level's result.
+// weight of the relaxation: l1-Jacobi takes none
+static double relax_weight(const EngineOpts& o) { return o.smoother == SHAPLEY_SMOOTH_L1 ? 1.0 : o.omega; }
+
+// One relaxation sweep cur -> nxt of the level-by-level rows (a C/F sweep is
+// two half sweeps through the free buffer, ending in nxt).
+template <class T>
+static void relax_sweep(Level& L, const EngineOpts& o, const int* act, const T* b, T* cur, T* nxt, T* tmp,
+                        hipStream_t s, double* sol) {
+  const T om = (T)relax_weight(o);
+  if (o.smoother == SHAPLEY_SMOOTH_CF) {
+    probe_begin(kProbeSmooth, s);
+    cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, LV<T>::a(L), LV<T>::d(L), b, cur, tmp, om, 0, L.gA,
+                  s, nullptr, L.cf.p, 1);
+    cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, LV<T>::a(L), LV<T>::d(L), b, tmp, nxt, om, 0, L.gA,
+                  s, nullptr, L.cf.p, -1);
+    probe_end(kProbeSmooth, s, 2 * bytes_smooth<T>(L, false));
+    return;
+  }
+  probe_begin(kProbeSmooth, s);
+  cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, LV<T>::a(L), LV<T>::d(L), b, cur, nxt, om, 0, L.gA, s,
+                sol);
+  probe_end(kProbeSmooth, s, bytes_smooth<T>(L, false));
+}
+
+// Level-by-level part of the multigrid cycle on level l (Algorithm MGcycle):
+// the games whose tail starts deeper.  The iterate starts from zero, or from
+// `start` (one of the level's x and y buffers: a W-cycle's second visit);
+// the coarse problem is visited gamma times.  Returns the buffer (x or y)
+// holding the level's result.
 template <class T>
 static T* vcycle_impl(Engine* e, std::vector<Level>& lv, int l, const EngineOpts& o, const int* act,
-                      hipStream_t s, double* sol) {
+                      hipStream_t s, double* sol, T* start) {
   Level& L = lv[l];
-  T* cur = LV<T>::x(L);
-  T* nxt = LV<T>::y(L);
+  T* cur = start ? start : LV<T>::x(L);
+  T* nxt = cur == LV<T>::x(L) ? LV<T>::y(L) : LV<T>::x(L);
   T* b = LV<T>::b(L);
-  const T om = (T)o.omega;
+  const T om = (T)relax_weight(o);
+  const bool cf = o.smoother == SHAPLEY_SMOOTH_CF;
   if (L.nvctiles) {
     const T* A = LV<T>::a(L);
     const T* D = LV<T>::d(L);
-    int k = 1;
-    probe_begin(kProbeSmooth, s);
-    if (o.nu1 >= 2) {  // the first two sweeps in one pass
+    T* tmp = LV<T>::r(L);  // free until the residual
+    int k = 0;
+    if (!start && cf) {
+      fill_async(cur, (T)0, (size_t)L.n, s);
+    } else if (!start && o.nu1 >= 2) {  // the first two sweeps in one pass
+      probe_begin(kProbeSmooth, s);
       cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, D, b, nullptr, nxt, om, 2, L.gA, s);
       probe_end(kProbeSmooth, s, bytes_smooth<T>(L, false) - (double)L.rows_vctiles * sizeof(T));
       std::swap(cur, nxt);
       k = 2;
-    } else {
+    } else if (!start) {
+      probe_begin(kProbeSmooth, s);
       cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, D, b, nullptr, cur, om, 1, 1, s);
       probe_end(kProbeSmooth, s, bytes_smooth<T>(L, true));
+      k = 1;
     }
     for (; k < o.nu1; ++k) {
-      probe_begin(kProbeSmooth, s);
-      cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, D, b, cur, nxt, om, 0, L.gA, s);
-      probe_end(kProbeSmooth, s, bytes_smooth<T>(L, false));
+      relax_sweep<T>(L, o, act, b, cur, nxt, tmp, s, nullptr);
       std::swap(cur, nxt);
     }
     T* r = LV<T>::r(L);
@@ -1085,15 +1118,13 @@ static T* vcycle_impl(Engine* e, std::vector<Level>& lv, int l, const EngineOpts
     probe_end(kProbeRestrict, s,
               (double)Ln.rows_rtiles * (4 + sizeof(T)) + (double)L.rows_vctiles * (4 + 2 * sizeof(T)));
     T* xc = vcycle_level<T>(e, lv, l + 1, o, act, s, nullptr);
+    for (int v = 1; v < o.gamma; ++v) xc = vcycle_level<T>(e, lv, l + 1, o, act, s, nullptr, nullptr, xc);
     probe_begin(kProbeProlong, s);
     cyc_prolong<T>(L.vctiles.p, L.nvctiles, act, L.pc.p, LV<T>::pv(L), xc, cur, s);
     probe_end(kProbeProlong, s,
               (double)L.rows_vctiles * (PW * (4 + sizeof(T)) + 2 * sizeof(T)) + (double)Ln.rows_rtiles * sizeof(T));
     for (int k = 0; k < o.nu2; ++k) {
-      probe_begin(kProbeSmooth, s);
-      cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, D, b, cur, nxt, om, 0, L.gA, s,
-                    k + 1 == o.nu2 ? sol : nullptr);
-      probe_end(kProbeSmooth, s, bytes_smooth<T>(L, false));
+      relax_sweep<T>(L, o, act, b, cur, nxt, tmp, s, k + 1 == o.nu2 ? sol : nullptr);
       std::swap(cur, nxt);
     }
   }
@@ -1101,13 +1132,13 @@ static T* vcycle_impl(Engine* e, std::vector<Level>& lv, int l, const EngineOpts
   return cur;
 }
 
-// V-cycle on level l: the level-by-level part, then one launch for the games
+// Cycle on level l: the level-by-level part, then one launch for the games
 // whose tail starts here, writing into the same buffer.
 template <class T>
 static T* vcycle_level(Engine* e, std::vector<Level>& lv, int l, const EngineOpts& o, const int* act,
-                       hipStream_t s, double* sol, const TailRefine* rf = nullptr) {
+                       hipStream_t s, double* sol, const TailRefine* rf, T* start) {
   Level& L = lv[l];
-  T* res = L.upper ? vcycle_impl<T>(e, lv, l, o, act, s, sol) : LV<T>::x(L);
+  T* res = L.upper ? vcycle_impl<T>(e, lv, l, o, act, s, sol, start) : (start ? start : LV<T>::x(L));
   if (L.ntailg) {
     double bytes = 0.0;
     if (probe_on(kProbeTail))
@@ -1122,8 +1153,8 @@ static T* vcycle_level(Engine* e, std::vector<Level>& lv, int l, const EngineOpt
       }
     probe_begin(kProbeTail, s);
     cyc_tail<T>(L.tailg.p, L.ntailg, l, e->num_levels(), e->num_slots(), e->tail_levels((T*)nullptr),
-                e->tail_games(), act, (T)o.omega, o.nu1, o.nu2, res == LV<T>::y(L) ? 1 : 0, L.tail_lds_rows, s,
-                sol, rf);
+                e->tail_games(), act, (T)relax_weight(o), o.nu1, o.nu2, res == LV<T>::y(L) ? 1 : 0,
+                L.tail_lds_rows, s, sol, rf);
     probe_end(kProbeTail, s, rf ? 0.0 : bytes);  // refinement: bytes once the cycles are known
     if (rf) e->tail_cycle_bytes = bytes;
   }
@@ -1170,7 +1201,7 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
     launch_lin_check(fold, G, d_bnorm.p, d_lin.p, d_lin_active, d_norm.p, stream);
   };
   // every level-0 row ends its cycle in a post-smoothing sweep or in a tail
-  const bool fuse_update = o.nu2 >= 1 && L0.nvblk == 0;
+  const bool fuse_update = o.nu2 >= 1 && L0.nvblk == 0 && o.smoother != SHAPLEY_SMOOTH_CF;
   resid_check();
   if (fuse_update && !L0.upper && L0.ntailg > 0) {
     // every game's tail starts on level 0: all its cycles, FP64 residuals and
@@ -1341,6 +1372,13 @@ int Engine::step() {
     refresh(o);
     ++refreshes;
   }
+  if (o.smoother == SHAPLEY_SMOOTH_L1) {
+    // l1-Jacobi: the relaxation diagonals replace 1/a_ii once setup or refresh
+    // (whose interpolation and Dirichlet scaling read 1/a_ii) is done
+    for (int l = 0; l < nlev; ++l)
+      amg_l1_diag(lv[l].tiles.p, lv[l].ntiles, lv[l].rp.p, lv[l].a64.p, lv[l].dinv64.p,
+                  mixed ? lv[l].dinv32.p : nullptr, stream);
+  }
   pt.mark("setup");
   double t1 = now_s();  // a full setup ends with a synchronisation; a refresh does not
   {
@@ -1412,7 +1450,14 @@ int Engine::step() {
       S->resolves += 1;
     } else {
       if (S->k <= 64) S->inner_per_outer[S->k - 1] = S->nk;
-      if (nout == 0) {
+      if (nout == 0 && nin > 0) {
+        // MIN still improves but its loop was cut by max_inner, and MAX has
+        // nothing to improve against an inexact inner solution: the stop of
+        // Algorithm PIalgo assumes an exact inner loop, so this is no fixed
+        // point (the residual is above eps, tested above)
+        S->status = SHAPLEY_ENOCONV;
+        S->done = true;
+      } else if (nout == 0) {
         S->converged = true;
         S->done = true;
       } else if (S->k >= S->opt.max_outer) {
@@ -1452,6 +1497,8 @@ EngineOpts engine_opts_from(const shapley_solve_opts& o, int dim) {
   e.verbose = o.verbose;
   e.reuse_frac = o.reuse_frac;
   e.forcing = o.forcing;
+  e.smoother = o.smoother;
+  e.gamma = o.gamma;
   return e;
 }
 

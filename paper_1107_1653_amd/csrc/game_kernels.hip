@@ -306,6 +306,9 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
     }
     int ac = lowa;
     if (al >= 0 && inner_al >= F - tie_rtol * scall) ac = al;
+    // an incumbent alpha with no valid b (never produced by the library: warm
+    // starts and transfers are checked) is not kept
+    const bool al_ok = al >= 0 && inner_al > -INFINITY;
     // MIN's answer at the new alpha (keep the incumbent if alpha is unchanged)
     int bc = -1;
     {
@@ -322,6 +325,7 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
           sq[base + ac * d.m2 + be] <= mn + tie_rtol * sc)
         bc = be;
     }
+    if (!al_ok) bin = bc;  // never -1: MIN's answer at MAX's improvement
     d.beta_in[x] = bin;
     d.alpha_c[x] = ac;
     d.beta_c[x] = bc;
@@ -330,7 +334,7 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
     res = dv == dv ? fabs(dv) : INFINITY;
     res2 = dv * dv;
     chg_in = (bin != be) ? 1 : 0;
-    chg_out = (ac != al) ? 1 : 0;
+    chg_out = (ac != al || !al_ok) ? 1 : 0;
   }
   // per-game max |F(v) - v|, sum (F(v) - v)^2 and change counts
   const double vd[2] = {warp_max(res), warp_sum(res2)};
@@ -434,7 +438,8 @@ void launch_apply(const GameDesc* d, const GTile* t, int nt, const int* decision
 __global__ void k_fmg(int dim, int sc, int sf, const double* __restrict__ vc,
                       const int* __restrict__ ac, const int* __restrict__ bc,
                       const double* __restrict__ bvals, double* __restrict__ vf,
-                      int* __restrict__ af, int* __restrict__ bf, int nf) {
+                      int* __restrict__ af, int* __restrict__ bf, int nf,
+                      const uint8_t* __restrict__ valid_f, int m1, int m2) {
   int xf = blockIdx.x * blockDim.x + threadIdx.x;
   if (xf >= nf) return;
   int kk[3] = {0, 0, 0};
@@ -479,19 +484,170 @@ __global__ void k_fmg(int dim, int sc, int sf, const double* __restrict__ vc,
     lin += (c - 1) * stride;
     stride *= sc;
   }
-  af[xf] = ac[lin];
-  bf[xf] = bc[lin];
+  int a = ac[lin], b = bc[lin];
+  if (valid_f) {
+    // the fine game may mask the copied pair: take MIN's lowest valid action
+    // at the copied a, else the lowest valid pair (every state has one)
+    const uint8_t* vx = valid_f + (int64_t)xf * m1 * m2;
+    if (a < 0 || a >= m1 || b < 0 || b >= m2 || !vx[a * m2 + b]) {
+      int nb = -1;
+      if (a >= 0 && a < m1)
+        for (int q = 0; q < m2 && nb < 0; ++q)
+          if (vx[a * m2 + q]) nb = q;
+      if (nb >= 0) {
+        b = nb;
+      } else {
+        for (int q = 0; q < m1 * m2; ++q)
+          if (vx[q]) { a = q / m2; b = q % m2; break; }
+      }
+    }
+  }
+  af[xf] = a;
+  bf[xf] = b;
 }
 
 void launch_fmg(const Game* c, const Game* f, hipStream_t s) {
   if (f->n == 0) return;
   hipLaunchKernelGGL(k_fmg, dim3(grid_for(f->n)), dim3(kBlock), 0, s, c->dim, c->s, f->s, c->v.p,
                      c->alpha.p, c->beta.p, c->has_bvals ? c->bvals.p : (const double*)nullptr,
-                     f->v.p, f->alpha.p, f->beta.p, f->n);
+                     f->v.p, f->alpha.p, f->beta.p, f->n, f->valid.p, f->m1, f->m2);
   SHP_LAUNCH_CHECK();
 }
 
 void fmg_transfer(Game* coarse, Game* fine, hipStream_t s) { launch_fmg(coarse, fine, s); }
+
+// ---------------------------------------------------------------------------
+// Checks of a game handed over in device memory: the conditions the create
+// call states for host arrays, evaluated per row (row pointer monotone and
+// within the entries, columns in [0, n), weights finite and >= 0, row sum
+// <= 1 + 1e-12 summed in entry order, finite reward), per state (a valid
+// pair), and a flag for rows whose columns are not ascending.
+// ---------------------------------------------------------------------------
+__global__ void k_check_game(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                             const double* __restrict__ w, const double* __restrict__ r, int nrows, int n,
+                             int64_t nnz, int* __restrict__ err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  int bits = 0;
+  const int64_t e0 = rp[i], e1 = rp[i + 1];
+  if (i == 0 && e0 != 0) bits |= kChkRp0;
+  if (e0 < 0 || e1 < e0 || e1 > nnz) {
+    bits |= kChkRp;
+  } else {
+    double sum = 0.0;
+    int last = INT_MIN;
+    for (int64_t e = e0; e < e1; ++e) {
+      const int c = ci[e];
+      const double x = w[e];
+      if (c < 0 || c >= n) bits |= kChkCol;
+      if (!(x >= 0.0 && x <= 1.7976931348623157e308)) bits |= kChkW;
+      if (c < last) bits |= kChkUnsorted;
+      last = c;
+      sum += x;
+    }
+    if (!(sum <= 1.0 + 1e-12) && !(bits & kChkW)) bits |= kChkSum;
+  }
+  const double ri = r[i];
+  if (!(ri - ri == 0.0)) bits |= kChkR;
+  if (bits) atomicOr(err, bits);
+}
+
+__global__ void k_check_valid(const uint8_t* __restrict__ valid, int n, int K, int* __restrict__ err) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  bool any = false;
+  for (int q = 0; q < K; ++q) any |= valid[(int64_t)x * K + q] != 0;
+  if (!any) atomicOr(err, kChkEmpty);
+}
+
+__global__ void k_rp_narrow(const int64_t* __restrict__ in, int* __restrict__ out, int m) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) out[i] = (int)in[i];
+}
+
+// stable insertion sort of each row's (column, weight) pairs, one thread per row
+__global__ void k_sort_pairs(const int* __restrict__ rp, int* __restrict__ ci, double* __restrict__ w,
+                             int nrows) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  const int e0 = rp[i], e1 = rp[i + 1];
+  for (int e = e0 + 1; e < e1; ++e) {
+    const int c = ci[e];
+    const double x = w[e];
+    int f = e - 1;
+    while (f >= e0 && ci[f] > c) {
+      ci[f + 1] = ci[f];
+      w[f + 1] = w[f];
+      --f;
+    }
+    ci[f + 1] = c;
+    w[f + 1] = x;
+  }
+}
+
+// warm-start strategies against the game: bit 1 = alpha out of range or with
+// no valid b (the action is not available), bit 2 = beta out of range or the
+// pair (alpha, beta) not valid
+__global__ void k_check_policy(const int* __restrict__ alpha, const int* __restrict__ beta,
+                               const uint8_t* __restrict__ valid, int n, int m1, int m2, int* __restrict__ err) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  const int a = alpha[x];
+  int bits = 0;
+  if (a < 0 || a >= m1) {
+    bits |= 1;
+  } else if (valid) {
+    bool any = false;
+    for (int b = 0; b < m2; ++b) any |= valid[((int64_t)x * m1 + a) * m2 + b] != 0;
+    if (!any) bits |= 1;
+  }
+  if (beta && !(bits & 1)) {
+    const int b = beta[x];
+    if (b < 0 || b >= m2 || (valid && !valid[((int64_t)x * m1 + a) * m2 + b])) bits |= 2;
+  }
+  if (bits) atomicOr(err, bits);
+}
+
+int check_game_device(const int64_t* rp, const int32_t* ci, const double* w, const double* r,
+                      const uint8_t* valid, int n, int K, int64_t nnz, int* err_dev, hipStream_t s) {
+  const int nrows = n * K;
+  fill_async(err_dev, 0, 1, s);
+  hipLaunchKernelGGL(k_check_game, dim3(grid_for(nrows)), dim3(kBlock), 0, s, rp, ci, w, r, nrows, n, nnz,
+                     err_dev);
+  SHP_LAUNCH_CHECK();
+  if (valid) {
+    hipLaunchKernelGGL(k_check_valid, dim3(grid_for(n)), dim3(kBlock), 0, s, valid, n, K, err_dev);
+    SHP_LAUNCH_CHECK();
+  }
+  int bits = 0;
+  d2h(&bits, err_dev, 1, s);
+  SHP_HIP(hipStreamSynchronize(s));
+  return bits;
+}
+
+void launch_rp_narrow(const int64_t* in, int* out, int m, hipStream_t s) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_rp_narrow, dim3(grid_for(m)), dim3(kBlock), 0, s, in, out, m);
+  SHP_LAUNCH_CHECK();
+}
+
+void launch_sort_pairs(const int* rp, int* ci, double* w, int nrows, hipStream_t s) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(k_sort_pairs, dim3(grid_for(nrows)), dim3(kBlock), 0, s, rp, ci, w, nrows);
+  SHP_LAUNCH_CHECK();
+}
+
+int check_policy_device(const int* alpha, const int* beta, const uint8_t* valid, int n, int m1, int m2,
+                        int* err_dev, hipStream_t s) {
+  fill_async(err_dev, 0, 1, s);
+  hipLaunchKernelGGL(k_check_policy, dim3(grid_for(n)), dim3(kBlock), 0, s, alpha, beta, valid, n, m1, m2,
+                     err_dev);
+  SHP_LAUNCH_CHECK();
+  int bits = 0;
+  d2h(&bits, err_dev, 1, s);
+  SHP_HIP(hipStreamSynchronize(s));
+  return bits;
+}
 
 // ---------------------------------------------------------------------------
 // exclusive scan of int32 (block scan + recursive scan of block sums)

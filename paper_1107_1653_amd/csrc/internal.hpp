@@ -194,6 +194,8 @@ struct EngineOpts {
   int verbose = 0;
   double reuse_frac = 0.05;
   double forcing = 0.0;
+  int smoother = SHAPLEY_SMOOTH_JACOBI;
+  int gamma = 1;
 };
 
 EngineOpts engine_opts_from(const shapley_solve_opts& o, int dim);
@@ -381,7 +383,7 @@ class Engine {
   DPtr<TailLev<double>> d_tail64;
   DPtr<TailLev<float>> d_tail32;
   std::vector<int> h_lt;  // first tail level of each game (nlev: none)
-  void build_tail(bool mixed);
+  void build_tail(bool mixed, bool allow);  // allow = false: no game takes the tail kernel
   DBuf<LinCtl> d_lin;                         // [G] controls, then the active flags
   int* d_lin_active = nullptr;                // [G] (inside d_lin)
   std::vector<LinCtl> h_linbuf;
@@ -486,6 +488,24 @@ void launch_union_count(const int* rp, const int* ci, int n, int m1, int m2, int
 void launch_union_fill(const int* rp, const int* ci, int n, int m1, int m2, const int* urp, int* uci,
                        hipStream_t s);
 void launch_fmg(const Game* c, const Game* f, hipStream_t s);
+
+// Checks of a game given in device memory (error bits kChk*; synchronises s).
+enum {
+  kChkRp0 = 1, kChkRp = 2, kChkCol = 4, kChkW = 8, kChkSum = 16, kChkR = 32, kChkEmpty = 64,
+  kChkUnsorted = 128
+};
+int check_game_device(const int64_t* rp, const int32_t* ci, const double* w, const double* r,
+                      const uint8_t* valid, int n, int K, int64_t nnz, int* err_dev, hipStream_t s);
+void launch_rp_narrow(const int64_t* in, int* out, int m, hipStream_t s);
+void launch_sort_pairs(const int* rp, int* ci, double* w, int nrows, hipStream_t s);
+// Warm-start strategies (device arrays; beta may be null) against the game:
+// bit 1 alpha unavailable or out of range, bit 2 beta or the pair invalid.
+// Checks solve options (EINVAL).
+void check_solve_opts(const shapley_solve_opts& o);
+// Checks warm-start strategies (host arrays) of game g; throws EINVAL.
+void check_warm_start(Game* g, const int32_t* alpha0, const int32_t* beta0, hipStream_t s);
+int check_policy_device(const int* alpha, const int* beta, const uint8_t* valid, int n, int m1, int m2,
+                        int* err_dev, hipStream_t s);
 
 // device scan (exclusive) of n ints into out (out may alias in):
 // out[i] = in[0] + ... + in[i-1] for i < n.  in[n-1] reaches no output, so a

@@ -2,17 +2,25 @@
 //
 // Submitted games (or FAMGpi hierarchies) wait in a FIFO queue.  A scheduling
 // step admits queued requests while their estimated device footprint fits the
-// HBM budget, then advances every active request by one policy-iteration step
-// in one lock-step engine (one merged launch per kernel for all of them).
-// Requests leave as they converge and free their budget; an FAMGpi request
-// that finishes a grid moves to the next finer grid in place (its state is
-// transferred by I and U) without leaving the batch.  Requests that arrive
-// while others run join at the next step boundary.
+// HBM budget and advances every active request by one policy-iteration step.
+// Requests admitted together with the same engine options form a cohort: one
+// lock-step engine on a stream of its own, whose merged launches serve all of
+// them and whose AMG hierarchy stays on the device until its last member
+// leaves (a member that converges leaves without a rebuild: the hierarchy
+// serves any subset of the games it was built for).  Cohorts run concurrently,
+// each stepped by its own host thread on its own stream, so that the work of
+// requests admitted at different times overlaps on the device.  An FAMGpi
+// request that finishes a grid moves to the next finer grid (its state is
+// transferred by I and U) and joins a new cohort there.  When the cohort
+// count reaches its limit, newly admitted requests join the compatible cohort
+// with the fewest running unknowns (that cohort rebuilds its hierarchy).
 #include "internal.hpp"
+#include "probe.hpp"
 
 #include <chrono>
 #include <cstring>
 #include <deque>
+#include <future>
 #include <map>
 #include <mutex>
 
@@ -21,6 +29,10 @@ namespace shp {
 static double wall_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
+
+constexpr int kMaxCohorts = 16;
+
+struct Cohort;
 
 struct Request {
   uint64_t ticket = 0;
@@ -33,13 +45,53 @@ struct Request {
   bool famg = false;
   bool done = false;
   int status = SHAPLEY_OK;
-  SlotState slot;
+  std::string msg;          // error message of a failed request
+  SlotState* slot = nullptr;  // inside the current cohort
+  Cohort* cohort = nullptr;
   double t_submit = 0, t_admit = 0, t_done = 0;
   int outer = 0, inner = 0, cycles = 0;
+  int sfull = 0, sref = 0, vsteps = 0;
   double setup_s = 0, cycle_s = 0, improve_s = 0;
   shapley_stats stats{};
 
   Game* current() { return famg ? handle->levels[level] : handle->finest(); }
+};
+
+// Engine options that act on the whole merged hierarchy or sweep: requests
+// share a cohort only when all of them agree.
+struct CohortKey {
+  int precision, nu1, nu2, coarse_max, max_levels, smoother, gamma;
+  double theta, omega, reuse_frac, tie_rtol;
+  bool operator==(const CohortKey& o) const {
+    return precision == o.precision && nu1 == o.nu1 && nu2 == o.nu2 && coarse_max == o.coarse_max &&
+           max_levels == o.max_levels && smoother == o.smoother && gamma == o.gamma && theta == o.theta &&
+           omega == o.omega && reuse_frac == o.reuse_frac && tie_rtol == o.tie_rtol;
+  }
+};
+static CohortKey key_of(const shapley_solve_opts& o) {
+  return CohortKey{o.precision, o.nu1,   o.nu2,   o.coarse_max, o.max_levels, o.smoother,
+                   o.gamma,     o.theta, o.omega, o.reuse_frac, o.tie_rtol};
+}
+
+struct Cohort {
+  CohortKey key{};
+  hipStream_t stream = nullptr;
+  std::unique_ptr<Engine> eng;
+  std::vector<std::unique_ptr<SlotState>> slots;  // one per membership
+  std::vector<Request*> members;                  // members[i] runs in slots[i]
+  int error = SHAPLEY_OK;
+  std::string msg;
+  int64_t running_unknowns() const {
+    int64_t u = 0;
+    for (const auto& s : slots)
+      if (!s->done) u += s->g->n;
+    return u;
+  }
+  bool running() const {
+    for (const auto& s : slots)
+      if (!s->done) return true;
+    return false;
+  }
 };
 
 }  // namespace shp
@@ -48,13 +100,17 @@ struct shapley_server_s {
   std::mutex mu;        // queue, tickets, results
   std::mutex step_mu;   // one scheduler at a time
   size_t budget = 0, used = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
+  int device = 0;
+  hipStream_t stream = nullptr;  // the caller's stream (all cohorts on it), or null
   uint64_t next_ticket = 1;
   std::deque<shp::Request*> queue;
   std::vector<shp::Request*> active;
   std::map<uint64_t, shp::Request*> all;
-  std::unique_ptr<shp::Engine> eng;
+  std::vector<std::unique_ptr<shp::Cohort>> cohorts;
+  // idle engines with their streams, reused by new cohorts (their device
+  // buffers are kept: a cohort no larger than an earlier one allocates nothing)
+  std::vector<std::pair<hipStream_t, std::unique_ptr<shp::Engine>>> pool;
+  std::vector<hipStream_t> own_streams;
 };
 
 namespace shp {
@@ -69,65 +125,181 @@ static size_t estimate_footprint(Game* h) {
   return b;
 }
 
-static void init_slot(Request* r, hipStream_t s) {
+// A fresh slot for the request's current grid, its start (v, alpha, beta)
+// written on stream s: the warm start on the first grid, the state
+// transferred from the coarser grid on the others.
+static std::unique_ptr<SlotState> make_slot(Request* r, hipStream_t s) {
   Game* g = r->current();
-  r->slot = SlotState();
-  r->slot.g = g;
-  r->slot.opt = engine_opts_from(r->opts, g->dim);
+  std::unique_ptr<SlotState> S(new SlotState());
+  S->g = g;
+  S->opt = engine_opts_from(r->opts, g->dim);
   const bool last = !r->famg || r->level == (int)r->handle->levels.size() - 1;
   if (r->famg && !last) {
     double h = 1.0 / (g->s + 1);
-    r->slot.opt.eps = r->opts.c_fmg * h * h;
+    S->opt.eps = r->opts.c_fmg * h * h;
   }
   if (r->level > 0) {
-    r->slot.init_alpha = r->slot.init_beta = true;  // v, alpha, beta transferred from the coarser grid
-    return;
+    S->init_alpha = S->init_beta = true;  // v, alpha, beta transferred from the coarser grid
+    return S;
   }
   const int n = g->n;
   if (!r->v0.empty()) h2d(g->v.p, r->v0.data(), n, s);
-  else SHP_HIP(hipMemsetAsync(g->v.p, 0, sizeof(double) * n, s));
+  else fill_async(g->v.p, 0.0, n, s);
   if (!r->alpha0.empty()) {
     h2d(g->alpha.p, r->alpha0.data(), n, s);
-    r->slot.init_alpha = true;
+    S->init_alpha = true;
   } else {
-    SHP_HIP(hipMemsetAsync(g->alpha.p, 0xFF, sizeof(int) * n, s));
+    fill_async(g->alpha.p, -1, n, s);
   }
   if (!r->alpha0.empty() && !r->beta0.empty()) {
     h2d(g->beta.p, r->beta0.data(), n, s);
-    r->slot.init_beta = true;
+    S->init_beta = true;
   } else {
-    SHP_HIP(hipMemsetAsync(g->beta.p, 0xFF, sizeof(int) * n, s));
+    fill_async(g->beta.p, -1, n, s);
   }
   SHP_HIP(hipStreamSynchronize(s));
+  return S;
 }
 
-static void finish(shapley_server_s* srv, Request* r) {
+static void finish(shapley_server_s* srv, Request* r, int status, const std::string& msg) {
+  SlotState* S = r->slot;
   r->done = true;
+  r->status = status;
+  r->msg = msg;
   r->t_done = wall_s();
   std::memset(&r->stats, 0, sizeof(r->stats));
   r->stats.outer = r->outer;
   r->stats.inner_total = r->inner;
   r->stats.cycles_total = r->cycles;
-  r->stats.levels = r->slot.levels;
-  r->stats.converged = r->slot.converged ? 1 : 0;
   r->stats.fmg_levels = r->famg ? r->level + 1 : 1;
-  r->stats.residual = r->slot.res;
-  r->stats.residual_l2 = r->slot.res_l2;
   r->stats.seconds = r->t_done - r->t_submit;  // latency: completion - submission
   r->stats.setup_seconds = r->setup_s;
   r->stats.cycle_seconds = r->cycle_s;
   r->stats.improve_seconds = r->improve_s;
-  r->stats.op_complexity = r->slot.opc;
-  r->stats.grid_complexity = r->slot.gc;
-  std::memcpy(r->stats.inner_per_outer, r->slot.inner_per_outer, sizeof(r->stats.inner_per_outer));
+  r->stats.setups_full = r->sfull;
+  r->stats.setups_refresh = r->sref;
+  r->stats.value_steps = r->vsteps;
+  if (S) {
+    r->stats.levels = S->levels;
+    r->stats.converged = S->converged && status == SHAPLEY_OK ? 1 : 0;
+    r->stats.residual = S->res;
+    r->stats.residual_l2 = S->res_l2;
+    r->stats.op_complexity = S->opc;
+    r->stats.grid_complexity = S->gc;
+    std::memcpy(r->stats.inner_per_outer, S->inner_per_outer, sizeof(r->stats.inner_per_outer));
+  }
   r->handle->finest()->solved = true;
+  r->cohort = nullptr;
+  r->slot = nullptr;  // owned by the cohort, which may retire now
   srv->used -= r->footprint;
+}
+
+static void account(Request* r) {
+  const SlotState& S = *r->slot;
+  r->outer += S.k;
+  r->inner += S.inner_total;
+  r->cycles += S.cycles_total;
+  r->sfull += S.setups_full;
+  r->sref += S.setups_refresh;
+  r->vsteps += S.solves;
+  r->setup_s += S.setup_s;
+  r->cycle_s += S.cycle_s;
+  r->improve_s += S.improve_s;
+}
+
+static Cohort* new_cohort(shapley_server_s* srv, const CohortKey& key) {
+  std::unique_ptr<Cohort> c(new Cohort());
+  c->key = key;
+  if (srv->stream) {
+    c->stream = srv->stream;
+    c->eng.reset(new Engine(srv->stream));
+  } else if (!srv->pool.empty()) {
+    c->stream = srv->pool.back().first;
+    c->eng = std::move(srv->pool.back().second);
+    srv->pool.pop_back();
+  } else {
+    hipStream_t s;
+    SHP_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    srv->own_streams.push_back(s);
+    c->stream = s;
+    c->eng.reset(new Engine(s));
+  }
+  c->eng->reset();
+  srv->cohorts.emplace_back(std::move(c));
+  return srv->cohorts.back().get();
+}
+
+// Puts requests (already counted in the budget) into cohorts: a new cohort
+// per group of equal engine options, or, with the cohort count at its limit,
+// the compatible cohort with the fewest running unknowns.
+static void place(shapley_server_s* srv, const std::vector<Request*>& rs) {
+  std::vector<std::pair<CohortKey, std::vector<Request*>>> groups;
+  for (Request* r : rs) {
+    const CohortKey k = key_of(r->opts);
+    bool found = false;
+    for (auto& gr : groups)
+      if (gr.first == k) { gr.second.push_back(r); found = true; break; }
+    if (!found) groups.push_back({k, {r}});
+  }
+  for (auto& gr : groups) {
+    Cohort* c = nullptr;
+    bool joining = false;
+    if ((int)srv->cohorts.size() >= kMaxCohorts) {
+      int64_t best = INT64_MAX;
+      for (auto& q : srv->cohorts)
+        if (q->key == gr.first && q->error == SHAPLEY_OK && q->running_unknowns() < best) {
+          best = q->running_unknowns();
+          c = q.get();
+        }
+      joining = c != nullptr;
+    }
+    if (!c) c = new_cohort(srv, gr.first);
+    if (joining) {
+      // finished memberships leave the merged layout at this rebuild
+      std::vector<std::unique_ptr<SlotState>> keep_s;
+      std::vector<Request*> keep_m;
+      for (size_t i = 0; i < c->slots.size(); ++i)
+        if (!c->slots[i]->done) {
+          keep_s.push_back(std::move(c->slots[i]));
+          keep_m.push_back(c->members[i]);
+        }
+      c->slots.swap(keep_s);
+      c->members.swap(keep_m);
+    }
+    for (Request* r : gr.second) {
+      c->slots.push_back(make_slot(r, c->stream));
+      c->members.push_back(r);
+      r->slot = c->slots.back().get();
+      r->cohort = c;
+    }
+    c->eng->slots.clear();
+    for (auto& s : c->slots) c->eng->slots.push_back(s.get());
+    c->eng->invalidate_layout();
+  }
+}
+
+static void step_cohort(Cohort* c, int device) {
+  try {
+    SHP_HIP(hipSetDevice(device));
+    c->eng->step();
+    SHP_HIP(hipStreamSynchronize(c->stream));
+  } catch (const Error& e) {
+    c->error = e.code;
+    c->msg = e.what();
+  } catch (const std::bad_alloc&) {
+    c->error = SHAPLEY_ENOMEM;
+    c->msg = "host allocation failed";
+  } catch (const std::exception& e) {
+    c->error = SHAPLEY_EDEVICE;
+    c->msg = e.what();
+  }
 }
 
 // One scheduling step; returns the number of requests still active.
 static int server_step(shapley_server_s* srv) {
   std::lock_guard<std::mutex> sl(srv->step_mu);
-  bool changed = false;
+  SHP_HIP(hipSetDevice(srv->device));
+  std::vector<Request*> admitted;
   {
     std::lock_guard<std::mutex> lk(srv->mu);
     while (!srv->queue.empty()) {
@@ -137,53 +309,73 @@ static int server_step(shapley_server_s* srv) {
       srv->used += r->footprint;
       r->t_admit = wall_s();
       srv->active.push_back(r);
-      init_slot(r, srv->stream);
-      changed = true;
+      admitted.push_back(r);
     }
   }
+  if (!admitted.empty()) place(srv, admitted);
   if (srv->active.empty()) return 0;
-  if (!srv->eng) srv->eng.reset(new Engine(srv->stream));
-  Engine& eng = *srv->eng;
-  if (changed || eng.slots.size() != srv->active.size()) {
-    eng.slots.clear();
-    for (Request* r : srv->active) eng.slots.push_back(&r->slot);
-    eng.invalidate_layout();
+  // one policy-iteration step of every cohort with running members; cohorts on
+  // streams of their own step concurrently (the timing probe's event pairs are
+  // process-wide, so with a probe on they step one after the other)
+  std::vector<Cohort*> run;
+  for (auto& c : srv->cohorts)
+    if (c->error == SHAPLEY_OK && c->running()) run.push_back(c.get());
+  bool probing = false;
+  for (int f = 0; f < kProbeFamilies; ++f) probing |= probe_on(f);
+  if (run.size() == 1 || srv->stream || probing) {
+    for (Cohort* c : run) step_cohort(c, srv->device);
+  } else {
+    std::vector<std::future<void>> fut;
+    for (size_t i = 1; i < run.size(); ++i)
+      fut.push_back(std::async(std::launch::async, step_cohort, run[i], srv->device));
+    step_cohort(run[0], srv->device);
+    for (auto& f : fut) f.get();
   }
-  eng.step();
-  SHP_HIP(hipStreamSynchronize(srv->stream));
+  // leave, finish or move to the next grid
+  std::vector<Request*> moving;
   std::vector<Request*> keep;
-  bool moved = false;
   for (Request* r : srv->active) {
-    SlotState& S = r->slot;
+    Cohort* c = r->cohort;
+    SlotState& S = *r->slot;
+    if (c->error != SHAPLEY_OK) {
+      account(r);
+      std::lock_guard<std::mutex> lk(srv->mu);
+      finish(srv, r, c->error, c->msg);
+      continue;
+    }
     if (!S.done) { keep.push_back(r); continue; }
-    r->outer += S.k;
-    r->inner += S.inner_total;
-    r->cycles += S.cycles_total;
-    r->setup_s += S.setup_s;
-    r->cycle_s += S.cycle_s;
-    r->improve_s += S.improve_s;
+    account(r);
     const bool more = r->famg && r->level + 1 < (int)r->handle->levels.size() &&
                       (S.status == SHAPLEY_OK || S.status == SHAPLEY_ENOCONV);
     if (more) {
-      fmg_transfer(r->handle->levels[r->level], r->handle->levels[r->level + 1], srv->stream);
-      SHP_HIP(hipStreamSynchronize(srv->stream));
+      fmg_transfer(r->handle->levels[r->level], r->handle->levels[r->level + 1], c->stream);
+      SHP_HIP(hipStreamSynchronize(c->stream));
       r->level += 1;
-      init_slot(r, srv->stream);
+      r->cohort = nullptr;
+      r->slot = nullptr;
+      moving.push_back(r);
       keep.push_back(r);
-      moved = true;
       continue;
     }
-    r->status = S.status;
     std::lock_guard<std::mutex> lk(srv->mu);
-    finish(srv, r);
-    moved = true;
+    finish(srv, r, S.status, S.status == SHAPLEY_OK ? std::string() : "policy iteration stopped with an error");
   }
   srv->active.swap(keep);
-  if (moved) {
-    eng.slots.clear();
-    for (Request* r : srv->active) eng.slots.push_back(&r->slot);
-    eng.invalidate_layout();
+  // retire cohorts with no running member: their engines return to the pool
+  // (or are dropped after an error)
+  std::vector<std::unique_ptr<Cohort>> live;
+  for (auto& c : srv->cohorts) {
+    if (c->error == SHAPLEY_OK && c->running()) {
+      live.push_back(std::move(c));
+      continue;
+    }
+    if (c->error == SHAPLEY_OK && !srv->stream) {
+      c->eng->reset();
+      srv->pool.emplace_back(c->stream, std::move(c->eng));
+    }
   }
+  srv->cohorts.swap(live);
+  if (!moving.empty()) place(srv, moving);
   return (int)srv->active.size();
 }
 
@@ -198,10 +390,19 @@ static int sguard(F&& f) {
   } catch (const Error& e) {
     set_last_error(e.what());
     return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return SHAPLEY_ENOMEM;
   } catch (const std::exception& e) {
     set_last_error(e.what());
     return SHAPLEY_EDEVICE;
   }
+}
+
+static int result_of(shp::Request* r, shapley_stats* st) {
+  if (st) *st = r->stats;
+  if (r->status != SHAPLEY_OK) set_last_error(r->msg);
+  return r->status;
 }
 
 extern "C" {
@@ -209,18 +410,12 @@ extern "C" {
 int shapley_server_create(shapley_server_t* out, size_t hbm_budget, void* stream) {
   return sguard([&] {
     if (!out || hbm_budget == 0) throw Error(SHAPLEY_EINVAL, "server: out and a positive budget required");
+    int dev = 0;
+    SHP_HIP(hipGetDevice(&dev));
     auto* s = new shapley_server_s();
     s->budget = hbm_budget;
-    if (stream) {
-      s->stream = (hipStream_t)stream;
-    } else {
-      hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-      if (e != hipSuccess) {
-        delete s;
-        throw Error(SHAPLEY_EDEVICE, "server: stream creation failed");
-      }
-      s->own_stream = true;
-    }
+    s->device = dev;
+    s->stream = (hipStream_t)stream;
     *out = s;
     return SHAPLEY_OK;
   });
@@ -232,41 +427,32 @@ int shapley_server_submit(shapley_server_t srv, shapley_game_t g, const shapley_
     if (!srv || !g || !g->g || !ticket) throw Error(SHAPLEY_EINVAL, "server: null argument");
     shapley_solve_opts opts;
     if (o) opts = *o; else shapley_default_opts(&opts);
-    if (opts.nu1 < 1 || opts.max_outer < 1 || opts.max_inner < 1 || opts.max_cycles < 1 ||
-        opts.coarse_max < 1 || opts.coarse_max > kDenseMax || opts.max_levels < 1 || opts.max_levels > 64 ||
-        !(opts.omega > 0.0 && opts.omega < 2.0) || !(opts.eps >= 0.0) || !(opts.c_fmg > 0.0) ||
-        !(opts.forcing >= 0.0 && opts.forcing < 1.0) || !(opts.reuse_frac >= 0.0 && opts.reuse_frac <= 1.0))
-      throw Error(SHAPLEY_EINVAL, "server: invalid options");
-    auto* r = new Request();
+    check_solve_opts(opts);
+    std::unique_ptr<Request> r(new Request());
     r->handle = g->g;
     r->famg = g->g->is_hierarchy() && opts.method == SHAPLEY_FAMGPI;
     Game* first = r->famg ? g->g->levels[0] : g->g->finest();
     const int n = first->n;
+    // warm start checked against the first grid now (the game is not in use
+    // by the server before its admission)
+    check_warm_start(first, opts.alpha0, opts.alpha0 ? opts.beta0 : nullptr, first->stream);
     if (opts.alpha0) {
       r->alpha0.assign(opts.alpha0, opts.alpha0 + n);
-      for (int32_t a : r->alpha0)
-        if (a < 0 || a >= first->m1) { delete r; throw Error(SHAPLEY_EINVAL, "alpha0 out of range"); }
-      if (opts.beta0) {
-        r->beta0.assign(opts.beta0, opts.beta0 + n);
-        for (int32_t b : r->beta0)
-          if (b < 0 || b >= first->m2) { delete r; throw Error(SHAPLEY_EINVAL, "beta0 out of range"); }
-      }
+      if (opts.beta0) r->beta0.assign(opts.beta0, opts.beta0 + n);
     }
     if (opts.v0) r->v0.assign(opts.v0, opts.v0 + n);
     opts.alpha0 = opts.beta0 = nullptr;
     opts.v0 = nullptr;
     r->opts = opts;
     r->footprint = estimate_footprint(g->g);
-    if (r->footprint > srv->budget) {
-      delete r;
+    if (r->footprint > srv->budget)
       throw Error(SHAPLEY_ENOMEM, "server: request larger than the HBM budget");
-    }
     std::lock_guard<std::mutex> lk(srv->mu);
     r->ticket = srv->next_ticket++;
     r->t_submit = wall_s();
-    srv->queue.push_back(r);
-    srv->all[r->ticket] = r;
     *ticket = r->ticket;
+    srv->all[r->ticket] = r.get();
+    srv->queue.push_back(r.release());
     return SHAPLEY_OK;
   });
 }
@@ -279,8 +465,7 @@ int shapley_server_poll(shapley_server_t srv, uint64_t ticket, shapley_stats* st
     if (it == srv->all.end()) throw Error(SHAPLEY_EINVAL, "server: unknown ticket");
     Request* r = it->second;
     if (!r->done) return SHAPLEY_EAGAIN;
-    if (st) *st = r->stats;
-    return r->status;
+    return result_of(r, st);
   });
 }
 
@@ -304,28 +489,38 @@ int shapley_server_wait(shapley_server_t srv, uint64_t ticket, int32_t max_steps
         std::lock_guard<std::mutex> lk(srv->mu);
         auto it = srv->all.find(ticket);
         if (it == srv->all.end()) throw Error(SHAPLEY_EINVAL, "server: unknown ticket");
-        if (it->second->done) {
-          if (st) *st = it->second->stats;
-          return it->second->status;
-        }
+        if (it->second->done) return result_of(it->second, st);
       }
       server_step(srv);
     }
     std::lock_guard<std::mutex> lk(srv->mu);
-    Request* r = srv->all[ticket];
-    if (r->done) {
-      if (st) *st = r->stats;
-      return r->status;
-    }
+    auto it = srv->all.find(ticket);
+    if (it == srv->all.end()) throw Error(SHAPLEY_EINVAL, "server: unknown ticket");
+    if (it->second->done) return result_of(it->second, st);
     return SHAPLEY_EAGAIN;
+  });
+}
+
+int shapley_server_info(shapley_server_t srv, shapley_server_stats* st) {
+  return sguard([&] {
+    if (!srv || !st) throw Error(SHAPLEY_EINVAL, "server: null argument");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    std::memset(st, 0, sizeof(*st));
+    st->queued = (int32_t)srv->queue.size();
+    st->active = (int32_t)srv->active.size();
+    st->cohorts = (int32_t)srv->cohorts.size();
+    st->budget_used = srv->used;
+    st->budget = srv->budget;
+    return SHAPLEY_OK;
   });
 }
 
 void shapley_server_destroy(shapley_server_t srv) {
   if (!srv) return;
-  srv->eng.reset();
+  srv->cohorts.clear();
+  srv->pool.clear();
   for (auto& kv : srv->all) delete kv.second;
-  if (srv->own_stream && srv->stream) (void)hipStreamDestroy(srv->stream);
+  for (hipStream_t s : srv->own_streams) (void)hipStreamDestroy(s);
   delete srv;
 }
 

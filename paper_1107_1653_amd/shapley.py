@@ -27,6 +27,10 @@ SHAPLEY_MIXED = 1
 SHAPLEY_AMGPI = 0
 SHAPLEY_FAMGPI = 1
 SHAPLEY_HOST_PTRS = 0
+SHAPLEY_DEVICE_PTRS = 1
+SHAPLEY_SMOOTH_JACOBI = 0
+SHAPLEY_SMOOTH_L1 = 1
+SHAPLEY_SMOOTH_CF = 2
 
 EXPORTED = [
     "shapley_last_error", "shapley_default_opts", "shapley_game_create",
@@ -34,7 +38,7 @@ EXPORTED = [
     "shapley_apply_operator", "shapley_game_info", "shapley_game_bytes", "shapley_hierarchy_level",
     "shapley_game_destroy",
     "shapley_solve_batch", "shapley_server_create", "shapley_server_submit", "shapley_server_wait",
-    "shapley_server_poll", "shapley_server_step", "shapley_server_destroy",
+    "shapley_server_poll", "shapley_server_step", "shapley_server_destroy", "shapley_server_info",
     "shapley_probe_enable", "shapley_probe_read", "shapley_probe_read_large", "shapley_tune_lanes",
 ]
 PROBE = dict(smooth=0, resid64=1, improve=2, resid=3, restrict=4, prolong=5, rap=6, interp=7, tail=8)
@@ -59,7 +63,13 @@ class shapley_solve_opts(C.Structure):
         ("theta", C.c_double), ("nu1", C.c_int32), ("nu2", C.c_int32), ("omega", C.c_double),
         ("coarse_max", C.c_int32), ("max_levels", C.c_int32), ("verbose", C.c_int32),
         ("stream", C.c_void_p), ("reuse_frac", C.c_double), ("forcing", C.c_double),
+        ("smoother", C.c_int32), ("gamma", C.c_int32),
     ]
+
+
+class shapley_server_stats(C.Structure):
+    _fields_ = [("queued", C.c_int32), ("active", C.c_int32), ("cohorts", C.c_int32), ("reserved", C.c_int32),
+                ("budget_used", C.c_size_t), ("budget", C.c_size_t)]
 
 
 class shapley_level_info(C.Structure):
@@ -125,6 +135,7 @@ def lib() -> C.CDLL:
         L.shapley_server_wait.argtypes = [P, C.c_uint64, C.c_int32, C.POINTER(shapley_stats)]
         L.shapley_server_poll.argtypes = [P, C.c_uint64, C.POINTER(shapley_stats)]
         L.shapley_server_step.argtypes = [P, C.POINTER(C.c_int32)]
+        L.shapley_server_info.argtypes = [P, C.POINTER(shapley_server_stats)]
         L.shapley_server_destroy.argtypes = [P]
         L.shapley_server_destroy.restype = None
         L.shapley_probe_enable.argtypes = [C.c_int32, C.c_int32]
@@ -176,7 +187,18 @@ def shapley_default_opts(**kw) -> shapley_solve_opts:
     return o
 
 
+def _dev_ptr(t, dtype):
+    """Device pointer of a contiguous torch tensor of the given torch dtype."""
+    if t is None:
+        return None
+    if not (t.is_cuda and t.is_contiguous() and t.dtype == dtype):
+        raise ValueError(f"expected a contiguous device tensor of {dtype}")
+    return C.c_void_p(t.data_ptr())
+
+
 def shapley_game_create(n, m1, m2, row_ptr, col, w, r, mu, valid=None, grid=None, flags=0, stream=None):
+    if flags == SHAPLEY_DEVICE_PTRS:
+        return _create_device(n, m1, m2, row_ptr, col, w, r, mu, valid, grid, stream)
     rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
     ci = np.ascontiguousarray(col, dtype=np.int32)
     ww = np.ascontiguousarray(w, dtype=np.float64)
@@ -196,6 +218,29 @@ def shapley_game_create(n, m1, m2, row_ptr, col, w, r, mu, valid=None, grid=None
     st = None if stream is None else C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
     _check(lib().shapley_game_create(C.byref(h), int(n), int(m1), int(m2), _ptr(rp), _ptr(ci), _ptr(ww),
                                      _ptr(rr), float(mu), _ptr(vv), gp, int(flags), st))
+    return h
+
+
+def _create_device(n, m1, m2, row_ptr, col, w, r, mu, valid, grid, stream):
+    """Create from torch device tensors (int64 row_ptr, int32 col, float64 w and
+    r, uint8 valid, float64 grid bvals): only their pointers are passed."""
+    import torch
+    gp = None
+    keep = []
+    if grid is not None:
+        dim, s, bvals = grid
+        gs = shapley_grid()
+        gs.dim, gs.s = int(dim), int(s)
+        if bvals is not None:
+            keep.append(bvals)
+            gs.bvals = C.cast(_dev_ptr(bvals, torch.float64), C.POINTER(C.c_double))
+        gp = C.byref(gs)
+    h = C.c_void_p()
+    st = None if stream is None else C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+    _check(lib().shapley_game_create(C.byref(h), int(n), int(m1), int(m2), _dev_ptr(row_ptr, torch.int64),
+                                     _dev_ptr(col, torch.int32), _dev_ptr(w, torch.float64),
+                                     _dev_ptr(r, torch.float64), float(mu), _dev_ptr(valid, torch.uint8), gp,
+                                     SHAPLEY_DEVICE_PTRS, st))
     return h
 
 
@@ -331,6 +376,12 @@ def shapley_server_wait(srv, ticket: int, max_steps: int = 0):
     return d
 
 
+def shapley_server_info(srv) -> dict:
+    st = shapley_server_stats()
+    _check(lib().shapley_server_info(srv, C.byref(st)))
+    return {f: getattr(st, f) for f, _ in st._fields_ if f != "reserved"}
+
+
 def shapley_server_destroy(srv) -> None:
     lib().shapley_server_destroy(srv)
 
@@ -364,10 +415,25 @@ def shapley_probe_read_large(family, frac: float = 0.5) -> dict:
 # r, mu, valid and optionally grid (dim, s, bvals)
 # ---------------------------------------------------------------------------
 
-def create_from(game, stream=None):
+def create_from(game, stream=None, device=False):
+    """Handle of a game object; device=True first copies its arrays into torch
+    device tensors and creates from their pointers (SHAPLEY_DEVICE_PTRS)."""
     grid = None
     gr = getattr(game, "grid", None)
     if gr is not None and not getattr(gr, "periodic", False):
         grid = (gr.dim, gr.s, gr.bvals)
-    return shapley_game_create(game.n, game.m1, game.m2, game.row_ptr, game.col, game.w, game.r,
-                               game.mu, getattr(game, "valid", None), grid, 0, stream)
+    if not device:
+        return shapley_game_create(game.n, game.m1, game.m2, game.row_ptr, game.col, game.w, game.r,
+                                   game.mu, getattr(game, "valid", None), grid, 0, stream)
+    import torch
+
+    def t(a, dt):
+        return None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).cuda()
+
+    if grid is not None:
+        grid = (grid[0], grid[1], t(grid[2], np.float64))
+    args = (t(game.row_ptr, np.int64), t(game.col, np.int32), t(game.w, np.float64), t(game.r, np.float64))
+    valid = t(getattr(game, "valid", None), np.uint8)
+    torch.cuda.synchronize()  # the copies are complete before the library reads them
+    return shapley_game_create(game.n, game.m1, game.m2, *args, game.mu, valid, grid, SHAPLEY_DEVICE_PTRS,
+                               stream)
