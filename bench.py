@@ -1,14 +1,20 @@
 #!/usr/bin/env python3
 """Throughput benchmark: unknowns solved per second to a 1e-8 Shapley residual.
 
-Workload (one "step" = one complete solve): the obstacle problem
-min(-0.5 Lap v + lambda v - f, v - psi) = 0 on 1025 x 1025 points
-(1,046,529 unknowns, lambda = 0.5, f = 8 seeded Gaussian bumps,
-psi = 0.2 sin(pi x1) sin(pi x2)), solved by full multilevel policy iteration
-(FAMGpi, coarse grids 33, 65, ..., 1025 points, eps_l = 1e-2 h_l^2) to
-||F(v) - v||_inf <= 1e-8 in FP64, with the data resident on the GPU.  The
-same solve in mixed precision (FP32 V-cycles, FP64 refinement) is reported
-beside it; `--amgpi` adds single-grid AMGpi from "stop everywhere".
+Default workload (one "step" = one complete batched solve): 256 independent
+2-D Isaacs games, grid sides drawn from {65, 129, 257} interior points
+(sum n = 7,540,224 unknowns), lambda log-uniform in [0.1, 10], seeded
+f = sin(2 pi x1) cos(2 pi x2) + 0.1 N(0,1), solved together by batched
+policy iteration with the algebraic-multigrid inner solve (one launch per
+kernel and level for all games), FP32 V-cycles under FP64 refinement, to
+||F(v) - v||_inf <= 1e-8 per game, with the data resident on the GPU.  The
+same batch in FP64, and the games solved one by one in FP64 (plain GPU
+policy iteration), are reported beside it.  The 3-D Isaacs game on 129^3
+(FP64 and mixed) and the obstacle problem on 1025 x 1025 points (FAMGpi) are
+reported in `extra`, each with its own roofline.  `--workload` picks one of
+c0 (Isaacs 33^2 latency), c1 (obstacle), c2 (3-D Isaacs), c3 (the default),
+c4 (serving stream), two_stopper (the paper's 1-D example, AMGpi vs FAMGpi)
+or general (random sparse games without a grid) as the headline instead.
 
 Prints one JSON line (see the repository's benchmark contract).
 """
@@ -17,7 +23,6 @@ from __future__ import annotations
 import argparse
 import json
 import os
-import subprocess
 import sys
 import time
 
@@ -28,48 +33,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "unknowns solved/s to 1e-8 Shapley residual, FP64 vs mixed; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-# HBM-streaming kernel families reported on the finest level
-STREAMING = ("smooth", "resid", "resid64", "improve")
 CALIB_BYTES = 1 << 30  # bytes read (and written) by the calibration kernel
+# the limiter of each kernel family: streaming kernels are bound by HBM
+# bandwidth; the Galerkin product, interpolation and the one-workgroup V-cycle
+# tail are irregular, latency-bound kernels (reported against the HBM peak)
+BOUND = {"smooth": "hbm", "resid": "hbm", "resid64": "hbm", "improve": "hbm", "restrict": "hbm",
+         "prolong": "hbm", "rap": "latency", "interp": "latency", "tail": "latency"}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
-
-
-def cpu_baseline(points: int) -> dict:
-    """The oracle (plain FP64 CPU FAMGpi with SuperLU) on a smaller grid of the
-    same obstacle workload, one thread, in a child process."""
-    code = f"""
-import json, sys, time
-sys.path.insert(0, {ROOT!r})
-import numpy as np
-from shapley_inputs import configs
-import oracle
-levels = configs.c1_levels(points={points}, coarsest_points=33)
-a0 = np.zeros(levels[0].n, np.int32)
-t = time.perf_counter()
-res = oracle.famg_pi(levels, eps=1e-8, c=1e-2, alpha0=a0, beta0=a0)
-dt = time.perf_counter() - t
-print(json.dumps(dict(seconds=dt, n=levels[-1].n, residual=res[-1].residual)))
-"""
-    env = dict(os.environ)
-    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
-        env[k] = "1"
-    env["HIP_VISIBLE_DEVICES"] = ""
-    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
-                         timeout=600)
-    if out.returncode != 0:
-        raise RuntimeError(out.stderr)
-    d = json.loads(out.stdout.strip().splitlines()[-1])
-    return {
-        "value": d["n"] / d["seconds"],
-        "unit": "unknowns/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": (f"obstacle workload at {points}x{points} points (n={d['n']}), oracle FAMGpi "
-                   f"(SuperLU per policy) to 1e-8, {d['seconds']:.2f} s, residual {d['residual']:.1e}"),
-    }
 
 
 def parse_args():
@@ -77,56 +50,29 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--points", type=int, default=1025)
-    ap.add_argument("--cpu-points", type=int, default=1025)
+    ap.add_argument("--workload", default="c3",
+                    choices=["c0", "c1", "c2", "c3", "c4", "two_stopper", "general"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--amgpi", action="store_true")
-    ap.add_argument("--roofline-kernel", default="auto")
+    ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--forcing", type=float, default=0.1)
     ap.add_argument("--reuse", type=float, default=0.5)
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4"])
     ap.add_argument("--games", type=int, default=256, help="C3 batch size")
-    ap.add_argument("--requests", type=int, default=100, help="C4 requests")
+    ap.add_argument("--requests", type=int, default=1000, help="C4 requests")
     ap.add_argument("--side", type=int, default=129, help="C2 interior points per side")
+    ap.add_argument("--points", type=int, default=1025, help="C1 points per side")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one elementwise kernel of known traffic (reads and writes "
                          f"{CALIB_BYTES >> 20} MiB): the reference for hardware byte counters")
     return ap.parse_args()
 
 
-def main() -> int:
-    args = parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 (sharding across GPUs is not implemented)"}))
-        return 2
-    return {"c0": run_c0, "c1": run_c1, "c2": run_c2, "c3": run_c3, "c4": run_c4}[args.workload](args)
+# ---------------------------------------------------------------------------
+# measurement helpers
+# ---------------------------------------------------------------------------
 
-
-def base_record(args, value, ms_per_step, dtype, config):
-    return {"metric": METRIC, "value": value, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
-            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
-
-
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_obstacle1025_famg_fp64.json")
-
-
-def measured_traffic(family):
-    """HBM bytes per launch of a kernel family from the committed counter
-    summary, or None when it is missing or the kernel sources changed since."""
-    from paper_1107_1653_amd import rocprof_summary
-    try:
-        with open(TRAFFIC_FILE) as f:
-            d = json.load(f)
-    except OSError:
-        return None, "no counter summary"
-    if d.get("source_sha256") != rocprof_summary.source_hash():
-        return None, "kernel sources changed since the counters were taken"
-    fam = d.get("families", {}).get(family)
-    if fam is None:
-        return None, "family not in the counter summary"
-    return fam["bytes_per_launch"], os.path.relpath(TRAFFIC_FILE, ROOT)
+def sync():
+    import torch
+    torch.cuda.synchronize()
 
 
 def calibration_kernel():
@@ -135,306 +81,356 @@ def calibration_kernel():
     import torch
     x = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
-    torch.cuda.synchronize()
+    sync()
     torch.neg(x, out=y)
-    torch.cuda.synchronize()
+    sync()
     del x, y
 
 
-def run_c1(args) -> int:
+def family_profile(P, solve):
+    """One (untimed) solve with every kernel family probed by HIP events:
+    per family the device time of all launches and of its largest launches
+    (at least half the largest algorithmic bytes: the finest AMG level)."""
+    for k in P.PROBE:
+        P.shapley_probe_enable(k, True)
+    solve()
+    out = {}
+    for k in P.PROBE:
+        a = P.shapley_probe_read(k)
+        b = P.shapley_probe_read_large(k, 0.5)
+        P.shapley_probe_enable(k, False)
+        if a["launches"] == 0:
+            continue
+        out[k] = {"total_ms": a["ms"], "launches": a["launches"], "large_launches": b["launches"],
+                  "large_avg_us": 1e3 * b["ms"] / max(b["launches"], 1),
+                  "large_alg_bytes_per_launch": b["bytes"] / max(b["launches"], 1),
+                  "large_gbs": b["bytes"] / max(b["ms"] * 1e-3, 1e-30) / 1e9}
+        out[k]["large_frac"] = out[k]["large_gbs"] / HBM_PEAK_GBS
+    return out
 
-    import torch  # device synchronisation around the timed region only
-    import paper_1107_1653_amd as P
-    from shapley_inputs import configs
-    if args.calibrate_copy:
-        calibration_kernel()
 
-    t0 = time.perf_counter()
-    levels = configs.c1_levels(points=args.points, coarsest_points=33)
-    n = levels[-1].n
-    log(f"[bench] generated {len(levels)} grids up to n={n} in {time.perf_counter() - t0:.1f}s")
-    hs = [P.create_from(g) for g in levels]
-    H = P.shapley_game_create_hierarchy(hs)
-    a0 = np.zeros(levels[0].n, np.int32)
-
-    def opts(prec):
-        # inexact policy iteration: each linear solve to 0.1 x the previous
-        # Shapley residual; AMG splitting reused while < 50% of policies change
-        return P.shapley_default_opts(eps=1e-8, precision=prec, method=P.SHAPLEY_FAMGPI, alpha0=a0,
-                                      beta0=a0, max_outer=5000, max_inner=5000, forcing=args.forcing,
-                                      reuse_frac=args.reuse)
-
-    o64 = opts(P.SHAPLEY_FP64)
-    # pick the kernel family with the largest device time (one probed solve)
-    fam = args.roofline_kernel
-    if fam == "auto":
-        for k in P.PROBE:
-            P.shapley_probe_enable(k, True)
-        log("[bench] probing kernel families (one solve)")
-        P.shapley_solve(H, o64)
-        tot = {k: P.shapley_probe_read(k)["ms"] for k in P.PROBE}
-        for k in P.PROBE:
-            P.shapley_probe_enable(k, False)
-        fam = max(tot, key=tot.get)
-        log(f"[bench] per-family device ms of one solve: " +
-            ", ".join(f"{k}={v:.1f}" for k, v in sorted(tot.items(), key=lambda kv: -kv[1])))
-
-    for _ in range(args.warmup):
-        P.shapley_solve(H, o64)
-    P.shapley_probe_enable(fam, True)
-    torch.cuda.synchronize()
+def timed(P, solve, steps, warmup, probe_family=None):
+    """`warmup` untimed solves, then `steps` timed ones between device
+    synchronisations; with probe_family, that family's launches are bracketed
+    by HIP events on their stream during the timed solves."""
+    for _ in range(warmup):
+        solve()
+    sync()
+    if probe_family:
+        P.shapley_probe_enable(probe_family, True)
     lat = []
     st = None
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        t = time.perf_counter()
-        st = P.shapley_solve(H, o64)
-        lat.append(time.perf_counter() - t)
-        log(f"[bench] step {k}: {1e3 * lat[-1]:.1f} ms")
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    pr = P.shapley_probe_read(fam)
-    P.shapley_probe_enable(fam, False)
-    ms_per_step = 1e3 * wall / args.steps
-    value = n / (wall / args.steps)
-    log(f"[bench] FAMGpi FP64: {ms_per_step:.1f} ms/solve, residual {st['residual']:.2e}, "
-        f"outer {st['outer']}, cycles {st['cycles_total']}")
-
-    extra = {}
-    if not args.no_mixed:
-        om = opts(P.SHAPLEY_MIXED)
-        P.shapley_solve(H, om)
-        lm = []
-        for _ in range(args.steps):
-            t = time.perf_counter()
-            sm = P.shapley_solve(H, om)
-            lm.append(time.perf_counter() - t)
-        vm = P.shapley_get_value(H)
-        extra["mixed"] = {"value": n / float(np.mean(lm)), "ms_per_step": 1e3 * float(np.mean(lm)),
-                          "residual": sm["residual"]}
-        log(f"[bench] FAMGpi mixed: {1e3 * np.mean(lm):.1f} ms/solve, residual {sm['residual']:.2e}")
-    # the streaming kernels on the finest grid's level 0, timed with HIP
-    # events in one more (untimed) solve: relaxation, cycle residual, FP64
-    # residual, policy improvement
-    for k in STREAMING:
-        P.shapley_probe_enable(k, True)
-    P.shapley_solve(H, o64)
-    streaming = {}
-    for k in STREAMING:
-        r = P.shapley_probe_read_large(k, 0.5)
-        P.shapley_probe_enable(k, False)
-        if r["launches"] == 0:
-            continue
-        gbs = r["bytes"] / (r["ms"] * 1e-3) / 1e9
-        streaming[k] = {"achieved": gbs, "frac": gbs / HBM_PEAK_GBS, "launches": r["launches"],
-                        "avg_launch_us": 1e3 * r["ms"] / r["launches"],
-                        "alg_bytes_per_launch": r["bytes"] / r["launches"]}
-    log("[bench] finest-level streaming kernels: " +
-        ", ".join(f"{k} {v['achieved']:.0f} GB/s ({v['avg_launch_us']:.1f} us)" for k, v in streaming.items()))
-    # sizes of the finest grid's first AMG levels (the launches above)
-    first = P.shapley_hierarchy_level(H, 0, sizes_only=True)
-    fine_levels = []
-    for lvl in range(min(3, first["levels"])):
-        d = P.shapley_hierarchy_level(H, lvl, sizes_only=True)
-        fine_levels.append({"level": lvl, "n": int(d["n"]), "nnz": int(d["nnz"])})
-    v64 = P.shapley_get_value(H)
-    if not args.no_mixed:
-        extra["mixed"]["max_abs_diff_vs_fp64"] = float(np.max(np.abs(vm - v64)))
-    if args.amgpi:
-        g = levels[-1]
-        h = P.create_from(g)
-        oa = P.shapley_default_opts(eps=1e-8, alpha0=np.zeros(n, np.int32), beta0=np.zeros(n, np.int32),
-                                    max_outer=5000, forcing=args.forcing, reuse_frac=args.reuse)
-        t = time.perf_counter()
-        sa = P.shapley_solve(h, oa)
-        dt = time.perf_counter() - t
-        extra["amgpi_fp64"] = {"value": n / dt, "seconds": dt, "outer": sa["outer"]}
-        P.shapley_game_destroy(h)
-        log(f"[bench] AMGpi FP64: {dt:.2f} s, outer {sa['outer']}")
-
-    achieved = (pr["bytes"] / max(pr["launches"], 1)) / (pr["ms"] / max(pr["launches"], 1) * 1e-3) / 1e9
-    traffic, tsrc = measured_traffic(fam)
-    roof = {"bound": "hbm", "kernel": fam, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": tsrc,
-            "launches": pr["launches"], "avg_launch_us": 1e3 * pr["ms"] / max(pr["launches"], 1),
-            "alg_bytes_per_launch": pr["bytes"] / max(pr["launches"], 1)}
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        try:
-            cpu = cpu_baseline(args.cpu_points)
-        except Exception as e:  # the GPU number stands on its own
-            log(f"[bench] cpu baseline failed: {e}")
-    lat_ms = 1e3 * np.array(lat)
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "unknowns/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"obstacle VI {args.points}x{args.points} points (n={n}), FAMGpi FP64 to 1e-8",
-                   "n": n, "eps": 1e-8, "grids": [g.meta["points"] for g in levels],
-                   "forcing": args.forcing, "reuse_frac": args.reuse},
-        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
-        "solve": {"outer": st["outer"], "inner": st["inner_total"], "cycles": st["cycles_total"],
-                  "residual": st["residual"], "setup_ms": 1e3 * st["setup_seconds"],
-                  "cycle_ms": 1e3 * st["cycle_seconds"]},
-        "roofline": roof,
-        "streaming": {"peak": HBM_PEAK_GBS, "unit": "GB/s",
-                      "launches": "launches moving at least half the largest algorithmic bytes of the family "
-                                  f"(the first AMG levels of the {args.points}x{args.points} grid), HIP events",
-                      "levels": fine_levels, "kernels": streaming},
-        "cpu_baseline": cpu,
-        "extra": extra,
-    }
-    P.shapley_game_destroy(H)
-    print(json.dumps(out), flush=True)
-    return 0
-
-
-
-
-def _opts(P, prec, args, **kw):
-    return P.shapley_default_opts(eps=1e-8, precision=prec, max_outer=5000, max_inner=5000,
-                                  forcing=args.forcing, reuse_frac=args.reuse, **kw)
-
-
-def run_c0(args) -> int:
-    """Isaacs 2-D, 33x33 interior grid (n = 1089): plain PI latency over
-    at least 20 repeats, FP64 and mixed."""
-    import torch
-    import paper_1107_1653_amd as P
-    from shapley_inputs import configs
-    g = configs.c0()
-    h = P.create_from(g)
-    reps = max(args.steps, 20)
-    out = {}
-    for name, prec in (("fp64", P.SHAPLEY_FP64), ("mixed", P.SHAPLEY_MIXED)):
-        o = _opts(P, prec, args)
-        for _ in range(max(args.warmup, 1)):
-            P.shapley_solve(h, o)
-        torch.cuda.synchronize()
-        lat = []
-        for _ in range(reps):
-            t = time.perf_counter()
-            st = P.shapley_solve(h, o)
-            lat.append(time.perf_counter() - t)
-        lat = 1e3 * np.array(lat)
-        out[name] = {"value": g.n / (np.mean(lat) * 1e-3), "p50_ms": float(np.percentile(lat, 50)),
-                     "p99_ms": float(np.percentile(lat, 99)), "residual": st["residual"],
-                     "outer": st["outer"], "inner": st["inner_total"]}
-    P.shapley_game_destroy(h)
-    rec = base_record(args, out["fp64"]["value"], out["fp64"]["p50_ms"], "f64",
-                      {"workload": "Isaacs 2-D 33x33 interior (n=1089), AMGpi FP64 to 1e-8", "repeats": reps})
-    rec["latency_ms"] = {"p50": out["fp64"]["p50_ms"], "p99": out["fp64"]["p99_ms"]}
-    rec["extra"] = out
-    print(json.dumps(rec), flush=True)
-    return 0
-
-
-def run_c2(args) -> int:
-    """Isaacs 3-D on 129^3: FP64 V-cycles vs FP32 V-cycles under FP64
-    refinement, AMGpi to 1e-8; the mixed result's distance to the FP64 one."""
-    import torch
-    import paper_1107_1653_amd as P
-    from shapley_inputs import configs
     t0 = time.perf_counter()
-    g = configs.c2(s=args.side)
-    log(f"[bench] generated C2 n={g.n} in {time.perf_counter() - t0:.1f}s")
-    h = P.create_from(g)
-    out, vals = {}, {}
-    for name, prec in (("fp64", P.SHAPLEY_FP64), ("mixed", P.SHAPLEY_MIXED)):
-        o = _opts(P, prec, args)
-        for _ in range(args.warmup):
-            P.shapley_solve(h, o)
-        torch.cuda.synchronize()
-        ts = []
-        for _ in range(args.steps):
-            t = time.perf_counter()
-            st = P.shapley_solve(h, o)
-            ts.append(time.perf_counter() - t)
-        vals[name] = P.shapley_get_value(h)
-        out[name] = {"value": g.n / float(np.mean(ts)), "ms_per_step": 1e3 * float(np.mean(ts)),
-                     "residual": st["residual"], "outer": st["outer"], "inner": st["inner_total"],
-                     "cycles": st["cycles_total"], "levels": st["levels"], "op_complexity": st["op_complexity"],
-                     "setup_ms": 1e3 * st["setup_seconds"], "cycle_ms": 1e3 * st["cycle_seconds"]}
-        log(f"[bench] C2 {name}: {out[name]['ms_per_step']:.1f} ms, residual {st['residual']:.1e}")
-    out["mixed"]["max_abs_diff_vs_fp64"] = float(np.max(np.abs(vals["mixed"] - vals["fp64"])))
-    P.shapley_game_destroy(h)
-    rec = base_record(args, out["fp64"]["value"], out["fp64"]["ms_per_step"], "f64",
-                      {"workload": f"Isaacs 3-D {args.side}^3 interior (n={g.n}), AMGpi to 1e-8"})
-    rec["extra"] = out
-    print(json.dumps(rec), flush=True)
-    return 0
+    for k in range(steps):
+        t = time.perf_counter()
+        st = solve()
+        lat.append(time.perf_counter() - t)
+    sync()
+    wall = time.perf_counter() - t0
+    pr = None
+    if probe_family:
+        pr = P.shapley_probe_read_large(probe_family, 0.5)
+        P.shapley_probe_enable(probe_family, False)
+    return wall, np.array(lat), st, pr
 
 
-def run_c3(args) -> int:
-    """256 independent 2-D Isaacs games (sides 65/129/257): one lock-step
-    batched solve (one launch per kernel and level for all games) vs the same
-    games solved one after another, FP64 and mixed."""
-    import torch
+def traffic_for(workload, family):
+    """HBM bytes per launch (largest launches of the family) from the
+    committed counter summary of this workload, or None when it is missing or
+    the kernel sources changed since the counters were taken."""
+    from paper_1107_1653_amd import rocprof_summary
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except OSError:
+        return None, "no counter summary"
+    if d.get("source_sha256") != rocprof_summary.source_hash():
+        return None, "kernel sources changed since the counters were taken"
+    fam = d.get("families", {}).get(family)
+    if fam is None:
+        return None, "family not in the counter summary"
+    return fam["bytes_per_launch"], os.path.relpath(path, ROOT)
+
+
+def roofline(workload, fam, pr):
+    """The roofline object of a kernel family from its probed launches."""
+    n = max(pr["launches"], 1)
+    bpl = pr["bytes"] / n
+    avg_s = pr["ms"] * 1e-3 / n
+    achieved = bpl / avg_s / 1e9 if avg_s > 0 else 0.0
+    traffic, src = traffic_for(workload, fam)
+    return {"bound": BOUND.get(fam, "hbm"), "kernel": fam, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": src,
+            "launches": pr["launches"], "avg_launch_us": 1e6 * avg_s, "alg_bytes_per_launch": bpl,
+            "launch_set": "the family's launches moving at least half its largest algorithmic bytes "
+                          "(finest AMG level), HIP events on the launch stream over the timed steps"}
+
+
+def dominant(fams):
+    return max(fams, key=lambda k: fams[k]["total_ms"])
+
+
+def mu_max(g):
+    csum = np.concatenate([[0.0], np.cumsum(g.w)])
+    rows = csum[g.row_ptr[1:]] - csum[g.row_ptr[:-1]]
+    return g.mu * float(rows.max())
+
+
+def record(args, value, ms_per_step, dtype, config, steps=None):
+    return {"metric": METRIC, "value": value, "unit": "unknowns/s", "n_gpus": 1,
+            "steps": args.steps if steps is None else steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+            "config": config}
+
+
+def opts(P, args, prec, **kw):
+    # inexact policy iteration: each linear solve to 0.1 x the previous Shapley
+    # residual; AMG splitting reused while < 50% of the policies changed
+    return P.shapley_default_opts(eps=1e-8, precision=prec, max_outer=5000, max_inner=5000, forcing=args.forcing,
+                                  reuse_frac=args.reuse, **kw)
+
+
+def measure(P, args, workload, solve, steps=None):
+    """Family profile, then the timed steps with the dominant family probed;
+    returns (wall, latencies, stats, roofline, families)."""
+    fams = family_profile(P, solve)
+    fam = dominant(fams)
+    log(f"[bench] {workload}: per-family device ms of one solve: " +
+        ", ".join(f"{k}={v['total_ms']:.1f}" for k, v in sorted(fams.items(), key=lambda kv: -kv[1]['total_ms'])))
+    wall, lat, st, pr = timed(P, solve, args.steps if steps is None else steps, args.warmup, fam)
+    return wall, lat, st, roofline(workload, fam, pr), fams
+
+
+# ---------------------------------------------------------------------------
+# workloads
+# ---------------------------------------------------------------------------
+
+def c3_line(args):
+    """256 2-D Isaacs games, batched mixed (headline), batched FP64 and one
+    by one in FP64."""
     import paper_1107_1653_amd as P
     from shapley_inputs import configs
     t0 = time.perf_counter()
     side, lam = configs.c3_sizes(count=args.games)
     gs = [configs.c3_game(k, side[k], lam[k]) for k in range(args.games)]
     total = int(sum(g.n for g in gs))
-    log(f"[bench] generated {len(gs)} games, sum n = {total} in {time.perf_counter() - t0:.1f}s")
+    log(f"[bench] C3: generated {len(gs)} games, sum n = {total} in {time.perf_counter() - t0:.1f}s")
+    sync()
+    t = time.perf_counter()
     hs = [P.create_from(g) for g in gs]
-    out = {}
-    vals = {}
-    for name, prec in (("batched_fp64", P.SHAPLEY_FP64), ("batched_mixed", P.SHAPLEY_MIXED)):
-        o = _opts(P, prec, args)
-        for _ in range(args.warmup):
-            P.shapley_solve_batch(hs, o)
-        torch.cuda.synchronize()
-        ts = []
-        for _ in range(args.steps):
-            t = time.perf_counter()
-            st = P.shapley_solve_batch(hs, o)
-            ts.append(time.perf_counter() - t)
-        vals[name] = [P.shapley_get_value(h) for h in hs[:8]]
-        out[name] = {"value": total / float(np.mean(ts)), "ms_per_step": 1e3 * float(np.mean(ts)),
-                     "max_residual": max(s["residual"] for s in st),
-                     "max_outer": max(s["outer"] for s in st)}
-        log(f"[bench] C3 {name}: {out[name]['ms_per_step']:.1f} ms")
-    o = _opts(P, P.SHAPLEY_FP64, args)
+    sync()
+    create_s = time.perf_counter() - t
+    om, o64 = opts(P, args, P.SHAPLEY_MIXED), opts(P, args, P.SHAPLEY_FP64)
+    mixed = lambda: P.shapley_solve_batch(hs, om)
+    wall, lat, st, roof, fams = measure(P, args, "c3", mixed)
+    ms = 1e3 * wall / args.steps
+    value = total / (wall / args.steps)
+    log(f"[bench] C3 batched mixed: {ms:.1f} ms/batch, worst residual {max(s['residual'] for s in st):.1e}")
+    v_mixed = [P.shapley_get_value(h) for h in hs]
+    # the same steps without any probe
+    w2, _, _, _ = timed(P, mixed, args.steps, 0)
+    w64, lat64, st64, _ = timed(P, lambda: P.shapley_solve_batch(hs, o64), args.steps, args.warmup)
+    v64 = [P.shapley_get_value(h) for h in hs]
+    log(f"[bench] C3 batched fp64: {1e3 * w64 / args.steps:.1f} ms/batch")
+    # plain FP64 GPU policy iteration, one game after another
     for h in hs[:4]:
-        P.shapley_solve(h, o)
-    torch.cuda.synchronize()
+        P.shapley_solve(h, o64)
+    sync()
     t = time.perf_counter()
     for h in hs:
-        P.shapley_solve(h, o)
-    dt = time.perf_counter() - t
-    seq = [P.shapley_get_value(h) for h in hs[:8]]
-    out["sequential_fp64"] = {"value": total / dt, "ms_per_step": 1e3 * dt}
-    log(f"[bench] C3 sequential fp64: {1e3 * dt:.1f} ms")
-    out["batched_vs_alone_max_rel_diff"] = float(max(
-        np.max(np.abs(a - b)) / np.max(np.abs(b)) for a, b in zip(vals["batched_fp64"], seq)))
+        P.shapley_solve(h, o64)
+    sync()
+    seq = time.perf_counter() - t
+    v_seq = [P.shapley_get_value(h) for h in hs]
+    log(f"[bench] C3 one by one fp64: {1e3 * seq:.1f} ms")
+    t = time.perf_counter()
+    P.shapley_solve_batch(hs, om)
+    vals = [P.shapley_get_value(h) for h in hs]
+    e2e = time.perf_counter() - t + create_s
     for h in hs:
         P.shapley_game_destroy(h)
-    rec = base_record(args, out["batched_mixed"]["value"], out["batched_mixed"]["ms_per_step"], "f64",
-                      {"workload": f"{len(gs)} Isaacs 2-D games, sides 65/129/257 (sum n={total}), "
-                                   "batched AMGpi mixed to 1e-8", "games": len(gs)})
-    rec["extra"] = out
-    print(json.dumps(rec), flush=True)
-    return 0
+    line = record(args, value, ms, "f32+f64",
+                  {"workload": f"{len(gs)} Isaacs 2-D games, interior sides 65/129/257 (sum n={total}), "
+                               "batched AMGpi, FP32 V-cycles + FP64 refinement, to 1e-8",
+                   "games": len(gs), "sum_n": total, "eps": 1e-8, "forcing": args.forcing,
+                   "reuse_frac": args.reuse})
+    line["latency_ms"] = {"p50": float(np.percentile(1e3 * lat, 50)), "p99": float(np.percentile(1e3 * lat, 99))}
+    line["roofline"] = roof
+    line["families"] = fams
+    line["extra_c3"] = {
+        "unprobed_ms_per_step": 1e3 * w2 / args.steps,
+        "batched_fp64": {"value": total / (w64 / args.steps), "ms_per_step": 1e3 * w64 / args.steps,
+                         "max_residual": max(s["residual"] for s in st64)},
+        "one_by_one_fp64": {"value": total / seq, "ms": 1e3 * seq,
+                            "what": "plain FP64 GPU policy iteration, the 256 games solved one after another"},
+        "batched_mixed_vs_fp64_max_abs": float(max(np.max(np.abs(a - b)) for a, b in zip(v_mixed, v64))),
+        "batched_vs_one_by_one_max_rel": float(max(np.max(np.abs(a - b)) / np.max(np.abs(b))
+                                                   for a, b in zip(v64, v_seq))),
+        "end_to_end_s": e2e, "create_s": create_s,
+        "end_to_end_what": "create from host arrays + one batched mixed solve + values copied to the host",
+        "max_residual": max(s["residual"] for s in st),
+    }
+    return line, gs, v_mixed
 
 
-def run_c4(args) -> int:
-    """Serving: Poisson arrivals of Isaacs (AMGpi) and obstacle (FAMGpi on a
-    non-nested hierarchy) requests, sides log-uniform in [33, 1025], through
-    the continuous-batching server with a 200 GB budget.  First a closed loop
-    (everything queued at once) gives the saturation rate X_sat; then open
-    loops at 0.5 and 0.8 X_sat report p50/p99 latency and solves/s."""
-    import torch
+def c3_cpu_baseline(args, gs, v_gpu):
+    """The oracle (FP64 policy iteration, SuperLU per policy) on a bounded
+    sample of the batch -- every 8th game -- in worker processes over the
+    host's cores, to the same 1e-8 residual; also the error of the GPU's
+    batched mixed values against it."""
+    from oracle.jobs import Jobs
+    from shapley_inputs import configs
+    side, lam = configs.c3_sizes(count=args.games)
+    pick = list(range(0, args.games, 8))
+    jobs = Jobs([(f"g{k}", "c3", [k, int(side[k]), float(lam[k])], 1e-8) for k in pick],
+                cost=lambda j: float(j[2][1]) ** 3)
+    res = jobs.wait(timeout=900, log=log)
+    n = sum(gs[k].n for k in pick)
+    err = max(float(np.max(np.abs(v_gpu[k] - res[f"g{k}"]["v"])) / np.max(np.abs(res[f"g{k}"]["v"]))) for k in pick)
+    bound = max(1e-8 / (1.0 - mu_max(gs[k])) / np.max(np.abs(res[f"g{k}"]["v"])) for k in pick)
+    cpu = {"value": n / jobs.seconds, "unit": "unknowns/s", "cores": jobs.workers, "kind": "oracle",
+           "sample": f"{len(pick)} of the {args.games} games (every 8th, sum n={n}), oracle policy iteration with "
+                     f"SuperLU to 1e-8, {jobs.workers} worker processes, {jobs.seconds:.1f} s wall"}
+    return cpu, {"games_compared": len(pick), "max_rel_err_vs_oracle": err,
+                 "contraction_bound_rel": bound,
+                 "what": "GPU batched mixed values vs the oracle, both stopped at ||F(v) - v|| <= 1e-8"}
+
+
+def c2_line(args):
+    """3-D Isaacs on 129^3: FP64 and mixed AMGpi; error against the oracle's
+    stored fixed point at every state."""
+    import paper_1107_1653_amd as P
+    from shapley_inputs import configs
+    t0 = time.perf_counter()
+    g = configs.c2(s=args.side)
+    log(f"[bench] C2: generated n={g.n} in {time.perf_counter() - t0:.1f}s")
+    sync()
+    t = time.perf_counter()
+    h = P.create_from(g)
+    sync()
+    create_s = time.perf_counter() - t
+    out, vals = {}, {}
+    for name, prec in (("mixed", P.SHAPLEY_MIXED), ("fp64", P.SHAPLEY_FP64)):
+        o = opts(P, args, prec)
+        solve = lambda: P.shapley_solve(h, o)
+        if name == "mixed":
+            wall, lat, st, roof, fams = measure(P, args, "c2", solve)
+        else:
+            wall, lat, st, _ = timed(P, solve, args.steps, args.warmup)
+        vals[name] = P.shapley_get_value(h)
+        out[name] = {"value": g.n / (wall / args.steps), "ms_per_step": 1e3 * wall / args.steps,
+                     "residual": st["residual"], "outer": st["outer"], "inner": st["inner_total"],
+                     "cycles": st["cycles_total"], "levels": st["levels"], "op_complexity": st["op_complexity"]}
+        log(f"[bench] C2 {name}: {out[name]['ms_per_step']:.1f} ms, residual {st['residual']:.1e}")
+    P.shapley_game_destroy(h)
+    err = None
+    path = os.path.join(ROOT, "tests", "golden", "isaacs3d_129_full.npz")
+    if args.side == 129 and os.path.exists(path):
+        with np.load(path) as d:
+            planes = d["v_planes"]
+            b = np.zeros((g.n, 8), np.uint8)
+            for k in range(planes.shape[0]):
+                b[:, 7 - k] = planes[k]
+            ref = b.view(np.float64).reshape(-1)
+        err = {k: float(np.max(np.abs(v - ref)) / np.max(np.abs(ref))) for k, v in vals.items()}
+        err["contraction_bound_rel"] = 1e-8 / (1.0 - mu_max(g)) / float(np.max(np.abs(ref)))
+        err["what"] = "max over all states of |v - v*| / max |v*|, v* the oracle's stored fixed point"
+    line = record(args, out["mixed"]["value"], out["mixed"]["ms_per_step"], "f32+f64",
+                  {"workload": f"Isaacs 3-D {args.side}^3 interior (n={g.n}), AMGpi to 1e-8, FP32 V-cycles + FP64 "
+                               "refinement", "n": g.n})
+    line["roofline"] = roof
+    line["families"] = fams
+    line["fp64"] = out["fp64"]
+    line["mixed"] = out["mixed"]
+    line["mixed_vs_fp64_max_abs"] = float(np.max(np.abs(vals["mixed"] - vals["fp64"])))
+    line["error_vs_oracle"] = err
+    line["create_s"] = create_s
+    return line
+
+
+def c1_line(args, with_oracle=True):
+    """Obstacle problem on 1025 x 1025 points, FAMGpi FP64 (and mixed);
+    error against the oracle's FAMGpi fixed point at every state."""
+    import paper_1107_1653_amd as P
+    from shapley_inputs import configs
+    levels = configs.c1_levels(points=args.points, coarsest_points=33)
+    g = levels[-1]
+    jobs = None
+    if with_oracle:
+        from oracle.jobs import Jobs
+        jobs = Jobs([("c1", "c1", [args.points, 33], 0.0)])
+    sync()
+    t = time.perf_counter()
+    H = P.shapley_game_create_hierarchy([P.create_from(x) for x in levels])
+    sync()
+    create_s = time.perf_counter() - t
+    a0 = np.zeros(levels[0].n, np.int32)
+    out, vals = {}, {}
+    for name, prec in (("fp64", P.SHAPLEY_FP64), ("mixed", P.SHAPLEY_MIXED)):
+        o = opts(P, args, prec, method=P.SHAPLEY_FAMGPI, alpha0=a0, beta0=a0)
+        solve = lambda: P.shapley_solve(H, o)
+        if name == "fp64":
+            wall, lat, st, roof, fams = measure(P, args, "c1", solve)
+        else:
+            wall, lat, st, _ = timed(P, solve, args.steps, args.warmup)
+        vals[name] = P.shapley_get_value(H)
+        out[name] = {"value": g.n / (wall / args.steps), "ms_per_step": 1e3 * wall / args.steps,
+                     "p50_ms": float(np.percentile(1e3 * lat, 50)), "p99_ms": float(np.percentile(1e3 * lat, 99)),
+                     "residual": st["residual"], "outer": st["outer"], "cycles": st["cycles_total"]}
+        log(f"[bench] C1 {name}: {out[name]['ms_per_step']:.1f} ms, residual {st['residual']:.1e}")
+    P.shapley_game_destroy(H)
+    line = record(args, out["fp64"]["value"], out["fp64"]["ms_per_step"], "f64",
+                  {"workload": f"obstacle VI {args.points}x{args.points} points (n={g.n}), FAMGpi to 1e-8",
+                   "grids": [x.meta["points"] for x in levels]})
+    line["roofline"] = roof
+    line["families"] = fams
+    line["fp64"] = out["fp64"]
+    line["mixed"] = out["mixed"]
+    line["create_s"] = create_s
+    if jobs is not None:
+        ref = jobs.wait(timeout=600, log=log)["c1"]["v"]
+        line["error_vs_oracle"] = {
+            k: float(np.max(np.abs(v - ref)) / np.max(np.abs(ref))) for k, v in vals.items()}
+        line["error_vs_oracle"]["contraction_bound_rel"] = 1e-8 / (1.0 - mu_max(g)) / float(np.max(np.abs(ref)))
+        line["error_vs_oracle"]["what"] = "max over all states, oracle FAMGpi fixed point"
+    return line
+
+
+def c0_line(args):
+    """Isaacs 2-D, 33x33 interior grid (n = 1089): plain PI latency over at
+    least 20 repeats, FP64 and mixed."""
+    import paper_1107_1653_amd as P
+    import oracle
+    from shapley_inputs import configs
+    g = configs.c0()
+    h = P.create_from(g)
+    reps = max(args.steps, 20)
+    out = {}
+    for name, prec in (("fp64", P.SHAPLEY_FP64), ("mixed", P.SHAPLEY_MIXED)):
+        o = opts(P, args, prec)
+        wall, lat, st, _ = timed(P, lambda: P.shapley_solve(h, o), reps, max(args.warmup, 1))
+        lat = 1e3 * lat
+        out[name] = {"value": g.n / (np.mean(lat) * 1e-3), "p50_ms": float(np.percentile(lat, 50)),
+                     "p99_ms": float(np.percentile(lat, 99)), "residual": st["residual"], "outer": st["outer"]}
+    v = P.shapley_get_value(h)
+    P.shapley_game_destroy(h)
+    ref = oracle.policy_iteration(g, eps=1e-8)
+    line = record(args, out["fp64"]["value"], out["fp64"]["p50_ms"], "f64",
+                  {"workload": "Isaacs 2-D 33x33 interior (n=1089), AMGpi FP64 to 1e-8", "repeats": reps}, reps)
+    line["latency_ms"] = {"p50": out["fp64"]["p50_ms"], "p99": out["fp64"]["p99_ms"]}
+    line["extra"] = out
+    line["error_vs_oracle"] = float(np.max(np.abs(v - ref.v)) / np.max(np.abs(ref.v)))
+    return line
+
+
+def c4_line(args):
+    """Serving: Poisson arrivals of Isaacs (AMGpi) and obstacle (FAMGpi)
+    requests, sides log-uniform in [33, 1025], through the request loop with a
+    200 GB budget.  A closed loop (everything queued at once) gives the
+    saturation rate X_sat; open loops at 0.5 and 0.8 X_sat give p50/p99
+    latency; the same requests solved one after another by plain FP64 GPU
+    policy iteration are the reference."""
     import paper_1107_1653_amd as P
     from shapley_inputs import configs
     reqs = configs.c4_requests(count=args.requests)
@@ -442,48 +438,45 @@ def run_c4(args) -> int:
     handles, sizes = [], []
     for kind, side, lam, seed in reqs:
         if kind == 0:
-            h = P.create_from(configs.c4_game(kind, side, lam, seed))
-            handles.append((h, False, None))
+            handles.append((P.create_from(configs.c4_game(kind, side, lam, seed)), False, None))
         else:
             lv = configs.obstacle_levels_for_side(side, seed, lam)
-            H = P.shapley_game_create_hierarchy([P.create_from(g) for g in lv])
-            handles.append((H, True, lv[0].n))
+            handles.append((P.shapley_game_create_hierarchy([P.create_from(g) for g in lv]), True, lv[0].n))
         sizes.append(side * side)
     total = int(sum(sizes))
-    log(f"[bench] created {len(handles)} requests (sum n = {total}) in {time.perf_counter() - t0:.1f}s")
+    log(f"[bench] C4: created {len(handles)} requests (sum n = {total}) in {time.perf_counter() - t0:.1f}s")
 
-    def opts_for(is_h, n0):
+    def opts_for(is_h, n0, prec):
         if is_h:
             a0 = np.zeros(n0, np.int32)
-            return _opts(P, P.SHAPLEY_MIXED, args, method=P.SHAPLEY_FAMGPI, alpha0=a0, beta0=a0)
-        return _opts(P, P.SHAPLEY_MIXED, args)
+            return opts(P, args, prec, method=P.SHAPLEY_FAMGPI, alpha0=a0, beta0=a0)
+        return opts(P, args, prec)
 
-    opts = [opts_for(is_h, n0) for (_, is_h, n0) in handles]
+    om = [opts_for(is_h, n0, P.SHAPLEY_MIXED) for (_, is_h, n0) in handles]
 
     def run(rate):
         srv = P.shapley_server_create(200 * 10 ** 9)
         rng = np.random.default_rng(7)
         arrivals = (np.zeros(len(handles)) if rate is None
                     else np.cumsum(rng.exponential(1.0 / rate, size=len(handles))))
-        torch.cuda.synchronize()
+        sync()
         start = time.perf_counter()
         tickets = [None] * len(handles)
-        sub_t = [0.0] * len(handles)
-        nxt = 0
-        done = 0
+        nxt = done = 0
         lat = [None] * len(handles)
+        max_cohorts = 0
         while done < len(handles):
             now = time.perf_counter() - start
             while nxt < len(handles) and arrivals[nxt] <= now:
-                tickets[nxt] = P.shapley_server_submit(srv, handles[nxt][0], opts[nxt])
-                sub_t[nxt] = arrivals[nxt]
+                tickets[nxt] = P.shapley_server_submit(srv, handles[nxt][0], om[nxt])
                 nxt += 1
             active = P.shapley_server_step(srv)
+            max_cohorts = max(max_cohorts, P.shapley_server_info(srv)["cohorts"])
             for i in range(nxt):
                 if lat[i] is None:
                     st = P.shapley_server_poll(srv, tickets[i])
                     if st is not None:
-                        lat[i] = (time.perf_counter() - start) - sub_t[i]
+                        lat[i] = (time.perf_counter() - start) - arrivals[i]
                         done += 1
             if active == 0 and nxt < len(handles):
                 time.sleep(max(0.0, min(0.01, arrivals[nxt] - (time.perf_counter() - start))))
@@ -491,9 +484,10 @@ def run_c4(args) -> int:
         P.shapley_server_destroy(srv)
         lat = 1e3 * np.array(lat)
         return {"solves_per_s": len(handles) / wall, "unknowns_per_s": total / wall, "wall_s": wall,
-                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))}
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "max_cohorts": max_cohorts}
 
-    run(None)  # warm-up pass (allocations)
+    run(None)  # warm-up pass (engines and their workspaces)
     closed = run(None)
     log(f"[bench] C4 closed loop: {closed}")
     xs = closed["solves_per_s"]
@@ -501,15 +495,113 @@ def run_c4(args) -> int:
     log(f"[bench] C4 open loop 0.5 X_sat: {o5}")
     o8 = run(0.8 * xs)
     log(f"[bench] C4 open loop 0.8 X_sat: {o8}")
+    # plain FP64 GPU policy iteration, one request after another
+    sync()
+    t = time.perf_counter()
+    for (h, is_h, n0) in handles:
+        P.shapley_solve(h, opts_for(is_h, n0, P.SHAPLEY_FP64))
+    sync()
+    seq = time.perf_counter() - t
+    log(f"[bench] C4 one by one fp64: {seq:.2f} s")
     for h, _, _ in handles:
         P.shapley_game_destroy(h)
-    rec = base_record(args, closed["unknowns_per_s"], 1e3 * closed["wall_s"], "f64",
-                      {"workload": f"{len(handles)} serving requests (50/50 Isaacs/obstacle, sides log-uniform "
-                                   f"33..1025, sum n={total}), mixed precision, 200 GB budget",
-                       "requests": len(handles)})
-    rec["latency_ms"] = {"p50": o8["p50_ms"], "p99": o8["p99_ms"], "load": "0.8 X_sat"}
-    rec["extra"] = {"closed_loop": closed, "open_0.5": o5, "open_0.8": o8}
-    print(json.dumps(rec), flush=True)
+    line = record(args, closed["unknowns_per_s"], 1e3 * closed["wall_s"], "f32+f64",
+                  {"workload": f"{len(handles)} serving requests (50/50 Isaacs/obstacle, sides log-uniform "
+                               f"33..1025, sum n={total}), mixed precision, 200 GB budget",
+                   "requests": len(handles)}, 1)
+    line["latency_ms"] = {"p50": o8["p50_ms"], "p99": o8["p99_ms"], "load": "0.8 X_sat"}
+    line["extra"] = {"closed_loop": closed, "open_0.5": o5, "open_0.8": o8,
+                     "one_by_one_fp64": {"unknowns_per_s": total / seq, "wall_s": seq,
+                                         "what": "plain FP64 GPU policy iteration, requests one after another"}}
+    return line
+
+
+def two_stopper_line(args):
+    """The paper's 1-D two-stopper game (Sec. 6.3) on 2049 points: AMGpi from
+    'stop everywhere' vs FAMGpi on the grids 33 ... 2049, to 1e-10 as in the
+    paper's tables; error against the closed form."""
+    import paper_1107_1653_amd as P
+    from shapley_inputs import games
+    pts = [33, 65, 129, 257, 513, 1025, 2049]
+    levels = [games.two_stopper_game(p) for p in pts]
+    g = levels[-1]
+    x = np.arange(1, pts[-1] - 1) / (pts[-1] - 1)
+    u = games.two_stopper_exact(x)
+    out = {}
+    h = P.create_from(g)
+    a0 = np.zeros(g.n, np.int32)
+    oa = P.shapley_default_opts(eps=1e-10, alpha0=a0, beta0=a0, max_outer=5000, max_inner=5000)
+    wall, lat, st, _ = timed(P, lambda: P.shapley_solve(h, oa), max(1, args.steps // 2), 0)
+    out["amgpi"] = {"seconds": wall / max(1, args.steps // 2), "outer": st["outer"], "residual": st["residual"],
+                    "err_inf": float(np.max(np.abs(P.shapley_get_value(h) - u)))}
+    P.shapley_game_destroy(h)
+    H = P.shapley_game_create_hierarchy([P.create_from(x_) for x_ in levels])
+    c0 = np.zeros(levels[0].n, np.int32)
+    of = P.shapley_default_opts(eps=1e-10, method=P.SHAPLEY_FAMGPI, alpha0=c0, beta0=c0, max_outer=5000,
+                                max_inner=5000)
+    wall, lat, st, _ = timed(P, lambda: P.shapley_solve(H, of), args.steps, args.warmup)
+    out["famgpi"] = {"seconds": wall / args.steps, "outer": st["outer"], "residual": st["residual"],
+                     "err_inf": float(np.max(np.abs(P.shapley_get_value(H) - u)))}
+    P.shapley_game_destroy(H)
+    log(f"[bench] two-stopper: {out}")
+    line = record(args, g.n / out["famgpi"]["seconds"], 1e3 * out["famgpi"]["seconds"], "f64",
+                  {"workload": "1-D two-stopper game, 2049 points (n=2047), FAMGpi on 33..2049 points to 1e-10",
+                   "n": g.n})
+    line["extra"] = out
+    line["extra"]["famgpi_speedup_over_amgpi"] = out["amgpi"]["seconds"] / out["famgpi"]["seconds"]
+    line["extra"]["paper"] = {"amgpi_outer": 841, "amgpi_s": 1740.0, "famgpi_s": 0.95, "err_inf": 1.16e-7,
+                              "hardware": "serial C on an unstated CPU (context only)"}
+    return line
+
+
+def general_line(args):
+    """Random sparse games without a grid (n = 2^18 states, 3 x 3 actions,
+    8 transitions per row): AMGpi, FP64 and mixed."""
+    import paper_1107_1653_amd as P
+    from shapley_inputs import games
+    g = games.random_sparse_game(1 << 18, 3, 3, seed=11, nnz_row=8)
+    h = P.create_from(g)
+    out = {}
+    for name, prec in (("mixed", P.SHAPLEY_MIXED), ("fp64", P.SHAPLEY_FP64)):
+        o = opts(P, args, prec)
+        wall, lat, st, _ = timed(P, lambda: P.shapley_solve(h, o), args.steps, args.warmup)
+        out[name] = {"value": g.n / (wall / args.steps), "ms_per_step": 1e3 * wall / args.steps,
+                     "outer": st["outer"], "cycles": st["cycles_total"], "levels": st["levels"],
+                     "op_complexity": st["op_complexity"], "residual": st["residual"]}
+    P.shapley_game_destroy(h)
+    line = record(args, out["mixed"]["value"], out["mixed"]["ms_per_step"], "f32+f64",
+                  {"workload": f"random sparse game n={g.n}, 3x3 actions, 8 transitions per row, AMGpi to 1e-8"})
+    line["extra"] = out
+    return line
+
+
+def main() -> int:
+    args = parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 (sharding across GPUs is not "
+                                   "implemented)"}))
+        return 2
+    import torch  # noqa: F401  (device synchronisation around the timed regions)
+    if args.calibrate_copy:
+        calibration_kernel()
+    if args.workload != "c3":
+        fn = {"c0": c0_line, "c1": c1_line, "c2": c2_line, "c4": c4_line, "two_stopper": two_stopper_line,
+              "general": general_line}[args.workload]
+        line = fn(args)
+        print(json.dumps(line), flush=True)
+        return 0
+    line, gs, v_mixed = c3_line(args)
+    extra = {}
+    if not args.no_extra:
+        extra["c2_isaacs3d_129"] = c2_line(args)
+        extra["c1_obstacle_1025"] = c1_line(args, with_oracle=not args.no_cpu_baseline)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"], line["error_vs_oracle"] = c3_cpu_baseline(args, gs, v_mixed)
+        log(f"[bench] cpu baseline: {line['cpu_baseline']}")
+    else:
+        line["cpu_baseline"] = None
+    line["extra"] = extra
+    print(json.dumps(line), flush=True)
     return 0
 
 

@@ -1,12 +1,16 @@
-"""Oracle fixed points of benchmark games, computed in worker processes beside
-a GPU test (test infrastructure: only the tests run it).
+"""Oracle solves of benchmark games in worker processes -- TEST
+INFRASTRUCTURE, like the rest of this package: only the tests, the smoke
+check and the benchmark's CPU-baseline leg run it.
 
-A job is (name, recipe, args): the worker rebuilds the game from its seeded
-recipe, runs the FP64 oracle to its fixed point (eps = 0) and writes the value,
-both strategies and the tie flags to <out>/<name>.npz.  Workers are separate
-Python processes started with subprocess (no GPU, one BLAS thread each).
+A job is (name, recipe, args, eps): the worker rebuilds the game from its
+seeded recipe, runs the FP64 oracle (policy iteration, or FAMGpi for the
+obstacle grids) to the Shapley residual eps (0: the fixed point, no policy
+improves) and writes the value, both strategies and the tie flags to
+<out>/<name>.npz.  Workers are separate Python processes started with
+subprocess (no GPU, one BLAS thread each), so a GPU process can run them
+beside its own work.
 
-    python tests/oracle_jobs.py <jobs.json> <out_dir>     # one worker
+    python -m oracle.jobs <jobs.json> <out_dir>     # one worker
 """
 import json
 import os
@@ -21,44 +25,45 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 
 
-def _build(recipe, args):
-    """Returns (game whose fixed point is compared, oracle result)."""
-    import oracle
+def _build(recipe, args, eps):
+    """Returns (game whose solution is compared, oracle result)."""
+    from . import shapley_oracle as orc
     from shapley_inputs import configs
     if recipe == "c3":                       # (k, side, lam)
         g = configs.c3_game(*args)
-        return g, oracle.policy_iteration(g)
+        return g, orc.policy_iteration(g, eps=eps)
     if recipe == "c4_isaacs":                # (side, lam, seed)
         side, lam, seed = args
         g = configs.c4_game(0, side, lam, seed)
-        return g, oracle.policy_iteration(g)
+        return g, orc.policy_iteration(g, eps=eps)
     if recipe == "c4_obstacle":              # (side, seed, lam): FAMGpi on its grids
         side, seed, lam = args
         lv = configs.obstacle_levels_for_side(side, seed, lam)
         a0 = np.zeros(lv[0].n, np.int32)
-        return lv[-1], oracle.famg_pi(lv, eps=0.0, c=1e-2, alpha0=a0, beta0=a0)[-1]
+        return lv[-1], orc.famg_pi(lv, eps=eps, c=1e-2, alpha0=a0, beta0=a0)[-1]
     if recipe == "c1":                       # (points, coarsest_points)
         lv = configs.c1_levels(points=args[0], coarsest_points=args[1])
         a0 = np.zeros(lv[0].n, np.int32)
-        return lv[-1], oracle.famg_pi(lv, eps=0.0, c=1e-2, alpha0=a0, beta0=a0)[-1]
+        return lv[-1], orc.famg_pi(lv, eps=eps, c=1e-2, alpha0=a0, beta0=a0)[-1]
     raise ValueError(recipe)
 
 
 def _work(jobs_path, out_dir):
-    import oracle
+    from . import shapley_oracle as orc
     with open(jobs_path) as f:
         jobs = json.load(f)
-    for name, recipe, args in jobs:
+    for name, recipe, args, eps in jobs:
         t = time.perf_counter()
-        g, res = _build(recipe, args)
-        tied = oracle.tied_states(g, res.v, res.alpha)
+        g, res = _build(recipe, args, eps)
+        tied = orc.tied_states(g, res.v, res.alpha)
         np.savez(os.path.join(out_dir, name + ".tmp.npz"), v=res.v, alpha=res.alpha, beta=res.beta, tied=tied,
                  seconds=time.perf_counter() - t, converged=res.converged)
         os.replace(os.path.join(out_dir, name + ".tmp.npz"), os.path.join(out_dir, name + ".npz"))
 
 
 class Jobs:
-    """Oracle jobs running in up to `workers` processes (longest first)."""
+    """Oracle jobs (name, recipe, args, eps) running in up to `workers`
+    processes, longest first (cost: estimated seconds of a job)."""
 
     def __init__(self, jobs, cost=None, workers=None):
         self.dir = tempfile.mkdtemp(prefix="oracle_jobs_")
@@ -76,6 +81,7 @@ class Jobs:
         env["HIP_VISIBLE_DEVICES"] = ""
         env["PYTHONPATH"] = ROOT + os.pathsep + env.get("PYTHONPATH", "")
         self.names = [j[0] for j in jobs]
+        self.workers = sum(1 for ch in chunks if ch)
         self.procs = []
         for i, ch in enumerate(chunks):
             if not ch:
@@ -83,8 +89,10 @@ class Jobs:
             path = os.path.join(self.dir, f"jobs{i}.json")
             with open(path, "w") as f:
                 json.dump(ch, f)
-            self.procs.append(subprocess.Popen([sys.executable, os.path.abspath(__file__), path, self.dir], env=env,
-                                               stdout=subprocess.DEVNULL, stderr=subprocess.PIPE))
+            self.procs.append(subprocess.Popen([sys.executable, "-m", "oracle.jobs", path, self.dir], env=env,
+                                               cwd=ROOT, stdout=subprocess.DEVNULL, stderr=subprocess.PIPE))
+        self.t_start = time.perf_counter()
+        self.t_end = None
 
     def wait(self, timeout=600.0, log=None):
         """Dict name -> dict(v, alpha, beta, tied, seconds); raises if a worker failed."""
@@ -100,6 +108,8 @@ class Jobs:
                     p.kill()
                 raise TimeoutError("oracle jobs did not finish")
             time.sleep(0.5)
+        if self.t_end is None:
+            self.t_end = time.perf_counter()
         for p in self.procs:
             if p.returncode != 0:
                 raise RuntimeError("oracle worker failed: " + p.stderr.read().decode()[-2000:])
@@ -110,6 +120,11 @@ class Jobs:
         return out
 
 
+    @property
+    def seconds(self):
+        """Wall time from the start of the workers to the end of the last one."""
+        return (self.t_end or time.perf_counter()) - self.t_start
+
+
 if __name__ == "__main__":
-    sys.path.insert(0, ROOT)
     _work(sys.argv[1], sys.argv[2])

@@ -9,7 +9,9 @@
         HBM bytes per launch of each probe family from two --pmc runs
         (FETCH_SIZE, then WRITE_SIZE, output format csv) of a benchmark run
         made with --calibrate-copy: both counters are scaled by what they
-        read for the calibration kernel, which reads and writes a known size
+        read for the calibration kernel, which reads and writes a known size;
+        per family over all launches and over its launches at the largest
+        grid (bytes_per_launch: the finest level, the roofline's launch set)
 
 Probe families are the kernel groups the library can time with HIP events
 (shapley_probe_enable): smooth, resid64, improve, resid, restrict, prolong,
@@ -158,42 +160,61 @@ def trace_summary(db_path: str, top: int = 25, largest=()) -> str:
 
 
 def _load_counter(path: str, counter: str):
+    """(kernel name, grid size or 0, value in KiB) of every dispatch."""
     out = []
     with open(path) as f:
         for r in csv.DictReader(f):
             if r["Counter_Name"] == counter:
-                out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+                grid = int(float(r.get("Grid_Size") or 0))
+                out.append((r["Kernel_Name"], grid, float(r["Counter_Value"])))
     return out
 
 
+def _per_family(rows, factor, largest):
+    """Per family: launches and bytes.  largest: only the dispatches of each
+    kernel at its largest grid (a streaming kernel's finest level)."""
+    top = collections.defaultdict(int)
+    for k, g, _ in rows:
+        top[short_name(k)] = max(top[short_name(k)], g)
+    fam = collections.defaultdict(lambda: [0, 0.0])
+    for k, g, v in rows:
+        f = family_of(k)
+        if not f or (largest and g != top[short_name(k)]):
+            continue
+        fam[f][0] += 1 if starts_launch(k) else 0
+        fam[f][1] += factor * v * 1024.0
+    return fam
+
+
 def traffic(fetch_csv: str, write_csv: str) -> dict:
+    """HBM bytes per launch of each family, over all its launches and over
+    its launches at the largest grid (the launch set the benchmark's roofline
+    uses), both counters scaled by what they read for the calibration
+    kernel."""
     fetch = _load_counter(fetch_csv, "FETCH_SIZE")
     write = _load_counter(write_csv, "WRITE_SIZE")
-    cal_f = [v for k, v in fetch if "neg_kernel" in k]
-    cal_w = [v for k, v in write if "neg_kernel" in k]
+    cal_f = [v for k, _, v in fetch if "neg_kernel" in k]
+    cal_w = [v for k, _, v in write if "neg_kernel" in k]
     if not cal_f or not cal_w:
         raise RuntimeError("no calibration kernel in the counter runs (use --calibrate-copy)")
     ff = CALIB_BYTES / (cal_f[0] * 1024.0)  # counters are in KiB
     fw = CALIB_BYTES / (cal_w[0] * 1024.0)
-    fam = collections.defaultdict(lambda: {"launches": 0, "fetch_kib": 0.0, "write_kib": 0.0})
-    for k, v in fetch:
-        f = family_of(k)
-        if f:
-            fam[f]["launches"] += 1 if starts_launch(k) else 0
-            fam[f]["fetch_kib"] += v
-    for k, v in write:
-        f = family_of(k)
-        if f:
-            fam[f]["write_kib"] += v
     out = {"calibration": {"bytes": CALIB_BYTES, "fetch_kib": cal_f[0], "write_kib": cal_w[0],
                            "fetch_factor": ff, "write_factor": fw},
            "families": {}}
-    for f, d in fam.items():
-        n = max(d["launches"], 1)
-        fb = ff * d["fetch_kib"] * 1024.0 / n
-        wb = fw * d["write_kib"] * 1024.0 / n
-        out["families"][f] = {"launches": d["launches"], "fetch_bytes_per_launch": fb,
-                              "write_bytes_per_launch": wb, "bytes_per_launch": fb + wb}
+    for largest in (False, True):
+        fa = _per_family(fetch, ff, largest)
+        wa = _per_family(write, fw, largest)
+        for f in fa:
+            n = max(fa[f][0], 1)
+            fb, wb = fa[f][1] / n, wa[f][1] / n if f in wa else 0.0
+            d = out["families"].setdefault(f, {})
+            if largest:
+                d.update({"largest_launches": fa[f][0], "fetch_bytes_per_launch": fb,
+                          "write_bytes_per_launch": wb, "bytes_per_launch": fb + wb})
+            else:
+                d.update({"launches": fa[f][0], "all_fetch_bytes_per_launch": fb,
+                          "all_write_bytes_per_launch": wb, "all_bytes_per_launch": fb + wb})
     return out
 
 

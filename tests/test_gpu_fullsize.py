@@ -29,7 +29,7 @@ import pytest
 import paper_1107_1653_amd as P
 from shapley_inputs import configs
 from tests.gpu_helpers import compare_with_oracle, log
-from tests.oracle_jobs import Jobs
+from oracle.jobs import Jobs
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -71,7 +71,7 @@ def mu_max(g):
 
 
 def test_obstacle_1025_famg_full_size():
-    jobs = Jobs([("c1", "c1", [1025, 33])])
+    jobs = Jobs([("c1", "c1", [1025, 33], 0.0)])
     levels = configs.c1_levels(points=1025, coarsest_points=33)
     g = levels[-1]
     hs = [P.create_from(x) for x in levels]
@@ -143,7 +143,7 @@ def _c3_cost(job):
 
 def test_batch_256_games_full_size():
     side, lam = configs.c3_sizes(count=256)
-    jobs = Jobs([(f"g{k}", "c3", [k, int(side[k]), float(lam[k])]) for k in range(256)], cost=_c3_cost)
+    jobs = Jobs([(f"g{k}", "c3", [k, int(side[k]), float(lam[k])], 0.0) for k in range(256)], cost=_c3_cost)
     gs = [configs.c3_game(k, side[k], lam[k]) for k in range(256)]
     hs = [P.create_from(g) for g in gs]
     try:
@@ -177,8 +177,8 @@ def test_serving_stream_full_size():
     reqs = configs.c4_requests(count=1000)[:16]
     specs = []
     for i, (kind, side, lam, seed) in enumerate(reqs):
-        specs.append((f"r{i}", "c4_isaacs", [int(side), float(lam), int(seed)]) if kind == 0 else
-                     (f"r{i}", "c4_obstacle", [int(side), int(seed), float(lam)]))
+        specs.append((f"r{i}", "c4_isaacs", [int(side), float(lam), int(seed)], 0.0) if kind == 0 else
+                     (f"r{i}", "c4_obstacle", [int(side), int(seed), float(lam)], 0.0))
     jobs = Jobs(specs, cost=lambda j: (j[2][0] ** 2) * (9 if j[1] == "c4_isaacs" else 2))
     handles = []
     for kind, side, lam, seed in reqs:

@@ -17,10 +17,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def write_counters(path, counter, rows):
     with open(path, "w", newline="") as f:
-        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"])
         w.writeheader()
-        for name, value in rows:
-            w.writerow({"Kernel_Name": name, "Counter_Name": counter, "Counter_Value": value})
+        for row in rows:
+            name, value = row[0], row[-1]
+            grid = row[1] if len(row) == 3 else 256
+            w.writerow({"Kernel_Name": name, "Grid_Size": grid, "Counter_Name": counter, "Counter_Value": value})
 
 
 def test_traffic_is_scaled_by_the_calibration_kernel(tmp_path):
@@ -53,15 +55,41 @@ def test_traffic_is_scaled_by_the_calibration_kernel(tmp_path):
     assert d["calibration"]["write_factor"] == pytest.approx(1.0)
     sm = d["families"]["smooth"]
     assert sm["launches"] == 2
-    assert sm["fetch_bytes_per_launch"] == pytest.approx(2.0 * 4000.0 * 1024 / 2)
-    assert sm["write_bytes_per_launch"] == pytest.approx(40.0 * 1024 / 2)
+    assert sm["all_fetch_bytes_per_launch"] == pytest.approx(2.0 * 4000.0 * 1024 / 2)
+    assert sm["all_write_bytes_per_launch"] == pytest.approx(40.0 * 1024 / 2)
     rap = d["families"]["rap"]
     # two launches (the row-wise and the dense product); the list kernel and
     # the dense product's later kernels continue a launch
     assert rap["launches"] == 2
-    assert rap["fetch_bytes_per_launch"] == pytest.approx(2.0 * 664.0 * 1024 / 2)
-    assert rap["bytes_per_launch"] == pytest.approx(rap["fetch_bytes_per_launch"] + 66.0 * 1024 / 2)
+    assert rap["all_fetch_bytes_per_launch"] == pytest.approx(2.0 * 664.0 * 1024 / 2)
+    assert rap["all_bytes_per_launch"] == pytest.approx(rap["all_fetch_bytes_per_launch"] + 66.0 * 1024 / 2)
     assert "scan" not in d["families"]
+
+
+def test_traffic_of_the_largest_launches(tmp_path):
+    """bytes_per_launch covers each kernel's launches at its largest grid
+    (the finest level), the launch set of the benchmark's roofline."""
+    cal = rs.CALIB_BYTES
+    fetch = [("void at::native::neg_kernel(...)", 1, cal / 2 / 1024),
+             ("shp::k_smooth<float, 4>(...)", 4 << 20, 3000.0),
+             ("shp::k_smooth<float, 4>(...)", 4 << 20, 5000.0),
+             ("shp::k_smooth<float, 4>(...)", 1 << 20, 100.0),
+             ("shp::k_smooth<float, 1>(...)", 1 << 16, 10.0)]
+    write = [("void at::native::neg_kernel(...)", 1, cal / 1024),
+             ("shp::k_smooth<float, 4>(...)", 4 << 20, 30.0),
+             ("shp::k_smooth<float, 4>(...)", 4 << 20, 50.0),
+             ("shp::k_smooth<float, 4>(...)", 1 << 20, 1.0),
+             ("shp::k_smooth<float, 1>(...)", 1 << 16, 1.0)]
+    fcsv, wcsv = tmp_path / "f.csv", tmp_path / "w.csv"
+    write_counters(fcsv, "FETCH_SIZE", fetch)
+    write_counters(wcsv, "WRITE_SIZE", write)
+    sm = rs.traffic(str(fcsv), str(wcsv))["families"]["smooth"]
+    assert sm["launches"] == 4
+    # largest grid of each kernel: the two big k_smooth<float, 4> dispatches and
+    # the one k_smooth<float, 1> dispatch
+    assert sm["largest_launches"] == 3
+    assert sm["fetch_bytes_per_launch"] == pytest.approx(2.0 * 8010.0 * 1024 / 3)
+    assert sm["write_bytes_per_launch"] == pytest.approx(81.0 * 1024 / 3)
 
 
 def test_traffic_needs_the_calibration_kernel(tmp_path):
@@ -110,16 +138,29 @@ def test_trace_summary_counts_launches_per_family(tmp_path):
 def test_bench_reports_no_traffic_for_changed_sources(tmp_path, monkeypatch):
     sys.path.insert(0, ROOT)
     import bench
-    f = tmp_path / "traffic.json"
+    (tmp_path / "profiles").mkdir()
+    f = tmp_path / "profiles" / "traffic_c3.json"
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     f.write_text(json.dumps({"source_sha256": "0" * 64, "families": {"rap": {"bytes_per_launch": 1.0}}}))
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
-    value, why = bench.measured_traffic("rap")
+    value, why = bench.traffic_for("c3", "rap")
     assert value is None and "changed" in why
     f.write_text(json.dumps({"source_sha256": rs.source_hash(), "families": {"rap": {"bytes_per_launch": 5.0}}}))
-    value, why = bench.measured_traffic("rap")
+    value, why = bench.traffic_for("c3", "rap")
     assert value == 5.0
-    value, why = bench.measured_traffic("tail")
+    value, why = bench.traffic_for("c3", "tail")
     assert value is None
+    value, why = bench.traffic_for("c2", "rap")
+    assert value is None and "no counter" in why
+
+
+def test_bench_roofline_object():
+    sys.path.insert(0, ROOT)
+    import bench
+    r = bench.roofline("c9", "smooth", {"launches": 4, "ms": 0.2, "bytes": 4e9})
+    # 1e9 bytes per launch in 50 us: 20000 GB/s
+    assert r["achieved"] == pytest.approx(2e4) and r["frac"] == pytest.approx(2.5)
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
+    assert bench.roofline("c9", "rap", {"launches": 1, "ms": 1.0, "bytes": 1.0})["bound"] == "latency"
 
 
 def test_bench_refuses_more_than_one_gpu():
