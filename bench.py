@@ -54,6 +54,8 @@ def parse_args():
                     choices=["c0", "c1", "c2", "c3", "c4", "two_stopper", "general"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="the headline's timed steps only (for kernel traces): no FP64 or one-by-one runs")
     ap.add_argument("--forcing", type=float, default=0.1)
     ap.add_argument("--reuse", type=float, default=0.5)
     ap.add_argument("--games", type=int, default=256, help="C3 batch size")
@@ -228,6 +230,11 @@ def c3_line(args):
     value = total / (wall / args.steps)
     log(f"[bench] C3 batched mixed: {ms:.1f} ms/batch, worst residual {max(s['residual'] for s in st):.1e}")
     v_mixed = [P.shapley_get_value(h) for h in hs]
+    if args.headline_only:
+        line = record(args, value, ms, "f32+f64", {"workload": "headline steps only", "sum_n": total})
+        line["roofline"] = roof
+        line["families"] = fams
+        return line, gs, v_mixed
     # the same steps without any probe
     w2, _, _, _ = timed(P, mixed, args.steps, 0)
     w64, lat64, st64, _ = timed(P, lambda: P.shapley_solve_batch(hs, o64), args.steps, args.warmup)

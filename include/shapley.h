@@ -111,6 +111,10 @@ typedef struct shapley_solve_opts {
   int32_t gamma;         /* cycle index of Algorithm MGcycle: 1 = V-cycle
                             (default), 2 = W-cycle (the coarse problem is
                             visited twice per level) */
+  int32_t graph;         /* 1 (default): the launches of one refinement cycle
+                            are captured once per AMG hierarchy into a HIP
+                            graph and replayed; 0: launched one by one.  The
+                            results are the same bit for bit. */
 } shapley_solve_opts;
 
 /* Per-solve statistics (the paper's table columns, Sec. 6, plus timings). */
@@ -141,7 +145,7 @@ typedef struct shapley_stats {
  * max_outer 100000, max_inner 100000, max_cycles 200, lin_rtol 1e-14,
  * lin_atol 0, tie_rtol 1e-12, theta auto, nu1 = nu2 = 2, omega 0.8,
  * coarse_max 64, max_levels 25, verbose 0, stream NULL, reuse_frac 0.5,
- * forcing 0, smoother SHAPLEY_SMOOTH_JACOBI, gamma 1. */
+ * forcing 0, smoother SHAPLEY_SMOOTH_JACOBI, gamma 1, graph 1. */
 void shapley_default_opts(shapley_solve_opts* o);
 
 /* ---------------------------------------------------------------- games */

@@ -229,6 +229,7 @@ void check_solve_opts(const shapley_solve_opts& o) {
                   o.smoother == SHAPLEY_SMOOTH_CF,
               "bad smoother");
   SHP_REQUIRE(o.gamma == 1 || o.gamma == 2, "gamma must be 1 (V-cycle) or 2 (W-cycle)");
+  SHP_REQUIRE(o.graph == 0 || o.graph == 1, "graph must be 0 or 1");
   SHP_REQUIRE(std::isfinite(o.theta) && std::isfinite(o.omega) && std::isfinite(o.c_fmg) &&
                   std::isfinite(o.lin_rtol) && std::isfinite(o.lin_atol) && std::isfinite(o.tie_rtol) &&
                   std::isfinite(o.reuse_frac),
@@ -375,6 +376,7 @@ void shapley_default_opts(shapley_solve_opts* o) {
   o->forcing = 0.0;
   o->smoother = SHAPLEY_SMOOTH_JACOBI;
   o->gamma = 1;
+  o->graph = 1;
 }
 
 int shapley_game_create(shapley_game_t* out, int64_t n, int32_t m1, int32_t m2, const int64_t* row_ptr,

@@ -124,6 +124,7 @@ void Engine::reset() {
   slots.clear();
   layout_dirty = true;
   have_hier = false;
+  ++hier_gen;
   run_at_setup.clear();
   changes_since_setup = 0;
   last_cycles = 0;
@@ -204,7 +205,13 @@ EngineLease::~EngineLease() {
   std::lock_guard<std::mutex> lk(g_cache_mu);
   if (g_games_alive > 0 && !g_cache.count(s_)) g_cache[s_] = std::move(e_);
 }
+void Engine::drop_graph() {
+  if (cyc_exec) (void)hipGraphExecDestroy(cyc_exec);
+  cyc_exec = nullptr;
+}
+
 Engine::~Engine() {
+  drop_graph();
   if (profiling() && !prof.empty()) {
     fprintf(stderr, "[shapley profile]");
     for (auto& p : prof) fprintf(stderr, " %s=%.2fms", p.first.c_str(), 1e3 * p.second);
@@ -1225,20 +1232,56 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
       probe_add_bytes(kProbeTail, tail_cycle_bytes * cyc);
     }
   } else {
+  // one refinement cycle: the V- or W-cycle, the FP64 update and the FP64
+  // residual with its stop test
+  auto cycle = [&]() {
+    // the last post-smoothing sweep of level 0 (or the tail that ends on
+    // it) adds the correction to the FP64 iterate; otherwise a separate pass
+    double* fused = fuse_update ? sol.p : nullptr;
+    if (mixed) {
+      float* e = vcycle_level<float>(this, lv, 0, o, d_lin_active, stream, fused);
+      if (!fused) cyc_update64<float>(L0.tiles.p, L0.ntiles, d_lin_active, e, sol.p, stream);
+    } else {
+      double* e = vcycle_level<double>(this, lv, 0, o, d_lin_active, stream, fused);
+      if (!fused) cyc_update64<double>(L0.tiles.p, L0.ntiles, d_lin_active, e, sol.p, stream);
+    }
+    resid_check();
+  };
+  // The cycle's launches are captured once per hierarchy into a HIP graph and
+  // replayed (the hierarchy's buffers, tiles and lane counts stay fixed
+  // through refreshes; the per-game flags are read from device memory).  A
+  // probed run launches one by one so that its events bracket each kernel.
+  bool probing = false;
+  for (int f = 0; f < kProbeFamilies; ++f) probing |= probe_on(f);
+  const bool use_graph = o.graph && !probing;
+  if (use_graph) {
+    const GraphKey key{hier_gen, mixed, o.nu1, o.nu2, o.omega, o.smoother, o.gamma, fuse_update, sol.p};
+    if (!cyc_exec || !(key == cyc_key)) {
+      drop_graph();
+      hipGraph_t gr = nullptr;
+      SHP_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed));
+      try {
+        cycle();
+      } catch (...) {
+        (void)hipStreamEndCapture(stream, &gr);
+        if (gr) (void)hipGraphDestroy(gr);
+        throw;
+      }
+      SHP_HIP(hipStreamEndCapture(stream, &gr));
+      const hipError_t ie = hipGraphInstantiate(&cyc_exec, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      if (ie != hipSuccess) {
+        cyc_exec = nullptr;
+        throw Error(SHAPLEY_EDEVICE, std::string("HIP graph instantiation failed: ") + hipGetErrorString(ie));
+      }
+      cyc_key = key;
+    }
+  }
   int chunk = std::max(1, std::min(last_cycles, 16));
   while (true) {
     for (int c = 0; c < chunk; ++c) {
-      // the last post-smoothing sweep of level 0 (or the tail that ends on
-      // it) adds the correction to the FP64 iterate; otherwise a separate pass
-      double* fused = fuse_update ? sol.p : nullptr;
-      if (mixed) {
-        float* e = vcycle_level<float>(this, lv, 0, o, d_lin_active, stream, fused);
-        if (!fused) cyc_update64<float>(L0.tiles.p, L0.ntiles, d_lin_active, e, sol.p, stream);
-      } else {
-        double* e = vcycle_level<double>(this, lv, 0, o, d_lin_active, stream, fused);
-        if (!fused) cyc_update64<double>(L0.tiles.p, L0.ntiles, d_lin_active, e, sol.p, stream);
-      }
-      resid_check();
+      if (use_graph) SHP_HIP(hipGraphLaunch(cyc_exec, stream));
+      else cycle();
     }
     const LinCtl* pl = down(d_lin.p, 2 * (size_t)Gm);
     const int* pe = refresh_errors_down();
@@ -1360,6 +1403,7 @@ int Engine::step() {
     if (full) ++slots[g]->setups_full; else ++slots[g]->setups_refresh;
   }
   if (full) {
+    ++hier_gen;  // a new hierarchy: captured cycles are stale
     setup(run, o);
     lv[0].a_prev.ensure(std::max(NNZ0, 1));
     d2d(lv[0].a_prev.p, lv[0].a64.p, NNZ0, stream);
@@ -1499,6 +1543,7 @@ EngineOpts engine_opts_from(const shapley_solve_opts& o, int dim) {
   e.forcing = o.forcing;
   e.smoother = o.smoother;
   e.gamma = o.gamma;
+  e.graph = o.graph;
   return e;
 }
 

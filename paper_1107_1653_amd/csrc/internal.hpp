@@ -196,6 +196,22 @@ struct EngineOpts {
   double forcing = 0.0;
   int smoother = SHAPLEY_SMOOTH_JACOBI;
   int gamma = 1;
+  int graph = 1;
+};
+
+// What a captured refinement cycle depends on besides device memory contents.
+struct GraphKey {
+  long long gen = -1;  // hierarchy generation (a full setup or a new layout starts a new one)
+  bool mixed = false;
+  int nu1 = 0, nu2 = 0;
+  double omega = 0.0;
+  int smoother = 0, gamma = 0;
+  bool fused = false;
+  const double* sol = nullptr;
+  bool operator==(const GraphKey& o) const {
+    return gen == o.gen && mixed == o.mixed && nu1 == o.nu1 && nu2 == o.nu2 && omega == o.omega &&
+           smoother == o.smoother && gamma == o.gamma && fused == o.fused && sol == o.sol;
+  }
 };
 
 EngineOpts engine_opts_from(const shapley_solve_opts& o, int dim);
@@ -314,7 +330,7 @@ class Engine {
   // Runs one PI step (solve + improve + decide) for every slot not done.
   // Returns the number of slots still running.
   int step();
-  void invalidate_layout() { layout_dirty = true; have_hier = false; }
+  void invalidate_layout() { layout_dirty = true; have_hier = false; ++hier_gen; }
   int num_levels() const { return nlev; }
   int num_slots() const { return G; }
   const TailGL* tail_games() const { return d_tailgl.p; }
@@ -424,6 +440,11 @@ class Engine {
   int64_t changes_since_setup = 0;
   int last_cycles = 0, cycles_after_full = -1;
   bool stagnated = false;  // a linear solve stalled: rebuild the hierarchy
+  // the refinement cycle captured as a HIP graph for the current hierarchy
+  long long hier_gen = 0;
+  hipGraphExec_t cyc_exec = nullptr;
+  GraphKey cyc_key;
+  void drop_graph();
  public:
   int full_setups = 0, refreshes = 0;
  private:

@@ -63,7 +63,7 @@ class shapley_solve_opts(C.Structure):
         ("theta", C.c_double), ("nu1", C.c_int32), ("nu2", C.c_int32), ("omega", C.c_double),
         ("coarse_max", C.c_int32), ("max_levels", C.c_int32), ("verbose", C.c_int32),
         ("stream", C.c_void_p), ("reuse_frac", C.c_double), ("forcing", C.c_double),
-        ("smoother", C.c_int32), ("gamma", C.c_int32),
+        ("smoother", C.c_int32), ("gamma", C.c_int32), ("graph", C.c_int32),
     ]
 
 

@@ -47,10 +47,10 @@ def test_default_options_match_header_documentation():
     assert o.c_fmg == 1e-2 and o.max_cycles == 200 and o.lin_rtol == 1e-14 and o.tie_rtol == 1e-12
     assert o.nu1 == 2 and o.nu2 == 2 and o.omega == 0.8 and o.coarse_max == 64
     assert o.reuse_frac == 0.5 and o.forcing == 0.0
-    assert o.smoother == P.SHAPLEY_SMOOTH_JACOBI and o.gamma == 1
+    assert o.smoother == P.SHAPLEY_SMOOTH_JACOBI and o.gamma == 1 and o.graph == 1
     # the struct layout in the binding equals the C layout: the C side wrote
-    # the last field (gamma) where the binding reads it
-    assert ctypes.sizeof(P.shapley_solve_opts) == P.shapley_solve_opts.gamma.offset + 4
+    # the last field (graph) where the binding reads it
+    assert ctypes.sizeof(P.shapley_solve_opts) == (P.shapley_solve_opts.graph.offset + 4 + 7) // 8 * 8
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")

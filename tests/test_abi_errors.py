@@ -142,7 +142,8 @@ BAD_OPTS = [("precision", 5, "precision"), ("method", 2, "method"), ("max_outer"
             ("coarse_max", 5000, "coarse_max"), ("max_levels", 0, "max_levels"), ("lin_rtol", -1.0, "tolerances"),
             ("tie_rtol", -1e-12, "tolerances"), ("c_fmg", 0.0, "c_fmg"), ("reuse_frac", 1.5, "reuse_frac"),
             ("forcing", 1.0, "forcing"), ("eps", -1.0, "eps"), ("eps", math.nan, "eps"),
-            ("smoother", 7, "smoother"), ("gamma", 3, "gamma"), ("theta", math.nan, "finite")]
+            ("smoother", 7, "smoother"), ("gamma", 3, "gamma"), ("graph", 2, "graph"),
+            ("theta", math.nan, "finite")]
 
 
 @pytest.mark.parametrize("field,value,needle", BAD_OPTS)
