@@ -388,3 +388,164 @@ def with_copied_action(g: Game, player: int, src: int, pos: int, dr: float = 0.0
     valid = None if g.valid is None else g.valid[idx].copy()
     return Game(g.n, m1n, m2n, row_ptr, g.col[take].copy(), g.w[take].copy(), r, g.mu, valid, g.grid,
                 meta=dict(g.meta, copied=(player, src, pos, dr)))
+
+
+# ----------------------------------------------------------------------------
+# games without a grid (the general finite games of Sec. 2)
+# ----------------------------------------------------------------------------
+
+def point_cloud_game(n: int, seed: int, k: int = 8, lam: float = 1.0,
+                     acts: Sequence[float] = ACTIONS_3) -> Game:
+    """A game on n random points of the unit square, each moving to its k
+    nearest neighbours: the upwind weights of the grid scheme with the
+    neighbour directions of the point cloud (no grid, no boundary).
+
+    At x with neighbours y_j, unit directions e_j and local step hx (the mean
+    neighbour distance), for MAX's action a (drift along x1) and MIN's b
+    (drift along x2): q_j = (1 + hx max(0, d . e_j)) / k with d = (a, b),
+    c = sum q_j, D = c + hx^2 lam, w_j = q_j / D, and reward
+    r~ = hx^2 (f(x) - 0.1 a^2 + 0.1 b^2) / D with f = sin(2 pi x1) cos(2 pi x2)
+    + 0.1 N(0, 1).  The rows are substochastic (sum c/D < 1): mu = 1 is
+    passed, as for the grid games."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(seed)
+    pts = rng.random((n, 2))
+    dist, nbr = cKDTree(pts).query(pts, k=k + 1)
+    dist, nbr = dist[:, 1:], nbr[:, 1:]                  # drop the point itself
+    e = (pts[nbr] - pts[:, None, :]) / np.maximum(dist, 1e-300)[:, :, None]
+    hx = dist.mean(axis=1)
+    f = np.sin(2 * np.pi * pts[:, 0]) * np.cos(2 * np.pi * pts[:, 1]) + 0.1 * rng.normal(size=n)
+    acts = np.asarray(acts, dtype=np.float64)
+    m = len(acts)
+    K = m * m
+    cols = np.empty((n, K, k), dtype=np.int64)
+    w = np.empty((n, K, k))
+    rt = np.empty((n, K))
+    for ia, a in enumerate(acts):
+        for ib, b in enumerate(acts):
+            q = (1.0 + hx[:, None] * np.maximum(0.0, a * e[:, :, 0] + b * e[:, :, 1])) / k
+            D = q.sum(axis=1) + hx * hx * lam
+            cols[:, ia * m + ib, :] = nbr
+            w[:, ia * m + ib, :] = q / D[:, None]
+            rt[:, ia * m + ib] = hx * hx * (f - 0.1 * a * a + 0.1 * b * b) / D
+    row_ptr, col, wv, r = _assemble(n, m, m, cols, w, rt)
+    return Game(n, m, m, row_ptr, col, wv, r, 1.0, None, None, meta=dict(kind="point_cloud", k=k, lam=lam))
+
+
+def random_sparse_game(n: int, m1: int, m2: int, seed: int, nnz_row: int = 8, mu: float = 0.95,
+                       window: Optional[int] = None) -> Game:
+    """A random Markov game without geometry: every row (x, a, b) moves to
+    nnz_row distinct states drawn uniformly (or, with `window`, from the
+    states within `window` of x, cyclically), with random weights summing to
+    U[0.5, 1]; normal rewards; discount mu."""
+    rng = np.random.default_rng(seed)
+    nr = n * m1 * m2
+    if window is None:
+        cols = rng.integers(0, n, size=(nr, nnz_row))
+    else:
+        x = np.repeat(np.arange(n), m1 * m2)
+        cols = (x[:, None] + rng.integers(-window, window + 1, size=(nr, nnz_row))) % n
+    cols = np.sort(cols, axis=1)
+    dup = np.zeros_like(cols, dtype=bool)
+    dup[:, 1:] = cols[:, 1:] == cols[:, :-1]
+    p = rng.random((nr, nnz_row)) + 0.05
+    p[dup] = 0.0
+    p = p / p.sum(axis=1, keepdims=True) * rng.uniform(0.5, 1.0, size=(nr, 1))
+    keep = ~dup
+    counts = keep.sum(axis=1)
+    row_ptr = np.zeros(nr + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    r = rng.normal(size=nr)
+    return Game(n, m1, m2, row_ptr, cols[keep].astype(np.int32), p[keep].astype(np.float64), r, mu, None, None,
+                meta=dict(kind="random_sparse", nnz_row=nnz_row, window=window))
+
+
+# ----------------------------------------------------------------------------
+# the Isaacs example with continuous action sets (Sec. 6.1, eqs. (Iex1),
+# (Iex1d)), its action sets replaced by finite subsets
+# ----------------------------------------------------------------------------
+
+def iex1_exact(x1: np.ndarray, x2: np.ndarray) -> np.ndarray:
+    """The exact solution u = sin x1 sin x2 of the example (Sec. 6.1)."""
+    return np.sin(x1) * np.sin(x2)
+
+
+def iex1_game(points: int, a_dirs: int = 8, b_per_axis: int = 5, b_max: float = 1.0,
+              lam: float = 0.0) -> Game:
+    """Eq. (Iex1) on `points` grid points per direction (boundary included,
+    h = 1/(points - 1)), discretised by the upwind scheme as in (Iex1d), with
+    the unit disk of MAX replaced by `a_dirs` directions on its boundary circle
+    (a linear function of a is maximised on it) and MIN's R^2 by a
+    b_per_axis x b_per_axis grid on [0, b_max]^2 (the optimal b = grad u lies
+    in [0, 1]^2 on the unit square).  Dirichlet data psi1 = u on the boundary,
+    f = -(Lap u + |grad u| - 0.5 |grad u|^2 - lam u).
+
+    (Iex1) carries the full Laplacian; dividing it by two gives the scheme of
+    this module with drift (a - b)/2, discount lam/2 and running reward
+    (|b|^2/2 + f)/2: the same weights (1 + h (a_k - b_k)^+-)/(c + h^2 lam) and
+    rewards h^2 (|b|^2/2 + f)/(c + h^2 lam) as (Iex1d), c = 4 + h|a1 - b1| +
+    h|a2 - b2|."""
+    s = points - 2
+    bv = np.zeros((s + 2, s + 2))
+    t = np.arange(s + 2) / (s + 1)
+    X1, X2 = np.meshgrid(t, t, indexing="xy")          # x1 fastest in memory
+    bv[:, :] = iex1_exact(X1, X2)
+    grid = Grid(2, s, bvals=bv.reshape(-1))
+    x1, x2 = grid_coords(grid)
+    n = grid.n
+    gx1, gx2 = np.cos(x1) * np.sin(x2), np.sin(x1) * np.cos(x2)
+    gnorm = np.hypot(gx1, gx2)
+    f = -(-2.0 * np.sin(x1) * np.sin(x2) + gnorm - 0.5 * gnorm ** 2 - lam * iex1_exact(x1, x2))
+    th = 2 * np.pi * np.arange(a_dirs) / a_dirs
+    A = np.stack([np.cos(th), np.sin(th)], axis=1)
+    bg = np.linspace(0.0, b_max, b_per_axis)
+    B = np.array([(u, v) for v in bg for u in bg])
+    m1, m2 = len(A), len(B)
+    K = m1 * m2
+    drifts = np.empty((n, K, 2))
+    rew = np.empty((n, K))
+    for ia in range(m1):
+        for ib in range(m2):
+            q = ia * m2 + ib
+            drifts[:, q, :] = 0.5 * (A[ia] - B[ib])
+            rew[:, q] = 0.5 * (0.5 * (B[ib] @ B[ib]) + f)
+    cols, w, rt = _stencil_rows(grid, drifts, 0.5 * lam, rew)
+    row_ptr, col, wv, r = _assemble(n, m1, m2, cols, w, rt)
+    return Game(n, m1, m2, row_ptr, col, wv, r, 1.0, None, grid,
+                meta=dict(kind="iex1", a_dirs=a_dirs, b_per_axis=b_per_axis, b_max=b_max, lam=lam))
+
+
+def iex1_local_game(points: int, a_dirs: int = 5, b_per_axis: int = 3, da: float = 0.2,
+                    db: float = 0.2) -> Game:
+    """Eq. (Iex1) discretised as in (Iex1d) with state-dependent finite action
+    sets refined around the continuous optimum of the exact solution u
+    (a* = grad u / |grad u|, b* = grad u, Sec. 6.1): MAX's directions at angles
+    within +-da of a*, MIN's b on a b_per_axis^2 grid within +-db of b*.
+    Knowing u, these sets contain the optimum of the discrete operator, so the
+    game's value is that of the scheme with exact inner optimisation (a test
+    workload: the paper does not state how it optimises over the continuous
+    sets).  lam = 0 as in the paper's tests."""
+    s = points - 2
+    t = np.arange(s + 2) / (s + 1)
+    X1, X2 = np.meshgrid(t, t, indexing="xy")
+    grid = Grid(2, s, bvals=iex1_exact(X1, X2).reshape(-1))
+    x1, x2 = grid_coords(grid)
+    n = grid.n
+    gx1, gx2 = np.cos(x1) * np.sin(x2), np.sin(x1) * np.cos(x2)
+    gn = np.hypot(gx1, gx2)
+    f = -(-2.0 * np.sin(x1) * np.sin(x2) + gn - 0.5 * gn ** 2)
+    th = np.arctan2(gx2, gx1)[:, None] + np.linspace(-da, da, a_dirs)[None, :]
+    A = np.stack([np.cos(th), np.sin(th)], axis=2)                        # (n, m1, 2)
+    off = np.linspace(-db, db, b_per_axis)
+    B = np.empty((n, b_per_axis * b_per_axis, 2))
+    for j, v in enumerate(off):
+        for i, u in enumerate(off):
+            B[:, j * b_per_axis + i, 0] = gx1 + u
+            B[:, j * b_per_axis + i, 1] = gx2 + v
+    m1, m2 = a_dirs, b_per_axis * b_per_axis
+    drifts = (0.5 * (A[:, :, None, :] - B[:, None, :, :])).reshape(n, m1 * m2, 2)
+    rew = np.broadcast_to(0.5 * (0.5 * (B ** 2).sum(axis=2)[:, None, :] + f[:, None, None]), (n, m1, m2))
+    cols, w, rt = _stencil_rows(grid, drifts, 0.0, rew.reshape(n, m1 * m2))
+    row_ptr, col, wv, r = _assemble(n, m1, m2, cols, w, rt)
+    return Game(n, m1, m2, row_ptr, col, wv, r, 1.0, None, grid,
+                meta=dict(kind="iex1_local", a_dirs=a_dirs, b_per_axis=b_per_axis, da=da, db=db))

@@ -358,6 +358,56 @@ def test_copied_actions_leave_the_value_unchanged():
 
 
 # ---------------------------------------------------------------------------
+# the Isaacs example with continuous action sets (Sec. 6.1)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("row", json.load(open(os.path.join(GOLDEN, "iex1_printed.json")))["rows"],
+                         ids=lambda r: f"{r['points']} points")
+def test_iex1_errors_match_paper_tables(row):
+    """Eq. (Iex1) with the scheme (Iex1d): with action sets that contain the
+    discrete optimum, the error against the exact solution sin x1 sin x2 is the
+    one the paper prints at its last policy iteration (Tables Iex1t1-Iex1t2),
+    to within 3 %.  The residual test mirrors the paper's stop."""
+    g = games.iex1_local_game(row["points"])
+    res = oracle.policy_iteration(g, eps=1e-10)
+    x1, x2 = games.grid_coords(g.grid)
+    e = res.v - games.iex1_exact(x1, x2)
+    err_inf, err_l2 = np.abs(e).max(), np.sqrt(np.mean(e ** 2))
+    assert res.converged
+    assert err_inf == pytest.approx(row["err_inf"], rel=0.03)
+    assert err_l2 == pytest.approx(row["err_l2"], rel=0.03)
+    # the optimal actions lie inside the local sets (not on their edges)
+    assert np.mean((res.alpha == 0) | (res.alpha == g.m1 - 1)) < 0.01
+
+
+def test_iex1_finite_action_sets_converge():
+    """Fixed finite subsets of the unit disk (directions on its circle) and of
+    R^2 (a grid): refining them brings the value toward the exact solution."""
+    errs = []
+    for dirs, bpa in ((4, 2), (8, 4), (16, 8)):
+        g = games.iex1_game(33, a_dirs=dirs, b_per_axis=bpa)
+        res = oracle.policy_iteration(g)
+        x1, x2 = games.grid_coords(g.grid)
+        errs.append(np.abs(res.v - games.iex1_exact(x1, x2)).max())
+    assert errs[0] > errs[1] > errs[2]
+
+
+# ---------------------------------------------------------------------------
+# games without a grid
+# ---------------------------------------------------------------------------
+
+def test_point_cloud_game_is_a_substochastic_game():
+    g = games.point_cloud_game(500, 4)
+    sums = np.add.reduceat(g.w, g.row_ptr[:-1].astype(np.int64))
+    assert np.all(g.w > 0) and np.all(sums < 1.0) and np.all(sums > 0.9)
+    res = oracle.policy_iteration(g)
+    assert res.converged
+    # fixed point of the operator written as loops (Sec. 2, eq. (eq1))
+    F = np.array(bellman_loop(g, rows_of(g), res.v))
+    assert np.max(np.abs(F - res.v)) <= 1e-12 * (1 + np.abs(res.v).max())
+
+
+# ---------------------------------------------------------------------------
 # closed forms
 # ---------------------------------------------------------------------------
 
