@@ -13,8 +13,9 @@ policy iteration), are reported beside it.  The 3-D Isaacs game on 129^3
 (FP64 and mixed) and the obstacle problem on 1025 x 1025 points (FAMGpi) are
 reported in `extra`, each with its own roofline.  `--workload` picks one of
 c0 (Isaacs 33^2 latency), c1 (obstacle), c2 (3-D Isaacs), c3 (the default),
-c4 (serving stream), two_stopper (the paper's 1-D example, AMGpi vs FAMGpi)
-or general (random sparse games without a grid) as the headline instead.
+c4 (serving stream), two_stopper (the paper's 1-D example, AMGpi vs FAMGpi),
+general (a point-cloud game without a grid) or iex1 (the paper's Isaacs
+example with continuous action sets) as the headline instead.
 
 Prints one JSON line (see the repository's benchmark contract).
 """
@@ -51,7 +52,7 @@ def parse_args():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3",
-                    choices=["c0", "c1", "c2", "c3", "c4", "two_stopper", "general"])
+                    choices=["c0", "c1", "c2", "c3", "c4", "two_stopper", "general", "iex1"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--headline-only", action="store_true",
@@ -562,11 +563,12 @@ def two_stopper_line(args):
 
 
 def general_line(args):
-    """Random sparse games without a grid (n = 2^18 states, 3 x 3 actions,
-    8 transitions per row): AMGpi, FP64 and mixed."""
+    """A game without a grid: 2^18 random points of the unit square, each
+    moving to its 8 nearest neighbours, 3 x 3 actions (drifts along x1 and
+    x2): AMGpi, FP64 and mixed."""
     import paper_1107_1653_amd as P
     from shapley_inputs import games
-    g = games.random_sparse_game(1 << 18, 3, 3, seed=11, nnz_row=8)
+    g = games.point_cloud_game(1 << 18, seed=11)
     h = P.create_from(g)
     out = {}
     for name, prec in (("mixed", P.SHAPLEY_MIXED), ("fp64", P.SHAPLEY_FP64)):
@@ -577,8 +579,51 @@ def general_line(args):
                      "op_complexity": st["op_complexity"], "residual": st["residual"]}
     P.shapley_game_destroy(h)
     line = record(args, out["mixed"]["value"], out["mixed"]["ms_per_step"], "f32+f64",
-                  {"workload": f"random sparse game n={g.n}, 3x3 actions, 8 transitions per row, AMGpi to 1e-8"})
+                  {"workload": f"point-cloud game n={g.n} (8 nearest neighbours, no grid), 3x3 actions, AMGpi to 1e-8"})
     line["extra"] = out
+    return line
+
+
+def iex1_line(args):
+    """The paper's Isaacs example (Sec. 6.1, eq. (Iex1)) on 1025 x 1025 points
+    with action sets around the continuous optimum (5 directions x 9 values of
+    b per state), lambda = 0, to 1e-10 as in the paper's Table table1Iex1:
+    AMGpi and FAMGpi (grids 33 ... 1025 points); errors against sin x1 sin x2."""
+    import paper_1107_1653_amd as P
+    from shapley_inputs import games
+    pts = [33, 65, 129, 257, 513, 1025]
+    t0 = time.perf_counter()
+    levels = [games.iex1_local_game(p) for p in pts]
+    g = levels[-1]
+    log(f"[bench] iex1: generated {len(levels)} grids up to n={g.n} in {time.perf_counter() - t0:.1f}s")
+    x1, x2 = games.grid_coords(g.grid)
+    u = games.iex1_exact(x1, x2)
+    out = {}
+    h = P.create_from(g)
+    for name, prec in (("amgpi_fp64", P.SHAPLEY_FP64), ("amgpi_mixed", P.SHAPLEY_MIXED)):
+        o = P.shapley_default_opts(eps=1e-10, precision=prec, max_outer=5000, max_inner=5000, forcing=args.forcing,
+                                   reuse_frac=args.reuse)
+        wall, lat, st, _ = timed(P, lambda: P.shapley_solve(h, o), args.steps, args.warmup)
+        v = P.shapley_get_value(h)
+        out[name] = {"seconds": wall / args.steps, "outer": st["outer"], "inner": st["inner_total"],
+                     "residual": st["residual"], "err_inf": float(np.max(np.abs(v - u))),
+                     "err_l2": float(np.sqrt(np.mean((v - u) ** 2)))}
+    P.shapley_game_destroy(h)
+    H = P.shapley_game_create_hierarchy([P.create_from(x) for x in levels])
+    of = P.shapley_default_opts(eps=1e-10, method=P.SHAPLEY_FAMGPI, c_fmg=0.1, max_outer=5000, max_inner=5000,
+                                forcing=args.forcing, reuse_frac=args.reuse)
+    wall, lat, st, _ = timed(P, lambda: P.shapley_solve(H, of), args.steps, args.warmup)
+    v = P.shapley_get_value(H)
+    out["famgpi_fp64"] = {"seconds": wall / args.steps, "outer": st["outer"], "residual": st["residual"],
+                          "err_inf": float(np.max(np.abs(v - u))), "err_l2": float(np.sqrt(np.mean((v - u) ** 2)))}
+    P.shapley_game_destroy(H)
+    log(f"[bench] iex1: {out}")
+    line = record(args, g.n / out["amgpi_fp64"]["seconds"], 1e3 * out["amgpi_fp64"]["seconds"], "f64",
+                  {"workload": f"Isaacs example (Iex1), {pts[-1]}x{pts[-1]} points (n={g.n}), {g.m1}x{g.m2} actions "
+                               "per state around the continuous optimum, AMGpi FP64 to 1e-10", "n": g.n})
+    line["extra"] = out
+    line["extra"]["paper"] = {"pi_lu_s": 277.0, "amgpi_s": 55.6, "famgpi_s": 18.5, "err_inf_1025": 4.13e-06,
+                              "hardware": "serial C on an unstated CPU (context only)"}
     return line
 
 
@@ -593,7 +638,7 @@ def main() -> int:
         calibration_kernel()
     if args.workload != "c3":
         fn = {"c0": c0_line, "c1": c1_line, "c2": c2_line, "c4": c4_line, "two_stopper": two_stopper_line,
-              "general": general_line}[args.workload]
+              "general": general_line, "iex1": iex1_line}[args.workload]
         line = fn(args)
         print(json.dumps(line), flush=True)
         return 0

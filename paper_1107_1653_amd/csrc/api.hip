@@ -466,8 +466,9 @@ int shapley_solve(shapley_game_t gh, const shapley_solve_opts* op, shapley_stats
       status = run_amgpi(g->finest(), o, o.eps, true, s, S);
       fill_stats(S, st, now_s() - t0);
     }
-    if (status == SHAPLEY_ENOCONV) set_last_error("policy iteration hit an iteration limit");
-    if (status == SHAPLEY_EDEVICE) set_last_error("non-finite values during the solve");
+    if (status == SHAPLEY_ENOCONV)
+      set_last_error(S.why.empty() ? "policy iteration hit an iteration limit" : S.why);
+    if (status == SHAPLEY_EDEVICE) set_last_error(S.why.empty() ? "non-finite values during the solve" : S.why);
   });
   return rc != SHAPLEY_OK ? rc : status;
 }
@@ -503,7 +504,11 @@ int shapley_solve_batch(shapley_game_t* games, int32_t count, const shapley_solv
     for (int i = 0; i < count; ++i) {
       games[i]->g->solved = true;
       if (stats) fill_stats(S[i], &stats[i], t1 - t0);
-      if (S[i].status != SHAPLEY_OK && status == SHAPLEY_OK) status = S[i].status;
+      if (S[i].status != SHAPLEY_OK && status == SHAPLEY_OK) {
+        status = S[i].status;
+        set_last_error("game " + std::to_string(i) + ": " +
+                       (S[i].why.empty() ? std::string("policy iteration stopped with an error") : S[i].why));
+      }
     }
   });
   return rc != SHAPLEY_OK ? rc : status;

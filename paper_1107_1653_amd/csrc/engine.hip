@@ -1303,7 +1303,13 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
     const LinCtl& c = h_lin[g];
     S->cycles_total += c.cyc;
     S->loose = (c.flags & 1) != 0;
-    if (c.flags & 4) S->status = SHAPLEY_EDEVICE;
+    if (c.flags & 4) {
+      S->status = SHAPLEY_EDEVICE;
+      S->why = "non-finite values in the linear solve";
+    } else if (c.flags & 16) {
+      S->status = SHAPLEY_ENOCONV;
+      S->why = "the multigrid cycles diverge on this game's policy system (its AMG hierarchy does not fit it)";
+    }
     if (c.flags & 2) stagnated = true;
   }
 }
@@ -1469,6 +1475,7 @@ int Engine::step() {
     }
     if (!std::isfinite(S->res)) {
       S->status = SHAPLEY_EDEVICE;
+      S->why = "non-finite Shapley residual";
       S->done = true;
       continue;
     }
@@ -1500,12 +1507,14 @@ int Engine::step() {
         // Algorithm PIalgo assumes an exact inner loop, so this is no fixed
         // point (the residual is above eps, tested above)
         S->status = SHAPLEY_ENOCONV;
+        S->why = "MIN's policy iteration was cut by max_inner while MAX had nothing left to improve";
         S->done = true;
       } else if (nout == 0) {
         S->converged = true;
         S->done = true;
       } else if (S->k >= S->opt.max_outer) {
         S->status = SHAPLEY_ENOCONV;
+        S->why = "policy iteration hit an iteration limit (max_outer)";
         S->done = true;
       } else {
         code[g] = 2;

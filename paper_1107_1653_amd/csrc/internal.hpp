@@ -226,6 +226,7 @@ struct SlotState {
   int k = 1, nk = 0;
   int inner_total = 0, cycles_total = 0;
   int status = SHAPLEY_OK;
+  std::string why;  // reason of a non-OK status
   bool converged = false;
   double res = 0.0, res_l2 = 0.0;
   double res_prev = INFINITY;   // Shapley residual after the previous value step
@@ -243,10 +244,12 @@ struct SlotState {
 // Per-game control of the refinement loop (FP64 residual, stop test, cycle
 // count), kept on the device so that several cycles can be queued between
 // two host checks.  flags: 1 forcing tolerance used, 2 stagnated (no halving
-// over six cycles), 4 non-finite residual, 8 cycle limit reached.
+// over six cycles), 4 non-finite residual, 8 cycle limit reached, 16
+// diverged (the residual grew 10^4 times past the solve's first one).
 struct LinCtl {
   double rtol, atol, forcing, res_prev;
   double hist[8];  // last residual norms, entry i at hist[i % 8]
+  double r0;       // the first residual norm of the solve
   int max_cycles, cyc, nh, flags;
 };
 
@@ -287,10 +290,14 @@ __device__ inline bool lin_decide(int g, double rn, double xn, const double* __r
   const int n = c.nh;
   c.hist[n & 7] = rn;
   c.nh = n + 1;
+  if (n == 0) c.r0 = rn;
   bool stop = false;
   if (!isfinite(rn)) {
     stop = true;
     flags |= 4;
+  } else if (n > 0 && rn > 1e4 * c.r0 && rn > tol) {
+    stop = true;  // the cycles amplify the error: no point in going on
+    flags |= 16;
   } else if (rn <= tol) {
     stop = true;
   } else if (c.cyc >= c.max_cycles) {

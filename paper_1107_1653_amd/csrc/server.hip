@@ -358,7 +358,8 @@ static int server_step(shapley_server_s* srv) {
       continue;
     }
     std::lock_guard<std::mutex> lk(srv->mu);
-    finish(srv, r, S.status, S.status == SHAPLEY_OK ? std::string() : "policy iteration stopped with an error");
+    finish(srv, r, S.status, S.status == SHAPLEY_OK ? std::string() : (S.why.empty() ? "policy iteration stopped "
+                                                                                     "with an error" : S.why));
   }
   srv->active.swap(keep);
   // retire cohorts with no running member: their engines return to the pool

@@ -395,41 +395,63 @@ def with_copied_action(g: Game, player: int, src: int, pos: int, dr: float = 0.0
 # ----------------------------------------------------------------------------
 
 def point_cloud_game(n: int, seed: int, k: int = 8, lam: float = 1.0,
-                     acts: Sequence[float] = ACTIONS_3) -> Game:
-    """A game on n random points of the unit square, each moving to its k
-    nearest neighbours: the upwind weights of the grid scheme with the
-    neighbour directions of the point cloud (no grid, no boundary).
+                     acts: Sequence[float] = ACTIONS_3, symmetric: bool = True) -> Game:
+    """A game on n random points of the unit square whose neighbourhoods are
+    those of the symmetric k-nearest-neighbour graph (y is a neighbour of x
+    when either is among the other's k nearest; with symmetric=False, x's own
+    k nearest only): the upwind weights of the grid scheme with the neighbour
+    directions of an unstructured point cloud (no grid, no boundary).
 
-    At x with neighbours y_j, unit directions e_j and local step hx (the mean
-    neighbour distance), for MAX's action a (drift along x1) and MIN's b
-    (drift along x2): q_j = (1 + hx max(0, d . e_j)) / k with d = (a, b),
-    c = sum q_j, D = c + hx^2 lam, w_j = q_j / D, and reward
+    At x with neighbours y_j (deg of them), unit directions e_j and local step
+    hx (the mean neighbour distance), for MAX's action a (drift along x1) and
+    MIN's b (drift along x2): q_j = (1 + hx max(0, d . e_j)) / deg with
+    d = (a, b), c = sum q_j, D = c + hx^2 lam, w_j = q_j / D, and reward
     r~ = hx^2 (f(x) - 0.1 a^2 + 0.1 b^2) / D with f = sin(2 pi x1) cos(2 pi x2)
     + 0.1 N(0, 1).  The rows are substochastic (sum c/D < 1): mu = 1 is
     passed, as for the grid games."""
+    import scipy.sparse as sp
     from scipy.spatial import cKDTree
     rng = np.random.default_rng(seed)
     pts = rng.random((n, 2))
-    dist, nbr = cKDTree(pts).query(pts, k=k + 1)
-    dist, nbr = dist[:, 1:], nbr[:, 1:]                  # drop the point itself
-    e = (pts[nbr] - pts[:, None, :]) / np.maximum(dist, 1e-300)[:, :, None]
-    hx = dist.mean(axis=1)
+    _, nbr = cKDTree(pts).query(pts, k=k + 1)
+    src = np.repeat(np.arange(n), k)
+    dst = nbr[:, 1:].reshape(-1)
+    if symmetric:
+        src, dst = np.concatenate([src, dst]), np.concatenate([dst, src])
+    adj = sp.coo_matrix((np.ones(len(src)), (src, dst)), shape=(n, n)).tocsr()
+    adj.setdiag(0)
+    adj.eliminate_zeros()
+    adj.sort_indices()
+    rp, cj = adj.indptr.astype(np.int64), adj.indices.astype(np.int64)
+    deg = np.diff(rp)
+    xi = np.repeat(np.arange(n), deg)                       # the state of each entry
+    dvec = pts[cj] - pts[xi]
+    dist = np.hypot(dvec[:, 0], dvec[:, 1])
+    e = dvec / np.maximum(dist, 1e-300)[:, None]
+    hx = np.add.reduceat(dist, rp[:-1]) / deg
     f = np.sin(2 * np.pi * pts[:, 0]) * np.cos(2 * np.pi * pts[:, 1]) + 0.1 * rng.normal(size=n)
     acts = np.asarray(acts, dtype=np.float64)
     m = len(acts)
     K = m * m
-    cols = np.empty((n, K, k), dtype=np.int64)
-    w = np.empty((n, K, k))
-    rt = np.empty((n, K))
+    # rows (x, a, b), b fastest: each repeats the state's neighbour list
+    row_len = np.repeat(deg, K)
+    row_ptr = np.zeros(n * K + 1, dtype=np.int64)
+    np.cumsum(row_len, out=row_ptr[1:])
+    col = np.empty(row_ptr[-1], dtype=np.int32)
+    w = np.empty(row_ptr[-1])
+    r = np.empty(n * K)
+    # entry t of state x in row (x, q) sits at row_ptr[x K + q] + t
+    t_in = np.arange(len(cj)) - rp[xi]
     for ia, a in enumerate(acts):
         for ib, b in enumerate(acts):
-            q = (1.0 + hx[:, None] * np.maximum(0.0, a * e[:, :, 0] + b * e[:, :, 1])) / k
-            D = q.sum(axis=1) + hx * hx * lam
-            cols[:, ia * m + ib, :] = nbr
-            w[:, ia * m + ib, :] = q / D[:, None]
-            rt[:, ia * m + ib] = hx * hx * (f - 0.1 * a * a + 0.1 * b * b) / D
-    row_ptr, col, wv, r = _assemble(n, m, m, cols, w, rt)
-    return Game(n, m, m, row_ptr, col, wv, r, 1.0, None, None, meta=dict(kind="point_cloud", k=k, lam=lam))
+            q = (1.0 + hx[xi] * np.maximum(0.0, a * e[:, 0] + b * e[:, 1])) / deg[xi]
+            D = np.add.reduceat(q, rp[:-1]) + hx * hx * lam
+            pos = row_ptr[xi * K + ia * m + ib] + t_in
+            col[pos] = cj
+            w[pos] = q / D[xi]
+            r[np.arange(n) * K + ia * m + ib] = hx * hx * (f - 0.1 * a * a + 0.1 * b * b) / D
+    return Game(n, m, m, row_ptr, col, w, r, 1.0, None, None,
+                meta=dict(kind="point_cloud", k=k, lam=lam, symmetric=symmetric))
 
 
 def random_sparse_game(n: int, m1: int, m2: int, seed: int, nnz_row: int = 8, mu: float = 0.95,

@@ -99,3 +99,22 @@ def test_iex1_fixed_action_sets_256_rows_per_state():
     err, ma, mb, _ = compare_with_oracle(g, v, a, b, ref, 1e-9)
     log(f"  iex1 fixed sets 16 x 16: err {err:.1e} outer {st['outer']} inner {st['inner_total']}")
     assert err <= 1e-9 and len(ma) == 0 and len(mb) == 0
+
+
+def test_diverging_cycles_are_reported():
+    """A game whose policy systems the AMG hierarchy does not fit (one-sided
+    nearest-neighbour transitions: strongly non-symmetric, the case the paper
+    leaves to future AMG work) ends with SHAPLEY_ENOCONV and a reason, not
+    with non-finite values; the values stay finite and readable."""
+    g = games.point_cloud_game(1 << 16, 11, symmetric=False)
+    h = P.create_from(g)
+    try:
+        st = P.shapley_solve(h, P.shapley_default_opts(eps=1e-8, max_outer=50, max_inner=50), allow_noconv=True)
+        log(f"  one-sided neighbourhoods: rc {st['rc']} ({P.shapley_last_error()}), cycles {st['cycles_total']}")
+        if st["rc"] == P.SHAPLEY_OK:
+            assert st["converged"] == 1 and st["residual"] <= 1e-8
+        else:
+            assert st["rc"] == P.SHAPLEY_ENOCONV and "diverge" in P.shapley_last_error()
+            assert np.all(np.isfinite(P.shapley_get_value(h)))
+    finally:
+        P.shapley_game_destroy(h)
