@@ -253,14 +253,14 @@ void Engine::build_layout() {
     d.rp = gm->rp.p; d.ci = gm->ci.p; d.w = gm->w.p; d.r = gm->r.p; d.valid = gm->valid.p;
     d.urp = gm->urp.p; d.uci = gm->uci.p;
     d.v = gm->v.p; d.alpha = gm->alpha.p; d.beta = gm->beta.p;
-    d.beta_in = gm->beta_in.p; d.alpha_c = gm->alpha_c.p; d.beta_c = gm->beta_c.p; d.F = gm->F.p;
+    d.beta_in = gm->beta_in.p; d.alpha_c = gm->alpha_c.p; d.beta_c = gm->beta_c.p;
+    d.F = keep_F ? gm->F.p : nullptr;  // policy-iteration sweeps need only its residual
     d.bvals = gm->has_bvals ? gm->bvals.p : nullptr;
     d.n = gm->n; d.m1 = gm->m1; d.m2 = gm->m2; d.slot = g; d.mu = gm->mu;
     d.x_off = x_off[g]; d.a_off = a_off[g];
     hdesc[g] = d;
     for (int x = 0; x < gm->n; x += kBlock) h_gtiles_all.push_back({g, x, std::min(x + kBlock, gm->n)});
-    int K = gm->m1 * gm->m2;
-    int spb = std::max(1, kBlock / K);
+    const int spb = improve_states_per_tile(gm->m1, gm->m2);
     for (int x = 0; x < gm->n; x += spb) h_gtiles_imp.push_back({g, x, std::min(x + spb, gm->n)});
   }
   ddesc.ensure(std::max(G, 1));
@@ -1364,6 +1364,10 @@ void Engine::run_init(const std::vector<int>& run) {
 }
 
 void Engine::improve_only() {
+  if (!keep_F) {
+    keep_F = true;
+    layout_dirty = true;
+  }
   if (layout_dirty) build_layout();
   std::vector<int> all;
   for (int g = 0; g < G; ++g) all.push_back(g);

@@ -4,6 +4,7 @@
 // serves every game of a batch.
 #include "internal.hpp"
 
+#include <algorithm>
 #include <climits>
 
 namespace shp {
@@ -224,18 +225,32 @@ void launch_assemble(const GameDesc* d, const GTile* t, int nt, const int* activ
 // adds its row's products in entry order into Q; one thread per state reduces.
 // ---------------------------------------------------------------------------
 constexpr int kImpStage = 1024;
+constexpr int kImpUnroll = kImpStage / 256;  // entries staged per thread and stage
 
+// One tile of states: either taken from the work list (FLAT = false: the
+// tile's game descriptor is read from gd), or, for a single game passed by
+// value, the states [blockIdx.x * spb, (blockIdx.x + 1) * spb).
+template <bool FLAT>
 __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd,
                                                  const GTile* __restrict__ tiles,
                                                  const int* __restrict__ active, double tie_rtol,
-                                                 Stripes red) {
+                                                 Stripes red, GameDesc d1, int spb) {
   __shared__ double sq[256];
   __shared__ double ss[256];
   __shared__ unsigned char sv[256];
   __shared__ double sp[kImpStage];
-  GTile t = tiles[blockIdx.x];
-  if (active && !active[t.game]) return;
-  const GameDesc d = gd[t.game];
+  GTile t;
+  GameDesc d;
+  if (FLAT) {
+    d = d1;
+    t.game = 0;
+    t.s0 = blockIdx.x * spb;
+    t.s1 = t.s0 + spb < d1.n ? t.s0 + spb : d1.n;
+  } else {
+    t = tiles[blockIdx.x];
+    if (active && !active[t.game]) return;
+    d = gd[t.game];
+  }
   const int K = d.m1 * d.m2;
   const int ns = t.s1 - t.s0;
   const int tid = threadIdx.x;
@@ -247,7 +262,21 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
   double acc = 0.0, sacc = 0.0;
   for (int c0 = eb; c0 < ee; c0 += kImpStage) {
     const int c1 = ee < c0 + kImpStage ? ee : c0 + kImpStage;
-    for (int e = c0 + tid; e < c1; e += 256) sp[e - c0] = d.w[e] * d.v[d.ci[e]];
+    // the stage's columns and weights first (all loads in flight), then the
+    // values they gather, then the products into LDS
+    int cc[kImpUnroll];
+    double ww[kImpUnroll], vv[kImpUnroll];
+#pragma unroll
+    for (int u = 0; u < kImpUnroll; ++u) {
+      const int e = c0 + tid + 256 * u;
+      cc[u] = e < c1 ? d.ci[e] : 0;
+      ww[u] = e < c1 ? d.w[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kImpUnroll; ++u) vv[u] = c0 + tid + 256 * u < c1 ? d.v[cc[u]] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kImpUnroll; ++u)
+      if (c0 + tid + 256 * u < c1) sp[tid + 256 * u] = ww[u] * vv[u];
     __syncthreads();
     const int lo = e0 > c0 ? e0 : c0, hi = e1 < c1 ? e1 : c1;
     for (int e = lo; e < hi; ++e) {
@@ -270,8 +299,8 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
   if (tid < ns) {
     const int x = t.s0 + tid;
     const int base = tid * K;
-    const int al = d.alpha[x];
-    const int be = d.beta[x];
+    const int al = d.alpha ? d.alpha[x] : -1;  // no incumbents: the greedy choice
+    const int be = d.beta ? d.beta[x] : -1;
     // MIN at the incumbent alpha
     int bin = -1;
     if (al >= 0) {
@@ -326,15 +355,15 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
         bc = be;
     }
     if (!al_ok) bin = bc;  // never -1: MIN's answer at MAX's improvement
-    d.beta_in[x] = bin;
+    if (d.beta_in) d.beta_in[x] = bin;
     d.alpha_c[x] = ac;
     d.beta_c[x] = bc;
-    d.F[x] = F;
+    if (d.F) d.F[x] = F;  // stored only when asked for
     double dv = F - d.v[x];
     res = dv == dv ? fabs(dv) : INFINITY;
     res2 = dv * dv;
     chg_in = (bin != be) ? 1 : 0;
-    chg_out = (ac != al || !al_ok) ? 1 : 0;
+    chg_out = (ac != al || (al >= 0 && !al_ok)) ? 1 : 0;
   }
   // per-game max |F(v) - v|, sum (F(v) - v)^2 and change counts
   const double vd[2] = {warp_max(res), warp_sum(res2)};
@@ -345,7 +374,18 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
 void launch_improve(const GameDesc* d, const GTile* t, int nt, const int* active, double tie_rtol,
                     Stripes red, hipStream_t s) {
   if (nt == 0) return;
-  hipLaunchKernelGGL(k_improve, dim3(nt), dim3(kBlock), 0, s, d, t, active, tie_rtol, red);
+  hipLaunchKernelGGL(k_improve<false>, dim3(nt), dim3(kBlock), 0, s, d, t, active, tie_rtol, red, GameDesc{}, 0);
+  SHP_LAUNCH_CHECK();
+}
+
+// states per improvement tile: whole states, at most kBlock rows
+int improve_states_per_tile(int m1, int m2) { return std::max(1, kBlock / (m1 * m2)); }
+
+void launch_improve_flat(const GameDesc& d, double tie_rtol, Stripes red, hipStream_t s) {
+  if (d.n == 0) return;
+  const int spb = improve_states_per_tile(d.m1, d.m2);
+  hipLaunchKernelGGL(k_improve<true>, dim3((d.n + spb - 1) / spb), dim3(kBlock), 0, s, (const GameDesc*)nullptr,
+                     (const GTile*)nullptr, (const int*)nullptr, tie_rtol, red, d, spb);
   SHP_LAUNCH_CHECK();
 }
 

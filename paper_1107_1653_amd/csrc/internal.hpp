@@ -30,7 +30,7 @@ struct GameDesc {
   int* beta_in;           // improvement outputs [n]
   int* alpha_c;
   int* beta_c;
-  double* F;              // F(v) [n]
+  double* F;              // F(v) [n], or null: not stored
   const double* bvals;    // Dirichlet values on the extended grid or null
   int n, m1, m2, slot;
   double mu;
@@ -365,8 +365,10 @@ class Engine {
   // Forgets the slots and the hierarchy; keeps the device buffers, so that
   // a reused engine allocates nothing for games no larger than before.
   void reset();
-  // Evaluates the improvement sweep at the slots' current v (no decisions).
+  // Evaluates the improvement sweep at the slots' current v (no decisions),
+  // storing F(v) in the games' F arrays.
   void improve_only();
+  bool keep_F = false;  // store F(v) in the sweeps (improve_only sets it)
   std::vector<int> pmis_need;        // PMIS rounds each level needed at its last setup
   double tail_cycle_bytes = 0.0;     // algorithmic bytes of one tail cycle (probe)
   bool err_pending = false;          // a refresh's error flags not read yet
@@ -504,6 +506,11 @@ void launch_assemble(const GameDesc* d, const GTile* t, int nt, const int* activ
                      Stripes bnorm, hipStream_t s);
 void launch_improve(const GameDesc* d, const GTile* t, int nt, const int* active, double tie_rtol,
                     Stripes red, hipStream_t s);
+// The same sweep over one game passed by value, tiles computed from the block
+// index (no work list in memory); alpha/beta/beta_in/F may be null (no
+// incumbents, outputs not stored); its reductions fold into red as game 0.
+void launch_improve_flat(const GameDesc& d, double tie_rtol, Stripes red, hipStream_t s);
+int improve_states_per_tile(int m1, int m2);
 void launch_fold_finish(Stripes st, int G, int nd, unsigned sum_mask, int ni, double* out_d, int sd, int* out_i,
                         int si, hipStream_t s);
 // combines the FP64-residual stripes (max |r|, max |x|) and takes the stop
