@@ -244,6 +244,21 @@ int shapley_get_policy(shapley_game_t g, int32_t* alpha, int32_t* beta, int32_t*
 int shapley_apply_operator(shapley_game_t g, const double* v, double* F, int32_t* alpha,
                            int32_t* beta);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * operator of shapley_apply_operator with device-resident arguments and no
+ * allocation of any kind.  v[n] (input), F[n] (optional), alpha[n], beta[n]
+ * (required) and res[2] (optional: max_x |F(v) - v| and sum_x (F(v) - v)^2)
+ * are device memory of the current device; the work is queued on `stream`
+ * (NULL: the handle's stream) and the call returns without synchronising.
+ * Its reductions use a fixed device array of the library (16 KB, the same
+ * for every game size; one copy per device, kept until the process ends):
+ * calls that overlap on one device race, so order them on one stream.  The
+ * results equal shapley_apply_operator's bit for bit.  Errors: SHAPLEY_EINVAL
+ * (null handle, v, alpha or beta), SHAPLEY_EDEVICE. */
+int shapley_apply_operator_noalloc(shapley_game_t g, const double* v, double* F, int32_t* alpha, int32_t* beta,
+                                   double* res, void* stream);
+
 /* n = |X|, m1 and m2 (Sec. 2) of a handle (the finest level for
  * hierarchies).  Errors: SHAPLEY_EINVAL (null game). */
 int shapley_game_info(shapley_game_t g, int64_t* n, int32_t* m1, int32_t* m2);

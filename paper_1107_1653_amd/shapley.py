@@ -35,7 +35,7 @@ SHAPLEY_SMOOTH_CF = 2
 EXPORTED = [
     "shapley_last_error", "shapley_default_opts", "shapley_game_create",
     "shapley_game_create_hierarchy", "shapley_solve", "shapley_get_value", "shapley_get_policy",
-    "shapley_apply_operator", "shapley_game_info", "shapley_game_bytes", "shapley_hierarchy_level",
+    "shapley_apply_operator", "shapley_apply_operator_noalloc", "shapley_game_info", "shapley_game_bytes", "shapley_hierarchy_level",
     "shapley_game_destroy",
     "shapley_solve_batch", "shapley_server_create", "shapley_server_submit", "shapley_server_wait",
     "shapley_server_poll", "shapley_server_step", "shapley_server_destroy", "shapley_server_info",
@@ -123,6 +123,7 @@ def lib() -> C.CDLL:
         L.shapley_get_value.argtypes = [P, P, C.c_int32]
         L.shapley_get_policy.argtypes = [P, P, P, P]
         L.shapley_apply_operator.argtypes = [P, P, P, P, P]
+        L.shapley_apply_operator_noalloc.argtypes = [P, P, P, P, P, P, P]
         L.shapley_game_info.argtypes = [P, P, P, P]
         L.shapley_game_bytes.argtypes = [P, C.POINTER(C.c_size_t)]
         L.shapley_hierarchy_level.argtypes = [P, C.c_int32, C.POINTER(shapley_level_info), P, P, P, P, P]
@@ -267,6 +268,17 @@ def shapley_solve_batch(games: Sequence, opts: Optional[shapley_solve_opts] = No
     allow = (SHAPLEY_OK, SHAPLEY_ENOCONV) if allow_noconv else (SHAPLEY_OK,)
     _check(lib().shapley_solve_batch(arr, len(games), None if opts is None else C.byref(opts), st), allow)
     return [s.as_dict() for s in st]
+
+
+def shapley_apply_operator_noalloc(g, v, F, alpha, beta, res=None, stream=None) -> None:
+    """Torch device tensors (float64 v, F, res; int32 alpha, beta) in and out;
+    queued on `stream` (a torch stream or handle; None: the handle's)."""
+    import torch
+    ptr = lambda t, dt: None if t is None else _dev_ptr(t, dt)
+    st = None if stream is None else C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+    _check(lib().shapley_apply_operator_noalloc(g, ptr(v, torch.float64), ptr(F, torch.float64),
+                                                ptr(alpha, torch.int32), ptr(beta, torch.int32),
+                                                ptr(res, torch.float64), st))
 
 
 def shapley_game_info(g):
