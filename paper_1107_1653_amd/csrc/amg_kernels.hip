@@ -1593,37 +1593,19 @@ __global__ __launch_bounds__(kBlock) void k_drap_known(int nc, const long long* 
 constexpr int kSmR = 64, kSmN = 128, kSmHash = 512;
 constexpr int kSmRing = 256;  // queued products: < 64 left over + <= 128 new
 
+// One coarse row I by one wavefront (the body of k_rap_small); the LDS
+// areas are the wavefront's own.  A row it cannot take goes to `big`.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_rap_small(int nc, const int* __restrict__ rrp, const int* __restrict__ rci,
-                                                   const double* __restrict__ rv, const int* __restrict__ rp,
-                                                   const int* __restrict__ ci, const double* __restrict__ a,
-                                                   const int* __restrict__ pc, const double* __restrict__ pv,
-                                                   const int* __restrict__ toff, int* __restrict__ tcnt,
-                                                   int* __restrict__ tcol, double* __restrict__ tval,
-                                                   const int* __restrict__ crp, const int* __restrict__ cci,
-                                                   double* __restrict__ cval, const uint8_t* __restrict__ only,
-                                                   int* __restrict__ big) {
-  static_assert(kSmHash * sizeof(int) <= kSmRing * sizeof(double), "hash must fit in the product queue");
-  static_assert((kSmRing & (kSmRing - 1)) == 0 && kSmRing >= 63 + 32 * PW, "queue too small");
-  __shared__ int s_rS[4][kSmR];
-  __shared__ int s_rO[4][kSmR + 1];
-  __shared__ double s_rV[4][kSmR];
-  __shared__ double s_buf[4][kSmRing];  // hash table, later the queued product values
-  __shared__ int s_lst[4][kSmN];
-  __shared__ int s_qpos[4][kSmRing];    // output position of each queued product
-  __shared__ double s_acc[4][kSmN];     // the row's sums by output position
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int I = blockIdx.x * 4 + w;
-  if (I >= nc) return;  // per wavefront; nothing below synchronises the workgroup
-  if (only && !only[I]) return;
-  int* rS = s_rS[w];
-  int* rO = s_rO[w];
-  double* rV = s_rV[w];
-  int* lst = s_lst[w];
-  int* qpos = s_qpos[w];
-  double* qval = s_buf[w];
-  double* acc = s_acc[w];
-  int* tab = reinterpret_cast<int*>(s_buf[w]);
+__device__ __forceinline__ void rap_small_row(int I, int lane, const int* __restrict__ rrp, const int* __restrict__ rci,
+                                              const double* __restrict__ rv, const int* __restrict__ rp,
+                                              const int* __restrict__ ci, const double* __restrict__ a,
+                                              const int* __restrict__ pc, const double* __restrict__ pv,
+                                              const int* __restrict__ toff, int* __restrict__ tcnt,
+                                              int* __restrict__ tcol, double* __restrict__ tval,
+                                              const int* __restrict__ crp, const int* __restrict__ cci,
+                                              double* __restrict__ cval, int* __restrict__ big, int* rS, int* rO,
+                                              double* rV, int* lst, int* qpos, double* qval, double* acc) {
+  int* tab = reinterpret_cast<int*>(qval);
   auto to_big = [&]() {
     if (lane == 0) big[1 + atomicAdd(big, 1)] = I;
   };
@@ -1758,6 +1740,45 @@ __global__ __launch_bounds__(256) void k_rap_small(int nc, const int* __restrict
     const int base = crp[I];
     for (int h = lane; h < nd; h += 64) cval[base + h] = acc[h];
   }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_rap_small(int nc, const int* __restrict__ rrp, const int* __restrict__ rci,
+                                                   const double* __restrict__ rv, const int* __restrict__ rp,
+                                                   const int* __restrict__ ci, const double* __restrict__ a,
+                                                   const int* __restrict__ pc, const double* __restrict__ pv,
+                                                   const int* __restrict__ toff, int* __restrict__ tcnt,
+                                                   int* __restrict__ tcol, double* __restrict__ tval,
+                                                   const int* __restrict__ crp, const int* __restrict__ cci,
+                                                   double* __restrict__ cval, const uint8_t* __restrict__ only,
+                                                   int* __restrict__ big, const int* __restrict__ list,
+                                                   const int* __restrict__ count) {
+  static_assert(kSmHash * sizeof(int) <= kSmRing * sizeof(double), "hash must fit in the product queue");
+  static_assert((kSmRing & (kSmRing - 1)) == 0 && kSmRing >= 63 + 32 * PW, "queue too small");
+  __shared__ int s_rS[4][kSmR];
+  __shared__ int s_rO[4][kSmR + 1];
+  __shared__ double s_rV[4][kSmR];
+  __shared__ double s_buf[4][kSmRing];  // hash table, later the queued product values
+  __shared__ int s_lst[4][kSmN];
+  __shared__ int s_qpos[4][kSmRing];    // output position of each queued product
+  __shared__ double s_acc[4][kSmN];     // the row's sums by output position
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // nothing below synchronises the workgroup: each wavefront runs its rows
+  if (list) {
+    // the rows listed (a refresh's changed rows), a fixed grid looping over them
+    const int cnt = *count;
+    for (int q = blockIdx.x * 4 + w; q < cnt; q += gridDim.x * 4) {
+      rap_small_row<MODE>(list[q], lane, rrp, rci, rv, rp, ci, a, pc, pv, toff, tcnt, tcol, tval, crp, cci, cval,
+                          big, s_rS[w], s_rO[w], s_rV[w], s_lst[w], s_qpos[w], s_buf[w], s_acc[w]);
+      wave_lds_sync();
+    }
+    return;
+  }
+  const int I = blockIdx.x * 4 + w;
+  if (I >= nc) return;
+  if (only && !only[I]) return;
+  rap_small_row<MODE>(I, lane, rrp, rci, rv, rp, ci, a, pc, pv, toff, tcnt, tcol, tval, crp, cci, cval, big,
+                      s_rS[w], s_rO[w], s_rV[w], s_lst[w], s_qpos[w], s_buf[w], s_acc[w]);
 }
 
 // rows of the scratch area into the final CSR (one wavefront per row)
@@ -2274,11 +2295,13 @@ template <int G>
 __global__ __launch_bounds__(256) void k_diag_dir(const Tile* __restrict__ tiles, const int* __restrict__ rp,
                                                   const int* __restrict__ ci, const double* __restrict__ a,
                                                   int keep_diag, double inv_omega, uint8_t* __restrict__ dir,
-                                                  double* __restrict__ d64, float* __restrict__ d32) {
+                                                  double* __restrict__ d64, float* __restrict__ d32,
+                                                  const uint8_t* __restrict__ only) {
   const Tile t = tiles[blockIdx.x / G];
   int gl;
   const int i = tile_row<G>(t, gl);
-  const bool in = i < t.r1;
+  // rows not flagged keep their data (the lanes of a row leave together)
+  const bool in = i < t.r1 && (!only || only[i]);
   int any = 0;
   double d = 0.0;  // one diagonal entry per row: the sum over lanes is exact
   if (in) {
@@ -2630,15 +2653,19 @@ void amg_dirichlet(const Tile* t, int nt, const int* rp, const int* ci, const do
   SHP_LAUNCH_CHECK();
 }
 void amg_diag_dir(const Tile* t, int nt, const int* rp, const int* ci, const double* a, bool keep_diag,
-                  double inv_omega, uint8_t* dir, double* d64, float* d32, int g, hipStream_t s) {
+                  double inv_omega, uint8_t* dir, double* d64, float* d32, int g, hipStream_t s,
+                  const uint8_t* only) {
   if (!nt) return;
   const int kd = keep_diag ? 1 : 0;
   if (g == 16)
-    hipLaunchKernelGGL(k_diag_dir<16>, dim3(nt * 16), dim3(kTileRows), 0, s, t, rp, ci, a, kd, inv_omega, dir, d64, d32);
+    hipLaunchKernelGGL(k_diag_dir<16>, dim3(nt * 16), dim3(kTileRows), 0, s, t, rp, ci, a, kd, inv_omega, dir, d64, d32,
+                       only);
   else if (g == 4)
-    hipLaunchKernelGGL(k_diag_dir<4>, dim3(nt * 4), dim3(kTileRows), 0, s, t, rp, ci, a, kd, inv_omega, dir, d64, d32);
+    hipLaunchKernelGGL(k_diag_dir<4>, dim3(nt * 4), dim3(kTileRows), 0, s, t, rp, ci, a, kd, inv_omega, dir, d64, d32,
+                       only);
   else
-    hipLaunchKernelGGL(k_diag_dir<1>, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, a, kd, inv_omega, dir, d64, d32);
+    hipLaunchKernelGGL(k_diag_dir<1>, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, a, kd, inv_omega, dir, d64, d32,
+                       only);
   SHP_LAUNCH_CHECK();
 }
 void amg_dir_scale(const Tile* t, int nt, const uint8_t* dir, double f, double* d64, float* d32,
@@ -2797,11 +2824,27 @@ void amg_identity_ops(int n, int* rrp, int* rci, double* rv, int* pc, double* pv
 // Levels with few coarse rows (long rows): one workgroup of 256 lanes per
 // row.  Larger levels (short rows): the wavefront kernel, then the rows it
 // could not take with 128 lanes each.  The results do not depend on the path.
+// rows whose flag is set, appended to list (order free: each row's result
+// does not depend on it); *count = their number (zero before the launch)
+__global__ void k_flag_list(const uint8_t* __restrict__ flags, int n, int* __restrict__ list, int* __restrict__ count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool f = i < n && flags[i] != 0;
+  const unsigned long long m = __ballot(f);
+  if (!m) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(count, __popcll(m));
+  base = __shfl(base, leader);
+  if (f) list[base + __popcll(m & ((1ull << lane) - 1ull))] = i;
+}
+constexpr int kRapListBlocks = 2048;  // grid of a refresh over a list of rows
+
 template <int MODE>
 static void rap_launch(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,
                        const double* a, const int* pc, const double* pv, const int* toff, int* tcnt, int* tcol,
                        double* tval, const int* crp, const int* cci, double* cval, int* err, const uint8_t* only,
-                       int* big, hipStream_t s) {
+                       int* big, hipStream_t s, int* list = nullptr) {
   if (nc < 8192) {
     hipLaunchKernelGGL((k_rap<256, MODE>), dim3(nc), dim3(256), 0, s, nc, rrp, rci, rv, rp, ci, a, pc, pv, toff,
                        tcnt, tcol, tval, crp, cci, cval, err, only);
@@ -2809,8 +2852,19 @@ static void rap_launch(int nc, const int* rrp, const int* rci, const double* rv,
     return;
   }
   fill_async(big, 0, 1, s);
-  hipLaunchKernelGGL((k_rap_small<MODE>), dim3((nc + 3) / 4), dim3(256), 0, s, nc, rrp, rci, rv, rp, ci, a, pc, pv,
-                     toff, tcnt, tcol, tval, crp, cci, cval, only, big);
+  if (only && list) {
+    // a refresh: the flagged rows into a list, then a fixed grid over it (a
+    // grid over every coarse row costs as much as the work when few changed)
+    fill_async(list, 0, 1, s);
+    hipLaunchKernelGGL(k_flag_list, dim3(grid_for(nc)), dim3(kBlock), 0, s, only, nc, list + 1, list);
+    SHP_LAUNCH_CHECK();
+    const unsigned blocks = (unsigned)std::min<int>((nc + 3) / 4, kRapListBlocks);
+    hipLaunchKernelGGL((k_rap_small<MODE>), dim3(blocks), dim3(256), 0, s, nc, rrp, rci, rv, rp, ci, a, pc, pv,
+                       toff, tcnt, tcol, tval, crp, cci, cval, only, big, (const int*)(list + 1), (const int*)list);
+  } else {
+    hipLaunchKernelGGL((k_rap_small<MODE>), dim3((nc + 3) / 4), dim3(256), 0, s, nc, rrp, rci, rv, rp, ci, a, pc,
+                       pv, toff, tcnt, tcol, tval, crp, cci, cval, only, big, (const int*)nullptr, (const int*)nullptr);
+  }
   SHP_LAUNCH_CHECK();
   hipLaunchKernelGGL((k_rap_list<128, MODE>), dim3(std::min(nc, 2048)), dim3(128), 0, s, big, rrp, rci, rv, rp, ci,
                      a, pc, pv, toff, tcnt, tcol, tval, crp, cci, cval, err);
@@ -2831,10 +2885,10 @@ void amg_rap_compact(int nc, const int* toff, const int* tcol, const double* tva
 }
 void amg_rap_known(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,
                    const double* a, const int* pc, const double* pv, const int* crp, const int* cci, double* cval,
-                   int* err, int* big, hipStream_t s, const uint8_t* only) {
+                   int* err, int* big, hipStream_t s, const uint8_t* only, int* list) {
   if (!nc) return;
   rap_launch<kRapKnown>(nc, rrp, rci, rv, rp, ci, a, pc, pv, nullptr, nullptr, nullptr, nullptr, crp, cci, cval, err,
-                        only, big, s);
+                        only, big, s, list);
 }
 static unsigned drap_blocks(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 void amg_drap_full(int nf, int nc, int maxc, const long long* tab, int G, long long ac_total, const int* rp,

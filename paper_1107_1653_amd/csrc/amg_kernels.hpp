@@ -9,8 +9,10 @@ namespace shp {
 void amg_level_init(int n, int nnz, int* lam, int8_t* cf, uint8_t* dir, uint8_t* strong, hipStream_t s);
 void amg_dirichlet(const Tile* t, int nt, const int* rp, const int* ci, const double* a, uint8_t* dir,
                    hipStream_t s);
+// only: rows with a nonzero flag (others keep their data), or null for all
 void amg_diag_dir(const Tile* t, int nt, const int* rp, const int* ci, const double* a, bool keep_diag,
-                  double inv_omega, uint8_t* dir, double* d64, float* d32, int g, hipStream_t s);
+                  double inv_omega, uint8_t* dir, double* d64, float* d32, int g, hipStream_t s,
+                  const uint8_t* only = nullptr);
 void amg_dir_scale(const Tile* t, int nt, const uint8_t* dir, double f, double* d64, float* d32,
                    hipStream_t s);
 // wide: one wavefront per row (levels whose rows are long)
@@ -66,9 +68,11 @@ void amg_rap_fused(int nc, const int* rrp, const int* rci, const double* rv, con
                    double* tval, int* err, int* big, hipStream_t s);
 void amg_rap_compact(int nc, const int* toff, const int* tcol, const double* tval, const int* crp, int* cci,
                      double* cval, hipStream_t s);
+// list: scratch of nc + 1 ints; with `only`, large levels run the flagged rows
+// from a list on a fixed grid
 void amg_rap_known(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,
                    const double* a, const int* pc, const double* pv, const int* crp, const int* cci, double* cval,
-                   int* err, int* big, hipStream_t s, const uint8_t* only);
+                   int* err, int* big, hipStream_t s, const uint8_t* only, int* list = nullptr);
 // Galerkin product of a small level through dense per-game blocks.  tab
 // holds four tables of G + 1 offsets: fine rows, coarse rows, AP entries
 // (sum of n_f * n_c over the games before) and coarse dense entries (sum of

@@ -984,8 +984,10 @@ void Engine::refresh(const EngineOpts& o) {
     if (L.nctiles) {
       // relaxation data of the smoothed rows (level 0 keeps the assembled
       // diagonal); rows of games that end here use the dense inverse instead
+      // level 0's diagonals were rewritten by the assembly; a coarse level's
+      // change only in the rows its Galerkin product recomputes
       amg_diag_dir(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, l == 0, 1.0 / o.omega, L.dir.p, L.dinv64.p,
-                   mixed ? L.dinv32.p : nullptr, L.gA, stream);
+                   mixed ? L.dinv32.p : nullptr, L.gA, stream, l == 0 ? nullptr : L.chg.p);
       Level& Ln = lv[l + 1];
       Ln.chg.ensure(std::max(L.nc, 1));
       fill_async(Ln.chg.p, (uint8_t)0, (size_t)std::max(L.nc, 1), stream);
@@ -1000,18 +1002,21 @@ void Engine::refresh(const EngineOpts& o) {
         // A P rows of the changed fine rows, then the coarse rows they reach
         s_big.ensure((size_t)std::max(n, L.nc) + 1);
         probe_begin(kProbeRap, stream);
+        s_list.ensure((size_t)n + 1);
         amg_rap_known(n, L.id_rp.p, L.id_ci.p, L.id_rv.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, L.ap_rp.p,
-                      L.ap_ci.p, L.ap_v.p, s_err.p + 1, s_big.p, stream, L.chg.p);
+                      L.ap_ci.p, L.ap_v.p, s_err.p + 1, s_big.p, stream, L.chg.p, s_list.p);
         probe_end(kProbeRap, stream, (double)L.ap_nnz * 12 + (double)L.nnz * 12 + (double)n * PW * 12);
         probe_begin(kProbeRap, stream);
+        s_list.ensure((size_t)L.nc + 1);
         amg_rap_known(L.nc, L.rrp.p, L.rci.p, L.rv64.p, L.ap_rp.p, L.ap_ci.p, L.ap_v.p, L.id_pc.p, L.id_pv.p,
-                      Ln.rp.p, Ln.ci.p, Ln.a64.p, s_err.p + 1, s_big.p, stream, Ln.chg.p);
+                      Ln.rp.p, Ln.ci.p, Ln.a64.p, s_err.p + 1, s_big.p, stream, Ln.chg.p, s_list.p);
         probe_end(kProbeRap, stream, (double)Ln.nnz * 12 + (double)L.ap_nnz * 12);
       } else {
         s_big.ensure((size_t)L.nc + 1);
+        s_list.ensure((size_t)L.nc + 1);
         probe_begin(kProbeRap, stream);
         amg_rap_known(L.nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, Ln.rp.p,
-                      Ln.ci.p, Ln.a64.p, s_err.p + 1, s_big.p, stream, Ln.chg.p);
+                      Ln.ci.p, Ln.a64.p, s_err.p + 1, s_big.p, stream, Ln.chg.p, s_list.p);
         probe_end(kProbeRap, stream, (double)Ln.nnz * 12 + (double)L.nnz * 12 + (double)n * PW * 12);
       }
     }

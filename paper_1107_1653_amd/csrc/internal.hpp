@@ -425,6 +425,7 @@ class Engine {
   DBuf<int> s_cnt, s_cursor, s_scan, s_err, s_left, s_newc, s_gidx, s_gout, s_goff;
   DBuf<int> s_toff, s_tcol;   // Galerkin product scratch rows (offsets, columns)
   DBuf<int> s_big;            // Galerkin product: rows left to the workgroup kernel
+  DBuf<int> s_list;           // refresh: count, then the changed coarse rows
   DBuf<int> s_defer;          // interpolation: rows left to the larger instance
   DBuf<double> s_tval;        // and values
   DBuf<double> s_dac;         // dense Galerkin product scratch: R A P
