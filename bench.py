@@ -637,8 +637,8 @@ def main() -> int:
     if args.calibrate_copy:
         calibration_kernel()
     if args.workload != "c3":
-        fn = {"c0": c0_line, "c1": c1_line, "c2": c2_line, "c4": c4_line, "two_stopper": two_stopper_line,
-              "general": general_line, "iex1": iex1_line}[args.workload]
+        fn = {"c0": c0_line, "c1": lambda a: c1_line(a, with_oracle=not a.no_cpu_baseline), "c2": c2_line,
+              "c4": c4_line, "two_stopper": two_stopper_line, "general": general_line, "iex1": iex1_line}[args.workload]
         line = fn(args)
         print(json.dumps(line), flush=True)
         return 0

@@ -244,6 +244,11 @@ void Engine::build_layout() {
   }
   N0 = x_off[G];
   NNZ0 = a_off[G];
+  // kernels with a wavefront per row index 64 N threads in 32 bits
+  if (N0 > kMaxMergedRows)
+    throw Error(SHAPLEY_ENOMEM, "the games solved together hold " + std::to_string(N0) +
+                                    " states, more than one merged hierarchy takes (" +
+                                    std::to_string(kMaxMergedRows) + "): solve fewer games together");
   hdesc.resize(G);
   h_gtiles_all.clear();
   h_gtiles_imp.clear();
@@ -448,6 +453,15 @@ int Engine::tune_lanes(Level& L, bool mixed) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tuned[key] = best;
   return best;
+}
+
+// The Galerkin product's scratch rows are addressed by 32-bit offsets (an
+// exclusive scan of per-row bounds): a level whose bound total could pass
+// 2^31 is refused before any launch instead of wrapping around.
+static void check_offsets(size_t total_bound) {
+  if (total_bound > (size_t)INT32_MAX)
+    throw Error(SHAPLEY_ENOMEM, "a merged AMG level is too large for one Galerkin product (bound " +
+                                    std::to_string(total_bound) + " entries > 2^31): solve fewer games together");
 }
 
 void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
@@ -721,6 +735,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
             s_big.ensure((size_t)n + 1);
             const size_t tcap1 = std::max<size_t>(
                 1, std::min((size_t)PW * (size_t)std::max(L.nnz, 1), (size_t)n * (size_t)kRapMaxCols));
+            check_offsets(tcap1);
             s_tcol.ensure(tcap1);
             s_tval.ensure(tcap1);
             amg_rap_bound(n, L.id_rp.p, L.id_ci.p, L.rp.p, s_cnt.p, PW, stream);
@@ -749,6 +764,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
           // sum of the bounds <= pwf * (pairs) <= pwf * PW * nnz(operand)
           const size_t tcap = std::max<size_t>(
               1, std::min((size_t)pwf * PW * opnnz, (size_t)nc * (size_t)kRapMaxCols));
+          check_offsets(tcap);
           s_tcol.ensure(tcap);
           s_tval.ensure(tcap);
           s_big.ensure((size_t)std::max(n, nc) + 1);

@@ -14,6 +14,7 @@ constexpr int kTileRows = 256;   // rows per level tile
 constexpr int kMaxUnion = 128;   // max entries of one state's level-0 pattern row
 constexpr int kDenseMax = 1024;  // largest dense coarse block
 constexpr int kDenseWave = 96;   // blocks up to this size: one thread per row, rows in registers
+constexpr int kMaxMergedRows = 1 << 25;  // states of the games solved together (64 lanes per row fit 2^31)
 
 // POD view of one game for work-list kernels.
 struct GameDesc {

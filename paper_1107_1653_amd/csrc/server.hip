@@ -31,6 +31,11 @@ static double wall_s() {
 }
 
 constexpr int kMaxCohorts = 16;
+// a cohort's games hold at most this many states together (a bigger request
+// runs alone): merged levels stay far from the 32-bit limits of one hierarchy
+// and the setup scratch of one engine stays a few GB
+constexpr int64_t kCohortMaxStates = int64_t(1) << 23;
+constexpr size_t kPoolEngines = 4;  // idle engines kept with their workspace
 
 struct Cohort;
 
@@ -111,17 +116,21 @@ struct shapley_server_s {
   // buffers are kept: a cohort no larger than an earlier one allocates nothing)
   std::vector<std::pair<hipStream_t, std::unique_ptr<shp::Engine>>> pool;
   std::vector<hipStream_t> own_streams;
+  std::vector<hipStream_t> free_streams;  // owned, not held by a cohort or the pool
 };
 
 namespace shp {
 
 // Device memory a request needs while active: its game data plus the merged
 // level-0 system, the AMG hierarchy and the cycle vectors (about 24 doubles
-// and 10 ints per unknown at operator complexity 2).
+// and 10 ints per unknown at operator complexity 2) and its share of the
+// setup scratch of the Galerkin product (up to 16 products of 12 bytes per
+// level-0 entry).
 static size_t estimate_footprint(Game* h) {
   Game* f = h->finest();
   size_t b = h->device_bytes();
   b += (size_t)f->n * (24 * sizeof(double) + 10 * sizeof(int)) + (size_t)f->unnz * 3 * (sizeof(double) + 4);
+  b += (size_t)f->unnz * PW * PW * (sizeof(double) + sizeof(int));
   return b;
 }
 
@@ -219,8 +228,13 @@ static Cohort* new_cohort(shapley_server_s* srv, const CohortKey& key) {
     srv->pool.pop_back();
   } else {
     hipStream_t s;
-    SHP_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-    srv->own_streams.push_back(s);
+    if (!srv->free_streams.empty()) {
+      s = srv->free_streams.back();
+      srv->free_streams.pop_back();
+    } else {
+      SHP_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      srv->own_streams.push_back(s);
+    }
     c->stream = s;
     c->eng.reset(new Engine(s));
   }
@@ -241,16 +255,35 @@ static void place(shapley_server_s* srv, const std::vector<Request*>& rs) {
       if (gr.first == k) { gr.second.push_back(r); found = true; break; }
     if (!found) groups.push_back({k, {r}});
   }
+  // each group in chunks of at most kCohortMaxStates states (in FIFO order)
+  std::vector<std::pair<CohortKey, std::vector<Request*>>> chunks;
   for (auto& gr : groups) {
+    int64_t states = 0;
+    chunks.push_back({gr.first, {}});
+    for (Request* r : gr.second) {
+      const int64_t n = r->current()->n;
+      if (!chunks.back().second.empty() && states + n > kCohortMaxStates) {
+        chunks.push_back({gr.first, {}});
+        states = 0;
+      }
+      chunks.back().second.push_back(r);
+      states += n;
+    }
+  }
+  for (auto& gr : chunks) {
+    int64_t add = 0;
+    for (Request* r : gr.second) add += r->current()->n;
     Cohort* c = nullptr;
     bool joining = false;
     if ((int)srv->cohorts.size() >= kMaxCohorts) {
       int64_t best = INT64_MAX;
-      for (auto& q : srv->cohorts)
-        if (q->key == gr.first && q->error == SHAPLEY_OK && q->running_unknowns() < best) {
-          best = q->running_unknowns();
+      for (auto& q : srv->cohorts) {
+        const int64_t u = q->running_unknowns();
+        if (q->key == gr.first && q->error == SHAPLEY_OK && u + add <= kCohortMaxStates && u < best) {
+          best = u;
           c = q.get();
         }
+      }
       joining = c != nullptr;
     }
     if (!c) c = new_cohort(srv, gr.first);
@@ -370,9 +403,14 @@ static int server_step(shapley_server_s* srv) {
       live.push_back(std::move(c));
       continue;
     }
-    if (c->error == SHAPLEY_OK && !srv->stream) {
+    if (c->error == SHAPLEY_OK && !srv->stream && srv->pool.size() < kPoolEngines) {
       c->eng->reset();
       srv->pool.emplace_back(c->stream, std::move(c->eng));
+    } else if (!srv->stream) {
+      // the engine and its workspace are released with the cohort; the stream
+      // serves a later cohort
+      c->eng.reset();
+      srv->free_streams.push_back(c->stream);
     }
   }
   srv->cohorts.swap(live);
