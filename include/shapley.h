@@ -278,6 +278,17 @@ int shapley_game_bytes(shapley_game_t g, size_t* bytes);
  * any other value. */
 int shapley_tune_lanes(int32_t lanes);
 
+/* Kernel choice of the row-wise Galerkin product A_{l+1} = R A_l P (Sec. 4.3)
+ * on large levels: -1 (default) lets the library choose per product from the
+ * level's average row length; 0 forces the wavefront-per-row kernel alone;
+ * 1 first runs a thread-per-row kernel and 4 a four-lanes-per-row kernel,
+ * each taking the rows whose columns fit it and handing the others to the
+ * wavefront kernel.  Every kernel sums each entry's products in the same
+ * order, so results do not depend on this setting.  Process-wide; applies
+ * to later setups and refreshes.  Errors: SHAPLEY_EINVAL for any other
+ * value. */
+int shapley_tune_galerkin(int32_t kernel);
+
 /* Inspection of the algebraic multigrid hierarchy (Sec. 4.3) built by the
  * last shapley_solve of g, run alone on the handle's own stream (opts.stream
  * NULL; for a hierarchy handle, the finest grid's).  Level 0 is the operator

@@ -1781,6 +1781,323 @@ __global__ __launch_bounds__(256) void k_rap_small(int nc, const int* __restrict
                       s_rS[w], s_rO[w], s_rV[w], s_lst[w], s_qpos[w], s_buf[w], s_acc[w]);
 }
 
+// Short coarse rows by one thread each (levels of grid stencils): the row's
+// sorted columns and sums live in the thread's column of two LDS arrays
+// (entry h at h * 64 + lane, so the lanes of a wavefront never share a bank).
+// The products r_Ii a_ik p_kJ are generated in the same order as in the
+// wavefront and workgroup kernels (R's row, A's row, P's slots) and each is
+// added to its column's sum when generated: every sum takes its products in
+// generation order, starting from zero, so the three kernels agree bit for
+// bit.  A row the thread cannot take (more than NC columns, or an R row
+// beyond the workgroup kernel's cap) is handed to the wavefront kernel.
+template <int MODE, int NC>
+__device__ __forceinline__ bool rap_thread_row(int I, const int* __restrict__ rrp, const int* __restrict__ rci,
+                                               const double* __restrict__ rv, const int* __restrict__ rp,
+                                               const int* __restrict__ ci, const double* __restrict__ a,
+                                               const int* __restrict__ pc, const double* __restrict__ pv,
+                                               const int* __restrict__ toff, int* __restrict__ tcnt,
+                                               int* __restrict__ tcol, double* __restrict__ tval,
+                                               const int* __restrict__ crp, const int* __restrict__ cci,
+                                               double* __restrict__ cval, int* col, double* acc) {
+#pragma clang fp contract(off)
+  const int p0 = rrp[I], p1 = rrp[I + 1];
+  if (p1 - p0 > kRapRCap) return false;
+  int nd = 0;
+  if (MODE == kRapKnown) {
+    const int base = crp[I];
+    nd = crp[I + 1] - base;
+    if (nd > NC) return false;
+    for (int h = 0; h < nd; ++h) {
+      col[h * 64] = cci[base + h];
+      acc[h * 64] = 0.0;
+    }
+  }
+  for (int p = p0; p < p1; ++p) {
+    const int i = rci[p];
+    const double r = rv[p];
+    const int e1 = rp[i + 1];
+    for (int e = rp[i]; e < e1; ++e) {
+      const int k = ci[e];
+      const double ra = r * a[e];
+#pragma unroll
+      for (int q = 0; q < PW; ++q) {
+        const int J = pc[(size_t)k * PW + q];
+        if (J < 0) continue;
+        const double x = ra * pv[(size_t)k * PW + q];
+        int lo = 0, hi = nd;  // first position with col >= J
+        while (lo < hi) {
+          const int m = (lo + hi) >> 1;
+          if (col[m * 64] < J) lo = m + 1; else hi = m;
+        }
+        if (lo < nd && col[lo * 64] == J) {
+          acc[lo * 64] = acc[lo * 64] + x;
+          continue;
+        }
+        if (MODE == kRapKnown) continue;  // outside the known pattern: skipped, as in the other kernels
+        if (nd == NC) return false;
+        for (int h = nd; h > lo; --h) {
+          col[h * 64] = col[(h - 1) * 64];
+          acc[h * 64] = acc[(h - 1) * 64];
+        }
+        col[lo * 64] = J;
+        acc[lo * 64] = 0.0 + x;
+        ++nd;
+      }
+    }
+  }
+  if (MODE == kRapFused) {
+    const int o = toff[I];
+    for (int h = 0; h < nd; ++h) {
+      tcol[o + h] = col[h * 64];
+      tval[o + h] = acc[h * 64];
+    }
+    tcnt[I] = nd;
+  } else {
+    const int base = crp[I];
+    for (int h = 0; h < nd; ++h) cval[base + h] = acc[h * 64];
+  }
+  return true;
+}
+
+// rows with f set appended to lst[1 ..] (count in lst[0]; order free), one
+// atomic per wavefront
+__device__ __forceinline__ void append_rows(bool f, int I, int* __restrict__ lst) {
+  const unsigned long long m = __ballot(f);
+  if (!m) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(lst, __popcll(m));
+  base = __shfl(base, leader);
+  if (f) lst[1 + base + __popcll(m & ((1ull << lane) - 1ull))] = I;
+}
+
+template <int MODE, int NC>
+__global__ __launch_bounds__(64) void k_rap_thr(int nc, const int* __restrict__ rrp, const int* __restrict__ rci,
+                                                const double* __restrict__ rv, const int* __restrict__ rp,
+                                                const int* __restrict__ ci, const double* __restrict__ a,
+                                                const int* __restrict__ pc, const double* __restrict__ pv,
+                                                const int* __restrict__ toff, int* __restrict__ tcnt,
+                                                int* __restrict__ tcol, double* __restrict__ tval,
+                                                const int* __restrict__ crp, const int* __restrict__ cci,
+                                                double* __restrict__ cval, const uint8_t* __restrict__ only,
+                                                int* __restrict__ mid, const int* __restrict__ list,
+                                                const int* __restrict__ count) {
+  __shared__ int s_col[NC * 64];
+  __shared__ double s_acc[NC * 64];
+  const int lane = threadIdx.x;
+  int* col = s_col + lane;
+  double* acc = s_acc + lane;
+  // nothing below synchronises the workgroup: each thread runs its own rows
+  if (list) {
+    const int cnt = *count;
+    for (int q = blockIdx.x * 64 + lane; q < cnt; q += gridDim.x * 64) {
+      const int I = list[q];
+      const bool ok = rap_thread_row<MODE, NC>(I, rrp, rci, rv, rp, ci, a, pc, pv, toff, tcnt, tcol, tval, crp,
+                                               cci, cval, col, acc);
+      append_rows(!ok, I, mid);
+    }
+    return;
+  }
+  const int I = blockIdx.x * 64 + lane;
+  if (I >= nc) return;
+  bool ok = true;
+  if (!only || only[I])
+    ok = rap_thread_row<MODE, NC>(I, rrp, rci, rv, rp, ci, a, pc, pv, toff, tcnt, tcol, tval, crp, cci, cval, col,
+                                  acc);
+  append_rows(!ok, I, mid);
+}
+
+// Coarse rows by four lanes each (16 rows per wavefront): lane q of a row's
+// group takes slot q of P's row in every (R entry, A entry) pair, so the four
+// products of a pair, which go to distinct columns, are formed at once and
+// each column still takes its products in generation order.  The group keeps
+// the row's sorted columns and sums in LDS (NC of each).  A full product
+// first finds the columns (inserted into a hash table in the sums' space,
+// then ranked), then forms the sums; a refresh reads the known columns.  The
+// pairs of an A row are taken four at a time, their loads issued together.
+// Rows that do not fit are handed to the wavefront kernel, as in the
+// thread-per-row kernel.
+template <int NC>
+__device__ __forceinline__ int quad_lower_bound(const int* col, int nd, int J) {
+  int pos = 0;  // number of columns < J (nd <= NC)
+#pragma unroll
+  for (int step = NC; step > 0; step >>= 1)
+    if (pos + step <= nd && col[pos + step - 1] < J) pos += step;
+  return pos;
+}
+
+template <int MODE, int NC>
+__device__ __forceinline__ bool rap_quad_row(int I, int q, const int* __restrict__ rrp, const int* __restrict__ rci,
+                                             const double* __restrict__ rv, const int* __restrict__ rp,
+                                             const int* __restrict__ ci, const double* __restrict__ a,
+                                             const int* __restrict__ pc, const double* __restrict__ pv,
+                                             const int* __restrict__ toff, int* __restrict__ tcnt,
+                                             int* __restrict__ tcol, double* __restrict__ tval,
+                                             const int* __restrict__ crp, const int* __restrict__ cci,
+                                             double* __restrict__ cval, int* col, double* acc) {
+#pragma clang fp contract(off)
+  constexpr int kU = 4;        // pairs whose loads are issued together
+  constexpr int kH = 2 * NC;   // hash slots (in the space of the sums)
+  constexpr int kR = NC / 4;   // columns ranked per lane
+  const int lane = threadIdx.x & 63;
+  const int gbase = lane & ~3;  // first lane of the group
+  const int p0 = rrp[I], p1 = rrp[I + 1];
+  if (p1 - p0 > kRapRCap) return false;
+  int nd = 0;
+  if (MODE == kRapKnown) {
+    const int base = crp[I];
+    nd = crp[I + 1] - base;
+    if (nd > NC) return false;
+    for (int h = q; h < nd; h += 4) col[h] = cci[base + h];
+  } else {
+    int* tab = reinterpret_cast<int*>(acc);
+    for (int h = q; h < kH; h += 4) tab[h] = -1;
+    wave_lds_sync();
+    bool full = false;  // a column found no free slot: more than kH columns
+    for (int p = p0; p < p1; ++p) {
+      const int i = rci[p];
+      const int e1 = rp[i + 1];
+      for (int e = rp[i]; e < e1; e += kU) {
+        int k[kU], J[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) k[u] = e + u < e1 ? ci[e + u] : -1;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) J[u] = k[u] >= 0 ? pc[(size_t)k[u] * PW + q] : -1;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          if (J[u] < 0) continue;
+          unsigned h = mix32((uint32_t)J[u]) & (kH - 1);
+          bool done = false;
+          for (int t = 0; t < kH && !done; ++t) {
+            const int old = atomicCAS(&tab[h], -1, J[u]);
+            done = old == -1 || old == J[u];
+            h = (h + 1) & (kH - 1);
+          }
+          full |= !done;
+        }
+      }
+    }
+    wave_lds_sync();
+    // the occupied slots into col (in slot order), then each column to its rank
+    for (int h0 = 0; h0 < kH; h0 += 4) {
+      const int key = tab[h0 + q];
+      const unsigned m = (unsigned)(__ballot(key >= 0) >> gbase) & 0xFu;
+      const int at = nd + __popc(m & ((1u << q) - 1u));
+      if (key >= 0 && at < NC) col[at] = key;
+      nd += __popc(m);
+    }
+    const bool over = (((unsigned)(__ballot(full) >> gbase) & 0xFu) != 0u) || nd > NC;
+    if (over) return false;
+    wave_lds_sync();
+    int key[kR], rank[kR];
+#pragma unroll
+    for (int u = 0; u < kR; ++u) {
+      const int j = q + 4 * u;
+      key[u] = j < nd ? col[j] : INT_MAX;
+      rank[u] = 0;
+    }
+    for (int t = 0; t < nd; ++t) {
+      const int c = col[t];
+#pragma unroll
+      for (int u = 0; u < kR; ++u) rank[u] += c < key[u] ? 1 : 0;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int u = 0; u < kR; ++u)
+      if (q + 4 * u < nd) col[rank[u]] = key[u];
+  }
+  for (int h = q; h < nd; h += 4) acc[h] = 0.0;
+  wave_lds_sync();
+  // the sums: the pairs in order, the four slots of a pair at once
+  for (int p = p0; p < p1; ++p) {
+    const int i = rci[p];
+    const double r = rv[p];
+    const int e1 = rp[i + 1];
+    for (int e = rp[i]; e < e1; e += kU) {
+      int k[kU], J[kU];
+      double av[kU], pw[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        k[u] = -1;
+        av[u] = 0.0;
+        if (e + u < e1) {
+          k[u] = ci[e + u];
+          av[u] = a[e + u];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        J[u] = -1;
+        pw[u] = 0.0;
+        if (k[u] >= 0) {
+          J[u] = pc[(size_t)k[u] * PW + q];
+          pw[u] = pv[(size_t)k[u] * PW + q];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        if (J[u] < 0) continue;
+        const double ra = r * av[u];
+        const double x = ra * pw[u];
+        const int pos = quad_lower_bound<NC>(col, nd, J[u]);
+        // outside a known pattern: skipped, as in the other kernels
+        if (pos < nd && col[pos] == J[u]) acc[pos] = acc[pos] + x;
+      }
+    }
+  }
+  if (MODE == kRapFused) {
+    const int o = toff[I];
+    for (int h = q; h < nd; h += 4) {
+      tcol[o + h] = col[h];
+      tval[o + h] = acc[h];
+    }
+    if (q == 0) tcnt[I] = nd;
+  } else {
+    const int base = crp[I];
+    for (int h = q; h < nd; h += 4) cval[base + h] = acc[h];
+  }
+  return true;
+}
+
+template <int MODE, int NC>
+__global__ __launch_bounds__(256) void k_rap_quad(int nc, const int* __restrict__ rrp, const int* __restrict__ rci,
+                                                  const double* __restrict__ rv, const int* __restrict__ rp,
+                                                  const int* __restrict__ ci, const double* __restrict__ a,
+                                                  const int* __restrict__ pc, const double* __restrict__ pv,
+                                                  const int* __restrict__ toff, int* __restrict__ tcnt,
+                                                  int* __restrict__ tcol, double* __restrict__ tval,
+                                                  const int* __restrict__ crp, const int* __restrict__ cci,
+                                                  double* __restrict__ cval, const uint8_t* __restrict__ only,
+                                                  int* __restrict__ mid, const int* __restrict__ list,
+                                                  const int* __restrict__ count) {
+  __shared__ int s_col[64][NC];
+  __shared__ double s_acc[64][NC];
+  const int grp = threadIdx.x >> 2, q = threadIdx.x & 3;
+  int* col = s_col[grp];
+  double* acc = s_acc[grp];
+  // nothing below synchronises the workgroup: each group of four lanes runs
+  // its own rows (the groups of a wavefront may diverge)
+  if (list) {
+    const int cnt = *count;
+    for (int t = blockIdx.x * 64 + grp; t < cnt; t += gridDim.x * 64) {
+      const int I = list[t];
+      const bool ok = rap_quad_row<MODE, NC>(I, q, rrp, rci, rv, rp, ci, a, pc, pv, toff, tcnt, tcol, tval, crp, cci,
+                                             cval, col, acc);
+      append_rows(!ok && q == 0, I, mid);
+      wave_lds_sync();
+    }
+    return;
+  }
+  const int I = blockIdx.x * 64 + grp;
+  if (I >= nc) return;
+  bool ok = true;
+  if (!only || only[I])
+    ok = rap_quad_row<MODE, NC>(I, q, rrp, rci, rv, rp, ci, a, pc, pv, toff, tcnt, tcol, tval, crp, cci, cval, col,
+                                acc);
+  append_rows(!ok && q == 0, I, mid);
+}
+
 // rows of the scratch area into the final CSR (one wavefront per row)
 __global__ __launch_bounds__(64) void k_rap_compact(int nc, const int* __restrict__ toff,
                                                     const int* __restrict__ tcol, const double* __restrict__ tval,
@@ -2821,9 +3138,6 @@ void amg_identity_ops(int n, int* rrp, int* rci, double* rv, int* pc, double* pv
   hipLaunchKernelGGL(k_identity_ops, dim3(grid_for(n + 1)), dim3(kBlock), 0, s, n, rrp, rci, rv, pc, pv);
   SHP_LAUNCH_CHECK();
 }
-// Levels with few coarse rows (long rows): one workgroup of 256 lanes per
-// row.  Larger levels (short rows): the wavefront kernel, then the rows it
-// could not take with 128 lanes each.  The results do not depend on the path.
 // rows whose flag is set, appended to list (order free: each row's result
 // does not depend on it); *count = their number (zero before the launch)
 __global__ void k_flag_list(const uint8_t* __restrict__ flags, int n, int* __restrict__ list, int* __restrict__ count) {
@@ -2840,26 +3154,66 @@ __global__ void k_flag_list(const uint8_t* __restrict__ flags, int n, int* __res
 }
 constexpr int kRapListBlocks = 2048;  // grid of a refresh over a list of rows
 
+// Levels with few coarse rows (long rows): one workgroup of 256 lanes per
+// row.  Larger levels: with a first kernel (kern: thread per row with 16 or
+// 32 columns, or four lanes per row with 32 or 64) taking the rows that fit,
+// then the wavefront kernel over the rows it handed on, then the workgroup
+// kernel over the rows the wavefront kernel could not take; without, the
+// wavefront kernel over every row.  big holds 2 (nc + 1) ints: the two
+// hand-over lists.  The results do not depend on the path.
+template <int MODE, typename K>
+static void first_pass(K kern, unsigned blocks, unsigned threads, hipStream_t s, int nc, const int* rrp,
+                       const int* rci, const double* rv, const int* rp, const int* ci, const double* a, const int* pc,
+                       const double* pv, const int* toff, int* tcnt, int* tcol, double* tval, const int* crp,
+                       const int* cci, double* cval, const uint8_t* only, int* mid, const int* tl, const int* tn) {
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, nc, rrp, rci, rv, rp, ci, a, pc, pv, toff, tcnt, tcol,
+                     tval, crp, cci, cval, only, mid, tl, tn);
+  SHP_LAUNCH_CHECK();
+}
+
 template <int MODE>
 static void rap_launch(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,
                        const double* a, const int* pc, const double* pv, const int* toff, int* tcnt, int* tcol,
                        double* tval, const int* crp, const int* cci, double* cval, int* err, const uint8_t* only,
-                       int* big, hipStream_t s, int* list = nullptr) {
+                       int* big, hipStream_t s, int* list, int kern) {
   if (nc < 8192) {
     hipLaunchKernelGGL((k_rap<256, MODE>), dim3(nc), dim3(256), 0, s, nc, rrp, rci, rv, rp, ci, a, pc, pv, toff,
                        tcnt, tcol, tval, crp, cci, cval, err, only);
     SHP_LAUNCH_CHECK();
     return;
   }
+  int* mid = big + nc + 1;  // rows handed from the first kernel to the wavefront kernel
   fill_async(big, 0, 1, s);
-  if (only && list) {
+  const bool refresh = only && list;
+  if (refresh) {
     // a refresh: the flagged rows into a list, then a fixed grid over it (a
     // grid over every coarse row costs as much as the work when few changed)
     fill_async(list, 0, 1, s);
     hipLaunchKernelGGL(k_flag_list, dim3(grid_for(nc)), dim3(kBlock), 0, s, only, nc, list + 1, list);
     SHP_LAUNCH_CHECK();
-    const unsigned blocks = (unsigned)std::min<int>((nc + 3) / 4, kRapListBlocks);
-    hipLaunchKernelGGL((k_rap_small<MODE>), dim3(blocks), dim3(256), 0, s, nc, rrp, rci, rv, rp, ci, a, pc, pv,
+  }
+  const unsigned wblocks = (unsigned)std::min<int>((nc + 3) / 4, kRapListBlocks);
+  if (kern != kGalWave) {
+    fill_async(mid, 0, 1, s);
+    const int* tl = refresh ? (const int*)(list + 1) : nullptr;
+    const int* tn = refresh ? (const int*)list : nullptr;
+    const bool quad = kern == kGalQuad32 || kern == kGalQuad64;
+    const int per = quad ? 64 : 64;  // rows per workgroup
+    const unsigned blocks = refresh ? (unsigned)std::min<int>((nc + per - 1) / per, kRapListBlocks)
+                                    : (unsigned)((nc + per - 1) / per);
+#define SHP_FIRST(K, T) first_pass<MODE>(K, blocks, T, s, nc, rrp, rci, rv, rp, ci, a, pc, pv, toff, tcnt, tcol, tval, \
+                                         crp, cci, cval, only, mid, tl, tn)
+    switch (kern) {
+      case kGalThread16: SHP_FIRST((k_rap_thr<MODE, 16>), 64); break;
+      case kGalThread32: SHP_FIRST((k_rap_thr<MODE, 32>), 64); break;
+      case kGalQuad32: SHP_FIRST((k_rap_quad<MODE, 32>), 256); break;
+      default: SHP_FIRST((k_rap_quad<MODE, 64>), 256); break;
+    }
+#undef SHP_FIRST
+    hipLaunchKernelGGL((k_rap_small<MODE>), dim3(wblocks), dim3(256), 0, s, nc, rrp, rci, rv, rp, ci, a, pc, pv,
+                       toff, tcnt, tcol, tval, crp, cci, cval, only, big, (const int*)(mid + 1), (const int*)mid);
+  } else if (refresh) {
+    hipLaunchKernelGGL((k_rap_small<MODE>), dim3(wblocks), dim3(256), 0, s, nc, rrp, rci, rv, rp, ci, a, pc, pv,
                        toff, tcnt, tcol, tval, crp, cci, cval, only, big, (const int*)(list + 1), (const int*)list);
   } else {
     hipLaunchKernelGGL((k_rap_small<MODE>), dim3((nc + 3) / 4), dim3(256), 0, s, nc, rrp, rci, rv, rp, ci, a, pc,
@@ -2872,10 +3226,10 @@ static void rap_launch(int nc, const int* rrp, const int* rci, const double* rv,
 }
 void amg_rap_fused(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,
                    const double* a, const int* pc, const double* pv, const int* toff, int* tcnt, int* tcol,
-                   double* tval, int* err, int* big, hipStream_t s) {
+                   double* tval, int* err, int* big, hipStream_t s, int kern) {
   if (!nc) return;
   rap_launch<kRapFused>(nc, rrp, rci, rv, rp, ci, a, pc, pv, toff, tcnt, tcol, tval, nullptr, nullptr, nullptr, err,
-                        nullptr, big, s);
+                        nullptr, big, s, nullptr, kern);
 }
 void amg_rap_compact(int nc, const int* toff, const int* tcol, const double* tval, const int* crp, int* cci,
                      double* cval, hipStream_t s) {
@@ -2885,10 +3239,10 @@ void amg_rap_compact(int nc, const int* toff, const int* tcol, const double* tva
 }
 void amg_rap_known(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,
                    const double* a, const int* pc, const double* pv, const int* crp, const int* cci, double* cval,
-                   int* err, int* big, hipStream_t s, const uint8_t* only, int* list) {
+                   int* err, int* big, hipStream_t s, const uint8_t* only, int* list, int kern) {
   if (!nc) return;
   rap_launch<kRapKnown>(nc, rrp, rci, rv, rp, ci, a, pc, pv, nullptr, nullptr, nullptr, nullptr, crp, cci, cval, err,
-                        only, big, s, list);
+                        only, big, s, list, kern);
 }
 static unsigned drap_blocks(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 void amg_drap_full(int nf, int nc, int maxc, const long long* tab, int G, long long ac_total, const int* rp,

@@ -63,16 +63,21 @@ void amg_identity_ops(int n, int* rrp, int* rci, double* rv, int* pc, double* pv
 // rows of P are then read once per fine row, not once per coarse row reaching
 // it) and R (AP) after
 constexpr int kApRowLen = 16;
+// The row-wise Galerkin product.  big: scratch of 2 (nc + 1) ints.  kern:
+// the kernel that takes the rows that fit it first (the wavefront kernel
+// alone, a thread per row with up to 16 or 32 columns, four lanes per row
+// with up to 32 or 64); the result is the same bit for bit either way.
+enum { kGalWave = 0, kGalThread16 = 1, kGalThread32 = 2, kGalQuad32 = 3, kGalQuad64 = 4 };
 void amg_rap_fused(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,
                    const double* a, const int* pc, const double* pv, const int* toff, int* tcnt, int* tcol,
-                   double* tval, int* err, int* big, hipStream_t s);
+                   double* tval, int* err, int* big, hipStream_t s, int kern = kGalWave);
 void amg_rap_compact(int nc, const int* toff, const int* tcol, const double* tval, const int* crp, int* cci,
                      double* cval, hipStream_t s);
 // list: scratch of nc + 1 ints; with `only`, large levels run the flagged rows
 // from a list on a fixed grid
 void amg_rap_known(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,
                    const double* a, const int* pc, const double* pv, const int* crp, const int* cci, double* cval,
-                   int* err, int* big, hipStream_t s, const uint8_t* only, int* list = nullptr);
+                   int* err, int* big, hipStream_t s, const uint8_t* only, int* list = nullptr, int kern = kGalWave);
 // Galerkin product of a small level through dense per-game blocks.  tab
 // holds four tables of G + 1 offsets: fine rows, coarse rows, AP entries
 // (sum of n_f * n_c over the games before) and coarse dense entries (sum of

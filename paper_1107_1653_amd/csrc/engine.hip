@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <climits>
 #include <exception>
 #include <map>
@@ -75,6 +76,27 @@ static bool profiling() {
     on = (e && e[0] == '1') ? 1 : 0;
   }
   return on == 1;
+}
+
+// First kernel of a row-wise Galerkin product whose rows are expected to
+// average `cols` distinct columns (the level's previous product, else an
+// estimate).  Products through P's four slots take four lanes per row (up
+// to 32 or 64 columns); products through an identity P (one slot) take a
+// thread per row (up to 16 or 32).  Rows beyond the kernel's columns go to
+// the wavefront kernel.  shapley_tune_galerkin forces the family; the
+// product is the same bit for bit whichever kernel computes a row.
+static std::atomic<int> g_gal_mode{-1};
+void set_forced_rap_cols(int mode) { g_gal_mode.store(mode); }
+static int gal_kernel(double cols, bool one_slot) {
+  const int mode = g_gal_mode.load();
+  if (mode == 0) return kGalWave;
+  const bool thread = mode == 1 || (mode == -1 && one_slot);
+  if (thread) {
+    if (mode == -1 && cols > 20.0) return kGalWave;
+    return cols <= 9.0 ? kGalThread16 : kGalThread32;
+  }
+  if (mode == -1 && cols > 44.0) return kGalWave;
+  return cols <= 18.0 ? kGalQuad32 : kGalQuad64;
 }
 
 struct PhaseTimer {
@@ -732,7 +754,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
             amg_identity_ops(n, L.id_rp.p, L.id_ci.p, L.id_rv.p, L.id_pc.p, L.id_pv.p, stream);
             s_cnt.ensure((size_t)n + 1);
             s_toff.ensure((size_t)n + 1);
-            s_big.ensure((size_t)n + 1);
+            s_big.ensure(2 * ((size_t)n + 1));
             const size_t tcap1 = std::max<size_t>(
                 1, std::min((size_t)PW * (size_t)std::max(L.nnz, 1), (size_t)n * (size_t)kRapMaxCols));
             check_offsets(tcap1);
@@ -741,8 +763,11 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
             amg_rap_bound(n, L.id_rp.p, L.id_ci.p, L.rp.p, s_cnt.p, PW, stream);
             scan_exclusive(s_cnt.p, s_toff.p, n + 1, stream, s_scan);
             probe_begin(kProbeRap, stream);
+            // A P rows: the previous product's average, else about A's
+            const double ap_cols = L.ap_nnz > 0 ? (double)L.ap_nnz / n : (double)L.nnz / n;
             amg_rap_fused(n, L.id_rp.p, L.id_ci.p, L.id_rv.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p,
-                          s_toff.p, s_cnt.p, s_tcol.p, s_tval.p, s_err.p + 1, s_big.p, stream);
+                          s_toff.p, s_cnt.p, s_tcol.p, s_tval.p, s_err.p + 1, s_big.p, stream,
+                          gal_kernel(ap_cols, false));
             probe_end(kProbeRap, stream, (double)L.nnz * 12 + (double)n * PW * 12);
             L.ap_rp.ensure((size_t)n + 1);
             scan_exclusive(s_cnt.p, L.ap_rp.p, n + 1, stream, s_scan);
@@ -767,12 +792,15 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
           check_offsets(tcap);
           s_tcol.ensure(tcap);
           s_tval.ensure(tcap);
-          s_big.ensure((size_t)std::max(n, nc) + 1);
+          s_big.ensure(2 * ((size_t)std::max(n, nc) + 1));
           amg_rap_bound(nc, L.rrp.p, L.rci.p, Arp, s_cnt.p, pwf, stream);
+          // coarse rows: the level's previous product, else about three
+          // times the fine rows' entries (grid stencils)
+          const double c_cols = (Ln.nnz > 0 && Ln.n == nc) ? (double)Ln.nnz / nc : 3.0 * L.nnz / n;
           scan_exclusive(s_cnt.p, s_toff.p, nc + 1, stream, s_scan);
           probe_begin(kProbeRap, stream);
           amg_rap_fused(nc, L.rrp.p, L.rci.p, L.rv64.p, Arp, Aci, Aa, Ppc, Ppv, s_toff.p, s_cnt.p, s_tcol.p,
-                        s_tval.p, s_err.p + 1, s_big.p, stream);
+                        s_tval.p, s_err.p + 1, s_big.p, stream, gal_kernel(c_cols, L.apf));
           probe_end(kProbeRap, stream, L.apf ? (double)L.ap_nnz * 12 + (double)nc * 8 : rap_bytes);
         }
         scan_exclusive(s_cnt.p, Ln.rp.p, nc + 1, stream, s_scan);
@@ -1016,23 +1044,26 @@ void Engine::refresh(const EngineOpts& o) {
         probe_end(kProbeRap, stream, (double)Ln.nnz * 12 + (double)L.nnz * 12 + (double)n * PW * 12);
       } else if (L.apf) {
         // A P rows of the changed fine rows, then the coarse rows they reach
-        s_big.ensure((size_t)std::max(n, L.nc) + 1);
+        s_big.ensure(2 * ((size_t)std::max(n, L.nc) + 1));
         probe_begin(kProbeRap, stream);
         s_list.ensure((size_t)n + 1);
         amg_rap_known(n, L.id_rp.p, L.id_ci.p, L.id_rv.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, L.ap_rp.p,
-                      L.ap_ci.p, L.ap_v.p, s_err.p + 1, s_big.p, stream, L.chg.p, s_list.p);
+                      L.ap_ci.p, L.ap_v.p, s_err.p + 1, s_big.p, stream, L.chg.p, s_list.p,
+                      gal_kernel((double)L.ap_nnz / std::max(n, 1), false));
         probe_end(kProbeRap, stream, (double)L.ap_nnz * 12 + (double)L.nnz * 12 + (double)n * PW * 12);
         probe_begin(kProbeRap, stream);
         s_list.ensure((size_t)L.nc + 1);
         amg_rap_known(L.nc, L.rrp.p, L.rci.p, L.rv64.p, L.ap_rp.p, L.ap_ci.p, L.ap_v.p, L.id_pc.p, L.id_pv.p,
-                      Ln.rp.p, Ln.ci.p, Ln.a64.p, s_err.p + 1, s_big.p, stream, Ln.chg.p, s_list.p);
+                      Ln.rp.p, Ln.ci.p, Ln.a64.p, s_err.p + 1, s_big.p, stream, Ln.chg.p, s_list.p,
+                      gal_kernel((double)Ln.nnz / std::max(L.nc, 1), true));
         probe_end(kProbeRap, stream, (double)Ln.nnz * 12 + (double)L.ap_nnz * 12);
       } else {
-        s_big.ensure((size_t)L.nc + 1);
+        s_big.ensure(2 * ((size_t)L.nc + 1));
         s_list.ensure((size_t)L.nc + 1);
         probe_begin(kProbeRap, stream);
         amg_rap_known(L.nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, Ln.rp.p,
-                      Ln.ci.p, Ln.a64.p, s_err.p + 1, s_big.p, stream, Ln.chg.p, s_list.p);
+                      Ln.ci.p, Ln.a64.p, s_err.p + 1, s_big.p, stream, Ln.chg.p, s_list.p,
+                      gal_kernel((double)Ln.nnz / std::max(L.nc, 1), false));
         probe_end(kProbeRap, stream, (double)Ln.nnz * 12 + (double)L.nnz * 12 + (double)n * PW * 12);
       }
     }

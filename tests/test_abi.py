@@ -78,6 +78,11 @@ def test_lane_control_arguments():
             P.shapley_tune_lanes(bad)
     for ok in (1, 2, 4, 0):
         P.shapley_tune_lanes(ok)
+    for bad in (2, 8, 32, -2):
+        with pytest.raises(P.ShapleyError):
+            P.shapley_tune_galerkin(bad)
+    for ok in (0, 1, 4, -1):
+        P.shapley_tune_galerkin(ok)
 
 
 def test_bench_refuses_more_than_one_gpu():
