@@ -1008,25 +1008,33 @@ __device__ inline void wave_sort64(int& key) {
   }
 }
 
-// rows of R = P^T sorted by column, one wavefront per row (rows longer than
-// a wavefront, rare, by one lane)
-__global__ __launch_bounds__(256) void k_sort_rows_wave(const int* __restrict__ rp, int* __restrict__ ci,
-                                                        double* __restrict__ v, int n) {
-  const int I = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (I >= n) return;  // uniform per wavefront
+// rows of R = P^T sorted by column, 16 lanes per row: a row of up to 64
+// entries is staged in LDS and each entry written at its rank (the columns
+// of a row are distinct); longer rows, rare, by one lane
+__global__ __launch_bounds__(256) void k_sort_rows_seg(const int* __restrict__ rp, int* __restrict__ ci,
+                                                       double* __restrict__ v, int n) {
+  __shared__ int sk[16][64];
+  __shared__ double sv[16][64];
+  const int seg = threadIdx.x >> 4, l = threadIdx.x & 15;
+  const int I = blockIdx.x * 16 + seg;
+  if (I >= n) return;  // nothing below synchronises the workgroup
   const int e0 = rp[I], len = rp[I + 1] - e0;
   if (len <= 64) {
-    int key = lane < len ? ci[e0 + lane] : INT_MAX;
-    double val = lane < len ? v[e0 + lane] : 0.0;
-    wave_sort64(key, val);
-    if (lane < len) {
-      ci[e0 + lane] = key;
-      v[e0 + lane] = val;
+    for (int j = l; j < len; j += 16) {
+      sk[seg][j] = ci[e0 + j];
+      sv[seg][j] = v[e0 + j];
+    }
+    wave_lds_sync();
+    for (int j = l; j < len; j += 16) {
+      const int key = sk[seg][j];
+      int r = 0;
+      for (int t = 0; t < len; ++t) r += sk[seg][t] < key ? 1 : 0;
+      ci[e0 + r] = key;
+      v[e0 + r] = sv[seg][j];
     }
     return;
   }
-  if (lane != 0) return;
+  if (l != 0) return;
   for (int e = e0 + 1; e < e0 + len; ++e) {
     const int c = ci[e];
     const double x = v[e];
@@ -2098,15 +2106,15 @@ __global__ __launch_bounds__(256) void k_rap_quad(int nc, const int* __restrict_
   append_rows(!ok && q == 0, I, mid);
 }
 
-// rows of the scratch area into the final CSR (one wavefront per row)
-__global__ __launch_bounds__(64) void k_rap_compact(int nc, const int* __restrict__ toff,
-                                                    const int* __restrict__ tcol, const double* __restrict__ tval,
-                                                    const int* __restrict__ crp, int* __restrict__ cci,
-                                                    double* __restrict__ cval) {
-  const int I = blockIdx.x;
+// rows of the scratch area into the final CSR (eight lanes per row)
+__global__ __launch_bounds__(256) void k_rap_compact(int nc, const int* __restrict__ toff,
+                                                     const int* __restrict__ tcol, const double* __restrict__ tval,
+                                                     const int* __restrict__ crp, int* __restrict__ cci,
+                                                     double* __restrict__ cval) {
+  const int I = blockIdx.x * 32 + (int)(threadIdx.x >> 3);
   if (I >= nc) return;
   const int o = toff[I], base = crp[I], nd = crp[I + 1] - base;
-  for (int h = threadIdx.x; h < nd; h += 64) {
+  for (int h = threadIdx.x & 7; h < nd; h += 8) {
     cci[base + h] = tcol[o + h];
     cval[base + h] = tval[o + h];
   }
@@ -3110,7 +3118,7 @@ void amg_pt_fill(const Tile* t, int nt, const int* pc, const double* pv, const i
 }
 void amg_sort_rows(const int* rp, int* ci, double* v, int n, hipStream_t s) {
   if (!n) return;
-  hipLaunchKernelGGL(k_sort_rows_wave, dim3((n + 3) / 4), dim3(256), 0, s, rp, ci, v, n);
+  hipLaunchKernelGGL(k_sort_rows_seg, dim3((n + 15) / 16), dim3(256), 0, s, rp, ci, v, n);
   SHP_LAUNCH_CHECK();
 }
 void amg_rap_bound(int nc, const int* rrp, const int* rci, const int* rp, int* ub, int pw, hipStream_t s) {
@@ -3139,19 +3147,41 @@ void amg_identity_ops(int n, int* rrp, int* rci, double* rv, int* pc, double* pv
   SHP_LAUNCH_CHECK();
 }
 // rows whose flag is set, appended to list (order free: each row's result
-// does not depend on it); *count = their number (zero before the launch)
-__global__ void k_flag_list(const uint8_t* __restrict__ flags, int n, int* __restrict__ list, int* __restrict__ count) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool f = i < n && flags[i] != 0;
-  const unsigned long long m = __ballot(f);
-  if (!m) return;
-  const int lane = threadIdx.x & 63;
-  const int leader = __ffsll((long long)m) - 1;
-  int base = 0;
-  if (lane == leader) base = atomicAdd(count, __popcll(m));
-  base = __shfl(base, leader);
-  if (f) list[base + __popcll(m & ((1ull << lane) - 1ull))] = i;
+// does not depend on it); *count = their number (zero before the launch).
+// Each thread looks at kFlagPer rows; one atomic per workgroup.
+constexpr int kFlagPer = 4;
+__global__ __launch_bounds__(kBlock) void k_flag_list(const uint8_t* __restrict__ flags, int n, int* __restrict__ list,
+                                                      int* __restrict__ count) {
+  __shared__ int s_w[kBlock / 64];
+  __shared__ int s_base;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i0 = (blockIdx.x * kBlock + threadIdx.x) * kFlagPer;
+  int mine = 0;
+#pragma unroll
+  for (int u = 0; u < kFlagPer; ++u) mine += (i0 + u < n && flags[i0 + u] != 0) ? 1 : 0;
+  int incl = mine;  // wavefront scan of the counts
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) s_w[w] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int k = 0; k < kBlock / 64; ++k) {
+      const int c = s_w[k];
+      s_w[k] = tot;
+      tot += c;
+    }
+    s_base = tot ? atomicAdd(count, tot) : 0;
+  }
+  __syncthreads();
+  int at = s_base + s_w[w] + incl - mine;
+#pragma unroll
+  for (int u = 0; u < kFlagPer; ++u)
+    if (i0 + u < n && flags[i0 + u] != 0) list[at++] = i0 + u;
 }
+static unsigned flag_blocks(int n) { return (unsigned)((n + kBlock * kFlagPer - 1) / (kBlock * kFlagPer)); }
 constexpr int kRapListBlocks = 2048;  // grid of a refresh over a list of rows
 
 // Levels with few coarse rows (long rows): one workgroup of 256 lanes per
@@ -3183,18 +3213,16 @@ static void rap_launch(int nc, const int* rrp, const int* rci, const double* rv,
     return;
   }
   int* mid = big + nc + 1;  // rows handed from the first kernel to the wavefront kernel
-  fill_async(big, 0, 1, s);
   const bool refresh = only && list;
+  zero_counters_async(s, big, kern != kGalWave ? mid : nullptr, refresh ? list : nullptr);
   if (refresh) {
     // a refresh: the flagged rows into a list, then a fixed grid over it (a
     // grid over every coarse row costs as much as the work when few changed)
-    fill_async(list, 0, 1, s);
-    hipLaunchKernelGGL(k_flag_list, dim3(grid_for(nc)), dim3(kBlock), 0, s, only, nc, list + 1, list);
+    hipLaunchKernelGGL(k_flag_list, dim3(flag_blocks(nc)), dim3(kBlock), 0, s, only, nc, list + 1, list);
     SHP_LAUNCH_CHECK();
   }
   const unsigned wblocks = (unsigned)std::min<int>((nc + 3) / 4, kRapListBlocks);
   if (kern != kGalWave) {
-    fill_async(mid, 0, 1, s);
     const int* tl = refresh ? (const int*)(list + 1) : nullptr;
     const int* tn = refresh ? (const int*)list : nullptr;
     const bool quad = kern == kGalQuad32 || kern == kGalQuad64;
@@ -3234,7 +3262,7 @@ void amg_rap_fused(int nc, const int* rrp, const int* rci, const double* rv, con
 void amg_rap_compact(int nc, const int* toff, const int* tcol, const double* tval, const int* crp, int* cci,
                      double* cval, hipStream_t s) {
   if (!nc) return;
-  hipLaunchKernelGGL(k_rap_compact, dim3(nc), dim3(64), 0, s, nc, toff, tcol, tval, crp, cci, cval);
+  hipLaunchKernelGGL(k_rap_compact, dim3((nc + 31) / 32), dim3(256), 0, s, nc, toff, tcol, tval, crp, cci, cval);
   SHP_LAUNCH_CHECK();
 }
 void amg_rap_known(int nc, const int* rrp, const int* rci, const double* rv, const int* rp, const int* ci,

@@ -127,6 +127,20 @@ __global__ void k_fill(T* __restrict__ p, T v, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
+// up to four counters set to zero by one launch (null pointers skipped)
+template <class T>
+__global__ void k_zero4(T* a, T* b, T* c, T* d) {
+  if (threadIdx.x == 0) {
+    if (a) *a = 0;
+    if (b) *b = 0;
+    if (c) *c = 0;
+    if (d) *d = 0;
+  }
+}
+inline void zero_counters_async(hipStream_t s, int* a, int* b = nullptr, int* c = nullptr, int* d = nullptr) {
+  hipLaunchKernelGGL(k_zero4<int>, dim3(1), dim3(64), 0, s, a, b, c, d);
+  SHP_LAUNCH_CHECK();
+}
 template <class T>
 inline void fill_async(T* p, T v, size_t n, hipStream_t s) {
   if (n == 0) return;

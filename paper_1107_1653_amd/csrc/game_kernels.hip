@@ -259,6 +259,13 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
   const int row = row0 + tid;
   const int e0 = mine ? d.rp[row] : 0, e1 = mine ? d.rp[row + 1] : 0;
   const int eb = d.rp[row0], ee = d.rp[row0 + ns * K];
+  // loads that do not depend on the products, issued before the stages
+  const double rr = mine ? d.r[row] : 0.0;
+  const bool ok = mine && (d.valid ? (d.valid[row] != 0) : true);
+  const bool owner = tid < ns;
+  const int al = owner && d.alpha ? d.alpha[t.s0 + tid] : -1;  // no incumbents: the greedy choice
+  const int be = owner && d.beta ? d.beta[t.s0 + tid] : -1;
+  const double vx = owner ? d.v[t.s0 + tid] : 0.0;
   double acc = 0.0, sacc = 0.0;
   for (int c0 = eb; c0 < ee; c0 += kImpStage) {
     const int c1 = ee < c0 + kImpStage ? ee : c0 + kImpStage;
@@ -287,8 +294,6 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
     __syncthreads();
   }
   if (mine) {
-    bool ok = d.valid ? (d.valid[row] != 0) : true;
-    double rr = d.r[row];
     sq[tid] = rr + d.mu * acc;
     ss[tid] = fabs(rr) + d.mu * sacc;
     sv[tid] = ok ? 1 : 0;
@@ -296,11 +301,9 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
   __syncthreads();
   double res = 0.0, res2 = 0.0;
   int chg_in = 0, chg_out = 0;
-  if (tid < ns) {
+  if (owner) {
     const int x = t.s0 + tid;
     const int base = tid * K;
-    const int al = d.alpha ? d.alpha[x] : -1;  // no incumbents: the greedy choice
-    const int be = d.beta ? d.beta[x] : -1;
     // MIN at the incumbent alpha
     int bin = -1;
     if (al >= 0) {
@@ -359,7 +362,7 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
     d.alpha_c[x] = ac;
     d.beta_c[x] = bc;
     if (d.F) d.F[x] = F;  // stored only when asked for
-    double dv = F - d.v[x];
+    double dv = F - vx;
     res = dv == dv ? fabs(dv) : INFINITY;
     res2 = dv * dv;
     chg_in = (bin != be) ? 1 : 0;
