@@ -289,6 +289,15 @@ int shapley_tune_lanes(int32_t lanes);
  * value. */
 int shapley_tune_galerkin(int32_t kernel);
 
+/* Kernel choice of the extended+i interpolation of coarse levels (the
+ * prolongation P of Sec. 4.3): -1 (default) or 4 first runs a four-lanes-per-
+ * row kernel that takes the rows whose sets fit it and hands the others to
+ * the wavefront-per-row kernel; 0 forces the wavefront kernel alone.  Both
+ * form every weight with the same operations in the same order, so results
+ * do not depend on this setting.  Process-wide; applies to later setups.
+ * Errors: SHAPLEY_EINVAL for any other value. */
+int shapley_tune_interp(int32_t kernel);
+
 /* Inspection of the algebraic multigrid hierarchy (Sec. 4.3) built by the
  * last shapley_solve of g, run alone on the handle's own stream (opts.stream
  * NULL; for a hierarchy handle, the finest grid's).  Level 0 is the operator

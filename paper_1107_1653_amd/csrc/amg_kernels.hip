@@ -84,8 +84,9 @@ __global__ __launch_bounds__(256) void k_strength_w(const Tile* __restrict__ til
                                                     const int* __restrict__ ci, const double* __restrict__ a,
                                                     const uint8_t* __restrict__ dir, double theta,
                                                     uint8_t* __restrict__ strong, int* __restrict__ lam) {
-  const Tile t = tiles[blockIdx.x / (kTileRows / 4)];
-  const int i = t.r0 + (int)(blockIdx.x % (kTileRows / 4)) * 4 + (int)(threadIdx.x >> 6);
+  const unsigned bid = blockIdx.x;
+  const Tile t = tiles[bid / (kTileRows / 4)];
+  const int i = t.r0 + (int)(bid % (kTileRows / 4)) * 4 + (int)(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= t.r1) return;  // per wavefront
   const int e0 = rp[i], e1 = rp[i + 1];
@@ -111,8 +112,9 @@ __global__ __launch_bounds__(256) void k_strength_t_w(const Tile* __restrict__ t
                                                       const int* __restrict__ ci, const uint8_t* __restrict__ strong,
                                                       const int* __restrict__ st_rp, int* __restrict__ cursor,
                                                       int* __restrict__ st_ci) {
-  const Tile t = tiles[blockIdx.x / (kTileRows / 4)];
-  const int i = t.r0 + (int)(blockIdx.x % (kTileRows / 4)) * 4 + (int)(threadIdx.x >> 6);
+  const unsigned bid = blockIdx.x;
+  const Tile t = tiles[bid / (kTileRows / 4)];
+  const int i = t.r0 + (int)(bid % (kTileRows / 4)) * 4 + (int)(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= t.r1) return;
   for (int e = rp[i] + lane; e < rp[i + 1]; e += 64)
@@ -195,7 +197,7 @@ __global__ void k_pmis_select(const Tile* __restrict__ tiles, const int* __restr
     if (round > 0 && left[(round - 1) & 1] == 0) atomicMin(&left[2], round);  // first round with nothing to do
   }
   if (round > 0 && left[(round - 1) & 1] == 0) return;
-  Tile t = tiles[blockIdx.x];
+  Tile t = tiles[xcd_block()];
   int i = t.r0 + threadIdx.x;
   if (i >= t.r1) return;
   newc[i] = pmis_select_row(i, rp, ci, strong, st_rp, st_ci, cf, key);
@@ -207,7 +209,7 @@ __global__ void k_pmis_update(const Tile* __restrict__ tiles, const int* __restr
                               int8_t* __restrict__ cf, const int* __restrict__ newc,
                               int* __restrict__ left, int round) {
   if (round > 0 && left[(round - 1) & 1] == 0) return;
-  Tile t = tiles[blockIdx.x];
+  Tile t = tiles[xcd_block()];
   int i = t.r0 + threadIdx.x;
   int und = 0;
   if (i < t.r1) und = pmis_update_row(i, rp, ci, strong, cf, newc);
@@ -228,8 +230,9 @@ __global__ __launch_bounds__(256) void k_pmis_select_w(const Tile* __restrict__ 
     if (round > 0 && left[(round - 1) & 1] == 0) atomicMin(&left[2], round);
   }
   if (round > 0 && left[(round - 1) & 1] == 0) return;
-  const Tile t = tiles[blockIdx.x / (kTileRows / 4)];
-  const int i = t.r0 + (int)(blockIdx.x % (kTileRows / 4)) * 4 + (int)(threadIdx.x >> 6);
+  const unsigned bid = xcd_block();
+  const Tile t = tiles[bid / (kTileRows / 4)];
+  const int i = t.r0 + (int)(bid % (kTileRows / 4)) * 4 + (int)(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= t.r1) return;  // per wavefront
   if (cf[i] != CF_U) {
@@ -256,8 +259,9 @@ __global__ __launch_bounds__(256) void k_pmis_update_w(const Tile* __restrict__ 
                                                        int8_t* __restrict__ cf, const int* __restrict__ newc,
                                                        int* __restrict__ left, int round) {
   if (round > 0 && left[(round - 1) & 1] == 0) return;
-  const Tile t = tiles[blockIdx.x / (kTileRows / 4)];
-  const int i = t.r0 + (int)(blockIdx.x % (kTileRows / 4)) * 4 + (int)(threadIdx.x >> 6);
+  const unsigned bid = xcd_block();
+  const Tile t = tiles[bid / (kTileRows / 4)];
+  const int i = t.r0 + (int)(bid % (kTileRows / 4)) * 4 + (int)(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= t.r1) return;
   if (newc[i]) {
@@ -502,8 +506,9 @@ __global__ __launch_bounds__(kIThreads) void k_interp_lds(const Tile* __restrict
                                                           int* __restrict__ defer) {
   __shared__ int lc[CAP * kIThreads];
   __shared__ double lw[CAP * kIThreads];
-  const Tile t = tiles[blockIdx.x / (kTileRows / kIThreads)];
-  const int sub = blockIdx.x % (kTileRows / kIThreads);
+  const unsigned bid = xcd_block();
+  const Tile t = tiles[bid / (kTileRows / kIThreads)];
+  const int sub = bid % (kTileRows / kIThreads);
   const int i = t.r0 + sub * kIThreads + (int)threadIdx.x;
   if (i >= t.r1) return;
   interp_lds_row<CAP, DEFER>(i, lc + threadIdx.x, lw + threadIdx.x, rp, ci, a, dinv, strong, cf, cidx, dir, pc, pv,
@@ -900,25 +905,28 @@ __global__ __launch_bounds__(64) void k_interp_wave(const Tile* __restrict__ til
                                                     const uint8_t* __restrict__ dir, int* __restrict__ pc,
                                                     double* __restrict__ pv, int* __restrict__ capped,
                                                     int* __restrict__ defer) {
-  const Tile t = tiles[blockIdx.x / kTileRows];
-  const int i = t.r0 + (int)(blockIdx.x % kTileRows);
+  const unsigned bid = xcd_block();
+  const Tile t = tiles[bid / kTileRows];
+  const int i = t.r0 + (int)(bid % kTileRows);
   if (i >= t.r1) return;
   interp_row<kIwHash, kIwK, STAGE, DEFER>(i, rp, ci, a, dinv, strong, cf, cidx, dir, pc, pv, capped, defer);
 }
 
-// the rows deferred by the smaller instance, one wavefront each in turn
-template <int kIwHash, int kIwK>
+// the rows of a list (rows deferred by a smaller kernel), one wavefront each
+// in turn; with DEFER, rows this instance cannot hold go on to defer[1 ..]
+template <int kIwHash, int kIwK, bool DEFER>
 __global__ __launch_bounds__(64) void k_interp_wave_list(const int* __restrict__ list, const int* __restrict__ rp,
                                                          const int* __restrict__ ci, const double* __restrict__ a,
                                                          const double* __restrict__ dinv,
                                                          const uint8_t* __restrict__ strong,
                                                          const int8_t* __restrict__ cf, const int* __restrict__ cidx,
                                                          const uint8_t* __restrict__ dir, int* __restrict__ pc,
-                                                         double* __restrict__ pv, int* __restrict__ capped) {
+                                                         double* __restrict__ pv, int* __restrict__ capped,
+                                                         int* __restrict__ defer) {
   const int cnt = list[0];
   for (int k = blockIdx.x; k < cnt; k += gridDim.x) {
-    interp_row<kIwHash, kIwK, 256, false>(list[1 + k], rp, ci, a, dinv, strong, cf, cidx, dir, pc, pv, capped,
-                                          nullptr);
+    interp_row<kIwHash, kIwK, 256, DEFER>(list[1 + k], rp, ci, a, dinv, strong, cf, cidx, dir, pc, pv, capped,
+                                          defer);
     __syncthreads();  // the next row reuses the LDS
   }
 }
@@ -1782,7 +1790,7 @@ __global__ __launch_bounds__(256) void k_rap_small(int nc, const int* __restrict
     }
     return;
   }
-  const int I = blockIdx.x * 4 + w;
+  const int I = (int)xcd_block() * 4 + w;
   if (I >= nc) return;
   if (only && !only[I]) return;
   rap_small_row<MODE>(I, lane, rrp, rci, rv, rp, ci, a, pc, pv, toff, tcnt, tcol, tval, crp, cci, cval, big,
@@ -1907,7 +1915,7 @@ __global__ __launch_bounds__(64) void k_rap_thr(int nc, const int* __restrict__ 
     }
     return;
   }
-  const int I = blockIdx.x * 64 + lane;
+  const int I = (int)xcd_block() * 64 + lane;
   if (I >= nc) return;
   bool ok = true;
   if (!only || only[I])
@@ -2097,13 +2105,365 @@ __global__ __launch_bounds__(256) void k_rap_quad(int nc, const int* __restrict_
     }
     return;
   }
-  const int I = blockIdx.x * 64 + grp;
+  const int I = (int)xcd_block() * 64 + grp;
   if (I >= nc) return;
   bool ok = true;
   if (!only || only[I])
     ok = rap_quad_row<MODE, NC>(I, q, rrp, rci, rv, rp, ci, a, pc, pv, toff, tcnt, tcol, tval, crp, cci, cval, col,
                                 acc);
   append_rows(!ok && q == 0, I, mid);
+}
+
+// ---------------------------------------------------------------------------
+// extended+i interpolation of coarse levels, four lanes per row (16 rows per
+// wavefront): the formula and every sum of the wavefront kernel above, in the
+// same orders, so a row gives the same weights bit for bit whichever of the
+// two computes it.  The set is collected in a per-row LDS hash, ranked by
+// fine index and searched by bisection; den_k takes its terms in row k's
+// entry order; a member's weight takes its direct entry, then the distributed
+// entries in the order of the F neighbours; the lumped diagonal and the
+// total are the wavefront's butterfly over 64 lane slots (slot s of the
+// butterfly held by lane s mod 4 of the group: its steps 32 ... 4 inside a
+// lane, 2 and 1 across the group).  Rows longer than 64 entries, with more
+// than 16 strong F neighbours or 32 set members, go to the wavefront kernel.
+// ---------------------------------------------------------------------------
+constexpr int kIqMem = 32, kIqHash = 64, kIqK = 16, kIqLen = 64;
+struct IqGroup {
+  int hs[kIqHash];  // the set's hash, later the members' weights (kIqMem doubles)
+  int mem[kIqMem];
+  int kcol[kIqK], kbeg[kIqK], kend[kIqK], kneg[kIqK];
+  double kaik[kIqK], kden[kIqK], kabi[kIqK];
+};
+static_assert(kIqHash * sizeof(int) >= kIqMem * sizeof(double), "weights must fit in the hash space");
+
+__device__ __forceinline__ unsigned group_ballot(bool b, int gbase) {
+  return (unsigned)(__ballot(b) >> gbase) & 0xFu;
+}
+
+__device__ __forceinline__ bool iq_insert(int* hs, int v) {
+  unsigned h = mix32((uint32_t)v) & (kIqHash - 1);
+  for (int pr = 0; pr < kIqHash; ++pr) {
+    const int old = atomicCAS(&hs[h], -1, v);
+    if (old == -1 || old == v) return true;
+    h = (h + 1) & (kIqHash - 1);
+  }
+  return false;
+}
+
+// position of v among the m sorted members, or -1
+__device__ __forceinline__ int iq_find(const int* mem, int m, int v) {
+  int pos = 0;
+#pragma unroll
+  for (int step = kIqMem; step > 0; step >>= 1)
+    if (pos + step <= m && mem[pos + step - 1] < v) pos += step;
+  return (pos < m && mem[pos] == v) ? pos : -1;
+}
+
+// the wavefront butterfly sum (xor 32, 16, ..., 1) of 64 slot values; lane q
+// of the group holds slots q + 4u in v[u].  Every pair of the butterfly adds
+// the same two values, so all lanes end with one result.
+__device__ __forceinline__ double iq_tree(double (&v)[16], int q, int gbase) {
+#pragma unroll
+  for (int b = 8; b >= 1; b >>= 1) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      if (u & b) continue;
+      const double t = v[u] + v[u | b];
+      v[u] = t;
+      v[u | b] = t;
+    }
+  }
+  double x = v[0];
+  x = x + __shfl(x, gbase | (q ^ 2));
+  x = x + __shfl(x, gbase | (q ^ 1));
+  return x;
+}
+
+__device__ __forceinline__ bool interp_quad_row(int i, int q, int gbase, IqGroup& G, const int* __restrict__ rp,
+                                                const int* __restrict__ ci, const double* __restrict__ a,
+                                                const double* __restrict__ dinv, const uint8_t* __restrict__ strong,
+                                                const int8_t* __restrict__ cf, const int* __restrict__ cidx,
+                                                const uint8_t* __restrict__ dir, int* __restrict__ pc,
+                                                double* __restrict__ pv) {
+#pragma clang fp contract(off)
+  const unsigned below = (1u << q) - 1u;
+  if (q < PW) {
+    pc[(size_t)i * PW + q] = -1;
+    pv[(size_t)i * PW + q] = 0.0;
+  }
+  if (cf[i] == CF_C) {
+    if (q == 0) {
+      pc[(size_t)i * PW] = cidx[i];
+      pv[(size_t)i * PW] = 1.0;
+    }
+    return true;
+  }
+  if (dir[i]) return true;
+  const int e0 = rp[i], len = rp[i + 1] - e0;
+  if (len > kIqLen) return false;
+  // ---- row i: strong C neighbours into the set, strong F neighbours listed in row order
+  for (int h = q; h < kIqHash; h += 4) G.hs[h] = -1;
+  wave_lds_sync();
+  int nK = 0;
+  bool full = false;
+  for (int base = 0; base < len; base += 4) {
+    const int t = base + q;
+    const bool in = t < len;
+    int j = -1;
+    bool st = false;
+    double aij = 0.0;
+    if (in) {
+      j = ci[e0 + t];
+      st = strong[e0 + t] != 0;
+      aij = a[e0 + t];
+    }
+    const bool off = in && st && j != i;
+    const int8_t cj = off ? cf[j] : (int8_t)0;
+    if (off && cj == CF_C && !iq_insert(G.hs, j)) full = true;
+    const bool isF = off && cj == CF_F;
+    const unsigned m4 = group_ballot(isF, gbase);
+    const int pos = nK + __popc(m4 & below);
+    if (isF && pos < kIqK) {
+      G.kcol[pos] = j;
+      G.kaik[pos] = aij;
+    }
+    nK += __popc(m4);
+  }
+  if (group_ballot(full, gbase) || nK > kIqK) return false;
+  wave_lds_sync();
+  for (int p = q; p < nK; p += 4) {
+    const int k = G.kcol[p];
+    G.kbeg[p] = rp[k];
+    G.kend[p] = rp[k + 1];
+    G.kneg[p] = dinv[k] < 0.0 ? 1 : 0;
+  }
+  wave_lds_sync();
+  // ---- distance-two candidates: strong C neighbours of the strong F neighbours
+  for (int p = 0; p < nK; ++p) {
+    const int k = G.kcol[p], en = G.kend[p];
+    for (int e2 = G.kbeg[p] + q; e2 < en; e2 += 4) {
+      const int l = ci[e2];
+      if (strong[e2] && l != k && cf[l] == CF_C && !iq_insert(G.hs, l)) full = true;
+    }
+  }
+  if (group_ballot(full, gbase)) return false;
+  wave_lds_sync();
+  // ---- members: the occupied slots compacted, then each to its rank
+  int m = 0;
+  for (int h0 = 0; h0 < kIqHash; h0 += 4) {
+    const int key = G.hs[h0 + q];
+    const unsigned m4 = group_ballot(key >= 0, gbase);
+    const int at = m + __popc(m4 & below);
+    if (key >= 0 && at < kIqMem) G.mem[at] = key;
+    m += __popc(m4);
+  }
+  if (m > kIqMem) return false;
+  wave_lds_sync();
+  {
+    int key[kIqMem / 4], rank[kIqMem / 4];
+#pragma unroll
+    for (int u = 0; u < kIqMem / 4; ++u) {
+      const int j = q + 4 * u;
+      key[u] = j < m ? G.mem[j] : INT_MAX;
+      rank[u] = 0;
+    }
+    for (int t = 0; t < m; ++t) {
+      const int c = G.mem[t];
+#pragma unroll
+      for (int u = 0; u < kIqMem / 4; ++u) rank[u] += c < key[u] ? 1 : 0;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int u = 0; u < kIqMem / 4; ++u)
+      if (q + 4 * u < m) G.mem[rank[u]] = key[u];
+  }
+  double* W = reinterpret_cast<double*>(G.hs);  // the hash is dead
+  wave_lds_sync();
+  for (int h = q; h < m; h += 4) W[h] = 0.0;
+  // ---- den_k and abar_ki: row k's terms in entry order (every lane forms the same sum)
+  for (int p = 0; p < nK; ++p) {
+    const int k = G.kcol[p], en = G.kend[p];
+    const bool neg = G.kneg[p] != 0;
+    double d = 0.0, abi = 0.0;
+    bool has_i = false;
+    for (int c0 = G.kbeg[p]; c0 < en; c0 += 4) {
+      const int e2 = c0 + q;
+      double term = 0.0;
+      if (e2 < en) {
+        const int l = ci[e2];
+        const double akl = a[e2];
+        const double abar = neg ? (akl > 0.0 ? akl : 0.0) : (akl < 0.0 ? akl : 0.0);
+        if (l != k && abar != 0.0) {
+          if (l == i) {
+            term = abar;
+            abi = abar;
+            has_i = true;
+          } else if (iq_find(G.mem, m, l) >= 0) {
+            term = abar;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) d = d + __shfl(term, gbase | u);
+    }
+    const unsigned hi = group_ballot(has_i, gbase);
+    abi = hi ? __shfl(abi, gbase | (__ffs(hi) - 1)) : 0.0;
+    if (q == 0) {
+      G.kden[p] = d;
+      G.kabi[p] = abi;
+    }
+  }
+  wave_lds_sync();
+  // ---- diagonal: a_ii, weak entries, parts of F neighbours sent back to i;
+  //      direct entries towards set members (slot t of the butterfly = entry t)
+  double v[16];
+  int rankF = 0;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    v[u] = 0.0;
+    const int t = 4 * u + q;
+    if (4 * u >= len) continue;  // the same for the whole group
+    const bool in = t < len;
+    int j = -1;
+    bool st = false;
+    double aij = 0.0;
+    if (in) {
+      j = ci[e0 + t];
+      st = strong[e0 + t] != 0;
+      aij = a[e0 + t];
+    }
+    const bool off = in && j != i;
+    const int8_t cj = off ? cf[j] : (int8_t)0;
+    const bool isF = off && st && cj == CF_F;
+    const unsigned m4 = group_ballot(isF, gbase);
+    const int p = rankF + __popc(m4 & below);
+    rankF += __popc(m4);
+    double c = 0.0;
+    if (in && j == i) {
+      c = aij;
+    } else if (off && aij != 0.0) {
+      const int qq = iq_find(G.mem, m, j);
+      if (qq >= 0) {
+        W[qq] = W[qq] + aij;  // one entry per column: no conflicts
+      } else if (isF) {
+        const double den = G.kden[p];
+        c = den == 0.0 ? aij : aij * G.kabi[p] / den;
+      } else if (!dir[j]) {
+        c = aij;
+      }
+    }
+    v[u] = 0.0 + c;
+  }
+  wave_lds_sync();
+  // ---- distributed entries: F neighbours in row order; each row k holds a
+  //      column at most once, so the lanes of one k never collide
+  for (int p = 0; p < nK; ++p) {
+    const int k = G.kcol[p], en = G.kend[p];
+    const bool neg = G.kneg[p] != 0;
+    const double den = G.kden[p], aik = G.kaik[p];
+    if (den != 0.0) {
+      for (int e2 = G.kbeg[p] + q; e2 < en; e2 += 4) {
+        const int l = ci[e2];
+        const double akl = a[e2];
+        const double abar = neg ? (akl > 0.0 ? akl : 0.0) : (akl < 0.0 ? akl : 0.0);
+        if (l == k || l == i || abar == 0.0) continue;
+        const int qq = iq_find(G.mem, m, l);
+        if (qq >= 0) W[qq] = W[qq] + aik * abar / den;
+      }
+    }
+    wave_lds_sync();
+  }
+  const double dd = iq_tree(v, q, gbase);
+  if (dd == 0.0 || m == 0) return true;
+  // ---- weights, their total, the PW largest (lowest member on ties)
+  double vt[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int s = 4 * u + q;
+    double w = 0.0;
+    if (s < m) {
+      w = -W[s] / dd;
+      W[s] = w;
+    }
+    vt[u] = 0.0 + w;
+  }
+  const double total = iq_tree(vt, q, gbase);
+  wave_lds_sync();
+  int kq[PW];
+  double kw[PW];
+  int nk = 0;
+#pragma unroll
+  for (int r = 0; r < PW; ++r) {
+    kq[r] = INT_MAX;
+    kw[r] = 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < PW; ++r) {
+    if (nk == r) {
+      double bw = 0.0;
+      int bq = INT_MAX;
+      for (int s = q; s < m; s += 4) {
+        bool used = false;
+#pragma unroll
+        for (int u = 0; u < r; ++u) used |= kq[u] == s;
+        const double aw = fabs(W[s]);
+        if (!used && (aw > bw || (aw == bw && aw > 0.0 && s < bq))) {
+          bw = aw;
+          bq = s;
+        }
+      }
+#pragma unroll
+      for (int o = 2; o >= 1; o >>= 1) {
+        const double ow = __shfl(bw, gbase | (q ^ o));
+        const int oq = __shfl(bq, gbase | (q ^ o));
+        if (ow > bw || (ow == bw && oq < bq)) {
+          bw = ow;
+          bq = oq;
+        }
+      }
+      if (bq != INT_MAX && bw != 0.0) {
+        kq[r] = bq;
+        kw[r] = W[bq];
+        nk = r + 1;
+      }
+    }
+  }
+  if (q == 0 && nk > 0) {
+    double kept = 0.0;
+#pragma unroll
+    for (int u = 0; u < PW; ++u)
+      if (u < nk) kept += kw[u];
+    const double scl = kept != 0.0 ? total / kept : 1.0;
+#pragma unroll
+    for (int u = 0; u < PW; ++u) {
+      if (u >= nk) continue;
+      int r = 0;
+#pragma unroll
+      for (int w2 = 0; w2 < PW; ++w2) r += (w2 < nk && kq[w2] < kq[u]) ? 1 : 0;
+      pc[(size_t)i * PW + r] = cidx[G.mem[kq[u]]];
+      pv[(size_t)i * PW + r] = kw[u] * scl;
+    }
+  }
+  return true;
+}
+
+// 16 rows of a tile per workgroup of one wavefront; rows that do not fit are
+// appended to defer[1 ..] for the wavefront kernel
+__global__ __launch_bounds__(64) void k_interp_quad(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                                                    const int* __restrict__ ci, const double* __restrict__ a,
+                                                    const double* __restrict__ dinv,
+                                                    const uint8_t* __restrict__ strong,
+                                                    const int8_t* __restrict__ cf, const int* __restrict__ cidx,
+                                                    const uint8_t* __restrict__ dir, int* __restrict__ pc,
+                                                    double* __restrict__ pv, int* __restrict__ defer) {
+  __shared__ IqGroup s_g[16];
+  const int grp = threadIdx.x >> 2, q = threadIdx.x & 3, gbase = threadIdx.x & ~3;
+  const unsigned bid = xcd_block();
+  const Tile t = tiles[bid / (kTileRows / 16)];
+  const int i = t.r0 + (int)(bid % (kTileRows / 16)) * 16 + grp;
+  if (i >= t.r1) return;  // nothing below synchronises the workgroup
+  const bool ok = interp_quad_row(i, q, gbase, s_g[grp], rp, ci, a, dinv, strong, cf, cidx, dir, pc, pv);
+  append_rows(!ok && q == 0, i, defer);
 }
 
 // rows of the scratch area into the final CSR (eight lanes per row)
@@ -2492,9 +2852,9 @@ constexpr int kAcc = 4;
 
 // row r of a tile-based launch: G blocks share one tile of kTileRows rows
 template <int G>
-__device__ inline int tile_row(const Tile& t, int& gl) {
+__device__ inline int tile_row(const Tile& t, int& gl, unsigned bid) {
   gl = threadIdx.x % G;
-  return t.r0 + (int)(blockIdx.x % G) * (kTileRows / G) + (int)threadIdx.x / G;
+  return t.r0 + (int)(bid % G) * (kTileRows / G) + (int)threadIdx.x / G;
 }
 
 // sum of a[e] f(ci[e]) over the row's entries [e0, e1); all G lanes of the
@@ -2560,10 +2920,11 @@ __global__ __launch_bounds__(256) void k_smooth(const Tile* __restrict__ tiles, 
                                                 T* __restrict__ xout, T omega, int first,
                                                 double* __restrict__ sol, const int8_t* __restrict__ cfm,
                                                 int cfphase) {
-  const Tile t = tiles[blockIdx.x / G];
+  const unsigned bid = blockIdx.x;
+  const Tile t = tiles[bid / G];
   if (!act[t.game]) return;
   int gl;
-  const int i = tile_row<G>(t, gl);
+  const int i = tile_row<G>(t, gl, bid);
   const bool in = i < t.r1;
   if (cfm) {
     // C/F relaxation: this half sweep relaxes the coarse points (cfphase 1)
@@ -2602,10 +2963,11 @@ __global__ __launch_bounds__(256) void k_resid(const Tile* __restrict__ tiles, c
                                                const int* __restrict__ rp, const int* __restrict__ ci,
                                                const T* __restrict__ a, const T* __restrict__ b,
                                                const T* __restrict__ x, T* __restrict__ r) {
-  const Tile t = tiles[blockIdx.x / G];
+  const unsigned bid = blockIdx.x;
+  const Tile t = tiles[bid / G];
   if (!act[t.game]) return;
   int gl;
-  const int i = tile_row<G>(t, gl);
+  const int i = tile_row<G>(t, gl, bid);
   const bool in = i < t.r1;
   const int e0 = in ? rp[i] : 0, e1 = in ? rp[i + 1] : 0;
   const T ax = row_dot<T, T, G>(ci, a, x, e0, e1, gl);
@@ -2622,9 +2984,10 @@ __global__ __launch_bounds__(256) void k_diag_dir(const Tile* __restrict__ tiles
                                                   int keep_diag, double inv_omega, uint8_t* __restrict__ dir,
                                                   double* __restrict__ d64, float* __restrict__ d32,
                                                   const uint8_t* __restrict__ only) {
-  const Tile t = tiles[blockIdx.x / G];
+  const unsigned bid = blockIdx.x;
+  const Tile t = tiles[bid / G];
   int gl;
-  const int i = tile_row<G>(t, gl);
+  const int i = tile_row<G>(t, gl, bid);
   // rows not flagged keep their data (the lanes of a row leave together)
   const bool in = i < t.r1 && (!only || only[i]);
   int any = 0;
@@ -2654,10 +3017,11 @@ __global__ __launch_bounds__(256) void k_restrict(const Tile* __restrict__ tiles
                                                   const int* __restrict__ rrp, const int* __restrict__ rci,
                                                   const T* __restrict__ rv, const T* __restrict__ rf,
                                                   T* __restrict__ bc) {
-  const Tile t = tiles[blockIdx.x / G];
+  const unsigned bid = blockIdx.x;
+  const Tile t = tiles[bid / G];
   if (!act[t.game]) return;
   int gl;
-  const int I = tile_row<G>(t, gl);
+  const int I = tile_row<G>(t, gl, bid);
   const bool in = I < t.r1;
   const int e0 = in ? rrp[I] : 0, e1 = in ? rrp[I + 1] : 0;
   const T s = row_dot<T, T, G>(rci, rv, rf, e0, e1, gl);
@@ -2903,11 +3267,11 @@ __global__ __launch_bounds__(256) void k_dense_solve(const int* __restrict__ blk
 // FP64 residual of the refinement: r = b - A x, its copy in the cycle type,
 // and per-game max |r|, max |x|.
 template <class T, int G>
-__device__ inline void resid64_block(const Tile& t, const int* __restrict__ rp, const int* __restrict__ ci,
+__device__ inline void resid64_block(const Tile& t, unsigned bid, const int* __restrict__ rp, const int* __restrict__ ci,
                                      const double* __restrict__ a, const double* __restrict__ b,
                                      const double* __restrict__ x, T* __restrict__ rc, const Stripes& norm) {
   int gl;
-  const int i = tile_row<G>(t, gl);
+  const int i = tile_row<G>(t, gl, bid);
   const bool in = i < t.r1;
   double rm = 0.0, xm = 0.0;
   const int e0 = in ? rp[i] : 0, e1 = in ? rp[i + 1] : 0;
@@ -2935,9 +3299,10 @@ __global__ __launch_bounds__(256) void k_resid64(const Tile* __restrict__ tiles,
                                                  const double* __restrict__ a, const double* __restrict__ b,
                                                  const double* __restrict__ x, T* __restrict__ rc,
                                                  Stripes norm) {
-  const Tile t = tiles[blockIdx.x / G];
+  const unsigned bid = blockIdx.x;
+  const Tile t = tiles[bid / G];
   if (!act[t.game]) return;
-  resid64_block<T, G>(t, rp, ci, a, b, x, rc, norm);
+  resid64_block<T, G>(t, bid, rp, ci, a, b, x, rc, norm);
 }
 
 template <class T>
@@ -3075,28 +3440,43 @@ void amg_interp(const Tile* t, int nt, const int* rp, const int* ci, const doubl
                 const uint8_t* strong, const int8_t* cf, const int* cidx, const uint8_t* dir, int* pc,
                 double* pv, int* capped, int wave, int* defer, int rows, hipStream_t s) {
   if (!nt) return;
+  const unsigned lb = (unsigned)std::max(1, std::min(rows, 2048));
   if (wave == 2) {
     // long rows: the 512-slot instance (18 KB of LDS per row) for all rows,
     // then the rows it could not hold with the largest one (33 KB)
-    fill_async(defer, 0, 1, s);
+    zero_counters_async(s, defer);
     hipLaunchKernelGGL((k_interp_wave<512, 128, 256, true>), dim3(nt * kTileRows), dim3(64), 0, s, t, rp, ci, a, dinv,
                        strong, cf, cidx, dir, pc, pv, capped, defer);
     SHP_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_interp_wave_list<1024, 256>), dim3(std::max(1, std::min(rows, 2048))), dim3(64), 0, s,
-                       defer, rp, ci, a, dinv, strong, cf, cidx, dir, pc, pv, capped);
+    hipLaunchKernelGGL((k_interp_wave_list<1024, 256, false>), dim3(lb), dim3(64), 0, s, defer, rp, ci, a, dinv,
+                       strong, cf, cidx, dir, pc, pv, capped, (int*)nullptr);
   } else if (wave == 1) {
     // a small instance (about 5 KB of LDS per row: twice the rows per CU of
     // the next size) for all rows, then the rows it could not hold
-    fill_async(defer, 0, 1, s);
+    zero_counters_async(s, defer);
     hipLaunchKernelGGL((k_interp_wave<128, 32, 128, true>), dim3(nt * kTileRows), dim3(64), 0, s, t, rp, ci, a, dinv,
                        strong, cf, cidx, dir, pc, pv, capped, defer);
     SHP_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_interp_wave_list<512, 128>), dim3(std::max(1, std::min(rows, 2048))), dim3(64), 0, s, defer,
-                       rp, ci, a, dinv, strong, cf, cidx, dir, pc, pv, capped);
+    hipLaunchKernelGGL((k_interp_wave_list<512, 128, false>), dim3(lb), dim3(64), 0, s, defer, rp, ci, a, dinv,
+                       strong, cf, cidx, dir, pc, pv, capped, (int*)nullptr);
+  } else if (wave == 3) {
+    // four lanes per row for the rows that fit, then the small wavefront
+    // instance over the others, then the larger over what that one could
+    // not hold (the same weights as wave == 1)
+    int* defer2 = defer + rows + 1;
+    zero_counters_async(s, defer, defer2);
+    hipLaunchKernelGGL(k_interp_quad, dim3(nt * (kTileRows / 16)), dim3(64), 0, s, t, rp, ci, a, dinv, strong, cf,
+                       cidx, dir, pc, pv, defer);
+    SHP_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_interp_wave_list<128, 32, true>), dim3(lb), dim3(64), 0, s, defer, rp, ci, a, dinv, strong,
+                       cf, cidx, dir, pc, pv, capped, defer2);
+    SHP_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_interp_wave_list<512, 128, false>), dim3(lb), dim3(64), 0, s, defer2, rp, ci, a, dinv,
+                       strong, cf, cidx, dir, pc, pv, capped, (int*)nullptr);
   } else {
     // the small set first (twice the wavefronts per CU), then the rows it
     // could not hold
-    fill_async(defer, 0, 1, s);
+    zero_counters_async(s, defer);
     hipLaunchKernelGGL((k_interp_lds<kIChatSmall, true>), dim3(nt * (kTileRows / kIThreads)), dim3(kIThreads), 0, s,
                        t, rp, ci, a, dinv, strong, cf, cidx, dir, pc, pv, capped, defer);
     SHP_LAUNCH_CHECK();

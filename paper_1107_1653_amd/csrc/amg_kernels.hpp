@@ -43,8 +43,10 @@ void amg_gather_int(const int* src, const int* idx, int m, int* dst, hipStream_t
 void amg_interp(const Tile* t, int nt, const int* rp, const int* ci, const double* a, const double* dinv,
                 const uint8_t* strong, const int8_t* cf, const int* cidx, const uint8_t* dir, int* pc,
                 double* pv, int* capped, int wave, int* defer, int rows, hipStream_t s);
-// wave: 0 thread per row, 1 or 2 wavefront per row; defer: scratch of rows + 1
-// ints (wave 1), rows: rows covered by the tiles
+// wave: 0 thread per row (level 0), 1 or 2 wavefront per row (small and
+// large LDS sets), 3 four lanes per row first and the wavefront kernels for
+// the rows it hands on (the same weights as 1); defer: scratch of
+// 2 (rows + 1) ints, rows: rows covered by the tiles
 void amg_pt_count(const Tile* t, int nt, const int* pc, int* cnt, hipStream_t s);
 void amg_pt_fill(const Tile* t, int nt, const int* pc, const double* pv, const int* rrp, int* cursor,
                  int* rci, double* rv, hipStream_t s);

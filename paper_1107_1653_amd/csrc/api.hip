@@ -639,6 +639,15 @@ int shapley_tune_galerkin(int32_t kernel) {
   return SHAPLEY_OK;
 }
 
+int shapley_tune_interp(int32_t kernel) {
+  if (kernel != -1 && kernel != 0 && kernel != 4) {
+    shp::set_last_error("kernel must be -1, 0 or 4");
+    return SHAPLEY_EINVAL;
+  }
+  shp::set_interp_mode(kernel);
+  return SHAPLEY_OK;
+}
+
 int shapley_game_bytes(shapley_game_t gh, size_t* bytes) {
   return guarded([&] {
     SHP_REQUIRE(gh && gh->g && bytes, "null argument");

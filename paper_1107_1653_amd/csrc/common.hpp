@@ -127,6 +127,20 @@ __global__ void k_fill(T* __restrict__ p, T v, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
+// Workgroups of a launch are dispatched to the 8 XCDs in turn (workgroup b
+// runs on XCD b mod 8, and each XCD has its own L2).  The logical index
+// gives each XCD one contiguous range of workgroups, so workgroups whose rows
+// gather the same neighbours share an L2.  A bijection of [0, gridDim.x).
+// Used by the setup's gather-bound kernels (interpolation, Galerkin
+// product); the streaming cycle kernels measured faster with the plain
+// order, whose concurrent workgroups on the eight XCDs read adjacent memory.
+__device__ __forceinline__ unsigned xcd_block() {
+  const unsigned n = gridDim.x, b = blockIdx.x;
+  if (n < 16) return b;
+  const unsigned per = n >> 3, rem = n & 7u, x = b & 7u;
+  return x * per + (x < rem ? x : rem) + (b >> 3);
+}
+
 // up to four counters set to zero by one launch (null pointers skipped)
 template <class T>
 __global__ void k_zero4(T* a, T* b, T* c, T* d) {

@@ -472,6 +472,7 @@ class Engine {
 void set_forced_lanes(int lanes);
 int forced_lanes();
 void set_forced_rap_cols(int mode);  // Galerkin kernel family, -1: automatic
+void set_interp_mode(int mode);      // coarse-level interpolation kernels, -1: automatic
 
 // Engines (with their device workspace) are kept per game stream between
 // solves; a lease takes the idle engine of a stream or makes one, and gives

@@ -40,7 +40,7 @@ EXPORTED = [
     "shapley_solve_batch", "shapley_server_create", "shapley_server_submit", "shapley_server_wait",
     "shapley_server_poll", "shapley_server_step", "shapley_server_destroy", "shapley_server_info",
     "shapley_probe_enable", "shapley_probe_read", "shapley_probe_read_large", "shapley_tune_lanes",
-    "shapley_tune_galerkin",
+    "shapley_tune_galerkin", "shapley_tune_interp",
 ]
 PROBE = dict(smooth=0, resid64=1, improve=2, resid=3, restrict=4, prolong=5, rap=6, interp=7, tail=8)
 
@@ -147,6 +147,7 @@ def lib() -> C.CDLL:
                                                C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.shapley_tune_lanes.argtypes = [C.c_int32]
         L.shapley_tune_galerkin.argtypes = [C.c_int32]
+        L.shapley_tune_interp.argtypes = [C.c_int32]
         _lib_handle = L
     return _lib_handle
 
@@ -421,6 +422,11 @@ def shapley_tune_galerkin(kernel: int = -1) -> None:
     """Galerkin product kernels: -1 chooses per product, 0 wavefront only, 1 thread per row first, 4 four lanes
     per row first."""
     _check(lib().shapley_tune_galerkin(int(kernel)))
+
+
+def shapley_tune_interp(kernel: int = -1) -> None:
+    """Coarse-level interpolation kernels: -1 or 4 four lanes per row first, 0 wavefront only."""
+    _check(lib().shapley_tune_interp(int(kernel)))
 
 
 def shapley_probe_read_large(family, frac: float = 0.5) -> dict:

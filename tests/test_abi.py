@@ -83,6 +83,11 @@ def test_lane_control_arguments():
             P.shapley_tune_galerkin(bad)
     for ok in (0, 1, 4, -1):
         P.shapley_tune_galerkin(ok)
+    for bad in (1, 2, 8, -2):
+        with pytest.raises(P.ShapleyError):
+            P.shapley_tune_interp(bad)
+    for ok in (0, 4, -1):
+        P.shapley_tune_interp(ok)
 
 
 def test_bench_refuses_more_than_one_gpu():

@@ -1,5 +1,7 @@
-"""The kernels of the row-wise Galerkin product A_{l+1} = R A_l P (Sec. 4.3)
-are a speed choice only: the thread-per-row kernel (rows of up to 16 or 32
+"""The kernels of the AMG setup are a speed choice only (Sec. 4.3).  The
+extended+i interpolation of coarse levels by four lanes per row forms every
+weight with the wavefront kernel's operations in the same order.  For the
+row-wise Galerkin product A_{l+1} = R A_l P, the thread-per-row kernel (rows of up to 16 or 32
 columns), the four-lanes-per-row kernel (32 or 64), the wavefront-per-row
 kernel and the workgroup-per-row kernel generate each coarse entry's products in one order (R's row, A's row, P's
 slots) and add them one after the other from zero, so every level of the
@@ -31,12 +33,13 @@ def levels_of(h):
 
 
 @pytest.mark.parametrize("name,make,precision", CASES, ids=[c[0] for c in CASES])
-def test_galerkin_kernel_choice_does_not_change_results(name, make, precision):
+def test_setup_kernel_choice_does_not_change_results(name, make, precision):
     g = make()
     ref = None
     try:
-        for cols in (0, 1, 4, -1):
+        for cols, interp in ((0, 0), (1, 0), (4, 4), (-1, -1)):
             P.shapley_tune_galerkin(cols)
+            P.shapley_tune_interp(interp)
             h = P.create_from(g)
             try:
                 st = P.shapley_solve(h, P.shapley_default_opts(precision=precision, max_outer=500, max_inner=500))
@@ -45,7 +48,7 @@ def test_galerkin_kernel_choice_does_not_change_results(name, make, precision):
                 lev = levels_of(h)
             finally:
                 P.shapley_game_destroy(h)
-            log(f"  {name} galerkin cols {cols}: outer {st['outer']} cycles {st['cycles_total']} "
+            log(f"  {name} galerkin {cols} interp {interp}: outer {st['outer']} cycles {st['cycles_total']} "
                 f"levels {len(lev)} sizes {[len(x[0]) - 1 for x in lev]} residual {st['residual']:.3e}")
             assert st["converged"] == 1
             if ref is None:
@@ -61,4 +64,5 @@ def test_galerkin_kernel_choice_does_not_change_results(name, make, precision):
             assert st["cycles_total"] == ref[3]
     finally:
         P.shapley_tune_galerkin(-1)
+        P.shapley_tune_interp(-1)
 
