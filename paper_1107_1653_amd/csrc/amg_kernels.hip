@@ -190,7 +190,7 @@ __global__ void k_pmis_select(const Tile* __restrict__ tiles, const int* __restr
                               const int* __restrict__ st_rp, const int* __restrict__ st_ci,
                               const int8_t* __restrict__ cf, const uint64_t* __restrict__ key,
                               int* __restrict__ newc, int* __restrict__ left, int round) {
-  // the following update kernel counts the undecided rows into left[round & 1];
+  // the following update kernel flags undecided rows in left[round & 1];
   // once a round has left none undecided, later rounds do nothing
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     left[round & 1] = 0;
@@ -203,18 +203,27 @@ __global__ void k_pmis_select(const Tile* __restrict__ tiles, const int* __restr
   newc[i] = pmis_select_row(i, rp, ci, strong, st_rp, st_ci, cf, key);
 }
 
-// `left` counts the points still undecided.
-__global__ void k_pmis_update(const Tile* __restrict__ tiles, const int* __restrict__ rp,
-                              const int* __restrict__ ci, const uint8_t* __restrict__ strong,
-                              int8_t* __restrict__ cf, const int* __restrict__ newc,
-                              int* __restrict__ left, int round) {
+// `left[round & 1]` becomes nonzero when a point is still undecided (only
+// zero or nonzero is read).  One write per workgroup at most, and none once
+// another workgroup has set it: a count by atomics on one address serialised
+// over a level's workgroups.
+__device__ __forceinline__ void flag_undecided(int* left, bool mine) {
+  if (mine && __hip_atomic_load(left, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+    __hip_atomic_store(left, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(kTileRows) void k_pmis_update(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                                                          const int* __restrict__ ci,
+                                                          const uint8_t* __restrict__ strong,
+                                                          int8_t* __restrict__ cf, const int* __restrict__ newc,
+                                                          int* __restrict__ left, int round) {
   if (round > 0 && left[(round - 1) & 1] == 0) return;
   Tile t = tiles[xcd_block()];
   int i = t.r0 + threadIdx.x;
   int und = 0;
   if (i < t.r1) und = pmis_update_row(i, rp, ci, strong, cf, newc);
-  for (int o = 32; o > 0; o >>= 1) und += __shfl_xor(und, o);
-  if ((threadIdx.x & 63) == 0 && und) atomicAdd(&left[round & 1], und);
+  const bool any = __syncthreads_or(und);
+  if (threadIdx.x == 0) flag_undecided(&left[round & 1], any);
 }
 
 // The same two kernels with one wavefront per row (levels with long rows):
@@ -278,7 +287,7 @@ __global__ __launch_bounds__(256) void k_pmis_update_w(const Tile* __restrict__ 
   const bool any = __ballot(hit) != 0;
   if (lane == 0) {
     if (any) cf[i] = CF_F;
-    else atomicAdd(&left[round & 1], 1);
+    else flag_undecided(&left[round & 1], true);
   }
 }
 
@@ -1953,7 +1962,7 @@ __device__ __forceinline__ bool rap_quad_row(int I, int q, const int* __restrict
                                              const int* __restrict__ crp, const int* __restrict__ cci,
                                              double* __restrict__ cval, int* col, double* acc) {
 #pragma clang fp contract(off)
-  constexpr int kU = 4;        // pairs whose loads are issued together
+  constexpr int kU = 8;        // pairs whose loads are issued together
   constexpr int kH = 2 * NC;   // hash slots (in the space of the sums)
   constexpr int kR = NC / 4;   // columns ranked per lane
   const int lane = threadIdx.x & 63;

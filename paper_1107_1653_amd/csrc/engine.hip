@@ -87,9 +87,10 @@ static bool profiling() {
 // product is the same bit for bit whichever kernel computes a row.
 static std::atomic<int> g_gal_mode{-1};
 void set_forced_rap_cols(int mode) { g_gal_mode.store(mode); }
-// interpolation of coarse levels: 0 the wavefront kernel alone, else four
-// lanes per row first (the same weights)
+// interpolation of coarse levels: 0 the wavefront kernel alone, 4 four lanes
+// per row first, -1 four lanes on large levels (the same weights either way)
 static std::atomic<int> g_interp_mode{-1};
+constexpr int kInterpQuadRows = 1 << 16;  // automatic choice: levels of at least this many rows
 void set_interp_mode(int mode) { g_interp_mode.store(mode); }
 static int gal_kernel(double cols, bool one_slot) {
   const int mode = g_gal_mode.load();
@@ -660,7 +661,11 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         // level 0 (grid stencils, short rows): one thread per row; coarse
         // levels (long rows): one wavefront per row, with the larger LDS sets
         // where rows average more than 32 entries
-        const int iw = l == 0 ? 0 : ((double)L.nnz > 32.0 * std::max(n, 1) ? 2 : (g_interp_mode.load() == 0 ? 1 : 3));
+        // (four lanes per row take a row through a longer chain than a
+        // wavefront does: only levels with rows enough to fill the chip)
+        const int imode = g_interp_mode.load();
+        const bool quad = imode == 4 || (imode == -1 && n >= kInterpQuadRows);
+        const int iw = l == 0 ? 0 : ((double)L.nnz > 32.0 * std::max(n, 1) ? 2 : (quad ? 3 : 1));
         s_defer.ensure(2 * ((size_t)L.rows_ctiles + 1));  // two hand-over lists
         amg_interp(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, L.dinv64.p, L.strong.p, L.cf.p,
                    L.cidx.p, L.dir.p, L.pc.p, L.pv64.p, s_err.p, iw, s_defer.p, L.rows_ctiles, stream);

@@ -425,7 +425,8 @@ def shapley_tune_galerkin(kernel: int = -1) -> None:
 
 
 def shapley_tune_interp(kernel: int = -1) -> None:
-    """Coarse-level interpolation kernels: -1 or 4 four lanes per row first, 0 wavefront only."""
+    """Coarse-level interpolation kernels: -1 four lanes per row first on large levels, 4 on every level,
+    0 wavefront only."""
     _check(lib().shapley_tune_interp(int(kernel)))
 
 

@@ -1,14 +1,18 @@
-"""The kernels of the AMG setup are a speed choice only (Sec. 4.3).  The
-extended+i interpolation of coarse levels by four lanes per row forms every
-weight with the wavefront kernel's operations in the same order.  For the
-row-wise Galerkin product A_{l+1} = R A_l P, the thread-per-row kernel (rows of up to 16 or 32
-columns), the four-lanes-per-row kernel (32 or 64), the wavefront-per-row
-kernel and the workgroup-per-row kernel generate each coarse entry's products in one order (R's row, A's row, P's
-slots) and add them one after the other from zero, so every level of the
-hierarchy, and every solve, is the same bit for bit whichever kernel took
-which row.  The games are large enough for the row-wise product (levels of
-8192 coarse rows or more): a 2-D five-point grid, a 3-D seven-point grid and
-a point cloud whose coarse rows overflow the thread kernel."""
+"""The kernels of the AMG setup are a speed choice only (Sec. 4.3).
+
+* The extended+i interpolation of coarse levels by four lanes per row forms
+  every weight with the wavefront kernel's operations in the same order.
+* The row-wise Galerkin product A_{l+1} = R A_l P by a thread per row (rows
+  of up to 16 or 32 columns), four lanes per row (32 or 64), a wavefront per
+  row or a workgroup per row generates each coarse entry's products in one
+  order (R's row, A's row, P's slots) and adds them one after the other from
+  zero.
+
+So every level of the hierarchy, and every solve, is the same bit for bit
+whichever kernel took which row.  The games are large enough for the
+row-wise product (levels of 8192 coarse rows or more): a 2-D five-point
+grid, a 3-D seven-point grid and a point cloud whose coarse rows overflow the
+thread kernel."""
 import numpy as np
 import pytest
 
