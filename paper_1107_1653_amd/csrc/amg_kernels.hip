@@ -2215,28 +2215,41 @@ __device__ __forceinline__ bool interp_quad_row(int i, int q, int gbase, IqGroup
   wave_lds_sync();
   int nK = 0;
   bool full = false;
-  for (int base = 0; base < len; base += 4) {
-    const int t = base + q;
-    const bool in = t < len;
-    int j = -1;
-    bool st = false;
-    double aij = 0.0;
-    if (in) {
-      j = ci[e0 + t];
-      st = strong[e0 + t] != 0;
-      aij = a[e0 + t];
+  for (int b16 = 0; b16 < len; b16 += 16) {  // four chunks of four entries, loads first
+    int jj[4];
+    bool offs[4];
+    double aa[4];
+    int8_t cc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = b16 + 4 * u + q;
+      jj[u] = -1;
+      offs[u] = false;
+      aa[u] = 0.0;
+      if (t < len) {
+        jj[u] = ci[e0 + t];
+        offs[u] = strong[e0 + t] != 0;
+        aa[u] = a[e0 + t];
+      }
     }
-    const bool off = in && st && j != i;
-    const int8_t cj = off ? cf[j] : (int8_t)0;
-    if (off && cj == CF_C && !iq_insert(G.hs, j)) full = true;
-    const bool isF = off && cj == CF_F;
-    const unsigned m4 = group_ballot(isF, gbase);
-    const int pos = nK + __popc(m4 & below);
-    if (isF && pos < kIqK) {
-      G.kcol[pos] = j;
-      G.kaik[pos] = aij;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      offs[u] = offs[u] && jj[u] != i;
+      cc[u] = offs[u] ? cf[jj[u]] : (int8_t)0;
     }
-    nK += __popc(m4);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (b16 + 4 * u >= len) break;  // the same for the whole group
+      if (offs[u] && cc[u] == CF_C && !iq_insert(G.hs, jj[u])) full = true;
+      const bool isF = offs[u] && cc[u] == CF_F;
+      const unsigned m4 = group_ballot(isF, gbase);
+      const int pos = nK + __popc(m4 & below);
+      if (isF && pos < kIqK) {
+        G.kcol[pos] = jj[u];
+        G.kaik[pos] = aa[u];
+      }
+      nK += __popc(m4);
+    }
   }
   if (group_ballot(full, gbase) || nK > kIqK) return false;
   wave_lds_sync();
@@ -2250,9 +2263,19 @@ __device__ __forceinline__ bool interp_quad_row(int i, int q, int gbase, IqGroup
   // ---- distance-two candidates: strong C neighbours of the strong F neighbours
   for (int p = 0; p < nK; ++p) {
     const int k = G.kcol[p], en = G.kend[p];
-    for (int e2 = G.kbeg[p] + q; e2 < en; e2 += 4) {
-      const int l = ci[e2];
-      if (strong[e2] && l != k && cf[l] == CF_C && !iq_insert(G.hs, l)) full = true;
+    for (int c0 = G.kbeg[p]; c0 < en; c0 += 16) {  // loads of four chunks first
+      int ll[4];
+      int8_t cl[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e2 = c0 + 4 * u + q;
+        ll[u] = (e2 < en && strong[e2]) ? ci[e2] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) cl[u] = (ll[u] >= 0 && ll[u] != k) ? cf[ll[u]] : (int8_t)0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (cl[u] == CF_C && !iq_insert(G.hs, ll[u])) full = true;
     }
   }
   if (group_ballot(full, gbase)) return false;
@@ -2295,25 +2318,38 @@ __device__ __forceinline__ bool interp_quad_row(int i, int q, int gbase, IqGroup
     const bool neg = G.kneg[p] != 0;
     double d = 0.0, abi = 0.0;
     bool has_i = false;
-    for (int c0 = G.kbeg[p]; c0 < en; c0 += 4) {
-      const int e2 = c0 + q;
-      double term = 0.0;
-      if (e2 < en) {
-        const int l = ci[e2];
-        const double akl = a[e2];
-        const double abar = neg ? (akl > 0.0 ? akl : 0.0) : (akl < 0.0 ? akl : 0.0);
-        if (l != k && abar != 0.0) {
-          if (l == i) {
-            term = abar;
-            abi = abar;
-            has_i = true;
-          } else if (iq_find(G.mem, m, l) >= 0) {
-            term = abar;
-          }
+    for (int c16 = G.kbeg[p]; c16 < en; c16 += 16) {  // loads of four chunks first
+      int ll[4];
+      double ak[4], term[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e2 = c16 + 4 * u + q;
+        ll[u] = -1;
+        ak[u] = 0.0;
+        if (e2 < en) {
+          ll[u] = ci[e2];
+          ak[u] = a[e2];
         }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) d = d + __shfl(term, gbase | u);
+      for (int u = 0; u < 4; ++u) {
+        term[u] = 0.0;
+        const double abar = neg ? (ak[u] > 0.0 ? ak[u] : 0.0) : (ak[u] < 0.0 ? ak[u] : 0.0);
+        if (ll[u] >= 0 && ll[u] != k && abar != 0.0) {
+          if (ll[u] == i) {
+            term[u] = abar;
+            abi = abar;
+            has_i = true;
+          } else if (iq_find(G.mem, m, ll[u]) >= 0) {
+            term[u] = abar;
+          }
+        }
+      }
+      // the terms in entry order: chunk by chunk, lane by lane
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) d = d + __shfl(term[u], gbase | w);
     }
     const unsigned hi = group_ballot(has_i, gbase);
     abi = hi ? __shfl(abi, gbase | (__ffs(hi) - 1)) : 0.0;
@@ -2371,13 +2407,26 @@ __device__ __forceinline__ bool interp_quad_row(int i, int q, int gbase, IqGroup
     const bool neg = G.kneg[p] != 0;
     const double den = G.kden[p], aik = G.kaik[p];
     if (den != 0.0) {
-      for (int e2 = G.kbeg[p] + q; e2 < en; e2 += 4) {
-        const int l = ci[e2];
-        const double akl = a[e2];
-        const double abar = neg ? (akl > 0.0 ? akl : 0.0) : (akl < 0.0 ? akl : 0.0);
-        if (l == k || l == i || abar == 0.0) continue;
-        const int qq = iq_find(G.mem, m, l);
-        if (qq >= 0) W[qq] = W[qq] + aik * abar / den;
+      for (int c16 = G.kbeg[p]; c16 < en; c16 += 16) {  // loads of four chunks first
+        int ll[4];
+        double ak[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e2 = c16 + 4 * u + q;
+          ll[u] = -1;
+          ak[u] = 0.0;
+          if (e2 < en) {
+            ll[u] = ci[e2];
+            ak[u] = a[e2];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double abar = neg ? (ak[u] > 0.0 ? ak[u] : 0.0) : (ak[u] < 0.0 ? ak[u] : 0.0);
+          if (ll[u] < 0 || ll[u] == k || ll[u] == i || abar == 0.0) continue;
+          const int qq = iq_find(G.mem, m, ll[u]);
+          if (qq >= 0) W[qq] = W[qq] + aik * abar / den;
+        }
       }
     }
     wave_lds_sync();
