@@ -101,7 +101,7 @@ static int gal_kernel(double cols, bool one_slot) {
     return cols <= 9.0 ? kGalThread16 : kGalThread32;
   }
   if (mode == -1 && cols > 44.0) return kGalWave;
-  return cols <= 18.0 ? kGalQuad32 : kGalQuad64;
+  return cols <= 24.0 ? kGalQuad32 : kGalQuad64;
 }
 
 struct PhaseTimer {
@@ -154,6 +154,7 @@ void Engine::reset() {
   ++hier_gen;
   run_at_setup.clear();
   changes_since_setup = 0;
+  changes_since_refresh = 0;
   last_cycles = 0;
   cycles_after_full = -1;
   stagnated = false;
@@ -207,7 +208,10 @@ void Engine::level_export(int l, int* levels, int64_t* n, int64_t* nnz, int64_t*
   SHP_HIP(hipStreamSynchronize(stream));
   if (rp) SHP_HIP(hipMemcpy(rp, L.rp.p, sizeof(int) * ((size_t)L.n + 1), hipMemcpyDeviceToHost));
   if (ci && L.nnz) SHP_HIP(hipMemcpy(ci, L.ci.p, sizeof(int) * (size_t)L.nnz, hipMemcpyDeviceToHost));
-  if (a && L.nnz) SHP_HIP(hipMemcpy(a, L.a64.p, sizeof(double) * (size_t)L.nnz, hipMemcpyDeviceToHost));
+  // level 0: the operator the coarse levels were formed from (the last setup
+  // or refresh; later policy steps may have assembled newer values since)
+  const double* av = (l == 0 && L.a_prev.p) ? L.a_prev.p : L.a64.p;
+  if (a && L.nnz) SHP_HIP(hipMemcpy(a, av, sizeof(double) * (size_t)L.nnz, hipMemcpyDeviceToHost));
   if (cn && pc) SHP_HIP(hipMemcpy(pc, L.pc.p, sizeof(int) * (size_t)L.n * PW, hipMemcpyDeviceToHost));
   if (cn && pv) SHP_HIP(hipMemcpy(pv, L.pv64.p, sizeof(double) * (size_t)L.n * PW, hipMemcpyDeviceToHost));
 }
@@ -803,9 +807,9 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
           s_tval.ensure(tcap);
           s_big.ensure(2 * ((size_t)std::max(n, nc) + 1));
           amg_rap_bound(nc, L.rrp.p, L.rci.p, Arp, s_cnt.p, pwf, stream);
-          // coarse rows: the level's previous product, else about three
+          // coarse rows: the level's previous product, else about four
           // times the fine rows' entries (grid stencils)
-          const double c_cols = (Ln.nnz > 0 && Ln.n == nc) ? (double)Ln.nnz / nc : 3.0 * L.nnz / n;
+          const double c_cols = (Ln.nnz > 0 && Ln.n == nc) ? (double)Ln.nnz / nc : 4.0 * L.nnz / n;
           scan_exclusive(s_cnt.p, s_toff.p, nc + 1, stream, s_scan);
           probe_begin(kProbeRap, stream);
           amg_rap_fused(nc, L.rrp.p, L.rci.p, L.rv64.p, Arp, Aci, Aa, Ppc, Ppv, s_toff.p, s_cnt.p, s_tcol.p,
@@ -1439,6 +1443,10 @@ void Engine::improve_only() {
   sync();
 }
 
+// a refresh is skipped while fewer than this fraction of the states changed
+// policy since the coarse operators were last formed
+constexpr double kLazyRefresh = 0.02;
+
 int Engine::step() {
   if (layout_dirty) build_layout();
   std::vector<int> run = running_slots();
@@ -1481,11 +1489,20 @@ int Engine::step() {
     have_hier = true;
     run_at_setup = run;
     changes_since_setup = 0;
+    changes_since_refresh = 0;
     cycles_after_full = -1;
     ++full_setups;
+  } else if ((double)changes_since_refresh < kLazyRefresh * std::max(1, N0) &&
+             last_cycles <= cycles_after_full + 2) {
+    // Few states changed policy since the coarse operators were last formed:
+    // they are kept.  Level 0 (the assembled operator, its diagonal) is
+    // always current, and the FP64 refinement measures the true residual, so
+    // a slightly stale coarse correction only costs cycles -- a refresh is
+    // taken again once the cycle count grows.
   } else {
     refresh(o);
     ++refreshes;
+    changes_since_refresh = 0;
   }
   if (o.smoother == SHAPLEY_SMOOTH_L1) {
     // l1-Jacobi: the relaxation diagonals replace 1/a_ii once setup or refresh
@@ -1555,6 +1572,7 @@ int Engine::step() {
     } else if (nin > 0 && S->nk < S->opt.max_inner) {
       code[g] = 1;
       changes_since_setup += nin;
+      changes_since_refresh += nin;
       S->resolves = 0;
     } else if (nout == 0 && S->loose && S->resolves < 2) {
       // both policies look stable after an inexact solve: solve the same
@@ -1586,6 +1604,7 @@ int Engine::step() {
         S->k += 1;
         S->nk = 0;
         changes_since_setup += nout;
+        changes_since_refresh += nout;
         S->resolves = 0;
       }
     }

@@ -448,7 +448,7 @@ class Engine {
   // hierarchy reuse across policy-iteration steps
   bool have_hier = false;
   std::vector<int> run_at_setup;
-  int64_t changes_since_setup = 0;
+  int64_t changes_since_setup = 0, changes_since_refresh = 0;
   int last_cycles = 0, cycles_after_full = -1;
   bool stagnated = false;  // a linear solve stalled: rebuild the hierarchy
   // the refinement cycle captured as a HIP graph for the current hierarchy
