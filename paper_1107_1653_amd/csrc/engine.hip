@@ -1445,7 +1445,7 @@ void Engine::improve_only() {
 
 // a refresh is skipped while fewer than this fraction of the states changed
 // policy since the coarse operators were last formed
-constexpr double kLazyRefresh = 0.02;
+constexpr double kLazyRefresh = 0.10;
 
 int Engine::step() {
   if (layout_dirty) build_layout();
