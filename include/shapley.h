@@ -299,6 +299,14 @@ int shapley_tune_galerkin(int32_t kernel);
  * Errors: SHAPLEY_EINVAL for any other value. */
 int shapley_tune_interp(int32_t kernel);
 
+/* Testing aid for the error paths (no passage of the paper: library
+ * robustness).  after > 0: the after-th device allocation made by the library
+ * from now on fails as if the device were out of memory, so that the call
+ * making it returns SHAPLEY_ENOMEM; 0 disarms.  Handles stay usable after
+ * such a failure (a later call allocates again).  Process-wide.  Errors:
+ * SHAPLEY_EINVAL for after < 0. */
+int shapley_debug_fail_alloc(int64_t after);
+
 /* Inspection of the algebraic multigrid hierarchy (Sec. 4.3) built by the
  * last shapley_solve of g, run alone on the handle's own stream (opts.stream
  * NULL; for a hierarchy handle, the finest grid's).  Level 0 is the operator

@@ -347,6 +347,10 @@ static int guarded(F&& f) {
   }
 }
 
+namespace shp {
+std::atomic<long long> g_alloc_fault{0};  // armed by shapley_debug_fail_alloc
+}
+
 extern "C" {
 
 const char* shapley_last_error(void) { return g_last_error.c_str(); }
@@ -619,6 +623,15 @@ int shapley_hierarchy_level(shapley_game_t gh, int32_t level, shapley_level_info
       info->nc = nc;
     }
   });
+}
+
+int shapley_debug_fail_alloc(int64_t after) {
+  if (after < 0) {
+    shp::set_last_error("after must be >= 0");
+    return SHAPLEY_EINVAL;
+  }
+  shp::g_alloc_fault.store(after);
+  return SHAPLEY_OK;
 }
 
 int shapley_tune_lanes(int32_t lanes) {

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <stdexcept>
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -38,6 +39,17 @@ void set_last_error(const std::string& msg);
 // device buffers
 // ---------------------------------------------------------------------------
 
+// Fault injection for tests of the error paths: when armed with k > 0, the
+// k-th device allocation from then on fails (shapley_debug_fail_alloc).
+extern std::atomic<long long> g_alloc_fault;
+inline bool alloc_fault_due() {
+  long long k = g_alloc_fault.load(std::memory_order_relaxed);
+  while (k > 0) {
+    if (g_alloc_fault.compare_exchange_weak(k, k - 1, std::memory_order_relaxed)) return k == 1;
+  }
+  return false;
+}
+
 // Owning device allocation (hipMalloc / hipFree), movable, not copyable.
 template <class T>
 struct DBuf {
@@ -57,6 +69,10 @@ struct DBuf {
     release();
     n = count;
     if (count) {
+      if (alloc_fault_due()) {
+        n = 0;
+        throw Error(SHAPLEY_ENOMEM, "device allocation failed (injected by shapley_debug_fail_alloc)");
+      }
       hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T));
       if (e != hipSuccess) {
         p = nullptr; n = 0;

@@ -88,6 +88,9 @@ def test_lane_control_arguments():
             P.shapley_tune_interp(bad)
     for ok in (0, 4, -1):
         P.shapley_tune_interp(ok)
+    with pytest.raises(P.ShapleyError):
+        P.shapley_debug_fail_alloc(-1)
+    P.shapley_debug_fail_alloc(0)
 
 
 def test_bench_refuses_more_than_one_gpu():
