@@ -320,7 +320,7 @@ void Engine::build_layout() {
   d_active.ensure(std::max(G, 1));
   h_active_dev.clear();
   d_norm.ensure(4 * std::max(G, 1));
-  d_shap.ensure(3 * std::max(G, 1));
+  d_shap.ensure(4 * std::max(G, 1));
   d_cnt = reinterpret_cast<int*>(d_shap.p + 2 * std::max(G, 1));
   d_lin.ensure(2 * std::max(G, 1));  // LinCtl is larger than an int
   d_lin_active = reinterpret_cast<int*>(d_lin.p + std::max(G, 1));
@@ -1244,7 +1244,7 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
     LinCtl& c = h_lin[g];
     c.rtol = S->opt.lin_rtol;
     c.atol = S->opt.lin_atol;
-    c.forcing = S->opt.forcing;
+    c.forcing = S->exact ? 0.0 : S->opt.forcing;  // exact solves once cycling was seen
     c.res_prev = S->res_prev;
     c.max_cycles = S->opt.max_cycles;
   }
@@ -1392,7 +1392,7 @@ void Engine::improve(const std::vector<int>& run, double tie_rtol) {
   probe_begin(kProbeImprove, stream);
   launch_improve(ddesc.p, gtiles_imp.p, (int)h_gtiles_imp.size(), d_active.p, tie_rtol, fold, stream);
   probe_end(kProbeImprove, stream, bytes);
-  launch_fold_finish(fold, G, 2, 2u, 2, d_shap.p, 2, d_cnt, 2, stream);
+  launch_fold_finish(fold, G, 2, 2u, 3, d_shap.p, 2, d_cnt, 3, stream);
 }
 
 // The decisions are applied asynchronously (the host copy stays alive in a
@@ -1441,6 +1441,14 @@ void Engine::improve_only() {
   h_active_dev = act;
   improve(all, slots.empty() ? 1e-12 : slots[0]->opt.tie_rtol);
   sync();
+}
+
+// whether MAX's improved strategy (hash h) is one of an earlier outer step
+// whose Shapley residual was no larger than the current one
+static bool revisits(const SlotState* S, uint32_t h) {
+  for (const auto& e : S->outer_hist)
+    if (e.first == h && e.second <= S->res) return true;
+  return false;
 }
 
 // a refresh is skipped while fewer than this fraction of the states changed
@@ -1527,12 +1535,12 @@ int Engine::step() {
   launch_scatter_v(ddesc.p, gtiles_all.p, (int)h_gtiles_all.size(), d_active.p, sol.p, stream);
   improve(run, o.tie_rtol);
   std::vector<double> hs(2 * G);
-  std::vector<int> hc(2 * G);
-  const double* ps = down(d_shap.p, 3 * (size_t)std::max(G, 1));  // residuals, then the counts
+  std::vector<int> hc(3 * G);
+  const double* ps = down(d_shap.p, 4 * (size_t)std::max(G, 1));  // residuals, then the counts and hashes
   const int* pcn = reinterpret_cast<const int*>(ps + 2 * std::max(G, 1));
   sync();
   hs.assign(ps, ps + 2 * G);
-  hc.assign(pcn, pcn + 2 * G);
+  hc.assign(pcn, pcn + 3 * G);
   double t3 = now_s();
   pt.mark("improve");
 
@@ -1548,7 +1556,8 @@ int Engine::step() {
     S->res_prev = S->res;
     ++S->solves;
     S->res_l2 = gm->n ? std::sqrt(hs[2 * g + 1] / gm->n) : 0.0;
-    int nin = hc[2 * g], nout = hc[2 * g + 1];
+    int nin = hc[3 * g], nout = hc[3 * g + 1];
+    const uint32_t hout = (uint32_t)hc[3 * g + 2];
     S->nk += 1;
     S->inner_total += 1;
     if (S->status != SHAPLEY_OK) {
@@ -1599,7 +1608,29 @@ int Engine::step() {
         S->status = SHAPLEY_ENOCONV;
         S->why = "policy iteration hit an iteration limit (max_outer)";
         S->done = true;
+      } else if (revisits(S, hout)) {
+        // MAX's improved strategy is one taken at an earlier outer step whose
+        // residual was no larger: policy iteration cycles (exact evaluations
+        // improve strictly, Sec. 4.1).  After inexact solves the game goes on
+        // with exact ones; with exact ones it stops.
+        if (S->loose && !S->exact) {
+          S->exact = true;
+          S->outer_hist.clear();
+          code[g] = 2;
+          S->k += 1;
+          S->nk = 0;
+          changes_since_setup += nout;
+          changes_since_refresh += nout;
+          S->resolves = 0;
+        } else {
+          S->status = SHAPLEY_ENOCONV;
+          S->why = "policy iteration cycles: MAX's strategy of an earlier outer step came back without a lower "
+                   "Shapley residual";
+          S->done = true;
+        }
       } else {
+        S->outer_hist.emplace_back(hout, S->res);
+        if (S->outer_hist.size() > 32) S->outer_hist.erase(S->outer_hist.begin());
         code[g] = 2;
         S->k += 1;
         S->nk = 0;

@@ -300,7 +300,7 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
   }
   __syncthreads();
   double res = 0.0, res2 = 0.0;
-  int chg_in = 0, chg_out = 0;
+  int chg_in = 0, chg_out = 0, hash_out = 0;
   if (owner) {
     const int x = t.s0 + tid;
     const int base = tid * K;
@@ -367,11 +367,14 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
     res2 = dv * dv;
     chg_in = (bin != be) ? 1 : 0;
     chg_out = (ac != al || (al >= 0 && !al_ok)) ? 1 : 0;
+    // a hash of MAX's improved strategy: the wrapping sum over states of a
+    // mix of (state, action), independent of the summation order
+    hash_out = (int)mix32((uint32_t)x * 0x9E3779B9u ^ (uint32_t)(ac + 1));
   }
-  // per-game max |F(v) - v|, sum (F(v) - v)^2 and change counts
+  // per-game max |F(v) - v|, sum (F(v) - v)^2, change counts, strategy hash
   const double vd[2] = {warp_max(res), warp_sum(res2)};
-  const int vi[2] = {warp_sum_i(chg_in), warp_sum_i(chg_out)};
-  block_fold<2, 2>(red, t.game, vd, 2u, vi);
+  const int vi[3] = {warp_sum_i(chg_in), warp_sum_i(chg_out), warp_sum_i(hash_out)};
+  block_fold<2, 3>(red, t.game, vd, 2u, vi);
 }
 
 void launch_improve(const GameDesc* d, const GTile* t, int nt, const int* active, double tie_rtol,

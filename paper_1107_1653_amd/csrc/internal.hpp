@@ -232,6 +232,8 @@ struct SlotState {
   double res = 0.0, res_l2 = 0.0;
   double res_prev = INFINITY;   // Shapley residual after the previous value step
   bool loose = false;           // the last linear solve used the forcing tolerance
+  bool exact = false;           // forcing off: cycling was seen after inexact solves
+  std::vector<std::pair<uint32_t, double>> outer_hist;  // (strategy hash, residual) of outer steps
   int resolves = 0;             // consecutive accuracy re-solves at stable policies
   int solves = 0;               // value steps performed (including accuracy re-solves)
   int setups_full = 0, setups_refresh = 0;
