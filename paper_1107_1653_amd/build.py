@@ -1,9 +1,14 @@
 """Builds libshapley.so (HIP for gfx950) in-tree.
 
     python -m paper_1107_1653_amd.build
+    python -m paper_1107_1653_amd.build --sanitize <dir>
 
 Every .hip file under csrc/ is compiled to an object with hipcc and the
-objects are linked into paper_1107_1653_amd/libshapley.so.
+objects are linked into paper_1107_1653_amd/libshapley.so.  With --sanitize
+the host code (validation, engine, server) is instrumented with
+AddressSanitizer and UndefinedBehaviorSanitizer and the library is written to
+<dir>/libshapley.so (device code is built as usual); load it with the
+sanitizer runtime preloaded (sanitizer_runtime()).
 """
 import concurrent.futures
 import os
@@ -26,9 +31,25 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = ["hipcc", *FLAGS, "-c", src, "-o", obj]
+# host-side sanitizers: every -fsanitize applies to the host compilation only
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+SANITIZE_LINK = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-shared-libasan"]
+
+
+def sanitizer_runtime() -> str:
+    """Path of the AddressSanitizer runtime of the compiler (to preload)."""
+    r = subprocess.run(["hipcc", "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if r.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
+        raise RuntimeError("AddressSanitizer runtime of hipcc not found")
+    return path
+
+
+def _compile(src: str, out_dir: str = BUILD, extra=()) -> str:
+    obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+    cmd = ["hipcc", *FLAGS, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -38,21 +59,28 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = True) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = True, sanitize_dir: str = "") -> str:
+    out_dir = os.path.join(sanitize_dir, "obj") if sanitize_dir else BUILD
+    lib = os.path.join(sanitize_dir, "libshapley.so") if sanitize_dir else LIB
+    extra = SANITIZE if sanitize_dir else []
+    os.makedirs(out_dir, exist_ok=True)
     srcs = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+        objs = list(ex.map(lambda f: _compile(f, out_dir, extra), srcs))
+    tmp = lib + ".tmp"
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *(SANITIZE_LINK if sanitize_dir else []), "-o", tmp,
+           *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {lib}")
+    return lib
 
 
 if __name__ == "__main__":
-    build()
+    if len(sys.argv) == 3 and sys.argv[1] == "--sanitize":
+        build(sanitize_dir=os.path.abspath(sys.argv[2]))
+    else:
+        build()
