@@ -305,6 +305,7 @@ void Engine::build_layout() {
   up(gtiles_all.p, h_gtiles_all.data(), h_gtiles_all.size());
   gtiles_imp.ensure(std::max<size_t>(h_gtiles_imp.size(), 1));
   up(gtiles_imp.p, h_gtiles_imp.data(), h_gtiles_imp.size());
+  launch_tile_entries(ddesc.p, gtiles_imp.p, (int)h_gtiles_imp.size(), stream);
 
   int maxlev = 2;
   for (auto* s : slots) maxlev = std::max(maxlev, s->opt.max_levels + 1);

@@ -258,7 +258,8 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
   const bool mine = tid < ns * K;
   const int row = row0 + tid;
   const int e0 = mine ? d.rp[row] : 0, e1 = mine ? d.rp[row + 1] : 0;
-  const int eb = d.rp[row0], ee = d.rp[row0 + ns * K];
+  // the tile's entry range: stored in the tile (one dependent load less)
+  const int eb = FLAT ? d.rp[row0] : t.e0, ee = FLAT ? d.rp[row0 + ns * K] : t.e1;
   // loads that do not depend on the products, issued before the stages
   const double rr = mine ? d.r[row] : 0.0;
   const bool ok = mine && (d.valid ? (d.valid[row] != 0) : true);
@@ -381,6 +382,23 @@ void launch_improve(const GameDesc* d, const GTile* t, int nt, const int* active
                     Stripes red, hipStream_t s) {
   if (nt == 0) return;
   hipLaunchKernelGGL(k_improve<false>, dim3(nt), dim3(kBlock), 0, s, d, t, active, tie_rtol, red, GameDesc{}, 0);
+  SHP_LAUNCH_CHECK();
+}
+
+__global__ void k_tile_entries(const GameDesc* __restrict__ gd, GTile* __restrict__ tiles, int nt) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nt) return;
+  GTile t = tiles[k];
+  const GameDesc& d = gd[t.game];
+  const int K = d.m1 * d.m2;
+  t.e0 = d.rp[(size_t)t.s0 * K];
+  t.e1 = d.rp[(size_t)t.s1 * K];
+  tiles[k] = t;
+}
+
+void launch_tile_entries(const GameDesc* d, GTile* t, int nt, hipStream_t s) {
+  if (nt == 0) return;
+  hipLaunchKernelGGL(k_tile_entries, dim3(grid_for(nt)), dim3(kBlock), 0, s, d, t, nt);
   SHP_LAUNCH_CHECK();
 }
 

@@ -42,6 +42,7 @@ struct GameDesc {
 // State range of one game for work-list kernels.
 struct GTile {
   int game, s0, s1;
+  int e0 = 0, e1 = 0;  // improvement tiles: the entry range of the tile's rows
 };
 
 // Device-resident game (the payload of a shapley_game_t).
@@ -517,6 +518,8 @@ void launch_improve(const GameDesc* d, const GTile* t, int nt, const int* active
 // incumbents, outputs not stored); its reductions fold into red as game 0.
 void launch_improve_flat(const GameDesc& d, double tie_rtol, Stripes red, hipStream_t s);
 int improve_states_per_tile(int m1, int m2);
+// the entry range [e0, e1) of each improvement tile's rows, from the games' row pointers
+void launch_tile_entries(const GameDesc* d, GTile* t, int nt, hipStream_t s);
 void launch_fold_finish(Stripes st, int G, int nd, unsigned sum_mask, int ni, double* out_d, int sd, int* out_i,
                         int si, hipStream_t s);
 // combines the FP64-residual stripes (max |r|, max |x|) and takes the stop
