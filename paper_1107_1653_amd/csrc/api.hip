@@ -260,24 +260,55 @@ void shp::check_warm_start(Game* g, const int32_t* alpha0, const int32_t* beta0,
 
 namespace shp {
 
-static void load_warm_start(Game* g, const shapley_solve_opts& o, SlotState& S, hipStream_t s) {
+// The default start of a solve (v = 0, no incumbent strategies) of several
+// games in one launch: blockIdx.y is the game; null arrays are left as they are.
+struct StartDesc {
+  double* v;
+  int* alpha;
+  int* beta;
+  int n;
+};
+__global__ void k_reset_start(const StartDesc* __restrict__ d, StartDesc one) {
+  const StartDesc g = d ? d[blockIdx.y] : one;
+  for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < g.n; x += gridDim.x * blockDim.x) {
+    if (g.v) g.v[x] = 0.0;
+    if (g.alpha) g.alpha[x] = -1;
+    if (g.beta) g.beta[x] = -1;
+  }
+}
+static unsigned reset_blocks(int n) { return (unsigned)std::max(1, std::min((n + kBlock - 1) / kBlock, 256)); }
+
+static void load_warm_start(Game* g, const shapley_solve_opts& o, SlotState& S, hipStream_t s,
+                            std::vector<StartDesc>* defer = nullptr) {
   const int n = g->n;
   check_warm_start(g, o.alpha0, o.beta0, s);
-  if (o.v0) h2d(g->v.p, o.v0, n, s);
-  else fill_async(g->v.p, 0.0, n, s);
+  bool copied = false;
+  if (o.v0) {
+    h2d(g->v.p, o.v0, n, s);
+    copied = true;
+  }
   if (o.alpha0) {
     h2d(g->alpha.p, o.alpha0, n, s);
     S.init_alpha = true;
-  } else {
-    fill_async(g->alpha.p, -1, n, s);
+    copied = true;
   }
   if (o.alpha0 && o.beta0) {
     h2d(g->beta.p, o.beta0, n, s);
     S.init_beta = true;
-  } else {
-    fill_async(g->beta.p, -1, n, s);
+    copied = true;
   }
-  SHP_HIP(hipStreamSynchronize(s));
+  const StartDesc d{o.v0 ? nullptr : g->v.p, o.alpha0 ? nullptr : g->alpha.p,
+                    (o.alpha0 && o.beta0) ? nullptr : g->beta.p, n};
+  if (d.v || d.alpha || d.beta) {
+    if (defer) {
+      defer->push_back(d);  // one launch for the games of a batch
+    } else {
+      hipLaunchKernelGGL(k_reset_start, dim3(reset_blocks(n)), dim3(kBlock), 0, s, (const StartDesc*)nullptr, d);
+      SHP_LAUNCH_CHECK();
+    }
+  }
+  // the caller's host arrays are no longer read once this returns
+  if (copied) SHP_HIP(hipStreamSynchronize(s));
 }
 
 static void fill_stats(const SlotState& S, shapley_stats* st, double seconds) {
@@ -494,12 +525,23 @@ int shapley_solve_batch(shapley_game_t* games, int32_t count, const shapley_solv
     hipStream_t s = o.stream ? (hipStream_t)o.stream : games[0]->g->stream;
     double t0 = now_s();
     EngineLease eng(s, o.stream == nullptr);
+    std::vector<StartDesc> starts;
+    int nmax = 1;
     for (int i = 0; i < count; ++i) {
       Game* g = games[i]->g;
       S[i].g = g;
       S[i].opt = engine_opts_from(o, g->dim);
-      load_warm_start(g, o, S[i], s);
+      load_warm_start(g, o, S[i], s, &starts);
+      nmax = std::max(nmax, g->n);
       eng->slots.push_back(&S[i]);
+    }
+    DBuf<StartDesc> dstarts(std::max<size_t>(starts.size(), 1));
+    for (size_t k0 = 0; k0 < starts.size(); k0 += 65535) {  // grid y limit
+      const size_t k1 = std::min(starts.size(), k0 + 65535);
+      h2d(dstarts.p + k0, starts.data() + k0, k1 - k0, s);
+      hipLaunchKernelGGL(k_reset_start, dim3(reset_blocks(nmax), (unsigned)(k1 - k0)), dim3(kBlock), 0, s,
+                         (const StartDesc*)(dstarts.p + k0), StartDesc{});
+      SHP_LAUNCH_CHECK();
     }
     while (eng->step() > 0) {
     }
