@@ -1055,7 +1055,7 @@ void Engine::refresh(const EngineOpts& o) {
         // the A P rows of the changed fine rows, then the coarse rows they reach
         amg_drap_known(L.n, L.nc, L.drap_maxc, L.drap_tab.p, G, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p,
                        L.rrp.p, L.rci.p, L.rv64.p, L.dap.p, Ln.rp.p, Ln.ci.p, Ln.a64.p, stream, Ln.chg.p, L.chg.p);
-        probe_end(kProbeRap, stream, (double)Ln.nnz * 12 + (double)L.nnz * 12 + (double)n * PW * 12);
+        probe_end(kProbeRap, stream, 0.0);  // a refresh recomputes the changed rows only: no bytes claimed
       } else if (L.apf) {
         // A P rows of the changed fine rows, then the coarse rows they reach
         s_big.ensure(2 * ((size_t)std::max(n, L.nc) + 1));
@@ -1064,13 +1064,13 @@ void Engine::refresh(const EngineOpts& o) {
         amg_rap_known(n, L.id_rp.p, L.id_ci.p, L.id_rv.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, L.ap_rp.p,
                       L.ap_ci.p, L.ap_v.p, s_err.p + 1, s_big.p, stream, L.chg.p, s_list.p,
                       gal_kernel((double)L.ap_nnz / std::max(n, 1), false));
-        probe_end(kProbeRap, stream, (double)L.ap_nnz * 12 + (double)L.nnz * 12 + (double)n * PW * 12);
+        probe_end(kProbeRap, stream, 0.0);  // a refresh recomputes the changed rows only: no bytes claimed
         probe_begin(kProbeRap, stream);
         s_list.ensure((size_t)L.nc + 1);
         amg_rap_known(L.nc, L.rrp.p, L.rci.p, L.rv64.p, L.ap_rp.p, L.ap_ci.p, L.ap_v.p, L.id_pc.p, L.id_pv.p,
                       Ln.rp.p, Ln.ci.p, Ln.a64.p, s_err.p + 1, s_big.p, stream, Ln.chg.p, s_list.p,
                       gal_kernel((double)Ln.nnz / std::max(L.nc, 1), true));
-        probe_end(kProbeRap, stream, (double)Ln.nnz * 12 + (double)L.ap_nnz * 12);
+        probe_end(kProbeRap, stream, 0.0);  // a refresh recomputes the changed rows only: no bytes claimed
       } else {
         s_big.ensure(2 * ((size_t)L.nc + 1));
         s_list.ensure((size_t)L.nc + 1);
@@ -1078,7 +1078,7 @@ void Engine::refresh(const EngineOpts& o) {
         amg_rap_known(L.nc, L.rrp.p, L.rci.p, L.rv64.p, L.rp.p, L.ci.p, L.a64.p, L.pc.p, L.pv64.p, Ln.rp.p,
                       Ln.ci.p, Ln.a64.p, s_err.p + 1, s_big.p, stream, Ln.chg.p, s_list.p,
                       gal_kernel((double)Ln.nnz / std::max(L.nc, 1), false));
-        probe_end(kProbeRap, stream, (double)Ln.nnz * 12 + (double)L.nnz * 12 + (double)n * PW * 12);
+        probe_end(kProbeRap, stream, 0.0);  // a refresh recomputes the changed rows only: no bytes claimed
       }
     }
     if (L.nblk)
@@ -1386,9 +1386,9 @@ void Engine::improve(const std::vector<int>& run, double tie_rtol) {
     for (int g : run) {
       const Game* gm = slots[g]->g;
       // per row: row pointer, reward, validity; per entry: column, weight;
-      // per state: value, F, and the five policy arrays
+      // per state: value, the five policy arrays and F when it is stored
       bytes += (double)gm->nrows * (4 + 8 + (gm->valid.p ? 1 : 0)) + (double)gm->nnz * 12 +
-               (double)gm->n * (8 + 8 + 5 * 4);
+               (double)gm->n * (8 + 5 * 4 + (keep_F ? 8 : 0));
     }
   probe_begin(kProbeImprove, stream);
   launch_improve(ddesc.p, gtiles_imp.p, (int)h_gtiles_imp.size(), d_active.p, tie_rtol, fold, stream);

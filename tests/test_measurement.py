@@ -67,8 +67,10 @@ def test_traffic_is_scaled_by_the_calibration_kernel(tmp_path):
 
 
 def test_traffic_of_the_largest_launches(tmp_path):
-    """bytes_per_launch covers each kernel's launches at its largest grid
-    (the finest level), the launch set of the benchmark's roofline."""
+    """bytes_per_launch covers the launches of one kernel of the family at its
+    largest grid -- the kernel moving the most bytes there in all (the
+    finest level) --, the launch set of the benchmark's roofline; a
+    refresh's Galerkin kernels are left out of it."""
     cal = rs.CALIB_BYTES
     fetch = [("void at::native::neg_kernel(...)", 1, cal / 2 / 1024),
              ("shp::k_smooth<float, 4>(...)", 4 << 20, 3000.0),
@@ -85,11 +87,22 @@ def test_traffic_of_the_largest_launches(tmp_path):
     write_counters(wcsv, "WRITE_SIZE", write)
     sm = rs.traffic(str(fcsv), str(wcsv))["families"]["smooth"]
     assert sm["launches"] == 4
-    # largest grid of each kernel: the two big k_smooth<float, 4> dispatches and
-    # the one k_smooth<float, 1> dispatch
-    assert sm["largest_launches"] == 3
-    assert sm["fetch_bytes_per_launch"] == pytest.approx(2.0 * 8010.0 * 1024 / 3)
-    assert sm["write_bytes_per_launch"] == pytest.approx(81.0 * 1024 / 3)
+    # the kernel moving the most at its largest grid: the two big
+    # k_smooth<float, 4> dispatches
+    assert sm["largest_launches"] == 2 and sm["kernel"] == "shp::k_smooth<float, 4>"
+    assert sm["fetch_bytes_per_launch"] == pytest.approx(2.0 * 8000.0 * 1024 / 2)
+    assert sm["write_bytes_per_launch"] == pytest.approx(80.0 * 1024 / 2)
+
+
+def test_refresh_kernels_are_not_the_roofline_launches():
+    assert rs.is_refresh("void shp::k_rap_small<1>(int)")
+    assert rs.is_refresh("void shp::k_rap_quad<1, 32>(int)")
+    assert rs.is_refresh("void shp::k_rap_list<128, 1>(int)")
+    assert rs.is_refresh("shp::k_drap_known(int)")
+    assert not rs.is_refresh("void shp::k_rap_quad<0, 32>(int)")
+    assert not rs.is_refresh("void shp::k_rap_small<0>(int)")
+    assert not rs.is_refresh("void shp::k_rap_list<128, 0>(int)")
+    assert not rs.is_refresh("void shp::k_smooth<float, 1>(int)")
 
 
 def test_traffic_needs_the_calibration_kernel(tmp_path):
