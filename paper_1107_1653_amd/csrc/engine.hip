@@ -150,6 +150,7 @@ void Engine::sync() {
 void Engine::reset() {
   slots.clear();
   layout_dirty = true;
+  asm_stale = true;
   have_hier = false;
   ++hier_gen;
   run_at_setup.clear();
@@ -337,6 +338,7 @@ void Engine::build_layout() {
   }
   h_active.assign(G, 0);
   h_lin_active.assign(G, 0);
+  asm_stale = true;
   layout_dirty = false;
 }
 
@@ -372,10 +374,22 @@ void Engine::assemble(const std::vector<int>& run, bool mixed) {
   L0.y64.ensure(std::max(N0, 1));
   d_norm.ensure(4 * std::max(G, 1));
   // refinement storage: solution in sol (L0.tmp is int; use dedicated buffers)
+  asm_pol.ensure(std::max(N0, 1));
+  asm_dinv.ensure(std::max(N0, 1));
+  // rows are kept only in the buffers they were built in
+  const std::array<const void*, 7> bufs{L0.a64.p, mixed ? L0.a32.p : nullptr, L0.dinv64.p,
+                                        mixed ? L0.dinv32.p : nullptr, rhs.p, asm_pol.p, asm_dinv.p};
+  if (asm_stale || asm_mixed != mixed || bufs != asm_bufs) {
+    asm_stale = true;
+    fill_async(asm_pol.p, -1, (size_t)std::max(N0, 1), stream);
+  }
+  asm_mixed = mixed;
+  asm_bufs = bufs;
   launch_gather_v(ddesc.p, gtiles_all.p, (int)h_gtiles_all.size(), d_active.p, sol.p, stream);
-  launch_assemble(ddesc.p, gtiles_all.p, (int)h_gtiles_all.size(), d_active.p, L0.rp.p, L0.a64.p,
-                  mixed ? L0.a32.p : nullptr, rhs.p, L0.dinv64.p, mixed ? L0.dinv32.p : nullptr,
-                  fold, stream);
+  launch_assemble(ddesc.p, gtiles_all.p, (int)h_gtiles_all.size(), d_active.p, L0.a64.p,
+                  mixed ? L0.a32.p : nullptr, rhs.p, L0.dinv64.p, mixed ? L0.dinv32.p : nullptr, asm_pol.p,
+                  asm_dinv.p, fold, stream);
+  asm_stale = false;
   launch_fold_finish(fold, G, 1, 0u, 0, d_bnorm.p, 1, nullptr, 0, stream);
   (void)run;
 }
@@ -1410,6 +1424,7 @@ void Engine::run_init(const std::vector<int>& run) {
   for (int g : run)
     if (slots[g]->need_init) fresh.push_back(g);
   if (fresh.empty()) return;
+  asm_stale = true;  // a slot's game starts: its level-0 rows were never built for it
   std::vector<int> act(G, 0);
   for (int g : fresh) act[g] = 1;
   up(d_active.p, act.data(), G);

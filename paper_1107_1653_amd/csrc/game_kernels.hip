@@ -109,6 +109,10 @@ void launch_scatter_v(const GameDesc* d, const GTile* t, int nt, const int* acti
 // Policy-system assembly.  Row x of A = I - mu M^{alpha beta} and
 // b = r^{alpha beta} (Sec. 4.2, eq. (LSPI)), written into the fixed level-0
 // pattern of the game (explicit zeros where the chosen row has no entry).
+// A row is rebuilt only when its pair (alpha(x), beta(x)) differs from the
+// one it was last built for (`pol`, -1: never built); 1/a_ii of the built
+// row is kept in `dbuilt` and copied to the relaxation diagonal of every row,
+// which the AMG setup rescales on Dirichlet rows.
 // ---------------------------------------------------------------------------
 __device__ inline double warp_max(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
@@ -130,14 +134,24 @@ __global__ __launch_bounds__(256) void k_assemble(const GameDesc* __restrict__ g
                                                   const int* __restrict__ active,
                                                   double* __restrict__ a64, float* __restrict__ a32,
                                                   double* __restrict__ b0, double* __restrict__ dinv64,
-                                                  float* __restrict__ dinv32, Stripes bnorm) {
+                                                  float* __restrict__ dinv32, int* __restrict__ pol,
+                                                  double* __restrict__ dbuilt, Stripes bnorm) {
   GTile t = tiles[blockIdx.x];
   if (!active[t.game]) return;
   const GameDesc d = gd[t.game];
   double bmax = 0.0;
   int x = t.s0 + threadIdx.x;
-  if (x < t.s1) {
-    const int s = (x * d.m1 + d.alpha[x]) * d.m2 + d.beta[x];
+  const int X = d.x_off + x;
+  const int q = x < t.s1 ? d.alpha[x] * d.m2 + d.beta[x] : -1;
+  if (x < t.s1 && q >= 0 && pol[X] == q) {
+    // the row already holds this pair's coefficients
+    const double rb = b0[X];
+    const double di = dbuilt[X];
+    dinv64[X] = di;
+    if (dinv32) dinv32[X] = (float)di;
+    bmax = rb == rb ? fabs(rb) : INFINITY;
+  } else if (x < t.s1) {
+    const int s = x * d.m1 * d.m2 + q;
     const int e0 = d.rp[s], e1 = d.rp[s + 1];
     const int j0 = d.urp[x], j1 = d.urp[x + 1];
     // the identity row on the level-0 pattern, then each entry of the chosen
@@ -188,25 +202,25 @@ __global__ __launch_bounds__(256) void k_assemble(const GameDesc* __restrict__ g
       if (a32)
         for (int j = j0; j < j1; ++j) a32[d.a_off + j] = (float)a64[d.a_off + j];
     }
-    int X = d.x_off + x;
-    double rb = d.r[s];
+    const double rb = d.r[s];
     b0[X] = rb;
-    double di = diag != 0.0 ? 1.0 / diag : 0.0;
+    const double di = diag != 0.0 ? 1.0 / diag : 0.0;
     dinv64[X] = di;
     if (dinv32) dinv32[X] = (float)di;
+    dbuilt[X] = di;
+    pol[X] = q;
     bmax = rb == rb ? fabs(rb) : INFINITY;
   }
   bmax = warp_max(bmax);
   block_fold<1, 0>(bnorm, t.game, &bmax, 0u, nullptr);
 }
 
-void launch_assemble(const GameDesc* d, const GTile* t, int nt, const int* active, const int* rp0,
-                     double* a64, float* a32, double* b0, double* dinv64, float* dinv32,
-                     Stripes bnorm, hipStream_t s) {
-  (void)rp0;
+void launch_assemble(const GameDesc* d, const GTile* t, int nt, const int* active, double* a64, float* a32,
+                     double* b0, double* dinv64, float* dinv32, int* pol, double* dbuilt, Stripes bnorm,
+                     hipStream_t s) {
   if (nt == 0) return;
   hipLaunchKernelGGL(k_assemble, dim3(nt), dim3(kBlock), 0, s, d, t, active, a64, a32, b0, dinv64,
-                     dinv32, bnorm);
+                     dinv32, pol, dbuilt, bnorm);
   SHP_LAUNCH_CHECK();
 }
 

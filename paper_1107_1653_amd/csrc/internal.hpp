@@ -4,6 +4,7 @@
 #include "../../include/shapley.h"
 #include "common.hpp"
 
+#include <array>
 #include <cstring>
 #include <memory>
 
@@ -425,6 +426,14 @@ class Engine {
   std::vector<int> h_active, h_lin_active;
   // refinement storage on the merged level 0
   DBuf<double> sol, rhs, d_bnorm;
+  // assembled level 0: the pair each row was built for and its 1/a_ii;
+  // asm_stale forces a rebuild of every row (new layout, new games, other
+  // precision)
+  DBuf<int> asm_pol;
+  DBuf<double> asm_dinv;
+  bool asm_stale = true;
+  bool asm_mixed = false;
+  std::array<const void*, 7> asm_bufs{};  // level-0 buffers the rows were built in
   // setup scratch
   DBuf<int> s_cnt, s_cursor, s_scan, s_err, s_left, s_newc, s_gidx, s_gout, s_goff;
   DBuf<int> s_toff, s_tcol;   // Galerkin product scratch rows (offsets, columns)
@@ -508,9 +517,11 @@ void launch_gather_v(const GameDesc* d, const GTile* t, int nt, const int* activ
                      hipStream_t s);
 void launch_scatter_v(const GameDesc* d, const GTile* t, int nt, const int* active, const double* x0,
                       hipStream_t s);
-void launch_assemble(const GameDesc* d, const GTile* t, int nt, const int* active, const int* rp0,
-                     double* a64, float* a32, double* b0, double* dinv64, float* dinv32,
-                     Stripes bnorm, hipStream_t s);
+// Rows whose (alpha, beta) equals pol[X] are kept (pol = -1: rebuild); the
+// rebuilt rows record their pair in pol and 1/a_ii in dbuilt.
+void launch_assemble(const GameDesc* d, const GTile* t, int nt, const int* active, double* a64, float* a32,
+                     double* b0, double* dinv64, float* dinv32, int* pol, double* dbuilt, Stripes bnorm,
+                     hipStream_t s);
 void launch_improve(const GameDesc* d, const GTile* t, int nt, const int* active, double tie_rtol,
                     Stripes red, hipStream_t s);
 // The same sweep over one game passed by value, tiles computed from the block

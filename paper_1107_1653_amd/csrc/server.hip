@@ -129,7 +129,7 @@ namespace shp {
 static size_t estimate_footprint(Game* h) {
   Game* f = h->finest();
   size_t b = h->device_bytes();
-  b += (size_t)f->n * (24 * sizeof(double) + 10 * sizeof(int)) + (size_t)f->unnz * 3 * (sizeof(double) + 4);
+  b += (size_t)f->n * (25 * sizeof(double) + 11 * sizeof(int)) + (size_t)f->unnz * 3 * (sizeof(double) + 4);
   b += (size_t)f->unnz * PW * PW * (sizeof(double) + sizeof(int));
   return b;
 }
