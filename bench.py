@@ -57,7 +57,7 @@ def parse_args():
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--headline-only", action="store_true",
                     help="the headline's timed steps only (for kernel traces): no FP64 or one-by-one runs")
-    ap.add_argument("--forcing", type=float, default=0.1)
+    ap.add_argument("--forcing", type=float, default=0.2)
     ap.add_argument("--reuse", type=float, default=0.5)
     ap.add_argument("--games", type=int, default=256, help="C3 batch size")
     ap.add_argument("--requests", type=int, default=1000, help="C4 requests")

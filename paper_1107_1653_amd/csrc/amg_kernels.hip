@@ -15,27 +15,6 @@ namespace shp {
 // ---------------------------------------------------------------------------
 // setup: Dirichlet rows (no non-zero off-diagonal) and strength
 // ---------------------------------------------------------------------------
-__global__ void k_dirichlet(const Tile* __restrict__ tiles, const int* __restrict__ rp,
-                            const int* __restrict__ ci, const double* __restrict__ a,
-                            uint8_t* __restrict__ dir) {
-  Tile t = tiles[blockIdx.x];
-  int i = t.r0 + threadIdx.x;
-  if (i >= t.r1) return;
-  bool any = false;
-  for (int e = rp[i]; e < rp[i + 1]; ++e)
-    if (ci[e] != i && a[e] != 0.0) any = true;
-  dir[i] = any ? 0 : 1;
-}
-
-__global__ void k_dir_scale(const Tile* __restrict__ tiles, const uint8_t* __restrict__ dir, double f,
-                            double* __restrict__ d64, float* __restrict__ d32) {
-  Tile t = tiles[blockIdx.x];
-  int i = t.r0 + threadIdx.x;
-  if (i >= t.r1 || !dir[i]) return;
-  d64[i] *= f;
-  if (d32) d32[i] = (float)d64[i];
-}
-
 // j strongly influences i when -a_ij >= theta max_{k != i} (-a_ik) (classical
 // strength for M-matrix rows); Dirichlet columns are never strong.
 // lam[j] counts the rows that depend strongly on j.
@@ -2584,19 +2563,6 @@ void amg_mark_coarse(const Tile* t, int nt, const int* pc, const uint8_t* chg, u
 // ---------------------------------------------------------------------------
 // level helpers
 // ---------------------------------------------------------------------------
-__global__ void k_diag_inv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                           const double* __restrict__ a, double* __restrict__ d64,
-                           float* __restrict__ d32) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double d = 0.0;
-  for (int e = rp[i]; e < rp[i + 1]; ++e)
-    if (ci[e] == i) d += a[e];
-  double di = d != 0.0 ? 1.0 / d : 0.0;
-  d64[i] = di;
-  if (d32) d32[i] = (float)di;
-}
-
 __global__ void k_cast(const double* __restrict__ in, float* __restrict__ out, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = (float)in[i];
@@ -3070,6 +3036,56 @@ __global__ __launch_bounds__(256) void k_diag_dir(const Tile* __restrict__ tiles
   if (d32) d32[i] = (float)di;
 }
 
+// Strength of connection and its transpose with G lanes per row (levels of
+// medium rows): the lanes take the row's entries in turn; the row maximum
+// (order-independent) by shuffles within the row's lanes.  Same flags and
+// counts as the thread-per-row and wavefront-per-row kernels.
+template <int G>
+__global__ __launch_bounds__(256) void k_strength_g(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                                                    const int* __restrict__ ci, const double* __restrict__ a,
+                                                    const uint8_t* __restrict__ dir, double theta,
+                                                    uint8_t* __restrict__ strong, int* __restrict__ lam) {
+  const unsigned bid = blockIdx.x;
+  const Tile t = tiles[bid / G];
+  int gl;
+  const int i = tile_row<G>(t, gl, bid);
+  const bool in = i < t.r1;
+  const int e0 = in ? rp[i] : 0, e1 = in ? rp[i + 1] : 0;
+  const bool di = !in || dir[i] != 0;
+  double m = 0.0;
+  if (!di)
+    for (int e = e0 + gl; e < e1; e += G) {
+      const int j = ci[e];
+      if (j != i && !dir[j]) m = fmax(m, -a[e]);
+    }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  for (int e = e0 + gl; e < e1; e += G) {
+    const int j = ci[e];
+    const bool st = !di && j != i && !dir[j] && m > 0.0 && -a[e] >= theta * m;
+    strong[e] = st ? 1 : 0;
+    if (st) atomicAdd(&lam[j], 1);
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_strength_t_g(const Tile* __restrict__ tiles, const int* __restrict__ rp,
+                                                      const int* __restrict__ ci, const uint8_t* __restrict__ strong,
+                                                      const int* __restrict__ st_rp, int* __restrict__ cursor,
+                                                      int* __restrict__ st_ci) {
+  const unsigned bid = blockIdx.x;
+  const Tile t = tiles[bid / G];
+  int gl;
+  const int i = tile_row<G>(t, gl, bid);
+  if (i >= t.r1) return;
+  for (int e = rp[i] + gl; e < rp[i + 1]; e += G)
+    if (strong[e]) {
+      const int j = ci[e];
+      const int pos = atomicAdd(&cursor[j], 1);
+      st_ci[st_rp[j] + pos] = i;
+    }
+}
+
 template <class T, int G>
 __global__ __launch_bounds__(256) void k_restrict(const Tile* __restrict__ tiles, const int* __restrict__ act,
                                                   const int* __restrict__ rrp, const int* __restrict__ rci,
@@ -3394,12 +3410,6 @@ void amg_level_init(int n, int nnz, int* lam, int8_t* cf, uint8_t* dir, uint8_t*
   hipLaunchKernelGGL(k_level_init, dim3(grid_for(m)), dim3(kBlock), 0, s, n, nnz, lam, cf, dir, strong);
   SHP_LAUNCH_CHECK();
 }
-void amg_dirichlet(const Tile* t, int nt, const int* rp, const int* ci, const double* a, uint8_t* dir,
-                   hipStream_t s) {
-  if (!nt) return;
-  hipLaunchKernelGGL(k_dirichlet, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, a, dir);
-  SHP_LAUNCH_CHECK();
-}
 void amg_diag_dir(const Tile* t, int nt, const int* rp, const int* ci, const double* a, bool keep_diag,
                   double inv_omega, uint8_t* dir, double* d64, float* d32, int g, hipStream_t s,
                   const uint8_t* only) {
@@ -3416,28 +3426,28 @@ void amg_diag_dir(const Tile* t, int nt, const int* rp, const int* ci, const dou
                        only);
   SHP_LAUNCH_CHECK();
 }
-void amg_dir_scale(const Tile* t, int nt, const uint8_t* dir, double f, double* d64, float* d32,
-                   hipStream_t s) {
-  if (!nt) return;
-  hipLaunchKernelGGL(k_dir_scale, dim3(nt), dim3(kTileRows), 0, s, t, dir, f, d64, d32);
-  SHP_LAUNCH_CHECK();
-}
 void amg_strength(const Tile* t, int nt, const int* rp, const int* ci, const double* a,
-                  const uint8_t* dir, double theta, uint8_t* strong, int* lam, bool wide, hipStream_t s) {
+                  const uint8_t* dir, double theta, uint8_t* strong, int* lam, int lanes, hipStream_t s) {
   if (!nt) return;
-  if (wide)
+  if (lanes == 64)
     hipLaunchKernelGGL(k_strength_w, dim3(nt * (kTileRows / 4)), dim3(256), 0, s, t, rp, ci, a, dir, theta, strong,
+                       lam);
+  else if (lanes == 4)
+    hipLaunchKernelGGL(k_strength_g<4>, dim3(nt * 4), dim3(kTileRows), 0, s, t, rp, ci, a, dir, theta, strong,
                        lam);
   else
     hipLaunchKernelGGL(k_strength, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, a, dir, theta, strong, lam);
   SHP_LAUNCH_CHECK();
 }
 void amg_strength_t(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
-                    const int* st_rp, int* cursor, int* st_ci, bool wide, hipStream_t s) {
+                    const int* st_rp, int* cursor, int* st_ci, int lanes, hipStream_t s) {
   if (!nt) return;
-  if (wide)
+  if (lanes == 64)
     hipLaunchKernelGGL(k_strength_t_w, dim3(nt * (kTileRows / 4)), dim3(256), 0, s, t, rp, ci, strong, st_rp,
                        cursor, st_ci);
+  else if (lanes == 4)
+    hipLaunchKernelGGL(k_strength_t_g<4>, dim3(nt * 4), dim3(kTileRows), 0, s, t, rp, ci, strong, st_rp, cursor,
+                       st_ci);
   else
     hipLaunchKernelGGL(k_strength_t, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, strong, st_rp, cursor,
                        st_ci);
@@ -3749,12 +3759,6 @@ void amg_drap_known(int nf, int nc, int maxc, const long long* tab, int G, const
   SHP_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_drap_known, dim3(drap_blocks(64LL * nc)), dim3(kBlock), 0, s, nc, tab, G, rrp, rci, rv, ap,
                      crp, cci, cval, only);
-  SHP_LAUNCH_CHECK();
-}
-void amg_diag_inv(int n, const int* rp, const int* ci, const double* a, double* d64, float* d32,
-                  hipStream_t s) {
-  if (!n) return;
-  hipLaunchKernelGGL(k_diag_inv, dim3(grid_for(n)), dim3(kBlock), 0, s, n, rp, ci, a, d64, d32);
   SHP_LAUNCH_CHECK();
 }
 void amg_cast(const double* in, float* out, size_t n, hipStream_t s) {

@@ -7,19 +7,18 @@ namespace shp {
 
 // lam[0..n] = 0, cf[0..n) = -2, dir[0..n) = 1, strong[0..nnz) = 0
 void amg_level_init(int n, int nnz, int* lam, int8_t* cf, uint8_t* dir, uint8_t* strong, hipStream_t s);
-void amg_dirichlet(const Tile* t, int nt, const int* rp, const int* ci, const double* a, uint8_t* dir,
-                   hipStream_t s);
+// Relaxation data of the tiles' rows in one pass, g lanes per row: Dirichlet
+// flag (no nonzero off-diagonal entry), 1/a_ii (kept from d64 when
+// keep_diag), divided by omega on Dirichlet rows.
 // only: rows with a nonzero flag (others keep their data), or null for all
 void amg_diag_dir(const Tile* t, int nt, const int* rp, const int* ci, const double* a, bool keep_diag,
                   double inv_omega, uint8_t* dir, double* d64, float* d32, int g, hipStream_t s,
                   const uint8_t* only = nullptr);
-void amg_dir_scale(const Tile* t, int nt, const uint8_t* dir, double f, double* d64, float* d32,
-                   hipStream_t s);
-// wide: one wavefront per row (levels whose rows are long)
+// lanes per row: 1, 4, or 64 (one wavefront per row, levels whose rows are long)
 void amg_strength(const Tile* t, int nt, const int* rp, const int* ci, const double* a,
-                  const uint8_t* dir, double theta, uint8_t* strong, int* lam, bool wide, hipStream_t s);
+                  const uint8_t* dir, double theta, uint8_t* strong, int* lam, int lanes, hipStream_t s);
 void amg_strength_t(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
-                    const int* st_rp, int* cursor, int* st_ci, bool wide, hipStream_t s);
+                    const int* st_rp, int* cursor, int* st_ci, int lanes, hipStream_t s);
 void amg_pmis_init(const Tile* t, int nt, const int* goff, const uint8_t* dir, const int* lam,
                    uint32_t salt, int8_t* cf, uint64_t* key, hipStream_t s);
 void amg_pmis_select(const Tile* t, int nt, const int* rp, const int* ci, const uint8_t* strong,
@@ -107,8 +106,6 @@ void amg_drap_known(int nf, int nc, int maxc, const long long* tab, int G, const
                     const double* a, const int* pc, const double* pv, const int* rrp, const int* rci,
                     const double* rv, double* ap, const int* crp, const int* cci, double* cval, hipStream_t s,
                     const uint8_t* only, const uint8_t* only_f);
-void amg_diag_inv(int n, const int* rp, const int* ci, const double* a, double* d64, float* d32,
-                  hipStream_t s);
 void amg_cast(const double* in, float* out, size_t n, hipStream_t s);
 void amg_dense_inv(const int* blk, int nblk, const int* rp, const int* ci, const double* a, double* work,
                    double* inv64, float* inv32, int* err, int max_nb, hipStream_t s,

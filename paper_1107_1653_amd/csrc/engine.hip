@@ -548,19 +548,15 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
     if (l > 0) {
       L.dinv64.ensure(std::max(n, 1));
       if (mixed) L.dinv32.ensure(std::max(n, 1));
-      amg_diag_inv(n, L.rp.p, L.ci.p, L.a64.p, L.dinv64.p, mixed ? L.dinv32.p : nullptr, stream);
       if (mixed) {
         L.a32.ensure(std::max(L.nnz, 1));
         amg_cast(L.a64.p, L.a32.p, L.nnz, stream);
       }
     }
     build_tiles(L, L.present, false);
-    L.gA = tune_lanes(L, mixed);
-    pt.mark("diag+tiles");
+    L.dir.ensure(std::max(n, 1));
     if (any_cont) {
       build_tiles(L, L.cont, true);
-      // ---- strength of connection
-      L.dir.ensure(std::max(n, 1));
       L.strong.ensure(std::max(L.nnz, 1));
       L.lam.ensure(n + 1);
       L.cf.ensure(std::max(n, 1));
@@ -569,20 +565,26 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
       L.tmp.ensure(n + 1);
       // cf = -2 on rows of terminal games, which no tile covers
       amg_level_init(n, L.nnz, L.lam.p, L.cf.p, L.dir.p, L.strong.p, stream);
-      amg_dirichlet(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, L.dir.p, stream);
-      const bool wide_rows = (long long)L.nnz > (long long)kApRowLen * n;  // one wavefront per row
-      amg_strength(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, L.dir.p, theta, L.strong.p, L.lam.p, wide_rows,
+    }
+    // 1/a_ii (level 0: the assembly's), Dirichlet flags, and Dirichlet rows
+    // relaxed exactly (unit weight), in one pass
+    amg_diag_dir(L.tiles.p, L.ntiles, L.rp.p, L.ci.p, L.a64.p, l == 0, 1.0 / o.omega, L.dir.p, L.dinv64.p,
+                 mixed ? L.dinv32.p : nullptr, L.gA, stream);
+    L.gA = tune_lanes(L, mixed);
+    pt.mark("diag+tiles");
+    if (any_cont) {
+      // ---- strength of connection: a thread, four lanes or a wavefront per row
+      const bool wide_rows = (long long)L.nnz > (long long)kApRowLen * n;
+      const int slanes = wide_rows ? 64 : row_group((double)L.nnz / std::max(n, 1));
+      amg_strength(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, L.dir.p, theta, L.strong.p, L.lam.p, slanes,
                    stream);
-      // Dirichlet rows are relaxed exactly (unit weight)
-      amg_dir_scale(L.ctiles.p, L.nctiles, L.dir.p, 1.0 / o.omega, L.dinv64.p, mixed ? L.dinv32.p : nullptr,
-                    stream);
       // transpose of the strength pattern
       L.st_rp.ensure(n + 1);
       scan_exclusive(L.lam.p, L.st_rp.p, n + 1, stream, s_scan);
       L.st_ci.ensure(std::max(L.nnz, 1));  // strong entries never exceed the entries of A
       s_cursor.ensure(n + 1);
       fill_async(s_cursor.p, 0, (size_t)n + 1, stream);
-      amg_strength_t(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.strong.p, L.st_rp.p, s_cursor.p, L.st_ci.p, wide_rows,
+      amg_strength_t(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.strong.p, L.st_rp.p, s_cursor.p, L.st_ci.p, slanes,
                      stream);
       pt.mark("strength");
       // ---- PMIS

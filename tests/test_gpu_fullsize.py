@@ -34,7 +34,7 @@ from oracle.jobs import Jobs
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-BENCH = dict(max_outer=5000, max_inner=5000, forcing=0.1, reuse_frac=0.5)
+BENCH = dict(max_outer=5000, max_inner=5000, forcing=0.2, reuse_frac=0.5)
 
 
 def ref_of(d):
