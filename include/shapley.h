@@ -91,7 +91,7 @@ typedef struct shapley_solve_opts {
   double lin_atol;       /* ... or <= lin_atol (absolute) */
   double tie_rtol;       /* an incumbent action is kept unless beaten by more than
                             tie_rtol * (|r| + mu sum |w||v|) of the compared rows */
-  double theta;          /* strength threshold; <= 0 picks 0.25 (dim <= 2) / 0.5 */
+  double theta;          /* strength threshold; <= 0 picks 0.25 (dim <= 2) / 0.3 */
   int32_t nu1, nu2;      /* pre/post Jacobi sweeps of the V(nu1,nu2) cycle */
   double omega;          /* Jacobi weight */
   int32_t coarse_max;    /* dense direct solve at or below this many unknowns */

@@ -348,7 +348,7 @@ __global__ void k_gather_int(const int* __restrict__ src, const int* __restrict_
 // ---------------------------------------------------------------------------
 constexpr int kIThreads = 64;
 constexpr int kIChat = 32;       // set cap of the interpolation formula
-constexpr int kIChatSmall = 16;  // first pass (grid stencils of 2-D problems fit)
+constexpr int kIChatSmall = 8;   // first pass (most rows of grid stencils fit)
 
 // Row i.  The set lives in this thread's column of the block's LDS arrays (C,
 // Wt: entry p at [p * kIThreads]).  DEFER: a row whose set would exceed CAP
@@ -2115,7 +2115,7 @@ __global__ __launch_bounds__(256) void k_rap_quad(int nc, const int* __restrict_
 // lane, 2 and 1 across the group).  Rows longer than 64 entries, with more
 // than 16 strong F neighbours or 32 set members, go to the wavefront kernel.
 // ---------------------------------------------------------------------------
-constexpr int kIqMem = 32, kIqHash = 64, kIqK = 16, kIqLen = 64;
+constexpr int kIqMem = 32, kIqHash = 64, kIqK = 8, kIqLen = 64;
 struct IqGroup {
   int hs[kIqHash];  // the set's hash, later the members' weights (kIqMem doubles)
   int mem[kIqMem];

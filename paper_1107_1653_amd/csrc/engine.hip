@@ -518,7 +518,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
   if (theta <= 0) {
     int dim = 0;
     for (int g : run) dim = std::max(dim, slots[g]->g->dim);
-    theta = dim >= 3 ? 0.5 : 0.25;
+    theta = dim >= 3 ? 0.3 : 0.25;
   }
   s_err.ensure(4);
   s_left.ensure(3);
