@@ -1391,6 +1391,7 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
     } else if (c.flags & 16) {
       S->status = SHAPLEY_ENOCONV;
       S->why = "the multigrid cycles diverge on this game's policy system (its AMG hierarchy does not fit it)";
+      S->diverged = true;
     }
     if (c.flags & 2) stagnated = true;
   }
@@ -1471,7 +1472,7 @@ static bool revisits(const SlotState* S, uint32_t h) {
 
 // a refresh is skipped while fewer than this fraction of the states changed
 // policy since the coarse operators were last formed
-constexpr double kLazyRefresh = 0.10;
+constexpr double kLazyRefresh = 0.20;
 
 int Engine::step() {
   if (layout_dirty) build_layout();
@@ -1504,6 +1505,10 @@ int Engine::step() {
               (double)changes_since_setup > o.reuse_frac * std::max(1, N0) ||
               last_cycles > std::max(2 * cycles_after_full, cycles_after_full + 6);
   stagnated = false;
+  double t1 = 0.0;
+  // a linear solve that diverges on a kept or refreshed hierarchy is done
+  // again, once, on a new one (from the same start)
+  for (int attempt = 0;; ++attempt) {
   for (int g : run) {
     if (full) ++slots[g]->setups_full; else ++slots[g]->setups_refresh;
   }
@@ -1538,7 +1543,7 @@ int Engine::step() {
                   mixed ? lv[l].dinv32.p : nullptr, stream);
   }
   pt.mark("setup");
-  double t1 = now_s();  // a full setup ends with a synchronisation; a refresh does not
+  t1 = now_s();  // a full setup ends with a synchronisation; a refresh does not
   {
     std::vector<int> before(G);
     for (int g : run) before[g] = slots[g]->cycles_total;
@@ -1547,6 +1552,20 @@ int Engine::step() {
     for (int g : run) mx = std::max(mx, slots[g]->cycles_total - before[g]);
     last_cycles = mx;
     if (cycles_after_full < 0) cycles_after_full = mx;
+  }
+  bool again = false;
+  if (!full && attempt == 0)
+    for (int g : run) again |= slots[g]->diverged;
+  if (!again) break;
+  for (int g : run) {
+    SlotState* S = slots[g];
+    if (!S->diverged) continue;
+    S->diverged = false;
+    S->status = SHAPLEY_OK;
+    S->why.clear();
+  }
+  launch_gather_v(ddesc.p, gtiles_all.p, (int)h_gtiles_all.size(), d_active.p, sol.p, stream);
+  full = true;
   }
   pt.mark("solve");
   double t2 = now_s();  // solve_linear ends with a synchronisation

@@ -234,6 +234,7 @@ struct SlotState {
   double res = 0.0, res_l2 = 0.0;
   double res_prev = INFINITY;   // Shapley residual after the previous value step
   bool loose = false;           // the last linear solve used the forcing tolerance
+  bool diverged = false;        // the last linear solve diverged
   bool exact = false;           // forcing off: cycling was seen after inexact solves
   std::vector<std::pair<uint32_t, double>> outer_hist;  // (strategy hash, residual) of outer steps
   int resolves = 0;             // consecutive accuracy re-solves at stable policies
