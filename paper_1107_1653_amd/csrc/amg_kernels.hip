@@ -3379,6 +3379,110 @@ __global__ __launch_bounds__(256) void k_resid64(const Tile* __restrict__ tiles,
   resid64_block<T, G>(t, bid, rp, ci, a, b, x, rc, norm);
 }
 
+// ---------------------------------------------------------------------------
+// Cycle kernels on the stencil form of level 0, one thread per row: slot t of
+// the row is loaded from its own array (coalesced over rows), its column is
+// the row plus the offset its code names.  Entry t goes into partial sum
+// t mod kAcc and the partial sums meet in row_sum's butterfly, so a row sum is
+// the same bit for bit as the CSR kernels'.
+// ---------------------------------------------------------------------------
+template <class T, class F>
+__device__ inline T st_row_sum(const StencilView& sv, const T* __restrict__ a, int i, const int* __restrict__ off,
+                               F f) {
+  // the game's offsets (the same for the whole tile) in registers
+  int o[kStencilMax];
+#pragma unroll
+  for (int q = 0; q < kStencilMax; ++q) o[q] = off[q];
+  const uint32_t c = sv.code[i];
+  const int len = (int)(c >> 24);
+  T v[kStencilMax];
+#pragma unroll
+  for (int t = 0; t < kStencilMax; ++t) v[t] = t < sv.w ? a[(size_t)t * sv.n + i] : (T)0;
+  T acc[kAcc];
+#pragma unroll
+  for (int j = 0; j < kAcc; ++j) acc[j] = 0;
+#pragma unroll
+  for (int t = 0; t < kStencilMax; ++t) {
+    const uint32_t ct = (c >> (3 * t)) & 7u;
+    int d = o[0];
+#pragma unroll
+    for (int q = 1; q < kStencilMax; ++q) d = ct == (uint32_t)q ? o[q] : d;
+    if (t < len) acc[t % kAcc] += v[t] * f(i + d);
+  }
+#pragma unroll
+  for (int o = kAcc / 2; o >= 1; o >>= 1) {
+#pragma unroll
+    for (int j = 0; j < o; ++j) acc[j] = acc[j] + acc[j + o];
+  }
+  return acc[0];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_smooth_st(const Tile* __restrict__ tiles, const int* __restrict__ act,
+                                                   StencilView sv, const T* __restrict__ a,
+                                                   const T* __restrict__ dinv, const T* __restrict__ b,
+                                                   const T* __restrict__ xin, T* __restrict__ xout, T omega,
+                                                   int first, double* __restrict__ sol) {
+  const Tile t = tiles[blockIdx.x];
+  if (!act[t.game]) return;
+  const int i = t.r0 + (int)threadIdx.x;
+  if (i >= t.r1) return;
+  const int* off = sv.off + kStencilMax * t.game;
+  if (first == 1) {
+    xout[i] = omega * dinv[i] * b[i];
+    return;
+  }
+  if (first == 2) {
+    const T ax = st_row_sum<T>(sv, a, i, off, [&](int j) -> T { return omega * dinv[j] * b[j]; });
+    const T x1 = omega * dinv[i] * b[i];
+    xout[i] = x1 + omega * dinv[i] * (b[i] - ax);
+    return;
+  }
+  const T ax = st_row_sum<T>(sv, a, i, off, [&](int j) -> T { return (T)xin[j]; });
+  const T xi = xin[i] + omega * dinv[i] * (b[i] - ax);
+  xout[i] = xi;
+  if (sol) sol[i] += (double)xi;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_resid_st(const Tile* __restrict__ tiles, const int* __restrict__ act,
+                                                  StencilView sv, const T* __restrict__ a,
+                                                  const T* __restrict__ b, const T* __restrict__ x,
+                                                  T* __restrict__ r) {
+  const Tile t = tiles[blockIdx.x];
+  if (!act[t.game]) return;
+  const int i = t.r0 + (int)threadIdx.x;
+  if (i >= t.r1) return;
+  const T ax = st_row_sum<T>(sv, a, i, sv.off + kStencilMax * t.game, [&](int j) -> T { return (T)x[j]; });
+  r[i] = b[i] - ax;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_resid64_st(const Tile* __restrict__ tiles, const int* __restrict__ act,
+                                                    StencilView sv, const double* __restrict__ a,
+                                                    const double* __restrict__ b, const double* __restrict__ x,
+                                                    T* __restrict__ rc, Stripes norm) {
+  const Tile t = tiles[blockIdx.x];
+  if (!act[t.game]) return;
+  const int i = t.r0 + (int)threadIdx.x;
+  double rm = 0.0, xm = 0.0;
+  if (i < t.r1) {
+    const double ax =
+        st_row_sum<double>(sv, a, i, sv.off + kStencilMax * t.game, [&](int j) -> double { return x[j]; });
+    const double s = b[i] - ax;
+    rc[i] = (T)s;
+    const double xi = x[i];
+    rm = s == s ? fabs(s) : INFINITY;  // NaN must survive the maximum
+    xm = xi == xi ? fabs(xi) : INFINITY;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    rm = fmax(rm, __shfl_xor(rm, o));
+    xm = fmax(xm, __shfl_xor(xm, o));
+  }
+  const double v[2] = {rm, xm};
+  block_fold<2, 0>(norm, t.game, v, 0u, nullptr);
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_update64(const Tile* __restrict__ tiles, const int* __restrict__ act,
                                                   const T* __restrict__ e, double* __restrict__ x) {
@@ -3508,7 +3612,7 @@ void amg_interp(const Tile* t, int nt, const int* rp, const int* ci, const doubl
                 const uint8_t* strong, const int8_t* cf, const int* cidx, const uint8_t* dir, int* pc,
                 double* pv, int* capped, int wave, int* defer, int rows, hipStream_t s) {
   if (!nt) return;
-  const unsigned lb = (unsigned)std::max(1, std::min(rows, 2048));
+  const unsigned lb = (unsigned)std::max(1, std::min(rows, 32768));  // wavefronts of the list kernels
   if (wave == 2) {
     // long rows: the 512-slot instance (18 KB of LDS per row) for all rows,
     // then the rows it could not hold with the largest one (33 KB)
@@ -3854,6 +3958,28 @@ void cyc_resid64(const Tile* t, int nt, const int* act, const int* rp, const int
   SHP_LAUNCH_CHECK();
 }
 template <class T>
+void cyc_smooth_st(const Tile* t, int nt, const int* act, const StencilView& sv, const T* a, const T* dinv,
+                   const T* b, const T* xin, T* xout, T omega, int first, hipStream_t s, double* sol) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_smooth_st<T>, dim3(nt), dim3(kTileRows), 0, s, t, act, sv, a, dinv, b, xin, xout, omega,
+                     first, sol);
+  SHP_LAUNCH_CHECK();
+}
+template <class T>
+void cyc_resid_st(const Tile* t, int nt, const int* act, const StencilView& sv, const T* a, const T* b, const T* x,
+                  T* r, hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_resid_st<T>, dim3(nt), dim3(kTileRows), 0, s, t, act, sv, a, b, x, r);
+  SHP_LAUNCH_CHECK();
+}
+template <class T>
+void cyc_resid64_st(const Tile* t, int nt, const int* act, const StencilView& sv, const double* a, const double* b,
+                    const double* x, T* rc, Stripes norm, hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_resid64_st<T>, dim3(nt), dim3(kTileRows), 0, s, t, act, sv, a, b, x, rc, norm);
+  SHP_LAUNCH_CHECK();
+}
+template <class T>
 void cyc_update64(const Tile* t, int nt, const int* act, const T* e, double* x, hipStream_t s) {
   if (!nt) return;
   hipLaunchKernelGGL(k_update64<T>, dim3(nt), dim3(kTileRows), 0, s, t, act, e, x);
@@ -3887,6 +4013,12 @@ void cyc_tail(const int* games, int ngames, int l0, int nlev, int G, const TailL
   template void cyc_resid64<T>(const Tile*, int, const int*, const int*, const int*, const double*,    \
                                const double*, const double*, T*, Stripes, int, hipStream_t);         \
   template void cyc_update64<T>(const Tile*, int, const int*, const T*, double*, hipStream_t);          \
+  template void cyc_smooth_st<T>(const Tile*, int, const int*, const StencilView&, const T*, const T*,  \
+                                 const T*, const T*, T*, T, int, hipStream_t, double*);              \
+  template void cyc_resid_st<T>(const Tile*, int, const int*, const StencilView&, const T*, const T*,   \
+                                const T*, T*, hipStream_t);                                          \
+  template void cyc_resid64_st<T>(const Tile*, int, const int*, const StencilView&, const double*,     \
+                                  const double*, const double*, T*, Stripes, hipStream_t);           \
   template void cyc_tail<T>(const int*, int, int, int, int, const TailLev<T>*, const TailGL*, const int*, T, int, \
                             int, int, int, hipStream_t, double*, const TailRefine*);
 SHP_INST(float)

@@ -148,5 +148,21 @@ void cyc_resid64(const Tile* t, int nt, const int* act, const int* rp, const int
                  const double* b, const double* x, T* rc, Stripes norm, int g, hipStream_t s);
 template <class T>
 void cyc_update64(const Tile* t, int nt, const int* act, const T* e, double* x, hipStream_t s);
+// the same sweeps and residuals on the stencil form of level 0 (the same sums
+// bit for bit); sv.off: kStencilMax offsets per game slot
+struct StencilView {
+  const uint32_t* code;
+  const int* off;
+  int w, n;
+};
+template <class T>
+void cyc_smooth_st(const Tile* t, int nt, const int* act, const StencilView& sv, const T* a, const T* dinv,
+                   const T* b, const T* xin, T* xout, T omega, int first, hipStream_t s, double* sol = nullptr);
+template <class T>
+void cyc_resid_st(const Tile* t, int nt, const int* act, const StencilView& sv, const T* a, const T* b, const T* x,
+                  T* r, hipStream_t s);
+template <class T>
+void cyc_resid64_st(const Tile* t, int nt, const int* act, const StencilView& sv, const double* a, const double* b,
+                    const double* x, T* rc, Stripes norm, hipStream_t s);
 
 }  // namespace shp

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <numeric>
 
@@ -53,6 +54,11 @@ static void finish_game(Game* g, const shapley_grid* grid, bool device_ptrs) {
   g->unnz = unnz;
   g->uci.alloc(std::max(unnz, 1));
   launch_union_fill(g->rp.p, g->ci.p, n, g->m1, g->m2, g->urp.p, g->uci.p, s);
+  // the pattern's offsets col - x: a stencil when few (grid games)
+  DBuf<int> st(2 + kStencilHash);
+  launch_stencil_scan(g->urp.p, g->uci.p, n, st.p, s);
+  int sth[2 + kStencilHash];
+  d2h(sth, st.p, 2 + kStencilHash, s);
   g->v.alloc(n); g->F.alloc(n);
   g->alpha.alloc(n); g->beta.alloc(n); g->beta_in.alloc(n); g->alpha_c.alloc(n); g->beta_c.alloc(n);
   fill_async(g->v.p, 0.0, n, s);
@@ -71,6 +77,18 @@ static void finish_game(Game* g, const shapley_grid* grid, bool device_ptrs) {
     }
   }
   SHP_HIP(hipStreamSynchronize(s));
+  g->st_off.clear();
+  g->st_w = 0;
+  if (sth[0] == 0 && sth[1] <= kStencilMax) {
+    std::vector<int> off;
+    for (int k = 0; k < kStencilHash; ++k)
+      if (sth[2 + k] != INT_MIN) off.push_back(sth[2 + k]);
+    if (!off.empty() && (int)off.size() <= kStencilMax) {
+      std::sort(off.begin(), off.end());
+      g->st_off = off;
+      g->st_w = sth[1];
+    }
+  }
 }
 
 static void check_grid(const shapley_grid* grid, int64_t n64) {
@@ -700,6 +718,15 @@ int shapley_tune_interp(int32_t kernel) {
     return SHAPLEY_EINVAL;
   }
   shp::set_interp_mode(kernel);
+  return SHAPLEY_OK;
+}
+
+int shapley_tune_stencil(int32_t mode) {
+  if (mode != -1 && mode != 0) {
+    shp::set_last_error("mode must be -1 or 0");
+    return SHAPLEY_EINVAL;
+  }
+  shp::set_stencil_mode(mode);
   return SHAPLEY_OK;
 }
 

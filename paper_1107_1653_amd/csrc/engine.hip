@@ -41,6 +41,7 @@ struct LV<float> {
   static float* y(Level& L) { return L.y32.p; }
   static float* b(Level& L) { return L.b32.p; }
   static float* r(Level& L) { return L.r32.p; }
+  static float* st(Level& L) { return L.st32.p; }
 };
 template <>
 struct LV<double> {
@@ -53,6 +54,7 @@ struct LV<double> {
   static double* y(Level& L) { return L.y64.p; }
   static double* b(Level& L) { return L.b64.p; }
   static double* r(Level& L) { return L.r64.p; }
+  static double* st(Level& L) { return L.st64.p; }
 };
 }  // namespace
 
@@ -92,6 +94,10 @@ void set_forced_rap_cols(int mode) { g_gal_mode.store(mode); }
 static std::atomic<int> g_interp_mode{-1};
 constexpr int kInterpQuadRows = 1 << 16;  // automatic choice: levels of at least this many rows
 void set_interp_mode(int mode) { g_interp_mode.store(mode); }
+// level 0 of stencil games in the stencil form for the cycle kernels: -1 when
+// every game is a stencil game (the default), 0 never (the same results)
+static std::atomic<int> g_stencil_mode{-1};
+void set_stencil_mode(int mode) { g_stencil_mode.store(mode); }
 static int gal_kernel(double cols, bool one_slot) {
   const int mode = g_gal_mode.load();
   if (mode == 0) return kGalWave;
@@ -318,6 +324,26 @@ void Engine::build_layout() {
   L0.ci.ensure(std::max(NNZ0, 1));
   launch_layout(ddesc.p, gtiles_all.p, (int)h_gtiles_all.size(), L0.rp.p, L0.ci.p, N0, NNZ0, stream);
   L0.goff = x_off;
+  // the stencil form of level 0: every game a stencil game, relaxation by
+  // whole sweeps (the C/F half sweeps keep the CSR kernels)
+  L0.stencil = g_stencil_mode.load() != 0 && G > 0 && slots[0]->opt.smoother != SHAPLEY_SMOOTH_CF;
+  L0.st_w = 0;
+  for (int g = 0; g < G && L0.stencil; ++g) {
+    const Game* gm = slots[g]->g;
+    L0.stencil = !gm->st_off.empty();
+    L0.st_w = std::max(L0.st_w, gm->st_w);
+  }
+  if (L0.stencil) {
+    std::vector<int> off((size_t)kStencilMax * G, 0);
+    for (int g = 0; g < G; ++g) {
+      const std::vector<int>& o = slots[g]->g->st_off;
+      std::copy(o.begin(), o.end(), off.begin() + (size_t)kStencilMax * g);
+    }
+    d_st_off.ensure(off.size());
+    up(d_st_off.p, off.data(), off.size());
+    L0.st_code.ensure(std::max(N0, 1));
+    launch_stencil_codes(ddesc.p, gtiles_all.p, (int)h_gtiles_all.size(), d_st_off.p, L0.st_code.p, stream);
+  }
 
   d_active.ensure(std::max(G, 1));
   h_active_dev.clear();
@@ -376,9 +402,15 @@ void Engine::assemble(const std::vector<int>& run, bool mixed) {
   // refinement storage: solution in sol (L0.tmp is int; use dedicated buffers)
   asm_pol.ensure(std::max(N0, 1));
   asm_dinv.ensure(std::max(N0, 1));
+  if (L0.stencil) {
+    L0.st64.ensure((size_t)L0.st_w * std::max(N0, 1));
+    if (mixed) L0.st32.ensure((size_t)L0.st_w * std::max(N0, 1));
+  }
+  double* st64 = L0.stencil ? L0.st64.p : nullptr;
+  float* st32 = L0.stencil && mixed ? L0.st32.p : nullptr;
   // rows are kept only in the buffers they were built in
-  const std::array<const void*, 7> bufs{L0.a64.p, mixed ? L0.a32.p : nullptr, L0.dinv64.p,
-                                        mixed ? L0.dinv32.p : nullptr, rhs.p, asm_pol.p, asm_dinv.p};
+  const std::array<const void*, 9> bufs{L0.a64.p, mixed ? L0.a32.p : nullptr, L0.dinv64.p,
+                                        mixed ? L0.dinv32.p : nullptr, rhs.p, asm_pol.p, asm_dinv.p, st64, st32};
   if (asm_stale || asm_mixed != mixed || bufs != asm_bufs) {
     asm_stale = true;
     fill_async(asm_pol.p, -1, (size_t)std::max(N0, 1), stream);
@@ -388,7 +420,7 @@ void Engine::assemble(const std::vector<int>& run, bool mixed) {
   launch_gather_v(ddesc.p, gtiles_all.p, (int)h_gtiles_all.size(), d_active.p, sol.p, stream);
   launch_assemble(ddesc.p, gtiles_all.p, (int)h_gtiles_all.size(), d_active.p, L0.a64.p,
                   mixed ? L0.a32.p : nullptr, rhs.p, L0.dinv64.p, mixed ? L0.dinv32.p : nullptr, asm_pol.p,
-                  asm_dinv.p, fold, stream);
+                  asm_dinv.p, st64, st32, L0.st_w, N0, fold, stream);
   asm_stale = false;
   launch_fold_finish(fold, G, 1, 0u, 0, d_bnorm.p, 1, nullptr, 0, stream);
   (void)run;
@@ -1118,18 +1150,19 @@ void Engine::refresh_errors_check(const int* pe) {
 }
 
 // algorithmic bytes of the cycle kernels (each value read or written once)
+// (the stencil form: per row a code word and st_w slot values, no columns)
 template <class T>
 static double bytes_smooth(const Level& L, bool first) {
   const double sv = sizeof(T), rows = L.rows_vctiles;
   if (first) return rows * 3 * sv;
   const double nnz = L.n ? (double)L.nnz * rows / L.n : 0.0;
-  return rows * (4 + 4 * sv) + nnz * (4 + sv);
+  return rows * (4 + 4 * sv) + (L.stencil ? rows * L.st_w * sv : nnz * (4 + sv));
 }
 template <class T>
 static double bytes_resid(const Level& L) {
   const double sv = sizeof(T), rows = L.rows_vctiles;
   const double nnz = L.n ? (double)L.nnz * rows / L.n : 0.0;
-  return rows * (4 + 3 * sv) + nnz * (4 + sv);
+  return rows * (4 + 3 * sv) + (L.stencil ? rows * L.st_w * sv : nnz * (4 + sv));
 }
 
 template <class T>
@@ -1141,9 +1174,13 @@ static double relax_weight(const EngineOpts& o) { return o.smoother == SHAPLEY_S
 
 // One relaxation sweep cur -> nxt of the level-by-level rows (a C/F sweep is
 // two half sweeps through the free buffer, ending in nxt).
+static StencilView stencil_view(const Level& L, const int* st_off) {
+  return StencilView{L.st_code.p, st_off, L.st_w, L.n};
+}
+
 template <class T>
 static void relax_sweep(Level& L, const EngineOpts& o, const int* act, const T* b, T* cur, T* nxt, T* tmp,
-                        hipStream_t s, double* sol) {
+                        hipStream_t s, double* sol, const int* st_off) {
   const T om = (T)relax_weight(o);
   if (o.smoother == SHAPLEY_SMOOTH_CF) {
     probe_begin(kProbeSmooth, s);
@@ -1155,8 +1192,12 @@ static void relax_sweep(Level& L, const EngineOpts& o, const int* act, const T* 
     return;
   }
   probe_begin(kProbeSmooth, s);
-  cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, LV<T>::a(L), LV<T>::d(L), b, cur, nxt, om, 0, L.gA, s,
-                sol);
+  if (L.stencil)
+    cyc_smooth_st<T>(L.vctiles.p, L.nvctiles, act, stencil_view(L, st_off), LV<T>::st(L), LV<T>::d(L), b, cur, nxt,
+                     om, 0, s, sol);
+  else
+    cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, LV<T>::a(L), LV<T>::d(L), b, cur, nxt, om, 0, L.gA,
+                  s, sol);
   probe_end(kProbeSmooth, s, bytes_smooth<T>(L, false));
 }
 
@@ -1173,6 +1214,7 @@ static T* vcycle_impl(Engine* e, std::vector<Level>& lv, int l, const EngineOpts
   T* nxt = cur == LV<T>::x(L) ? LV<T>::y(L) : LV<T>::x(L);
   T* b = LV<T>::b(L);
   const T om = (T)relax_weight(o);
+  const int* st_off = e->stencil_offsets();
   const bool cf = o.smoother == SHAPLEY_SMOOTH_CF;
   if (L.nvctiles) {
     const T* A = LV<T>::a(L);
@@ -1183,7 +1225,11 @@ static T* vcycle_impl(Engine* e, std::vector<Level>& lv, int l, const EngineOpts
       fill_async(cur, (T)0, (size_t)L.n, s);
     } else if (!start && o.nu1 >= 2) {  // the first two sweeps in one pass
       probe_begin(kProbeSmooth, s);
-      cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, D, b, nullptr, nxt, om, 2, L.gA, s);
+      if (L.stencil)
+        cyc_smooth_st<T>(L.vctiles.p, L.nvctiles, act, stencil_view(L, st_off), LV<T>::st(L), D, b, nullptr, nxt,
+                         om, 2, s);
+      else
+        cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, D, b, nullptr, nxt, om, 2, L.gA, s);
       probe_end(kProbeSmooth, s, bytes_smooth<T>(L, false) - (double)L.rows_vctiles * sizeof(T));
       std::swap(cur, nxt);
       k = 2;
@@ -1194,12 +1240,15 @@ static T* vcycle_impl(Engine* e, std::vector<Level>& lv, int l, const EngineOpts
       k = 1;
     }
     for (; k < o.nu1; ++k) {
-      relax_sweep<T>(L, o, act, b, cur, nxt, tmp, s, nullptr);
+      relax_sweep<T>(L, o, act, b, cur, nxt, tmp, s, nullptr, st_off);
       std::swap(cur, nxt);
     }
     T* r = LV<T>::r(L);
     probe_begin(kProbeResid, s);
-    cyc_resid<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, b, cur, r, L.gA, s);
+    if (L.stencil)
+      cyc_resid_st<T>(L.vctiles.p, L.nvctiles, act, stencil_view(L, st_off), LV<T>::st(L), b, cur, r, s);
+    else
+      cyc_resid<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, b, cur, r, L.gA, s);
     probe_end(kProbeResid, s, bytes_resid<T>(L));
     Level& Ln = lv[l + 1];
     probe_begin(kProbeRestrict, s);
@@ -1213,7 +1262,7 @@ static T* vcycle_impl(Engine* e, std::vector<Level>& lv, int l, const EngineOpts
     probe_end(kProbeProlong, s,
               (double)L.rows_vctiles * (PW * (4 + sizeof(T)) + 2 * sizeof(T)) + (double)Ln.rows_rtiles * sizeof(T));
     for (int k = 0; k < o.nu2; ++k) {
-      relax_sweep<T>(L, o, act, b, cur, nxt, tmp, s, k + 1 == o.nu2 ? sol : nullptr);
+      relax_sweep<T>(L, o, act, b, cur, nxt, tmp, s, k + 1 == o.nu2 ? sol : nullptr, st_off);
       std::swap(cur, nxt);
     }
   }
@@ -1276,16 +1325,28 @@ void Engine::solve_linear(const std::vector<int>& run, const EngineOpts& o) {
   // long as the previous solve (cycles of games that stopped return at once).
   auto resid_check = [&]() {
     probe_begin(kProbeResid64, stream);
-    if (mixed)
+    if (L0.stencil) {
+      const StencilView sv = stencil_view(L0, d_st_off.p);
+      if (mixed)
+        cyc_resid64_st<float>(L0.tiles.p, L0.ntiles, d_lin_active, sv, L0.st64.p, rhs.p, sol.p, L0.b32.p, fold,
+                              stream);
+      else
+        cyc_resid64_st<double>(L0.tiles.p, L0.ntiles, d_lin_active, sv, L0.st64.p, rhs.p, sol.p, L0.b64.p, fold,
+                               stream);
+    } else if (mixed) {
       cyc_resid64<float>(L0.tiles.p, L0.ntiles, d_lin_active, L0.rp.p, L0.ci.p, L0.a64.p, rhs.p, sol.p,
                          L0.b32.p, fold, L0.gA, stream);
-    else
+    } else {
       cyc_resid64<double>(L0.tiles.p, L0.ntiles, d_lin_active, L0.rp.p, L0.ci.p, L0.a64.p, rhs.p, sol.p,
                           L0.b64.p, fold, L0.gA, stream);
+    }
     {
+      // per row: row pointer or code word, b, x, the residual; per entry (or
+      // stencil slot): column and value, or the value alone
       const double rows = L0.rows_tiles;
       const double nnz = L0.n ? (double)L0.nnz * rows / L0.n : 0.0;
-      probe_end(kProbeResid64, stream, rows * (4 + 8 + 8 + (mixed ? 4 : 8)) + nnz * 12);
+      probe_end(kProbeResid64, stream,
+                rows * (4 + 8 + 8 + (mixed ? 4 : 8)) + (L0.stencil ? rows * L0.st_w * 8 : nnz * 12));
     }
     launch_lin_check(fold, G, d_bnorm.p, d_lin.p, d_lin_active, d_norm.p, stream);
   };

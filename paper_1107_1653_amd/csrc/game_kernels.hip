@@ -135,7 +135,8 @@ __global__ __launch_bounds__(256) void k_assemble(const GameDesc* __restrict__ g
                                                   double* __restrict__ a64, float* __restrict__ a32,
                                                   double* __restrict__ b0, double* __restrict__ dinv64,
                                                   float* __restrict__ dinv32, int* __restrict__ pol,
-                                                  double* __restrict__ dbuilt, Stripes bnorm) {
+                                                  double* __restrict__ dbuilt, double* __restrict__ st64,
+                                                  float* __restrict__ st32, int st_w, int N, Stripes bnorm) {
   GTile t = tiles[blockIdx.x];
   if (!active[t.game]) return;
   const GameDesc d = gd[t.game];
@@ -182,6 +183,16 @@ __global__ __launch_bounds__(256) void k_assemble(const GameDesc* __restrict__ g
         if (a32) a32[d.a_off + j0 + k] = (float)val[k];
         if (col[k] == x) diag = val[k];
       }
+      if (st64) {
+        // the stencil form: slot k = entry k of the row, zero past its end
+#pragma unroll
+        for (int k = 0; k < kAsmRow; ++k) {
+          if (k >= st_w) break;
+          const double vk = j0 + k < j1 ? val[k] : 0.0;
+          st64[(size_t)k * N + X] = vk;
+          if (st32) st32[(size_t)k * N + X] = (float)vk;
+        }
+      }
     } else {
       int jd = j0;
       for (int j = j0; j < j1; ++j) {
@@ -216,11 +227,89 @@ __global__ __launch_bounds__(256) void k_assemble(const GameDesc* __restrict__ g
 }
 
 void launch_assemble(const GameDesc* d, const GTile* t, int nt, const int* active, double* a64, float* a32,
-                     double* b0, double* dinv64, float* dinv32, int* pol, double* dbuilt, Stripes bnorm,
-                     hipStream_t s) {
+                     double* b0, double* dinv64, float* dinv32, int* pol, double* dbuilt, double* st64,
+                     float* st32, int st_w, int N, Stripes bnorm, hipStream_t s) {
   if (nt == 0) return;
   hipLaunchKernelGGL(k_assemble, dim3(nt), dim3(kBlock), 0, s, d, t, active, a64, a32, b0, dinv64,
-                     dinv32, pol, dbuilt, bnorm);
+                     dinv32, pol, dbuilt, st64, st32, st_w, N, bnorm);
+  SHP_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Level-0 patterns as stencils.  A pattern whose entries take at most
+// kStencilMax distinct offsets col - x, in rows of at most kStencilMax
+// entries (grid games), is stored for the cycle kernels by slot: entry t of
+// every row in one array (coalesced over rows), its column from a 3-bit code.
+// ---------------------------------------------------------------------------
+__global__ void k_stencil_scan(const int* __restrict__ urp, const int* __restrict__ uci, int n,
+                               int* __restrict__ out) {
+  int* tab = out + 2;
+  int len = 0;
+  for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
+    const int j0 = urp[x], j1 = urp[x + 1];
+    len = max(len, j1 - j0);
+    for (int j = j0; j < j1; ++j) {
+      const int o = uci[j] - x;
+      unsigned h = mix32((uint32_t)o) & (kStencilHash - 1);
+      bool done = false;
+      for (int p = 0; p < kStencilHash && !done; ++p) {
+        const int cur = tab[h];
+        if (cur == o) { done = true; break; }
+        if (cur == INT_MIN) {
+          const int old = atomicCAS(&tab[h], INT_MIN, o);
+          if (old == INT_MIN || old == o) { done = true; break; }
+        }
+        h = (h + 1) & (kStencilHash - 1);
+      }
+      if (!done) out[0] = 1;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) len = max(len, __shfl_xor(len, o));
+  if ((threadIdx.x & 63) == 0 && len > 0) atomicMax(&out[1], len);
+}
+
+__global__ void k_stencil_clear(int* __restrict__ out) {
+  const int i = threadIdx.x;
+  if (i < 2) out[i] = 0;
+  if (i < kStencilHash) out[2 + i] = INT_MIN;
+}
+
+void launch_stencil_scan(const int* urp, const int* uci, int n, int* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_stencil_clear, dim3(1), dim3(64), 0, s, out);
+  SHP_LAUNCH_CHECK();
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_stencil_scan, dim3(std::min<unsigned>(grid_for(n), 4096u)), dim3(kBlock), 0, s, urp, uci, n, out);
+  SHP_LAUNCH_CHECK();
+}
+
+__global__ void k_stencil_codes(const GameDesc* __restrict__ gd, const GTile* __restrict__ tiles,
+                                const int* __restrict__ off, uint32_t* __restrict__ code) {
+  const GTile t = tiles[blockIdx.x];
+  const GameDesc d = gd[t.game];
+  const int x = t.s0 + (int)threadIdx.x;
+  if (x >= t.s1) return;
+  const int* o = off + kStencilMax * t.game;
+  int zero = 0;  // the code of offset 0 (the diagonal), for the slots past the row's end
+  for (int c = 0; c < kStencilMax; ++c)
+    if (o[c] == 0) zero = c;
+  const int j0 = d.urp[x], j1 = d.urp[x + 1];
+  uint32_t w = (uint32_t)(j1 - j0) << 24;
+  for (int k = 0; k < kStencilMax; ++k) {
+    int c = zero;
+    if (j0 + k < j1) {
+      const int dlt = d.uci[j0 + k] - x;
+      for (int q = 0; q < kStencilMax; ++q)
+        if (o[q] == dlt) c = q;
+    }
+    w |= (uint32_t)c << (3 * k);
+  }
+  code[d.x_off + x] = w;
+}
+
+void launch_stencil_codes(const GameDesc* d, const GTile* t, int nt, const int* off, uint32_t* code,
+                          hipStream_t s) {
+  if (nt == 0) return;
+  hipLaunchKernelGGL(k_stencil_codes, dim3(nt), dim3(kBlock), 0, s, d, t, off, code);
   SHP_LAUNCH_CHECK();
 }
 
@@ -238,7 +327,7 @@ void launch_assemble(const GameDesc* d, const GTile* t, int nt, const int* activ
 // with coalesced loads, kImpStage at a time, into LDS; one thread per row then
 // adds its row's products in entry order into Q; one thread per state reduces.
 // ---------------------------------------------------------------------------
-constexpr int kImpStage = 1024;
+constexpr int kImpStage = 1280;  // a tile of 2-D grid states (28 states, 9 rows of 5 entries) in one stage
 constexpr int kImpUnroll = kImpStage / 256;  // entries staged per thread and stage
 
 // One tile of states: either taken from the work list (FLAT = false: the

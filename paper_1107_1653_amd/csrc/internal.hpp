@@ -16,6 +16,8 @@ constexpr int kMaxUnion = 128;   // max entries of one state's level-0 pattern r
 constexpr int kDenseMax = 1024;  // largest dense coarse block
 constexpr int kDenseWave = 96;   // blocks up to this size: one thread per row, rows in registers
 constexpr int kMaxMergedRows = 1 << 25;  // states of the games solved together (64 lanes per row fit 2^31)
+constexpr int kStencilMax = 8;   // offsets and row length of a stencil pattern (3-bit slot codes)
+constexpr int kStencilHash = 32;
 
 // POD view of one game for work-list kernels.
 struct GameDesc {
@@ -56,6 +58,11 @@ struct Game {
   DBuf<uint8_t> valid;
   DBuf<int> urp, uci;
   int unnz = 0;
+  // the level-0 pattern as a stencil: the distinct offsets col - x of its
+  // entries, ascending (empty: more than kStencilMax of them or rows longer
+  // than kStencilMax), and its longest row
+  std::vector<int> st_off;
+  int st_w = 0;
   DBuf<double> v, F;
   DBuf<int> alpha, beta, beta_in, alpha_c, beta_c;
   int dim = 0, s = 0;
@@ -122,6 +129,15 @@ struct Level {
   DBuf<int> rp, ci;
   DBuf<double> a64, dinv64;
   DBuf<float> a32, dinv32;
+  // level 0 of stencil games, for the cycle kernels: slot t of row i at
+  // [t * n + i] (st_w slots, zero past the row's end), its column
+  // i + offset[code_t] from the row's code word (3 bits per slot, the row
+  // length in bits 24..27); the slots follow the CSR order of the row
+  bool stencil = false;
+  int st_w = 0;
+  DBuf<uint32_t> st_code;
+  DBuf<double> st64;
+  DBuf<float> st32;
   std::vector<int> goff;          // per slot offsets, size G+1
   std::vector<char> present;      // slot has rows here
   std::vector<char> cont;         // slot continues to the next level
@@ -347,6 +363,7 @@ class Engine {
   int num_levels() const { return nlev; }
   int num_slots() const { return G; }
   const TailGL* tail_games() const { return d_tailgl.p; }
+  const int* stencil_offsets() const { return d_st_off.p; }
   const TailLev<double>* tail_levels(double*) const { return d_tail64.p; }
   const TailLev<float>* tail_levels(float*) const { return d_tail32.p; }
   // Small host <-> device transfers go through a pinned bump arena (pageable
@@ -427,6 +444,7 @@ class Engine {
   std::vector<int> h_active, h_lin_active;
   // refinement storage on the merged level 0
   DBuf<double> sol, rhs, d_bnorm;
+  DBuf<int> d_st_off;  // stencil offsets of each slot's game, kStencilMax per slot
   // assembled level 0: the pair each row was built for and its 1/a_ii;
   // asm_stale forces a rebuild of every row (new layout, new games, other
   // precision)
@@ -434,7 +452,7 @@ class Engine {
   DBuf<double> asm_dinv;
   bool asm_stale = true;
   bool asm_mixed = false;
-  std::array<const void*, 7> asm_bufs{};  // level-0 buffers the rows were built in
+  std::array<const void*, 9> asm_bufs{};  // level-0 buffers the rows were built in
   // setup scratch
   DBuf<int> s_cnt, s_cursor, s_scan, s_err, s_left, s_newc, s_gidx, s_gout, s_goff;
   DBuf<int> s_toff, s_tcol;   // Galerkin product scratch rows (offsets, columns)
@@ -486,6 +504,7 @@ void set_forced_lanes(int lanes);
 int forced_lanes();
 void set_forced_rap_cols(int mode);  // Galerkin kernel family, -1: automatic
 void set_interp_mode(int mode);      // coarse-level interpolation kernels, -1: automatic
+void set_stencil_mode(int mode);     // level 0 in the stencil form: -1 where it applies, 0 never
 
 // Engines (with their device workspace) are kept per game stream between
 // solves; a lease takes the idle engine of a stream or makes one, and gives
@@ -519,10 +538,19 @@ void launch_gather_v(const GameDesc* d, const GTile* t, int nt, const int* activ
 void launch_scatter_v(const GameDesc* d, const GTile* t, int nt, const int* active, const double* x0,
                       hipStream_t s);
 // Rows whose (alpha, beta) equals pol[X] are kept (pol = -1: rebuild); the
-// rebuilt rows record their pair in pol and 1/a_ii in dbuilt.
+// rebuilt rows record their pair in pol and 1/a_ii in dbuilt.  st64/st32
+// (may be null): the rows also in the stencil form (st_w slots of stride N).
 void launch_assemble(const GameDesc* d, const GTile* t, int nt, const int* active, double* a64, float* a32,
-                     double* b0, double* dinv64, float* dinv32, int* pol, double* dbuilt, Stripes bnorm,
-                     hipStream_t s);
+                     double* b0, double* dinv64, float* dinv32, int* pol, double* dbuilt, double* st64,
+                     float* st32, int st_w, int N, Stripes bnorm, hipStream_t s);
+// Offsets of a level-0 pattern (out: [0] overflow flag, [1] longest row,
+// [2 ..] a kStencilHash-slot table of the distinct offsets, INT_MIN = empty;
+// cleared here).
+void launch_stencil_scan(const int* urp, const int* uci, int n, int* out, hipStream_t s);
+// Code words of the merged level-0 rows (offsets of each slot's game in
+// off[kStencilMax * slot]).
+void launch_stencil_codes(const GameDesc* d, const GTile* t, int nt, const int* off, uint32_t* code,
+                          hipStream_t s);
 void launch_improve(const GameDesc* d, const GTile* t, int nt, const int* active, double tie_rtol,
                     Stripes red, hipStream_t s);
 // The same sweep over one game passed by value, tiles computed from the block

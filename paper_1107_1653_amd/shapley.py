@@ -40,7 +40,7 @@ EXPORTED = [
     "shapley_solve_batch", "shapley_server_create", "shapley_server_submit", "shapley_server_wait",
     "shapley_server_poll", "shapley_server_step", "shapley_server_destroy", "shapley_server_info",
     "shapley_probe_enable", "shapley_probe_read", "shapley_probe_read_large", "shapley_tune_lanes",
-    "shapley_tune_galerkin", "shapley_tune_interp", "shapley_debug_fail_alloc",
+    "shapley_tune_galerkin", "shapley_tune_interp", "shapley_tune_stencil", "shapley_debug_fail_alloc",
 ]
 PROBE = dict(smooth=0, resid64=1, improve=2, resid=3, restrict=4, prolong=5, rap=6, interp=7, tail=8)
 
@@ -148,6 +148,7 @@ def lib() -> C.CDLL:
         L.shapley_tune_lanes.argtypes = [C.c_int32]
         L.shapley_tune_galerkin.argtypes = [C.c_int32]
         L.shapley_tune_interp.argtypes = [C.c_int32]
+        L.shapley_tune_stencil.argtypes = [C.c_int32]
         L.shapley_debug_fail_alloc.argtypes = [C.c_int64]
         _lib_handle = L
     return _lib_handle
@@ -434,6 +435,11 @@ def shapley_tune_interp(kernel: int = -1) -> None:
     """Coarse-level interpolation kernels: -1 four lanes per row first on large levels, 4 on every level,
     0 wavefront only."""
     _check(lib().shapley_tune_interp(int(kernel)))
+
+
+def shapley_tune_stencil(mode: int = -1) -> None:
+    """Finest level of the cycle in the stencil form: -1 where it applies, 0 CSR only."""
+    _check(lib().shapley_tune_stencil(int(mode)))
 
 
 def shapley_probe_read_large(family, frac: float = 0.5) -> dict:
