@@ -131,6 +131,8 @@ static size_t estimate_footprint(Game* h) {
   size_t b = h->device_bytes();
   b += (size_t)f->n * (25 * sizeof(double) + 11 * sizeof(int)) + (size_t)f->unnz * 3 * (sizeof(double) + 4);
   b += (size_t)f->unnz * PW * PW * (sizeof(double) + sizeof(int));
+  // the stencil form of level 0 (grid games): slot values in both precisions and a code word
+  if (!f->st_off.empty()) b += (size_t)f->n * ((size_t)f->st_w * (sizeof(double) + sizeof(float)) + 4);
   return b;
 }
 
