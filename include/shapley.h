@@ -299,15 +299,17 @@ int shapley_tune_galerkin(int32_t kernel);
  * Errors: SHAPLEY_EINVAL for any other value. */
 int shapley_tune_interp(int32_t kernel);
 
-/* Storage of the finest level for the relaxation sweeps and residuals of the
+/* Storage of the matrices read by the relaxation sweeps and residuals of the
  * multigrid cycle (Algorithm MGcycle, Sec. 4.3) and the FP64 residual of the
- * refinement: -1 (default) stores it as a stencil -- value slots by row,
- * columns from a few per-game offsets -- when every game of the solve has a
- * level-0 pattern of at most 8 distinct offsets col - x and rows of at most
- * 8 entries (grid games), and the relaxation is not C/F; 0 keeps the CSR
- * form.  Both sum each row's entries in the same order, so results do not
- * depend on this setting.  Process-wide; applies to later solves.  Errors:
- * SHAPLEY_EINVAL for any other value. */
+ * refinement: -1 (default) stores the finest level as a stencil -- value
+ * slots by row, columns from a few per-game offsets -- when every game of
+ * the solve has a level-0 pattern of at most 8 distinct offsets col - x and
+ * rows of at most 8 entries (grid games) and the relaxation is not C/F, and
+ * gives the other levels' columns as 16-bit offsets from the row where all
+ * fit; 0 keeps CSR with 32-bit columns everywhere.  Every form sums each
+ * row's entries in the same order, so results do not depend on this
+ * setting.  Process-wide; applies to later solves.  Errors: SHAPLEY_EINVAL
+ * for any other value. */
 int shapley_tune_stencil(int32_t mode);
 
 /* Testing aid for the error paths (no passage of the paper: library

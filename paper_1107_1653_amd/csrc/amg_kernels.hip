@@ -2883,8 +2883,9 @@ __device__ inline int tile_row(const Tile& t, int& gl, unsigned bid) {
 
 // sum of a[e] f(ci[e]) over the row's entries [e0, e1); all G lanes of the
 // row call it (the shuffles need them)
-template <class T, int G, class F>
-__device__ inline T row_sum(const int* __restrict__ ci, const T* __restrict__ a, F f, int e0, int e1, int gl) {
+template <class T, int G, class F, class CI = int>
+__device__ inline T row_sum(const CI* __restrict__ ci, const T* __restrict__ a, F f, int e0, int e1, int gl,
+                            int cbase = 0) {
   static_assert(G >= 1 && G <= kAcc && (kAcc % G) == 0, "lane count must divide kAcc");
   constexpr int J = kAcc / G;  // partial sums per lane
   T acc[J];
@@ -2898,7 +2899,7 @@ __device__ inline T row_sum(const int* __restrict__ ci, const T* __restrict__ a,
     T v[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      c[j] = ci[base + gl + G * j];
+      c[j] = cbase + (int)ci[base + gl + G * j];
       v[j] = a[base + gl + G * j];
     }
 #pragma unroll
@@ -2908,7 +2909,7 @@ __device__ inline T row_sum(const int* __restrict__ ci, const T* __restrict__ a,
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const int e = base + gl + G * j;
-      if (e < e1) acc[j] += a[e] * f(ci[e]);
+      if (e < e1) acc[j] += a[e] * f(cbase + (int)ci[e]);
     }
   }
 #pragma unroll
@@ -2922,23 +2923,25 @@ __device__ inline T row_sum(const int* __restrict__ ci, const T* __restrict__ a,
   return s;
 }
 
-template <class T, class TX, int G>
-__device__ inline T row_dot(const int* __restrict__ ci, const T* __restrict__ a, const TX* __restrict__ x, int e0,
-                            int e1, int gl) {
-  return row_sum<T, G>(ci, a, [&](int j) -> T { return (T)x[j]; }, e0, e1, gl);
+// CI = int: absolute columns; CI = int16_t: columns relative to the row (cbase = the row)
+template <class T, class TX, int G, class CI = int>
+__device__ inline T row_dot(const CI* __restrict__ ci, const T* __restrict__ a, const TX* __restrict__ x, int e0,
+                            int e1, int gl, int cbase = 0) {
+  return row_sum<T, G>(ci, a, [&](int j) -> T { return (T)x[j]; }, e0, e1, gl, cbase);
 }
 
-template <class T, int G, class F>
-__device__ inline T row_dot_fn(const int* __restrict__ ci, const T* __restrict__ a, F f, int e0, int e1, int gl) {
-  return row_sum<T, G>(ci, a, f, e0, e1, gl);
+template <class T, int G, class F, class CI = int>
+__device__ inline T row_dot_fn(const CI* __restrict__ ci, const T* __restrict__ a, F f, int e0, int e1, int gl,
+                               int cbase = 0) {
+  return row_sum<T, G>(ci, a, f, e0, e1, gl, cbase);
 }
 
 // first = 1: the first sweep from zero, x = omega D^-1 b; first = 2: the first
 // two sweeps from zero in one pass (the first sweep's values recomputed where
 // the second reads them, the same operations as the two passes)
-template <class T, int G>
+template <class T, int G, class CI = int>
 __global__ __launch_bounds__(256) void k_smooth(const Tile* __restrict__ tiles, const int* __restrict__ act,
-                                                const int* __restrict__ rp, const int* __restrict__ ci,
+                                                const int* __restrict__ rp, const CI* __restrict__ ci,
                                                 const T* __restrict__ a, const T* __restrict__ dinv,
                                                 const T* __restrict__ b, const T* __restrict__ xin,
                                                 T* __restrict__ xout, T omega, int first,
@@ -2950,11 +2953,12 @@ __global__ __launch_bounds__(256) void k_smooth(const Tile* __restrict__ tiles, 
   int gl;
   const int i = tile_row<G>(t, gl, bid);
   const bool in = i < t.r1;
+  const int cb = sizeof(CI) < sizeof(int) ? i : 0;  // relative columns: offsets from the row
   if (cfm) {
     // C/F relaxation: this half sweep relaxes the coarse points (cfphase 1)
     // or the others (cfphase -1) and carries the rest over unchanged
     const int e0 = in ? rp[i] : 0, e1 = in ? rp[i + 1] : 0;
-    const T ax = row_dot<T, T, G>(ci, a, xin, e0, e1, gl);
+    const T ax = row_dot<T, T, G>(ci, a, xin, e0, e1, gl, cb);
     if (in && gl == 0) {
       const bool mine = (cfm[i] == CF_C) == (cfphase == 1);
       xout[i] = mine ? xin[i] + omega * dinv[i] * (b[i] - ax) : xin[i];
@@ -2967,14 +2971,14 @@ __global__ __launch_bounds__(256) void k_smooth(const Tile* __restrict__ tiles, 
   }
   const int e0 = in ? rp[i] : 0, e1 = in ? rp[i + 1] : 0;
   if (first == 2) {
-    const T ax = row_dot_fn<T, G>(ci, a, [&](int j) -> T { return omega * dinv[j] * b[j]; }, e0, e1, gl);
+    const T ax = row_dot_fn<T, G>(ci, a, [&](int j) -> T { return omega * dinv[j] * b[j]; }, e0, e1, gl, cb);
     if (in && gl == 0) {
       const T x1 = omega * dinv[i] * b[i];
       xout[i] = x1 + omega * dinv[i] * (b[i] - ax);
     }
     return;
   }
-  const T ax = row_dot<T, T, G>(ci, a, xin, e0, e1, gl);  // all lanes: the shuffles need them
+  const T ax = row_dot<T, T, G>(ci, a, xin, e0, e1, gl, cb);  // all lanes: the shuffles need them
   if (in && gl == 0) {
     const T xi = xin[i] + omega * dinv[i] * (b[i] - ax);
     xout[i] = xi;
@@ -2982,9 +2986,9 @@ __global__ __launch_bounds__(256) void k_smooth(const Tile* __restrict__ tiles, 
   }
 }
 
-template <class T, int G>
+template <class T, int G, class CI = int>
 __global__ __launch_bounds__(256) void k_resid(const Tile* __restrict__ tiles, const int* __restrict__ act,
-                                               const int* __restrict__ rp, const int* __restrict__ ci,
+                                               const int* __restrict__ rp, const CI* __restrict__ ci,
                                                const T* __restrict__ a, const T* __restrict__ b,
                                                const T* __restrict__ x, T* __restrict__ r) {
   const unsigned bid = blockIdx.x;
@@ -2994,7 +2998,7 @@ __global__ __launch_bounds__(256) void k_resid(const Tile* __restrict__ tiles, c
   const int i = tile_row<G>(t, gl, bid);
   const bool in = i < t.r1;
   const int e0 = in ? rp[i] : 0, e1 = in ? rp[i + 1] : 0;
-  const T ax = row_dot<T, T, G>(ci, a, x, e0, e1, gl);
+  const T ax = row_dot<T, T, G>(ci, a, x, e0, e1, gl, sizeof(CI) < sizeof(int) ? i : 0);
   if (in && gl == 0) r[i] = b[i] - ax;
 }
 
@@ -3896,13 +3900,43 @@ int row_group(double avg_len) { return avg_len <= 10.0 ? 1 : 4; }
     else hipLaunchKernelGGL((K<T, 1>), dim3(nt), dim3(kTileRows), 0, s, __VA_ARGS__);                  \
   } while (0)
 
+#define SHP_GROUP_LAUNCH16(K, g, nt, s, ...)                                                               \
+  do {                                                                                                     \
+    if ((g) == 4) hipLaunchKernelGGL((K<T, 4, int16_t>), dim3((nt) * 4), dim3(kTileRows), 0, s, __VA_ARGS__); \
+    else if ((g) == 2) hipLaunchKernelGGL((K<T, 2, int16_t>), dim3((nt) * 2), dim3(kTileRows), 0, s, __VA_ARGS__); \
+    else hipLaunchKernelGGL((K<T, 1, int16_t>), dim3(nt), dim3(kTileRows), 0, s, __VA_ARGS__);            \
+  } while (0)
+
 template <class T>
 void cyc_smooth(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const T* a,
                 const T* dinv, const T* b, const T* xin, T* xout, T omega, int first, int g, hipStream_t s,
-                double* sol, const int8_t* cf, int cfphase) {
+                double* sol, const int8_t* cf, int cfphase, const int16_t* ci16) {
   if (!nt) return;
-  SHP_GROUP_LAUNCH(k_smooth, first == 1 && !cf ? 1 : g, nt, s, t, act, rp, ci, a, dinv, b, xin, xout, omega, first,
-                   sol, cf, cfphase);
+  if (ci16 && !(first == 1 && !cf))
+    SHP_GROUP_LAUNCH16(k_smooth, g, nt, s, t, act, rp, ci16, a, dinv, b, xin, xout, omega, first, sol, cf, cfphase);
+  else
+    SHP_GROUP_LAUNCH(k_smooth, first == 1 && !cf ? 1 : g, nt, s, t, act, rp, ci, a, dinv, b, xin, xout, omega,
+                     first, sol, cf, cfphase);
+  SHP_LAUNCH_CHECK();
+}
+
+// columns as 16-bit offsets from their row (thread per row)
+__global__ void k_rel16(const Tile* __restrict__ tiles, const int* __restrict__ rp, const int* __restrict__ ci,
+                        int16_t* __restrict__ ci16, int* __restrict__ over) {
+  const Tile t = tiles[blockIdx.x];
+  const int i = t.r0 + (int)threadIdx.x;
+  if (i >= t.r1) return;
+  bool bad = false;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const int d = ci[e] - i;
+    bad |= d < -32768 || d > 32767;
+    ci16[e] = (int16_t)d;
+  }
+  if (bad) *over = 1;
+}
+void amg_rel16(const Tile* t, int nt, const int* rp, const int* ci, int16_t* ci16, int* over, hipStream_t s) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_rel16, dim3(nt), dim3(kTileRows), 0, s, t, rp, ci, ci16, over);
   SHP_LAUNCH_CHECK();
 }
 
@@ -3925,9 +3959,12 @@ void amg_l1_diag(const Tile* t, int nt, const int* rp, const double* a, double* 
 }
 template <class T>
 void cyc_resid(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const T* a, const T* b,
-               const T* x, T* r, int g, hipStream_t s) {
+               const T* x, T* r, int g, hipStream_t s, const int16_t* ci16) {
   if (!nt) return;
-  SHP_GROUP_LAUNCH(k_resid, g, nt, s, t, act, rp, ci, a, b, x, r);
+  if (ci16)
+    SHP_GROUP_LAUNCH16(k_resid, g, nt, s, t, act, rp, ci16, a, b, x, r);
+  else
+    SHP_GROUP_LAUNCH(k_resid, g, nt, s, t, act, rp, ci, a, b, x, r);
   SHP_LAUNCH_CHECK();
 }
 template <class T>
@@ -4002,9 +4039,9 @@ void cyc_tail(const int* games, int ngames, int l0, int nlev, int G, const TailL
 #define SHP_INST(T)                                                                                  \
   template void cyc_smooth<T>(const Tile*, int, const int*, const int*, const int*, const T*, const T*, \
                               const T*, const T*, T*, T, int, int, hipStream_t, double*,             \
-                              const int8_t*, int);                                                   \
+                              const int8_t*, int, const int16_t*);                                   \
   template void cyc_resid<T>(const Tile*, int, const int*, const int*, const int*, const T*, const T*,  \
-                             const T*, T*, int, hipStream_t);                                        \
+                             const T*, T*, int, hipStream_t, const int16_t*);                        \
   template void cyc_restrict<T>(const Tile*, int, const int*, const int*, const int*, const T*,        \
                                 const T*, T*, int, hipStream_t);                                     \
   template void cyc_prolong<T>(const Tile*, int, const int*, const int*, const T*, const T*, T*,       \

@@ -129,12 +129,16 @@ template <class T>
 void cyc_smooth(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const T* a,
                 const T* dinv, const T* b, const T* xin, T* xout, T omega, int first, int g, hipStream_t s,
                 double* sol = nullptr,  // sol: also sol += xout (FP64), sweeps with first == 0
-                const int8_t* cf = nullptr, int cfphase = 0);  // cf: C/F half sweep (first == 0, no sol)
+                const int8_t* cf = nullptr, int cfphase = 0,  // cf: C/F half sweep (first == 0, no sol)
+                const int16_t* ci16 = nullptr);  // columns as 16-bit offsets from the row (instead of ci)
 // l1-Jacobi diagonal 1 / sum_j |a_ij| of the tiles' rows
 void amg_l1_diag(const Tile* t, int nt, const int* rp, const double* a, double* d64, float* d32, hipStream_t s);
 template <class T>
 void cyc_resid(const Tile* t, int nt, const int* act, const int* rp, const int* ci, const T* a, const T* b,
-               const T* x, T* r, int g, hipStream_t s);
+               const T* x, T* r, int g, hipStream_t s, const int16_t* ci16 = nullptr);
+// columns of the tiles' rows as 16-bit offsets from the row; *over = 1 when
+// one does not fit (ci16 then unusable)
+void amg_rel16(const Tile* t, int nt, const int* rp, const int* ci, int16_t* ci16, int* over, hipStream_t s);
 template <class T>
 void cyc_restrict(const Tile* t, int nt, const int* act, const int* rrp, const int* rci, const T* rv,
                   const T* rf, T* bc, int g, hipStream_t s);

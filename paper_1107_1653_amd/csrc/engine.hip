@@ -94,8 +94,9 @@ void set_forced_rap_cols(int mode) { g_gal_mode.store(mode); }
 static std::atomic<int> g_interp_mode{-1};
 constexpr int kInterpQuadRows = 1 << 16;  // automatic choice: levels of at least this many rows
 void set_interp_mode(int mode) { g_interp_mode.store(mode); }
-// level 0 of stencil games in the stencil form for the cycle kernels: -1 when
-// every game is a stencil game (the default), 0 never (the same results)
+// compact matrix forms for the cycle kernels: -1 (default) level 0 in the
+// stencil form when every game is a stencil game, 16-bit column offsets on
+// the other levels where they fit; 0 CSR with 32-bit columns (the same results)
 static std::atomic<int> g_stencil_mode{-1};
 void set_stencil_mode(int mode) { g_stencil_mode.store(mode); }
 static int gal_kernel(double cols, bool one_slot) {
@@ -170,10 +171,15 @@ void Engine::reset() {
 
 namespace {
 // idle engines per stream; never destroyed at process exit (the runtime may
-// already be gone then), emptied when the last game handle is destroyed
+// already be gone then), emptied when the last game handle is destroyed.  At
+// most kIdleEngines are kept: games solved one after another on streams of
+// their own do not each keep a workspace (the least recently used go first).
 std::mutex g_cache_mu;
 auto& g_cache = *new std::map<hipStream_t, std::unique_ptr<Engine>>();
+auto& g_cache_use = *new std::map<hipStream_t, uint64_t>();
+uint64_t g_cache_clock = 0;
 int g_games_alive = 0;
+constexpr size_t kIdleEngines = 8;
 }  // namespace
 
 void games_alive_add(int delta) {
@@ -184,6 +190,7 @@ void games_alive_add(int delta) {
     if (g_games_alive <= 0) {
       g_games_alive = 0;
       drop.swap(g_cache);  // last game gone: release the workspace
+      g_cache_use.clear();
     }
   }
 }
@@ -195,6 +202,7 @@ void engine_cache_drop(hipStream_t s) {
   if (it == g_cache.end()) return;
   drop = std::move(it->second);
   g_cache.erase(it);
+  g_cache_use.erase(s);
 }
 
 Engine* engine_cached(hipStream_t s) {
@@ -231,6 +239,7 @@ EngineLease::EngineLease(hipStream_t s, bool keep)
     if (it != g_cache.end()) {
       e_ = std::move(it->second);
       g_cache.erase(it);
+      g_cache_use.erase(s);
     }
   }
   if (!e_) e_.reset(new Engine(s));
@@ -240,8 +249,20 @@ EngineLease::EngineLease(hipStream_t s, bool keep)
 EngineLease::~EngineLease() {
   if (!keep_ || std::uncaught_exceptions() > uncaught_) return;  // not kept: destroyed here
   e_->reset();
+  std::vector<std::unique_ptr<Engine>> drop;  // destroyed after the lock is released
   std::lock_guard<std::mutex> lk(g_cache_mu);
-  if (g_games_alive > 0 && !g_cache.count(s_)) g_cache[s_] = std::move(e_);
+  if (g_games_alive > 0 && !g_cache.count(s_)) {
+    g_cache[s_] = std::move(e_);
+    g_cache_use[s_] = ++g_cache_clock;
+    while (g_cache.size() > kIdleEngines) {
+      auto lru = g_cache_use.begin();
+      for (auto u = g_cache_use.begin(); u != g_cache_use.end(); ++u)
+        if (u->second < lru->second) lru = u;
+      drop.push_back(std::move(g_cache[lru->first]));
+      g_cache.erase(lru->first);
+      g_cache_use.erase(lru);
+    }
+  }
 }
 void Engine::drop_graph() {
   if (cyc_exec) (void)hipGraphExecDestroy(cyc_exec);
@@ -542,6 +563,8 @@ static void check_offsets(size_t total_bound) {
                                     std::to_string(total_bound) + " entries > 2^31): solve fewer games together");
 }
 
+constexpr int kRelLevels = 72;  // > the most levels a hierarchy takes
+
 void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
   const bool mixed = o.precision == SHAPLEY_MIXED;
   std::vector<char> present(G, 0);
@@ -555,9 +578,12 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
   s_err.ensure(4);
   s_left.ensure(3);
   fill_async(s_err.p, 0, 4, stream);
+  s_rel.ensure(kRelLevels);
+  fill_async(s_rel.p, 0, (size_t)kRelLevels, stream);
   PhaseTimer pt(this, prof);
   nlev = 0;
   int l = 0;
+  double growth = 2.6;  // entries per coarse row / per fine row of the last product
   lv[0].goff = x_off;
   lv[0].present = present;
   while (true) {
@@ -586,6 +612,13 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
       }
     }
     build_tiles(L, L.present, false);
+    // the cycle kernels' columns as 16-bit offsets from the row where they fit
+    L.rel16 = false;
+    L.rel16_built = !L.stencil && L.ntiles && g_stencil_mode.load() != 0;
+    if (L.rel16_built) {
+      L.ci16.ensure(std::max(L.nnz, 1));
+      amg_rel16(L.tiles.p, L.ntiles, L.rp.p, L.ci.p, L.ci16.p, s_rel.p + l, stream);
+    }
     L.dir.ensure(std::max(n, 1));
     if (any_cont) {
       build_tiles(L, L.cont, true);
@@ -856,9 +889,11 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
           s_tval.ensure(tcap);
           s_big.ensure(2 * ((size_t)std::max(n, nc) + 1));
           amg_rap_bound(nc, L.rrp.p, L.rci.p, Arp, s_cnt.p, pwf, stream);
-          // coarse rows: the level's previous product, else about four
-          // times the fine rows' entries (grid stencils)
-          const double c_cols = (Ln.nnz > 0 && Ln.n == nc) ? (double)Ln.nnz / nc : 4.0 * L.nnz / n;
+          // coarse rows: the level's previous product, else the fine rows'
+          // entries times the growth of the level above (2.6 on level 0: grid
+          // stencils)
+          const double c_cols =
+              (Ln.nnz > 0 && Ln.n == nc) ? (double)Ln.nnz / nc : growth * L.nnz / std::max(n, 1);
           scan_exclusive(s_cnt.p, s_toff.p, nc + 1, stream, s_scan);
           probe_begin(kProbeRap, stream);
           amg_rap_fused(nc, L.rrp.p, L.rci.p, L.rv64.p, Arp, Aci, Aa, Ppc, Ppv, s_toff.p, s_cnt.p, s_tcol.p,
@@ -873,6 +908,7 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         cnnz = *pc_nnz;
         rnnz_used = *pr_nnz;
         Ln.nnz = cnnz;
+        if (L.nnz > 0 && nc > 0) growth = ((double)cnnz / nc) / ((double)L.nnz / std::max(n, 1));
         L.gR = forced_lanes() ? forced_lanes() : row_group((double)rnnz_used / std::max(nc, 1));
         Ln.ci.ensure(std::max(cnnz, 1));
         Ln.a64.ensure(std::max(cnnz, 1));
@@ -940,8 +976,10 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
   {
     int herr[4] = {0, 0, 0, 0};
     const int* pe = down(s_err.p, 4);
+    const int* pr = down(s_rel.p, (size_t)kRelLevels);
     sync();
     std::memcpy(herr, pe, sizeof(herr));
+    for (int k = 0; k < nlev; ++k) lv[k].rel16 = lv[k].rel16_built && pr[k] == 0;
     if (herr[1] != 0)
       throw Error(SHAPLEY_EDEVICE, "Galerkin product: coarse row too long (code " + std::to_string(herr[1]) + ")");
     if (herr[2] != 0) throw Error(SHAPLEY_EDEVICE, "singular coarsest block");
@@ -1156,13 +1194,13 @@ static double bytes_smooth(const Level& L, bool first) {
   const double sv = sizeof(T), rows = L.rows_vctiles;
   if (first) return rows * 3 * sv;
   const double nnz = L.n ? (double)L.nnz * rows / L.n : 0.0;
-  return rows * (4 + 4 * sv) + (L.stencil ? rows * L.st_w * sv : nnz * (4 + sv));
+  return rows * (4 + 4 * sv) + (L.stencil ? rows * L.st_w * sv : nnz * ((L.rel16 ? 2 : 4) + sv));
 }
 template <class T>
 static double bytes_resid(const Level& L) {
   const double sv = sizeof(T), rows = L.rows_vctiles;
   const double nnz = L.n ? (double)L.nnz * rows / L.n : 0.0;
-  return rows * (4 + 3 * sv) + (L.stencil ? rows * L.st_w * sv : nnz * (4 + sv));
+  return rows * (4 + 3 * sv) + (L.stencil ? rows * L.st_w * sv : nnz * ((L.rel16 ? 2 : 4) + sv));
 }
 
 template <class T>
@@ -1174,6 +1212,8 @@ static double relax_weight(const EngineOpts& o) { return o.smoother == SHAPLEY_S
 
 // One relaxation sweep cur -> nxt of the level-by-level rows (a C/F sweep is
 // two half sweeps through the free buffer, ending in nxt).
+static const int16_t* ci16_of(const Level& L) { return L.rel16 ? L.ci16.p : nullptr; }
+
 static StencilView stencil_view(const Level& L, const int* st_off) {
   return StencilView{L.st_code.p, st_off, L.st_w, L.n};
 }
@@ -1185,9 +1225,9 @@ static void relax_sweep(Level& L, const EngineOpts& o, const int* act, const T* 
   if (o.smoother == SHAPLEY_SMOOTH_CF) {
     probe_begin(kProbeSmooth, s);
     cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, LV<T>::a(L), LV<T>::d(L), b, cur, tmp, om, 0, L.gA,
-                  s, nullptr, L.cf.p, 1);
+                  s, nullptr, L.cf.p, 1, ci16_of(L));
     cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, LV<T>::a(L), LV<T>::d(L), b, tmp, nxt, om, 0, L.gA,
-                  s, nullptr, L.cf.p, -1);
+                  s, nullptr, L.cf.p, -1, ci16_of(L));
     probe_end(kProbeSmooth, s, 2 * bytes_smooth<T>(L, false));
     return;
   }
@@ -1197,7 +1237,7 @@ static void relax_sweep(Level& L, const EngineOpts& o, const int* act, const T* 
                      om, 0, s, sol);
   else
     cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, LV<T>::a(L), LV<T>::d(L), b, cur, nxt, om, 0, L.gA,
-                  s, sol);
+                  s, sol, nullptr, 0, ci16_of(L));
   probe_end(kProbeSmooth, s, bytes_smooth<T>(L, false));
 }
 
@@ -1229,7 +1269,8 @@ static T* vcycle_impl(Engine* e, std::vector<Level>& lv, int l, const EngineOpts
         cyc_smooth_st<T>(L.vctiles.p, L.nvctiles, act, stencil_view(L, st_off), LV<T>::st(L), D, b, nullptr, nxt,
                          om, 2, s);
       else
-        cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, D, b, nullptr, nxt, om, 2, L.gA, s);
+        cyc_smooth<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, D, b, nullptr, nxt, om, 2, L.gA, s, nullptr,
+                      nullptr, 0, ci16_of(L));
       probe_end(kProbeSmooth, s, bytes_smooth<T>(L, false) - (double)L.rows_vctiles * sizeof(T));
       std::swap(cur, nxt);
       k = 2;
@@ -1248,7 +1289,7 @@ static T* vcycle_impl(Engine* e, std::vector<Level>& lv, int l, const EngineOpts
     if (L.stencil)
       cyc_resid_st<T>(L.vctiles.p, L.nvctiles, act, stencil_view(L, st_off), LV<T>::st(L), b, cur, r, s);
     else
-      cyc_resid<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, b, cur, r, L.gA, s);
+      cyc_resid<T>(L.vctiles.p, L.nvctiles, act, L.rp.p, L.ci.p, A, b, cur, r, L.gA, s, ci16_of(L));
     probe_end(kProbeResid, s, bytes_resid<T>(L));
     Level& Ln = lv[l + 1];
     probe_begin(kProbeRestrict, s);

@@ -241,10 +241,16 @@ void launch_assemble(const GameDesc* d, const GTile* t, int nt, const int* activ
 // entries (grid games), is stored for the cycle kernels by slot: entry t of
 // every row in one array (coalesced over rows), its column from a 3-bit code.
 // ---------------------------------------------------------------------------
-__global__ void k_stencil_scan(const int* __restrict__ urp, const int* __restrict__ uci, int n,
-                               int* __restrict__ out) {
-  int* tab = out + 2;
+__global__ __launch_bounds__(256) void k_stencil_scan(const int* __restrict__ urp, const int* __restrict__ uci,
+                                                      int n, int* __restrict__ out) {
+  // the workgroup's distinct offsets in LDS, merged into the global table at the end
+  __shared__ int tab[kStencilHash];
+  __shared__ int s_over, s_len;
+  if (threadIdx.x < kStencilHash) tab[threadIdx.x] = INT_MIN;
+  if (threadIdx.x == 0) { s_over = 0; s_len = 0; }
+  __syncthreads();
   int len = 0;
+  bool over = false;
   for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
     const int j0 = urp[x], j1 = urp[x + 1];
     len = max(len, j1 - j0);
@@ -253,19 +259,34 @@ __global__ void k_stencil_scan(const int* __restrict__ urp, const int* __restric
       unsigned h = mix32((uint32_t)o) & (kStencilHash - 1);
       bool done = false;
       for (int p = 0; p < kStencilHash && !done; ++p) {
-        const int cur = tab[h];
-        if (cur == o) { done = true; break; }
-        if (cur == INT_MIN) {
-          const int old = atomicCAS(&tab[h], INT_MIN, o);
-          if (old == INT_MIN || old == o) { done = true; break; }
-        }
+        const int old = atomicCAS(&tab[h], INT_MIN, o);
+        done = old == INT_MIN || old == o;
+        h = (h + 1) & (kStencilHash - 1);
+      }
+      over |= !done;
+    }
+  }
+  if (over) s_over = 1;
+  atomicMax(&s_len, len);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_over) out[0] = 1;
+    atomicMax(&out[1], s_len);
+  }
+  if (threadIdx.x < kStencilHash) {
+    const int o = tab[threadIdx.x];
+    if (o != INT_MIN) {
+      int* g = out + 2;
+      unsigned h = mix32((uint32_t)o) & (kStencilHash - 1);
+      bool done = false;
+      for (int p = 0; p < kStencilHash && !done; ++p) {
+        const int old = atomicCAS(&g[h], INT_MIN, o);
+        done = old == INT_MIN || old == o;
         h = (h + 1) & (kStencilHash - 1);
       }
       if (!done) out[0] = 1;
     }
   }
-  for (int o = 32; o > 0; o >>= 1) len = max(len, __shfl_xor(len, o));
-  if ((threadIdx.x & 63) == 0 && len > 0) atomicMax(&out[1], len);
 }
 
 __global__ void k_stencil_clear(int* __restrict__ out) {
@@ -278,7 +299,7 @@ void launch_stencil_scan(const int* urp, const int* uci, int n, int* out, hipStr
   hipLaunchKernelGGL(k_stencil_clear, dim3(1), dim3(64), 0, s, out);
   SHP_LAUNCH_CHECK();
   if (n == 0) return;
-  hipLaunchKernelGGL(k_stencil_scan, dim3(std::min<unsigned>(grid_for(n), 4096u)), dim3(kBlock), 0, s, urp, uci, n, out);
+  hipLaunchKernelGGL(k_stencil_scan, dim3(std::min<unsigned>(grid_for(n), 1024u)), dim3(kBlock), 0, s, urp, uci, n, out);
   SHP_LAUNCH_CHECK();
 }
 

@@ -135,6 +135,10 @@ struct Level {
   // length in bits 24..27); the slots follow the CSR order of the row
   bool stencil = false;
   int st_w = 0;
+  // columns as 16-bit offsets from the row for the cycle kernels (when all fit)
+  bool rel16 = false;
+  bool rel16_built = false;  // ci16 written by this setup (usable once no offset overflowed)
+  DBuf<int16_t> ci16;
   DBuf<uint32_t> st_code;
   DBuf<double> st64;
   DBuf<float> st32;
@@ -459,6 +463,7 @@ class Engine {
   DBuf<int> s_big;            // Galerkin product: rows left to the workgroup kernel
   DBuf<int> s_list;           // refresh: count, then the changed coarse rows
   DBuf<int> s_defer;          // interpolation: rows left to the larger instance
+  DBuf<int> s_rel;            // per level: a column offset does not fit 16 bits
   DBuf<double> s_tval;        // and values
   DBuf<double> s_dac;         // dense Galerkin product scratch: R A P
   DBuf<uint8_t> s_dapt, s_dacf;  // and their structural flags

@@ -438,7 +438,8 @@ def shapley_tune_interp(kernel: int = -1) -> None:
 
 
 def shapley_tune_stencil(mode: int = -1) -> None:
-    """Finest level of the cycle in the stencil form: -1 where it applies, 0 CSR only."""
+    """Compact matrix forms of the cycle (stencil finest level, 16-bit column offsets): -1 where they apply,
+    0 CSR with 32-bit columns only."""
     _check(lib().shapley_tune_stencil(int(mode)))
 
 
