@@ -171,15 +171,17 @@ void Engine::reset() {
 
 namespace {
 // idle engines per stream; never destroyed at process exit (the runtime may
-// already be gone then), emptied when the last game handle is destroyed.  At
-// most kIdleEngines are kept: games solved one after another on streams of
-// their own do not each keep a workspace (the least recently used go first).
+// already be gone then), emptied when the last game handle is destroyed.
+// While less than a quarter of the device memory is free (or more than
+// kIdleEngines are idle), the least recently used are destroyed: games solved
+// one after another on streams of their own keep their workspaces only as
+// long as memory allows.
 std::mutex g_cache_mu;
 auto& g_cache = *new std::map<hipStream_t, std::unique_ptr<Engine>>();
 auto& g_cache_use = *new std::map<hipStream_t, uint64_t>();
 uint64_t g_cache_clock = 0;
 int g_games_alive = 0;
-constexpr size_t kIdleEngines = 8;
+constexpr size_t kIdleEngines = 1024;
 }  // namespace
 
 void games_alive_add(int delta) {
@@ -249,16 +251,26 @@ EngineLease::EngineLease(hipStream_t s, bool keep)
 EngineLease::~EngineLease() {
   if (!keep_ || std::uncaught_exceptions() > uncaught_) return;  // not kept: destroyed here
   e_->reset();
-  std::vector<std::unique_ptr<Engine>> drop;  // destroyed after the lock is released
-  std::lock_guard<std::mutex> lk(g_cache_mu);
-  if (g_games_alive > 0 && !g_cache.count(s_)) {
-    g_cache[s_] = std::move(e_);
-    g_cache_use[s_] = ++g_cache_clock;
-    while (g_cache.size() > kIdleEngines) {
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    if (g_games_alive > 0 && !g_cache.count(s_)) {
+      g_cache[s_] = std::move(e_);
+      g_cache_use[s_] = ++g_cache_clock;
+    }
+  }
+  // one engine at a time, each destroyed (its memory freed) before the next check
+  for (;;) {
+    std::unique_ptr<Engine> victim;
+    {
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      if (g_cache.empty()) break;
+      size_t fr = 0, tot = 0;
+      const bool low = hipMemGetInfo(&fr, &tot) == hipSuccess && fr < tot / 4;
+      if (!low && g_cache.size() <= kIdleEngines) break;
       auto lru = g_cache_use.begin();
       for (auto u = g_cache_use.begin(); u != g_cache_use.end(); ++u)
         if (u->second < lru->second) lru = u;
-      drop.push_back(std::move(g_cache[lru->first]));
+      victim = std::move(g_cache[lru->first]);
       g_cache.erase(lru->first);
       g_cache_use.erase(lru);
     }

@@ -346,7 +346,8 @@ void launch_stencil_codes(const GameDesc* d, const GTile* t, int nt, const int* 
 // otherwise the lowest index attaining the extremum is taken.
 // The products w v of the tile's entries (contiguous in the CSR) are formed
 // with coalesced loads, kImpStage at a time, into LDS; one thread per row then
-// adds its row's products in entry order into Q; one thread per state reduces.
+// adds its row's products in entry order into Q; one thread per (state, a)
+// takes MIN over b, one thread per state MAX over a and the decisions.
 // ---------------------------------------------------------------------------
 constexpr int kImpStage = 1280;  // a tile of 2-D grid states (28 states, 9 rows of 5 entries) in one stage
 constexpr int kImpUnroll = kImpStage / 256;  // entries staged per thread and stage
@@ -362,6 +363,8 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
   __shared__ double sq[256];
   __shared__ double ss[256];
   __shared__ unsigned char sv[256];
+  __shared__ double s_mn[256], s_sc[256];  // per (state, a): MIN's minimum over b and its scale
+  __shared__ int s_lb[256];                // and its lowest b
   __shared__ double sp[kImpStage];
   GTile t;
   GameDesc d;
@@ -424,23 +427,33 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
     sv[tid] = ok ? 1 : 0;
   }
   __syncthreads();
+  // MIN over b for every (state, a) in parallel: the minimum, its lowest b
+  // and the rounding scale of the rows compared (one thread per pair)
+  if (tid < ns * d.m1) {
+    const int qb = tid * d.m2;  // rows of the pair: state tid / m1, action tid % m1
+    double mn = INFINITY, sc = 0.0;
+    int low = -1;
+    for (int b = 0; b < d.m2; ++b) {
+      if (!sv[qb + b]) continue;
+      if (sq[qb + b] < mn) { mn = sq[qb + b]; low = b; }
+      sc = fmax(sc, ss[qb + b]);
+    }
+    s_mn[tid] = mn;
+    s_sc[tid] = sc;
+    s_lb[tid] = low;
+  }
+  __syncthreads();
   double res = 0.0, res2 = 0.0;
   int chg_in = 0, chg_out = 0, hash_out = 0;
   if (owner) {
     const int x = t.s0 + tid;
     const int base = tid * K;
+    const int pb = tid * d.m1;  // the state's pairs
     // MIN at the incumbent alpha
     int bin = -1;
     if (al >= 0) {
-      double mn = INFINITY, sc = 0.0;
-      int low = -1;
-      for (int b = 0; b < d.m2; ++b) {
-        int q = base + al * d.m2 + b;
-        if (!sv[q]) continue;
-        if (sq[q] < mn) { mn = sq[q]; low = b; }
-        sc = fmax(sc, ss[q]);
-      }
-      bin = low;
+      const double mn = s_mn[pb + al], sc = s_sc[pb + al];
+      bin = s_lb[pb + al];
       if (be >= 0 && be < d.m2 && sv[base + al * d.m2 + be] &&
           sq[base + al * d.m2 + be] <= mn + tie_rtol * sc)
         bin = be;
@@ -450,13 +463,8 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
     int lowa = -1;
     double inner_al = -INFINITY;
     for (int a = 0; a < d.m1; ++a) {
-      double mn = INFINITY;
-      for (int b = 0; b < d.m2; ++b) {
-        int q = base + a * d.m2 + b;
-        if (!sv[q]) continue;
-        mn = fmin(mn, sq[q]);
-        scall = fmax(scall, ss[q]);
-      }
+      const double mn = s_mn[pb + a];
+      scall = fmax(scall, s_sc[pb + a]);
       if (mn == INFINITY) continue;  // no valid b: action a not available
       if (a == al) inner_al = mn;
       if (mn > F) { F = mn; lowa = a; }
@@ -468,16 +476,9 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
     const bool al_ok = al >= 0 && inner_al > -INFINITY;
     // MIN's answer at the new alpha (keep the incumbent if alpha is unchanged)
     int bc = -1;
-    {
-      double mn = INFINITY, sc = 0.0;
-      int low = -1;
-      for (int b = 0; b < d.m2; ++b) {
-        int q = base + ac * d.m2 + b;
-        if (!sv[q]) continue;
-        if (sq[q] < mn) { mn = sq[q]; low = b; }
-        sc = fmax(sc, ss[q]);
-      }
-      bc = low;
+    if (ac >= 0) {
+      const double mn = s_mn[pb + ac], sc = s_sc[pb + ac];
+      bc = s_lb[pb + ac];
       if (ac == al && be >= 0 && be < d.m2 && sv[base + ac * d.m2 + be] &&
           sq[base + ac * d.m2 + be] <= mn + tie_rtol * sc)
         bc = be;
