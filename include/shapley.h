@@ -312,6 +312,30 @@ int shapley_tune_interp(int32_t kernel);
  * for any other value. */
 int shapley_tune_stencil(int32_t mode);
 
+/* Kernel of the exact solve on the coarsest level of the multigrid cycle
+ * (Algorithm MGcycle, Sec. 4.3), whose blocks are inverted once per setup:
+ * -1 (default) inverts blocks of at most 64 unknowns with the FP64 matrix
+ * cores (a blocked Gauss-Jordan sweep over panels of 16 columns with partial
+ * pivoting); 0 takes the register Gauss-Jordan kernel with partial pivoting
+ * for them.  Larger blocks always take the Gauss-Jordan kernels.  The two
+ * differ in rounding order only (results agree to a few units in the last
+ * place times the block's condition number).  Process-wide; applies to later
+ * setups.  Errors: SHAPLEY_EINVAL for any other value. */
+int shapley_tune_dense(int32_t kernel);
+
+/* The coarsest-level inverse of Algorithm MGcycle (Sec. 4.3) on given dense
+ * blocks, with the kernels the solver uses (shapley_tune_dense selects the
+ * one for blocks of at most 64 unknowns): a testing and inspection aid.
+ *   a:     count blocks back to back, block g of sizes[g] x sizes[g] entries,
+ *          row-major, finite (host, read only);
+ *   sizes: count block sizes in 1 .. 1024 (host);
+ *   inv:   receives the inverses in the layout of a (host, caller-owned).
+ * Runs on the null stream and synchronises it.  Errors: SHAPLEY_EINVAL (null
+ * argument, count < 0, a size out of range, a non-finite entry),
+ * SHAPLEY_EDEVICE when a block is singular (no nonzero pivot left),
+ * SHAPLEY_ENOMEM. */
+int shapley_coarse_inverse(const double* a, const int32_t* sizes, int32_t count, double* inv);
+
 /* Testing aid for the error paths (no passage of the paper: library
  * robustness).  after > 0: the after-th device allocation made by the library
  * from now on fails as if the device were out of memory, so that the call

@@ -6,6 +6,7 @@
 // iterative refinement.  Every row kernel takes a tile list (row ranges of
 // one game each) so one launch covers all games of a merged level.
 #include <utility>
+#include <atomic>
 #include "amg_kernels.hpp"
 
 #include <climits>
@@ -2754,6 +2755,247 @@ __global__ __launch_bounds__(256) void k_dense_inv_cols(const int* __restrict__ 
   }
 }
 
+// Dense inverse of blocks of at most 64 unknowns on the FP64 matrix cores: a
+// blocked Gauss-Jordan sweep in LDS over panels of 16 columns, the block padded
+// to a multiple of 16 with identity rows and columns.  For the panel at
+// columns K = k0 .. k0+15:
+//   1. pivot rows: wavefront 0 factors a copy of rows k0 .. of the panel (LU
+//      with row exchanges; each column takes the row with the largest |entry|,
+//      magnitudes compared on their leading 56 bits, the lowest row first) and
+//      the chosen rows are moved to positions k0 .. k0+15;
+//   2. T = A11^-1 of the pivot block by Gauss-Jordan without exchanges (its
+//      pivots are the LU pivots of step 1);
+//   3. the block sweep, as 16x16x4 FP64 MFMA tiles over the other rows R and
+//      columns C:  A_KC <- T A_KC,  A_RC <- A_RC - A_RK A_KC,  A_RK <- -A_RK T,
+//      A_KK <- T.
+// Sweeping the panels one after another leaves the inverse of the row-
+// exchanged block; the exchanges are undone as column exchanges in reverse
+// order when the result is written (column-major, like the other kernels).
+// The accumulator layout of the MFMA is read at run time from two products
+// whose entries are their own row and column indices, so the kernel assumes
+// only the operand layout: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16].
+typedef double shp_dbl4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_dense_inv_mfma(const int* __restrict__ blk, const int* __restrict__ rp,
+                                                        const int* __restrict__ ci, const double* __restrict__ a,
+                                                        double* __restrict__ inv64, float* __restrict__ inv32,
+                                                        int* __restrict__ err, const uint8_t* __restrict__ only) {
+  constexpr int NP = 64, LD = NP + 1, B = 16, LT = B + 1;
+  __shared__ double M[NP * LD];
+  __shared__ double T[B * LT];
+  __shared__ int sw[NP];    // position k was exchanged with row sw[k] at step k
+  __shared__ int perm[NP];  // row moved to position k by the exchanges of its panel
+  __shared__ int q[NP];     // column of the swept matrix holding column j of the inverse
+  __shared__ int bad;
+  const int row0 = blk[4 * blockIdx.x], nb = blk[4 * blockIdx.x + 1];
+  const size_t doff = (size_t)blk[4 * blockIdx.x + 2];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  if (nb > NP) return;  // a larger block: another kernel
+  if (only) {           // incremental refresh: skip blocks none of whose rows changed
+    int any = 0;
+    for (int r = tid; r < nb; r += 256) any |= only[row0 + r];
+    if (!__syncthreads_or(any)) return;
+  }
+  const int np = (nb + B - 1) / B * B, nt = np / B;
+  for (int idx = tid; idx < np * np; idx += 256) {
+    const int i = idx / np, j = idx - i * np;
+    M[i * LD + j] = (i == j && i >= nb) ? 1.0 : 0.0;
+  }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  if (tid < nb) {
+    const int r = row0 + tid;
+    for (int e = rp[r]; e < rp[r + 1]; ++e) {
+      const int c = ci[e] - row0;
+      if (c >= 0 && c < nb) M[tid * LD + c] += a[e];
+    }
+  }
+  // accumulator layout: register r of this lane holds entry (crow[r], ccol[r])
+  int crow[4], ccol[4];
+  {
+    const shp_dbl4 z = {0.0, 0.0, 0.0, 0.0};
+    const double lead = lk == 0 ? 1.0 : 0.0, idx = lk == 0 ? (double)li : 0.0;
+    const shp_dbl4 ri = __builtin_amdgcn_mfma_f64_16x16x4f64(idx, lead, z, 0, 0, 0);
+    const shp_dbl4 cj = __builtin_amdgcn_mfma_f64_16x16x4f64(lead, idx, z, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      crow[r] = (int)ri[r];
+      ccol[r] = (int)cj[r];
+    }
+  }
+  __syncthreads();
+  for (int kb = 0; kb < nt; ++kb) {
+    const int k0 = kb * B;
+    // 1. pivot rows of the panel
+    if (w == 0) {
+      const bool live = lane < np - k0;
+      double v[B];
+#pragma unroll
+      for (int c = 0; c < B; ++c) v[c] = live ? M[(k0 + lane) * LD + k0 + c] : 0.0;
+      int rid = k0 + lane;
+      bool sing = false;
+#pragma unroll
+      for (int jj = 0; jj < B; ++jj) {
+        if (!sing) {
+          unsigned long long key = 0;
+          if (live && lane >= jj) {
+            const double m = fabs(v[jj]);
+            if (m == m)
+              key = ((unsigned long long)__double_as_longlong(m) & ~0xFFull) | (unsigned long long)(255 - lane);
+          }
+          key = __ockl_wfred_max_u64(key);
+          if ((key >> 8) == 0) {  // no nonzero pivot left (uniform): singular block
+            sing = true;
+          } else {
+            const int p = 255 - (int)(key & 0xFF);
+            if (lane == 0) sw[k0 + jj] = k0 + p;
+            if (p != jj) {
+#pragma unroll
+              for (int c = 0; c < B; ++c) {
+                const double x = lane_read(v[c], jj), y = lane_read(v[c], p);
+                v[c] = lane == jj ? y : (lane == p ? x : v[c]);
+              }
+              const int rx = __builtin_amdgcn_readlane(rid, jj), ry = __builtin_amdgcn_readlane(rid, p);
+              rid = lane == jj ? ry : (lane == p ? rx : rid);
+            }
+            const double f = v[jj] / lane_read(v[jj], jj);
+#pragma unroll
+            for (int c = jj + 1; c < B; ++c) {
+              const double pr = lane_read(v[c], jj);
+              if (lane > jj) v[c] -= f * pr;
+            }
+          }
+        }
+      }
+      if (live) perm[k0 + lane] = rid;
+      if (sing && lane == 0) bad = 1;
+    }
+    __syncthreads();
+    if (bad) {  // uniform
+      if (tid == 0) atomicOr(err, 4);
+      return;
+    }
+    {  // move the pivot rows (rows k0 .. np-1 permuted among themselves)
+      const int cnt = (np - k0) * np;
+      double tmp[B];
+#pragma unroll
+      for (int t = 0; t < B; ++t) {
+        const int idx = tid + 256 * t;
+        if (idx < cnt) {
+          const int pos = k0 + idx / np, c = idx % np;
+          tmp[t] = M[perm[pos] * LD + c];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < B; ++t) {
+        const int idx = tid + 256 * t;
+        if (idx < cnt) {
+          const int pos = k0 + idx / np, c = idx % np;
+          M[pos * LD + c] = tmp[t];
+        }
+      }
+    }
+    __syncthreads();
+    // 2. T = A_KK^-1 (lanes 0..15 of wavefront 0 hold its rows)
+    if (w == 0) {
+      double t[B];
+#pragma unroll
+      for (int c = 0; c < B; ++c) t[c] = M[(k0 + li) * LD + k0 + c];
+      bool zero = false;
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        double pr[B];
+#pragma unroll
+        for (int c = 0; c < B; ++c) pr[c] = lane_read(t[c], j);
+        zero |= pr[j] == 0.0;
+        const double inv = 1.0 / pr[j];
+        const double f = t[j];
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+          if (c == j) t[c] = lane == j ? inv : -f * inv;
+          else t[c] = lane == j ? pr[c] * inv : t[c] - f * (pr[c] * inv);
+        }
+      }
+      if (lane < B) {
+#pragma unroll
+        for (int c = 0; c < B; ++c) T[lane * LT + c] = t[c];
+      }
+      if (zero && lane == 0) bad = 1;
+    }
+    __syncthreads();
+    if (bad) {  // uniform
+      if (tid == 0) atomicOr(err, 4);
+      return;
+    }
+    // 3a. A_KC <- T A_KC (the wavefront of the pivot rows' tile)
+    if (w == kb) {
+      for (int ct = 0; ct < nt; ++ct) {
+        if (ct == kb) continue;
+        shp_dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+        double bo[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) bo[s] = M[(k0 + 4 * s + lk) * LD + ct * B + li];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(T[li * LT + 4 * s + lk], bo[s], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) M[(k0 + crow[r]) * LD + ct * B + ccol[r]] = acc[r];
+      }
+    }
+    __syncthreads();
+    // 3b. row tile w (not the pivot tile): A_RC -= A_RK A_KC, then A_RK <- -A_RK T
+    if (w < nt && w != kb) {
+      const int r0 = w * B;
+      double na[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) na[s] = -M[(r0 + li) * LD + k0 + 4 * s + lk];
+      for (int ct = 0; ct < nt; ++ct) {
+        if (ct == kb) continue;
+        shp_dbl4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = M[(r0 + crow[r]) * LD + ct * B + ccol[r]];
+        double bo[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) bo[s] = M[(k0 + 4 * s + lk) * LD + ct * B + li];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(na[s], bo[s], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) M[(r0 + crow[r]) * LD + ct * B + ccol[r]] = acc[r];
+      }
+      shp_dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(na[s], T[(4 * s + lk) * LT + li], acc, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) M[(r0 + crow[r]) * LD + k0 + ccol[r]] = acc[r];
+    } else if (w == kb) {
+      for (int idx = lane; idx < B * B; idx += 64) {
+        const int i = idx / B, j = idx % B;
+        M[(k0 + i) * LD + k0 + j] = T[i * LT + j];
+      }
+    }
+    __syncthreads();
+  }
+  // undo the exchanges: column j of the inverse is column q[j] of the swept matrix
+  if (tid == 0) {
+    for (int j = 0; j < np; ++j) q[j] = j;
+    for (int j = np - 1; j >= 0; --j) {
+      const int o = sw[j], t = q[j];
+      q[j] = q[o];
+      q[o] = t;
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nb * nb; idx += 256) {
+    const int j = idx / nb, i = idx - j * nb;
+    const double v = M[i * LD + q[j]];
+    inv64[doff + idx] = v;
+    if (inv32) inv32[doff + idx] = (float)v;
+  }
+}
+
 // In-place Gauss-Jordan inversion with partial pivoting for blocks of at
 // most NB <= kDenseWave unknowns: one thread per row of the block, the row in
 // registers.  Pivot rows are not swapped: step k takes the row p not yet used
@@ -3874,11 +4116,18 @@ void amg_cast(const double* in, float* out, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_cast, dim3(grid_for((int64_t)n)), dim3(kBlock), 0, s, in, out, n);
   SHP_LAUNCH_CHECK();
 }
+// kernel of the dense coarsest inverses of blocks up to 64 unknowns:
+// -1 the FP64 matrix-core sweep, 0 the register Gauss-Jordan kernel
+static std::atomic<int> g_dense_mode{-1};
+void set_dense_mode(int mode) { g_dense_mode.store(mode); }
+
 void amg_dense_inv(const int* blk, int nblk, const int* rp, const int* ci, const double* a, double* work,
                    double* inv64, float* inv32, int* err, int max_nb, hipStream_t s, const uint8_t* only) {
   if (!nblk) return;
   static_assert(kDenseWave == 96, "register kernel sizes");
-  if (max_nb <= 64)
+  if (max_nb <= 64 && g_dense_mode.load(std::memory_order_relaxed) != 0)
+    hipLaunchKernelGGL(k_dense_inv_mfma, dim3(nblk), dim3(256), 0, s, blk, rp, ci, a, inv64, inv32, err, only);
+  else if (max_nb <= 64)
     hipLaunchKernelGGL(k_dense_inv_cols, dim3(nblk), dim3(256), 0, s, blk, rp, ci, a, inv64, inv32, err, only);
   else
     hipLaunchKernelGGL((k_dense_inv_reg<96, 128>), dim3(nblk), dim3(128), 0, s, blk, rp, ci, a, inv64, inv32, err,

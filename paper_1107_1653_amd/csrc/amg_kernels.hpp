@@ -107,6 +107,7 @@ void amg_drap_known(int nf, int nc, int maxc, const long long* tab, int G, const
                     const double* rv, double* ap, const int* crp, const int* cci, double* cval, hipStream_t s,
                     const uint8_t* only, const uint8_t* only_f);
 void amg_cast(const double* in, float* out, size_t n, hipStream_t s);
+void set_dense_mode(int mode);  // -1: matrix-core sweep for blocks <= 64, 0: register Gauss-Jordan
 void amg_dense_inv(const int* blk, int nblk, const int* rp, const int* ci, const double* a, double* work,
                    double* inv64, float* inv32, int* err, int max_nb, hipStream_t s,
                    const uint8_t* only = nullptr);

@@ -1,6 +1,7 @@
 // C ABI of libshapley: argument checking, game creation, solve drivers
 // (AMGpi, FAMGpi, batch), result getters.
 #include "internal.hpp"
+#include "amg_kernels.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -719,6 +720,68 @@ int shapley_tune_interp(int32_t kernel) {
   }
   shp::set_interp_mode(kernel);
   return SHAPLEY_OK;
+}
+
+int shapley_tune_dense(int32_t kernel) {
+  if (kernel != -1 && kernel != 0) {
+    shp::set_last_error("kernel must be -1 or 0");
+    return SHAPLEY_EINVAL;
+  }
+  shp::set_dense_mode(kernel);
+  return SHAPLEY_OK;
+}
+
+int shapley_coarse_inverse(const double* a, const int32_t* sizes, int32_t count, double* inv) {
+  return guarded([&] {
+    SHP_REQUIRE(count >= 0, "count must be >= 0");
+    if (count == 0) return;
+    SHP_REQUIRE(a && sizes && inv, "null argument");
+    std::vector<int> hblk, hrp(1, 0), hci;
+    std::vector<double> ha;
+    size_t doff = 0;
+    int row0 = 0, max_nb = 0;
+    for (int g = 0; g < count; ++g) {
+      const int nb = sizes[g];
+      SHP_REQUIRE(nb >= 1 && nb <= kDenseMax, "block sizes must lie in 1 .. 1024");
+      SHP_REQUIRE(doff + (size_t)nb * nb < (size_t)INT_MAX, "blocks exceed 2^31 entries together");
+      hblk.insert(hblk.end(), {row0, nb, (int)doff, g});
+      for (int i = 0; i < nb; ++i) {
+        for (int j = 0; j < nb; ++j) {
+          const double v = a[doff + (size_t)i * nb + j];
+          SHP_REQUIRE(std::isfinite(v), "entries must be finite");
+          hci.push_back(row0 + j);
+          ha.push_back(v);
+        }
+        hrp.push_back((int)hci.size());
+      }
+      row0 += nb;
+      doff += (size_t)nb * nb;
+      max_nb = std::max(max_nb, nb);
+    }
+    hipStream_t s = nullptr;
+    DBuf<int> dblk(hblk.size()), drp(hrp.size()), dci(hci.size()), derr(1);
+    DBuf<double> da(ha.size()), dinv(doff), dwork(max_nb > kDenseWave ? 2 * doff : 0);
+    const int zero = 0;
+    h2d(dblk.p, hblk.data(), hblk.size(), s);
+    h2d(drp.p, hrp.data(), hrp.size(), s);
+    h2d(dci.p, hci.data(), hci.size(), s);
+    h2d(da.p, ha.data(), ha.size(), s);
+    h2d(derr.p, &zero, 1, s);
+    amg_dense_inv(dblk.p, count, drp.p, dci.p, da.p, dwork.p, dinv.p, nullptr, derr.p, max_nb, s);
+    std::vector<double> hinv(doff);
+    int herr = 0;
+    d2h(hinv.data(), dinv.p, doff, s);
+    d2h(&herr, derr.p, 1, s);
+    SHP_HIP(hipStreamSynchronize(s));
+    if (herr & 4) throw Error(SHAPLEY_EDEVICE, "singular block");
+    doff = 0;
+    for (int g = 0; g < count; ++g) {  // column-major on the device, row-major for the caller
+      const int nb = sizes[g];
+      for (int i = 0; i < nb; ++i)
+        for (int j = 0; j < nb; ++j) inv[doff + (size_t)i * nb + j] = hinv[doff + (size_t)j * nb + i];
+      doff += (size_t)nb * nb;
+    }
+  });
 }
 
 int shapley_tune_stencil(int32_t mode) {

@@ -41,6 +41,7 @@ EXPORTED = [
     "shapley_server_poll", "shapley_server_step", "shapley_server_destroy", "shapley_server_info",
     "shapley_probe_enable", "shapley_probe_read", "shapley_probe_read_large", "shapley_tune_lanes",
     "shapley_tune_galerkin", "shapley_tune_interp", "shapley_tune_stencil", "shapley_debug_fail_alloc",
+    "shapley_tune_dense", "shapley_coarse_inverse",
 ]
 PROBE = dict(smooth=0, resid64=1, improve=2, resid=3, restrict=4, prolong=5, rap=6, interp=7, tail=8)
 
@@ -150,6 +151,8 @@ def lib() -> C.CDLL:
         L.shapley_tune_interp.argtypes = [C.c_int32]
         L.shapley_tune_stencil.argtypes = [C.c_int32]
         L.shapley_debug_fail_alloc.argtypes = [C.c_int64]
+        L.shapley_tune_dense.argtypes = [C.c_int32]
+        L.shapley_coarse_inverse.argtypes = [P, P, C.c_int32, P]
         _lib_handle = L
     return _lib_handle
 
@@ -435,6 +438,29 @@ def shapley_tune_interp(kernel: int = -1) -> None:
     """Coarse-level interpolation kernels: -1 four lanes per row first on large levels, 4 on every level,
     0 wavefront only."""
     _check(lib().shapley_tune_interp(int(kernel)))
+
+
+def shapley_tune_dense(kernel: int = -1) -> None:
+    """Coarsest-level inverse of blocks up to 64 unknowns: -1 FP64 matrix-core sweep, 0 register Gauss-Jordan."""
+    _check(lib().shapley_tune_dense(int(kernel)))
+
+
+def shapley_coarse_inverse(blocks) -> list:
+    """Inverses of dense square blocks (a list of 2-D arrays) computed by the coarsest-level kernels."""
+    mats = [np.ascontiguousarray(b, dtype=np.float64) for b in blocks]
+    for m in mats:
+        if m.ndim != 2 or m.shape[0] != m.shape[1]:
+            raise ValueError("blocks must be square matrices")
+    sizes = np.array([m.shape[0] for m in mats], dtype=np.int32)
+    flat = np.concatenate([m.ravel() for m in mats]) if mats else np.zeros(0)
+    out = np.empty_like(flat)
+    _check(lib().shapley_coarse_inverse(_ptr(flat), _ptr(sizes), int(len(mats)), _ptr(out)))
+    res, off = [], 0
+    for m in mats:
+        k = m.size
+        res.append(out[off:off + k].reshape(m.shape))
+        off += k
+    return res
 
 
 def shapley_tune_stencil(mode: int = -1) -> None:
