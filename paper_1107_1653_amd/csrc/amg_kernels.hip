@@ -2759,18 +2759,19 @@ __global__ __launch_bounds__(256) void k_dense_inv_cols(const int* __restrict__ 
 // blocked Gauss-Jordan sweep in LDS over panels of 16 columns, the block padded
 // to a multiple of 16 with identity rows and columns.  For the panel at
 // columns K = k0 .. k0+15:
-//   1. pivot rows: wavefront 0 factors a copy of rows k0 .. of the panel (LU
-//      with row exchanges; each column takes the row with the largest |entry|,
-//      magnitudes compared on their leading 56 bits, the lowest row first) and
-//      the chosen rows are moved to positions k0 .. k0+15;
-//   2. T = A11^-1 of the pivot block by Gauss-Jordan without exchanges (its
-//      pivots are the LU pivots of step 1);
-//   3. the block sweep, as 16x16x4 FP64 MFMA tiles over the other rows R and
-//      columns C:  A_KC <- T A_KC,  A_RC <- A_RC - A_RK A_KC,  A_RK <- -A_RK T,
-//      A_KK <- T.
-// Sweeping the panels one after another leaves the inverse of the row-
-// exchanged block; the exchanges are undone as column exchanges in reverse
-// order when the result is written (column-major, like the other kernels).
+//   1. wavefront 0 holds the panel's columns of every row (lane = row) and
+//      sweeps its 16 pivots by Gauss-Jordan with partial pivoting: each column
+//      takes, among the rows at positions k0 .. not yet chosen, the one with
+//      the largest |entry| (magnitudes compared on their leading 56 bits, the
+//      lowest row first) and eliminates it from every other row.  This leaves
+//      T = A_KK^-1 in the pivot rows and -A_RK T in the others R;
+//   2. the rows at positions k0 .. are regrouped, the pivots first in the
+//      order chosen, the others after them in their order;
+//   3. the columns C outside the panel, as 16x16x4 FP64 MFMA tiles, one
+//      wavefront per row tile:  A_RC <- A_RC + (-A_RK T) A_KC,  A_KC <- T A_KC.
+// After the last panel the matrix holds X = (Pi A)^-1 for the accumulated row
+// regrouping Pi, and column j of A^-1 is column q(j) of X, q(j) the final
+// position of row j (written column-major, like the other kernels).
 // The accumulator layout of the MFMA is read at run time from two products
 // whose entries are their own row and column indices, so the kernel assumes
 // only the operand layout: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16].
@@ -2780,12 +2781,12 @@ __global__ __launch_bounds__(256) void k_dense_inv_mfma(const int* __restrict__ 
                                                         const int* __restrict__ ci, const double* __restrict__ a,
                                                         double* __restrict__ inv64, float* __restrict__ inv32,
                                                         int* __restrict__ err, const uint8_t* __restrict__ only) {
-  constexpr int NP = 64, LD = NP + 1, B = 16, LT = B + 1;
+  constexpr int NP = 64, LD = NP + 1, B = 16, NT = NP / B;
   __shared__ double M[NP * LD];
-  __shared__ double T[B * LT];
-  __shared__ int sw[NP];    // position k was exchanged with row sw[k] at step k
-  __shared__ int perm[NP];  // row moved to position k by the exchanges of its panel
-  __shared__ int q[NP];     // column of the swept matrix holding column j of the inverse
+  __shared__ int npos[NP];  // this panel: new position of the row at position l
+  __shared__ int orig[NP];  // original row now at position l
+  __shared__ int q[NP];     // final position of original row j
+  __shared__ int srp[NP + 1];
   __shared__ int bad;
   const int row0 = blk[4 * blockIdx.x], nb = blk[4 * blockIdx.x + 1];
   const size_t doff = (size_t)blk[4 * blockIdx.x + 2];
@@ -2802,14 +2803,21 @@ __global__ __launch_bounds__(256) void k_dense_inv_mfma(const int* __restrict__ 
     const int i = idx / np, j = idx - i * np;
     M[i * LD + j] = (i == j && i >= nb) ? 1.0 : 0.0;
   }
+  if (tid < NP) orig[tid] = tid;
+  if (tid <= nb) srp[tid] = rp[row0 + tid];
   if (tid == 0) bad = 0;
   __syncthreads();
-  if (tid < nb) {
-    const int r = row0 + tid;
-    for (int e = rp[r]; e < rp[r + 1]; ++e) {
-      const int c = ci[e] - row0;
-      if (c >= 0 && c < nb) M[tid * LD + c] += a[e];
+  // the block's rows are contiguous in the CSR: a thread per entry, its row by
+  // bisection of the row pointers (entries outside the block are dropped)
+  for (int e = srp[0] + tid; e < srp[nb]; e += 256) {
+    int lo = 0, hi = nb;  // srp[lo] <= e < srp[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (srp[mid] <= e) lo = mid;
+      else hi = mid;
     }
+    const int c = ci[e] - row0;
+    if (c >= 0 && c < nb) atomicAdd(&M[lo * LD + c], a[e]);
   }
   // accumulator layout: register r of this lane holds entry (crow[r], ccol[r])
   int crow[4], ccol[4];
@@ -2827,20 +2835,21 @@ __global__ __launch_bounds__(256) void k_dense_inv_mfma(const int* __restrict__ 
   __syncthreads();
   for (int kb = 0; kb < nt; ++kb) {
     const int k0 = kb * B;
-    // 1. pivot rows of the panel
+    // 1. Gauss-Jordan sweep of the panel's pivots on its columns (wavefront 0)
+    double pv[B];
     if (w == 0) {
-      const bool live = lane < np - k0;
-      double v[B];
+      const bool live = lane < np;
 #pragma unroll
-      for (int c = 0; c < B; ++c) v[c] = live ? M[(k0 + lane) * LD + k0 + c] : 0.0;
-      int rid = k0 + lane;
+      for (int c = 0; c < B; ++c) pv[c] = live ? M[lane * LD + k0 + c] : 0.0;
+      bool used = !live || lane < k0;
+      int myk = -1;
       bool sing = false;
 #pragma unroll
       for (int jj = 0; jj < B; ++jj) {
         if (!sing) {
           unsigned long long key = 0;
-          if (live && lane >= jj) {
-            const double m = fabs(v[jj]);
+          if (!used) {
+            const double m = fabs(pv[jj]);
             if (m == m)
               key = ((unsigned long long)__double_as_longlong(m) & ~0xFFull) | (unsigned long long)(255 - lane);
           }
@@ -2849,26 +2858,27 @@ __global__ __launch_bounds__(256) void k_dense_inv_mfma(const int* __restrict__ 
             sing = true;
           } else {
             const int p = 255 - (int)(key & 0xFF);
-            if (lane == 0) sw[k0 + jj] = k0 + p;
-            if (p != jj) {
+            const double inv = 1.0 / lane_read(pv[jj], p);
+            const double f = pv[jj];
+            const bool isp = lane == p;
 #pragma unroll
-              for (int c = 0; c < B; ++c) {
-                const double x = lane_read(v[c], jj), y = lane_read(v[c], p);
-                v[c] = lane == jj ? y : (lane == p ? x : v[c]);
-              }
-              const int rx = __builtin_amdgcn_readlane(rid, jj), ry = __builtin_amdgcn_readlane(rid, p);
-              rid = lane == jj ? ry : (lane == p ? rx : rid);
+            for (int c = 0; c < B; ++c) {
+              const double pr = lane_read(pv[c], p);
+              if (c == jj) pv[c] = isp ? inv : -f * inv;
+              else pv[c] = isp ? pr * inv : pv[c] - f * (pr * inv);
             }
-            const double f = v[jj] / lane_read(v[jj], jj);
-#pragma unroll
-            for (int c = jj + 1; c < B; ++c) {
-              const double pr = lane_read(v[c], jj);
-              if (lane > jj) v[c] -= f * pr;
+            if (isp) {
+              used = true;
+              myk = jj;
             }
           }
         }
       }
-      if (live) perm[k0 + lane] = rid;
+      // 2. new positions: pivots in the order chosen, then the other rows
+      const unsigned long long rest = __ballot(live && lane >= k0 && myk < 0);
+      int to = lane;
+      if (lane >= k0) to = myk >= 0 ? k0 + myk : k0 + B + __popcll(rest & ((1ull << lane) - 1ull));
+      if (live) npos[lane] = to;
       if (sing && lane == 0) bad = 1;
     }
     __syncthreads();
@@ -2876,117 +2886,77 @@ __global__ __launch_bounds__(256) void k_dense_inv_mfma(const int* __restrict__ 
       if (tid == 0) atomicOr(err, 4);
       return;
     }
-    {  // move the pivot rows (rows k0 .. np-1 permuted among themselves)
+    {  // regroup rows k0 .. np-1 (columns outside the panel); wavefront 0 writes the panel
       const int cnt = (np - k0) * np;
-      double tmp[B];
+      double tmp[NP * NP / 256];
 #pragma unroll
-      for (int t = 0; t < B; ++t) {
+      for (int t = 0; t < NP * NP / 256; ++t) {
         const int idx = tid + 256 * t;
-        if (idx < cnt) {
-          const int pos = k0 + idx / np, c = idx % np;
-          tmp[t] = M[perm[pos] * LD + c];
-        }
+        if (idx < cnt) tmp[t] = M[(k0 + idx / np) * LD + idx % np];
       }
+      const int o_l = tid >= k0 && tid < np ? orig[tid] : 0;
       __syncthreads();
 #pragma unroll
-      for (int t = 0; t < B; ++t) {
+      for (int t = 0; t < NP * NP / 256; ++t) {
         const int idx = tid + 256 * t;
-        if (idx < cnt) {
-          const int pos = k0 + idx / np, c = idx % np;
-          M[pos * LD + c] = tmp[t];
+        const int l = k0 + idx / np, c = idx % np;
+        if (idx < cnt && (c < k0 || c >= k0 + B)) M[npos[l] * LD + c] = tmp[t];
+      }
+      if (tid >= k0 && tid < np) orig[npos[tid]] = o_l;
+      if (w == 0 && lane < np) {
+        const int to = npos[lane];
+#pragma unroll
+        for (int c = 0; c < B; ++c) M[to * LD + k0 + c] = pv[c];
+      }
+    }
+    __syncthreads();
+    // 3. columns outside the panel: row tiles R first (they read the old A_KC),
+    // the pivot tile's T A_KC kept in registers until they are done
+    shp_dbl4 keep[NT];
+    if (w < nt && w == kb) {
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) {
+        keep[ct] = shp_dbl4{0.0, 0.0, 0.0, 0.0};
+        if (ct < nt && ct != kb) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            keep[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(M[(k0 + li) * LD + k0 + 4 * s + lk],
+                                                             M[(k0 + 4 * s + lk) * LD + ct * B + li], keep[ct], 0,
+                                                             0, 0);
         }
       }
-    }
-    __syncthreads();
-    // 2. T = A_KK^-1 (lanes 0..15 of wavefront 0 hold its rows)
-    if (w == 0) {
-      double t[B];
-#pragma unroll
-      for (int c = 0; c < B; ++c) t[c] = M[(k0 + li) * LD + k0 + c];
-      bool zero = false;
-#pragma unroll
-      for (int j = 0; j < B; ++j) {
-        double pr[B];
-#pragma unroll
-        for (int c = 0; c < B; ++c) pr[c] = lane_read(t[c], j);
-        zero |= pr[j] == 0.0;
-        const double inv = 1.0 / pr[j];
-        const double f = t[j];
-#pragma unroll
-        for (int c = 0; c < B; ++c) {
-          if (c == j) t[c] = lane == j ? inv : -f * inv;
-          else t[c] = lane == j ? pr[c] * inv : t[c] - f * (pr[c] * inv);
-        }
-      }
-      if (lane < B) {
-#pragma unroll
-        for (int c = 0; c < B; ++c) T[lane * LT + c] = t[c];
-      }
-      if (zero && lane == 0) bad = 1;
-    }
-    __syncthreads();
-    if (bad) {  // uniform
-      if (tid == 0) atomicOr(err, 4);
-      return;
-    }
-    // 3a. A_KC <- T A_KC (the wavefront of the pivot rows' tile)
-    if (w == kb) {
-      for (int ct = 0; ct < nt; ++ct) {
-        if (ct == kb) continue;
-        shp_dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-        double bo[4];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) bo[s] = M[(k0 + 4 * s + lk) * LD + ct * B + li];
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(T[li * LT + 4 * s + lk], bo[s], acc, 0, 0, 0);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) M[(k0 + crow[r]) * LD + ct * B + ccol[r]] = acc[r];
-      }
-    }
-    __syncthreads();
-    // 3b. row tile w (not the pivot tile): A_RC -= A_RK A_KC, then A_RK <- -A_RK T
-    if (w < nt && w != kb) {
+    } else if (w < nt) {
       const int r0 = w * B;
-      double na[4];
+      double ar[4];  // -A_RK T of this row tile
 #pragma unroll
-      for (int s = 0; s < 4; ++s) na[s] = -M[(r0 + li) * LD + k0 + 4 * s + lk];
-      for (int ct = 0; ct < nt; ++ct) {
-        if (ct == kb) continue;
-        shp_dbl4 acc;
+      for (int s = 0; s < 4; ++s) ar[s] = M[(r0 + li) * LD + k0 + 4 * s + lk];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[r] = M[(r0 + crow[r]) * LD + ct * B + ccol[r]];
-        double bo[4];
+      for (int ct = 0; ct < NT; ++ct) {
+        if (ct < nt && ct != kb) {
+          shp_dbl4 acc;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) bo[s] = M[(k0 + 4 * s + lk) * LD + ct * B + li];
+          for (int r = 0; r < 4; ++r) acc[r] = M[(r0 + crow[r]) * LD + ct * B + ccol[r]];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(na[s], bo[s], acc, 0, 0, 0);
+          for (int s = 0; s < 4; ++s)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[s], M[(k0 + 4 * s + lk) * LD + ct * B + li], acc, 0, 0,
+                                                       0);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) M[(r0 + crow[r]) * LD + ct * B + ccol[r]] = acc[r];
-      }
-      shp_dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(na[s], T[(4 * s + lk) * LT + li], acc, 0, 0, 0);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) M[(r0 + crow[r]) * LD + k0 + ccol[r]] = acc[r];
-    } else if (w == kb) {
-      for (int idx = lane; idx < B * B; idx += 64) {
-        const int i = idx / B, j = idx % B;
-        M[(k0 + i) * LD + k0 + j] = T[i * LT + j];
+          for (int r = 0; r < 4; ++r) M[(r0 + crow[r]) * LD + ct * B + ccol[r]] = acc[r];
+        }
       }
     }
     __syncthreads();
-  }
-  // undo the exchanges: column j of the inverse is column q[j] of the swept matrix
-  if (tid == 0) {
-    for (int j = 0; j < np; ++j) q[j] = j;
-    for (int j = np - 1; j >= 0; --j) {
-      const int o = sw[j], t = q[j];
-      q[j] = q[o];
-      q[o] = t;
+    if (w < nt && w == kb) {
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct)
+        if (ct < nt && ct != kb) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) M[(k0 + crow[r]) * LD + ct * B + ccol[r]] = keep[ct][r];
+        }
     }
+    __syncthreads();
   }
+  if (tid < np) q[orig[tid]] = tid;
   __syncthreads();
   for (int idx = tid; idx < nb * nb; idx += 256) {
     const int j = idx / nb, i = idx - j * nb;
