@@ -59,6 +59,8 @@ def parse_args():
                     help="the headline's timed steps only (for kernel traces): no FP64 or one-by-one runs")
     ap.add_argument("--forcing", type=float, default=0.2)
     ap.add_argument("--reuse", type=float, default=0.5)
+    ap.add_argument("--nu1", type=int, default=1, help="relaxation sweeps before the coarse correction")
+    ap.add_argument("--nu2", type=int, default=2, help="relaxation sweeps after the coarse correction")
     ap.add_argument("--games", type=int, default=256, help="C3 batch size")
     ap.add_argument("--requests", type=int, default=1000, help="C4 requests")
     ap.add_argument("--side", type=int, default=129, help="C2 interior points per side")
@@ -188,10 +190,11 @@ def record(args, value, ms_per_step, dtype, config, steps=None):
 
 
 def opts(P, args, prec, **kw):
-    # inexact policy iteration: each linear solve to 0.1 x the previous Shapley
-    # residual; AMG splitting reused while < 50% of the policies changed
+    # inexact policy iteration: each linear solve to `forcing` x the previous
+    # Shapley residual; AMG splitting reused while < 50% of the policies
+    # changed; V(nu1, nu2) cycles
     return P.shapley_default_opts(eps=1e-8, precision=prec, max_outer=5000, max_inner=5000, forcing=args.forcing,
-                                  reuse_frac=args.reuse, **kw)
+                                  reuse_frac=args.reuse, nu1=args.nu1, nu2=args.nu2, **kw)
 
 
 def measure(P, args, workload, solve, steps=None):
@@ -262,7 +265,7 @@ def c3_line(args):
                   {"workload": f"{len(gs)} Isaacs 2-D games, interior sides 65/129/257 (sum n={total}), "
                                "batched AMGpi, FP32 V-cycles + FP64 refinement, to 1e-8",
                    "games": len(gs), "sum_n": total, "eps": 1e-8, "forcing": args.forcing,
-                   "reuse_frac": args.reuse})
+                   "reuse_frac": args.reuse, "cycle": f"V({args.nu1},{args.nu2}) weighted Jacobi, omega 0.8"})
     line["latency_ms"] = {"p50": float(np.percentile(1e3 * lat, 50)), "p99": float(np.percentile(1e3 * lat, 99))}
     line["roofline"] = roof
     line["families"] = fams
