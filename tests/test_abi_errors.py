@@ -1,7 +1,7 @@
 """Every SHAPLEY_EINVAL condition of the boundary is driven through the C ABI
 on the host, where it is detected before any device call: bad sizes, w < 0,
 row sum > 1 + 1e-12, mu outside (0, 1], NaN/Inf, empty action set, bad
-options.  Inputs that pass the checks reach the device (SHAPLEY_EDEVICE
+options, bad blocks for the coarsest-level inverse.  Inputs that pass the checks reach the device (SHAPLEY_EDEVICE
 without a GPU), which shows the checks are not too strict."""
 import ctypes as C
 import math
@@ -170,3 +170,19 @@ def test_server_arguments(P):
     assert P.lib().shapley_server_submit(None, None, None, C.byref(t)) == P.SHAPLEY_EINVAL
     assert P.lib().shapley_server_step(None, None) == P.SHAPLEY_EINVAL
     assert P.lib().shapley_server_poll(None, 1, None) == P.SHAPLEY_EINVAL
+
+
+def test_coarse_inverse_arguments(P):
+    assert P.shapley_coarse_inverse([]) == []
+    for bad in ([np.zeros((1025, 1025))], [np.array([[1.0, np.nan], [0.0, 1.0]])],
+                [np.eye(3), np.array([[np.inf]])]):
+        with pytest.raises(P.ShapleyError) as e:
+            P.shapley_coarse_inverse(bad)
+        assert e.value.code == P.SHAPLEY_EINVAL
+    one = (C.c_double * 1)(1.0)
+    size0 = (C.c_int32 * 1)(0)
+    assert P.lib().shapley_coarse_inverse(one, size0, 1, one) == P.SHAPLEY_EINVAL
+    assert P.lib().shapley_coarse_inverse(None, None, -1, None) == P.SHAPLEY_EINVAL
+    assert P.lib().shapley_coarse_inverse(None, size0, 1, one) == P.SHAPLEY_EINVAL
+    for bad in (1, 4, -2):
+        assert P.lib().shapley_tune_dense(bad) == P.SHAPLEY_EINVAL
