@@ -349,22 +349,24 @@ void launch_stencil_codes(const GameDesc* d, const GTile* t, int nt, const int* 
 // adds its row's products in entry order into Q; one thread per (state, a)
 // takes MIN over b, one thread per state MAX over a and the decisions.
 // ---------------------------------------------------------------------------
-constexpr int kImpStage = 1280;  // a tile of 2-D grid states (28 states, 9 rows of 5 entries) in one stage
-constexpr int kImpUnroll = kImpStage / 256;  // entries staged per thread and stage
+constexpr int kImpUnroll = 5;  // entries staged per thread and stage: a tile of 2-D grid states (9 rows of 5
+                               // entries each) in one stage
 
-// One tile of states: either taken from the work list (FLAT = false: the
-// tile's game descriptor is read from gd), or, for a single game passed by
-// value, the states [blockIdx.x * spb, (blockIdx.x + 1) * spb).
-template <bool FLAT>
-__global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd,
-                                                 const GTile* __restrict__ tiles,
-                                                 const int* __restrict__ active, double tie_rtol,
-                                                 Stripes red, GameDesc d1, int spb) {
-  __shared__ double sq[256];
-  __shared__ double ss[256];
-  __shared__ unsigned char sv[256];
-  __shared__ double s_mn[256], s_sc[256];  // per (state, a): MIN's minimum over b and its scale
-  __shared__ int s_lb[256];                // and its lowest b
+// One tile of states (at most NT rows, a thread per row): either taken from
+// the work list (FLAT = false: the tile's game descriptor is read from gd),
+// or, for a single game passed by value, the states
+// [blockIdx.x * spb, (blockIdx.x + 1) * spb).
+template <bool FLAT, int NT>
+__global__ __launch_bounds__(NT) void k_improve(const GameDesc* __restrict__ gd,
+                                                const GTile* __restrict__ tiles,
+                                                const int* __restrict__ active, double tie_rtol,
+                                                Stripes red, GameDesc d1, int spb) {
+  constexpr int kImpStage = NT * kImpUnroll;
+  __shared__ double sq[NT];
+  __shared__ double ss[NT];
+  __shared__ unsigned char sv[NT];
+  __shared__ double s_mn[NT], s_sc[NT];  // per (state, a): MIN's minimum over b and its scale
+  __shared__ int s_lb[NT];               // and its lowest b
   __shared__ double sp[kImpStage];
   GTile t;
   GameDesc d;
@@ -403,15 +405,15 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
     double ww[kImpUnroll], vv[kImpUnroll];
 #pragma unroll
     for (int u = 0; u < kImpUnroll; ++u) {
-      const int e = c0 + tid + 256 * u;
+      const int e = c0 + tid + NT * u;
       cc[u] = e < c1 ? d.ci[e] : 0;
       ww[u] = e < c1 ? d.w[e] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < kImpUnroll; ++u) vv[u] = c0 + tid + 256 * u < c1 ? d.v[cc[u]] : 0.0;
+    for (int u = 0; u < kImpUnroll; ++u) vv[u] = c0 + tid + NT * u < c1 ? d.v[cc[u]] : 0.0;
 #pragma unroll
     for (int u = 0; u < kImpUnroll; ++u)
-      if (c0 + tid + 256 * u < c1) sp[tid + 256 * u] = ww[u] * vv[u];
+      if (c0 + tid + NT * u < c1) sp[tid + NT * u] = ww[u] * vv[u];
     __syncthreads();
     const int lo = e0 > c0 ? e0 : c0, hi = e1 < c1 ? e1 : c1;
     for (int e = lo; e < hi; ++e) {
@@ -504,10 +506,25 @@ __global__ __launch_bounds__(256) void k_improve(const GameDesc* __restrict__ gd
 }
 
 void launch_improve(const GameDesc* d, const GTile* t, int nt, const int* active, double tie_rtol,
-                    Stripes red, hipStream_t s) {
+                    Stripes red, int threads, hipStream_t s) {
   if (nt == 0) return;
-  hipLaunchKernelGGL(k_improve<false>, dim3(nt), dim3(kBlock), 0, s, d, t, active, tie_rtol, red, GameDesc{}, 0);
+  if (threads == 64)
+    hipLaunchKernelGGL((k_improve<false, 64>), dim3(nt), dim3(64), 0, s, d, t, active, tie_rtol, red, GameDesc{}, 0);
+  else if (threads == 128)
+    hipLaunchKernelGGL((k_improve<false, 128>), dim3(nt), dim3(128), 0, s, d, t, active, tie_rtol, red, GameDesc{},
+                       0);
+  else
+    hipLaunchKernelGGL((k_improve<false, 256>), dim3(nt), dim3(256), 0, s, d, t, active, tie_rtol, red, GameDesc{},
+                       0);
   SHP_LAUNCH_CHECK();
+}
+
+// threads of the improvement workgroups: the smallest of 64, 128, 256 that
+// holds a state's rows and is at least `want`
+int improve_threads(int max_rows_per_state, int want) {
+  int t = want == 64 || want == 128 ? want : 256;
+  while (t < 256 && t < max_rows_per_state) t *= 2;
+  return t;
 }
 
 __global__ void k_tile_entries(const GameDesc* __restrict__ gd, GTile* __restrict__ tiles, int nt) {
@@ -527,14 +544,14 @@ void launch_tile_entries(const GameDesc* d, GTile* t, int nt, hipStream_t s) {
   SHP_LAUNCH_CHECK();
 }
 
-// states per improvement tile: whole states, at most kBlock rows
-int improve_states_per_tile(int m1, int m2) { return std::max(1, kBlock / (m1 * m2)); }
+// states per improvement tile: whole states, at most `threads` rows
+int improve_states_per_tile(int m1, int m2, int threads) { return std::max(1, threads / (m1 * m2)); }
 
 void launch_improve_flat(const GameDesc& d, double tie_rtol, Stripes red, hipStream_t s) {
   if (d.n == 0) return;
-  const int spb = improve_states_per_tile(d.m1, d.m2);
-  hipLaunchKernelGGL(k_improve<true>, dim3((d.n + spb - 1) / spb), dim3(kBlock), 0, s, (const GameDesc*)nullptr,
-                     (const GTile*)nullptr, (const int*)nullptr, tie_rtol, red, d, spb);
+  const int spb = improve_states_per_tile(d.m1, d.m2, kBlock);
+  hipLaunchKernelGGL((k_improve<true, 256>), dim3((d.n + spb - 1) / spb), dim3(kBlock), 0, s,
+                     (const GameDesc*)nullptr, (const GTile*)nullptr, (const int*)nullptr, tie_rtol, red, d, spb);
   SHP_LAUNCH_CHECK();
 }
 

@@ -419,6 +419,7 @@ class Engine {
   DBuf<GameDesc> ddesc;
   DBuf<GTile> gtiles_all, gtiles_imp;  // state tiles (assembly / improvement)
   std::vector<GTile> h_gtiles_all, h_gtiles_imp;
+  int imp_threads = 256;  // workgroup size of the improvement sweep (tiles of at most this many rows)
   std::vector<Level> lv;
   int nlev = 0;
   // per-slot device scalars
@@ -557,12 +558,13 @@ void launch_stencil_scan(const int* urp, const int* uci, int n, int* out, hipStr
 void launch_stencil_codes(const GameDesc* d, const GTile* t, int nt, const int* off, uint32_t* code,
                           hipStream_t s);
 void launch_improve(const GameDesc* d, const GTile* t, int nt, const int* active, double tie_rtol,
-                    Stripes red, hipStream_t s);
+                    Stripes red, int threads, hipStream_t s);
+int improve_threads(int max_rows_per_state, int want);
 // The same sweep over one game passed by value, tiles computed from the block
 // index (no work list in memory); alpha/beta/beta_in/F may be null (no
 // incumbents, outputs not stored); its reductions fold into red as game 0.
 void launch_improve_flat(const GameDesc& d, double tie_rtol, Stripes red, hipStream_t s);
-int improve_states_per_tile(int m1, int m2);
+int improve_states_per_tile(int m1, int m2, int threads);
 // the entry range [e0, e1) of each improvement tile's rows, from the games' row pointers
 void launch_tile_entries(const GameDesc* d, GTile* t, int nt, hipStream_t s);
 void launch_fold_finish(Stripes st, int G, int nd, unsigned sum_mask, int ni, double* out_d, int sd, int* out_i,
