@@ -293,7 +293,8 @@ int shapley_tune_galerkin(int32_t kernel);
  * prolongation P of Sec. 4.3): 4 first runs a four-lanes-per-row kernel that
  * takes the rows whose sets fit it and hands the others to the wavefront-per-
  * row kernel; 0 forces the wavefront kernel alone; -1 (default) takes the
- * four-lane kernel on levels of 2^16 rows or more.  Both
+ * four-lane kernel on levels of 2^16 rows or more whose rows average at most
+ * 24 entries.  Both
  * form every weight with the same operations in the same order, so results
  * do not depend on this setting.  Process-wide; applies to later setups.
  * Errors: SHAPLEY_EINVAL for any other value. */

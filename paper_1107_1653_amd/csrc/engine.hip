@@ -768,9 +768,13 @@ void Engine::setup(const std::vector<int>& run, const EngineOpts& o) {
         // levels (long rows): one wavefront per row, with the larger LDS sets
         // where rows average more than 32 entries
         // (four lanes per row take a row through a longer chain than a
-        // wavefront does: only levels with rows enough to fill the chip)
+        // wavefront does: only levels with rows enough to fill the chip, and
+        // rows averaging at most 24 entries -- measured: the 129^3 game's
+        // coarse levels, longer, 42.5 -> 40.7 ms per solve with the wavefront
+        // kernel; the 256-game batch unchanged)
         const int imode = g_interp_mode.load();
-        const bool quad = imode == 4 || (imode == -1 && n >= kInterpQuadRows);
+        const bool quad =
+            imode == 4 || (imode == -1 && n >= kInterpQuadRows && (double)L.nnz <= 24.0 * std::max(n, 1));
         const int iw = l == 0 ? 0 : ((double)L.nnz > 32.0 * std::max(n, 1) ? 2 : (quad ? 3 : 1));
         s_defer.ensure(2 * ((size_t)L.rows_ctiles + 1));  // two hand-over lists
         amg_interp(L.ctiles.p, L.nctiles, L.rp.p, L.ci.p, L.a64.p, L.dinv64.p, L.strong.p, L.cf.p,
